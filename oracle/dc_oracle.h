@@ -1,0 +1,152 @@
+/*
+ * dc_oracle.h -- plain, slow, single-threaded CPU oracle for Delta-screening
+ * incremental dynamic community detection (Zarayeneh & Kalyanaraman,
+ * arXiv 1904.08553).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library under paper_1904_08553_amd/csrc) shares no code, header,
+ * table or helper with it.
+ *
+ * Deterministic reading of the method (the paper is silent on these points):
+ *   - modularity Q = N / (2m)^2 with N = 2m*I - sum_C a_C^2 held exactly in
+ *     int64 (Sec. 3.1, Eq. 1);
+ *   - the gain of moving i from c to D is compared through the scaled integer
+ *     G = score(D) - score(c), score(X) = 2m*e_{i->X} - k_i*a_X^{(-i)}
+ *     (Sec. 3.1; Appendix A algebra);
+ *   - synchronous sweeps, ties to the smallest community label, a move only on
+ *     a strictly positive gain, the minimum-label singleton guard, revert of a
+ *     sweep whose exact Delta N is negative, stop when a sweep moves nothing or
+ *     gains at most T = floor((2m)^2 / tau_den) (Sec. 3.2, Alg. 1);
+ *   - levels: level 0 starts from the inherited partition and visits only R_t,
+ *     later levels start from singletons and visit every coarse vertex
+ *     (Sec. 3.4);
+ *   - Delta-screening over additions per Alg. 2 (Sec. 3.5); deletions use a
+ *     best-move test (the paper leaves deletions to future work, Sec. 5).
+ */
+#ifndef DC_ORACLE_H
+#define DC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes (same numbering as the product library so tests can compare) */
+enum {
+  ORC_OK = 0,
+  ORC_E_ARG = -1,
+  ORC_E_RANGE = -2,
+  ORC_E_SELF_LOOP = -3,
+  ORC_E_WEIGHT = -4,
+  ORC_E_NO_EDGE = -5,
+  ORC_E_DUP = -6,
+  ORC_E_OVERFLOW = -7,
+  ORC_E_OOM = -8
+};
+
+enum { ORC_MODE_DELTA = 0, ORC_MODE_ALL = 1, ORC_MODE_STATIC = 2 };
+enum { ORC_DEL_GAIN = 0, ORC_DEL_CONSERVATIVE = 1 };
+
+typedef struct orc_options {
+  int32_t mode;            /* ORC_MODE_* */
+  int32_t max_levels;      /* >= 1 */
+  int32_t max_sweeps;      /* >= 1 */
+  int32_t singleton_guard; /* 0/1 */
+  int32_t del_rule;        /* ORC_DEL_* */
+  int32_t pad;
+  int64_t tau_den;         /* T = floor((2m)^2 / tau_den); 0 means T = 0 */
+} orc_options;
+
+/* One record per executed sweep. */
+typedef struct orc_sweep_rec {
+  int32_t level;
+  int32_t sweep;
+  int32_t n_level;   /* vertices of the level graph */
+  int32_t n_active;  /* vertices evaluated */
+  int64_t nnz_level; /* stored CSR entries of the level graph */
+  int64_t moves;
+  int64_t dN;        /* exact change of N over the sweep */
+  int32_t kept;      /* 1 if applied, 0 if reverted */
+  int32_t pad;
+} orc_sweep_rec;
+
+typedef struct orc_step_info {
+  int64_t R_size;         /* |R_t| (n for ALL/STATIC) */
+  int64_t ds_sources;     /* addition sources examined */
+  int64_t ds_accepted;    /* addition sources whose test passed */
+  int64_t del_sources;    /* deletion sources examined (intra-community) */
+  int64_t del_accepted;
+  int32_t levels;         /* levels run */
+  int32_t n_sweeps;       /* records written */
+  int64_t N;              /* final exact numerator */
+  int64_t two_m;
+} orc_step_info;
+
+typedef struct orc_state orc_state;
+
+void orc_default_options(orc_options* o);
+
+/* Build G_1 from an undirected edge list (u != v, w >= 1, duplicates summed)
+ * and run the static method from singletons (Alg. 1).  C_out (n) receives
+ * the canonical labels; sweeps (capacity cap) receive the trace. */
+int32_t orc_init(orc_state** out, int32_t n, int64_t m, const int32_t* u,
+                 const int32_t* v, const int32_t* w, const orc_options* opt,
+                 int32_t* C_out, orc_sweep_rec* sweeps, int32_t cap,
+                 orc_step_info* info);
+
+/* One time step: validate, delete, insert, screen, levels, canonical labels.
+ * R_out (n, nullable) receives the screened set as 0/1 bytes. */
+int32_t orc_apply_batch(orc_state* s, int64_t na, const int32_t* au,
+                        const int32_t* av, const int32_t* aw, int64_t nd,
+                        const int32_t* du, const int32_t* dv, int32_t* C_out,
+                        uint8_t* R_out, orc_sweep_rec* sweeps, int32_t cap,
+                        orc_step_info* info);
+
+int32_t orc_modularity(const orc_state* s, int64_t* N, int64_t* two_m,
+                       double* q);
+int32_t orc_communities(const orc_state* s, int32_t* out);
+int64_t orc_num_entries(const orc_state* s); /* directed entries of G_t */
+/* Export G_t as a CSR (rows sorted by neighbour). off has n+1 entries. */
+int32_t orc_export_csr(const orc_state* s, int64_t* off, int32_t* col,
+                       int32_t* w);
+void orc_destroy(orc_state* s);
+
+/* ---- stateless building blocks exposed for the pin tests ---- */
+
+/* Exact numerator N = 2m*I - sum a^2 of a partition C on a CSR graph that may
+ * carry diagonal entries (coarse levels). */
+int32_t orc_csr_modularity(int32_t n, const int64_t* off, const int32_t* col,
+                           const int64_t* w, const int32_t* C, int64_t* N,
+                           int64_t* two_m);
+
+/* Scaled gain G(i -> D) for the partition C (0 when D == C(i)). */
+int64_t orc_csr_gain(int32_t n, const int64_t* off, const int32_t* col,
+                     const int64_t* w, const int32_t* C, int32_t i, int32_t D);
+
+/* Local-move decision of vertex i under partition C (singleton guard as
+ * given).  Returns the chosen label; *best_gain receives G of the best
+ * candidate other than C(i) (0 if none). */
+int32_t orc_csr_decide(int32_t n, const int64_t* off, const int32_t* col,
+                       const int64_t* w, const int32_t* C, int32_t i,
+                       int32_t guard, int64_t* best_gain);
+
+/* Run the level procedure once on a CSR graph from partition C (labels in
+ * [0,n)) with the given active flags; C receives canonical final labels. */
+int32_t orc_csr_run_levels(int32_t n, const int64_t* off, const int32_t* col,
+                           const int64_t* w, int32_t* C, const uint8_t* active,
+                           const orc_options* opt, orc_sweep_rec* sweeps,
+                           int32_t cap, int32_t* n_sweeps, int32_t* levels);
+
+/* Coarsen: returns the coarse CSR in caller buffers sized n_out<=n,
+ * nnz_out<=nnz.  rank[] (n) receives the coarse id of each label (-1 empty). */
+int32_t orc_csr_coarsen(int32_t n, const int64_t* off, const int32_t* col,
+                        const int64_t* w, const int32_t* C, int32_t* rank,
+                        int32_t* n_out, int64_t* off_out, int32_t* col_out,
+                        int64_t* w_out, int64_t* nnz_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

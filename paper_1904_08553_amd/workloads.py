@@ -1,0 +1,396 @@
+"""Seeded synthetic dynamic-graph workloads.
+
+This module only draws inputs: graphs and per-step batches of edge additions
+and deletions.  It holds none of the community-detection arithmetic, and both
+the HIP path and the CPU oracle consume exactly the arrays it returns.
+
+The shapes follow the paper's inputs (Sec. 4.1, Table 1): streaming
+stochastic-block-model graphs with random edge sampling, and a long temporal
+interaction stream with mostly intra-community, localised growth.  Those
+datasets are not reproduced; every input here is drawn from
+``numpy.random.Generator(PCG64)`` seeded by ``SeedSequence((seed, tag, step))``.
+
+Edges are canonical undirected pairs ``u < v`` with int32 ids and weights.
+A batch is ``Batch(add_u, add_v, add_w, del_u, del_v)``: deletions remove
+existing edges of the previous graph, insertions add edges absent from it.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def _rng(seed: int, *tags: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence((int(seed),) + tuple(int(t) for t in tags))))
+
+
+def _key(u, v):
+    u = np.asarray(u, np.int64)
+    v = np.asarray(v, np.int64)
+    lo = np.minimum(u, v)
+    hi = np.maximum(u, v)
+    return (lo << 32) | hi
+
+
+def _unkey(k):
+    k = np.asarray(k, np.int64)
+    return (k >> 32).astype(np.int32), (k & 0xFFFFFFFF).astype(np.int32)
+
+
+@dataclass
+class Batch:
+    add_u: np.ndarray
+    add_v: np.ndarray
+    add_w: np.ndarray
+    del_u: np.ndarray
+    del_v: np.ndarray
+
+    @property
+    def size(self) -> int:
+        return int(len(self.add_u) + len(self.del_u))
+
+
+@dataclass
+class EdgeSet:
+    """Sorted canonical keys of the current graph with aligned weights."""
+    keys: np.ndarray
+    w: np.ndarray
+
+    @staticmethod
+    def from_edges(u, v, w):
+        k = _key(u, v)
+        order = np.argsort(k, kind="stable")
+        return EdgeSet(k[order], np.asarray(w, np.int32)[order])
+
+    def __len__(self):
+        return len(self.keys)
+
+    def contains(self, k):
+        if len(self.keys) == 0:
+            return np.zeros(len(k), bool)
+        pos = np.searchsorted(self.keys, k)
+        pos = np.minimum(pos, len(self.keys) - 1)
+        return self.keys[pos] == k
+
+    def apply(self, b: Batch):
+        if len(b.del_u):
+            dk = np.sort(_key(b.del_u, b.del_v))
+            pos = np.searchsorted(self.keys, dk)
+            keep = np.ones(len(self.keys), bool)
+            keep[pos] = False
+            self.keys, self.w = self.keys[keep], self.w[keep]
+        if len(b.add_u):
+            ak = _key(b.add_u, b.add_v)
+            order = np.argsort(ak, kind="stable")
+            ak, aw = ak[order], np.asarray(b.add_w, np.int32)[order]
+            pos = np.searchsorted(self.keys, ak)
+            self.keys = np.insert(self.keys, pos, ak)
+            self.w = np.insert(self.w, pos, aw)
+
+    def edges(self):
+        u, v = _unkey(self.keys)
+        return u, v, self.w.copy()
+
+
+def _fresh_pairs(sampler, count, existing: EdgeSet, rng, max_rounds=64):
+    """Draw ``count`` distinct canonical non-self-loop pairs absent from
+    ``existing``; ``sampler(rng, k)`` returns candidate (u, v) arrays."""
+    got = np.empty(0, np.int64)
+    for _ in range(max_rounds):
+        need = count - len(got)
+        if need <= 0:
+            break
+        u, v = sampler(rng, int(need * 1.25) + 16)
+        ok = u != v
+        k = _key(u[ok], v[ok])
+        k = k[~existing.contains(k)]
+        k = k[~np.isin(k, got)]
+        _, first = np.unique(k, return_index=True)
+        k = k[np.sort(first)]
+        got = np.concatenate([got, k[:need]])
+    if len(got) < count:
+        raise RuntimeError("could not draw enough distinct new pairs")
+    return got
+
+
+def _pick_deletions(es: EdgeSet, count, rng):
+    count = min(int(count), len(es))
+    idx = rng.choice(len(es), size=count, replace=False)
+    return _unkey(es.keys[np.sort(idx)])
+
+
+# ---------------------------------------------------------------------------
+# Planted partition (equal blocks), the small stand-in for the streaming SBM
+# inputs.
+
+
+@dataclass
+class PlantedPartition:
+    n: int = 2000
+    blocks: int = 20
+    p_in: float = 0.05
+    p_out: float = 0.001
+    seed: int = 0
+    block_of: np.ndarray = field(default=None, repr=False)
+
+    def __post_init__(self):
+        rng = _rng(self.seed, 1)
+        perm = rng.permutation(self.n)
+        bsz = self.n // self.blocks
+        self.block_of = np.minimum(perm // bsz, self.blocks - 1).astype(np.int32)
+        self.order = np.argsort(self.block_of, kind="stable").astype(np.int32)
+        counts = np.bincount(self.block_of, minlength=self.blocks)
+        self.bstart = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self.members = [self.order[self.bstart[b]:self.bstart[b + 1]] for b in range(self.blocks)]
+
+    def graph(self):
+        rng = _rng(self.seed, 2)
+        keys = []
+        for b in range(self.blocks):
+            mem = self.members[b]
+            iu, ju = np.triu_indices(len(mem), 1)
+            m = rng.random(len(iu)) < self.p_in
+            keys.append(_key(mem[iu[m]], mem[ju[m]]))
+        sizes = np.array([len(m) for m in self.members], np.int64)
+        inter_pairs = (self.n * (self.n - 1)) // 2 - int((sizes * (sizes - 1) // 2).sum())
+        n_inter = rng.binomial(inter_pairs, self.p_out)
+        intra = np.concatenate(keys) if keys else np.empty(0, np.int64)
+        es = EdgeSet.from_edges(*_unkey(intra), np.ones(len(intra), np.int32))
+        inter = _fresh_pairs(self._inter_sampler, n_inter, es, rng)
+        k = np.concatenate([intra, inter])
+        u, v = _unkey(np.sort(k))
+        return u, v, np.ones(len(u), np.int32)
+
+    def _intra_sampler(self, rng, k):
+        b = rng.integers(0, self.blocks, size=k)
+        sz = self.bstart[b + 1] - self.bstart[b]
+        i = (rng.random(k) * sz).astype(np.int64)
+        j = (rng.random(k) * (sz - 1)).astype(np.int64)
+        j = j + (j >= i)
+        return self.order[self.bstart[b] + i], self.order[self.bstart[b] + j]
+
+    def _inter_sampler(self, rng, k):
+        u = rng.integers(0, self.n, size=k).astype(np.int32)
+        v = rng.integers(0, self.n, size=k).astype(np.int32)
+        ok = self.block_of[u] != self.block_of[v]
+        return u[ok], v[ok]
+
+    def batches(self, steps=4, n_ins=500, intra_frac=0.7, n_del=200, weight=None):
+        """Per step: ``n_ins`` insertions of non-edges (``intra_frac`` inside
+        a block) and ``n_del`` deletions uniform over the current edges."""
+        u, v, w = self.graph()
+        es = EdgeSet.from_edges(u, v, w)
+        out = []
+        for t in range(steps):
+            rng = _rng(self.seed, 3, t)
+            du, dv = _pick_deletions(es, n_del, rng)
+            n_intra = int(round(n_ins * intra_frac))
+            ki = _fresh_pairs(self._intra_sampler, n_intra, es, rng)
+            tmp = EdgeSet(np.sort(np.concatenate([es.keys, ki])), np.zeros(len(es) + len(ki), np.int32))
+            ko = _fresh_pairs(self._inter_sampler, n_ins - n_intra, tmp, rng)
+            k = np.concatenate([ki, ko])
+            au, av = _unkey(k)
+            aw = np.ones(len(k), np.int32) if weight is None else rng.integers(1, weight + 1, len(k)).astype(np.int32)
+            b = Batch(au, av, aw, du, dv)
+            es.apply(b)
+            out.append(b)
+        return (u, v, w), out
+
+
+# ---------------------------------------------------------------------------
+# Degree-corrected SBM with power-law propensities and Zipf block sizes.
+
+
+def _powerlaw_int(rng, n, gamma, lo, hi):
+    d = np.arange(lo, hi + 1, dtype=np.float64)
+    p = d ** (-gamma)
+    cdf = np.cumsum(p)
+    cdf /= cdf[-1]
+    return (lo + np.searchsorted(cdf, rng.random(n), side="right")).astype(np.float64)
+
+
+def _zipf_sizes(n, blocks, s):
+    """Block sizes proportional to rank^(-s), each at least 1, summing to n."""
+    r = np.arange(1, blocks + 1, dtype=np.float64) ** (-s)
+    raw = r / r.sum() * n
+    sz = np.maximum(np.floor(raw).astype(np.int64), 1)
+    diff = n - int(sz.sum())
+    if diff > 0:
+        frac = raw - np.floor(raw)
+        sz[np.argsort(-frac, kind="stable")[:diff]] += 1
+    elif diff < 0:
+        sz[0] += diff  # the largest block absorbs the excess of the minimum-1 rule
+    return sz
+
+
+@dataclass
+class DCSBM:
+    n: int = 1_000_000
+    m: int = 20_000_000
+    blocks: int = 1000
+    zipf_s: float = 1.1
+    gamma: float = 2.3
+    dmin: int = 4
+    dmax: int = 5000
+    mixing: float = 0.2
+    wmax: int = 8
+    seed: int = 0
+
+    def __post_init__(self):
+        rng = _rng(self.seed, 11)
+        self.theta = _powerlaw_int(rng, self.n, self.gamma, self.dmin, self.dmax)
+        sizes = _zipf_sizes(self.n, self.blocks, self.zipf_s)
+        perm = rng.permutation(self.n)
+        self.block_of = np.empty(self.n, np.int32)
+        self.block_of[perm] = np.repeat(np.arange(self.blocks, dtype=np.int32), sizes)
+        self._index()
+
+    def _index(self):
+        order = np.argsort(self.block_of, kind="stable").astype(np.int32)
+        self.order = order
+        th = self.theta[order]
+        self.cum_sorted = np.cumsum(th)
+        counts = np.bincount(self.block_of, minlength=self.blocks)
+        self.bstart = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        csum = np.concatenate([[0.0], self.cum_sorted])
+        self.bmass_lo = csum[self.bstart[:-1]]
+        self.bmass_hi = csum[self.bstart[1:]]
+        self.cum_all = np.cumsum(self.theta)
+
+    def _draw_global(self, rng, k):
+        x = rng.random(k) * self.cum_all[-1]
+        return np.minimum(np.searchsorted(self.cum_all, x, side="right"), self.n - 1).astype(np.int32)
+
+    def _draw_in_block(self, rng, b):
+        lo, hi = self.bmass_lo[b], self.bmass_hi[b]
+        x = lo + rng.random(len(b)) * (hi - lo)
+        pos = np.searchsorted(self.cum_sorted, x, side="right")
+        pos = np.clip(pos, self.bstart[b], self.bstart[b + 1] - 1)
+        return self.order[pos]
+
+    def _sampler(self, rng, k):
+        u = self._draw_global(rng, k)
+        inside = rng.random(k) >= self.mixing
+        v = np.empty(k, np.int32)
+        v[inside] = self._draw_in_block(rng, self.block_of[u[inside]])
+        out_idx = np.flatnonzero(~inside)
+        vo = self._draw_global(rng, len(out_idx))
+        same = self.block_of[vo] == self.block_of[u[out_idx]]
+        for _ in range(64):
+            if not same.any():
+                break
+            vo[same] = self._draw_global(rng, int(same.sum()))
+            same = self.block_of[vo] == self.block_of[u[out_idx]]
+        v[out_idx] = vo
+        keep = np.ones(k, bool)
+        keep[out_idx[same]] = False  # a pair still inside one block is dropped
+        return u[keep], v[keep]
+
+    def graph(self):
+        rng = _rng(self.seed, 12)
+        empty = EdgeSet(np.empty(0, np.int64), np.empty(0, np.int32))
+        k = np.sort(_fresh_pairs(self._sampler, self.m, empty, rng))
+        u, v = _unkey(k)
+        w = rng.integers(1, self.wmax + 1, len(k)).astype(np.int32) if self.wmax > 1 else np.ones(len(k), np.int32)
+        return u, v, w
+
+    def next_batch(self, es: EdgeSet, t: int, frac=0.01, ins_frac=0.6):
+        rng = _rng(self.seed, 13, t)
+        total = int(round(len(es) * frac))
+        n_ins = int(round(total * ins_frac))
+        n_del = total - n_ins
+        du, dv = _pick_deletions(es, n_del, rng)
+        k = _fresh_pairs(self._sampler, n_ins, es, rng)
+        au, av = _unkey(k)
+        aw = rng.integers(1, self.wmax + 1, len(k)).astype(np.int32) if self.wmax > 1 else np.ones(len(k), np.int32)
+        return Batch(au, av, aw, du, dv)
+
+    def stream(self, steps, frac=0.01, ins_frac=0.6):
+        """Initial graph plus ``steps`` batches; yields batches lazily."""
+        u, v, w = self.graph()
+        es = EdgeSet.from_edges(u, v, w)
+
+        def gen():
+            for t in range(steps):
+                b = self.next_batch(es, t, frac, ins_frac)
+                es.apply(b)
+                yield b
+
+        return (u, v, w), gen()
+
+    def drift(self, t, frac):
+        """Reassign ``frac`` of the vertices to blocks drawn by size."""
+        rng = _rng(self.seed, 14, t)
+        k = int(round(self.n * frac))
+        who = rng.choice(self.n, size=k, replace=False)
+        counts = np.bincount(self.block_of, minlength=self.blocks).astype(np.float64)
+        cdf = np.cumsum(counts)
+        cdf /= cdf[-1]
+        nb = np.minimum(np.searchsorted(cdf, rng.random(k), side="right"), self.blocks - 1)
+        self.block_of[who] = nb.astype(np.int32)
+        self._index()
+
+
+def temporal_stream(n=8_000_000, events=63_000_000, steps=12, ins_frac=0.85,
+                    blocks=8000, gamma=2.1, dmin=2, dmax=100_000, mixing=0.2,
+                    drift=0.02, seed=0):
+    """Temporal interaction stream with ``events`` unit-weight edge events in
+    ``steps`` equal steps.  Step 1 holds insertions only (the initial graph);
+    later steps hold ``ins_frac`` insertions and deletions of edges alive
+    before the step, and ``drift`` of the vertices change block first."""
+    g = DCSBM(n=n, m=0, blocks=blocks, gamma=gamma, dmin=dmin, dmax=dmax,
+              mixing=mixing, wmax=1, seed=seed)
+    per = events // steps
+    rng = _rng(seed, 21)
+    empty = EdgeSet(np.empty(0, np.int64), np.empty(0, np.int32))
+    k = np.sort(_fresh_pairs(g._sampler, per, empty, rng))
+    u, v = _unkey(k)
+    w = np.ones(len(k), np.int32)
+    es = EdgeSet(k, w.copy())
+
+    def gen():
+        for t in range(1, steps):
+            g.drift(t, drift)
+            r = _rng(seed, 22, t)
+            n_ins = int(round(per * ins_frac))
+            n_del = per - n_ins
+            du, dv = _pick_deletions(es, n_del, r)
+            kk = _fresh_pairs(g._sampler, n_ins, es, r)
+            au, av = _unkey(kk)
+            b = Batch(au, av, np.ones(len(kk), np.int32), du, dv)
+            es.apply(b)
+            yield b
+
+    return (u, v, w), gen()
+
+
+# ---------------------------------------------------------------------------
+# Small random dynamic graphs for exhaustive checks.
+
+
+def random_dynamic(n, m, steps, n_add, n_del, seed, wmax=3):
+    """Uniform random graph and batches (used for tiny exhaustive tests)."""
+    rng = _rng(seed, 31)
+    full = n * (n - 1) // 2
+    m = min(m, full)
+    iu, ju = np.triu_indices(n, 1)
+    pick = rng.choice(full, size=m, replace=False)
+    u, v = iu[pick].astype(np.int32), ju[pick].astype(np.int32)
+    w = rng.integers(1, wmax + 1, m).astype(np.int32)
+    es = EdgeSet.from_edges(u, v, w)
+    out = []
+    for t in range(steps):
+        r = _rng(seed, 32, t)
+        du, dv = _pick_deletions(es, min(n_del, len(es)), r)
+        present = set(es.keys.tolist())
+        cand = [(a, b) for a, b in zip(iu.tolist(), ju.tolist()) if ((a << 32) | b) not in present]
+        na = min(n_add, len(cand))
+        sel = r.choice(len(cand), size=na, replace=False) if na else np.empty(0, np.int64)
+        au = np.array([cand[s][0] for s in sel], np.int32)
+        av = np.array([cand[s][1] for s in sel], np.int32)
+        aw = r.integers(1, wmax + 1, na).astype(np.int32)
+        b = Batch(au, av, aw, du, dv)
+        es.apply(b)
+        out.append(b)
+    return (u, v, w), out

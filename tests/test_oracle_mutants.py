@@ -1,0 +1,47 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check
+that the pin suite rejects every one of them."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dc_oracle.c")
+
+MUTANTS = {
+    "own-community total keeps i": ("return two_m * e - ki * (own ? aX - ki : aX);",
+                                    "return two_m * e - ki * aX;"),
+    "ties to the larger label": ("(s == bs && X < best)", "(s == bs && X > best)"),
+    "self-loop counted in e": ("    if (v == i) continue;\n    int32_t X = C[v];",
+                               "    int32_t X = C[v];"),
+    "numerator without 2m": ("return two_m * I - S;", "return I - S;"),
+    "guard inverted": ("size[best] == 1 && best > c", "size[best] == 1 && best < c"),
+    "no revert of a losing sweep": ("if (dN < 0) break; /* revert", "if (0) break; /* revert"),
+    "level 0 ignores R": ("level == 0 ? active0 : all", "all"),
+    "Alg. 2 without gain2 test": ("if (g1 >= g2 && g1 > 0) {", "if (g1 > 0) {"),
+    "Alg. 2 forgets Gamma(i)": ("      R[jstar] = 1;\n      for (int64_t e = g->off[i]; e < g->off[i + 1]; ++e) R[g->col[e]] = 1;",
+                                "      R[jstar] = 1;"),
+    "Alg. 2 forgets C(j*)": ("      cflag[cj] = 1;", "      (void)cj;"),
+    "coarsening drops the diagonal": ("          int32_t Y = rank[C[g->col[e]]];\n",
+                                      "          int32_t Y = rank[C[g->col[e]]];\n          if (Y == r) continue;\n"),
+    "deletion rule off": ("    if (d != C[i]) {\n      if (info) info->del_accepted++;",
+                          "    if (0) {\n      if (info) info->del_accepted++;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name!r} not unique"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-I", os.path.join(ROOT, "oracle"),
+                    "-o", str(so), str(mut)], check=True)
+    env = dict(os.environ, DC_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins did not catch mutant {name!r}:\n{r.stdout[-2000:]}"

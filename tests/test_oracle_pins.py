@@ -1,0 +1,390 @@
+"""Pins of the CPU oracle to things other than itself.
+
+* Eq. (1) (Sec. 3.1) by brute force over every partition of small graphs, in
+  exact rationals, plus closed forms;
+* the scaled gain against the exact change of Eq. (1) and against the gain
+  algebra printed in Appendix A (Lemma 3.2 and Lemma 3.4 (B)/(C));
+* whole traces against the spec-literal rational implementation
+  (tests/spec_literal.py), which derives every gain by recomputing Eq. (1);
+* invariants and special cases of Alg. 1 and Alg. 2.
+"""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import spec_literal as L
+
+
+def csr_from_adj(adj):
+    n = len(adj)
+    off = [0]
+    col, w = [], []
+    for i in range(n):
+        for j in sorted(adj[i]):
+            col.append(j)
+            w.append(adj[i][j])
+        off.append(len(col))
+    return np.array(off, np.int64), np.array(col, np.int32), np.array(w, np.int64)
+
+
+def rand_adj(rng, n, p, wmax=4, selfloops=False):
+    adj = {i: {} for i in range(n)}
+    for i in range(n):
+        for j in range(i + 1, n):
+            if rng.random() < p:
+                x = int(rng.integers(1, wmax + 1))
+                adj[i][j] = x
+                adj[j][i] = x
+        if selfloops and rng.random() < 0.5:
+            adj[i][i] = 2 * int(rng.integers(1, wmax + 1))  # coarse diagonal: even
+    return adj
+
+
+def set_partitions(n):
+    """Restricted growth strings: every set partition of range(n) once."""
+    def rec(prefix, mx):
+        if len(prefix) == n:
+            yield list(prefix)
+            return
+        for b in range(mx + 2):
+            prefix.append(b)
+            yield from rec(prefix, max(mx, b))
+            prefix.pop()
+    yield from rec([], -1)
+
+
+def Q_of(N, tm):
+    return Fraction(0) if tm == 0 else Fraction(N, tm * tm)
+
+
+# --------------------------------------------------------------------------
+# Eq. (1)
+
+
+@pytest.mark.parametrize("seed,n,selfloops", [(1, 6, False), (2, 7, False), (3, 8, False),
+                                              (4, 7, True), (5, 8, True)])
+def test_modularity_brute_force(oracle_mod, seed, n, selfloops):
+    rng = np.random.default_rng(seed)
+    adj = rand_adj(rng, n, 0.45, selfloops=selfloops)
+    off, col, w = csr_from_adj(adj)
+    best = None
+    count = 0
+    for part in set_partitions(n):
+        C = np.array(part, np.int32)
+        N, tm = oracle_mod.csr_modularity(off, col, w, C)
+        q = L.modularity(adj, {i: part[i] for i in range(n)})
+        assert Q_of(N, tm) == q
+        best = q if best is None else max(best, q)
+        count += 1
+    assert count == [1, 1, 2, 5, 15, 52, 203, 877, 4140][n]
+    # the heuristic can never beat the exhaustive optimum
+    C, _, _ = oracle_mod.csr_run_levels(off, col, w, np.arange(n, dtype=np.int32))
+    N, tm = oracle_mod.csr_modularity(off, col, w, C)
+    assert Q_of(N, tm) <= best
+
+
+def test_modularity_closed_forms(oracle_mod):
+    # two disjoint cliques K5, each its own community: Q = 1/2
+    adj = {i: {} for i in range(10)}
+    for base in (0, 5):
+        for i, j in itertools.combinations(range(base, base + 5), 2):
+            adj[i][j] = adj[j][i] = 1
+    off, col, w = csr_from_adj(adj)
+    N, tm = oracle_mod.csr_modularity(off, col, w, np.array([0] * 5 + [5] * 5, np.int32))
+    assert Q_of(N, tm) == Fraction(1, 2)
+    # one community: Q = 0
+    N, tm = oracle_mod.csr_modularity(off, col, w, np.zeros(10, np.int32))
+    assert N == 0
+    # singletons: Q = -sum k^2 / (2m)^2
+    N, tm = oracle_mod.csr_modularity(off, col, w, np.arange(10, dtype=np.int32))
+    k = np.diff(off) * 1
+    assert N == -int((k.astype(np.int64) ** 2).sum())
+    # the method finds the two cliques
+    C, _, _ = oracle_mod.csr_run_levels(off, col, w, np.arange(10, dtype=np.int32))
+    assert list(C) == [0] * 5 + [5] * 5
+    # empty graph: Q = 0
+    off0 = np.zeros(5, np.int64)
+    N, tm = oracle_mod.csr_modularity(off0, np.zeros(0, np.int32), np.zeros(0, np.int64),
+                                      np.arange(4, dtype=np.int32))
+    assert (N, tm) == (0, 0)
+
+
+# --------------------------------------------------------------------------
+# gain
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gain_is_half_exact_delta_N(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 9
+    adj = rand_adj(rng, n, 0.4, selfloops=(seed % 2 == 1))
+    off, col, w = csr_from_adj(adj)
+    for _ in range(40):
+        C = rng.integers(0, 4, n).astype(np.int32)
+        i = int(rng.integers(n))
+        D = int(rng.integers(0, 5))
+        G = oracle_mod.csr_gain(off, col, w, C, i, D)
+        N0, tm = oracle_mod.csr_modularity(off, col, w, C)
+        C2 = C.copy()
+        C2[i] = D
+        N1, _ = oracle_mod.csr_modularity(off, col, w, C2)
+        assert N1 - N0 == 2 * G
+        # and the rational gain of Eq. (1)
+        dq = L.gain(adj, {x: int(C[x]) for x in range(n)}, i, D)
+        assert dq * tm * tm == 2 * G
+
+
+def _gains(oracle_mod, off, col, w, C, v, D):
+    return oracle_mod.csr_gain(off, col, w, C, v, D)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_appendix_a_lemma_deltas(oracle_mod, seed):
+    """Appendix A: moving i into C(j*) lowers G(i2 -> C(j*)) by exactly
+    2 k_i2 k_i for i2 in C(i) outside Gamma(i) (Lemma 3.2), lowers
+    G(k -> C(j*)) by k_k k_i for k outside Gamma(i), C(i), C(j*) (Lemma 3.4 B),
+    leaves G(k -> X) unchanged for other targets X (Lemma 3.4 C), and raises
+    G(k -> C(i)) by k_k k_i (the exact form of C)."""
+    rng = np.random.default_rng(200 + seed)
+    n = 14
+    adj = rand_adj(rng, n, 0.3)
+    off, col, w = csr_from_adj(adj)
+    k = np.array([sum(adj[x].values()) for x in range(n)], np.int64)
+    checked = 0
+    for _ in range(60):
+        C = rng.integers(0, 4, n).astype(np.int32)
+        i = int(rng.integers(n))
+        D = int(C[int(rng.integers(n))])
+        if D == C[i]:
+            continue
+        C2 = C.copy()
+        C2[i] = D
+        ci = int(C[i])
+        for v in range(n):
+            if v == i or v in adj[i]:
+                continue
+            if C[v] == ci:  # Lemma 3.2
+                before = _gains(oracle_mod, off, col, w, C, v, D)
+                after = _gains(oracle_mod, off, col, w, C2, v, D)
+                assert after - before == -2 * k[v] * k[i]
+                checked += 1
+            elif C[v] != D:  # Lemma 3.4
+                before = _gains(oracle_mod, off, col, w, C, v, D)
+                after = _gains(oracle_mod, off, col, w, C2, v, D)
+                assert after - before == -k[v] * k[i]
+                for X in range(5):
+                    if X in (ci, D, int(C[v])):
+                        continue
+                    assert _gains(oracle_mod, off, col, w, C2, v, X) == _gains(oracle_mod, off, col, w, C, v, X)
+                b = _gains(oracle_mod, off, col, w, C, v, ci)
+                a = _gains(oracle_mod, off, col, w, C2, v, ci)
+                assert a - b == k[v] * k[i]
+                checked += 1
+    assert checked > 20
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_decide_matches_literal(oracle_mod, seed):
+    rng = np.random.default_rng(300 + seed)
+    n = 10
+    adj = rand_adj(rng, n, 0.35, selfloops=(seed % 2 == 0))
+    off, col, w = csr_from_adj(adj)
+    for _ in range(30):
+        C = rng.integers(0, 6, n).astype(np.int32)
+        Cd = {x: int(C[x]) for x in range(n)}
+        for i in range(n):
+            for guard in (0, 1):
+                d, bg = oracle_mod.csr_decide(off, col, w, C, i, guard)
+                dl, bl = L.decide(adj, Cd, i, bool(guard))
+                assert d == dl
+                _, tm = oracle_mod.csr_modularity(off, col, w, C)
+                assert Fraction(2 * bg) == bl * tm * tm
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 invariants
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_coarsening_preserves_N(oracle_mod, seed):
+    rng = np.random.default_rng(400 + seed)
+    n = 30
+    adj = rand_adj(rng, n, 0.15, selfloops=(seed % 2 == 1))
+    off, col, w = csr_from_adj(adj)
+    C = rng.integers(0, 8, n).astype(np.int32)
+    rank, o2, c2, w2 = oracle_mod.csr_coarsen(off, col, w, C)
+    N, tm = oracle_mod.csr_modularity(off, col, w, C)
+    N2, tm2 = oracle_mod.csr_modularity(o2, c2, w2, np.arange(len(o2) - 1, dtype=np.int32))
+    assert (N, tm) == (N2, tm2)
+    # coarse weights are exact block sums of A
+    H, rk = L.coarsen(adj, {x: int(C[x]) for x in range(n)})
+    for a in H:
+        row = dict(zip(c2[o2[a]:o2[a + 1]].tolist(), w2[o2[a]:o2[a + 1]].tolist()))
+        assert row == H[a]
+    assert all(rank[x] == rk[x] for x in rk)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_kept_sweeps_never_lower_N_and_final_is_local_optimum(oracle_mod, seed):
+    rng = np.random.default_rng(500 + seed)
+    n = 60
+    adj = rand_adj(rng, n, 0.08)
+    off, col, w = csr_from_adj(adj)
+    C, trace, _ = oracle_mod.csr_run_levels(off, col, w, np.arange(n, dtype=np.int32),
+                                            max_levels=1, tau_den=0)
+    for rec in trace:
+        if rec[7]:
+            assert rec[6] >= 0
+    if trace[-1][5] == 0:  # stopped on a sweep without moves
+        for i in range(n):
+            d, _ = oracle_mod.csr_decide(off, col, w, C, i, 1)
+            assert d == C[i]
+
+
+def test_k2_merges_in_one_sweep_with_guard(oracle_mod):
+    off = np.array([0, 1, 2], np.int64)
+    col = np.array([1, 0], np.int32)
+    w = np.array([1, 1], np.int64)
+    C, trace, _ = oracle_mod.csr_run_levels(off, col, w, np.arange(2, dtype=np.int32), max_levels=1)
+    assert list(C) == [0, 0]
+    assert trace[0][5] == 1  # only vertex 1 moves (toward the smaller label)
+    # without the guard both singletons swap labels and nothing merges
+    C, trace, _ = oracle_mod.csr_run_levels(off, col, w, np.arange(2, dtype=np.int32), max_levels=1,
+                                            singleton_guard=0)
+    assert list(C) == [0, 1]
+    assert trace[0][5] == 2 and trace[0][6] == 0
+
+
+# --------------------------------------------------------------------------
+# whole dynamic traces against the spec-literal reading
+
+
+def _strip(trace):
+    return [(r[0], r[1], r[2], r[3], r[5], r[6], r[7]) for r in trace]
+
+
+CASES = [
+    dict(mode="delta", del_rule="gain", max_levels=32, guard=True),
+    dict(mode="delta", del_rule="conservative", max_levels=2, guard=True),
+    dict(mode="all", del_rule="gain", max_levels=32, guard=True),
+    dict(mode="static", del_rule="gain", max_levels=3, guard=True),
+    dict(mode="delta", del_rule="gain", max_levels=1, guard=False),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("seed", range(6))
+def test_oracle_matches_literal_traces(oracle_mod, case, seed):
+    from paper_1904_08553_amd import workloads as W
+    cfg = CASES[case]
+    n = 9 + (seed % 4)
+    (u, v, w), batches = W.random_dynamic(n, 2 * n, 3, 4, 2, seed=1000 + seed)
+    modes = {"delta": 0, "all": 1, "static": 2}
+    o = oracle_mod.Oracle(n, u, v, w, mode=modes[cfg["mode"]], max_levels=cfg["max_levels"],
+                          singleton_guard=int(cfg["guard"]),
+                          del_rule=0 if cfg["del_rule"] == "gain" else 1)
+    lit = L.Literal(n, u, v, w, mode=cfg["mode"], del_rule=cfg["del_rule"],
+                    max_levels=cfg["max_levels"], guard=cfg["guard"])
+    assert list(o.C) == [lit.C[i] for i in range(n)]
+    assert _strip(o.trace) == lit.trace
+    for b in batches:
+        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        lit.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        assert list(o.C) == [lit.C[i] for i in range(n)]
+        assert set(np.flatnonzero(o.R).tolist()) == lit.R
+        assert _strip(o.trace) == lit.trace
+        q, N, tm = o.modularity()
+        assert Q_of(N, tm) == lit.modularity()
+
+
+def test_planted_partition_step_matches_literal(oracle_mod):
+    """A 60-vertex planted partition with ~0.7 intra insertions per step."""
+    from paper_1904_08553_amd import workloads as W
+    pp = W.PlantedPartition(n=60, blocks=4, p_in=0.3, p_out=0.02, seed=7)
+    (u, v, w), batches = pp.batches(steps=3, n_ins=8, n_del=4)
+    o = oracle_mod.Oracle(60, u, v, w)
+    lit = L.Literal(60, u, v, w)
+    assert list(o.C) == [lit.C[i] for i in range(60)]
+    for b in batches:
+        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        lit.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        assert list(o.C) == [lit.C[i] for i in range(60)]
+        assert set(np.flatnonzero(o.R).tolist()) == lit.R
+
+
+# --------------------------------------------------------------------------
+# Alg. 2 special cases
+
+
+def test_intra_only_additions_screen_nothing(oracle_mod):
+    """Sec. 4.2: intra-community additions leave R_t empty (gain1 = 0)."""
+    adj = {i: {} for i in range(10)}
+    for base in (0, 5):
+        for i, j in itertools.combinations(range(base, base + 5), 2):
+            if (i + j) % 3:
+                adj[i][j] = adj[j][i] = 1
+    u = [i for i in adj for j in adj[i] if i < j]
+    v = [j for i in adj for j in adj[i] if i < j]
+    o = oracle_mod.Oracle(10, u, v, [1] * len(u))
+    assert list(o.C) == [0] * 5 + [5] * 5
+    missing = [(i, j) for i, j in itertools.combinations(range(5), 2) if j not in adj[i]]
+    au = [p[0] for p in missing]
+    av = [p[1] for p in missing]
+    o.apply_batch(au, av, [1] * len(au))
+    assert o.R.sum() == 0
+    assert o.info.ds_accepted == 0
+
+
+def test_accepted_source_pulls_neighbourhood_and_target_community(oracle_mod):
+    rng = np.random.default_rng(9)
+    from paper_1904_08553_amd import workloads as W
+    for seed in range(20):
+        (u, v, w), batches = W.random_dynamic(16, 24, 1, 3, 0, seed=2000 + seed)
+        o = oracle_mod.Oracle(16, u, v, w)
+        Cprev = o.C.copy()
+        b = batches[0]
+        o.apply_batch(b.add_u, b.add_v, b.add_w)
+        adj = L.adjacency(16, np.concatenate([u, b.add_u]), np.concatenate([v, b.add_v]),
+                          np.concatenate([w, b.add_w]))
+        Cd = {x: int(Cprev[x]) for x in range(16)}
+        R = set(np.flatnonzero(o.R).tolist())
+        for i, j in zip(b.add_u.tolist(), b.add_v.tolist()):
+            for src, snk in ((i, j), (j, i)):
+                g1 = L.gain(adj, Cd, src, Cd[snk])
+                if g1 > 0 and g1 >= L.gain(adj, Cd, snk, Cd[src]):
+                    # some sink was accepted for this source: i and Gamma(i) are in R
+                    assert src in R and set(adj[src]) <= R
+    del rng
+
+
+# --------------------------------------------------------------------------
+# batch validation
+
+
+def test_batch_errors_leave_state_unchanged(oracle_mod):
+    O = oracle_mod
+    u, v, w = [0, 1, 2], [1, 2, 3], [1, 1, 1]
+    o = O.Oracle(5, u, v, w)
+    C0 = o.C.copy()
+    q0 = o.modularity()
+    bad = [
+        (dict(add_u=[0], add_v=[7], add_w=[1]), -2),
+        (dict(del_u=[-1], del_v=[2]), -2),
+        (dict(add_u=[3], add_v=[3], add_w=[1]), -3),
+        (dict(add_u=[3], add_v=[4], add_w=[0]), -4),
+        (dict(del_u=[0, 1], del_v=[1, 0]), -6),
+        (dict(del_u=[0], del_v=[4]), -5),
+        (dict(add_u=[3], add_v=[4], add_w=[2 ** 30]), -7),
+    ]
+    for kw, code in bad:
+        with pytest.raises(O.OracleError) as e:
+            o.apply_batch(**kw)
+        assert e.value.status == code
+        assert list(o.communities()) == list(C0)
+        assert o.modularity() == q0
+    # delete then re-add the same pair in one batch replaces the weight
+    o.apply_batch(add_u=[0], add_v=[1], add_w=[5], del_u=[1], del_v=[0])
+    off, col, ww = o.csr()
+    assert ww[off[0]:off[1]][list(col[off[0]:off[1]]).index(1)] == 5
