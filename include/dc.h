@@ -1,0 +1,203 @@
+/*
+ * dc.h -- C ABI of the MI355X (gfx950) library for Delta-screening incremental
+ * dynamic community detection (Zarayeneh & Kalyanaraman, "A Fast and
+ * Efficient Incremental Approach toward Dynamic Community Detection",
+ * arXiv 1904.08553).
+ *
+ * Problem (Sec. 3.2, Definition 3.1): given a dynamic graph G_1..G_T, report
+ * at every time step a partition C_t of the vertices that maximises the
+ * modularity Q_t of Eq. (1).  The incremental procedure of Sec. 3.4 is
+ * followed: Static(G_1) at t = 1, and for t > 1 the previous labels are
+ * inherited, Delta-screening (Alg. 2, Sec. 3.5) selects R_t from the batch,
+ * and the multi-level local-moving method (Alg. 1) evaluates only R_t at its
+ * first level.
+ *
+ * Conventions
+ *   - Every call returns a dc_status: 0 on success, a negative code on error.
+ *     No call throws.  A failing dc_apply_batch leaves the context exactly as
+ *     it was (checks run before anything is changed) except DC_E_DEVICE, after
+ *     which the context refuses further work with DC_E_STATE.
+ *   - Vertices are int32 ids in [0, n); n is fixed by dc_init.  Edges are
+ *     undirected, without self-loops, with int32 weights >= 1.  The total
+ *     weight 2m must stay below 2^31, so every gain fits int64 exactly.
+ *   - Pointer arguments are borrowed for the duration of the call only; the
+ *     context owns all device memory it allocates (hipMalloc) and frees it in
+ *     dc_destroy.  Input arrays may live on the host or on the device
+ *     (dc_edges.on_device).  All device work is enqueued on the stream given
+ *     in dc_options.stream (a hipStream_t; NULL = the default stream) and
+ *     every call returns after its results are written (stream-synchronous).
+ *   - One context per host thread at a time.
+ */
+#ifndef DC_H
+#define DC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dc_status;
+
+enum {
+  DC_OK = 0,
+  DC_E_ARG = -1,       /* null pointer, bad size or bad option            */
+  DC_E_RANGE = -2,     /* a vertex id outside [0, n)                       */
+  DC_E_SELF_LOOP = -3, /* an edge (v, v)                                   */
+  DC_E_WEIGHT = -4,    /* an insertion weight < 1                          */
+  DC_E_NO_EDGE = -5,   /* a deletion of an edge absent from G_{t-1}        */
+  DC_E_DUP = -6,       /* the same undirected pair deleted twice           */
+  DC_E_OVERFLOW = -7,  /* 2m would reach 2^31                              */
+  DC_E_OOM = -8,       /* device allocation failed                         */
+  DC_E_DEVICE = -9,    /* a HIP call failed; the context is poisoned       */
+  DC_E_STATE = -10     /* the context was poisoned by an earlier failure   */
+};
+
+/* How the first level chooses its start partition and its active set. */
+enum {
+  DC_MODE_DELTA = 0,  /* inherit C_{t-1}; level 0 visits R_t from Alg. 2 */
+  DC_MODE_ALL = 1,    /* inherit C_{t-1}; level 0 visits every vertex (the
+                         baseline of Sec. 3.4 with R_t = V_t)            */
+  DC_MODE_STATIC = 2  /* restart from singletons (naive rerun, Sec. 3.3)  */
+};
+
+/* Deletions are outside the paper (Sec. 5 lists them as future work). */
+enum {
+  DC_DEL_GAIN = 0,        /* a source of an intra-community deletion joins R
+                             with Gamma(i) and its best community only when
+                             its best move has a positive gain              */
+  DC_DEL_CONSERVATIVE = 1 /* every such source joins R with Gamma(i)       */
+};
+
+typedef struct dc_options {
+  int32_t mode;            /* DC_MODE_*; default DELTA                       */
+  int32_t max_levels;      /* >= 1; default 32 (levels 0..max_levels-1)     */
+  int32_t max_sweeps;      /* >= 1 sweeps per level; default 100            */
+  int32_t singleton_guard; /* 1: two singletons merge only toward the
+                              smaller label; default 1                      */
+  int32_t del_rule;        /* DC_DEL_*; default GAIN                         */
+  int32_t timing;          /* 1: time the level sweeps with hipEvents and
+                              report them in dc_step_stats                  */
+  int64_t tau_den;         /* a sweep gaining at most floor((2m)^2/tau_den)
+                              in the exact numerator ends the level (the
+                              threshold tau of Sec. 3.2); 0 = threshold 0;
+                              default 10^6                                 */
+  void* stream;            /* hipStream_t for all work; NULL = default       */
+  int64_t reserved[4];     /* must be zero                                   */
+} dc_options;
+
+/* An edge list: count entries (u[e], v[e], w[e]).  w is ignored (may be
+ * NULL) for deletions.  on_device = 1 when the arrays are device pointers. */
+typedef struct dc_edges {
+  int64_t count;
+  const int32_t* u;
+  const int32_t* v;
+  const int32_t* w;
+  int32_t on_device;
+  int32_t pad;
+} dc_edges;
+
+/* One record per executed synchronous sweep of the last call. */
+typedef struct dc_sweep_rec {
+  int32_t level;     /* 0 = the input graph                                */
+  int32_t sweep;     /* index within the level                             */
+  int32_t n_level;   /* vertices of the level graph                        */
+  int32_t n_active;  /* vertices evaluated in the sweep                    */
+  int64_t nnz_level; /* stored (directed) entries of the level graph       */
+  int64_t moves;     /* vertices that changed community                    */
+  int64_t dN;        /* exact change of N = 2m*I - sum a^2 (Q = N/(2m)^2)  */
+  int32_t kept;      /* 1 applied, 0 reverted (dN < 0) or no move          */
+  int32_t pad;
+} dc_sweep_rec;
+
+typedef struct dc_step_stats {
+  int64_t changes;        /* insertions + deletions of the batch            */
+  int64_t R_size;         /* |R_t| (n for ALL and STATIC)                   */
+  int64_t ds_sources;     /* addition sources examined by Alg. 2            */
+  int64_t ds_accepted;    /* sources whose test passed                      */
+  int64_t del_sources;    /* sources of intra-community deletions           */
+  int64_t del_accepted;
+  int32_t levels;         /* levels run                                     */
+  int32_t sweeps;         /* sweeps run over all levels                     */
+  int64_t moves;          /* vertex moves kept over all levels              */
+  int64_t vertex_evals;   /* vertex-gain evaluations (active vertices summed
+                             over sweeps, plus Alg. 2 sources)              */
+  int64_t N;              /* exact numerator of Q_t                         */
+  int64_t two_m;          /* 2m of G_t                                      */
+  double q;               /* N / (2m)^2                                     */
+  double ms_total;        /* host wall time of the call                     */
+  double ms_sweep_kernel; /* device time of the sweep kernels (timing=1)    */
+  int64_t sweep_launches; /* sweep kernel launches timed                    */
+  int64_t sweep_bytes;    /* algorithmic bytes of those launches            */
+  int64_t level0_sweeps;  /* sweeps at level 0                              */
+  int64_t level0_active;  /* active vertices summed over level-0 sweeps     */
+  int64_t level0_volume;  /* adjacency entries of active vertices, summed
+                             over level-0 sweeps                            */
+  int64_t reserved[4];
+} dc_step_stats;
+
+typedef struct dc_ctx dc_ctx;
+
+/* Defaults as documented in dc_options. */
+void dc_default_options(dc_options* opt);
+
+/* Builds G_1 on n vertices from g1 (duplicate pairs sum their weights) and
+ * runs Static(G_1) (Sec. 3.4 step 1): Alg. 1 from singletons with every
+ * vertex active.  *out receives the context; C_1 is read with
+ * dc_communities.  Errors: ARG, RANGE, SELF_LOOP, WEIGHT, OVERFLOW, OOM,
+ * DEVICE. */
+dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1,
+                  const dc_options* opt);
+
+/* One time step (Sec. 3.4 step 2): deletions `del` are removed first (each
+ * must exist in G_{t-1}), then insertions `add` are added (weights sum onto
+ * an existing edge).  Either list may be NULL or empty.  Then R_t is chosen
+ * per the mode (Alg. 2 for DELTA), the levels run from the inherited labels,
+ * and the canonical labels C_t (each community labelled by its smallest
+ * vertex id) are written to C_out[n] when C_out is not NULL (device memory
+ * when out_on_device = 1).  stats may be NULL.  Checks, in this order, over
+ * the whole batch: RANGE, SELF_LOOP, WEIGHT, DUP, NO_EDGE, OVERFLOW. */
+dc_status dc_apply_batch(dc_ctx* ctx, const dc_edges* add, const dc_edges* del,
+                         int32_t* C_out, int32_t out_on_device,
+                         dc_step_stats* stats);
+
+/* Modularity Q_t of Eq. (1) for the current (G_t, C_t), computed from its
+ * definition over the whole graph: q = N / (2m)^2 with the exact int64
+ * numerator N = 2m * sum_i e_{i->C(i)} - sum_C a_C^2.  Any pointer may be
+ * NULL.  2m = 0 gives q = 0. */
+dc_status dc_modularity(dc_ctx* ctx, double* q, int64_t* num, int64_t* two_m);
+
+/* Current canonical labels into out[n] (device memory when on_device). */
+dc_status dc_communities(dc_ctx* ctx, int32_t* out, int32_t on_device);
+
+/* R_t of the last dc_apply_batch as n bytes of 0/1 (all ones after dc_init). */
+dc_status dc_last_R(dc_ctx* ctx, uint8_t* out, int32_t on_device);
+
+/* Sweep records of the last dc_init / dc_apply_batch: up to cap records are
+ * copied to out; *count receives the total number of sweeps. */
+dc_status dc_last_trace(dc_ctx* ctx, dc_sweep_rec* out, int32_t cap,
+                        int32_t* count);
+
+/* Statistics of the last dc_init / dc_apply_batch. */
+dc_status dc_last_stats(dc_ctx* ctx, dc_step_stats* out);
+
+/* Number of stored directed entries of G_t (2 per undirected edge). */
+dc_status dc_num_entries(dc_ctx* ctx, int64_t* nnz);
+
+/* G_t as a CSR in host memory: off[n+1] (int64), col[nnz], w[nnz]; rows are
+ * sorted by neighbour id. */
+dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w);
+
+void dc_destroy(dc_ctx* ctx);
+
+const char* dc_strerror(dc_status s);
+
+/* Text of the last HIP failure seen by a call on this host thread (the failing
+ * call, its error string and source location); "" if none.  The pointer stays
+ * valid until the next call on the same thread. */
+const char* dc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,719 @@
+// api.hip -- the C ABI of dc.h: context, dc_init, dc_apply_batch and queries.
+//
+// dc_init runs Static(G_1) (Sec. 3.4 step 1).  dc_apply_batch runs one time
+// step (Sec. 3.4 step 2): the batch is validated in full before anything is
+// changed, merged into the CSR, R_t is chosen (Alg. 2 plus the deletion rule
+// for DELTA, all vertices for ALL and STATIC), and the levels of Alg. 1 run
+// with level 0 restricted to R_t.  All work goes to the caller's stream; the
+// host waits only where a size or a convergence decision is needed.
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dc_louvain.h"
+
+using namespace dc;
+
+struct dc_ctx {
+  int32_t n = 0;
+  dc_options opt{};
+  hipStream_t st = nullptr;
+  bool poisoned = false;
+  int64_t two_m = 0;
+  int64_t nnz = 0;
+  int cur = 0;
+  DBuf off[2], adj[2];
+  DBuf k0, C, a0, sz0;
+  // batch
+  DBuf in_au, in_av, in_aw, in_du, in_dv;
+  DBuf dkeys, dvals, dk1, dv1, dw_old;
+  DBuf akeys, avals, ak1, av1, aheads, apos, ukeys, uw;
+  DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
+  DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
+  DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
+  DBuf R, cflag, rflag, rpos2, Rlist;
+  // levels
+  DBuf Cl, Cn, al, szl, dpack, tflag, tlist, movers, map0, cnt[2], minv[2], lab, cntf;
+  CoarseGraph cg[2];
+  DBuf stat;
+  long long* hstat = nullptr;  // pinned mirror of the status block
+  void* hbuf = nullptr;        // pinned scratch for the kernels' host reads
+  BinScratch bins;
+  CoarsenScratch cs;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<dc_sweep_rec> trace;
+  dc_step_stats stats{};
+  int64_t R_count = 0;
+  bool have_R_all = true;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+dc_status map_device_error(const DeviceError& e) {
+  g_last_error = e.what();
+  return (e.code == hipErrorOutOfMemory || e.code == hipErrorMemoryAllocation) ? DC_E_OOM
+                                                                              : DC_E_DEVICE;
+}
+
+bool options_ok(const dc_options* o) {
+  if (!o) return false;
+  if (o->mode < DC_MODE_DELTA || o->mode > DC_MODE_STATIC) return false;
+  if (o->max_levels < 1 || o->max_sweeps < 1) return false;
+  if (o->del_rule != DC_DEL_GAIN && o->del_rule != DC_DEL_CONSERVATIVE) return false;
+  if (o->tau_den < 0) return false;
+  for (int i = 0; i < 4; ++i)
+    if (o->reserved[i] != 0) return false;
+  return true;
+}
+
+// Copies an edge list to the device when it lives on the host.
+void stage_edges(dc_ctx* c, const dc_edges* e, bool weights, DBuf& bu, DBuf& bv, DBuf& bw,
+                 const int32_t** u, const int32_t** v, const int32_t** w) {
+  *u = *v = *w = nullptr;
+  if (!e || e->count <= 0) return;
+  size_t bytes = size_t(e->count) * 4;
+  if (e->on_device) {
+    *u = e->u;
+    *v = e->v;
+    *w = weights ? e->w : nullptr;
+    return;
+  }
+  bu.ensure(bytes);
+  bv.ensure(bytes);
+  DC_HIP(hipMemcpyAsync(bu.p, e->u, bytes, hipMemcpyHostToDevice, c->st));
+  DC_HIP(hipMemcpyAsync(bv.p, e->v, bytes, hipMemcpyHostToDevice, c->st));
+  *u = bu.as<int32_t>();
+  *v = bv.as<int32_t>();
+  if (weights) {
+    bw.ensure(bytes);
+    DC_HIP(hipMemcpyAsync(bw.p, e->w, bytes, hipMemcpyHostToDevice, c->st));
+    *w = bw.as<int32_t>();
+  }
+}
+
+void ensure_vertex_state(dc_ctx* c) {
+  size_t n = size_t(c->n);
+  for (DBuf* b : {&c->k0, &c->C, &c->a0, &c->sz0, &c->Cl, &c->Cn, &c->al, &c->szl, &c->tflag,
+                  &c->tlist, &c->movers, &c->map0, &c->cnt[0], &c->cnt[1], &c->minv[0],
+                  &c->minv[1], &c->lab, &c->cntf, &c->dflag, &c->dpos, &c->dlist, &c->rflag,
+                  &c->rpos2, &c->Rlist})
+    b->ensure((n + 1) * 4);
+  c->dpack.ensure((n + 1) * 8);
+  c->R.ensure(n + 1);
+  c->cflag.ensure(n + 1);
+  c->stat.ensure(ST_COUNT * 8);
+  fill_i64(c->dpack.as<int64_t>(), 0, int64_t(n) + 1, c->st);
+  fill_i32(c->tflag.as<int32_t>(), 0, int64_t(n) + 1, c->st);
+}
+
+void read_stat(dc_ctx* c) {
+  DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, c->st));
+  DC_HIP(hipStreamSynchronize(c->st));
+}
+
+// Alg. 1 with level 0 visiting `active` (null = every vertex).  The level-0
+// partition is (Cl, al, szl), prepared by the caller.
+void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
+  hipStream_t st = c->st;
+  const long long two_m = c->two_m;
+  const long long T = c->opt.tau_den > 0 ? (two_m * two_m) / c->opt.tau_den : 0;
+  LevelView g{c->n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
+              c->k0.as<int32_t>()};
+  int32_t* Cl = c->Cl.as<int32_t>();
+  int32_t* Cn = c->Cn.as<int32_t>();
+  int32_t* al = c->al.as<int32_t>();
+  int32_t* szl = c->szl.as<int32_t>();
+  DC_HIP(hipMemcpyAsync(Cn, Cl, size_t(c->n) * 4, hipMemcpyDeviceToDevice, st));
+  int level = 0;
+  c->trace.clear();
+  dc_step_stats& S = c->stats;
+  while (true) {
+    const int32_t* act = level == 0 ? active : nullptr;
+    const int64_t nact = level == 0 ? n_active : g.n;
+    Bins bins;
+    make_bins(act, nullptr, nact, g.off, bins, c->bins, st);
+    const int64_t n_eval = bins.n[0] + bins.n[1] + bins.n[2];
+    long long level_gain = 0;
+    for (int s = 0; s < c->opt.max_sweeps; ++s) {
+      sweep_reset(c->stat.as<long long>(), st);
+      if (c->opt.timing) DC_HIP(hipEventRecord(c->ev0, st));
+      sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
+                 c->movers.as<int32_t>(), c->stat.as<long long>(), st);
+      if (c->opt.timing) DC_HIP(hipEventRecord(c->ev1, st));
+      sweep_apply(g, Cl, Cn, al, szl, two_m, n_eval > 0 ? n_eval : 1, c->movers.as<int32_t>(),
+                  c->dpack.as<long long>(), c->tflag.as<int32_t>(), c->tlist.as<int32_t>(),
+                  c->stat.as<long long>(), st);
+      read_stat(c);
+      if (c->opt.timing) {
+        float ms = 0;
+        DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        S.ms_sweep_kernel += ms;
+        S.sweep_launches += 1;
+        // algorithmic bytes of one sweep: 12 B per adjacency entry (8 B
+        // entry + 4 B neighbour label) and 32 B per evaluated vertex
+        // (offsets, label, degree, own total and size, best total, result)
+        S.sweep_bytes += 12 * (bins.vol[0] + bins.vol[1] + bins.vol[2]) + 32 * n_eval;
+      }
+      dc_sweep_rec r{};
+      r.level = level;
+      r.sweep = s;
+      r.n_level = g.n;
+      r.n_active = int32_t(n_eval);
+      r.nnz_level = g.nnz;
+      r.moves = c->hstat[ST_MOVES];
+      r.dN = c->hstat[ST_DN];
+      r.kept = int32_t(c->hstat[ST_KEEP]);
+      c->trace.push_back(r);
+      S.vertex_evals += n_eval;
+      if (level == 0) {
+        S.level0_sweeps += 1;
+        S.level0_active += n_eval;
+        S.level0_volume += bins.vol[0] + bins.vol[1] + bins.vol[2];
+      }
+      if (r.moves == 0 || r.dN < 0) break;
+      S.moves += r.moves;
+      level_gain += r.dN;
+      if (r.dN <= T) break;
+    }
+    const bool stop = (level + 1 >= c->opt.max_levels) || (level >= 1 && level_gain <= T);
+    if (stop && level >= 1) break;
+    // coarsen (after level 0 always: it also yields the canonical labels)
+    const int next = level % 2;
+    const int32_t* cnt_in = level == 0 ? nullptr : c->cnt[(level - 1) % 2].as<int32_t>();
+    const int32_t* minv_in = level == 0 ? nullptr : c->minv[(level - 1) % 2].as<int32_t>();
+    coarsen(g, Cl, szl, al, cnt_in, minv_in, level == 0, c->n, c->map0.as<int32_t>(),
+            c->cg[next], c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, st);
+    g = c->cg[next].view();
+    iota_i32(Cl, g.n, st);
+    iota_i32(Cn, g.n, st);
+    DC_HIP(hipMemcpyAsync(al, g.k, size_t(g.n) * 4, hipMemcpyDeviceToDevice, st));
+    fill_i32(szl, 1, g.n, st);
+    level++;
+    if (stop) break;  // max_levels == 1: final = the identity partition of level 1
+  }
+  S.levels = c->trace.empty() ? 1 : c->trace.back().level + 1;
+  S.sweeps = int32_t(c->trace.size());
+  const int32_t* cntL = c->cnt[(level - 1) % 2].as<int32_t>();
+  const int32_t* minvL = c->minv[(level - 1) % 2].as<int32_t>();
+  finalize_labels(g.n, Cl, al, szl, cntL, minvL, c->n, c->map0.as<int32_t>(),
+                  c->lab.as<int32_t>(), c->cntf.as<int32_t>(), c->C.as<int32_t>(),
+                  c->a0.as<int32_t>(), c->sz0.as<int32_t>(), st);
+  // exact numerator on the final level (coarsening preserves N)
+  long long* stat = c->stat.as<long long>();
+  DC_HIP(hipMemsetAsync(stat + ST_I, 0, 16, st));
+  intra_weight(g.off, g.adj, Cl, g.n, stat + ST_I, st);
+  sum_squares(al, g.n, stat + ST_S, st);
+  read_stat(c);
+  S.N = two_m * c->hstat[ST_I] - c->hstat[ST_S];
+  S.two_m = two_m;
+  S.q = two_m == 0 ? 0.0 : double(S.N) / (double(two_m) * double(two_m));
+}
+
+void start_from_singletons(dc_ctx* c) {
+  iota_i32(c->C.as<int32_t>(), c->n, c->st);
+  DC_HIP(hipMemcpyAsync(c->a0.p, c->k0.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
+  fill_i32(c->sz0.as<int32_t>(), 1, c->n, c->st);
+}
+
+void load_level0_partition(dc_ctx* c) {
+  DC_HIP(hipMemcpyAsync(c->Cl.p, c->C.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
+  DC_HIP(hipMemcpyAsync(c->al.p, c->a0.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
+  DC_HIP(hipMemcpyAsync(c->szl.p, c->sz0.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
+}
+
+dc_status status_from_flags(int32_t f) {
+  if (f & F_RANGE) return DC_E_RANGE;
+  if (f & F_SELF) return DC_E_SELF_LOOP;
+  if (f & F_WEIGHT) return DC_E_WEIGHT;
+  if (f & F_DUP) return DC_E_DUP;
+  if (f & F_NO_EDGE) return DC_E_NO_EDGE;
+  return DC_OK;
+}
+
+int sort_bits(int32_t n) { return ilog2_ceil(uint64_t(n) * uint64_t(n)); }
+
+dc_status do_init(dc_ctx* c, const dc_edges* g1) {
+  hipStream_t st = c->st;
+  ensure_vertex_state(c);
+  long long* stat = c->stat.as<long long>();
+  DC_HIP(hipMemsetAsync(stat, 0, ST_COUNT * 8, st));
+  const int32_t *u, *v, *w;
+  stage_edges(c, g1, true, c->in_au, c->in_av, c->in_aw, &u, &v, &w);
+  const int64_t m = g1 ? g1->count : 0;
+  validate_edges(u, v, w, m, c->n, reinterpret_cast<int32_t*>(stat + ST_FLAGS),
+                 stat + ST_WSUM_ADD, st);
+  read_stat(c);
+  int32_t f = int32_t(c->hstat[ST_FLAGS]);
+  if (f) return status_from_flags(f);
+  const long long wsum = c->hstat[ST_WSUM_ADD];
+  if (2 * wsum >= TWO_M_LIMIT) return DC_E_OVERFLOW;
+  // directed entries, sorted, duplicates summed
+  const int64_t md = 2 * m;
+  c->akeys.ensure(size_t(md + 1) * 8);
+  c->ak1.ensure(size_t(md + 1) * 8);
+  c->avals.ensure(size_t(md + 1) * 4);
+  c->av1.ensure(size_t(md + 1) * 4);
+  c->aheads.ensure(size_t(md + 1) * 4);
+  c->apos.ensure(size_t(md + 1) * 4);
+  uint64_t* keys = c->akeys.as<uint64_t>();
+  uint32_t* vals = c->avals.as<uint32_t>();
+  make_directed(u, v, w, m, c->n, keys, vals, st);
+  radix_sort_pairs(keys, vals, c->ak1.as<uint64_t>(), c->av1.as<uint32_t>(), md,
+                   sort_bits(c->n), st);
+  run_heads(keys, md, c->aheads.as<int32_t>(), st);
+  int32_t* pos = c->apos.as<int32_t>();
+  scan_excl_i32(c->aheads.as<int32_t>(), pos, md, pos + md, st);
+  int32_t U = 0;
+  if (md > 0) {
+    DC_HIP(hipMemcpyAsync(c->hbuf, pos + md, 4, hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    U = *static_cast<int32_t*>(c->hbuf);
+  }
+  c->ukeys.ensure(size_t(U + 1) * 8);
+  c->uw.ensure(size_t(U + 1) * 4);
+  fill_i32(c->uw.as<int32_t>(), 0, U, st);
+  reduce_runs(keys, vals, nullptr, pos, md, c->ukeys.as<uint64_t>(), c->uw.as<int32_t>(), st);
+  c->cur = 0;
+  c->off[0].ensure(size_t(c->n + 1) * 4);
+  c->adj[0].ensure(size_t(U + 1) * 8);
+  row_bounds(c->ukeys.as<uint64_t>(), U, c->n, c->off[0].as<int32_t>(), st);
+  keys_to_adj(c->ukeys.as<uint64_t>(), c->uw.as<int32_t>(), U, c->n, c->adj[0].as<int2>(), st);
+  row_weight_sums(c->off[0].as<int32_t>(), c->adj[0].as<int2>(), c->n, c->k0.as<int32_t>(), st);
+  c->nnz = U;
+  c->two_m = 2 * wsum;
+  start_from_singletons(c);
+  load_level0_partition(c);
+  c->stats = dc_step_stats{};
+  c->stats.R_size = c->n;
+  run_levels(c, nullptr, c->n);
+  c->have_R_all = true;
+  return DC_OK;
+}
+
+dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t* C_out,
+                   int32_t out_on_device, dc_step_stats* out_stats) {
+  hipStream_t st = c->st;
+  const int32_t n = c->n;
+  long long* stat = c->stat.as<long long>();
+  long long* hs = c->hstat;
+  DC_HIP(hipMemsetAsync(stat, 0, ST_COUNT * 8, st));
+  const int32_t *au, *av, *aw, *du, *dv, *dw;
+  stage_edges(c, add, true, c->in_au, c->in_av, c->in_aw, &au, &av, &aw);
+  stage_edges(c, del, false, c->in_du, c->in_dv, c->in_aw, &du, &dv, &dw);
+  const int64_t na = add ? add->count : 0;
+  const int64_t nd = del ? del->count : 0;
+  int32_t* flags = reinterpret_cast<int32_t*>(stat + ST_FLAGS);
+  validate_edges(du, dv, nullptr, nd, n, flags, nullptr, st);
+  validate_edges(au, av, aw, na, n, flags, stat + ST_WSUM_ADD, st);
+  const int bits = sort_bits(n);
+  // deletions: canonical, sorted, unique, present in G_{t-1}
+  c->dkeys.ensure(size_t(nd + 1) * 8);
+  c->dk1.ensure(size_t(nd + 1) * 8);
+  c->dvals.ensure(size_t(nd + 1) * 4);
+  c->dv1.ensure(size_t(nd + 1) * 4);
+  c->dw_old.ensure(size_t(nd + 1) * 4);
+  uint64_t* dkeys = c->dkeys.as<uint64_t>();
+  make_canonical(du, dv, nd, n, dkeys, c->dvals.as<uint32_t>(), st);
+  radix_sort_pairs(dkeys, c->dvals.as<uint32_t>(), c->dk1.as<uint64_t>(), c->dv1.as<uint32_t>(),
+                   nd, bits, st);
+  detect_dups(dkeys, nd, flags, st);
+  const int32_t* off_old = c->off[c->cur].as<int32_t>();
+  const int2* adj_old = c->adj[c->cur].as<int2>();
+  lookup_deleted(dkeys, nd, n, off_old, adj_old, c->dw_old.as<int32_t>(), flags,
+                 stat + ST_WSUM_DEL, st);
+  // insertions: canonical, sorted, duplicates summed
+  c->akeys.ensure(size_t(na + 1) * 8);
+  c->ak1.ensure(size_t(na + 1) * 8);
+  c->avals.ensure(size_t(na + 1) * 4);
+  c->av1.ensure(size_t(na + 1) * 4);
+  c->aheads.ensure(size_t(na + 1) * 4);
+  c->apos.ensure(size_t(na + 1) * 4);
+  uint64_t* akeys = c->akeys.as<uint64_t>();
+  uint32_t* avals = c->avals.as<uint32_t>();
+  make_canonical(au, av, na, n, akeys, avals, st);
+  radix_sort_pairs(akeys, avals, c->ak1.as<uint64_t>(), c->av1.as<uint32_t>(), na, bits, st);
+  run_heads(akeys, na, c->aheads.as<int32_t>(), st);
+  int32_t* apos = c->apos.as<int32_t>();
+  scan_excl_i32(c->aheads.as<int32_t>(), apos, na, reinterpret_cast<int32_t*>(stat + ST_N0), st);
+  read_stat(c);
+  // checks in the documented order; nothing has been changed yet
+  if (int32_t f = int32_t(hs[ST_FLAGS])) return status_from_flags(f);
+  const long long two_m_new = c->two_m - 2 * hs[ST_WSUM_DEL] + 2 * hs[ST_WSUM_ADD];
+  if (two_m_new >= TWO_M_LIMIT) return DC_E_OVERFLOW;
+  const int64_t na_u = na > 0 ? int32_t(hs[ST_N0]) : 0;
+
+  // ---- from here on the state changes ----
+  c->ukeys.ensure(size_t(na_u + 1) * 8);
+  c->uw.ensure(size_t(na_u + 1) * 4);
+  fill_i32(c->uw.as<int32_t>(), 0, na_u, st);
+  reduce_runs(akeys, avals, aw, apos, na, c->ukeys.as<uint64_t>(), c->uw.as<int32_t>(), st);
+  // directed change records
+  const int64_t nr = 2 * (nd + na_u);
+  for (DBuf* b : {&c->rkeys, &c->rk1, &c->ch_key}) b->ensure(size_t(nr + 1) * 8);
+  for (DBuf* b : {&c->rvals, &c->rv1, &c->rheads, &c->rpos, &c->ch_op, &c->ch_w, &c->ch_dk,
+                  &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->ins_flag, &c->ins_pos,
+                  &c->src_flag, &c->src_pos, &c->src_list})
+    b->ensure(size_t(nr + 1) * 4);
+  c->ins_keys.ensure(size_t(nr + 1) * 8);
+  uint64_t* rkeys = c->rkeys.as<uint64_t>();
+  uint32_t* rvals = c->rvals.as<uint32_t>();
+  make_change_records(dkeys, nd, c->ukeys.as<uint64_t>(), na_u, n, rkeys, rvals, st);
+  radix_sort_pairs(rkeys, rvals, c->rk1.as<uint64_t>(), c->rv1.as<uint32_t>(), nr, bits, st);
+  int32_t* rheads = c->rheads.as<int32_t>();
+  int32_t* rpos = c->rpos.as<int32_t>();
+  run_heads(rkeys, nr, rheads, st);
+  scan_excl_i32(rheads, rpos, nr, reinterpret_cast<int32_t*>(stat + ST_N1), st);
+  read_stat(c);
+  const int64_t nch = nr > 0 ? int32_t(hs[ST_N1]) : 0;
+  uint64_t* ch_key = c->ch_key.as<uint64_t>();
+  int32_t* ch_op = c->ch_op.as<int32_t>();
+  int32_t* ch_w = c->ch_w.as<int32_t>();
+  int32_t* ch_dk = c->ch_dk.as<int32_t>();
+  combine_changes(rkeys, rvals, nr, rheads, rpos, n, c->dw_old.as<int32_t>(),
+                  c->uw.as<int32_t>(), off_old, adj_old, ch_key, ch_op, ch_w, ch_dk,
+                  c->is_del.as<int32_t>(), c->is_new.as<int32_t>(), st);
+  int32_t* cum_del = c->cum_del.as<int32_t>();
+  int32_t* cum_new = c->cum_new.as<int32_t>();
+  scan_excl_i32(c->is_del.as<int32_t>(), cum_del, nch, cum_del + nch, st);
+  scan_excl_i32(c->is_new.as<int32_t>(), cum_new, nch, cum_new + nch, st);
+  c->cptr.ensure(size_t(n + 1) * 4);
+  c->new_deg.ensure(size_t(n + 1) * 4);
+  int32_t* cptr = c->cptr.as<int32_t>();
+  row_bounds(ch_key, nch, n, cptr, st);
+  row_changes(cptr, ch_op, ch_dk, off_old, n, c->new_deg.as<int32_t>(), c->k0.as<int32_t>(),
+              c->C.as<int32_t>(), c->a0.as<int32_t>(), st);
+  const int nxt = c->cur ^ 1;
+  c->off[nxt].ensure(size_t(n + 1) * 4);
+  int32_t* off_new = c->off[nxt].as<int32_t>();
+  scan_excl_i32(c->new_deg.as<int32_t>(), off_new, n, off_new + n, st);
+  // insertion keys (sorted directed pairs) and their sources
+  select_insertions(ch_op, nch, c->ins_flag.as<int32_t>(), st);
+  scan_excl_i32(c->ins_flag.as<int32_t>(), c->ins_pos.as<int32_t>(), nch,
+                reinterpret_cast<int32_t*>(stat + ST_N2), st);
+  DC_HIP(hipMemcpyAsync(c->hbuf, off_new + n, 4, hipMemcpyDeviceToHost, st));
+  read_stat(c);
+  const int64_t nnz_new = *static_cast<int32_t*>(c->hbuf);
+  const int64_t n_ins = nch > 0 ? int32_t(hs[ST_N2]) : 0;
+  c->adj[nxt].ensure(size_t(nnz_new + 1) * 8);
+  merge_rows(off_old, adj_old, off_new, c->adj[nxt].as<int2>(), n, cptr, ch_key, ch_op, ch_w,
+             cum_del, cum_new, st);
+  c->cur = nxt;
+  c->nnz = nnz_new;
+  c->two_m = two_m_new;
+
+  dc_step_stats& S = c->stats;
+  S = dc_step_stats{};
+  S.changes = na + nd;
+  LevelView g0{n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
+               c->k0.as<int32_t>()};
+  const int mode = c->opt.mode;
+  if (mode == DC_MODE_DELTA) {
+    uint8_t* R = c->R.as<uint8_t>();
+    uint8_t* cflag = c->cflag.as<uint8_t>();
+    fill_u8(R, 0, n, st);
+    fill_u8(cflag, 0, n, st);
+    uint64_t* ins_keys = c->ins_keys.as<uint64_t>();
+    gather_u64(ch_key, c->ins_flag.as<int32_t>(), c->ins_pos.as<int32_t>(), nch, ins_keys, st);
+    int32_t* src_flag = c->src_flag.as<int32_t>();
+    int32_t* src_pos = c->src_pos.as<int32_t>();
+    source_heads(ins_keys, n_ins, n, src_flag, st);
+    scan_excl_i32(src_flag, src_pos, n_ins, reinterpret_cast<int32_t*>(stat + ST_N3), st);
+    gather_sources(ins_keys, src_flag, src_pos, n_ins, n, c->src_list.as<int32_t>(), st);
+    // deletion sources (labels C_{t-1})
+    int32_t* dflag = c->dflag.as<int32_t>();
+    fill_i32(dflag, 0, n, st);
+    deletion_sources(ch_key, ch_op, nch, n, c->C.as<int32_t>(), dflag, st);
+    int32_t* dpos = c->dpos.as<int32_t>();
+    scan_excl_i32(dflag, dpos, n, dpos + n, st);
+    compact_index(dflag, dpos, n, c->dlist.as<int32_t>(), st);
+    DC_HIP(hipMemcpyAsync(c->hbuf, dpos + n, 4, hipMemcpyDeviceToHost, st));
+    read_stat(c);
+    const int64_t n_src = n_ins > 0 ? int32_t(hs[ST_N3]) : 0;
+    const int64_t n_dsrc = *static_cast<int32_t*>(c->hbuf);
+    if (n_src > 0) {
+      Bins b;
+      make_bins(c->src_list.as<int32_t>(), nullptr, n_src, g0.off, b, c->bins, st);
+      ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins, b, R,
+                   cflag, stat, st);
+    }
+    if (n_dsrc > 0) {
+      if (c->opt.del_rule == DC_DEL_CONSERVATIVE) {
+        mark_neighbourhoods(c->dlist.as<int32_t>(), n_dsrc, g0.off, g0.adj, R, st);
+      } else {
+        Bins b;
+        make_bins(c->dlist.as<int32_t>(), nullptr, n_dsrc, g0.off, b, c->bins, st);
+        ds_deletions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->sz0.as<int32_t>(),
+                     c->two_m, b, R, cflag, stat, st);
+      }
+    }
+    int32_t* rflag = c->rflag.as<int32_t>();
+    int32_t* rpos2 = c->rpos2.as<int32_t>();
+    materialize_R(R, cflag, c->C.as<int32_t>(), n, rflag, st);
+    scan_excl_i32(rflag, rpos2, n, rpos2 + n, st);
+    compact_index(rflag, rpos2, n, c->Rlist.as<int32_t>(), st);
+    DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
+    read_stat(c);
+    c->R_count = *static_cast<int32_t*>(c->hbuf);
+    S.ds_sources = hs[ST_DS_SRC];
+    S.ds_accepted = hs[ST_DS_ACC];
+    if (c->opt.del_rule == DC_DEL_CONSERVATIVE) {
+      S.del_sources = n_dsrc;
+      S.del_accepted = n_dsrc;
+    } else {
+      S.del_sources = hs[ST_DEL_SRC];
+      S.del_accepted = hs[ST_DEL_ACC];
+    }
+    S.R_size = c->R_count;
+    S.vertex_evals += S.ds_sources + S.del_sources;
+    c->have_R_all = false;
+    load_level0_partition(c);
+    run_levels(c, c->Rlist.as<int32_t>(), c->R_count);
+  } else {
+    if (mode == DC_MODE_STATIC) start_from_singletons(c);
+    load_level0_partition(c);
+    S.R_size = n;
+    c->have_R_all = true;
+    run_levels(c, nullptr, n);
+  }
+  if (C_out) {
+    DC_HIP(hipMemcpyAsync(C_out, c->C.p, size_t(n) * 4,
+                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+  }
+  if (out_stats) *out_stats = S;
+  return DC_OK;
+}
+
+template <class F>
+dc_status guarded(dc_ctx* c, F&& f) {
+  if (!c) return DC_E_ARG;
+  if (c->poisoned) return DC_E_STATE;
+  try {
+    return f();
+  } catch (const DeviceError& e) {
+    dc_status s = map_device_error(e);
+    if (s == DC_E_DEVICE) c->poisoned = true;
+    return s;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return DC_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    c->poisoned = true;
+    return DC_E_DEVICE;
+  } catch (...) {
+    c->poisoned = true;
+    return DC_E_DEVICE;
+  }
+}
+
+void destroy_ctx(dc_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  if (c->hstat) (void)hipHostFree(c->hstat);
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  if (c->bins.host) (void)hipHostFree(c->bins.host);
+  if (c->cs.host) (void)hipHostFree(c->cs.host);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dc_default_options(dc_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->mode = DC_MODE_DELTA;
+  opt->max_levels = 32;
+  opt->max_sweeps = 100;
+  opt->singleton_guard = 1;
+  opt->del_rule = DC_DEL_GAIN;
+  opt->timing = 0;
+  opt->tau_den = 1000000;
+  opt->stream = nullptr;
+}
+
+dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1, const dc_options* opt) {
+  if (!out || n < 1 || !options_ok(opt)) return DC_E_ARG;
+  if (g1 && g1->count < 0) return DC_E_ARG;
+  if (g1 && g1->count > 0 && (!g1->u || !g1->v || !g1->w)) return DC_E_ARG;
+  *out = nullptr;
+  dc_ctx* c = new (std::nothrow) dc_ctx();
+  if (!c) return DC_E_OOM;
+  c->n = n;
+  c->opt = *opt;
+  c->st = static_cast<hipStream_t>(opt->stream);
+  dc_status s;
+  try {
+    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
+    DC_HIP(hipHostMalloc(&c->hbuf, 64));
+    DC_HIP(hipHostMalloc(&c->bins.host, 64));
+    DC_HIP(hipHostMalloc(&c->cs.host, 64));
+    DC_HIP(hipEventCreate(&c->ev0));
+    DC_HIP(hipEventCreate(&c->ev1));
+    double t0 = now_ms();
+    s = do_init(c, g1);
+    c->stats.ms_total = now_ms() - t0;
+  } catch (const DeviceError& e) {
+    s = map_device_error(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    s = DC_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    s = DC_E_DEVICE;
+  } catch (...) {
+    s = DC_E_DEVICE;
+  }
+  if (s != DC_OK) {
+    destroy_ctx(c);
+    return s;
+  }
+  *out = c;
+  return DC_OK;
+}
+
+dc_status dc_apply_batch(dc_ctx* ctx, const dc_edges* add, const dc_edges* del, int32_t* C_out,
+                         int32_t out_on_device, dc_step_stats* stats) {
+  if (add && (add->count < 0 || (add->count > 0 && (!add->u || !add->v || !add->w))))
+    return DC_E_ARG;
+  if (del && (del->count < 0 || (del->count > 0 && (!del->u || !del->v)))) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    double t0 = now_ms();
+    dc_status s = do_apply(ctx, add, del, C_out, out_on_device, nullptr);
+    if (s == DC_OK) {
+      ctx->stats.ms_total = now_ms() - t0;
+      if (stats) *stats = ctx->stats;
+    }
+    return s;
+  });
+}
+
+dc_status dc_modularity(dc_ctx* ctx, double* q, int64_t* num, int64_t* two_m) {
+  return guarded(ctx, [&] {
+    hipStream_t st = ctx->st;
+    long long* stat = ctx->stat.as<long long>();
+    DC_HIP(hipMemsetAsync(stat + ST_I, 0, 16, st));
+    int32_t* atmp = ctx->lab.as<int32_t>();
+    fill_i32(atmp, 0, ctx->n, st);
+    intra_weight(ctx->off[ctx->cur].as<int32_t>(), ctx->adj[ctx->cur].as<int2>(),
+                 ctx->C.as<int32_t>(), ctx->n, stat + ST_I, st);
+    label_totals(ctx->k0.as<int32_t>(), ctx->C.as<int32_t>(), ctx->n, atmp, st);
+    sum_squares(atmp, ctx->n, stat + ST_S, st);
+    read_stat(ctx);
+    long long N = ctx->two_m * ctx->hstat[ST_I] - ctx->hstat[ST_S];
+    if (num) *num = N;
+    if (two_m) *two_m = ctx->two_m;
+    if (q) *q = ctx->two_m == 0 ? 0.0 : double(N) / (double(ctx->two_m) * double(ctx->two_m));
+    return DC_OK;
+  });
+}
+
+dc_status dc_communities(dc_ctx* ctx, int32_t* out, int32_t on_device) {
+  if (!out) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    DC_HIP(hipMemcpyAsync(out, ctx->C.p, size_t(ctx->n) * 4,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->st));
+    DC_HIP(hipStreamSynchronize(ctx->st));
+    return DC_OK;
+  });
+}
+
+dc_status dc_last_R(dc_ctx* ctx, uint8_t* out, int32_t on_device) {
+  if (!out) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    if (ctx->have_R_all) {
+      if (on_device) {
+        fill_u8(out, 1, ctx->n, ctx->st);
+        DC_HIP(hipStreamSynchronize(ctx->st));
+      } else {
+        std::memset(out, 1, size_t(ctx->n));
+      }
+      return DC_OK;
+    }
+    DC_HIP(hipMemcpyAsync(out, ctx->R.p, size_t(ctx->n),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->st));
+    DC_HIP(hipStreamSynchronize(ctx->st));
+    return DC_OK;
+  });
+}
+
+dc_status dc_last_trace(dc_ctx* ctx, dc_sweep_rec* out, int32_t cap, int32_t* count) {
+  if (cap < 0 || (cap > 0 && !out)) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    int32_t total = int32_t(ctx->trace.size());
+    for (int32_t i = 0; i < total && i < cap; ++i) out[i] = ctx->trace[size_t(i)];
+    if (count) *count = total;
+    return DC_OK;
+  });
+}
+
+dc_status dc_last_stats(dc_ctx* ctx, dc_step_stats* out) {
+  if (!out) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    *out = ctx->stats;
+    return DC_OK;
+  });
+}
+
+dc_status dc_num_entries(dc_ctx* ctx, int64_t* nnz) {
+  if (!nnz) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    *nnz = ctx->nnz;
+    return DC_OK;
+  });
+}
+
+dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w) {
+  if (!off || (!col && ctx && ctx->nnz > 0) || (!w && ctx && ctx->nnz > 0)) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    std::vector<int32_t> o(size_t(ctx->n) + 1);
+    std::vector<int2> e(size_t(ctx->nnz));
+    DC_HIP(hipMemcpyAsync(o.data(), ctx->off[ctx->cur].p, o.size() * 4, hipMemcpyDeviceToHost,
+                          ctx->st));
+    if (ctx->nnz > 0)
+      DC_HIP(hipMemcpyAsync(e.data(), ctx->adj[ctx->cur].p, e.size() * 8, hipMemcpyDeviceToHost,
+                            ctx->st));
+    DC_HIP(hipStreamSynchronize(ctx->st));
+    for (size_t i = 0; i < o.size(); ++i) off[i] = o[i];
+    for (size_t i = 0; i < e.size(); ++i) {
+      col[i] = e[i].x;
+      w[i] = e[i].y;
+    }
+    return DC_OK;
+  });
+}
+
+void dc_destroy(dc_ctx* ctx) { destroy_ctx(ctx); }
+
+const char* dc_last_error(void) { return g_last_error.c_str(); }
+
+const char* dc_strerror(dc_status s) {
+  switch (s) {
+    case DC_OK: return "ok";
+    case DC_E_ARG: return "invalid argument";
+    case DC_E_RANGE: return "vertex id out of range";
+    case DC_E_SELF_LOOP: return "self-loop";
+    case DC_E_WEIGHT: return "edge weight below 1";
+    case DC_E_NO_EDGE: return "deleted edge not present";
+    case DC_E_DUP: return "pair deleted twice";
+    case DC_E_OVERFLOW: return "total weight 2m would reach 2^31";
+    case DC_E_OOM: return "device memory exhausted";
+    case DC_E_DEVICE: return "device error";
+    case DC_E_STATE: return "context poisoned by an earlier device error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

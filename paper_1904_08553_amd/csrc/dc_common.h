@@ -1,0 +1,201 @@
+// dc_common.h -- internal declarations of the gfx950 library behind dc.h.
+//
+// Layout in HBM (one GPU, everything resident):
+//   level-0 graph G_t   : CSR, int32 row offsets (n+1) and packed int2
+//                         entries {neighbour, weight} (8 B, one 64-bit load
+//                         per entry); double-buffered so a batch merge
+//                         streams old -> new.  2m < 2^31 keeps every count,
+//                         offset, degree and community total in int32.
+//   k, C, a, size       : int32 per vertex / per label.
+//   coarse levels       : the same CSR form, built per step.
+// Exact integer arithmetic everywhere (scores in int64), so every reduction
+// order gives the same bits and results do not depend on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dc.h"
+
+namespace dc {
+
+constexpr int WAVE = 64;
+constexpr int64_t TWO_M_LIMIT = int64_t(1) << 31;
+
+struct DeviceError : std::runtime_error {
+  hipError_t code;
+  DeviceError(hipError_t c, const std::string& what)
+      : std::runtime_error(what), code(c) {}
+};
+
+#define DC_HIP(x)                                                        \
+  do {                                                                   \
+    hipError_t e_ = (x);                                                 \
+    if (e_ != hipSuccess)                                                \
+      throw ::dc::DeviceError(e_, std::string(#x) + " -> " +             \
+                                      hipGetErrorString(e_) + " at " +   \
+                                      __FILE__ + ":" +                   \
+                                      std::to_string(__LINE__));         \
+  } while (0)
+
+// After every launch: the launch status, and with DC_SYNC_CHECK=1 in the
+// environment also the kernel's completion (localises a failing kernel).
+bool sync_check_enabled();
+#define DC_LAUNCH_CHECK()                                                  \
+  do {                                                                     \
+    DC_HIP(hipGetLastError());                                             \
+    if (::dc::sync_check_enabled()) DC_HIP(hipDeviceSynchronize());        \
+  } while (0)
+
+// Grow-only device buffer; contents are not preserved on growth.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    size_t want = b < 256 ? 256 : b;
+    DC_HIP(hipMalloc(&p, want));
+    bytes = want;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int ilog2_ceil(uint64_t x) {
+  int b = 0;
+  while ((uint64_t(1) << b) < x) ++b;
+  return b;
+}
+
+inline uint32_t pow2_ceil32(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T y = __shfl_xor(v, o, WAVE);
+    v = y > v ? y : v;
+  }
+  return v;
+}
+
+// Best candidate order: larger score first, then smaller label.
+struct Best {
+  long long s;
+  int x;
+};
+
+__device__ __forceinline__ bool better(long long s, int x, long long bs,
+                                       int bx) {
+  return s > bs || (s == bs && x < bx);
+}
+
+__device__ __forceinline__ Best wave_best(Best b) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    long long s = __shfl_xor(b.s, o, WAVE);
+    int x = __shfl_xor(b.x, o, WAVE);
+    if (better(s, x, b.s, b.x)) {
+      b.s = s;
+      b.x = x;
+    }
+  }
+  return b;
+}
+
+constexpr int EMPTY_KEY = -1;
+constexpr long long NO_SCORE = (long long)0x8000000000000000ull;
+constexpr int NO_LABEL = 0x7fffffff;
+
+__device__ __forceinline__ uint32_t hash_slot(int key, uint32_t mask) {
+  return (uint32_t(key) * 2654435761u) & mask;
+}
+
+// Open-addressing insert-or-add into a table of int32 keys and int32 sums;
+// the table never fills (capacity >= 2 * distinct keys).
+__device__ __forceinline__ void table_add(int* keys, int* vals, uint32_t mask,
+                                          int key, int w) {
+  uint32_t h = hash_slot(key, mask);
+  while (true) {
+    int prev = atomicCAS(&keys[h], EMPTY_KEY, key);
+    if (prev == EMPTY_KEY || prev == key) {
+      atomicAdd(&vals[h], w);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ int table_get(const int* keys, const int* vals,
+                                         uint32_t mask, int key) {
+  uint32_t h = hash_slot(key, mask);
+  while (true) {
+    int k = keys[h];
+    if (k == key) return vals[h];
+    if (k == EMPTY_KEY) return 0;
+    h = (h + 1) & mask;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// primitives (prims.hip)
+
+// out[i] = sum_{j<i} in[j]; *total (device, may be null) = sum of all.
+void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n,
+                   int32_t* total, hipStream_t st);
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n,
+                   int64_t* total, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+// Sorted data ends in (k0, v0); (k1, v1) are scratch of the same size.
+void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                      int64_t n, int bits, hipStream_t st);
+
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
+void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
+void iota_i32(int32_t* p, int64_t n, hipStream_t st);
+
+// Scratch for the primitives (owned by the context).
+struct PrimScratch {
+  DBuf scan_tmp;
+  DBuf sort_hist;
+};
+PrimScratch& prim_scratch();
+
+}  // namespace dc

@@ -1,0 +1,131 @@
+// dc_kernels.h -- host launchers of the gfx950 kernels (plain pointers, one
+// stream).  The orchestration in api.hip composes them into dc_init and
+// dc_apply_batch.
+#pragma once
+
+#include "dc_common.h"
+
+namespace dc {
+
+// ---- per-block aggregated scatter-add (hot community labels) ------------
+// Pre-combines (key, value) pairs of a 256-thread block in an LDS table so a
+// label shared by many vertices of the block costs one global atomic.
+constexpr int AGG_SLOTS = 1024;
+
+struct AggLds {
+  int keys[AGG_SLOTS];
+  long long vals[AGG_SLOTS];
+};
+
+__device__ __forceinline__ void agg_init(AggLds& s) {
+  for (int i = threadIdx.x; i < AGG_SLOTS; i += blockDim.x) {
+    s.keys[i] = EMPTY_KEY;
+    s.vals[i] = 0;
+  }
+}
+
+__device__ __forceinline__ void agg_put(AggLds& s, int key, long long v) {
+  uint32_t h = hash_slot(key, AGG_SLOTS - 1);
+  while (true) {
+    int prev = atomicCAS(&s.keys[h], EMPTY_KEY, key);
+    if (prev == EMPTY_KEY || prev == key) {
+      atomicAdd((unsigned long long*)&s.vals[h], (unsigned long long)v);
+      return;
+    }
+    h = (h + 1) & (AGG_SLOTS - 1);
+  }
+}
+
+// ---- graph.hip -----------------------------------------------------------
+enum EdgeFlag : int32_t { F_RANGE = 1, F_SELF = 2, F_WEIGHT = 4, F_DUP = 8, F_NO_EDGE = 16 };
+
+// flags |= F_RANGE / F_SELF / F_WEIGHT (w may be null); *wsum += sum of w.
+void validate_edges(const int32_t* u, const int32_t* v, const int32_t* w,
+                    int64_t m, int32_t n, int32_t* flags, long long* wsum,
+                    hipStream_t st);
+
+// Directed entries of an edge list for the initial CSR: keys u*n+v and v*n+u
+// with the weight as value.
+void make_directed(const int32_t* u, const int32_t* v, const int32_t* w,
+                   int64_t m, int32_t n, uint64_t* keys, uint32_t* vals,
+                   hipStream_t st);
+
+// Canonical keys min*n+max with the input index as value.
+void make_canonical(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
+                    uint64_t* keys, uint32_t* vals, hipStream_t st);
+
+// flag[i] = 1 if keys[i] starts a run of equal keys.
+void run_heads(const uint64_t* keys, int64_t m, int32_t* flag, hipStream_t st);
+
+// Sums runs of equal sorted keys: out_key[pos[i]] = keys[i] at heads and
+// out_w[pos[i]] += w_of(vals[i]) where w_of is wsrc[vals[i]] (wsrc != null)
+// or vals[i] itself.  out_w must be zeroed.
+void reduce_runs(const uint64_t* keys, const uint32_t* vals,
+                 const int32_t* wsrc, const int32_t* pos, int64_t m,
+                 uint64_t* out_key, int32_t* out_w, hipStream_t st);
+
+// row_ptr[u] = first index i with keys[i] >= u*n (u in [0, n]).
+void row_bounds(const uint64_t* keys, int64_t m, int32_t n, int32_t* row_ptr,
+                hipStream_t st);
+
+// CSR entries from sorted unique directed keys.
+void keys_to_adj(const uint64_t* keys, const int32_t* w, int64_t m, int32_t n,
+                 int2* adj, hipStream_t st);
+
+// k[u] = sum of row weights.
+void row_weight_sums(const int32_t* off, const int2* adj, int32_t n,
+                     int32_t* k, hipStream_t st);
+
+// flags |= F_DUP if two sorted canonical keys are equal.
+void detect_dups(const uint64_t* keys, int64_t m, int32_t* flags,
+                 hipStream_t st);
+
+// For sorted canonical deletions: the weight of the edge in G (or flag
+// F_NO_EDGE); *wsum += sum of the weights found.  Skips out-of-range ids.
+void lookup_deleted(const uint64_t* keys, int64_t m, int32_t n,
+                    const int32_t* off, const int2* adj, int32_t* w_old,
+                    int32_t* flags, long long* wsum, hipStream_t st);
+
+// Change records of a batch, sorted by directed key src*n+dst.
+enum ChangeOp : int32_t { OP_DELETE = 1, OP_ADD = 2, OP_NEW = 3, OP_REPLACE = 4 };
+
+// Directed records: for canonical deletion d: keys lo*n+hi and hi*n+lo with
+// value (d<<1)|0; for canonical insertion a: value (a<<1)|1.
+void make_change_records(const uint64_t* del_keys, int64_t nd,
+                         const uint64_t* ins_keys, int64_t na, int32_t n,
+                         uint64_t* rkeys, uint32_t* rvals, hipStream_t st);
+
+// Combines sorted records into one change per directed key (heads/pos from
+// run_heads + scan).  Writes ch_key, ch_op, ch_w (new weight for NEW and
+// REPLACE, added weight for ADD), ch_dk (change of the row's weighted
+// degree), is_del, is_new (0/1 per change).
+void combine_changes(const uint64_t* rkeys, const uint32_t* rvals, int64_t nr,
+                     const int32_t* heads, const int32_t* pos, int32_t n,
+                     const int32_t* del_w_old, const int32_t* ins_w,
+                     const int32_t* off, const int2* adj, uint64_t* ch_key,
+                     int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
+                     int32_t* is_del, int32_t* is_new, hipStream_t st);
+
+// Per row: new degree and degree-weight change; k += dk; a[C[u]] += dk.
+void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk,
+                 const int32_t* off, int32_t n, int32_t* new_deg, int32_t* k,
+                 const int32_t* C, int32_t* a, hipStream_t st);
+
+// Merge G_{t-1} with the sorted change list into G_t (one wave per row).
+void merge_rows(const int32_t* off_old, const int2* adj_old,
+                const int32_t* off_new, int2* adj_new, int32_t n,
+                const int32_t* cptr, const uint64_t* ch_key,
+                const int32_t* ch_op, const int32_t* ch_w,
+                const int32_t* cum_del, const int32_t* cum_new,
+                hipStream_t st);
+
+// Exact numerator pieces of Eq. (1) over a CSR with labels C:
+// *I += sum of intra-community entry weights; a_tmp (zeroed, n) receives
+// sum of k by label; *S += sum a^2 (second launcher).
+void intra_weight(const int32_t* off, const int2* adj, const int32_t* C,
+                  int32_t n, long long* I, hipStream_t st);
+void label_totals(const int32_t* k, const int32_t* C, int32_t n, int32_t* a,
+                  hipStream_t st);
+void sum_squares(const int32_t* a, int32_t n, long long* S, hipStream_t st);
+
+}  // namespace dc

@@ -1,0 +1,140 @@
+// dc_louvain.h -- launchers of the level, screening and coarsening kernels.
+#pragma once
+
+#include "dc_kernels.h"
+
+namespace dc {
+
+// Slots of the int64 device status block shared by the kernels of one call.
+enum StatSlot : int {
+  ST_MOVES = 0,    // movers of the current sweep
+  ST_TOUCHED = 1,  // labels touched by the current sweep
+  ST_DI = 2,       // change of the intra-community weight I
+  ST_DS = 3,       // change of sum a^2
+  ST_DN = 4,       // exact change of N = 2m*I - sum a^2
+  ST_KEEP = 5,     // 1: the sweep was applied
+  ST_DS_SRC = 6,   // Alg. 2 sources examined
+  ST_DS_ACC = 7,   // Alg. 2 sources accepted
+  ST_DEL_SRC = 8,
+  ST_DEL_ACC = 9,
+  ST_I = 10,       // modularity: intra weight
+  ST_S = 11,       // modularity: sum of squares
+  ST_N0 = 12,      // scratch counters (sizes read by the host)
+  ST_N1 = 13,
+  ST_N2 = 14,
+  ST_N3 = 15,
+  ST_FLAGS = 16,   // batch validation flags (int32 in the low half)
+  ST_WSUM_ADD = 17,
+  ST_WSUM_DEL = 18,
+  ST_COUNT = 24
+};
+
+enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2 };
+
+// LDS hash-table sizes of the two LDS bins; rows up to half a table fit.
+constexpr int WAVE_SLOTS = 256;   // bin 0: one wave per vertex, deg <= 128
+constexpr int BLOCK_SLOTS = 4096; // bin 1: one block per vertex, deg <= 2048
+
+struct LevelView {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* off;
+  const int2* adj;
+  const int32_t* k;
+};
+
+struct Bins {
+  int64_t n[3];
+  const int32_t* list[3];
+  const int32_t* count_dev;   // 3 device counts
+  long long vol[3];           // adjacency entries of each bin
+  int* gkeys;
+  int* gvals;
+  const long long* tab_off;
+};
+
+struct BinScratch {
+  DBuf lists[3];
+  DBuf counts;
+  DBuf tab_off;
+  DBuf gkeys;
+  DBuf gvals;
+  void* host = nullptr;  // pinned, 64 bytes
+};
+
+// Splits a vertex list (null = all of [0, count_host)) into the three bins by
+// row length; synchronises to read the bin sizes.
+void make_bins(const int32_t* list, const int32_t* count_dev, int64_t count_host,
+               const int32_t* off, Bins& b, BinScratch& s, hipStream_t st);
+
+void sweep_reset(long long* stat, hipStream_t st);
+void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                const int32_t* sz, long long two_m, int guard, const Bins& bins,
+                int32_t* movers, long long* stat, hipStream_t st);
+void sweep_apply(const LevelView& g, int32_t* C, int32_t* Cn, int32_t* a, int32_t* sz,
+                 long long two_m, int64_t max_movers, int32_t* movers, long long* dpack,
+                 int32_t* tflag, int32_t* tlist, long long* stat, hipStream_t st);
+
+void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
+                  const uint64_t* ins_keys, int64_t n_ins, const Bins& bins, uint8_t* R,
+                  uint8_t* cflag, long long* stat, hipStream_t st);
+void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
+                  long long two_m, const Bins& bins, uint8_t* R, uint8_t* cflag,
+                  long long* stat, hipStream_t st);
+
+// ---- screen.hip ----
+// out[pos[i]] = i for flag[i] != 0 (pos = exclusive scan of flag).
+void compact_index(const int32_t* flag, const int32_t* pos, int64_t n, int32_t* out,
+                   hipStream_t st);
+// Insertion changes (op != DELETE) of the sorted change list, compacted.
+void select_insertions(const int32_t* ch_op, int64_t nch, int32_t* flag, hipStream_t st);
+void gather_u64(const uint64_t* in, const int32_t* flag, const int32_t* pos, int64_t n,
+                uint64_t* out, hipStream_t st);
+// flag[q] = 1 where the source of sorted directed keys changes; out ids.
+void source_heads(const uint64_t* keys, int64_t m, int32_t n, int32_t* flag, hipStream_t st);
+void gather_sources(const uint64_t* keys, const int32_t* flag, const int32_t* pos, int64_t m,
+                    int32_t n, int32_t* out, hipStream_t st);
+// dflag[src] = 1 for deleted pairs inside one community.
+void deletion_sources(const uint64_t* ch_key, const int32_t* ch_op, int64_t nch, int32_t n,
+                      const int32_t* C, int32_t* dflag, hipStream_t st);
+// R[i] = 1 and R[Gamma(i)] = 1 for every listed vertex.
+void mark_neighbourhoods(const int32_t* list, int64_t cnt, const int32_t* off, const int2* adj,
+                         uint8_t* R, hipStream_t st);
+// R[v] |= cflag[C[v]]; rflag[v] = R[v].
+void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n,
+                   int32_t* rflag, hipStream_t st);
+
+// ---- coarsen.hip ----
+struct CoarsenScratch {
+  DBuf flag, rank, keys0, keys1, vals0, vals1, cntr, mstart, labof, mdeg, mvol, caps, tkeys,
+      tvals, chead, cpos, chunks, cdeg, mcnt;
+  void* host = nullptr;  // pinned, 64 bytes
+};
+
+struct CoarseGraph {
+  DBuf off, adj, k;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  LevelView view() const {
+    return LevelView{n, nnz, off.as<int32_t>(), adj.as<int2>(), k.as<int32_t>()};
+  }
+};
+
+// Builds the next level from the partition C of g (Alg. 1 compaction): one
+// coarse vertex per non-empty community, numbered by ascending label, with
+// A'_{XY} = sum of the entries between the two communities (diagonal kept).
+// Updates map0 (level-0 vertex -> vertex of the new level); cnt/minv of the
+// new level from those of g (first_level: all ones / identity).
+void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int32_t* a,
+             const int32_t* cnt, const int32_t* minv, bool first_level, int32_t n0,
+             int32_t* map0, CoarseGraph& out, int32_t* cnt_out, int32_t* minv_out,
+             CoarsenScratch& s, hipStream_t st);
+
+// Canonical labels of the final partition (smallest level-0 id per
+// community), the level-0 totals and sizes by label, and C_t.
+void finalize_labels(int32_t nL, const int32_t* CL, const int32_t* aL, const int32_t* szL,
+                     const int32_t* cntL, const int32_t* minvL, int32_t n0, const int32_t* map0,
+                     int32_t* lab, int32_t* cntf, int32_t* C0, int32_t* a0, int32_t* sz0,
+                     hipStream_t st);
+
+}  // namespace dc

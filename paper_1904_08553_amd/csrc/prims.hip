@@ -1,0 +1,294 @@
+// prims.hip -- scan, stable LSD radix sort, fills.  Hand-written for gfx950:
+// 256-thread blocks of four 64-wide waves, wave prefix sums by shuffles,
+// radix ranking by eight 64-bit ballots per round.
+#include <cstdlib>
+
+#include "dc_common.h"
+
+namespace dc {
+
+bool sync_check_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("DC_SYNC_CHECK");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+PrimScratch& prim_scratch() {
+  static thread_local PrimScratch s;
+  return s;
+}
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;  // 2048
+
+template <class T>
+__device__ T block_excl_scan(T v, T* lds, T* total) {
+  const int lane = lane_id(), wid = threadIdx.x / WAVE;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == WAVE - 1) lds[wid] = x;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < SCAN_THREADS / WAVE; ++w) {
+    T t = lds[w];
+    pre += (w < wid) ? t : T(0);
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+template <class T>
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_tile_reduce(const T* __restrict__ in, int64_t n, T* __restrict__ part) {
+  __shared__ T lds[SCAN_THREADS / WAVE];
+  int64_t base = int64_t(blockIdx.x) * SCAN_TILE;
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    int64_t idx = base + int64_t(i) * SCAN_THREADS + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  T tot;
+  (void)block_excl_scan<T>(s, lds, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Each thread owns SCAN_ITEMS consecutive elements (blocked layout).
+template <class T>
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_tile_scan(const T* in, T* out, int64_t n, const T* __restrict__ part_excl,
+                T* total, int64_t nblocks) {
+  __shared__ T lds[SCAN_THREADS / WAVE];
+  int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
+  T v[SCAN_ITEMS];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    int64_t idx = base + i;
+    v[i] = idx < n ? in[idx] : T(0);
+    s += v[i];
+  }
+  T tot;
+  T pre = block_excl_scan<T>(s, lds, &tot);
+  T off = part_excl ? part_excl[blockIdx.x] : T(0);
+  T run = off + pre;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    int64_t idx = base + i;
+    if (idx < n) out[idx] = run;
+    run += v[i];
+  }
+  if (total && blockIdx.x == nblocks - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+template <class T>
+__global__ void k_set_scalar(T* p, T v) {
+  *p = v;
+}
+
+template <class T>
+void scan_excl_impl(const T* in, T* out, int64_t n, T* total, hipStream_t st,
+                    T* tmp, size_t tmp_elems) {
+  if (n <= 0) {
+    if (total) {
+      k_set_scalar<T><<<1, 1, 0, st>>>(total, T(0));
+      DC_LAUNCH_CHECK();
+    }
+    return;
+  }
+  int64_t nb = ceil_div(n, SCAN_TILE);
+  if (nb == 1) {
+    k_tile_scan<T><<<1, SCAN_THREADS, 0, st>>>(in, out, n, nullptr, total, 1);
+    DC_LAUNCH_CHECK();
+    return;
+  }
+  if (size_t(nb) > tmp_elems) throw std::runtime_error("scan scratch too small");
+  T* part = tmp;
+  k_tile_reduce<T><<<nb, SCAN_THREADS, 0, st>>>(in, n, part);
+  DC_LAUNCH_CHECK();
+  // exclusive scan of the block partials in place (recursion on the tail)
+  scan_excl_impl<T>(part, part, nb, nullptr, st, tmp + nb, tmp_elems - size_t(nb));
+  k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, total, nb);
+  DC_LAUNCH_CHECK();
+}
+
+template <class T>
+void scan_excl(const T* in, T* out, int64_t n, T* total, hipStream_t st) {
+  // partial sums need ~ n/2048 + n/2048^2 + ... elements
+  size_t need = size_t(ceil_div(n, SCAN_TILE)) + 64;
+  need += need / SCAN_TILE + 64;
+  DBuf& b = prim_scratch().scan_tmp;
+  b.ensure(need * sizeof(T));
+  scan_excl_impl<T>(in, out, n, total, st, b.as<T>(), b.bytes / sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// radix sort
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ROUNDS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 2048 keys per block
+constexpr int RS_BINS = 256;
+constexpr int RS_WAVES = RS_THREADS / WAVE;
+
+__global__ void __launch_bounds__(RS_THREADS)
+    k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                 int32_t* __restrict__ hist, int64_t nblocks) {
+  __shared__ int32_t h[RS_BINS];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * RS_TILE;
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    int64_t idx = base + int64_t(r) * RS_THREADS + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xff], 1);
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: elements are ranked in index order within the tile.  Each
+// round covers 256 consecutive elements; within a wave the rank among equal
+// digits comes from a ballot match, across waves from per-wave digit counts.
+__global__ void __launch_bounds__(RS_THREADS)
+    k_radix_scatter(const uint64_t* __restrict__ kin,
+                    const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                    uint32_t* __restrict__ vout, int64_t n, int shift,
+                    const int32_t* __restrict__ hist_excl, int64_t nblocks) {
+  __shared__ int32_t base_d[RS_BINS];
+  __shared__ int32_t wcnt[RS_WAVES][RS_BINS];
+  const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
+  base_d[t] = hist_excl[int64_t(t) * nblocks + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < RS_WAVES; ++w) wcnt[w][t] = 0;
+  __syncthreads();
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  int64_t tile = int64_t(blockIdx.x) * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    int64_t idx = tile + int64_t(r) * RS_THREADS + t;
+    bool valid = idx < n;
+    uint64_t key = valid ? kin[idx] : 0;
+    uint32_t val = valid ? vin[idx] : 0;
+    int d = int((key >> shift) & 0xff);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1;
+      uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    int rank = __popcll(m & lt);
+    if (valid && rank == 0) wcnt[wid][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      int pos = base_d[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+      add += wcnt[w][t];
+      wcnt[w][t] = 0;
+    }
+    base_d[t] += add;
+    __syncthreads();
+  }
+}
+
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_iota(int32_t* p, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = int32_t(i);
+}
+
+inline int grid_for(int64_t n, int threads = 256) {
+  int64_t g = ceil_div(n, threads);
+  if (g > 8192) g = 8192;
+  return int(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total,
+                   hipStream_t st) {
+  scan_excl<int32_t>(in, out, n, total, st);
+}
+
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total,
+                   hipStream_t st) {
+  scan_excl<int64_t>(in, out, n, total, st);
+}
+
+void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                      int64_t n, int bits, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return;
+  int passes = (bits + 7) / 8;
+  int64_t nb = ceil_div(n, RS_TILE);
+  DBuf& hb = prim_scratch().sort_hist;
+  hb.ensure(size_t(nb) * RS_BINS * sizeof(int32_t));
+  int32_t* hist = hb.as<int32_t>();
+  uint64_t *ka = k0, *kb = k1;
+  uint32_t *va = v0, *vb = v1;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    k_radix_hist<<<nb, RS_THREADS, 0, st>>>(ka, n, shift, hist, nb);
+    DC_LAUNCH_CHECK();
+    scan_excl_i32(hist, hist, nb * RS_BINS, nullptr, st);
+    k_radix_scatter<<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, hist, nb);
+    DC_LAUNCH_CHECK();
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != k0) {
+    DC_HIP(hipMemcpyAsync(k0, ka, size_t(n) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    DC_HIP(hipMemcpyAsync(v0, va, size_t(n) * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+}
+
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill<int32_t><<<grid_for(n), 256, 0, st>>>(p, v, n);
+  DC_LAUNCH_CHECK();
+}
+
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill<int64_t><<<grid_for(n), 256, 0, st>>>(p, v, n);
+  DC_LAUNCH_CHECK();
+}
+
+void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill<uint8_t><<<grid_for(n), 256, 0, st>>>(p, v, n);
+  DC_LAUNCH_CHECK();
+}
+
+void iota_i32(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  k_iota<<<grid_for(n), 256, 0, st>>>(p, n);
+  DC_LAUNCH_CHECK();
+}
+
+}  // namespace dc

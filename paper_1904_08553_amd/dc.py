@@ -1,0 +1,266 @@
+"""ctypes binding of ``libdc.so`` (include/dc.h), argument marshalling only.
+
+Every step of the method runs in the HIP library.  Inputs may be numpy arrays
+(host memory) or torch tensors on the GPU (device memory, passed by pointer);
+the library enqueues its work on torch's current stream.  The binding fails
+loudly when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdc.so")
+
+OK = 0
+MODE_DELTA, MODE_ALL, MODE_STATIC = 0, 1, 2
+DEL_GAIN, DEL_CONSERVATIVE = 0, 1
+STATUS = {
+    0: "OK", -1: "ARG", -2: "RANGE", -3: "SELF_LOOP", -4: "WEIGHT", -5: "NO_EDGE",
+    -6: "DUP", -7: "OVERFLOW", -8: "OOM", -9: "DEVICE", -10: "STATE",
+}
+
+
+class Options(ct.Structure):
+    _fields_ = [
+        ("mode", ct.c_int32), ("max_levels", ct.c_int32), ("max_sweeps", ct.c_int32),
+        ("singleton_guard", ct.c_int32), ("del_rule", ct.c_int32), ("timing", ct.c_int32),
+        ("tau_den", ct.c_int64), ("stream", ct.c_void_p), ("reserved", ct.c_int64 * 4),
+    ]
+
+
+class Edges(ct.Structure):
+    _fields_ = [
+        ("count", ct.c_int64), ("u", ct.c_void_p), ("v", ct.c_void_p), ("w", ct.c_void_p),
+        ("on_device", ct.c_int32), ("pad", ct.c_int32),
+    ]
+
+
+class SweepRec(ct.Structure):
+    _fields_ = [
+        ("level", ct.c_int32), ("sweep", ct.c_int32), ("n_level", ct.c_int32),
+        ("n_active", ct.c_int32), ("nnz_level", ct.c_int64), ("moves", ct.c_int64),
+        ("dN", ct.c_int64), ("kept", ct.c_int32), ("pad", ct.c_int32),
+    ]
+
+
+class StepStats(ct.Structure):
+    _fields_ = [
+        ("changes", ct.c_int64), ("R_size", ct.c_int64), ("ds_sources", ct.c_int64),
+        ("ds_accepted", ct.c_int64), ("del_sources", ct.c_int64), ("del_accepted", ct.c_int64),
+        ("levels", ct.c_int32), ("sweeps", ct.c_int32), ("moves", ct.c_int64),
+        ("vertex_evals", ct.c_int64), ("N", ct.c_int64), ("two_m", ct.c_int64), ("q", ct.c_double),
+        ("ms_total", ct.c_double), ("ms_sweep_kernel", ct.c_double),
+        ("sweep_launches", ct.c_int64), ("sweep_bytes", ct.c_int64),
+        ("level0_sweeps", ct.c_int64), ("level0_active", ct.c_int64),
+        ("level0_volume", ct.c_int64), ("reserved", ct.c_int64 * 4),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+EXPORTS = [
+    "dc_default_options", "dc_init", "dc_apply_batch", "dc_modularity", "dc_communities",
+    "dc_last_R", "dc_last_trace", "dc_last_stats", "dc_num_entries", "dc_export_csr",
+    "dc_destroy", "dc_strerror", "dc_last_error",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdc.so and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1904_08553_amd/build.py "
+                           "(there is no CPU fallback)")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) then satisfies
+    # libdc.so's dependency, so one runtime serves both and torch's stream
+    # handles are valid in the library.
+    import torch  # noqa: F401
+    L = ct.CDLL(path)
+    P, i32, i64 = ct.c_void_p, ct.c_int32, ct.c_int64
+    L.dc_default_options.argtypes = [P]
+    L.dc_default_options.restype = None
+    L.dc_init.argtypes = [P, i32, P, P]
+    L.dc_init.restype = i32
+    L.dc_apply_batch.argtypes = [P, P, P, P, i32, P]
+    L.dc_apply_batch.restype = i32
+    L.dc_modularity.argtypes = [P, P, P, P]
+    L.dc_modularity.restype = i32
+    L.dc_communities.argtypes = [P, P, i32]
+    L.dc_communities.restype = i32
+    L.dc_last_R.argtypes = [P, P, i32]
+    L.dc_last_R.restype = i32
+    L.dc_last_trace.argtypes = [P, P, i32, P]
+    L.dc_last_trace.restype = i32
+    L.dc_last_stats.argtypes = [P, P]
+    L.dc_last_stats.restype = i32
+    L.dc_num_entries.argtypes = [P, P]
+    L.dc_num_entries.restype = i32
+    L.dc_export_csr.argtypes = [P, P, P, P]
+    L.dc_export_csr.restype = i32
+    L.dc_destroy.argtypes = [P]
+    L.dc_destroy.restype = None
+    L.dc_strerror.argtypes = [i32]
+    L.dc_strerror.restype = ct.c_char_p
+    L.dc_last_error.argtypes = []
+    L.dc_last_error.restype = ct.c_char_p
+    _lib = L
+    return L
+
+
+class DCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().dc_strerror(status).decode()
+        detail = load().dc_last_error().decode() if status in (-8, -9) else ""
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg}) {detail}".rstrip())
+        self.status = status
+
+
+def _check(status, where):
+    if status != OK:
+        raise DCError(status, where)
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class _Arr:
+    """Pointer to an int32 array, host (numpy) or device (torch tensor)."""
+
+    def __init__(self, x):
+        if x is None:
+            self.ptr, self.n, self.dev, self.keep = None, 0, 0, None
+        elif _is_torch(x):
+            import torch
+            if x.dtype != torch.int32 or not x.is_contiguous():
+                x = x.to(torch.int32).contiguous()
+            self.ptr, self.n, self.dev, self.keep = x.data_ptr(), x.numel(), int(x.is_cuda), x
+            if not x.is_cuda:
+                self.keep = x.numpy()
+                self.ptr = self.keep.ctypes.data
+        else:
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+            self.ptr, self.n, self.dev, self.keep = a.ctypes.data, a.size, 0, a
+
+
+def _edges(u, v, w=None):
+    au, av, aw = _Arr(u), _Arr(v), _Arr(w)
+    if au.n != av.n or (w is not None and aw.n != au.n):
+        raise ValueError("edge arrays differ in length")
+    if au.dev != av.dev or (w is not None and aw.dev != au.dev):
+        raise ValueError("edge arrays must all be on the host or all on the device")
+    e = Edges(au.n, au.ptr, av.ptr, aw.ptr, au.dev, 0)
+    return e, (au, av, aw)
+
+
+def current_stream():
+    """torch's current HIP stream handle (0 when torch or a GPU is absent)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
+            del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current"):
+    o = Options()
+    load().dc_default_options(ct.byref(o))
+    o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
+    o.singleton_guard, o.del_rule, o.timing, o.tau_den = singleton_guard, del_rule, timing, tau_den
+    o.stream = current_stream() if stream == "current" else stream
+    return o
+
+
+class DynamicCommunities:
+    """A dynamic graph with its communities, held on the GPU by libdc.so."""
+
+    def __init__(self, n, u, v, w, **opt):
+        self.n = int(n)
+        self._opt = options(**opt)
+        e, keep = _edges(u, v, w)
+        h = ct.c_void_p()
+        _check(load().dc_init(ct.byref(h), self.n, ct.byref(e), ct.byref(self._opt)), "dc_init")
+        self._h = h
+        del keep
+
+    def apply_batch(self, add_u=None, add_v=None, add_w=None, del_u=None, del_v=None, out=None):
+        """Apply one batch; returns C_t as a numpy array (or fills ``out``,
+        a device tensor, without a host copy)."""
+        add, ka = _edges(add_u if add_u is not None else [], add_v if add_v is not None else [],
+                         add_w if add_w is not None else [])
+        dele, kd = _edges(del_u if del_u is not None else [], del_v if del_v is not None else [])
+        st = StepStats()
+        if out is not None:
+            o = _Arr(out)
+            _check(load().dc_apply_batch(self._h, ct.byref(add), ct.byref(dele), o.ptr, o.dev,
+                                         ct.byref(st)), "dc_apply_batch")
+            self.stats = st
+            return out
+        C = np.empty(self.n, np.int32)
+        _check(load().dc_apply_batch(self._h, ct.byref(add), ct.byref(dele), C.ctypes.data, 0,
+                                     ct.byref(st)), "dc_apply_batch")
+        self.stats = st
+        del ka, kd
+        return C
+
+    def modularity(self):
+        q, N, tm = ct.c_double(), ct.c_int64(), ct.c_int64()
+        _check(load().dc_modularity(self._h, ct.byref(q), ct.byref(N), ct.byref(tm)),
+               "dc_modularity")
+        return q.value, N.value, tm.value
+
+    def communities(self):
+        C = np.empty(self.n, np.int32)
+        _check(load().dc_communities(self._h, C.ctypes.data, 0), "dc_communities")
+        return C
+
+    def last_R(self):
+        R = np.empty(self.n, np.uint8)
+        _check(load().dc_last_R(self._h, R.ctypes.data, 0), "dc_last_R")
+        return R
+
+    def last_trace(self):
+        cnt = ct.c_int32()
+        _check(load().dc_last_trace(self._h, None, 0, ct.byref(cnt)), "dc_last_trace")
+        recs = (SweepRec * max(cnt.value, 1))()
+        _check(load().dc_last_trace(self._h, recs, cnt.value, ct.byref(cnt)), "dc_last_trace")
+        return [(r.level, r.sweep, r.n_level, r.n_active, r.nnz_level, r.moves, r.dN, r.kept)
+                for r in recs[: cnt.value]]
+
+    def last_stats(self):
+        st = StepStats()
+        _check(load().dc_last_stats(self._h, ct.byref(st)), "dc_last_stats")
+        return st
+
+    def csr(self):
+        nnz = ct.c_int64()
+        _check(load().dc_num_entries(self._h, ct.byref(nnz)), "dc_num_entries")
+        off = np.empty(self.n + 1, np.int64)
+        col = np.empty(max(nnz.value, 1), np.int32)
+        w = np.empty(max(nnz.value, 1), np.int32)
+        _check(load().dc_export_csr(self._h, off.ctypes.data, col.ctypes.data, w.ctypes.data),
+               "dc_export_csr")
+        return off, col[: nnz.value], w[: nnz.value]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

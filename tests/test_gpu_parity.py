@@ -1,0 +1,149 @@
+"""GPU parity: the HIP path (through include/dc.h) against the CPU oracle,
+element by element, bit-exact for labels, R_t and every exact integer."""
+import numpy as np
+import pytest
+
+from gpu_common import compare, make_pair, step_pair
+from paper_1904_08553_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def test_two_triangles():
+    _log("case: two triangles")
+    o, g = make_pair(6, [0, 0, 1, 3, 3, 4, 2], [1, 2, 2, 4, 5, 5, 3], [1] * 7)
+    compare(o, g, "init")
+    assert list(g.communities()) == [0, 0, 0, 3, 3, 3]
+
+
+@pytest.mark.parametrize("guard", [1, 0])
+def test_k2(guard):
+    _log(f"case: K2 guard={guard}")
+    o, g = make_pair(2, [0], [1], [1], max_levels=1, guard=guard)
+    compare(o, g, "init")
+
+
+def test_edgeless_and_single_vertex():
+    _log("case: edgeless")
+    o, g = make_pair(5, [], [], [])
+    compare(o, g, "init")
+    assert g.modularity()[2] == 0
+    o, g = make_pair(1, [], [], [])
+    compare(o, g, "init")
+    # a batch that adds the first edges
+    o, g = make_pair(4, [], [], [])
+    o.apply_batch([0, 2], [1, 3], [2, 5])
+    g.apply_batch([0, 2], [1, 3], [2, 5])
+    compare(o, g, "first edges")
+
+
+CASES = [
+    dict(mode="delta"),
+    dict(mode="delta", del_rule=1, max_levels=2),
+    dict(mode="all"),
+    dict(mode="static", max_levels=3),
+    dict(mode="delta", max_levels=1, guard=0),
+    dict(mode="delta", tau_den=0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_dynamic(case, seed):
+    cfg = CASES[case]
+    n = 9 + seed
+    _log(f"case: random small n={n} seed={seed} cfg={cfg}")
+    (u, v, w), batches = W.random_dynamic(n, 2 * n, 4, 5, 3, seed=3000 + seed)
+    o, g = make_pair(n, u, v, w, **cfg)
+    compare(o, g, "init")
+    for t, b in enumerate(batches):
+        step_pair(o, g, b)
+        compare(o, g, f"step {t}")
+
+
+@pytest.mark.parametrize("mode", ["delta", "all", "static"])
+def test_planted_partition_2000(mode):
+    """2,000 vertices in 20 equal blocks (p_in 0.05, p_out 0.001), 4 steps of
+    500 insertions (70% intra) and 200 deletions, one coarsening level."""
+    _log(f"case: planted partition mode={mode}")
+    pp = W.PlantedPartition()
+    (u, v, w), batches = pp.batches()
+    o, g = make_pair(pp.n, u, v, w, mode=mode, max_levels=2)
+    compare(o, g, "init")
+    for t, b in enumerate(batches):
+        step_pair(o, g, b)
+        compare(o, g, f"step {t}")
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_dcsbm_with_hubs(seed):
+    """Power-law degrees up to thousands: all three row-length bins and
+    multi-chunk coarsening are exercised; several steps of 1% batches."""
+    _log(f"case: dcsbm hubs seed={seed}")
+    gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=seed)
+    (u, v, w), it = gen.stream(3, frac=0.01)
+    deg = np.bincount(np.concatenate([u, v]), minlength=gen.n)
+    assert deg.max() > 2048 and ((deg > 128) & (deg <= 2048)).any()
+    o, g = make_pair(gen.n, u, v, w)
+    compare(o, g, "init")
+    for t, b in enumerate(it):
+        step_pair(o, g, b)
+        compare(o, g, f"step {t}")
+
+
+def test_batch_errors_leave_state_unchanged():
+    from paper_1904_08553_amd.dc import DCError
+    _log("case: batch errors")
+    pp = W.PlantedPartition(n=200, blocks=4, p_in=0.2, p_out=0.01)
+    (u, v, w), _ = pp.batches(steps=0)
+    o, g = make_pair(200, u, v, w)
+    C0 = g.communities().copy()
+    q0 = g.modularity()
+    csr0 = g.csr()
+    e0 = (int(u[0]), int(v[0]))
+    missing = next((a, b) for a in range(200) for b in range(a + 1, 200)
+                   if not ((u == a) & (v == b)).any())
+    bad = [
+        (dict(add_u=[0], add_v=[700], add_w=[1]), -2),
+        (dict(del_u=[-1], del_v=[2]), -2),
+        (dict(add_u=[3], add_v=[3], add_w=[1]), -3),
+        (dict(add_u=[3], add_v=[4], add_w=[0]), -4),
+        (dict(del_u=[e0[0], e0[1]], del_v=[e0[1], e0[0]]), -6),
+        (dict(del_u=[missing[0]], del_v=[missing[1]]), -5),
+        (dict(add_u=[3], add_v=[4], add_w=[2 ** 30]), -7),
+    ]
+    for kw, code in bad:
+        with pytest.raises(DCError) as e:
+            g.apply_batch(**kw)
+        assert e.value.status == code
+        assert np.array_equal(g.communities(), C0)
+        assert g.modularity() == q0
+        c1 = g.csr()
+        assert all(np.array_equal(x, y) for x, y in zip(csr0, c1))
+    # the context still works and agrees with the oracle afterwards
+    o.apply_batch([missing[0]], [missing[1]], [3], [e0[0]], [e0[1]])
+    g.apply_batch([missing[0]], [missing[1]], [3], [e0[0]], [e0[1]])
+    compare(o, g, "after errors")
+
+
+def test_replace_and_duplicate_insertions():
+    _log("case: replace + duplicates")
+    (u, v, w), _ = W.random_dynamic(30, 60, 0, 0, 0, seed=77)
+    o, g = make_pair(30, u, v, w)
+    a, b = int(u[0]), int(v[0])
+    # delete and re-add one edge, add a new pair twice in both orientations
+    new = next((x, y) for x in range(30) for y in range(x + 1, 30)
+               if not ((u == x) & (v == y)).any())
+    add_u = [a, new[0], new[1]]
+    add_v = [b, new[1], new[0]]
+    add_w = [7, 2, 3]
+    o.apply_batch(add_u, add_v, add_w, [b], [a])
+    g.apply_batch(add_u, add_v, add_w, [b], [a])
+    compare(o, g, "replace")
+    offo, colo, wo = o.csr()
+    offg, colg, wg = g.csr()
+    assert np.array_equal(offo, offg) and np.array_equal(colo, colg) and np.array_equal(wo, wg)
