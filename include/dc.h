@@ -126,9 +126,11 @@ typedef struct dc_step_stats {
   int64_t two_m;          /* 2m of G_t                                      */
   double q;               /* N / (2m)^2                                     */
   double ms_total;        /* host wall time of the call                     */
-  double ms_sweep_kernel; /* device time of the sweep kernels (timing=1)    */
-  int64_t sweep_launches; /* sweep kernel launches timed                    */
-  int64_t sweep_bytes;    /* algorithmic bytes of those launches            */
+  double ms_sweep_kernel; /* device time of the one-wave-per-vertex sweep
+                             kernel (rows up to 128 entries), timing=1      */
+  int64_t sweep_launches; /* launches of that kernel timed                  */
+  int64_t sweep_bytes;    /* their algorithmic bytes: 12 per adjacency entry
+                             and 32 per evaluated vertex                    */
   int64_t level0_sweeps;  /* sweeps at level 0                              */
   int64_t level0_active;  /* active vertices summed over level-0 sweeps     */
   int64_t level0_volume;  /* adjacency entries of active vertices, summed

@@ -144,23 +144,23 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
     long long level_gain = 0;
     for (int s = 0; s < c->opt.max_sweeps; ++s) {
       sweep_reset(c->stat.as<long long>(), st);
-      if (c->opt.timing) DC_HIP(hipEventRecord(c->ev0, st));
+      const bool timed = c->opt.timing && bins.n[0] > 0;
       sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
-                 c->movers.as<int32_t>(), c->stat.as<long long>(), st);
-      if (c->opt.timing) DC_HIP(hipEventRecord(c->ev1, st));
+                 c->movers.as<int32_t>(), c->stat.as<long long>(), st,
+                 timed ? c->ev0 : nullptr, timed ? c->ev1 : nullptr);
       sweep_apply(g, Cl, Cn, al, szl, two_m, n_eval > 0 ? n_eval : 1, c->movers.as<int32_t>(),
                   c->dpack.as<long long>(), c->tflag.as<int32_t>(), c->tlist.as<int32_t>(),
                   c->stat.as<long long>(), st);
       read_stat(c);
-      if (c->opt.timing) {
+      if (timed) {
         float ms = 0;
         DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
         S.ms_sweep_kernel += ms;
         S.sweep_launches += 1;
-        // algorithmic bytes of one sweep: 12 B per adjacency entry (8 B
-        // entry + 4 B neighbour label) and 32 B per evaluated vertex
-        // (offsets, label, degree, own total and size, best total, result)
-        S.sweep_bytes += 12 * (bins.vol[0] + bins.vol[1] + bins.vol[2]) + 32 * n_eval;
+        // algorithmic bytes of the bin-0 launch: 12 B per adjacency entry
+        // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
+        // (two offsets, label, degree, own total and size, best total, result)
+        S.sweep_bytes += 12 * bins.vol[0] + 32 * bins.n[0];
       }
       dc_sweep_rec r{};
       r.level = level;

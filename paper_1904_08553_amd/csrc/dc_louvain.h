@@ -68,9 +68,12 @@ void make_bins(const int32_t* list, const int32_t* count_dev, int64_t count_host
                const int32_t* off, Bins& b, BinScratch& s, hipStream_t st);
 
 void sweep_reset(long long* stat, hipStream_t st);
+// ev0/ev1 (may be null) bracket the launch of bin 0, the one-wave-per-vertex
+// kernel that carries most of the work.
 void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                 const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                int32_t* movers, long long* stat, hipStream_t st);
+                int32_t* movers, long long* stat, hipStream_t st, hipEvent_t ev0,
+                hipEvent_t ev1);
 void sweep_apply(const LevelView& g, int32_t* C, int32_t* Cn, int32_t* a, int32_t* sz,
                  long long two_m, int64_t max_movers, int32_t* movers, long long* dpack,
                  int32_t* tflag, int32_t* tlist, long long* stat, hipStream_t st);

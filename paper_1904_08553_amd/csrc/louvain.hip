@@ -480,13 +480,16 @@ __global__ void k_reset_sweep(long long* stat) {
 }
 
 template <int MODE>
-void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st) {
+void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st,
+                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   EvalArgs A = base;
   if (bins.n[0] > 0) {
     A.list = bins.list[0];
     A.count = bins.count_dev + 0;
+    if (ev0) DC_HIP(hipEventRecord(ev0, st));
     k_eval_wave<MODE><<<ceil_div(bins.n[0], NW), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
+    if (ev1) DC_HIP(hipEventRecord(ev1, st));
   }
   if (bins.n[1] > 0) {
     A.list = bins.list[1];
@@ -562,7 +565,8 @@ void make_bins(const int32_t* list, const int32_t* count_dev, int64_t count_host
 
 void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                 const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                int32_t* movers, long long* stat, hipStream_t st) {
+                int32_t* movers, long long* stat, hipStream_t st, hipEvent_t ev0,
+                hipEvent_t ev1) {
   EvalArgs A{};
   A.off = g.off;
   A.adj = g.adj;
@@ -576,7 +580,7 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
   A.movers = movers;
   A.stat = stat;
   A.n0 = g.n;
-  launch_eval<EV_SWEEP>(A, bins, st);
+  launch_eval<EV_SWEEP>(A, bins, st, ev0, ev1);
 }
 
 void sweep_reset(long long* stat, hipStream_t st) {
