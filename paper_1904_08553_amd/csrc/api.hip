@@ -139,16 +139,17 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
     const int32_t* act = level == 0 ? active : nullptr;
     const int64_t nact = level == 0 ? n_active : g.n;
     Bins bins;
-    make_bins(act, nullptr, nact, g.off, bins, c->bins, st);
-    const int64_t n_eval = bins.n[0] + bins.n[1] + bins.n[2];
+    make_bins(act, nact, g.off, bins, c->bins, st);
+    const int64_t n_eval = bins.n[0] + bins.n[1] + bins.n[2] + bins.n[3];
+    const long long vol_eval = bins.vol[0] + bins.vol[1] + bins.vol[2] + bins.vol[3];
     long long level_gain = 0;
     for (int s = 0; s < c->opt.max_sweeps; ++s) {
       sweep_reset(c->stat.as<long long>(), st);
       const bool timed = c->opt.timing && bins.n[0] > 0;
       sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
-                 c->movers.as<int32_t>(), c->stat.as<long long>(), st,
-                 timed ? c->ev0 : nullptr, timed ? c->ev1 : nullptr);
-      sweep_apply(g, Cl, Cn, al, szl, two_m, n_eval > 0 ? n_eval : 1, c->movers.as<int32_t>(),
+                 c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,
+                 timed ? c->ev1 : nullptr);
+      sweep_apply(g, act, nact, Cl, Cn, al, szl, two_m, c->movers.as<int32_t>(),
                   c->dpack.as<long long>(), c->tflag.as<int32_t>(), c->tlist.as<int32_t>(),
                   c->stat.as<long long>(), st);
       read_stat(c);
@@ -157,7 +158,7 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
         DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
         S.ms_sweep_kernel += ms;
         S.sweep_launches += 1;
-        // algorithmic bytes of the bin-0 launch: 12 B per adjacency entry
+        // algorithmic bytes of the bin-S launch: 12 B per adjacency entry
         // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
         // (two offsets, label, degree, own total and size, best total, result)
         S.sweep_bytes += 12 * bins.vol[0] + 32 * bins.n[0];
@@ -176,7 +177,7 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
       if (level == 0) {
         S.level0_sweeps += 1;
         S.level0_active += n_eval;
-        S.level0_volume += bins.vol[0] + bins.vol[1] + bins.vol[2];
+        S.level0_volume += vol_eval;
       }
       if (r.moves == 0 || r.dN < 0) break;
       S.moves += r.moves;
@@ -403,8 +404,15 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
   const int64_t nnz_new = *static_cast<int32_t*>(c->hbuf);
   const int64_t n_ins = nch > 0 ? int32_t(hs[ST_N2]) : 0;
   c->adj[nxt].ensure(size_t(nnz_new + 1) * 8);
-  merge_rows(off_old, adj_old, off_new, c->adj[nxt].as<int2>(), n, cptr, ch_key, ch_op, ch_w,
-             cum_del, cum_new, st);
+  // rows with changes: the distinct sources of the change list
+  int32_t* crow_flag = c->rheads.as<int32_t>();
+  int32_t* crow_pos = c->rpos.as<int32_t>();
+  int32_t* crows = c->src_list.as<int32_t>();
+  source_heads(ch_key, nch, n, crow_flag, st);
+  scan_excl_i32(crow_flag, crow_pos, nch, crow_pos + nch, st);
+  gather_sources(ch_key, crow_flag, crow_pos, nch, n, crows, st);
+  merge_rows(off_old, adj_old, c->nnz, off_new, c->adj[nxt].as<int2>(), n, cptr, crows,
+             crow_pos + nch, nch, ch_key, ch_op, ch_w, cum_del, cum_new, st);
   c->cur = nxt;
   c->nnz = nnz_new;
   c->two_m = two_m_new;
@@ -440,7 +448,7 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
     const int64_t n_dsrc = *static_cast<int32_t*>(c->hbuf);
     if (n_src > 0) {
       Bins b;
-      make_bins(c->src_list.as<int32_t>(), nullptr, n_src, g0.off, b, c->bins, st);
+      make_bins(c->src_list.as<int32_t>(), n_src, g0.off, b, c->bins, st);
       ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins, b, R,
                    cflag, stat, st);
     }
@@ -449,7 +457,7 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
         mark_neighbourhoods(c->dlist.as<int32_t>(), n_dsrc, g0.off, g0.adj, R, st);
       } else {
         Bins b;
-        make_bins(c->dlist.as<int32_t>(), nullptr, n_dsrc, g0.off, b, c->bins, st);
+        make_bins(c->dlist.as<int32_t>(), n_dsrc, g0.off, b, c->bins, st);
         ds_deletions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->sz0.as<int32_t>(),
                      c->two_m, b, R, cflag, stat, st);
       }
@@ -462,15 +470,10 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
     DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
     read_stat(c);
     c->R_count = *static_cast<int32_t*>(c->hbuf);
-    S.ds_sources = hs[ST_DS_SRC];
+    S.ds_sources = n_src;
     S.ds_accepted = hs[ST_DS_ACC];
-    if (c->opt.del_rule == DC_DEL_CONSERVATIVE) {
-      S.del_sources = n_dsrc;
-      S.del_accepted = n_dsrc;
-    } else {
-      S.del_sources = hs[ST_DEL_SRC];
-      S.del_accepted = hs[ST_DEL_ACC];
-    }
+    S.del_sources = n_dsrc;
+    S.del_accepted = c->opt.del_rule == DC_DEL_CONSERVATIVE ? n_dsrc : hs[ST_DEL_ACC];
     S.R_size = c->R_count;
     S.vertex_evals += S.ds_sources + S.del_sources;
     c->have_R_all = false;
@@ -558,7 +561,7 @@ dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1, const dc_options*
   try {
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
     DC_HIP(hipHostMalloc(&c->hbuf, 64));
-    DC_HIP(hipHostMalloc(&c->bins.host, 64));
+    DC_HIP(hipHostMalloc(&c->bins.host, 128));
     DC_HIP(hipHostMalloc(&c->cs.host, 64));
     DC_HIP(hipEventCreate(&c->ev0));
     DC_HIP(hipEventCreate(&c->ev1));

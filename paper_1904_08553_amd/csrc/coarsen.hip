@@ -4,11 +4,12 @@
 // Coarse vertices are the non-empty communities numbered by ascending label.
 // Members are grouped by a stable radix sort of (coarse id, vertex), so each
 // community's members are contiguous and ascending.  The member list is cut
-// into chunks of bounded adjacency volume; one block aggregates a chunk's
-// entries by coarse neighbour in an LDS hash table and flushes the partial
-// sums into the community's global table, so a hub community's diagonal costs
-// one atomic per chunk instead of one per entry.  A pass per community then
-// packs its table into the coarse CSR row.
+// into chunks of bounded adjacency volume; one block sums a chunk's entries
+// by coarse neighbour in an LDS hash table and writes the distinct sums as
+// (coarse row, coarse column, weight) partials.  Sorting the partials by
+// (row, column) and taking segment sums from a prefix scan gives the coarse
+// CSR with sorted rows -- no global atomics on hot rows (a hub community's
+// diagonal gets one partial per chunk).
 #include <cstring>
 
 #include "dc_louvain.h"
@@ -18,8 +19,9 @@ namespace dc {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int VCH = 1024;            // target adjacency volume of a chunk
-constexpr int CHUNK_SLOTS = 4096;    // LDS table; a chunk holds < 2*VCH entries
+constexpr int VCH = 2048;            // target adjacency volume of a chunk
+constexpr int CHUNK_SLOTS = 8192;    // LDS table; a slice holds <= 2*VCH entries
+constexpr int SLICE = 2 * VCH;       // entries aggregated per table fill
 
 inline int grid_for(int64_t n, int64_t cap = 16384) {
   int64_t g = ceil_div(n, TPB);
@@ -65,18 +67,6 @@ __global__ void k_member_deg(const uint32_t* __restrict__ members,
   }
 }
 
-__global__ void k_comm_caps(const int32_t* __restrict__ mstart,
-                            const int32_t* __restrict__ mvol, int32_t nc,
-                            long long* caps) {
-  GRID_STRIDE(r, nc) {
-    int64_t U = mvol[mstart[r + 1]] - mvol[mstart[r]];
-    int64_t lim = U < nc ? U : nc;
-    long long c = 2;
-    while (c < 2 * lim) c <<= 1;
-    caps[r] = c;
-  }
-}
-
 __global__ void k_chunk_heads(const uint64_t* __restrict__ rkey,
                               const int32_t* __restrict__ mstart,
                               const int32_t* __restrict__ mvol,
@@ -97,87 +87,96 @@ __global__ void k_chunk_heads(const uint64_t* __restrict__ rkey,
   }
 }
 
-// one block per chunk of members of one community
+// One block per chunk of members of one community: entries are summed by
+// coarse neighbour in LDS, one slice of at most SLICE entries at a time (a
+// chunk is one slice unless it is a single member with a longer row), and
+// each slice's distinct sums are appended as partials.
 __global__ void __launch_bounds__(TPB)
-    k_coarse_agg(const int32_t* __restrict__ chunks, const uint64_t* __restrict__ rkey,
-                 const uint32_t* __restrict__ members, const int32_t* __restrict__ mvol,
-                 const int32_t* __restrict__ mdeg, const int32_t* __restrict__ off,
-                 const int2* __restrict__ adj, const int32_t* __restrict__ C,
-                 const int32_t* __restrict__ rank, const long long* __restrict__ tab_off,
-                 int* tkeys, int* tvals) {
+    k_coarse_partials(const int32_t* __restrict__ chunks, const uint64_t* __restrict__ rkey,
+                      const uint32_t* __restrict__ members, const int32_t* __restrict__ mvol,
+                      const int32_t* __restrict__ off, const int2* __restrict__ adj,
+                      const int32_t* __restrict__ C, const int32_t* __restrict__ rank,
+                      int32_t nc, uint64_t* pkey, uint32_t* pval, int32_t* pcount) {
   __shared__ int keys[CHUNK_SLOTS];
   __shared__ int vals[CHUNK_SLOTS];
+  __shared__ int wc[TPB / WAVE];
+  __shared__ int bbase;
   const int32_t p0 = chunks[blockIdx.x], p1 = chunks[blockIdx.x + 1];
-  const int32_t r = int32_t(rkey[p0]);
-  const long long t0 = tab_off[r];
-  int* gk = tkeys + t0;
-  int* gv = tvals + t0;
-  const uint32_t gmask = uint32_t(tab_off[r + 1] - t0) - 1;
-  if (p1 - p0 == 1 && mdeg[p0] > VCH) {
-    const uint32_t x = members[p0];
-    for (int32_t j = off[x] + threadIdx.x; j < off[x + 1]; j += TPB) {
-      int2 e = adj[j];
-      table_add(gk, gv, gmask, rank[C[e.x]], e.y);
-    }
-    return;
-  }
-  for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) {
-    keys[s] = EMPTY_KEY;
-    vals[s] = 0;
-  }
-  __syncthreads();
+  const uint64_t row = rkey[p0];
   const int32_t v0 = mvol[p0], v1 = mvol[p1];
-  for (int32_t q = v0 + threadIdx.x; q < v1; q += TPB) {
-    // member p with mvol[p] <= q < mvol[p+1]
-    int32_t lo = p0, hi = p1 - 1;
-    while (lo < hi) {
-      int32_t mid = (lo + hi + 1) >> 1;
-      if (mvol[mid] <= q)
-        lo = mid;
-      else
-        hi = mid - 1;
+  const int wid = threadIdx.x / WAVE, lane = lane_id();
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  for (int32_t s0 = v0; s0 < v1; s0 += SLICE) {
+    const int32_t s1 = s0 + SLICE < v1 ? s0 + SLICE : v1;
+    for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) {
+      keys[s] = EMPTY_KEY;
+      vals[s] = 0;
     }
-    const uint32_t x = members[lo];
-    int2 e = adj[off[x] + (q - mvol[lo])];
-    table_add(keys, vals, CHUNK_SLOTS - 1, rank[C[e.x]], e.y);
-  }
-  __syncthreads();
-  for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) {
-    int key = keys[s];
-    if (key != EMPTY_KEY) table_add(gk, gv, gmask, key, vals[s]);
+    __syncthreads();
+    for (int32_t q = s0 + threadIdx.x; q < s1; q += TPB) {
+      // member p with mvol[p] <= q < mvol[p+1]
+      int32_t lo = p0, hi = p1 - 1;
+      while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (mvol[mid] <= q)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const uint32_t x = members[lo];
+      int2 e = adj[off[x] + (q - mvol[lo])];
+      table_add(keys, vals, CHUNK_SLOTS - 1, rank[C[e.x]], e.y);
+    }
+    __syncthreads();
+    // compact the occupied slots: per-wave ballots, one atomic per block
+    int n_mine = 0;
+    for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) n_mine += keys[s] != EMPTY_KEY ? 1 : 0;
+    int wsum = wave_sum(n_mine);
+    if (lane == 0) wc[wid] = wsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < TPB / WAVE; ++w) tot += wc[w];
+      bbase = atomicAdd(pcount, tot);
+    }
+    __syncthreads();
+    int pos = bbase;
+    for (int w = 0; w < wid; ++w) pos += wc[w];
+    for (int s0b = 0; s0b < CHUNK_SLOTS; s0b += TPB) {
+      const int s = s0b + threadIdx.x;
+      const bool occ = keys[s] != EMPTY_KEY;
+      const uint64_t m = __ballot(occ);
+      if (occ) {
+        const int at = pos + __popcll(m & lt);
+        pkey[at] = row * uint64_t(nc) + uint64_t(keys[s]);
+        pval[at] = uint32_t(vals[s]);
+      }
+      pos += __popcll(m);
+    }
+    __syncthreads();
   }
 }
 
-// one wave per community: number of occupied slots
-__global__ void k_comm_count(const long long* __restrict__ tab_off,
-                             const int* __restrict__ tkeys, int32_t nc, int32_t* cdeg) {
-  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
-  for (int64_t r = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; r < nc;
-       r += nwaves) {
-    int32_t c = 0;
-    for (long long s = tab_off[r] + lane_id(); s < tab_off[r + 1]; s += WAVE)
-      c += tkeys[s] != EMPTY_KEY ? 1 : 0;
-    c = wave_sum(c);
-    if (lane_id() == 0) cdeg[r] = c;
+// Segment sums of sorted partials: the u-th distinct key spans positions
+// [hidx[u], hidx[u+1]); its sum is S[hidx[u+1]] - S[hidx[u]] with S the
+// exclusive prefix of the weights.
+__global__ void k_segment_sums(const uint64_t* __restrict__ pkey,
+                               const int32_t* __restrict__ hidx, int64_t U,
+                               const int32_t* __restrict__ S, int32_t nc, int2* cadj,
+                               uint64_t* ukey) {
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < U;
+       u += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t i = hidx[u], j = hidx[u + 1];
+    const uint64_t k = pkey[i];
+    cadj[u] = make_int2(int32_t(k % uint64_t(nc)), S[j] - S[i]);
+    ukey[u] = k;
   }
 }
 
-__global__ void k_comm_fill(const long long* __restrict__ tab_off,
-                            const int* __restrict__ tkeys, const int* __restrict__ tvals,
-                            int32_t nc, const int32_t* __restrict__ coff, int2* cadj) {
-  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
-  const uint64_t lt = (uint64_t(1) << lane_id()) - 1;
-  for (int64_t r = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; r < nc;
-       r += nwaves) {
-    int32_t w = coff[r];
-    for (long long s0 = tab_off[r]; s0 < tab_off[r + 1]; s0 += WAVE) {
-      long long s = s0 + lane_id();
-      bool occ = s < tab_off[r + 1] && tkeys[s] != EMPTY_KEY;
-      uint64_t m = __ballot(occ);
-      if (occ) cadj[w + __popcll(m & lt)] = make_int2(tkeys[s], tvals[s]);
-      w += __popcll(m);
-    }
-  }
+__global__ void k_u32_to_i32(const uint32_t* __restrict__ in, int64_t n, int32_t* out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = int32_t(in[i]);
 }
 
 __global__ void k_coarse_k(const int32_t* __restrict__ labof, const int32_t* __restrict__ a,
@@ -298,14 +297,6 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
   DC_LAUNCH_CHECK();
   scan_excl_i32(mdeg, mvol, nl, mvol + nl, st);
 
-  // per-community global tables
-  s.caps.ensure(size_t(nc + 1) * 8);
-  long long* caps = s.caps.as<long long>();
-  k_comm_caps<<<grid_for(nc), TPB, 0, st>>>(mstart, mvol, nc, caps);
-  DC_LAUNCH_CHECK();
-  scan_excl_i64(reinterpret_cast<int64_t*>(caps), reinterpret_cast<int64_t*>(caps), nc,
-                reinterpret_cast<int64_t*>(caps + nc), st);
-
   // chunks of bounded volume
   s.chead.ensure(size_t(nl + 1) * 4);
   s.cpos.ensure(size_t(nl + 1) * 4);
@@ -318,41 +309,62 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
   scan_excl_i32(chead, cpos, nl, cpos + nl, st);
   compact_index(chead, cpos, nl, chunks, st);
   DC_HIP(hipMemcpyAsync(host, cpos + nl, 4, hipMemcpyDeviceToHost, st));
-  DC_HIP(hipMemcpyAsync(host + 2, caps + nc, 8, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
   const int32_t nchunks = host[0];
-  long long tslots;
-  memcpy(&tslots, host + 2, 8);
   fill_i32(chunks + nchunks, nl, 1, st);
 
-  s.tkeys.ensure(size_t(tslots) * 4);
-  s.tvals.ensure(size_t(tslots) * 4);
-  int* tkeys = s.tkeys.as<int>();
-  int* tvals = s.tvals.as<int>();
-  fill_i32(tkeys, EMPTY_KEY, tslots, st);
-  fill_i32(tvals, 0, tslots, st);
+  // partial sums per chunk, at most one per entry
+  const int64_t pcap = g.nnz + 1;
+  s.pk0.ensure(size_t(pcap) * 8);
+  s.pk1.ensure(size_t(pcap) * 8);
+  s.pv0.ensure(size_t(pcap) * 4);
+  s.pv1.ensure(size_t(pcap) * 4);
+  s.ph.ensure(size_t(pcap + 1) * 4);
+  s.pp.ensure(size_t(pcap + 1) * 4);
+  s.pS.ensure(size_t(pcap + 1) * 4);
+  uint64_t* pkey = s.pk0.as<uint64_t>();
+  uint32_t* pval = s.pv0.as<uint32_t>();
+  s.pcnt.ensure(8);
+  int32_t* pcnt_dev = s.pcnt.as<int32_t>();
+  fill_i32(pcnt_dev, 0, 1, st);
   if (nchunks > 0) {
-    k_coarse_agg<<<nchunks, TPB, 0, st>>>(chunks, rkey, members, mvol, mdeg, g.off, g.adj, C,
-                                           rank, caps, tkeys, tvals);
+    k_coarse_partials<<<nchunks, TPB, 0, st>>>(chunks, rkey, members, mvol, g.off, g.adj, C, rank,
+                                               nc, pkey, pval, pcnt_dev);
     DC_LAUNCH_CHECK();
   }
-
-  // coarse CSR
-  s.cdeg.ensure(size_t(nc + 1) * 4);
-  int32_t* cdeg = s.cdeg.as<int32_t>();
-  k_comm_count<<<grid_for(int64_t(nc) * WAVE, 4096), TPB, 0, st>>>(caps, tkeys, nc, cdeg);
-  DC_LAUNCH_CHECK();
-  out.off.ensure(size_t(nc + 1) * 4);
-  int32_t* coff = out.off.as<int32_t>();
-  scan_excl_i32(cdeg, coff, nc, coff + nc, st);
-  DC_HIP(hipMemcpyAsync(host, coff + nc, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(host, pcnt_dev, 4, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
-  const int32_t cnnz = host[0];
-  out.adj.ensure(size_t(cnnz) * 8);
-  out.k.ensure(size_t(nc) * 4);
-  k_comm_fill<<<grid_for(int64_t(nc) * WAVE, 4096), TPB, 0, st>>>(caps, tkeys, tvals, nc, coff,
-                                                                  out.adj.as<int2>());
+  const int64_t P = host[0];
+  radix_sort_pairs(pkey, pval, s.pk1.as<uint64_t>(), s.pv1.as<uint32_t>(), P,
+                   ilog2_ceil(uint64_t(nc) * uint64_t(nc)), st);
+  int32_t* ph = s.ph.as<int32_t>();
+  int32_t* pp = s.pp.as<int32_t>();
+  int32_t* pS = s.pS.as<int32_t>();
+  run_heads(pkey, P, ph, st);
+  scan_excl_i32(ph, pp, P, pp + P, st);
+  k_u32_to_i32<<<grid_for(P), TPB, 0, st>>>(pval, P, pS);
   DC_LAUNCH_CHECK();
+  scan_excl_i32(pS, pS, P, pS + P, st);
+  DC_HIP(hipMemcpyAsync(host, pp + P, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  const int32_t cnnz = P > 0 ? host[0] : 0;
+  s.hidx.ensure(size_t(cnnz + 1) * 4);
+  int32_t* hidx = s.hidx.as<int32_t>();
+  compact_index(ph, pp, P, hidx, st);
+  fill_i32(hidx + cnnz, int32_t(P), 1, st);
+
+  // coarse CSR: rows sorted by coarse neighbour
+  out.off.ensure(size_t(nc + 1) * 4);
+  out.adj.ensure(size_t(cnnz + 1) * 8);
+  out.k.ensure(size_t(nc + 1) * 4);
+  s.ukey.ensure(size_t(cnnz + 1) * 8);
+  int32_t* coff = out.off.as<int32_t>();
+  if (P > 0) {
+    k_segment_sums<<<grid_for(cnnz), TPB, 0, st>>>(pkey, hidx, cnnz, pS, nc,
+                                                   out.adj.as<int2>(), s.ukey.as<uint64_t>());
+    DC_LAUNCH_CHECK();
+  }
+  row_bounds(s.ukey.as<uint64_t>(), cnnz, nc, coff, st);
   k_coarse_k<<<grid_for(nc), TPB, 0, st>>>(labof, a, nc, out.k.as<int32_t>());
   DC_LAUNCH_CHECK();
   out.n = nc;

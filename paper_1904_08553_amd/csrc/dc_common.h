@@ -52,7 +52,10 @@ bool sync_check_enabled();
     if (::dc::sync_check_enabled()) DC_HIP(hipDeviceSynchronize());        \
   } while (0)
 
-// Grow-only device buffer; contents are not preserved on growth.
+// Grow-only device buffer; contents are not preserved on growth.  Growth
+// takes 25% headroom so sizes that creep up step by step (the edge count of
+// a growing graph) do not pay a hipFree/hipMalloc pair (an implicit device
+// synchronisation) on every call.
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -68,7 +71,7 @@ struct DBuf {
   void ensure(size_t b) {
     if (b <= bytes && p) return;
     release();
-    size_t want = b < 256 ? 256 : b;
+    size_t want = b < 256 ? 256 : b + b / 4;
     DC_HIP(hipMalloc(&p, want));
     bytes = want;
   }
@@ -78,7 +81,7 @@ struct DBuf {
   }
 };
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline int ilog2_ceil(uint64_t x) {
   int b = 0;

@@ -111,13 +111,15 @@ void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk
                  const int32_t* off, int32_t n, int32_t* new_deg, int32_t* k,
                  const int32_t* C, int32_t* a, hipStream_t st);
 
-// Merge G_{t-1} with the sorted change list into G_t (one wave per row).
-void merge_rows(const int32_t* off_old, const int2* adj_old,
-                const int32_t* off_new, int2* adj_new, int32_t n,
-                const int32_t* cptr, const uint64_t* ch_key,
-                const int32_t* ch_op, const int32_t* ch_w,
-                const int32_t* cum_del, const int32_t* cum_new,
-                hipStream_t st);
+// Merge G_{t-1} with the sorted change list into G_t: rows without changes
+// are copied entry-parallel with their offset shift; the rows listed in
+// `rows` (device count nrows_dev, at most nrows_max) are merged one wave
+// per row.
+void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
+                const int32_t* off_new, int2* adj_new, int32_t n, const int32_t* cptr,
+                const int32_t* rows, const int32_t* nrows_dev, int64_t nrows_max,
+                const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ch_w,
+                const int32_t* cum_del, const int32_t* cum_new, hipStream_t st);
 
 // Exact numerator pieces of Eq. (1) over a CSR with labels C:
 // *I += sum of intra-community entry weights; a_tmp (zeroed, n) receives

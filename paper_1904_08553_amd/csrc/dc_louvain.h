@@ -31,9 +31,13 @@ enum StatSlot : int {
 
 enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2 };
 
-// LDS hash-table sizes of the two LDS bins; rows up to half a table fit.
-constexpr int WAVE_SLOTS = 256;   // bin 0: one wave per vertex, deg <= 128
-constexpr int BLOCK_SLOTS = 4096; // bin 1: one block per vertex, deg <= 2048
+// Row-length bins of the evaluation kernels (eval.hip).
+constexpr int NBINS = 4;
+constexpr int SMALL_MAX = 64;     // bin S: one wave per vertex, no table
+constexpr int WTAB_MAX = 512;     // bin W: one wave, wave-private LDS table
+constexpr int WTAB_SLOTS = 1024;
+constexpr int BTAB_MAX = 4096;    // bin B: one block, block LDS table
+constexpr int BTAB_SLOTS = 8192;  // bin G beyond: one block, global table
 
 struct LevelView {
   int32_t n;
@@ -44,39 +48,38 @@ struct LevelView {
 };
 
 struct Bins {
-  int64_t n[3];
-  const int32_t* list[3];
-  const int32_t* count_dev;   // 3 device counts
-  long long vol[3];           // adjacency entries of each bin
+  int64_t n[NBINS];
+  const int32_t* list[NBINS];
+  long long vol[NBINS];       // adjacency entries of each bin
+  const int32_t* count_dev;   // NBINS device counts
   int* gkeys;
   int* gvals;
   const long long* tab_off;
 };
 
 struct BinScratch {
-  DBuf lists[3];
-  DBuf counts;
-  DBuf tab_off;
-  DBuf gkeys;
-  DBuf gvals;
-  void* host = nullptr;  // pinned, 64 bytes
+  DBuf lists, bcnt, boff, counts, tab_off, gkeys, gvals;
+  void* host = nullptr;  // pinned, 128 bytes
 };
 
-// Splits a vertex list (null = all of [0, count_host)) into the three bins by
-// row length; synchronises to read the bin sizes.
-void make_bins(const int32_t* list, const int32_t* count_dev, int64_t count_host,
-               const int32_t* off, Bins& b, BinScratch& s, hipStream_t st);
+// Splits a vertex list (null = all of [0, count)) into the row-length bins,
+// keeping list order within a bin; synchronises to read the bin sizes.
+void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
+               hipStream_t st);
 
 void sweep_reset(long long* stat, hipStream_t st);
-// ev0/ev1 (may be null) bracket the launch of bin 0, the one-wave-per-vertex
-// kernel that carries most of the work.
+void sweep_reset(long long* stat, hipStream_t st);
+// Writes the next label of every active vertex that moves.  ev0/ev1 (may be
+// null) bracket the launch of bin S, the kernel that carries most vertices.
 void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                 const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                int32_t* movers, long long* stat, hipStream_t st, hipEvent_t ev0,
-                hipEvent_t ev1);
-void sweep_apply(const LevelView& g, int32_t* C, int32_t* Cn, int32_t* a, int32_t* sz,
-                 long long two_m, int64_t max_movers, int32_t* movers, long long* dpack,
-                 int32_t* tflag, int32_t* tlist, long long* stat, hipStream_t st);
+                long long* stat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+// Collects movers from the active list (null = all of [0, n_active)),
+// applies them, computes the exact Delta N and keeps or reverts the sweep.
+void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, int32_t* C,
+                 int32_t* Cn, int32_t* a, int32_t* sz, long long two_m, int32_t* movers,
+                 long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
+                 hipStream_t st);
 
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                   const uint64_t* ins_keys, int64_t n_ins, const Bins& bins, uint8_t* R,
@@ -109,8 +112,8 @@ void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n
 
 // ---- coarsen.hip ----
 struct CoarsenScratch {
-  DBuf flag, rank, keys0, keys1, vals0, vals1, cntr, mstart, labof, mdeg, mvol, caps, tkeys,
-      tvals, chead, cpos, chunks, cdeg, mcnt;
+  DBuf flag, rank, keys0, keys1, vals0, vals1, cntr, mstart, labof, mdeg, mvol, chead, cpos,
+      chunks, mcnt, pk0, pk1, pv0, pv1, ph, pp, pS, pcnt, hidx, ukey;
   void* host = nullptr;  // pinned, 64 bytes
 };
 

@@ -272,52 +272,89 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
-__global__ void k_merge_rows(const int32_t* __restrict__ off_old,
-                             const int2* __restrict__ adj_old,
-                             const int32_t* __restrict__ off_new, int2* adj_new,
-                             int32_t n, const int32_t* __restrict__ cptr,
-                             const uint64_t* __restrict__ ch_key,
-                             const int32_t* __restrict__ ch_op,
-                             const int32_t* __restrict__ ch_w,
-                             const int32_t* __restrict__ cum_del,
-                             const int32_t* __restrict__ cum_new) {
-  int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
+// Untouched rows move as a block: entry e of row r goes to
+// e + off_new[r] - off_old[r].  Each wave takes 256 consecutive entries,
+// finds the first row by a binary search and the row of every entry by a
+// short search inside the few rows the range spans; reads and writes stay
+// contiguous.
+constexpr int COPY_RANGE = 256;
+
+__global__ void __launch_bounds__(TPB)
+    k_merge_copy(const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
+                 const int32_t* __restrict__ off_new, int2* adj_new, int32_t n, int64_t nnz_old,
+                 const int32_t* __restrict__ cptr) {
+  const int64_t nranges = ceil_div(nnz_old, COPY_RANGE);
+  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
   const int lane = lane_id();
-  if (row >= n) return;
-  const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
-  const int32_t cb = cptr[row], ce = cptr[row + 1];
-  if (cb == ce) {
-    for (int32_t j = lane; j < oe - ob; j += WAVE) adj_new[nb + j] = adj_old[ob + j];
-    return;
-  }
-  const uint64_t base = uint64_t(row) * uint64_t(n);
-  const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
-  for (int32_t j = lane; j < oe - ob; j += WAVE) {
-    int2 e = adj_old[ob + j];
-    // first change q in [cb, ce) with dst >= e.x
-    int32_t lo = cb, hi = ce;
+  for (int64_t rg = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; rg < nranges;
+       rg += nwaves) {
+    const int64_t e0 = rg * COPY_RANGE;
+    const int64_t e1 = e0 + COPY_RANGE < nnz_old ? e0 + COPY_RANGE : nnz_old;
+    // r0 = last row with off_old[r] <= e0 (rows may be empty)
+    int32_t lo = 0, hi = n - 1;
     while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (int32_t(ch_key[mid] - base) < e.x)
-        lo = mid + 1;
-      else
-        hi = mid;
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (off_old[mid] <= e0) lo = mid; else hi = mid - 1;
     }
-    int32_t shift = (cum_new[lo] - new0) - (cum_del[lo] - del0);
-    if (lo < ce && int32_t(ch_key[lo] - base) == e.x) {
-      int32_t op = ch_op[lo];
-      if (op == OP_DELETE) continue;
-      if (op == OP_ADD) e.y += ch_w[lo];
-      if (op == OP_REPLACE) e.y = ch_w[lo];
+    const int32_t r0 = lo;
+    for (int64_t e = e0 + lane; e < e1; e += WAVE) {
+      int32_t r = r0;
+      while (off_old[r + 1] <= e) ++r;
+      if (cptr[r] != cptr[r + 1]) continue;  // merged by k_merge_changed
+      adj_new[e + (off_new[r] - off_old[r])] = adj_old[e];
     }
-    adj_new[nb + j + shift] = e;
   }
-  for (int32_t q = cb + lane; q < ce; q += WAVE) {
-    if (ch_op[q] != OP_NEW) continue;
-    int32_t c = int32_t(ch_key[q] - base);
-    int32_t p = find_in_row(adj_old, ob, oe, c) - ob;
-    int32_t shift = (cum_new[q] - new0) - (cum_del[q] - del0);
-    adj_new[nb + p + shift] = make_int2(c, ch_w[q]);
+}
+
+// Rows with changes: one wave per row merges the sorted old row with the
+// row's sorted change list.
+__global__ void k_merge_changed(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
+                                const int32_t* __restrict__ off_old,
+                                const int2* __restrict__ adj_old,
+                                const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
+                                const int32_t* __restrict__ cptr,
+                                const uint64_t* __restrict__ ch_key,
+                                const int32_t* __restrict__ ch_op,
+                                const int32_t* __restrict__ ch_w,
+                                const int32_t* __restrict__ cum_del,
+                                const int32_t* __restrict__ cum_new) {
+  const int64_t nrows = *nrows_dev;
+  const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / WAVE);
+  const int lane = lane_id();
+  for (int64_t p = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE; p < nrows;
+       p += nwaves) {
+    const int32_t row = rows[p];
+    const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
+    const int32_t cb = cptr[row], ce = cptr[row + 1];
+    const uint64_t base = uint64_t(row) * uint64_t(n);
+    const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
+    for (int32_t j = lane; j < oe - ob; j += WAVE) {
+      int2 e = adj_old[ob + j];
+      // first change q in [cb, ce) with dst >= e.x
+      int32_t lo = cb, hi = ce;
+      while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (int32_t(ch_key[mid] - base) < e.x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      int32_t shift = (cum_new[lo] - new0) - (cum_del[lo] - del0);
+      if (lo < ce && int32_t(ch_key[lo] - base) == e.x) {
+        int32_t op = ch_op[lo];
+        if (op == OP_DELETE) continue;
+        if (op == OP_ADD) e.y += ch_w[lo];
+        if (op == OP_REPLACE) e.y = ch_w[lo];
+      }
+      adj_new[nb + j + shift] = e;
+    }
+    for (int32_t q = cb + lane; q < ce; q += WAVE) {
+      if (ch_op[q] != OP_NEW) continue;
+      int32_t c = int32_t(ch_key[q] - base);
+      int32_t pos = find_in_row(adj_old, ob, oe, c) - ob;
+      int32_t shift = (cum_new[q] - new0) - (cum_del[q] - del0);
+      adj_new[nb + pos + shift] = make_int2(c, ch_w[q]);
+    }
   }
 }
 
@@ -475,16 +512,23 @@ void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk
   DC_LAUNCH_CHECK();
 }
 
-void merge_rows(const int32_t* off_old, const int2* adj_old,
-                const int32_t* off_new, int2* adj_new, int32_t n,
-                const int32_t* cptr, const uint64_t* ch_key,
-                const int32_t* ch_op, const int32_t* ch_w,
-                const int32_t* cum_del, const int32_t* cum_new,
-                hipStream_t st) {
+void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
+                const int32_t* off_new, int2* adj_new, int32_t n, const int32_t* cptr,
+                const int32_t* rows, const int32_t* nrows_dev, int64_t nrows_max,
+                const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ch_w,
+                const int32_t* cum_del, const int32_t* cum_new, hipStream_t st) {
   if (n <= 0) return;
-  k_merge_rows<<<ceil_div(int64_t(n) * WAVE, TPB), TPB, 0, st>>>(
-      off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w, cum_del, cum_new);
-  DC_LAUNCH_CHECK();
+  if (nnz_old > 0) {
+    k_merge_copy<<<grid_for(ceil_div(nnz_old, COPY_RANGE) * WAVE, TPB, 16384), TPB, 0, st>>>(
+        off_old, adj_old, off_new, adj_new, n, nnz_old, cptr);
+    DC_LAUNCH_CHECK();
+  }
+  if (nrows_max > 0) {
+    k_merge_changed<<<grid_for(nrows_max * WAVE, TPB, 16384), TPB, 0, st>>>(
+        rows, nrows_dev, off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w,
+        cum_del, cum_new);
+    DC_LAUNCH_CHECK();
+  }
 }
 
 void intra_weight(const int32_t* off, const int2* adj, const int32_t* C,
