@@ -32,7 +32,7 @@ struct dc_ctx {
   DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
   DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
   DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
-  DBuf R, cflag, rflag, rpos2, Rlist;
+  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end;
   // levels
   DBuf Cl, Cn, al, szl, dpack, tflag, tlist, movers, map0, cnt[2], minv[2], lab, cntf;
   CoarseGraph cg[2];
@@ -104,7 +104,7 @@ void ensure_vertex_state(dc_ctx* c) {
   for (DBuf* b : {&c->k0, &c->C, &c->a0, &c->sz0, &c->Cl, &c->Cn, &c->al, &c->szl, &c->tflag,
                   &c->tlist, &c->movers, &c->map0, &c->cnt[0], &c->cnt[1], &c->minv[0],
                   &c->minv[1], &c->lab, &c->cntf, &c->dflag, &c->dpos, &c->dlist, &c->rflag,
-                  &c->rpos2, &c->Rlist})
+                  &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end})
     b->ensure((n + 1) * 4);
   c->dpack.ensure((n + 1) * 8);
   c->R.ensure(n + 1);
@@ -140,12 +140,16 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
     const int64_t nact = level == 0 ? n_active : g.n;
     Bins bins;
     make_bins(act, nact, g.off, bins, c->bins, st);
-    const int64_t n_eval = bins.n[0] + bins.n[1] + bins.n[2] + bins.n[3];
-    const long long vol_eval = bins.vol[0] + bins.vol[1] + bins.vol[2] + bins.vol[3];
+    int64_t n_eval = 0;
+    long long vol_eval = 0;
+    for (int q = 0; q < NBINS; ++q) {
+      n_eval += bins.n[q];
+      vol_eval += bins.vol[q];
+    }
     long long level_gain = 0;
     for (int s = 0; s < c->opt.max_sweeps; ++s) {
       sweep_reset(c->stat.as<long long>(), st);
-      const bool timed = c->opt.timing && bins.n[0] > 0;
+      const bool timed = c->opt.timing && bins.n[TIMED_BIN] > 0;
       sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
                  c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,
                  timed ? c->ev1 : nullptr);
@@ -158,10 +162,10 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
         DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
         S.ms_sweep_kernel += ms;
         S.sweep_launches += 1;
-        // algorithmic bytes of the bin-S launch: 12 B per adjacency entry
+        // algorithmic bytes of the timed launch: 12 B per adjacency entry
         // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
         // (two offsets, label, degree, own total and size, best total, result)
-        S.sweep_bytes += 12 * bins.vol[0] + 32 * bins.n[0];
+        S.sweep_bytes += 12 * bins.vol[TIMED_BIN] + 32 * bins.n[TIMED_BIN];
       }
       dc_sweep_rec r{};
       r.level = level;
@@ -435,6 +439,7 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
     source_heads(ins_keys, n_ins, n, src_flag, st);
     scan_excl_i32(src_flag, src_pos, n_ins, reinterpret_cast<int32_t*>(stat + ST_N3), st);
     gather_sources(ins_keys, src_flag, src_pos, n_ins, n, c->src_list.as<int32_t>(), st);
+    source_segments(ins_keys, n_ins, n, c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), st);
     // deletion sources (labels C_{t-1})
     int32_t* dflag = c->dflag.as<int32_t>();
     fill_i32(dflag, 0, n, st);
@@ -449,8 +454,8 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
     if (n_src > 0) {
       Bins b;
       make_bins(c->src_list.as<int32_t>(), n_src, g0.off, b, c->bins, st);
-      ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins, b, R,
-                   cflag, stat, st);
+      ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
+                   c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), b, R, cflag, stat, st);
     }
     if (n_dsrc > 0) {
       if (c->opt.del_rule == DC_DEL_CONSERVATIVE) {
@@ -561,7 +566,7 @@ dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1, const dc_options*
   try {
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
     DC_HIP(hipHostMalloc(&c->hbuf, 64));
-    DC_HIP(hipHostMalloc(&c->bins.host, 128));
+    DC_HIP(hipHostMalloc(&c->bins.host, 256));
     DC_HIP(hipHostMalloc(&c->cs.host, 64));
     DC_HIP(hipEventCreate(&c->ev0));
     DC_HIP(hipEventCreate(&c->ev1));

@@ -31,13 +31,14 @@ enum StatSlot : int {
 
 enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2 };
 
-// Row-length bins of the evaluation kernels (eval.hip).
-constexpr int NBINS = 4;
-constexpr int SMALL_MAX = 64;     // bin S: one wave per vertex, no table
-constexpr int WTAB_MAX = 512;     // bin W: one wave, wave-private LDS table
+// Row-length bins of the evaluation kernels (eval.hip): rows of at most 16,
+// 32 and 64 entries (4, 2 and 1 vertices per wave, no table), then
+constexpr int NBINS = 6;
+constexpr int WTAB_MAX = 512;     // one wave, wave-private LDS table
 constexpr int WTAB_SLOTS = 1024;
-constexpr int BTAB_MAX = 4096;    // bin B: one block, block LDS table
-constexpr int BTAB_SLOTS = 8192;  // bin G beyond: one block, global table
+constexpr int BTAB_MAX = 4096;    // one block, block LDS table
+constexpr int BTAB_SLOTS = 8192;  // beyond: one block, global table
+constexpr int TIMED_BIN = 1;      // the bin whose launches the timing option brackets
 
 struct LevelView {
   int32_t n;
@@ -59,7 +60,7 @@ struct Bins {
 
 struct BinScratch {
   DBuf lists, bcnt, boff, counts, tab_off, gkeys, gvals;
-  void* host = nullptr;  // pinned, 128 bytes
+  void* host = nullptr;  // pinned, 256 bytes
 };
 
 // Splits a vertex list (null = all of [0, count)) into the row-length bins,
@@ -70,7 +71,8 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
 void sweep_reset(long long* stat, hipStream_t st);
 void sweep_reset(long long* stat, hipStream_t st);
 // Writes the next label of every active vertex that moves.  ev0/ev1 (may be
-// null) bracket the launch of bin S, the kernel that carries most vertices.
+// null) bracket the launch of bin TIMED_BIN (rows of 17 to 32 entries, two
+// vertices per wave), the kernel that carries the most vertices.
 void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                 const int32_t* sz, long long two_m, int guard, const Bins& bins,
                 long long* stat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
@@ -81,9 +83,11 @@ void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, in
                  long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
                  hipStream_t st);
 
+// seg_beg/seg_end: per source vertex, its sinks are ins_keys[beg, end).
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
-                  const uint64_t* ins_keys, int64_t n_ins, const Bins& bins, uint8_t* R,
-                  uint8_t* cflag, long long* stat, hipStream_t st);
+                  const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
+                  const int32_t* seg_end, const Bins& bins, uint8_t* R, uint8_t* cflag,
+                  long long* stat, hipStream_t st);
 void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
                   long long two_m, const Bins& bins, uint8_t* R, uint8_t* cflag,
                   long long* stat, hipStream_t st);
@@ -100,6 +104,9 @@ void gather_u64(const uint64_t* in, const int32_t* flag, const int32_t* pos, int
 void source_heads(const uint64_t* keys, int64_t m, int32_t n, int32_t* flag, hipStream_t st);
 void gather_sources(const uint64_t* keys, const int32_t* flag, const int32_t* pos, int64_t m,
                     int32_t n, int32_t* out, hipStream_t st);
+// seg_beg[src] / seg_end[src] = first / one-past-last index of src's keys.
+void source_segments(const uint64_t* keys, int64_t m, int32_t n, int32_t* seg_beg,
+                     int32_t* seg_end, hipStream_t st);
 // dflag[src] = 1 for deleted pairs inside one community.
 void deletion_sources(const uint64_t* ch_key, const int32_t* ch_op, int64_t nch, int32_t n,
                       const int32_t* C, int32_t* dflag, hipStream_t st);

@@ -47,6 +47,8 @@ struct EvalArgs {
   const long long* tab_off;
   long long* stat;
   const uint64_t* ins_keys;  // Alg. 2: sorted directed insertions src*n0+dst
+  const int32_t* seg_beg;    // per source vertex: its sinks are ins_keys[beg, end)
+  const int32_t* seg_end;
   int64_t n_ins;
   int32_t n0;
   uint8_t* R;
@@ -113,25 +115,6 @@ __device__ __forceinline__ Cand wave_cand(Cand c) {
   return c;
 }
 
-// Sources of i among the sorted directed insertion keys: [q0, q1).
-__device__ __forceinline__ void sink_range(const EvalArgs& A, int i, int64_t& q0,
-                                           int64_t& q1) {
-  const uint64_t base = uint64_t(i) * uint64_t(A.n0);
-  int64_t lo = 0, hi = A.n_ins;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (A.ins_keys[mid] < base) lo = mid + 1; else hi = mid;
-  }
-  q0 = lo;
-  hi = A.n_ins;
-  const uint64_t end = base + uint64_t(A.n0);
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (A.ins_keys[mid] < end) lo = mid + 1; else hi = mid;
-  }
-  q1 = lo;
-}
-
 // gain2 of Alg. 2: G(j* -> c), streamed over the row of j* by one wave.
 __device__ __forceinline__ long long reverse_gain(const EvalArgs& A, int js, int cj, int c) {
   long long e_to = 0, e_self = 0;
@@ -149,77 +132,166 @@ __device__ __forceinline__ long long reverse_gain(const EvalArgs& A, int js, int
 }
 
 // --------------------------------------------------------------------------
-// bin S: rows of at most 64 entries, one wave per vertex, no table.
+// bins S16/S32/S64: rows of at most GS entries, no table.  A wave is split
+// into 64/GS groups of GS lanes, each group evaluating its own vertex: wave
+// instructions cost the same for 16 or 64 busy lanes, so packing four
+// 16-entry rows into one wave divides the instruction count per vertex by
+// four.  Ballots stay wave-wide and are masked to the group; shuffles and
+// reductions run within the group.
 
-template <int MODE>
-__global__ void __launch_bounds__(TPB) k_eval_small(EvalArgs A) {
+template <int GS>
+__device__ __forceinline__ long long group_sum_ll(long long v) {
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
+  return v;
+}
+
+template <int GS>
+__device__ __forceinline__ int group_sum_i(int v) {
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
+  return v;
+}
+
+template <int GS>
+__device__ __forceinline__ Best group_best_w(Best b) {
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) {
+    long long s = __shfl_xor(b.s, o, GS);
+    int x = __shfl_xor(b.x, o, GS);
+    if (better(s, x, b.s, b.x)) {
+      b.s = s;
+      b.x = x;
+    }
+  }
+  return b;
+}
+
+template <int GS>
+__device__ __forceinline__ Cand group_cand_w(Cand c) {
+#pragma unroll
+  for (int o = GS / 2; o > 0; o >>= 1) {
+    Cand y;
+    y.g = __shfl_xor(c.g, o, GS);
+    y.x = __shfl_xor(c.x, o, GS);
+    y.j = __shfl_xor(c.j, o, GS);
+    if (cand_better(y, c)) c = y;
+  }
+  return c;
+}
+
+// Per group: lane r of the group (r < returned count) receives the r-th
+// distinct label of the group's valid lanes and its weight sum.
+template <int GS>
+__device__ __forceinline__ int group_collect(bool valid, int key, int w, uint64_t gmask,
+                                             int& ck, int& cs) {
   const int lane = lane_id();
+  const int gl = lane & (GS - 1);
+  uint64_t rem = __ballot(valid) & gmask;
+  int r = 0;
+  while (__ballot(rem != 0)) {
+    const bool act = rem != 0;
+    const int leader = act ? __ffsll((unsigned long long)rem) - 1 : lane;
+    const int kl = __shfl(key, leader, WAVE);
+    const bool mine = act && valid && key == kl;
+    rem &= ~(__ballot(mine) & gmask);
+    const int sum = group_sum_i<GS>(mine ? w : 0);
+    if (act && gl == r) {
+      ck = kl;
+      cs = sum;
+    }
+    r += act ? 1 : 0;
+  }
+  return r;
+}
+
+template <int MODE, int GS>
+__global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
+  constexpr int GPW = WAVE / GS;  // groups per wave
+  const int lane = lane_id();
+  const int gl = lane & (GS - 1);
+  const int gbase = lane - gl;
+  const uint64_t gmask = GS == WAVE ? ~uint64_t(0) : (((uint64_t(1) << GS) - 1) << gbase);
   const int64_t cnt = *A.count;
-  const int64_t nwaves = int64_t(gridDim.x) * NW;
+  const int64_t ngroups = int64_t(gridDim.x) * NW * GPW;
   long long accepted = 0;
-  for (int64_t idx = int64_t(blockIdx.x) * NW + threadIdx.x / WAVE; idx < cnt; idx += nwaves) {
-    const int i = uniform(A.list[idx]);
-    const int32_t rb = A.off[i], re = A.off[i + 1];
-    const int c = A.C[i];
-    const long long ki = A.k[i];
-    bool valid = rb + lane < re;
-    int2 e = valid ? A.adj[rb + lane] : make_int2(0, 0);
-    if (e.x == i) valid = false;
+  const int64_t g0 = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * GPW + lane / GS;
+  // every group of a wave runs the same number of iterations (wave-uniform)
+  const int64_t w0 = g0 - lane / GS;
+  for (int64_t wb = w0; wb < cnt; wb += ngroups) {
+    const int64_t idx = wb + lane / GS;
+    const bool have = idx < cnt;
+    const int i = have ? A.list[idx] : 0;
+    const int32_t rb = have ? A.off[i] : 0;
+    const int32_t re = have ? A.off[i + 1] : 0;
+    const int c = have ? A.C[i] : 0;
+    const long long ki = have ? A.k[i] : 0;
+    const int2 e = rb + gl < re ? A.adj[rb + gl] : make_int2(-1, 0);
+    const bool valid = e.x >= 0 && e.x != i;
     const int key = valid ? A.C[e.x] : EMPTY_KEY;
     int ck = EMPTY_KEY, cs = 0;
-    const int nd = wave_collect(valid, key, e.y, ck, cs);
-    const long long e_own = collected_sum(nd, ck, cs, c);
-    const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
+    const int nd = group_collect<GS>(valid, key, e.y, gmask, ck, cs);
+    const bool pair = gl < nd;
+    const long long e_own = group_sum_ll<GS>(pair && ck == c ? (long long)cs : 0);
+    const long long s_own = A.two_m * e_own - ki * ((have ? A.a[c] : 0) - ki);
     if (MODE == EV_DSADD) {
-      int64_t q0, q1;
-      sink_range(A, i, q0, q1);
-      const int nsk = int(q1 - q0);  // sinks are neighbours, so nsk <= 64
-      const bool has = lane < nsk;
-      const int j = has ? int(A.ins_keys[q0 + lane] - uint64_t(i) * uint64_t(A.n0)) : 0;
-      const int Xj = has ? A.C[j] : EMPTY_KEY;
-      // e_{i->C(j)} for every sink lane: scan the nd collected pairs
+      const int q0 = have ? A.seg_beg[i] : 0;
+      const int nsk = have ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
+      const bool has = gl < nsk;
+      const int sj = has ? int(A.ins_keys[q0 + gl] - uint64_t(i) * uint64_t(A.n0)) : 0;
+      const int Xj = has ? A.C[sj] : EMPTY_KEY;
       long long ej = 0;
-      for (int r = 0; r < nd; ++r) {
-        const int kr = __builtin_amdgcn_readlane(ck, r);
-        const int sr = __builtin_amdgcn_readlane(cs, r);
-        if (Xj == kr) ej = sr;
+      const int ndw = wave_max(nd);
+      for (int r = 0; r < ndw; ++r) {
+        const int kr = __shfl(ck, gbase + r, WAVE);
+        const int sr = __shfl(cs, gbase + r, WAVE);
+        if (r < nd && Xj == kr) ej = sr;
       }
       Cand cd = {NO_SCORE, NO_LABEL, NO_LABEL};
       if (has) {
         long long g = Xj == c ? 0 : A.two_m * ej - ki * A.a[Xj] - s_own;
-        cd = {g, Xj, j};
+        cd = {g, Xj, sj};
       }
-      const Cand best = wave_cand(cd);
-      if (best.j != NO_LABEL && best.x != c && best.g > 0) {
-        const long long g2 = reverse_gain(A, best.j, best.x, c);
-        if (best.g >= g2) {
-          if (valid) A.R[e.x] = 1;
-          if (lane == 0) {
-            A.R[i] = 1;
-            A.R[best.j] = 1;
-            A.cflag[best.x] = 1;
-            accepted++;
-          }
+      const Cand best = group_cand_w<GS>(cd);
+      const bool live = have && best.j != NO_LABEL && best.x != c && best.g > 0;
+      // gain2 of each live group, streamed by the whole wave (j* is often a
+      // high-degree vertex, and a 16-lane group would walk its row alone)
+      long long g2 = 0;
+      for (uint64_t lm = __ballot(live && gl == 0); lm; lm &= lm - 1) {
+        const int ld = __ffsll((unsigned long long)lm) - 1;
+        const long long r = reverse_gain(A, __shfl(best.j, ld, WAVE), __shfl(best.x, ld, WAVE),
+                                         __shfl(c, ld, WAVE));
+        if (lane / GS == ld / GS) g2 = r;
+      }
+      if (live && best.g >= g2) {
+        if (e.x >= 0) A.R[e.x] = 1;
+        if (gl == 0) {
+          A.R[i] = 1;
+          A.R[best.j] = 1;
+          A.cflag[best.x] = 1;
+          accepted++;
         }
       }
       continue;
     }
     Best b = {NO_SCORE, NO_LABEL};
-    if (lane < nd && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
-    b = wave_best(b);
-    bool move = b.x != NO_LABEL && b.s > s_own;
+    if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
+    b = group_best_w<GS>(b);
+    bool move = have && b.x != NO_LABEL && b.s > s_own;
     if (MODE == EV_SWEEP) {
-      if (move && A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c) move = false;
-      if (move && lane == 0) A.Cn[i] = b.x;
+      if (move && gl == 0) {
+        if (!(A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c)) A.Cn[i] = b.x;
+      }
     } else if (move) {  // EV_DSDEL
-      if (valid) A.R[e.x] = 1;
-      if (lane == 0) {
+      if (e.x >= 0) A.R[e.x] = 1;
+      if (gl == 0) {
         A.R[i] = 1;
         A.cflag[b.x] = 1;
         accepted++;
       }
     }
   }
+  accepted = group_sum_ll<WAVE>(accepted);
   if (MODE != EV_SWEEP && lane == 0 && accepted)
     atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC],
               (unsigned long long)accepted);
@@ -272,6 +344,27 @@ __device__ __forceinline__ Cand group_cand(Cand c, GroupLds<G>& L) {
     if (cand_better(L.cand[w], r)) r = L.cand[w];
   __syncthreads();
   return r;
+}
+
+template <int G>
+__device__ __forceinline__ void group_sum2(long long& x, long long& y, GroupLds<G>& L) {
+  x = wave_sum(x);
+  y = wave_sum(y);
+  if (G == WAVE) return;
+  const int wid = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    L.s0[wid] = x;
+    L.s1[wid] = y;
+  }
+  __syncthreads();
+  x = 0;
+  y = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    x += L.s0[w];
+    y += L.s1[w];
+  }
+  __syncthreads();
 }
 
 template <int G>
@@ -329,25 +422,28 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
     keys[s] = EMPTY_KEY;
     vals[s] = 0;
   }
-  if (t == 0) *own = 0;
   group_sync<G>();
+  // the own community (usually most of the row) is summed in registers;
+  // every other entry goes straight into the table, one lane per entry
+  long long own_part = 0;
   const int w0 = (G == WAVE) ? 0 : int(threadIdx.x) / WAVE;
   for (int32_t c0 = rb + w0 * WAVE; c0 < re; c0 += G) {
     bool valid = c0 + lane < re;
     int2 e = valid ? A.adj[c0 + lane] : make_int2(0, 0);
     if (e.x == i) valid = false;
     const int key = valid ? A.C[e.x] : EMPTY_KEY;
-    int ck = EMPTY_KEY, cs = 0;
-    const int nd = wave_collect(valid, key, e.y, ck, cs);
-    if (lane < nd) table_add(keys, vals, mask, ck, cs);
+    if (key == c)
+      own_part += e.y;
+    else if (valid)
+      table_add(keys, vals, mask, key, e.y);
   }
+  long long e_own = own_part, unused = 0;
+  group_sum2<G>(e_own, unused, L);
   group_sync<G>();
   int accepted = 0;
   if (MODE == EV_DSADD) {
-    const int e_own = table_get(keys, vals, mask, c);
     const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
-    int64_t q0, q1;
-    sink_range(A, i, q0, q1);
+    const int64_t q0 = A.seg_beg[i], q1 = A.seg_end[i];
     const uint64_t base = uint64_t(i) * uint64_t(A.n0);
     Cand best = {NO_SCORE, NO_LABEL, NO_LABEL};
     for (int64_t q = q0 + t; q < q1; q += G) {
@@ -378,12 +474,7 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   for (uint32_t s = t; s <= mask; s += G) {
     const int X = keys[s];
     if (X == EMPTY_KEY) continue;
-    const int e = vals[s];
-    if (X == c) {
-      *own = e;
-      continue;
-    }
-    const long long sc = A.two_m * e - ki * A.a[X];
+    const long long sc = A.two_m * vals[s] - ki * A.a[X];
     if (better(sc, X, b.s, b.x)) {
       b.s = sc;
       b.x = X;
@@ -391,7 +482,7 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   }
   b = group_best<G>(b, L);
   group_sync<G>();
-  const long long s_own = A.two_m * (long long)(*own) - ki * (A.a[c] - ki);
+  const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
   bool move = b.x != NO_LABEL && b.s > s_own;
   if (MODE == EV_SWEEP) {
     if (move && A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c) move = false;
@@ -468,7 +559,7 @@ constexpr int BIN_ITEMS = 4;
 constexpr int BIN_TILE = TPB * BIN_ITEMS;
 
 __device__ __forceinline__ int bin_of(int d) {
-  return d <= SMALL_MAX ? 0 : (d <= WTAB_MAX ? 1 : (d <= BTAB_MAX ? 2 : 3));
+  return d <= 16 ? 0 : d <= 32 ? 1 : d <= 64 ? 2 : d <= WTAB_MAX ? 3 : d <= BTAB_MAX ? 4 : 5;
 }
 
 __global__ void __launch_bounds__(TPB)
@@ -481,8 +572,13 @@ __global__ void __launch_bounds__(TPB)
     v[threadIdx.x] = 0;
   }
   __syncthreads();
-  int lc[NBINS] = {0, 0, 0, 0};
-  long long lv[NBINS] = {0, 0, 0, 0};
+  int lc[NBINS];
+  long long lv[NBINS];
+#pragma unroll
+  for (int q = 0; q < NBINS; ++q) {
+    lc[q] = 0;
+    lv[q] = 0;
+  }
   for (int r = 0; r < BIN_ITEMS; ++r) {
     int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
     if (p < cnt) {
@@ -601,33 +697,43 @@ template <int MODE>
 void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEvent_t ev0,
                  hipEvent_t ev1) {
   EvalArgs A = base;
+  auto setbin = [&](int q) {
+    A.list = bins.list[q];
+    A.count = bins.count_dev + q;
+  };
   if (bins.n[0] > 0) {
-    A.list = bins.list[0];
-    A.count = bins.count_dev + 0;
+    setbin(0);
+    k_eval_group<MODE, 16><<<wave_grid(ceil_div(bins.n[0], 4)), TPB, 0, st>>>(A);
+    DC_LAUNCH_CHECK();
+  }
+  if (bins.n[1] > 0) {
+    setbin(1);
     if (ev0) DC_HIP(hipEventRecord(ev0, st));
-    k_eval_small<MODE><<<wave_grid(bins.n[0]), TPB, 0, st>>>(A);
+    k_eval_group<MODE, 32><<<wave_grid(ceil_div(bins.n[1], 2)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
     if (ev1) DC_HIP(hipEventRecord(ev1, st));
   }
-  if (bins.n[1] > 0) {
-    A.list = bins.list[1];
-    A.count = bins.count_dev + 1;
-    k_eval_wtab<MODE><<<wave_grid(bins.n[1]), TPB, 0, st>>>(A);
-    DC_LAUNCH_CHECK();
-  }
   if (bins.n[2] > 0) {
-    A.list = bins.list[2];
-    A.count = bins.count_dev + 2;
-    k_eval_btab<MODE><<<bins.n[2], TPB, 0, st>>>(A);
+    setbin(2);
+    k_eval_group<MODE, 64><<<wave_grid(bins.n[2]), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
   if (bins.n[3] > 0) {
-    A.list = bins.list[3];
-    A.count = bins.count_dev + 3;
+    setbin(3);
+    k_eval_wtab<MODE><<<wave_grid(bins.n[3]), TPB, 0, st>>>(A);
+    DC_LAUNCH_CHECK();
+  }
+  if (bins.n[4] > 0) {
+    setbin(4);
+    k_eval_btab<MODE><<<bins.n[4], TPB, 0, st>>>(A);
+    DC_LAUNCH_CHECK();
+  }
+  if (bins.n[5] > 0) {
+    setbin(5);
     A.gkeys = bins.gkeys;
     A.gvals = bins.gvals;
     A.tab_off = bins.tab_off;
-    k_eval_gtab<MODE><<<bins.n[3], TPB, 0, st>>>(A);
+    k_eval_gtab<MODE><<<bins.n[5], TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
 }
@@ -641,28 +747,31 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   s.lists.ensure(size_t(cap) * sizeof(int32_t));
   s.bcnt.ensure(size_t(NBINS * nb + 1) * sizeof(int32_t));
   s.boff.ensure(size_t(NBINS * nb + 1) * sizeof(int32_t));
-  constexpr size_t META = 16 * sizeof(int32_t) + NBINS * sizeof(long long);
+  constexpr size_t META = 32 * sizeof(int32_t) + NBINS * sizeof(long long);
+  static_assert(META <= 256, "bin metadata must fit the pinned host buffer");
   s.counts.ensure(META);
-  int32_t* counts = s.counts.as<int32_t>();      // [0..3] counts, [4..7] starts, [8] total
-  long long* vol = reinterpret_cast<long long*>(counts + 16);
+  // [0, NBINS) counts, [NBINS, 2 NBINS) starts, [2 NBINS] total
+  int32_t* counts = s.counts.as<int32_t>();
+  long long* vol = reinterpret_cast<long long*>(counts + 32);
   int32_t* bcnt = s.bcnt.as<int32_t>();
   int32_t* boff = s.boff.as<int32_t>();
   DC_HIP(hipMemsetAsync(counts, 0, META, st));
   if (count > 0) {
     k_bin_count<<<nb, TPB, 0, st>>>(list, count, off, bcnt, vol, nb);
     DC_LAUNCH_CHECK();
-    scan_excl_i32(bcnt, boff, NBINS * nb, counts + 8, st);
-    k_bin_starts<<<1, 64, 0, st>>>(boff, nb, NBINS * nb, counts + 8, counts + 4, counts);
+    scan_excl_i32(bcnt, boff, NBINS * nb, counts + 2 * NBINS, st);
+    k_bin_starts<<<1, 64, 0, st>>>(boff, nb, NBINS * nb, counts + 2 * NBINS, counts + NBINS,
+                                   counts);
     DC_LAUNCH_CHECK();
   }
   DC_HIP(hipMemcpyAsync(s.host, counts, META, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
   const int32_t* hc = static_cast<const int32_t*>(s.host);
-  const long long* hv = reinterpret_cast<const long long*>(hc + 16);
+  const long long* hv = reinterpret_cast<const long long*>(hc + 32);
   int32_t* lists = s.lists.as<int32_t>();
   for (int q = 0; q < NBINS; ++q) {
     b.n[q] = hc[q];
-    b.list[q] = lists + hc[4 + q];
+    b.list[q] = lists + hc[NBINS + q];
     b.vol[q] = hv[q];
   }
   b.count_dev = counts;
@@ -673,14 +782,15 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
     k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, boff, nb, lists);
     DC_LAUNCH_CHECK();
   }
-  if (b.n[3] > 0) {
-    s.tab_off.ensure(size_t(b.n[3] + 1) * sizeof(long long));
+  constexpr int G = NBINS - 1;
+  if (b.n[G] > 0) {
+    s.tab_off.ensure(size_t(b.n[G] + 1) * sizeof(long long));
     long long* caps = s.tab_off.as<long long>();
-    k_table_caps<<<grid_for(b.n[3]), TPB, 0, st>>>(b.list[3], off, b.n[3], caps);
+    k_table_caps<<<grid_for(b.n[G]), TPB, 0, st>>>(b.list[G], off, b.n[G], caps);
     DC_LAUNCH_CHECK();
-    scan_excl_i64(reinterpret_cast<int64_t*>(caps), reinterpret_cast<int64_t*>(caps), b.n[3],
-                  reinterpret_cast<int64_t*>(caps + b.n[3]), st);
-    const size_t slots = size_t(4 * hv[3] + 2 * b.n[3] + 16);
+    scan_excl_i64(reinterpret_cast<int64_t*>(caps), reinterpret_cast<int64_t*>(caps), b.n[G],
+                  reinterpret_cast<int64_t*>(caps + b.n[G]), st);
+    const size_t slots = size_t(4 * hv[G] + 2 * b.n[G] + 16);
     s.gkeys.ensure(slots * sizeof(int));
     s.gvals.ensure(slots * sizeof(int));
     b.gkeys = s.gkeys.as<int>();
@@ -708,8 +818,9 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
 }
 
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
-                  const uint64_t* ins_keys, int64_t n_ins, const Bins& bins, uint8_t* R,
-                  uint8_t* cflag, long long* stat, hipStream_t st) {
+                  const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
+                  const int32_t* seg_end, const Bins& bins, uint8_t* R, uint8_t* cflag,
+                  long long* stat, hipStream_t st) {
   EvalArgs A{};
   A.off = g.off;
   A.adj = g.adj;
@@ -719,6 +830,8 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
   A.two_m = two_m;
   A.stat = stat;
   A.ins_keys = ins_keys;
+  A.seg_beg = seg_beg;
+  A.seg_end = seg_end;
   A.n_ins = n_ins;
   A.n0 = g.n;
   A.R = R;

@@ -58,6 +58,15 @@ __global__ void k_gather_sources(const uint64_t* __restrict__ keys,
   }
 }
 
+__global__ void k_source_segments(const uint64_t* __restrict__ keys, int64_t m, int32_t n,
+                                  int32_t* seg_beg, int32_t* seg_end) {
+  GRID_STRIDE(i, m) {
+    const uint64_t src = keys[i] / uint64_t(n);
+    if (i == 0 || keys[i - 1] / uint64_t(n) != src) seg_beg[src] = int32_t(i);
+    if (i == m - 1 || keys[i + 1] / uint64_t(n) != src) seg_end[src] = int32_t(i + 1);
+  }
+}
+
 __global__ void k_deletion_sources(const uint64_t* __restrict__ key,
                                    const int32_t* __restrict__ op, int64_t nch,
                                    int32_t n, const int32_t* __restrict__ C,
@@ -125,6 +134,13 @@ void gather_sources(const uint64_t* keys, const int32_t* flag, const int32_t* po
                     int32_t n, int32_t* out, hipStream_t st) {
   if (m <= 0) return;
   k_gather_sources<<<grid_for(m), TPB, 0, st>>>(keys, flag, pos, m, n, out);
+  DC_LAUNCH_CHECK();
+}
+
+void source_segments(const uint64_t* keys, int64_t m, int32_t n, int32_t* seg_beg,
+                     int32_t* seg_end, hipStream_t st) {
+  if (m <= 0) return;
+  k_source_segments<<<grid_for(m), TPB, 0, st>>>(keys, m, n, seg_beg, seg_end);
   DC_LAUNCH_CHECK();
 }
 
