@@ -19,9 +19,10 @@ namespace dc {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int VCH = 2048;            // target adjacency volume of a chunk
-constexpr int CHUNK_SLOTS = 8192;    // LDS table; a slice holds <= 2*VCH entries
+constexpr int VCH = 1024;            // target adjacency volume of a chunk
+constexpr int CHUNK_SLOTS = 4096;    // LDS table; a slice holds <= 2*VCH entries
 constexpr int SLICE = 2 * VCH;       // entries aggregated per table fill
+constexpr int MAXM = 512;            // members per chunk (rows may be empty)
 
 inline int grid_for(int64_t n, int64_t cap = 16384) {
   int64_t g = ceil_div(n, TPB);
@@ -39,10 +40,12 @@ __global__ void k_nonempty(const int32_t* __restrict__ sz, int32_t n, int32_t* f
 
 __global__ void k_member_pairs(const int32_t* __restrict__ C,
                                const int32_t* __restrict__ rank, int32_t n,
-                               uint64_t* keys, uint32_t* vals) {
+                               uint64_t* keys, uint32_t* vals, int32_t* rc) {
   GRID_STRIDE(x, n) {
-    keys[x] = uint64_t(uint32_t(rank[C[x]]));
+    const int32_t r = rank[C[x]];
+    keys[x] = uint64_t(uint32_t(r));
     vals[x] = uint32_t(x);
+    rc[x] = r;
   }
 }
 
@@ -76,7 +79,7 @@ __global__ void k_chunk_heads(const uint64_t* __restrict__ rkey,
     int32_t r = int32_t(rkey[p]);
     int32_t ms = mstart[r];
     int32_t h;
-    if (p == ms || mdeg[p] > VCH || mdeg[p - 1] > VCH) {
+    if (p == ms || mdeg[p] > VCH || mdeg[p - 1] > VCH || (p - ms) % MAXM == 0) {
       h = 1;
     } else {
       int32_t vin = mvol[p] - mvol[ms];
@@ -87,74 +90,139 @@ __global__ void k_chunk_heads(const uint64_t* __restrict__ rkey,
   }
 }
 
-// One block per chunk of members of one community: entries are summed by
-// coarse neighbour in LDS, one slice of at most SLICE entries at a time (a
-// chunk is one slice unless it is a single member with a longer row), and
-// each slice's distinct sums are appended as partials.
+// One block per chunk of members of one community r.  Entries whose far end
+// is also in r (the diagonal of the coarse row, usually most of the volume)
+// are summed in registers; the rest go into an LDS hash table sized to the
+// chunk's volume.  A chunk is either one member whose row exceeds VCH
+// entries (walked in slices of SLICE entries) or up to MAXM members with
+// fewer than 2*VCH entries in total (one table fill; every thread takes
+// independent entries, finding its member in LDS-staged row starts).
+// The diagonal sum and the occupied slots are appended as partials.
+__device__ __forceinline__ void emit_partials(const int* keys, const int* vals, uint32_t cap,
+                                              uint64_t row, int32_t nc, long long diag,
+                                              uint64_t* pkey, uint32_t* pval, int32_t* pcount,
+                                              int* wc, int* bbase) {
+  const int wid = threadIdx.x / WAVE, lane = lane_id();
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  int n_mine = 0;
+  for (uint32_t s = threadIdx.x; s < cap; s += TPB) n_mine += keys[s] != EMPTY_KEY ? 1 : 0;
+  const int wsum = wave_sum(n_mine);
+  if (lane == 0) wc[wid] = wsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = diag != 0 ? 1 : 0;
+    for (int w = 0; w < TPB / WAVE; ++w) tot += wc[w];
+    const int b = atomicAdd(pcount, tot);
+    *bbase = b;
+    if (diag != 0) {
+      pkey[b] = row * uint64_t(nc) + row;
+      pval[b] = uint32_t(diag);
+    }
+  }
+  __syncthreads();
+  int pos = *bbase + (diag != 0 ? 1 : 0);
+  for (int w = 0; w < wid; ++w) pos += wc[w];
+  for (uint32_t s0 = 0; s0 < cap; s0 += TPB) {
+    const uint32_t s = s0 + threadIdx.x;
+    const bool occ = s < cap && keys[s] != EMPTY_KEY;
+    const uint64_t m = __ballot(occ);
+    if (occ) {
+      const int at = pos + __popcll(m & lt);
+      pkey[at] = row * uint64_t(nc) + uint64_t(keys[s]);
+      pval[at] = uint32_t(vals[s]);
+    }
+    pos += __popcll(m);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ long long block_sum(long long v, long long* red) {
+  v = wave_sum(v);
+  const int wid = threadIdx.x / WAVE;
+  if (lane_id() == 0) red[wid] = v;
+  __syncthreads();
+  long long t = 0;
+  for (int w = 0; w < TPB / WAVE; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
 __global__ void __launch_bounds__(TPB)
     k_coarse_partials(const int32_t* __restrict__ chunks, const uint64_t* __restrict__ rkey,
                       const uint32_t* __restrict__ members, const int32_t* __restrict__ mvol,
                       const int32_t* __restrict__ off, const int2* __restrict__ adj,
-                      const int32_t* __restrict__ C, const int32_t* __restrict__ rank,
-                      int32_t nc, uint64_t* pkey, uint32_t* pval, int32_t* pcount) {
+                      const int32_t* __restrict__ rc, int32_t nc, uint64_t* pkey,
+                      uint32_t* pval, int32_t* pcount) {
   __shared__ int keys[CHUNK_SLOTS];
   __shared__ int vals[CHUNK_SLOTS];
   __shared__ int wc[TPB / WAVE];
   __shared__ int bbase;
+  __shared__ long long red[TPB / WAVE];
+  __shared__ int lvol[MAXM + 1];
+  __shared__ int lrow[MAXM];
   const int32_t p0 = chunks[blockIdx.x], p1 = chunks[blockIdx.x + 1];
-  const uint64_t row = rkey[p0];
+  const int32_t r = int32_t(rkey[p0]);
   const int32_t v0 = mvol[p0], v1 = mvol[p1];
   const int wid = threadIdx.x / WAVE, lane = lane_id();
-  const uint64_t lt = (uint64_t(1) << lane) - 1;
-  for (int32_t s0 = v0; s0 < v1; s0 += SLICE) {
-    const int32_t s1 = s0 + SLICE < v1 ? s0 + SLICE : v1;
-    for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) {
-      keys[s] = EMPTY_KEY;
-      vals[s] = 0;
-    }
-    __syncthreads();
-    for (int32_t q = s0 + threadIdx.x; q < s1; q += TPB) {
-      // member p with mvol[p] <= q < mvol[p+1]
-      int32_t lo = p0, hi = p1 - 1;
-      while (lo < hi) {
-        int32_t mid = (lo + hi + 1) >> 1;
-        if (mvol[mid] <= q)
-          lo = mid;
+  if (p1 - p0 == 1 && v1 - v0 > VCH) {
+    // one long row, in slices
+    const uint32_t x = members[p0];
+    const int32_t rb = off[x];
+    for (int32_t s0 = 0; s0 < v1 - v0; s0 += SLICE) {
+      const int32_t s1 = s0 + SLICE < v1 - v0 ? s0 + SLICE : v1 - v0;
+      for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) {
+        keys[s] = EMPTY_KEY;
+        vals[s] = 0;
+      }
+      __syncthreads();
+      long long diag = 0;
+      for (int32_t q = s0 + threadIdx.x; q < s1; q += TPB) {
+        const int2 e = adj[rb + q];
+        const int Y = rc[e.x];
+        if (Y == r)
+          diag += e.y;
         else
-          hi = mid - 1;
+          table_add(keys, vals, CHUNK_SLOTS - 1, Y, e.y);
       }
-      const uint32_t x = members[lo];
-      int2 e = adj[off[x] + (q - mvol[lo])];
-      table_add(keys, vals, CHUNK_SLOTS - 1, rank[C[e.x]], e.y);
+      diag = block_sum(diag, red);
+      emit_partials(keys, vals, CHUNK_SLOTS, uint64_t(r), nc, diag, pkey, pval, pcount, wc,
+                    &bbase);
     }
-    __syncthreads();
-    // compact the occupied slots: per-wave ballots, one atomic per block
-    int n_mine = 0;
-    for (int s = threadIdx.x; s < CHUNK_SLOTS; s += TPB) n_mine += keys[s] != EMPTY_KEY ? 1 : 0;
-    int wsum = wave_sum(n_mine);
-    if (lane == 0) wc[wid] = wsum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int tot = 0;
-      for (int w = 0; w < TPB / WAVE; ++w) tot += wc[w];
-      bbase = atomicAdd(pcount, tot);
-    }
-    __syncthreads();
-    int pos = bbase;
-    for (int w = 0; w < wid; ++w) pos += wc[w];
-    for (int s0b = 0; s0b < CHUNK_SLOTS; s0b += TPB) {
-      const int s = s0b + threadIdx.x;
-      const bool occ = keys[s] != EMPTY_KEY;
-      const uint64_t m = __ballot(occ);
-      if (occ) {
-        const int at = pos + __popcll(m & lt);
-        pkey[at] = row * uint64_t(nc) + uint64_t(keys[s]);
-        pval[at] = uint32_t(vals[s]);
-      }
-      pos += __popcll(m);
-    }
-    __syncthreads();
+    return;
   }
+  // table sized to the chunk: at least twice its volume
+  const uint32_t want = 2u * uint32_t(v1 - v0 > 32 ? v1 - v0 : 32);
+  uint32_t cap = 1u << (32 - __clz(want - 1));
+  if (cap > CHUNK_SLOTS) cap = CHUNK_SLOTS;
+  for (uint32_t s = threadIdx.x; s < cap; s += TPB) {
+    keys[s] = EMPTY_KEY;
+    vals[s] = 0;
+  }
+  // member volumes and row starts staged in LDS: entry q of the chunk
+  // belongs to the last member m with lvol[m] <= q
+  const int nm = p1 - p0;
+  for (int m = threadIdx.x; m <= nm; m += TPB) lvol[m] = mvol[p0 + m] - v0;
+  for (int m = threadIdx.x; m < nm; m += TPB) lrow[m] = off[members[p0 + m]];
+  __syncthreads();
+  long long diag = 0;
+  for (int32_t q = threadIdx.x; q < v1 - v0; q += TPB) {
+    int lo = 0, hi = nm - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lvol[mid] <= q)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int2 e = adj[lrow[lo] + (q - lvol[lo])];
+    const int Y = rc[e.x];
+    if (Y == r)
+      diag += e.y;
+    else
+      table_add(keys, vals, cap - 1, Y, e.y);
+  }
+  diag = block_sum(diag, red);
+  emit_partials(keys, vals, cap, uint64_t(r), nc, diag, pkey, pval, pcount, wc, &bbase);
 }
 
 // Segment sums of sorted partials: the u-th distinct key spans positions
@@ -274,7 +342,9 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
   s.vals1.ensure(size_t(nl) * 4);
   uint64_t* rkey = s.keys0.as<uint64_t>();
   uint32_t* members = s.vals0.as<uint32_t>();
-  k_member_pairs<<<grid_for(nl), TPB, 0, st>>>(C, rank, nl, rkey, members);
+  s.rc.ensure(size_t(nl + 1) * 4);
+  int32_t* rc = s.rc.as<int32_t>();
+  k_member_pairs<<<grid_for(nl), TPB, 0, st>>>(C, rank, nl, rkey, members, rc);
   DC_LAUNCH_CHECK();
   radix_sort_pairs(rkey, members, s.keys1.as<uint64_t>(), s.vals1.as<uint32_t>(), nl,
                    ilog2_ceil(uint64_t(nc)), st);
@@ -328,8 +398,8 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
   int32_t* pcnt_dev = s.pcnt.as<int32_t>();
   fill_i32(pcnt_dev, 0, 1, st);
   if (nchunks > 0) {
-    k_coarse_partials<<<nchunks, TPB, 0, st>>>(chunks, rkey, members, mvol, g.off, g.adj, C, rank,
-                                               nc, pkey, pval, pcnt_dev);
+    k_coarse_partials<<<nchunks, TPB, 0, st>>>(chunks, rkey, members, mvol, g.off, g.adj, rc, nc,
+                                               pkey, pval, pcnt_dev);
     DC_LAUNCH_CHECK();
   }
   DC_HIP(hipMemcpyAsync(host, pcnt_dev, 4, hipMemcpyDeviceToHost, st));

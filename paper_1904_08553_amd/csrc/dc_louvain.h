@@ -120,7 +120,7 @@ void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n
 // ---- coarsen.hip ----
 struct CoarsenScratch {
   DBuf flag, rank, keys0, keys1, vals0, vals1, cntr, mstart, labof, mdeg, mvol, chead, cpos,
-      chunks, mcnt, pk0, pk1, pv0, pv1, ph, pp, pS, pcnt, hidx, ukey;
+      chunks, mcnt, pk0, pk1, pv0, pv1, ph, pp, pS, pcnt, hidx, ukey, rc;
   void* host = nullptr;  // pinned, 64 bytes
 };
 

@@ -273,41 +273,146 @@ __global__ void __launch_bounds__(TPB)
 }
 
 // Untouched rows move as a block: entry e of row r goes to
-// e + off_new[r] - off_old[r].  Each wave takes 256 consecutive entries,
-// finds the first row by a binary search and the row of every entry by a
-// short search inside the few rows the range spans; reads and writes stay
-// contiguous.
-constexpr int COPY_RANGE = 256;
-
+// e + off_new[r] - off_old[r].  A wave takes 64 consecutive rows: one
+// coalesced load brings each row's bounds, shift and changed-flag into a
+// lane, then the wave copies the rows one after another with contiguous
+// reads and writes.
 __global__ void __launch_bounds__(TPB)
     k_merge_copy(const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
-                 const int32_t* __restrict__ off_new, int2* adj_new, int32_t n, int64_t nnz_old,
+                 const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
                  const int32_t* __restrict__ cptr) {
-  const int64_t nranges = ceil_div(nnz_old, COPY_RANGE);
+  const int64_t nbatch = ceil_div(n, WAVE);
   const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
   const int lane = lane_id();
-  for (int64_t rg = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; rg < nranges;
-       rg += nwaves) {
-    const int64_t e0 = rg * COPY_RANGE;
-    const int64_t e1 = e0 + COPY_RANGE < nnz_old ? e0 + COPY_RANGE : nnz_old;
-    // r0 = last row with off_old[r] <= e0 (rows may be empty)
-    int32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-      int32_t mid = (lo + hi + 1) >> 1;
-      if (off_old[mid] <= e0) lo = mid; else hi = mid - 1;
+  for (int64_t bt = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; bt < nbatch;
+       bt += nwaves) {
+    const int64_t r = bt * WAVE + lane;
+    int beg = 0, end = 0, shift = 0, skip = 1;
+    if (r < n) {
+      beg = off_old[r];
+      end = off_old[r + 1];
+      shift = off_new[r] - beg;
+      skip = cptr[r] != cptr[r + 1];
     }
-    const int32_t r0 = lo;
-    for (int64_t e = e0 + lane; e < e1; e += WAVE) {
-      int32_t r = r0;
-      while (off_old[r + 1] <= e) ++r;
-      if (cptr[r] != cptr[r + 1]) continue;  // merged by k_merge_changed
-      adj_new[e + (off_new[r] - off_old[r])] = adj_old[e];
+    // rows to copy, in lane order
+    for (uint64_t todo = __ballot(!skip && end > beg); todo; todo &= todo - 1) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      const int b = __builtin_amdgcn_readlane(beg, l);
+      const int e = __builtin_amdgcn_readlane(end, l);
+      const int sh = __builtin_amdgcn_readlane(shift, l);
+      for (int q = b + lane; q < e; q += WAVE) adj_new[q + sh] = adj_old[q];
     }
   }
 }
 
-// Rows with changes: one wave per row merges the sorted old row with the
-// row's sorted change list.
+// Rows with changes: one wave per row.  For a row with few changes relative
+// to its length the changes (sorted by neighbour) sit one per lane, and the
+// number of deletions and insertions before a neighbour id comes from a
+// register loop instead of searches in memory; other rows use searches.
+// Long rows with many changes: every old entry and every insertion finds
+// its place by binary search (changes with a smaller neighbour id, counted
+// through the prefix sums of the DELETE / NEW flags).
+__device__ void merge_row_search(int32_t row, int32_t n, const int2* __restrict__ adj_old,
+                                 int32_t ob, int32_t oe, int32_t nb, int32_t cb, int32_t ce,
+                                 int2* adj_new, const uint64_t* __restrict__ ch_key,
+                                 const int32_t* __restrict__ ch_op,
+                                 const int32_t* __restrict__ ch_w,
+                                 const int32_t* __restrict__ cum_del,
+                                 const int32_t* __restrict__ cum_new) {
+  const int lane = lane_id();
+  const uint64_t base = uint64_t(row) * uint64_t(n);
+  const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
+  for (int32_t j = lane; j < oe - ob; j += WAVE) {
+    int2 e = adj_old[ob + j];
+    int32_t lo = cb, hi = ce;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (int32_t(ch_key[mid] - base) < e.x)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const int32_t shift = (cum_new[lo] - new0) - (cum_del[lo] - del0);
+    if (lo < ce && int32_t(ch_key[lo] - base) == e.x) {
+      const int32_t op = ch_op[lo];
+      if (op == OP_DELETE) continue;
+      if (op == OP_ADD) e.y += ch_w[lo];
+      if (op == OP_REPLACE) e.y = ch_w[lo];
+    }
+    adj_new[nb + j + shift] = e;
+  }
+  for (int32_t q = cb + lane; q < ce; q += WAVE) {
+    if (ch_op[q] != OP_NEW) continue;
+    const int32_t c = int32_t(ch_key[q] - base);
+    const int32_t pos = find_in_row(adj_old, ob, oe, c) - ob;
+    const int32_t shift = (cum_new[q] - new0) - (cum_del[q] - del0);
+    adj_new[nb + pos + shift] = make_int2(c, ch_w[q]);
+  }
+}
+
+constexpr int BIG_ROW = 1024;       // rows longer than this are merged by a block
+constexpr int BIG_CHANGES = 4096;   // changes staged in LDS per big row
+
+// Long changed rows: one block per row.  The row's change neighbours and the
+// cumulative shift before each change are staged in LDS, so every old entry
+// finds its place by a binary search on chip.
+__global__ void __launch_bounds__(TPB)
+    k_merge_big(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
+                const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
+                const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
+                const int32_t* __restrict__ cptr, const uint64_t* __restrict__ ch_key,
+                const int32_t* __restrict__ ch_op, const int32_t* __restrict__ ch_w,
+                const int32_t* __restrict__ cum_del, const int32_t* __restrict__ cum_new) {
+  __shared__ int ldst[BIG_CHANGES];
+  __shared__ int lsh[BIG_CHANGES + 1];
+  const int64_t nrows = *nrows_dev;
+  for (int64_t p = blockIdx.x; p < nrows; p += gridDim.x) {
+    const int32_t row = rows[p];
+    const int32_t ob = off_old[row], oe = off_old[row + 1];
+    if (oe - ob <= BIG_ROW) continue;  // uniform over the block
+    const int32_t nb = off_new[row], cb = cptr[row], ce = cptr[row + 1];
+    const int32_t nchg = ce - cb;
+    if (nchg > BIG_CHANGES) {
+      if (threadIdx.x < WAVE)
+        merge_row_search(row, n, adj_old, ob, oe, nb, cb, ce, adj_new, ch_key, ch_op, ch_w,
+                         cum_del, cum_new);
+      __syncthreads();
+      continue;
+    }
+    const uint64_t base = uint64_t(row) * uint64_t(n);
+    const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
+    for (int k = threadIdx.x; k <= nchg; k += TPB) {
+      if (k < nchg) ldst[k] = int32_t(ch_key[cb + k] - base);
+      lsh[k] = (cum_new[cb + k] - new0) - (cum_del[cb + k] - del0);
+    }
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < oe - ob; j += TPB) {
+      int2 e = adj_old[ob + j];
+      int lo = 0, hi = nchg;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ldst[mid] < e.x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < nchg && ldst[lo] == e.x) {
+        const int32_t op = ch_op[cb + lo];
+        if (op == OP_DELETE) continue;
+        if (op == OP_ADD) e.y += ch_w[cb + lo];
+        if (op == OP_REPLACE) e.y = ch_w[cb + lo];
+      }
+      adj_new[nb + j + lsh[lo]] = e;
+    }
+    for (int k = threadIdx.x; k < nchg; k += TPB) {
+      if (ch_op[cb + k] != OP_NEW) continue;
+      const int32_t pos = find_in_row(adj_old, ob, oe, ldst[k]) - ob;
+      adj_new[nb + pos + lsh[k]] = make_int2(ldst[k], ch_w[cb + k]);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_merge_changed(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
                                 const int32_t* __restrict__ off_old,
                                 const int2* __restrict__ adj_old,
@@ -326,34 +431,68 @@ __global__ void k_merge_changed(const int32_t* __restrict__ rows, const int32_t*
     const int32_t row = rows[p];
     const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
     const int32_t cb = cptr[row], ce = cptr[row + 1];
-    const uint64_t base = uint64_t(row) * uint64_t(n);
-    const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
-    for (int32_t j = lane; j < oe - ob; j += WAVE) {
-      int2 e = adj_old[ob + j];
-      // first change q in [cb, ce) with dst >= e.x
-      int32_t lo = cb, hi = ce;
-      while (lo < hi) {
-        int32_t mid = (lo + hi) >> 1;
-        if (int32_t(ch_key[mid] - base) < e.x)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      int32_t shift = (cum_new[lo] - new0) - (cum_del[lo] - del0);
-      if (lo < ce && int32_t(ch_key[lo] - base) == e.x) {
-        int32_t op = ch_op[lo];
-        if (op == OP_DELETE) continue;
-        if (op == OP_ADD) e.y += ch_w[lo];
-        if (op == OP_REPLACE) e.y = ch_w[lo];
-      }
-      adj_new[nb + j + shift] = e;
+    if (oe - ob > BIG_ROW) continue;  // k_merge_big
+    if (int64_t(ce - cb) * ceil_div(oe - ob + 1, WAVE) > WAVE) {
+      merge_row_search(row, n, adj_old, ob, oe, nb, cb, ce, adj_new, ch_key, ch_op, ch_w,
+                       cum_del, cum_new);
+      continue;
     }
-    for (int32_t q = cb + lane; q < ce; q += WAVE) {
-      if (ch_op[q] != OP_NEW) continue;
-      int32_t c = int32_t(ch_key[q] - base);
-      int32_t pos = find_in_row(adj_old, ob, oe, c) - ob;
-      int32_t shift = (cum_new[q] - new0) - (cum_del[q] - del0);
-      adj_new[nb + pos + shift] = make_int2(c, ch_w[q]);
+    const uint64_t base = uint64_t(row) * uint64_t(n);
+    // old entries: final position = nb + j - (#DELETE with dst < col) + (#NEW with dst < col)
+    for (int32_t j0 = 0; j0 < oe - ob; j0 += WAVE) {
+      const int32_t j = j0 + lane;
+      const bool live = j < oe - ob;
+      int2 e = live ? adj_old[ob + j] : make_int2(0x7fffffff, 0);
+      int shift = 0;
+      bool drop = false;
+      for (int32_t w0 = cb; w0 < ce; w0 += WAVE) {
+        const int32_t q = w0 + lane;
+        const bool hq = q < ce;
+        const int dst = hq ? int32_t(ch_key[q] - base) : 0x7fffffff;
+        const int op = hq ? ch_op[q] : 0;
+        const int cw = hq ? ch_w[q] : 0;
+        const int nw = ce - w0 < WAVE ? ce - w0 : WAVE;
+        for (int k = 0; k < nw; ++k) {
+          const int dk = __builtin_amdgcn_readlane(dst, k);
+          const int ok = __builtin_amdgcn_readlane(op, k);
+          if (dk < e.x) {
+            shift += ok == OP_NEW ? 1 : (ok == OP_DELETE ? -1 : 0);
+          } else if (dk == e.x) {
+            const int wk = __builtin_amdgcn_readlane(cw, k);
+            if (ok == OP_DELETE) drop = true;
+            if (ok == OP_ADD) e.y += wk;
+            if (ok == OP_REPLACE) e.y = wk;
+          }
+        }
+      }
+      if (live && !drop) adj_new[nb + j + shift] = e;
+    }
+    // new entries: position = nb + (#old with col < dst) - (#DELETE before) + (#NEW before)
+    for (int32_t w0 = cb; w0 < ce; w0 += WAVE) {
+      const int32_t q = w0 + lane;
+      const bool hq = q < ce && ch_op[q] == OP_NEW;
+      const int dst = q < ce ? int32_t(ch_key[q] - base) : 0x7fffffff;
+      const int nw0 = ce - w0 < WAVE ? ce - w0 : WAVE;
+      int pos = 0;
+      for (int32_t j0 = 0; j0 < oe - ob; j0 += WAVE) {
+        const int col = j0 + lane < oe - ob ? adj_old[ob + j0 + lane].x : 0x7fffffff;
+        for (int k = 0; k < nw0; ++k) {
+          const int c = __popcll(__ballot(col < __builtin_amdgcn_readlane(dst, k)));
+          if (lane == k) pos += c;
+        }
+      }
+      for (int32_t v0 = cb; v0 < ce; v0 += WAVE) {
+        const int32_t qq = v0 + lane;
+        const int d2 = qq < ce ? int32_t(ch_key[qq] - base) : 0x7fffffff;
+        const int o2 = qq < ce ? ch_op[qq] : 0;
+        const int nw = ce - v0 < WAVE ? ce - v0 : WAVE;
+        for (int k = 0; k < nw; ++k) {
+          const int dk = __builtin_amdgcn_readlane(d2, k);
+          const int ok = __builtin_amdgcn_readlane(o2, k);
+          if (dk < dst) pos += ok == OP_NEW ? 1 : (ok == OP_DELETE ? -1 : 0);
+        }
+      }
+      if (hq) adj_new[nb + pos] = make_int2(dst, ch_w[q]);
     }
   }
 }
@@ -519,14 +658,17 @@ void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
                 const int32_t* cum_del, const int32_t* cum_new, hipStream_t st) {
   if (n <= 0) return;
   if (nnz_old > 0) {
-    k_merge_copy<<<grid_for(ceil_div(nnz_old, COPY_RANGE) * WAVE, TPB, 16384), TPB, 0, st>>>(
-        off_old, adj_old, off_new, adj_new, n, nnz_old, cptr);
+    k_merge_copy<<<grid_for(ceil_div(n, WAVE) * WAVE, TPB, 16384), TPB, 0, st>>>(
+        off_old, adj_old, off_new, adj_new, n, cptr);
     DC_LAUNCH_CHECK();
   }
   if (nrows_max > 0) {
     k_merge_changed<<<grid_for(nrows_max * WAVE, TPB, 16384), TPB, 0, st>>>(
         rows, nrows_dev, off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w,
         cum_del, cum_new);
+    DC_LAUNCH_CHECK();
+    k_merge_big<<<2048, TPB, 0, st>>>(rows, nrows_dev, off_old, adj_old, off_new, adj_new, n,
+                                      cptr, ch_key, ch_op, ch_w, cum_del, cum_new);
     DC_LAUNCH_CHECK();
   }
 }
