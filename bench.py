@@ -27,6 +27,21 @@ if ROOT not in sys.path:
 
 METRIC = "edge updates/sec at matched modularity (ΔS vs full); p50/p99 per-batch latency"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC = os.path.join(ROOT, "profiles", "k_eval_group32_dcsbm_1M_20M_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the counter passes
+    recorded in profiles/, or None once the kernel source has changed."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def log(msg):
@@ -112,6 +127,9 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-recompute replay")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="also run three plain device-to-device copies of BYTES bytes (a "
+                         "reference kernel of known traffic for hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -125,6 +143,14 @@ def main():
     from paper_1904_08553_amd import dc, workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        src = torch.empty(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration: 3 device copies of {args.calibrate_copy} bytes")
+        del src, dst
     t0 = time.perf_counter()
     gen = W.DCSBM(n=args.n, m=args.m, blocks=args.blocks, seed=args.seed)
     graph, it = gen.stream(args.warmup + args.steps, frac=0.01, ins_frac=0.6)
@@ -192,9 +218,10 @@ def main():
     if d["k_launch"] > 0 and d["k_ms"] > 0:
         ach = d["k_bytes"] / (d["k_ms"] * 1e-3) / 1e9
         out["roofline"] = {
-            "kernel": "k_eval_wave<0> (one wave per active vertex, rows <= 128 entries)",
+            "kernel": "k_eval_group<0, 32> (level-0/1+ sweeps, rows of 17-32 entries, "
+                      "two vertices per wave)",
             "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "launches": d["k_launch"], "avg_launch_us": d["k_ms"] * 1e3 / d["k_launch"],
             "bytes_per_launch": d["k_bytes"] / d["k_launch"],
         }

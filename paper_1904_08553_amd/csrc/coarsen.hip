@@ -163,7 +163,6 @@ __global__ void __launch_bounds__(TPB)
   const int32_t p0 = chunks[blockIdx.x], p1 = chunks[blockIdx.x + 1];
   const int32_t r = int32_t(rkey[p0]);
   const int32_t v0 = mvol[p0], v1 = mvol[p1];
-  const int wid = threadIdx.x / WAVE, lane = lane_id();
   if (p1 - p0 == 1 && v1 - v0 > VCH) {
     // one long row, in slices
     const uint32_t x = members[p0];
