@@ -16,7 +16,8 @@
  *   Sec. 3.1 gain, Appendix A algebra ........ score / csr_gain
  *   Sec. 3.2 Louvain move rule ............... decide
  *   Sec. 3.2 Alg. 1 (sweeps, compaction) ..... level_sweeps, coarsen, run_levels
- *   Sec. 3.4 incremental procedure ........... orc_apply_batch
+ *   Sec. 3.4 incremental procedure ........... orc_stage_batch / orc_finish_batch
+ *   learned screener samples (extension) ..... collect_samples, features_of
  *   Sec. 3.5 Alg. 2 (Delta-screening) ........ screen_additions
  *   deletions (paper: future work, Sec. 5) ... screen_deletions
  */
@@ -444,6 +445,17 @@ struct orc_state {
   int64_t two_m;
   int32_t* C; /* canonical labels of the current partition */
   orc_options opt;
+  /* a staged batch: G_t, the screened (or full) active set, counters */
+  int staged;
+  csr_t g;
+  uint8_t* R;
+  orc_step_info sinfo;
+  /* screener samples of the last staged batch */
+  int64_t ns;
+  int32_t* s_ids;
+  double* s_X;
+  int64_t* s_raw;
+  uint8_t* s_y;
 };
 
 static int64_t row_find(const row_t* r, int32_t v) {
@@ -535,7 +547,8 @@ void orc_default_options(orc_options* o) {
 static int options_ok(const orc_options* o) {
   return o && o->max_levels >= 1 && o->max_sweeps >= 1 &&
          (o->mode == ORC_MODE_DELTA || o->mode == ORC_MODE_ALL ||
-          o->mode == ORC_MODE_STATIC) &&
+          o->mode == ORC_MODE_STATIC || o->mode == ORC_MODE_LEARNED) &&
+         (o->collect == 0 || o->collect == 1) &&
          (o->del_rule == ORC_DEL_GAIN || o->del_rule == ORC_DEL_CONSERVATIVE) &&
          o->tau_den >= 0;
 }
@@ -780,19 +793,169 @@ static void screen_deletions(const csr_t* g, const int32_t* C,
   free(src);
 }
 
-int32_t orc_apply_batch(orc_state* s, int64_t na, const int32_t* au,
+/* ------------------------------------------------------------------------ */
+/* Screener samples (the learned screener; an extension, not in the paper).  */
+
+static void free_samples(orc_state* s) {
+  free(s->s_ids);
+  free(s->s_X);
+  free(s->s_raw);
+  free(s->s_y);
+  s->s_ids = NULL;
+  s->s_X = NULL;
+  s->s_raw = NULL;
+  s->s_y = NULL;
+  s->ns = 0;
+}
+
+/* The eight features of one vertex from its exact integer quantities; every
+ * feature is one correctly rounded fp64 operation on exact integers. */
+static void features_of(const int64_t* raw, int64_t two_m, double* x) {
+  int64_t k = raw[0], kp = raw[1], t = raw[2];
+  int64_t mx = k > kp ? k : kp;
+  x[0] = (double)k / ((double)k + 16.0);
+  x[1] = mx > 0 ? (double)(k - kp) / (double)mx : 0.0;
+  x[2] = (double)t / ((double)t + 4.0);
+  x[3] = k > 0 ? (double)raw[3] / (double)k : 0.0;
+  x[4] = (k > 0 && raw[4] != ORC_NO_GAIN) ? (double)raw[4] / (double)(two_m * k) : -3.0;
+  x[5] = (k > 0 && raw[5] != ORC_NO_GAIN) ? (double)raw[5] / (double)(two_m * k) : -3.0;
+  x[6] = (double)raw[7];
+  x[7] = two_m > 0 ? (double)raw[6] / (double)two_m : 0.0;
+}
+
+/* Records the samples of the staged batch.  src[v]: v is an endpoint of a
+ * changed pair; touch[v]: number of changed pairs at v; kprev: degrees in
+ * G_{t-1}; Rds: the Delta-screened set (0/1). */
+static int collect_samples(orc_state* s, const csr_t* g, const int64_t* k,
+                           const int64_t* kprev, const int64_t* a,
+                           const int64_t* touch, const uint8_t* src,
+                           const uint8_t* Rds, agg_t* ag) {
+  int32_t n = s->n;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  const int32_t* C = s->C;
+  int64_t two_m = s->two_m;
+  free_samples(s);
+  uint8_t* T = (uint8_t*)calloc(nn, 1);
+  int32_t* Cl = (int32_t*)malloc(sizeof(int32_t) * nn);
+  uint8_t* all = (uint8_t*)malloc(nn);
+  if (!T || !Cl || !all) {
+    free(T);
+    free(Cl);
+    free(all);
+    return 0;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    if (Rds[v]) T[v] = 1;
+    if (!src[v]) continue;
+    T[v] = 1;
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; ++e) T[g->col[e]] = 1;
+  }
+  int64_t cnt = 0;
+  for (int32_t v = 0; v < n; ++v) cnt += T[v];
+  size_t cc = (size_t)(cnt > 0 ? cnt : 1);
+  s->s_ids = (int32_t*)malloc(sizeof(int32_t) * cc);
+  s->s_X = (double*)malloc(sizeof(double) * ORC_FEATURES * cc);
+  s->s_raw = (int64_t*)malloc(sizeof(int64_t) * ORC_FEATURES * cc);
+  s->s_y = (uint8_t*)malloc(cc);
+  if (!s->s_ids || !s->s_X || !s->s_raw || !s->s_y) {
+    free(T);
+    free(Cl);
+    free(all);
+    free_samples(s);
+    return 0;
+  }
+  /* move labels: level 0 rerun from C_{t-1} with every vertex active */
+  memcpy(Cl, C, sizeof(int32_t) * nn);
+  memset(all, 1, nn);
+  int64_t Tthr = s->opt.tau_den > 0 ? (two_m * two_m) / s->opt.tau_den : 0;
+  int oom = 0;
+  (void)level_sweeps(g, two_m, Tthr, Cl, all, &s->opt, 0, NULL, &oom);
+  if (oom) {
+    free(T);
+    free(Cl);
+    free(all);
+    free_samples(s);
+    return 0;
+  }
+  int64_t q = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!T[i]) continue;
+    int64_t* raw = s->s_raw + ORC_FEATURES * q;
+    int32_t c = C[i];
+    aggregate(g, C, i, ag);
+    int64_t e_own = ag->seen[c] ? ag->acc[c] : 0;
+    int64_t s_own = score(two_m, e_own, k[i], a[c], 1);
+    /* best and second-best other communities: score desc, label asc */
+    int32_t b1 = -1, b2 = -1;
+    int64_t s1 = 0, s2 = 0;
+    for (int32_t t = 0; t < ag->nt; ++t) {
+      int32_t X = ag->touched[t];
+      if (X == c) continue;
+      int64_t sc = score(two_m, ag->acc[X], k[i], a[X], 0);
+      if (b1 < 0 || sc > s1 || (sc == s1 && X < b1)) {
+        b2 = b1;
+        s2 = s1;
+        b1 = X;
+        s1 = sc;
+      } else if (b2 < 0 || sc > s2 || (sc == s2 && X < b2)) {
+        b2 = X;
+        s2 = sc;
+      }
+    }
+    agg_clear(ag);
+    raw[0] = k[i];
+    raw[1] = kprev[i];
+    raw[2] = touch[i];
+    raw[3] = e_own;
+    raw[4] = b1 >= 0 ? s1 - s_own : ORC_NO_GAIN;
+    raw[5] = b2 >= 0 ? s2 - s_own : ORC_NO_GAIN;
+    raw[6] = a[c];
+    raw[7] = Rds[i] ? 1 : 0;
+    features_of(raw, two_m, s->s_X + ORC_FEATURES * q);
+    s->s_ids[q] = i;
+    s->s_y[q] = Cl[i] != c ? 1 : 0;
+    ++q;
+  }
+  s->ns = cnt;
+  free(T);
+  free(Cl);
+  free(all);
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One time step (Sec. 3.4): stage (validate, update, screen), then finish   */
+/* (levels over the active set, canonical labels).                           */
+
+static void drop_stage(orc_state* s) {
+  if (!s->staged) return;
+  csr_free(&s->g);
+  free(s->R);
+  s->R = NULL;
+  s->staged = 0;
+}
+
+int32_t orc_stage_batch(orc_state* s, int64_t na, const int32_t* au,
                         const int32_t* av, const int32_t* aw, int64_t nd,
-                        const int32_t* du, const int32_t* dv, int32_t* C_out,
-                        uint8_t* R_out, orc_sweep_rec* sweeps, int32_t cap,
-                        orc_step_info* info) {
-  if (!s || na < 0 || nd < 0 || (na > 0 && (!au || !av || !aw)) ||
+                        const int32_t* du, const int32_t* dv) {
+  if (!s || s->staged || na < 0 || nd < 0 || (na > 0 && (!au || !av || !aw)) ||
       (nd > 0 && (!du || !dv)))
     return ORC_E_ARG;
   int64_t two_m_new = 0;
   int32_t st = validate_batch(s, na, au, av, aw, nd, du, dv, &two_m_new);
   if (st != ORC_OK) return st;
   int32_t n = s->n;
-  size_t nn = (size_t)n;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  int mode = s->opt.mode;
+  int collect = s->opt.collect || mode == ORC_MODE_LEARNED;
+  int screen = mode == ORC_MODE_DELTA || mode == ORC_MODE_LEARNED || collect;
+  int64_t* kprev = (int64_t*)malloc(sizeof(int64_t) * nn);
+  if (!kprev) return ORC_E_OOM;
+  for (int32_t v = 0; v < n; ++v) {
+    int64_t t = 0;
+    for (int32_t q = 0; q < s->rows[v].deg; ++q) t += s->rows[v].w[q];
+    kprev[v] = t;
+  }
   /* deletions first, then insertions (weights add; duplicates sum) */
   for (int64_t e = 0; e < nd; ++e) {
     row_remove(&s->rows[du[e]], dv[e]);
@@ -800,67 +963,128 @@ int32_t orc_apply_batch(orc_state* s, int64_t na, const int32_t* au,
   }
   for (int64_t e = 0; e < na; ++e) {
     if (!row_add(&s->rows[au[e]], av[e], aw[e]) ||
-        !row_add(&s->rows[av[e]], au[e], aw[e]))
+        !row_add(&s->rows[av[e]], au[e], aw[e])) {
+      free(kprev);
       return ORC_E_OOM;
+    }
   }
   s->two_m = two_m_new;
 
-  csr_t g;
-  memset(&g, 0, sizeof(g));
-  if (!snapshot(s, &g)) return ORC_E_OOM;
-  uint8_t* R = (uint8_t*)calloc(nn, 1);
+  memset(&s->g, 0, sizeof(s->g));
+  memset(&s->sinfo, 0, sizeof(s->sinfo));
+  if (!snapshot(s, &s->g)) {
+    free(kprev);
+    return ORC_E_OOM;
+  }
+  s->R = (uint8_t*)calloc(nn, 1);
   uint8_t* cflag = (uint8_t*)calloc(nn, 1);
   int64_t* k = (int64_t*)malloc(sizeof(int64_t) * nn);
   int64_t* a = (int64_t*)malloc(sizeof(int64_t) * nn);
   int64_t* size = (int64_t*)malloc(sizeof(int64_t) * nn);
+  int64_t* touch = (int64_t*)calloc(nn, sizeof(int64_t));
+  uint8_t* src = (uint8_t*)calloc(nn, 1);
+  int64_t* pairs = (int64_t*)malloc(sizeof(int64_t) * (size_t)(na + nd + 1));
   agg_t ag;
   int have_ag = agg_alloc(&ag, n);
-  if (!R || !cflag || !k || !a || !size || !have_ag) {
-    free(R);
-    free(cflag);
-    free(k);
-    free(a);
-    free(size);
-    if (have_ag) agg_free(&ag);
-    csr_free(&g);
-    return ORC_E_OOM;
+  int ok = s->R && cflag && k && a && size && touch && src && pairs && have_ag;
+  if (ok) {
+    csr_degrees(&s->g, k);
+    totals(&s->g, s->C, k, a, size);
+    if (screen) {
+      screen_additions(&s->g, s->C, k, a, s->two_m, na, au, av, s->R, cflag,
+                       &ag, &s->sinfo);
+      screen_deletions(&s->g, s->C, k, a, size, s->two_m, nd, du, dv,
+                       s->opt.del_rule, s->R, cflag, &ag, &s->sinfo);
+      for (int32_t v = 0; v < n; ++v)
+        if (cflag[s->C[v]]) s->R[v] = 1;
+    }
+    if (collect) {
+      /* changed pairs (a pair deleted and re-added counts once) */
+      int64_t np = 0;
+      for (int64_t e = 0; e < nd; ++e) pairs[np++] = pair_key(du[e], dv[e]);
+      for (int64_t e = 0; e < na; ++e) pairs[np++] = pair_key(au[e], av[e]);
+      qsort(pairs, (size_t)np, sizeof(int64_t), cmp_i64);
+      for (int64_t p = 0; p < np; ++p) {
+        if (p > 0 && pairs[p] == pairs[p - 1]) continue;
+        int32_t x = (int32_t)(pairs[p] >> 32), y = (int32_t)(pairs[p] & 0xffffffff);
+        touch[x]++;
+        touch[y]++;
+        src[x] = 1;
+        src[y] = 1;
+      }
+      ok = collect_samples(s, &s->g, k, kprev, a, touch, src, s->R, &ag);
+    } else {
+      free_samples(s);
+    }
+    if (mode == ORC_MODE_ALL || mode == ORC_MODE_STATIC) memset(s->R, 1, nn);
   }
-  if (info) memset(info, 0, sizeof(*info));
-  if (s->opt.mode == ORC_MODE_DELTA) {
-    csr_degrees(&g, k);
-    totals(&g, s->C, k, a, size);
-    screen_additions(&g, s->C, k, a, s->two_m, na, au, av, R, cflag, &ag,
-                     info);
-    screen_deletions(&g, s->C, k, a, size, s->two_m, nd, du, dv,
-                     s->opt.del_rule, R, cflag, &ag, info);
-    for (int32_t v = 0; v < n; ++v)
-      if (cflag[s->C[v]]) R[v] = 1;
-  } else {
-    memset(R, 1, nn);
-    if (s->opt.mode == ORC_MODE_STATIC)
-      for (int32_t v = 0; v < n; ++v) s->C[v] = v;
-  }
-  int64_t Rsz = 0;
-  for (int32_t v = 0; v < n; ++v) Rsz += R[v];
-  if (R_out) memcpy(R_out, R, nn);
-  agg_free(&ag);
+  if (have_ag) agg_free(&ag);
   free(cflag);
   free(k);
   free(a);
   free(size);
+  free(touch);
+  free(src);
+  free(pairs);
+  free(kprev);
+  if (!ok) {
+    csr_free(&s->g);
+    free(s->R);
+    s->R = NULL;
+    return ORC_E_OOM;
+  }
+  s->staged = 1;
+  return ORC_OK;
+}
 
+int32_t orc_finish_batch(orc_state* s, const uint8_t* R_override,
+                         int32_t* C_out, uint8_t* R_out, orc_sweep_rec* sweeps,
+                         int32_t cap, orc_step_info* info) {
+  if (!s || !s->staged) return ORC_E_ARG;
+  int32_t n = s->n;
+  size_t nn = (size_t)n;
+  if (R_override)
+    for (int32_t v = 0; v < n; ++v) s->R[v] = R_override[v] ? 1 : 0;
+  if (s->opt.mode == ORC_MODE_STATIC)
+    for (int32_t v = 0; v < n; ++v) s->C[v] = v;
+  int64_t Rsz = 0;
+  for (int32_t v = 0; v < n; ++v) Rsz += s->R[v];
+  if (R_out) memcpy(R_out, s->R, nn);
   trace_t tr = {sweeps, cap, 0};
   int32_t levels = 0;
   int64_t N = 0;
-  int ok = run_levels(&g, s->C, R, &s->opt, &tr, &levels, &N);
-  free(R);
-  csr_free(&g);
+  int ok = run_levels(&s->g, s->C, s->R, &s->opt, &tr, &levels, &N);
+  orc_step_info si = s->sinfo;
+  drop_stage(s);
   if (!ok) return ORC_E_OOM;
   if (info) {
+    *info = si;
     info->R_size = Rsz;
     fill_info(info, &tr, levels, N, s->two_m);
   }
   if (C_out) memcpy(C_out, s->C, sizeof(int32_t) * nn);
+  return ORC_OK;
+}
+
+int32_t orc_apply_batch(orc_state* s, int64_t na, const int32_t* au,
+                        const int32_t* av, const int32_t* aw, int64_t nd,
+                        const int32_t* du, const int32_t* dv, int32_t* C_out,
+                        uint8_t* R_out, orc_sweep_rec* sweeps, int32_t cap,
+                        orc_step_info* info) {
+  int32_t st = orc_stage_batch(s, na, au, av, aw, nd, du, dv);
+  if (st != ORC_OK) return st;
+  return orc_finish_batch(s, NULL, C_out, R_out, sweeps, cap, info);
+}
+
+int32_t orc_last_samples(const orc_state* s, int64_t* count, int32_t* ids,
+                         double* X, int64_t* raw, uint8_t* y) {
+  if (!s) return ORC_E_ARG;
+  if (count) *count = s->ns;
+  if (s->ns == 0) return ORC_OK;
+  if (ids) memcpy(ids, s->s_ids, sizeof(int32_t) * (size_t)s->ns);
+  if (X) memcpy(X, s->s_X, sizeof(double) * ORC_FEATURES * (size_t)s->ns);
+  if (raw) memcpy(raw, s->s_raw, sizeof(int64_t) * ORC_FEATURES * (size_t)s->ns);
+  if (y) memcpy(y, s->s_y, (size_t)s->ns);
   return ORC_OK;
 }
 
@@ -929,6 +1153,8 @@ void orc_destroy(orc_state* s) {
     free(s->rows);
   }
   free(s->C);
+  drop_stage(s);
+  free_samples(s);
   free(s);
 }
 

@@ -46,7 +46,9 @@ enum {
   ORC_E_OOM = -8
 };
 
-enum { ORC_MODE_DELTA = 0, ORC_MODE_ALL = 1, ORC_MODE_STATIC = 2 };
+/* LEARNED screens like DELTA and always collects screener samples; the
+ * caller then passes the active set it chose to orc_finish_batch. */
+enum { ORC_MODE_DELTA = 0, ORC_MODE_ALL = 1, ORC_MODE_STATIC = 2, ORC_MODE_LEARNED = 3 };
 enum { ORC_DEL_GAIN = 0, ORC_DEL_CONSERVATIVE = 1 };
 
 typedef struct orc_options {
@@ -55,9 +57,28 @@ typedef struct orc_options {
   int32_t max_sweeps;      /* >= 1 */
   int32_t singleton_guard; /* 0/1 */
   int32_t del_rule;        /* ORC_DEL_* */
-  int32_t pad;
+  int32_t collect;         /* 1: record screener samples every batch */
   int64_t tau_den;         /* T = floor((2m)^2 / tau_den); 0 means T = 0 */
 } orc_options;
+
+/* Screener samples of one batch (the learned screener; not in the paper).
+ * Touched vertices: the endpoints of every changed pair, their neighbours in
+ * G_t and the Delta-screened set, in ascending id.  Per touched vertex i, on
+ * (G_t, C_{t-1}, totals on G_t):
+ *   raw[0] k_i (G_t)        raw[1] k_i in G_{t-1}   raw[2] changed pairs at i
+ *   raw[3] e_{i->C(i)}      raw[4] G(i->D1)         raw[5] G(i->D2)
+ *   raw[6] a_{C(i)}         raw[7] 1 if Delta-screening selected i
+ * where D1, D2 are the best and second-best neighbouring communities other
+ * than C(i) (score descending, then label ascending); ORC_NO_GAIN when absent.
+ * Features (fp64, each one correctly rounded division):
+ *   x0 = k/(k+16)                      x1 = (k-kprev)/max(k,kprev) (0 if both 0)
+ *   x2 = t/(t+4)                       x3 = e_own/k (0 if k = 0)
+ *   x4 = G1/(2m*k), -3 if absent       x5 = G2/(2m*k), -3 if absent
+ *   x6 = raw[7]                        x7 = a_{C(i)}/2m (0 if 2m = 0)
+ * Label: 1 if i ends level 0 in another community when level 0 is rerun
+ * from C_{t-1} with every vertex active (full re-evaluation). */
+#define ORC_FEATURES 8
+#define ORC_NO_GAIN INT64_MIN
 
 /* One record per executed sweep. */
 typedef struct orc_sweep_rec {
@@ -103,6 +124,23 @@ int32_t orc_apply_batch(orc_state* s, int64_t na, const int32_t* au,
                         const int32_t* du, const int32_t* dv, int32_t* C_out,
                         uint8_t* R_out, orc_sweep_rec* sweeps, int32_t cap,
                         orc_step_info* info);
+
+/* The same step in two halves.  stage validates, updates the graph, screens
+ * (DELTA, LEARNED, or any mode when collecting) and records samples; finish
+ * runs the levels over R_override when given (0/1 bytes over the vertices),
+ * else over the screened set (DELTA, LEARNED) or every vertex (ALL, STATIC).
+ * A second stage before finish, or finish without stage, is ORC_E_ARG. */
+int32_t orc_stage_batch(orc_state* s, int64_t na, const int32_t* au,
+                        const int32_t* av, const int32_t* aw, int64_t nd,
+                        const int32_t* du, const int32_t* dv);
+int32_t orc_finish_batch(orc_state* s, const uint8_t* R_override,
+                         int32_t* C_out, uint8_t* R_out, orc_sweep_rec* sweeps,
+                         int32_t cap, orc_step_info* info);
+
+/* Samples of the last staged batch (count 0 when not collected).  Any output
+ * may be NULL; X holds count*8 doubles, raw count*8 int64, y count bytes. */
+int32_t orc_last_samples(const orc_state* s, int64_t* count, int32_t* ids,
+                         double* X, int64_t* raw, uint8_t* y);
 
 int32_t orc_modularity(const orc_state* s, int64_t* N, int64_t* two_m,
                        double* q);

@@ -17,7 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "dc_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-MODE_DELTA, MODE_ALL, MODE_STATIC = 0, 1, 2
+MODE_DELTA, MODE_ALL, MODE_STATIC, MODE_LEARNED = 0, 1, 2, 3
+FEATURES = 8
+NO_GAIN = -(1 << 63)
 DEL_GAIN, DEL_CONSERVATIVE = 0, 1
 
 STATUS_NAMES = {
@@ -43,7 +45,7 @@ class Options(ct.Structure):
     _fields_ = [
         ("mode", ct.c_int32), ("max_levels", ct.c_int32),
         ("max_sweeps", ct.c_int32), ("singleton_guard", ct.c_int32),
-        ("del_rule", ct.c_int32), ("pad", ct.c_int32), ("tau_den", ct.c_int64),
+        ("del_rule", ct.c_int32), ("collect", ct.c_int32), ("tau_den", ct.c_int64),
     ]
 
 
@@ -82,6 +84,12 @@ def lib():
         L.orc_init.restype = i32
         L.orc_apply_batch.argtypes = [P, i64, P, P, P, i64, P, P, P, P, P, i32, P]
         L.orc_apply_batch.restype = i32
+        L.orc_stage_batch.argtypes = [P, i64, P, P, P, i64, P, P]
+        L.orc_stage_batch.restype = i32
+        L.orc_finish_batch.argtypes = [P, P, P, P, P, i32, P]
+        L.orc_finish_batch.restype = i32
+        L.orc_last_samples.argtypes = [P, P, P, P, P, P]
+        L.orc_last_samples.restype = i32
         L.orc_modularity.argtypes = [P, P, P, P]
         L.orc_modularity.restype = i32
         L.orc_communities.argtypes = [P, P]
@@ -110,10 +118,11 @@ def _p(a):
 
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
-            del_rule=DEL_GAIN, tau_den=1000000) -> Options:
+            del_rule=DEL_GAIN, tau_den=1000000, collect=0) -> Options:
     o = Options()
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.tau_den = singleton_guard, del_rule, tau_den
+    o.collect = collect
     return o
 
 
@@ -169,6 +178,43 @@ class Oracle:
         self.C, self.R, self.info = C, R, info
         self.trace = _trace(recs, info.n_sweeps, self.TRACE_CAP)
         return C
+
+    def stage_batch(self, add_u=(), add_v=(), add_w=(), del_u=(), del_v=()):
+        """First half of a step: validate, update G_t, screen, collect samples."""
+        au, av, aw = _i32(add_u), _i32(add_v), _i32(add_w)
+        du, dv = _i32(del_u), _i32(del_v)
+        st = lib().orc_stage_batch(self._h, len(au), _p(au), _p(av), _p(aw),
+                                   len(du), _p(du), _p(dv))
+        if st != 0:
+            raise OracleError(st)
+
+    def finish_batch(self, R=None):
+        """Second half: levels over R (0/1 per vertex) or the staged set."""
+        Ro = None if R is None else np.ascontiguousarray(R, np.uint8)
+        C = np.empty(self.n, np.int32)
+        Rout = np.empty(self.n, np.uint8)
+        recs = (SweepRec * self.TRACE_CAP)()
+        info = StepInfo()
+        st = lib().orc_finish_batch(self._h, _p(Ro), _p(C), _p(Rout), recs, self.TRACE_CAP,
+                                    ct.byref(info))
+        if st != 0:
+            raise OracleError(st)
+        self.C, self.R, self.info = C, Rout, info
+        self.trace = _trace(recs, info.n_sweeps, self.TRACE_CAP)
+        return C
+
+    def samples(self):
+        """Screener samples of the last staged batch: ids (int32, ascending),
+        X (fp64 [count, 8]), raw (int64 [count, 8]), y (uint8)."""
+        cnt = ct.c_int64()
+        lib().orc_last_samples(self._h, ct.byref(cnt), None, None, None, None)
+        c = cnt.value
+        ids = np.empty(max(c, 1), np.int32)
+        X = np.empty((max(c, 1), FEATURES), np.float64)
+        raw = np.empty((max(c, 1), FEATURES), np.int64)
+        y = np.empty(max(c, 1), np.uint8)
+        lib().orc_last_samples(self._h, ct.byref(cnt), _p(ids), _p(X), _p(raw), _p(y))
+        return dict(ids=ids[:c], X=X[:c], raw=raw[:c], y=y[:c])
 
     def modularity(self):
         N, tm, q = ct.c_int64(), ct.c_int64(), ct.c_double()

@@ -29,10 +29,29 @@ MUTANTS = {
                           "    if (0) {\n      if (info) info->del_accepted++;"),
 }
 
+# mistakes in the screener-sample code, caught by its own pins
+SCREENER = "test_oracle_screener.py"
+MUTANTS.update({
+    "replaced pair counted twice": ("        if (p > 0 && pairs[p] == pairs[p - 1]) continue;\n", "", SCREENER),
+    "labels from the screened set only": ("level_sweeps(g, two_m, Tthr, Cl, all,",
+                                          "level_sweeps(g, two_m, Tthr, Cl, Rds,", SCREENER),
+    "touched set misses neighbours": (
+        "    T[v] = 1;\n    for (int64_t e = g->off[v]; e < g->off[v + 1]; ++e) T[g->col[e]] = 1;",
+        "    T[v] = 1;", SCREENER),
+    "degree feature scale": ("x[0] = (double)k / ((double)k + 16.0);",
+                             "x[0] = (double)k / ((double)k + 8.0);", SCREENER),
+    "gain feature not scaled by k": (
+        "x[4] = (k > 0 && raw[4] != ORC_NO_GAIN) ? (double)raw[4] / (double)(two_m * k) : -3.0;",
+        "x[4] = (k > 0 && raw[4] != ORC_NO_GAIN) ? (double)raw[4] / (double)two_m : -3.0;", SCREENER),
+    "second best keeps the own community": ("      if (X == c) continue;\n      int64_t sc = score(two_m, ag->acc[X], k[i], a[X], 0);",
+                                            "      int64_t sc = score(two_m, ag->acc[X], k[i], a[X], 0);", SCREENER),
+})
+
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_reject_planted_mistake(name, tmp_path):
-    old, new = MUTANTS[name]
+    old, new, *target = MUTANTS[name]
+    target = target[0] if target else "test_oracle_pins.py"
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name!r} not unique"
     mut = tmp_path / "mut.c"
@@ -42,6 +61,6 @@ def test_pins_reject_planted_mistake(name, tmp_path):
                     "-o", str(so), str(mut)], check=True)
     env = dict(os.environ, DC_ORACLE_LIB=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", target)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch mutant {name!r}:\n{r.stdout[-2000:]}"
