@@ -58,7 +58,11 @@ enum {
   DC_MODE_DELTA = 0,  /* inherit C_{t-1}; level 0 visits R_t from Alg. 2 */
   DC_MODE_ALL = 1,    /* inherit C_{t-1}; level 0 visits every vertex (the
                          baseline of Sec. 3.4 with R_t = V_t)            */
-  DC_MODE_STATIC = 2  /* restart from singletons (naive rerun, Sec. 3.3)  */
+  DC_MODE_STATIC = 2, /* restart from singletons (naive rerun, Sec. 3.3)  */
+  DC_MODE_LEARNED = 3 /* inherit C_{t-1}; level 0 visits the touched
+                         vertices whose screener logit is >= theta (see
+                         dc_screener_set); plain Alg. 2 while no screener
+                         is set                                          */
 };
 
 /* Deletions are outside the paper (Sec. 5 lists them as future work). */
@@ -83,7 +87,12 @@ typedef struct dc_options {
                               threshold tau of Sec. 3.2); 0 = threshold 0;
                               default 10^6                                 */
   void* stream;            /* hipStream_t for all work; NULL = default       */
-  int64_t reserved[4];     /* must be zero                                   */
+  int32_t collect;         /* 1: every dc_apply_batch also records screener
+                              samples (dc_last_samples): features of the
+                              touched vertices and their move labels under a
+                              full re-evaluation of level 0; default 0      */
+  int32_t pad;             /* must be zero                                   */
+  int64_t reserved[3];     /* must be zero                                   */
 } dc_options;
 
 /* An edge list: count entries (u[e], v[e], w[e]).  w is ignored (may be
@@ -126,8 +135,9 @@ typedef struct dc_step_stats {
   int64_t two_m;          /* 2m of G_t                                      */
   double q;               /* N / (2m)^2                                     */
   double ms_total;        /* host wall time of the call                     */
-  double ms_sweep_kernel; /* device time of the one-wave-per-vertex sweep
-                             kernel (rows up to 128 entries), timing=1      */
+  double ms_sweep_kernel; /* device time of the sweep kernel for rows of 17
+                             to 32 entries (two vertices per wave), summed
+                             over its launches; timing = 1 only            */
   int64_t sweep_launches; /* launches of that kernel timed                  */
   int64_t sweep_bytes;    /* their algorithmic bytes: 12 per adjacency entry
                              and 32 per evaluated vertex                    */
@@ -135,7 +145,10 @@ typedef struct dc_step_stats {
   int64_t level0_active;  /* active vertices summed over level-0 sweeps     */
   int64_t level0_volume;  /* adjacency entries of active vertices, summed
                              over level-0 sweeps                            */
-  int64_t reserved[4];
+  int64_t touched;        /* touched vertices of the batch (LEARNED mode or
+                             collect = 1), else 0                          */
+  int64_t screened;       /* 1 when the screener network chose R_t         */
+  int64_t reserved[2];
 } dc_step_stats;
 
 typedef struct dc_ctx dc_ctx;
@@ -191,6 +204,73 @@ dc_status dc_num_entries(dc_ctx* ctx, int64_t* nnz);
 dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w);
 
 void dc_destroy(dc_ctx* ctx);
+
+/* ---- Learned screener (an extension; the paper has no learned part) ----
+ *
+ * A vertex is touched by a batch when it is an endpoint of a changed pair, a
+ * neighbour in G_t of such an endpoint, or in the set Alg. 2 (plus the
+ * deletion rule) selects.  Its eight features, computed on (G_t, C_{t-1},
+ * community totals on G_t) from exact integers, each one correctly rounded
+ * fp64 division, then rounded to bfloat16 (to fp32, then to nearest even):
+ *   x0 = k/(k+16)        k: weighted degree in G_t
+ *   x1 = (k-kp)/max(k,kp), 0 when both are 0; kp: degree in G_{t-1}
+ *   x2 = t/(t+4)         t: changed pairs at the vertex
+ *   x3 = e_own/k         e_own = e_{i->C(i)} (0 when k = 0)
+ *   x4 = G1/(2m*k)       G1: scaled gain (Sec. 3.1) to the best other
+ *                        neighbouring community (score descending, label
+ *                        ascending); -3 when there is none
+ *   x5 = G2/(2m*k)       the same for the second best; -3 when none
+ *   x6 = 1 if Alg. 2 (or the deletion rule) selected the vertex, else 0
+ *   x7 = a_{C(i)}/2m     (0 when 2m = 0)
+ * The move label of a touched vertex is 1 when it ends level 0 in another
+ * community if level 0 is run from C_{t-1} with every vertex active.
+ *
+ * The network: 8 -> 64 -> 64 -> 1, ReLU, ReLU, logit (sigmoid score), with
+ * DC_MLP_PARAMS fp32 parameters in one flat vector
+ *   W1[64][8] | b1[64] | W2[64][64] | b2[64] | w3[64] | b3
+ * (row = output unit).  Device compute rounds every parameter and every
+ * activation or back-propagated signal entering a matrix product to
+ * bfloat16 and accumulates in fp32 on the matrix cores. */
+#define DC_MLP_INPUTS 8
+#define DC_MLP_HIDDEN 64
+#define DC_MLP_PARAMS 4801
+
+/* Sets (w != NULL: DC_MLP_PARAMS host floats, copied) or clears (w = NULL)
+ * the screener of a context.  In LEARNED mode R_t becomes the touched
+ * vertices whose logit is >= theta. */
+dc_status dc_screener_set(dc_ctx* ctx, const float* w, float theta);
+
+/* Samples of the last dc_apply_batch (LEARNED mode or collect = 1): *count
+ * receives the number of touched vertices; then, for every non-NULL output
+ * (device memory when on_device = 1): ids[count] (ascending vertex ids),
+ * X[count][8] bfloat16 bit patterns, y[count] move labels (0/1; collect = 1
+ * only, else ARG), logits[count] (when the screener scored the batch, else
+ * ARG).  *count = 0 when nothing was recorded. */
+dc_status dc_last_samples(dc_ctx* ctx, int64_t* count, int32_t* ids,
+                          uint16_t* X, uint8_t* y, float* logits,
+                          int32_t on_device);
+
+/* A trainable copy of the network on the device: fp32 master parameters,
+ * Adam moments (beta1 0.9, beta2 0.999, eps 1e-8) and the bfloat16 copy the
+ * kernels read.  All work goes to `stream` (hipStream_t, NULL = default);
+ * calls return after their results are written. */
+typedef struct dc_mlp dc_mlp;
+
+dc_status dc_mlp_create(dc_mlp** out, const float* w, void* stream);
+dc_status dc_mlp_set_weights(dc_mlp* m, const float* w);  /* resets Adam */
+dc_status dc_mlp_get_weights(dc_mlp* m, float* w);
+/* logits[n] (device) of X[n][8] (device, bfloat16 bit patterns). */
+dc_status dc_mlp_forward(dc_mlp* m, const uint16_t* X, int64_t n, float* logits);
+/* Mean binary cross-entropy over the n samples (labels y[n] on the device,
+ * 0/1; positives weighted by pos_weight > 0) and its gradient, into the host
+ * arrays grad[DC_MLP_PARAMS] and *loss (either may be NULL).  No update. */
+dc_status dc_mlp_grad(dc_mlp* m, const uint16_t* X, const uint8_t* y, int64_t n,
+                      float pos_weight, float* grad, double* loss);
+/* One Adam step of learning rate lr on the same loss; *loss (may be NULL)
+ * receives the loss before the step. */
+dc_status dc_mlp_train_step(dc_mlp* m, const uint16_t* X, const uint8_t* y,
+                            int64_t n, float pos_weight, float lr, double* loss);
+void dc_mlp_destroy(dc_mlp* m);
 
 const char* dc_strerror(dc_status s);
 

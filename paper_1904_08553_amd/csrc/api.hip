@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dc_louvain.h"
+#include "learned.h"
 
 using namespace dc;
 
@@ -32,9 +33,15 @@ struct dc_ctx {
   DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
   DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
   DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
-  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end;
+  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc;
+  // learned screener: touched set, features, labels, scores
+  DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
+  bool have_scr = false;
+  float theta = 0.f;
+  int64_t T_count = 0;
+  bool have_y = false, have_logits = false;
   // levels
-  DBuf Cl, Cn, al, szl, dpack, tflag, tlist, movers, map0, cnt[2], minv[2], lab, cntf;
+  DBuf Cl, Cn, al, szl, dpack, lflag, tlist, movers, map0, cnt[2], minv[2], lab, cntf;
   CoarseGraph cg[2];
   DBuf stat;
   long long* hstat = nullptr;  // pinned mirror of the status block
@@ -65,11 +72,13 @@ dc_status map_device_error(const DeviceError& e) {
 
 bool options_ok(const dc_options* o) {
   if (!o) return false;
-  if (o->mode < DC_MODE_DELTA || o->mode > DC_MODE_STATIC) return false;
+  if (o->mode < DC_MODE_DELTA || o->mode > DC_MODE_LEARNED) return false;
+  if (o->collect != 0 && o->collect != 1) return false;
+  if (o->pad != 0) return false;
   if (o->max_levels < 1 || o->max_sweeps < 1) return false;
   if (o->del_rule != DC_DEL_GAIN && o->del_rule != DC_DEL_CONSERVATIVE) return false;
   if (o->tau_den < 0) return false;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (o->reserved[i] != 0) return false;
   return true;
 }
@@ -101,7 +110,7 @@ void stage_edges(dc_ctx* c, const dc_edges* e, bool weights, DBuf& bu, DBuf& bv,
 
 void ensure_vertex_state(dc_ctx* c) {
   size_t n = size_t(c->n);
-  for (DBuf* b : {&c->k0, &c->C, &c->a0, &c->sz0, &c->Cl, &c->Cn, &c->al, &c->szl, &c->tflag,
+  for (DBuf* b : {&c->k0, &c->C, &c->a0, &c->sz0, &c->Cl, &c->Cn, &c->al, &c->szl, &c->lflag,
                   &c->tlist, &c->movers, &c->map0, &c->cnt[0], &c->cnt[1], &c->minv[0],
                   &c->minv[1], &c->lab, &c->cntf, &c->dflag, &c->dpos, &c->dlist, &c->rflag,
                   &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end})
@@ -111,12 +120,93 @@ void ensure_vertex_state(dc_ctx* c) {
   c->cflag.ensure(n + 1);
   c->stat.ensure(ST_COUNT * 8);
   fill_i64(c->dpack.as<int64_t>(), 0, int64_t(n) + 1, c->st);
-  fill_i32(c->tflag.as<int32_t>(), 0, int64_t(n) + 1, c->st);
+  fill_i32(c->lflag.as<int32_t>(), 0, int64_t(n) + 1, c->st);
+}
+
+void ensure_sample_state(dc_ctx* c) {
+  size_t n = size_t(c->n) + 1;
+  for (DBuf* b : {&c->kprev, &c->tflag, &c->tpos, &c->Tlist, &c->f_own, &c->logits})
+    b->ensure(n * 4);
+  c->f_g1.ensure(n * 8);
+  c->f_g2.ensure(n * 8);
+  c->tmark.ensure(n);
+  c->y.ensure(n);
+  c->X.ensure(n * 16);
 }
 
 void read_stat(dc_ctx* c) {
   DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, c->st));
   DC_HIP(hipStreamSynchronize(c->st));
+}
+
+// Synchronous sweeps of one level over the binned active set (Alg. 1 inner
+// loop); returns the level's total exact gain.  record: trace records,
+// statistics and timing of the call.
+long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t nact,
+                     const Bins& bins, int level, long long T, bool record) {
+  hipStream_t st = c->st;
+  const long long two_m = c->two_m;
+  int32_t* Cl = c->Cl.as<int32_t>();
+  int32_t* Cn = c->Cn.as<int32_t>();
+  int32_t* al = c->al.as<int32_t>();
+  int32_t* szl = c->szl.as<int32_t>();
+  dc_step_stats& S = c->stats;
+  int64_t n_eval = 0;
+  long long vol_eval = 0;
+  for (int q = 0; q < NBINS; ++q) {
+    n_eval += bins.n[q];
+    vol_eval += bins.vol[q];
+  }
+  long long level_gain = 0;
+  for (int s = 0; s < c->opt.max_sweeps; ++s) {
+    sweep_reset(c->stat.as<long long>(), st);
+    const bool timed = record && c->opt.timing && bins.n[TIMED_BIN] > 0;
+    sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
+               c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,
+               timed ? c->ev1 : nullptr);
+    sweep_apply(g, act, nact, Cl, Cn, al, szl, two_m, c->movers.as<int32_t>(),
+                c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
+                c->stat.as<long long>(), st);
+    read_stat(c);
+    const long long moves = c->hstat[ST_MOVES], dN = c->hstat[ST_DN];
+    if (!record) {
+      if (moves == 0 || dN < 0) break;
+      level_gain += dN;
+      if (dN <= T) break;
+      continue;
+    }
+    if (timed) {
+      float ms = 0;
+      DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      S.ms_sweep_kernel += ms;
+      S.sweep_launches += 1;
+      // algorithmic bytes of the timed launch: 12 B per adjacency entry
+      // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
+      // (two offsets, label, degree, own total and size, best total, result)
+      S.sweep_bytes += 12 * bins.vol[TIMED_BIN] + 32 * bins.n[TIMED_BIN];
+    }
+    dc_sweep_rec r{};
+    r.level = level;
+    r.sweep = s;
+    r.n_level = g.n;
+    r.n_active = int32_t(n_eval);
+    r.nnz_level = g.nnz;
+    r.moves = c->hstat[ST_MOVES];
+    r.dN = c->hstat[ST_DN];
+    r.kept = int32_t(c->hstat[ST_KEEP]);
+    c->trace.push_back(r);
+    S.vertex_evals += n_eval;
+    if (level == 0) {
+      S.level0_sweeps += 1;
+      S.level0_active += n_eval;
+      S.level0_volume += vol_eval;
+    }
+    if (r.moves == 0 || r.dN < 0) break;
+    S.moves += r.moves;
+    level_gain += r.dN;
+    if (r.dN <= T) break;
+  }
+  return level_gain;
 }
 
 // Alg. 1 with level 0 visiting `active` (null = every vertex).  The level-0
@@ -140,54 +230,7 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
     const int64_t nact = level == 0 ? n_active : g.n;
     Bins bins;
     make_bins(act, nact, g.off, bins, c->bins, st);
-    int64_t n_eval = 0;
-    long long vol_eval = 0;
-    for (int q = 0; q < NBINS; ++q) {
-      n_eval += bins.n[q];
-      vol_eval += bins.vol[q];
-    }
-    long long level_gain = 0;
-    for (int s = 0; s < c->opt.max_sweeps; ++s) {
-      sweep_reset(c->stat.as<long long>(), st);
-      const bool timed = c->opt.timing && bins.n[TIMED_BIN] > 0;
-      sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
-                 c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,
-                 timed ? c->ev1 : nullptr);
-      sweep_apply(g, act, nact, Cl, Cn, al, szl, two_m, c->movers.as<int32_t>(),
-                  c->dpack.as<long long>(), c->tflag.as<int32_t>(), c->tlist.as<int32_t>(),
-                  c->stat.as<long long>(), st);
-      read_stat(c);
-      if (timed) {
-        float ms = 0;
-        DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        S.ms_sweep_kernel += ms;
-        S.sweep_launches += 1;
-        // algorithmic bytes of the timed launch: 12 B per adjacency entry
-        // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
-        // (two offsets, label, degree, own total and size, best total, result)
-        S.sweep_bytes += 12 * bins.vol[TIMED_BIN] + 32 * bins.n[TIMED_BIN];
-      }
-      dc_sweep_rec r{};
-      r.level = level;
-      r.sweep = s;
-      r.n_level = g.n;
-      r.n_active = int32_t(n_eval);
-      r.nnz_level = g.nnz;
-      r.moves = c->hstat[ST_MOVES];
-      r.dN = c->hstat[ST_DN];
-      r.kept = int32_t(c->hstat[ST_KEEP]);
-      c->trace.push_back(r);
-      S.vertex_evals += n_eval;
-      if (level == 0) {
-        S.level0_sweeps += 1;
-        S.level0_active += n_eval;
-        S.level0_volume += vol_eval;
-      }
-      if (r.moves == 0 || r.dN < 0) break;
-      S.moves += r.moves;
-      level_gain += r.dN;
-      if (r.dN <= T) break;
-    }
+    const long long level_gain = run_sweeps(c, g, act, nact, bins, level, T, true);
     const bool stop = (level + 1 >= c->opt.max_levels) || (level >= 1 && level_gain <= T);
     if (stop && level >= 1) break;
     // coarsen (after level 0 always: it also yields the canonical labels)
@@ -220,6 +263,60 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
   S.N = two_m * c->hstat[ST_I] - c->hstat[ST_S];
   S.two_m = two_m;
   S.q = two_m == 0 ? 0.0 : double(S.N) / (double(two_m) * double(two_m));
+}
+
+void load_level0_partition(dc_ctx* c);
+
+// Move labels of the touched vertices: level 0 rerun from C_{t-1} with every
+// vertex active (full re-evaluation), nothing recorded, state untouched.
+void level0_labels(dc_ctx* c) {
+  hipStream_t st = c->st;
+  const long long two_m = c->two_m;
+  const long long T = c->opt.tau_den > 0 ? (two_m * two_m) / c->opt.tau_den : 0;
+  LevelView g{c->n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
+              c->k0.as<int32_t>()};
+  load_level0_partition(c);
+  DC_HIP(hipMemcpyAsync(c->Cn.p, c->Cl.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, st));
+  Bins bins;
+  make_bins(nullptr, c->n, g.off, bins, c->bins, st);
+  (void)run_sweeps(c, g, nullptr, c->n, bins, 0, T, false);
+  move_labels(c->Tlist.as<int32_t>(), c->T_count, c->Cl.as<int32_t>(), c->C.as<int32_t>(),
+              c->y.as<uint8_t>(), st);
+}
+
+// The touched set T = R (screened) + S_Delta + Gamma_t(S_Delta) (tmark holds
+// the last two), its features on (G_t, C_{t-1}), and, as asked, its move
+// labels and its screener logits.
+void touched_samples(dc_ctx* c, const LevelView& g0, bool labels, bool score) {
+  hipStream_t st = c->st;
+  const int32_t n = c->n;
+  int32_t* tflag = c->tflag.as<int32_t>();
+  int32_t* tpos = c->tpos.as<int32_t>();
+  merge_flags(c->R.as<uint8_t>(), c->tmark.as<uint8_t>(), n, tflag, st);
+  scan_excl_i32(tflag, tpos, n, tpos + n, st);
+  compact_index(tflag, tpos, n, c->Tlist.as<int32_t>(), st);
+  DC_HIP(hipMemcpyAsync(c->hbuf, tpos + n, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  c->T_count = *static_cast<int32_t*>(c->hbuf);
+  if (c->T_count == 0) return;
+  Bins b;
+  make_bins(c->Tlist.as<int32_t>(), c->T_count, g0.off, b, c->bins, st);
+  feat_eval(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, b, c->f_own.as<int32_t>(),
+            c->f_g1.as<long long>(), c->f_g2.as<long long>(), st);
+  assemble_features(c->Tlist.as<int32_t>(), c->T_count, c->k0.as<int32_t>(),
+                    c->kprev.as<int32_t>(), c->cptr.as<int32_t>(), c->f_own.as<int32_t>(),
+                    c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->a0.as<int32_t>(),
+                    c->C.as<int32_t>(), c->R.as<uint8_t>(), c->two_m, c->X.as<uint16_t>(), st);
+  c->stats.vertex_evals += c->T_count;
+  if (labels) {
+    level0_labels(c);
+    c->have_y = true;
+  }
+  if (score) {
+    mlp_forward(c->scr_wq.as<uint16_t>(), c->X.as<uint16_t>(), c->T_count,
+                c->logits.as<float>(), st);
+    c->have_logits = true;
+  }
 }
 
 void start_from_singletons(dc_ctx* c) {
@@ -393,6 +490,14 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
   c->new_deg.ensure(size_t(n + 1) * 4);
   int32_t* cptr = c->cptr.as<int32_t>();
   row_bounds(ch_key, nch, n, cptr, st);
+  const int mode = c->opt.mode;
+  const bool samples = mode == DC_MODE_LEARNED || c->opt.collect;
+  c->T_count = 0;
+  c->have_y = c->have_logits = false;
+  if (samples) {
+    ensure_sample_state(c);
+    DC_HIP(hipMemcpyAsync(c->kprev.p, c->k0.p, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+  }
   row_changes(cptr, ch_op, ch_dk, off_old, n, c->new_deg.as<int32_t>(), c->k0.as<int32_t>(),
               c->C.as<int32_t>(), c->a0.as<int32_t>(), st);
   const int nxt = c->cur ^ 1;
@@ -411,7 +516,8 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
   // rows with changes: the distinct sources of the change list
   int32_t* crow_flag = c->rheads.as<int32_t>();
   int32_t* crow_pos = c->rpos.as<int32_t>();
-  int32_t* crows = c->src_list.as<int32_t>();
+  c->chsrc.ensure(size_t(nr + 1) * 4);
+  int32_t* crows = c->chsrc.as<int32_t>();
   source_heads(ch_key, nch, n, crow_flag, st);
   scan_excl_i32(crow_flag, crow_pos, nch, crow_pos + nch, st);
   gather_sources(ch_key, crow_flag, crow_pos, nch, n, crows, st);
@@ -426,8 +532,12 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
   S.changes = na + nd;
   LevelView g0{n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
                c->k0.as<int32_t>()};
-  const int mode = c->opt.mode;
-  if (mode == DC_MODE_DELTA) {
+  if (samples) {
+    // endpoints of the changed pairs and their neighbours in G_t
+    fill_u8(c->tmark.as<uint8_t>(), 0, n, st);
+    mark_touched(crows, crow_pos + nch, nch, g0.off, g0.adj, c->tmark.as<uint8_t>(), st);
+  }
+  if (mode == DC_MODE_DELTA || samples) {
     uint8_t* R = c->R.as<uint8_t>();
     uint8_t* cflag = c->cflag.as<uint8_t>();
     fill_u8(R, 0, n, st);
@@ -481,6 +591,30 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
     S.del_accepted = c->opt.del_rule == DC_DEL_CONSERVATIVE ? n_dsrc : hs[ST_DEL_ACC];
     S.R_size = c->R_count;
     S.vertex_evals += S.ds_sources + S.del_sources;
+  }
+  if (samples) {
+    const bool score = mode == DC_MODE_LEARNED && c->have_scr;
+    touched_samples(c, g0, c->opt.collect != 0, score);
+    S.touched = c->T_count;
+    if (score) {
+      // R_t = touched vertices scoring at least theta
+      uint8_t* R = c->R.as<uint8_t>();
+      int32_t* rflag = c->rflag.as<int32_t>();
+      int32_t* rpos2 = c->rpos2.as<int32_t>();
+      fill_u8(R, 0, n, st);
+      select_by_score(c->Tlist.as<int32_t>(), c->T_count, c->logits.as<float>(), c->theta, R,
+                      st);
+      merge_flags(R, nullptr, n, rflag, st);
+      scan_excl_i32(rflag, rpos2, n, rpos2 + n, st);
+      compact_index(rflag, rpos2, n, c->Rlist.as<int32_t>(), st);
+      DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
+      DC_HIP(hipStreamSynchronize(st));
+      c->R_count = *static_cast<int32_t*>(c->hbuf);
+      S.R_size = c->R_count;
+      S.screened = 1;
+    }
+  }
+  if (mode == DC_MODE_DELTA || mode == DC_MODE_LEARNED) {
     c->have_R_all = false;
     load_level0_partition(c);
     run_levels(c, c->Rlist.as<int32_t>(), c->R_count);
@@ -704,6 +838,41 @@ dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w) {
 }
 
 void dc_destroy(dc_ctx* ctx) { destroy_ctx(ctx); }
+
+dc_status dc_screener_set(dc_ctx* ctx, const float* w, float theta) {
+  return guarded(ctx, [&] {
+    if (!w) {
+      ctx->have_scr = false;
+      return DC_OK;
+    }
+    std::vector<uint16_t> q(MLP_P);
+    for (int p = 0; p < MLP_P; ++p) q[size_t(p)] = bf16_bits(w[p]);
+    ctx->scr_wq.ensure(MLP_P * 2);
+    DC_HIP(hipMemcpyAsync(ctx->scr_wq.p, q.data(), MLP_P * 2, hipMemcpyHostToDevice, ctx->st));
+    DC_HIP(hipStreamSynchronize(ctx->st));
+    ctx->theta = theta;
+    ctx->have_scr = true;
+    return DC_OK;
+  });
+}
+
+dc_status dc_last_samples(dc_ctx* ctx, int64_t* count, int32_t* ids, uint16_t* X, uint8_t* y,
+                          float* logits, int32_t on_device) {
+  if (!count) return DC_E_ARG;
+  return guarded(ctx, [&] {
+    const int64_t cnt = ctx->T_count;
+    *count = cnt;
+    if (cnt == 0) return DC_OK;
+    if ((y && !ctx->have_y) || (logits && !ctx->have_logits)) return DC_E_ARG;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (ids) DC_HIP(hipMemcpyAsync(ids, ctx->Tlist.p, size_t(cnt) * 4, kind, ctx->st));
+    if (X) DC_HIP(hipMemcpyAsync(X, ctx->X.p, size_t(cnt) * 16, kind, ctx->st));
+    if (y) DC_HIP(hipMemcpyAsync(y, ctx->y.p, size_t(cnt), kind, ctx->st));
+    if (logits) DC_HIP(hipMemcpyAsync(logits, ctx->logits.p, size_t(cnt) * 4, kind, ctx->st));
+    DC_HIP(hipStreamSynchronize(ctx->st));
+    return DC_OK;
+  });
+}
 
 const char* dc_last_error(void) { return g_last_error.c_str(); }
 

@@ -29,7 +29,10 @@ enum StatSlot : int {
   ST_COUNT = 24
 };
 
-enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2 };
+// EV_FEAT: e_{i->C(i)} and the gains to the best and second-best other
+// neighbouring community, the integer inputs of the screener features.
+enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2, EV_FEAT = 3 };
+constexpr long long NO_GAIN = (long long)0x8000000000000000ull;
 
 // Row-length bins of the evaluation kernels (eval.hip): rows of at most 16,
 // 32 and 64 entries (4, 2 and 1 vertices per wave, no table), then
@@ -91,6 +94,13 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
 void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
                   long long two_m, const Bins& bins, uint8_t* R, uint8_t* cflag,
                   long long* stat, hipStream_t st);
+
+// Per listed vertex i: f_own[i] = e_{i->C(i)}, f_g1[i] / f_g2[i] = scaled
+// gains to the best / second-best other neighbouring community (score
+// descending, label ascending), NO_GAIN when absent.
+void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
+               const Bins& bins, int32_t* f_own, long long* f_g1, long long* f_g2,
+               hipStream_t st);
 
 // ---- screen.hip ----
 // out[pos[i]] = i for flag[i] != 0 (pos = exclusive scan of flag).

@@ -53,6 +53,9 @@ struct EvalArgs {
   int32_t n0;
   uint8_t* R;
   uint8_t* cflag;
+  int32_t* f_own;  // EV_FEAT outputs, indexed by vertex
+  long long* f_g1;
+  long long* f_g2;
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -234,6 +237,18 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
     const bool pair = gl < nd;
     const long long e_own = group_sum_ll<GS>(pair && ck == c ? (long long)cs : 0);
     const long long s_own = A.two_m * e_own - ki * ((have ? A.a[c] : 0) - ki);
+    if (MODE == EV_FEAT) {
+      Best b = {NO_SCORE, NO_LABEL};
+      if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
+      const Best b1 = group_best_w<GS>(b);
+      const Best b2 = group_best_w<GS>(b.x != b1.x ? b : Best{NO_SCORE, NO_LABEL});
+      if (have && gl == 0) {
+        A.f_own[i] = int32_t(e_own);
+        A.f_g1[i] = b1.x != NO_LABEL ? b1.s - s_own : NO_GAIN;
+        A.f_g2[i] = b2.x != NO_LABEL ? b2.s - s_own : NO_GAIN;
+      }
+      continue;
+    }
     if (MODE == EV_DSADD) {
       const int q0 = have ? A.seg_beg[i] : 0;
       const int nsk = have ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
@@ -483,6 +498,27 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   b = group_best<G>(b, L);
   group_sync<G>();
   const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
+  if (MODE == EV_FEAT) {
+    // the table holds only foreign labels; a second scan skips the best
+    Best b2 = {NO_SCORE, NO_LABEL};
+    for (uint32_t s = t; s <= mask; s += G) {
+      const int X = keys[s];
+      if (X == EMPTY_KEY || X == b.x) continue;
+      const long long sc = A.two_m * vals[s] - ki * A.a[X];
+      if (better(sc, X, b2.s, b2.x)) {
+        b2.s = sc;
+        b2.x = X;
+      }
+    }
+    b2 = group_best<G>(b2, L);
+    if (t == 0) {
+      A.f_own[i] = int32_t(e_own);
+      A.f_g1[i] = b.x != NO_LABEL ? b.s - s_own : NO_GAIN;
+      A.f_g2[i] = b2.x != NO_LABEL ? b2.s - s_own : NO_GAIN;
+    }
+    group_sync<G>();  // the table is reused by the next item of this group
+    return 0;
+  }
   bool move = b.x != NO_LABEL && b.s > s_own;
   if (MODE == EV_SWEEP) {
     if (move && A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c) move = false;
@@ -837,6 +873,23 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
   A.R = R;
   A.cflag = cflag;
   launch_eval<EV_DSADD>(A, bins, st, nullptr, nullptr);
+}
+
+void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
+               const Bins& bins, int32_t* f_own, long long* f_g1, long long* f_g2,
+               hipStream_t st) {
+  EvalArgs A{};
+  A.off = g.off;
+  A.adj = g.adj;
+  A.k = g.k;
+  A.C = C;
+  A.a = a;
+  A.two_m = two_m;
+  A.n0 = g.n;
+  A.f_own = f_own;
+  A.f_g1 = f_g1;
+  A.f_g2 = f_g2;
+  launch_eval<EV_FEAT>(A, bins, st, nullptr, nullptr);
 }
 
 void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,

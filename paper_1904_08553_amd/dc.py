@@ -16,7 +16,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdc.so")
 
 OK = 0
-MODE_DELTA, MODE_ALL, MODE_STATIC = 0, 1, 2
+MODE_DELTA, MODE_ALL, MODE_STATIC, MODE_LEARNED = 0, 1, 2, 3
+MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 8, 64, 4801
 DEL_GAIN, DEL_CONSERVATIVE = 0, 1
 STATUS = {
     0: "OK", -1: "ARG", -2: "RANGE", -3: "SELF_LOOP", -4: "WEIGHT", -5: "NO_EDGE",
@@ -28,7 +29,8 @@ class Options(ct.Structure):
     _fields_ = [
         ("mode", ct.c_int32), ("max_levels", ct.c_int32), ("max_sweeps", ct.c_int32),
         ("singleton_guard", ct.c_int32), ("del_rule", ct.c_int32), ("timing", ct.c_int32),
-        ("tau_den", ct.c_int64), ("stream", ct.c_void_p), ("reserved", ct.c_int64 * 4),
+        ("tau_den", ct.c_int64), ("stream", ct.c_void_p), ("collect", ct.c_int32),
+        ("pad", ct.c_int32), ("reserved", ct.c_int64 * 3),
     ]
 
 
@@ -56,7 +58,8 @@ class StepStats(ct.Structure):
         ("ms_total", ct.c_double), ("ms_sweep_kernel", ct.c_double),
         ("sweep_launches", ct.c_int64), ("sweep_bytes", ct.c_int64),
         ("level0_sweeps", ct.c_int64), ("level0_active", ct.c_int64),
-        ("level0_volume", ct.c_int64), ("reserved", ct.c_int64 * 4),
+        ("level0_volume", ct.c_int64), ("touched", ct.c_int64), ("screened", ct.c_int64),
+        ("reserved", ct.c_int64 * 2),
     ]
 
     def as_dict(self):
@@ -66,7 +69,9 @@ class StepStats(ct.Structure):
 EXPORTS = [
     "dc_default_options", "dc_init", "dc_apply_batch", "dc_modularity", "dc_communities",
     "dc_last_R", "dc_last_trace", "dc_last_stats", "dc_num_entries", "dc_export_csr",
-    "dc_destroy", "dc_strerror", "dc_last_error",
+    "dc_destroy", "dc_strerror", "dc_last_error", "dc_screener_set", "dc_last_samples",
+    "dc_mlp_create", "dc_mlp_set_weights", "dc_mlp_get_weights", "dc_mlp_forward", "dc_mlp_grad",
+    "dc_mlp_train_step", "dc_mlp_destroy",
 ]
 
 _lib = None
@@ -112,6 +117,25 @@ def load(path: str = LIB_PATH):
     L.dc_strerror.restype = ct.c_char_p
     L.dc_last_error.argtypes = []
     L.dc_last_error.restype = ct.c_char_p
+    f32, f64p = ct.c_float, ct.c_void_p
+    L.dc_screener_set.argtypes = [P, P, f32]
+    L.dc_screener_set.restype = i32
+    L.dc_last_samples.argtypes = [P, P, P, P, P, P, i32]
+    L.dc_last_samples.restype = i32
+    L.dc_mlp_create.argtypes = [P, P, P]
+    L.dc_mlp_create.restype = i32
+    L.dc_mlp_set_weights.argtypes = [P, P]
+    L.dc_mlp_set_weights.restype = i32
+    L.dc_mlp_get_weights.argtypes = [P, P]
+    L.dc_mlp_get_weights.restype = i32
+    L.dc_mlp_forward.argtypes = [P, P, i64, P]
+    L.dc_mlp_forward.restype = i32
+    L.dc_mlp_grad.argtypes = [P, P, P, i64, f32, P, f64p]
+    L.dc_mlp_grad.restype = i32
+    L.dc_mlp_train_step.argtypes = [P, P, P, i64, f32, f32, f64p]
+    L.dc_mlp_train_step.restype = i32
+    L.dc_mlp_destroy.argtypes = [P]
+    L.dc_mlp_destroy.restype = None
     _lib = L
     return L
 
@@ -174,11 +198,12 @@ def current_stream():
 
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
-            del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current"):
+            del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current", collect=0):
     o = Options()
     load().dc_default_options(ct.byref(o))
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.timing, o.tau_den = singleton_guard, del_rule, timing, tau_den
+    o.collect = collect
     o.stream = current_stream() if stream == "current" else stream
     return o
 
@@ -244,6 +269,50 @@ class DynamicCommunities:
         _check(load().dc_last_stats(self._h, ct.byref(st)), "dc_last_stats")
         return st
 
+    def set_screener(self, w, theta):
+        """Screener parameters (MLP_PARAMS floats, or None to clear) and the
+        logit threshold of LEARNED mode."""
+        if w is None:
+            _check(load().dc_screener_set(self._h, None, 0.0), "dc_screener_set")
+            return
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+        if a.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        _check(load().dc_screener_set(self._h, a.ctypes.data, float(theta)), "dc_screener_set")
+
+    def samples(self, device=False, labels=True, logits=False):
+        """Screener samples of the last batch: dict of ids (int32), X (uint16
+        bfloat16 bits, [count, 8]), y (uint8) and logits (float32), as numpy
+        arrays or (device=True) torch tensors on the GPU."""
+        L = load()
+        cnt = ct.c_int64()
+        _check(L.dc_last_samples(self._h, ct.byref(cnt), None, None, None, None, 0),
+               "dc_last_samples")
+        c = cnt.value
+        if device:
+            import torch
+            dev = torch.device("cuda")
+            ids = torch.empty(max(c, 1), dtype=torch.int32, device=dev)
+            X = torch.empty((max(c, 1), MLP_INPUTS), dtype=torch.int16, device=dev)
+            y = torch.empty(max(c, 1), dtype=torch.uint8, device=dev) if labels else None
+            z = torch.empty(max(c, 1), dtype=torch.float32, device=dev) if logits else None
+            ptr = lambda t: None if t is None else t.data_ptr()
+        else:
+            ids = np.empty(max(c, 1), np.int32)
+            X = np.empty((max(c, 1), MLP_INPUTS), np.uint16)
+            y = np.empty(max(c, 1), np.uint8) if labels else None
+            z = np.empty(max(c, 1), np.float32) if logits else None
+            ptr = lambda a: None if a is None else a.ctypes.data
+        if c > 0:
+            _check(L.dc_last_samples(self._h, ct.byref(cnt), ptr(ids), ptr(X), ptr(y), ptr(z),
+                                     int(device)), "dc_last_samples")
+        out = dict(ids=ids[:c], X=X[:c])
+        if labels:
+            out["y"] = y[:c]
+        if logits:
+            out["logits"] = z[:c]
+        return out
+
     def csr(self):
         nnz = ct.c_int64()
         _check(load().dc_num_entries(self._h, ct.byref(nnz)), "dc_num_entries")
@@ -257,6 +326,70 @@ class DynamicCommunities:
     def close(self):
         if getattr(self, "_h", None):
             load().dc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The screener network on the GPU (libdc.so's dc_mlp): forward, loss
+    gradient and Adam steps over device tensors of bfloat16 feature bits."""
+
+    def __init__(self, w):
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+        if a.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        h = ct.c_void_p()
+        _check(load().dc_mlp_create(ct.byref(h), a.ctypes.data, current_stream()),
+               "dc_mlp_create")
+        self._h = h
+
+    @staticmethod
+    def _dev(t, dtype_name):
+        if not (_is_torch(t) and t.is_cuda and t.is_contiguous()):
+            raise ValueError(f"{dtype_name} must be a contiguous CUDA tensor")
+        return t.data_ptr()
+
+    def set_weights(self, w):
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+        _check(load().dc_mlp_set_weights(self._h, a.ctypes.data), "dc_mlp_set_weights")
+
+    def weights(self):
+        w = np.empty(MLP_PARAMS, np.float32)
+        _check(load().dc_mlp_get_weights(self._h, w.ctypes.data), "dc_mlp_get_weights")
+        return w
+
+    def forward(self, X):
+        import torch
+        n = X.shape[0]
+        z = torch.empty(max(n, 1), dtype=torch.float32, device=X.device)
+        _check(load().dc_mlp_forward(self._h, self._dev(X, "X"), n, z.data_ptr()),
+               "dc_mlp_forward")
+        return z[:n]
+
+    def grad(self, X, y, pos_weight):
+        g = np.empty(MLP_PARAMS, np.float32)
+        loss = ct.c_double()
+        _check(load().dc_mlp_grad(self._h, self._dev(X, "X"), self._dev(y, "y"), X.shape[0],
+                                  float(pos_weight), g.ctypes.data, ct.byref(loss)),
+               "dc_mlp_grad")
+        return loss.value, g
+
+    def train_step(self, X, y, pos_weight, lr, want_loss=False):
+        loss = ct.c_double()
+        _check(load().dc_mlp_train_step(self._h, self._dev(X, "X"), self._dev(y, "y"), X.shape[0],
+                                        float(pos_weight), float(lr),
+                                        ct.byref(loss) if want_loss else None),
+               "dc_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dc_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

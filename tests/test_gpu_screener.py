@@ -1,0 +1,224 @@
+"""GPU parity of the learned screener (through include/dc.h) against the CPU
+oracle: screener samples bit for bit (touched ids, bfloat16 feature bits,
+move labels), the network's logits and gradients within the bounds the
+oracle derives from the BF16/FP32 arithmetic, Adam, and LEARNED mode end to
+end (R_t decided identically wherever the logit is clear of theta by more
+than its bound, then C_t and the sweep trace bit-exact with the oracle run
+over the GPU's R_t)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import compare
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_1904_08553_amd import dc
+from paper_1904_08553_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def oracle_bits(s):
+    return M.bf16_bits(s["X"]).reshape(-1, 8)
+
+
+def feature_bits(n, seed):
+    """bfloat16 feature rows shaped like the screener's inputs."""
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([rng.uniform(0, 1, n), rng.uniform(-1, 1, n), rng.uniform(0, 1, n),
+                         rng.uniform(0, 1, n), rng.uniform(-2, 1, n), rng.uniform(-2, 1, n),
+                         rng.integers(0, 2, n), rng.uniform(0, 0.2, n)])
+    return M.bf16_bits(X).reshape(n, 8)
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def dev_bits(bits):
+    return torch.from_numpy(bits.astype(np.uint16).view(np.int16)).cuda().contiguous()
+
+
+@pytest.mark.parametrize("n", [1, 16, 1000, 4101])
+def test_forward_within_bound(n):
+    _log(f"case: mlp forward n={n}")
+    w = M.init_weights(n)
+    w[M.OFF_B1:M.OFF_W2] = 0.1
+    bits = feature_bits(n, 7 + n)
+    net = dc.MLP(w)
+    z = net.forward(dev_bits(bits)).cpu().numpy().astype(np.float64)
+    X = M.from_bits(bits)
+    zo, _ = M.forward(w, X)
+    bnd = M.forward_bound(w, X)
+    assert np.all(np.abs(z - zo) <= bnd + 1e-6), np.max(np.abs(z - zo) - bnd)
+    net.close()
+
+
+@pytest.mark.parametrize("n", [1, 37, 4096, 20011])
+def test_gradient_within_bound(n):
+    _log(f"case: mlp gradient n={n}")
+    w = M.init_weights(100 + n)
+    w[M.OFF_B1:M.OFF_W2] = 0.05
+    w[M.OFF_B2:M.OFF_W3] = 0.05
+    bits = feature_bits(n, 200 + n)
+    y = (np.random.default_rng(n).uniform(size=n) < 0.25).astype(np.uint8)
+    net = dc.MLP(w)
+    loss, g = net.grad(dev_bits(bits), to_dev(y, torch.uint8), 3.0)
+    lo, go, bnd = M.loss_grad(w, M.from_bits(bits), y, 3.0)
+    assert loss == pytest.approx(lo, rel=1e-4, abs=1e-6)
+    dev = np.abs(g.astype(np.float64) - go)
+    tol = bnd + 1e-7 * np.max(np.abs(go))
+    assert np.all(dev <= tol), (np.argmax(dev - tol), np.max(dev - tol))
+    assert np.linalg.norm(g - go) <= 1e-2 * np.linalg.norm(go)
+    net.close()
+
+
+def test_adam_steps():
+    """Two Adam steps on the GPU against the reference applied to the
+    reference gradient; entries whose gradient is within its bound of zero
+    (where the two sides may take different signs) are skipped."""
+    _log("case: adam")
+    n = 3000
+    w0 = M.init_weights(9)
+    bits = feature_bits(n, 10)
+    y = (np.random.default_rng(11).uniform(size=n) < 0.3).astype(np.uint8)
+    X = M.from_bits(bits)
+    net = dc.MLP(w0)
+    Xd, yd = dev_bits(bits), to_dev(y, torch.uint8)
+    lr = 1e-3
+    w, m, v = w0.astype(np.float64), np.zeros(M.NPARAM), np.zeros(M.NPARAM)
+    ok = np.ones(M.NPARAM, bool)
+    for t in (1, 2):
+        _, g, bnd = M.loss_grad(w.astype(np.float32), X, y, 2.0)
+        ok &= np.abs(g) > 4 * bnd + 1e-9
+        net.train_step(Xd, yd, 2.0, lr)
+        w, m, v = M.adam(w, m, v, g, t, lr)
+    wg = net.weights().astype(np.float64)
+    assert ok.mean() > 0.5
+    assert np.all(np.abs(wg - w)[ok] <= 0.02 * lr + 1e-6 * np.abs(w)[ok])
+    net.close()
+
+
+def _pair(n, u, v, w, mode, collect):
+    om = {"delta": O.MODE_DELTA, "all": O.MODE_ALL, "learned": O.MODE_LEARNED}[mode]
+    gm = {"delta": dc.MODE_DELTA, "all": dc.MODE_ALL, "learned": dc.MODE_LEARNED}[mode]
+    return (O.Oracle(n, u, v, w, mode=om, collect=collect),
+            dc.DynamicCommunities(n, u, v, w, mode=gm, collect=collect))
+
+
+def _check_samples(o, g, where):
+    so = o.samples()
+    sg = g.samples()
+    assert np.array_equal(so["ids"], sg["ids"]), f"{where}: touched set differs"
+    assert np.array_equal(oracle_bits(so), sg["X"]), (
+        f"{where}: feature bits differ at {np.argwhere(oracle_bits(so) != sg['X'])[:5]}")
+    assert np.array_equal(so["y"], sg["y"]), f"{where}: move labels differ"
+    assert g.last_stats().touched == len(so["ids"])
+    return so
+
+
+@pytest.mark.parametrize("mode", ["delta", "all"])
+def test_samples_planted_partition(mode):
+    _log(f"case: samples planted partition mode={mode}")
+    pp = W.PlantedPartition()
+    (u, v, w), batches = pp.batches()
+    o, g = _pair(pp.n, u, v, w, mode, 1)
+    for t, b in enumerate(batches):
+        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        compare(o, g, f"step {t}")
+        s = _check_samples(o, g, f"step {t}")
+        assert s["y"].sum() > 0
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_samples_dcsbm_hubs(seed):
+    """All six row-length bins of the feature evaluation (rows up to
+    thousands of entries) and ragged touched sets."""
+    _log(f"case: samples dcsbm hubs seed={seed}")
+    gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=seed)
+    (u, v, w), it = gen.stream(2, frac=0.01)
+    o, g = _pair(gen.n, u, v, w, "delta", 1)
+    for t, b in enumerate(it):
+        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        compare(o, g, f"step {t}")
+        _check_samples(o, g, f"step {t}")
+
+
+def test_samples_small_random():
+    for seed in range(6):
+        n = 9 + seed
+        _log(f"case: samples random small n={n}")
+        (u, v, w), batches = W.random_dynamic(n, 2 * n, 4, 5, 3, seed=5000 + seed)
+        o, g = _pair(n, u, v, w, "delta", 1)
+        for t, b in enumerate(batches):
+            o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+            g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+            compare(o, g, f"n={n} step {t}")
+            _check_samples(o, g, f"n={n} step {t}")
+
+
+def test_learned_without_screener_is_delta():
+    _log("case: learned fallback")
+    pp = W.PlantedPartition(n=600, blocks=6, p_in=0.1, p_out=0.005, seed=5)
+    (u, v, w), batches = pp.batches(steps=3, n_ins=150, n_del=60)
+    o = O.Oracle(pp.n, u, v, w)
+    g = dc.DynamicCommunities(pp.n, u, v, w, mode=dc.MODE_LEARNED)
+    for t, b in enumerate(batches):
+        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        compare(o, g, f"step {t}")
+        assert g.last_stats().screened == 0 and g.last_stats().touched > 0
+
+
+@pytest.mark.parametrize("graph", ["planted", "dcsbm"])
+def test_learned_mode_end_to_end(graph):
+    _log(f"case: learned end to end {graph}")
+    if graph == "planted":
+        pp = W.PlantedPartition()
+        (u, v, w), batches = pp.batches()
+        n = pp.n
+    else:
+        gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=3)
+        (u, v, w), it = gen.stream(2, frac=0.01)
+        batches, n = list(it), gen.n
+    wts = M.init_weights(77)
+    o = O.Oracle(n, u, v, w, mode=O.MODE_LEARNED)
+    g = dc.DynamicCommunities(n, u, v, w, mode=dc.MODE_LEARNED)
+    theta = None
+    for t, b in enumerate(batches):
+        o.stage_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        s = o.samples()
+        X = M.from_bits(oracle_bits(s))
+        zo, _ = M.forward(wts, X)
+        bnd = M.forward_bound(wts, X)
+        if theta is None:
+            theta = float(np.median(zo))  # about half of the touched set
+        g.set_screener(wts, theta)
+        g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        sg = g.samples(labels=False, logits=True)
+        assert np.array_equal(sg["ids"], s["ids"])
+        assert np.array_equal(sg["X"], oracle_bits(s))
+        zg = sg["logits"].astype(np.float64)
+        assert np.all(np.abs(zg - zo) <= bnd + 1e-6)
+        Rg = g.last_R()
+        sel = np.zeros(n, np.uint8)
+        sel[s["ids"][zg >= np.float32(theta)]] = 1
+        assert np.array_equal(Rg, sel), "R_t is not the thresholded touched set"
+        # the bound is a worst case (every bf16 rounding may flip); decisions
+        # must agree wherever it rules a flip out, and flips must be rare
+        clear = np.abs(zo - theta) > bnd
+        agree = (zo >= theta) == (zg >= np.float32(theta))
+        assert agree[clear].all()
+        assert (~agree).sum() <= 2 + 0.005 * len(agree)
+        _log(f"  step {t}: touched {len(zo)}, clear of theta {clear.mean():.3f}, "
+             f"max |dz| {np.max(np.abs(zg - zo)):.2e}, decisions differing {(~agree).sum()}")
+        st = g.last_stats()
+        assert st.screened == 1 and st.R_size == int(sel.sum())
+        o.finish_batch(Rg)
+        compare(o, g, f"step {t}")
