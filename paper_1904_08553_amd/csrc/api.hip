@@ -33,7 +33,7 @@ struct dc_ctx {
   DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
   DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
   DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
-  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc;
+  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc, bigrows;
   // learned screener: touched set, features, labels, scores
   DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
   bool have_scr = false;
@@ -221,7 +221,6 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
   int32_t* Cn = c->Cn.as<int32_t>();
   int32_t* al = c->al.as<int32_t>();
   int32_t* szl = c->szl.as<int32_t>();
-  DC_HIP(hipMemcpyAsync(Cn, Cl, size_t(c->n) * 4, hipMemcpyDeviceToDevice, st));
   int level = 0;
   c->trace.clear();
   dc_step_stats& S = c->stats;
@@ -240,10 +239,7 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
     coarsen(g, Cl, szl, al, cnt_in, minv_in, level == 0, c->n, c->map0.as<int32_t>(),
             c->cg[next], c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, st);
     g = c->cg[next].view();
-    iota_i32(Cl, g.n, st);
-    iota_i32(Cn, g.n, st);
-    DC_HIP(hipMemcpyAsync(al, g.k, size_t(g.n) * 4, hipMemcpyDeviceToDevice, st));
-    fill_i32(szl, 1, g.n, st);
+    start_level(Cl, Cn, al, szl, g.k, g.n, st);
     level++;
     if (stop) break;  // max_levels == 1: final = the identity partition of level 1
   }
@@ -276,7 +272,6 @@ void level0_labels(dc_ctx* c) {
   LevelView g{c->n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
               c->k0.as<int32_t>()};
   load_level0_partition(c);
-  DC_HIP(hipMemcpyAsync(c->Cn.p, c->Cl.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, st));
   Bins bins;
   make_bins(nullptr, c->n, g.off, bins, c->bins, st);
   (void)run_sweeps(c, g, nullptr, c->n, bins, 0, T, false);
@@ -325,10 +320,13 @@ void start_from_singletons(dc_ctx* c) {
   fill_i32(c->sz0.as<int32_t>(), 1, c->n, c->st);
 }
 
+// (Cl, Cn, al, szl) = (C, C, a0, sz0): the level-0 start partition.
 void load_level0_partition(dc_ctx* c) {
-  DC_HIP(hipMemcpyAsync(c->Cl.p, c->C.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
-  DC_HIP(hipMemcpyAsync(c->al.p, c->a0.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
-  DC_HIP(hipMemcpyAsync(c->szl.p, c->sz0.p, size_t(c->n) * 4, hipMemcpyDeviceToDevice, c->st));
+  int32_t* dst[4] = {c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
+                     c->szl.as<int32_t>()};
+  const int32_t* src[4] = {c->C.as<int32_t>(), c->C.as<int32_t>(), c->a0.as<int32_t>(),
+                           c->sz0.as<int32_t>()};
+  copy_i32(dst, src, 4, c->n, c->st);
 }
 
 dc_status status_from_flags(int32_t f) {
@@ -521,8 +519,10 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
   source_heads(ch_key, nch, n, crow_flag, st);
   scan_excl_i32(crow_flag, crow_pos, nch, crow_pos + nch, st);
   gather_sources(ch_key, crow_flag, crow_pos, nch, n, crows, st);
+  c->bigrows.ensure(size_t(nch + 2) * 4);
   merge_rows(off_old, adj_old, c->nnz, off_new, c->adj[nxt].as<int2>(), n, cptr, crows,
-             crow_pos + nch, nch, ch_key, ch_op, ch_w, cum_del, cum_new, st);
+             crow_pos + nch, nch, ch_key, ch_op, ch_w, cum_del, cum_new,
+             c->bigrows.as<int32_t>(), st);
   c->cur = nxt;
   c->nnz = nnz_new;
   c->two_m = two_m_new;

@@ -193,6 +193,12 @@ void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 void iota_i32(int32_t* p, int64_t n, hipStream_t st);
+// dst[j][i] = src[j][i] for j < count (<= 4) in one launch.
+void copy_i32(int32_t* const* dst, const int32_t* const* src, int count, int64_t n,
+              hipStream_t st);
+// A level's start partition: C[i] = Cn[i] = i, a[i] = k[i], size[i] = 1.
+void start_level(int32_t* C, int32_t* Cn, int32_t* a, int32_t* sz, const int32_t* k, int64_t n,
+                 hipStream_t st);
 
 // Scratch for the primitives (owned by the context).
 struct PrimScratch {

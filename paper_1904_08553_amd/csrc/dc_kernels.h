@@ -36,6 +36,24 @@ __device__ __forceinline__ void agg_put(AggLds& s, int key, long long v) {
   }
 }
 
+// Bounded insert-or-add: false when AGG_PROBES slots are taken by other
+// keys (the caller then updates global memory directly).  Lets one block's
+// table absorb many rows: updates of a large community, which would
+// serialise as same-address atomics from every block, arrive as one sum.
+constexpr int AGG_PROBES = 16;
+__device__ __forceinline__ bool agg_try(AggLds& s, int key, long long v) {
+  uint32_t h = hash_slot(key, AGG_SLOTS - 1);
+  for (int p = 0; p < AGG_PROBES; ++p) {
+    const int prev = atomicCAS(&s.keys[h], EMPTY_KEY, key);
+    if (prev == EMPTY_KEY || prev == key) {
+      atomicAdd((unsigned long long*)&s.vals[h], (unsigned long long)v);
+      return true;
+    }
+    h = (h + 1) & (AGG_SLOTS - 1);
+  }
+  return false;
+}
+
 // ---- graph.hip -----------------------------------------------------------
 enum EdgeFlag : int32_t { F_RANGE = 1, F_SELF = 2, F_WEIGHT = 4, F_DUP = 8, F_NO_EDGE = 16 };
 
@@ -114,12 +132,14 @@ void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk
 // Merge G_{t-1} with the sorted change list into G_t: rows without changes
 // are copied entry-parallel with their offset shift; the rows listed in
 // `rows` (device count nrows_dev, at most nrows_max) are merged one wave
-// per row.
+// per row, rows longer than 1024 entries one block per row.  big: scratch
+// of nrows_max + 1 ints (the long rows' list and its count).
 void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
                 const int32_t* off_new, int2* adj_new, int32_t n, const int32_t* cptr,
                 const int32_t* rows, const int32_t* nrows_dev, int64_t nrows_max,
                 const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ch_w,
-                const int32_t* cum_del, const int32_t* cum_new, hipStream_t st);
+                const int32_t* cum_del, const int32_t* cum_new, int32_t* big,
+                hipStream_t st);
 
 // Exact numerator pieces of Eq. (1) over a CSR with labels C:
 // *I += sum of intra-community entry weights; a_tmp (zeroed, n) receives

@@ -240,7 +240,10 @@ __global__ void k_combine_changes(
   }
 }
 
-// thread per row; label totals pre-combined per block
+// Thread per row: new degree, k += the row's weight change, and the label
+// totals a[C(u)] += the same change.  A block walks many rows and sums the
+// label changes in its LDS table first, so a large community receives one
+// update per block instead of one per row (same-address atomics serialise).
 __global__ void __launch_bounds__(TPB)
     k_row_changes(const int32_t* __restrict__ cptr,
                   const int32_t* __restrict__ ch_op,
@@ -250,24 +253,25 @@ __global__ void __launch_bounds__(TPB)
   __shared__ AggLds agg;
   agg_init(agg);
   __syncthreads();
-  int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (u < n) {
-    int32_t b = cptr[u], e = cptr[u + 1];
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n; u += stride) {
+    const int32_t b = cptr[u], e = cptr[u + 1];
     int32_t dd = 0, dk = 0;
     for (int32_t q = b; q < e; ++q) {
-      int32_t op = ch_op[q];
+      const int32_t op = ch_op[q];
       dd += op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
       dk += ch_dk[q];
     }
     new_deg[u] = off[u + 1] - off[u] + dd;
     if (dk != 0) {
       k[u] += dk;
-      agg_put(agg, C[u], dk);
+      const int c = C[u];
+      if (!agg_try(agg, c, dk)) atomicAdd(&a[c], dk);
     }
   }
   __syncthreads();
   for (int s = threadIdx.x; s < AGG_SLOTS; s += blockDim.x) {
-    int key = agg.keys[s];
+    const int key = agg.keys[s];
     if (key != EMPTY_KEY && agg.vals[s] != 0) atomicAdd(&a[key], int32_t(agg.vals[s]));
   }
 }
@@ -357,7 +361,7 @@ constexpr int BIG_CHANGES = 4096;   // changes staged in LDS per big row
 // cumulative shift before each change are staged in LDS, so every old entry
 // finds its place by a binary search on chip.
 __global__ void __launch_bounds__(TPB)
-    k_merge_big(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
+    k_merge_big(const int32_t* __restrict__ big,
                 const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
                 const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
                 const int32_t* __restrict__ cptr, const uint64_t* __restrict__ ch_key,
@@ -365,11 +369,10 @@ __global__ void __launch_bounds__(TPB)
                 const int32_t* __restrict__ cum_del, const int32_t* __restrict__ cum_new) {
   __shared__ int ldst[BIG_CHANGES];
   __shared__ int lsh[BIG_CHANGES + 1];
-  const int64_t nrows = *nrows_dev;
+  const int64_t nrows = big[0];  // rows longer than BIG_ROW, listed from big[1]
   for (int64_t p = blockIdx.x; p < nrows; p += gridDim.x) {
-    const int32_t row = rows[p];
+    const int32_t row = big[1 + p];
     const int32_t ob = off_old[row], oe = off_old[row + 1];
-    if (oe - ob <= BIG_ROW) continue;  // uniform over the block
     const int32_t nb = off_new[row], cb = cptr[row], ce = cptr[row + 1];
     const int32_t nchg = ce - cb;
     if (nchg > BIG_CHANGES) {
@@ -422,7 +425,7 @@ __global__ void k_merge_changed(const int32_t* __restrict__ rows, const int32_t*
                                 const int32_t* __restrict__ ch_op,
                                 const int32_t* __restrict__ ch_w,
                                 const int32_t* __restrict__ cum_del,
-                                const int32_t* __restrict__ cum_new) {
+                                const int32_t* __restrict__ cum_new, int32_t* big) {
   const int64_t nrows = *nrows_dev;
   const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / WAVE);
   const int lane = lane_id();
@@ -431,7 +434,10 @@ __global__ void k_merge_changed(const int32_t* __restrict__ rows, const int32_t*
     const int32_t row = rows[p];
     const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
     const int32_t cb = cptr[row], ce = cptr[row + 1];
-    if (oe - ob > BIG_ROW) continue;  // k_merge_big
+    if (oe - ob > BIG_ROW) {  // merged by k_merge_big
+      if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = row;
+      continue;
+    }
     if (int64_t(ce - cb) * ceil_div(oe - ob + 1, WAVE) > WAVE) {
       merge_row_search(row, n, adj_old, ob, oe, nb, cb, ce, adj_new, ch_key, ch_op, ch_w,
                        cum_del, cum_new);
@@ -647,7 +653,8 @@ void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk
                  const int32_t* off, int32_t n, int32_t* new_deg, int32_t* k,
                  const int32_t* C, int32_t* a, hipStream_t st) {
   if (n <= 0) return;
-  k_row_changes<<<ceil_div(n, TPB), TPB, 0, st>>>(cptr, ch_op, ch_dk, off, n, new_deg, k, C, a);
+  k_row_changes<<<grid_for(n, TPB, 512), TPB, 0, st>>>(cptr, ch_op, ch_dk, off, n, new_deg, k,
+                                                       C, a);
   DC_LAUNCH_CHECK();
 }
 
@@ -655,7 +662,8 @@ void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
                 const int32_t* off_new, int2* adj_new, int32_t n, const int32_t* cptr,
                 const int32_t* rows, const int32_t* nrows_dev, int64_t nrows_max,
                 const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ch_w,
-                const int32_t* cum_del, const int32_t* cum_new, hipStream_t st) {
+                const int32_t* cum_del, const int32_t* cum_new, int32_t* big,
+                hipStream_t st) {
   if (n <= 0) return;
   if (nnz_old > 0) {
     k_merge_copy<<<grid_for(ceil_div(n, WAVE) * WAVE, TPB, 16384), TPB, 0, st>>>(
@@ -663,12 +671,13 @@ void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
     DC_LAUNCH_CHECK();
   }
   if (nrows_max > 0) {
+    fill_i32(big, 0, 1, st);
     k_merge_changed<<<grid_for(nrows_max * WAVE, TPB, 16384), TPB, 0, st>>>(
         rows, nrows_dev, off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w,
-        cum_del, cum_new);
+        cum_del, cum_new, big);
     DC_LAUNCH_CHECK();
-    k_merge_big<<<2048, TPB, 0, st>>>(rows, nrows_dev, off_old, adj_old, off_new, adj_new, n,
-                                      cptr, ch_key, ch_op, ch_w, cum_del, cum_new);
+    k_merge_big<<<256, TPB, 0, st>>>(big, off_old, adj_old, off_new, adj_new, n, cptr, ch_key,
+                                     ch_op, ch_w, cum_del, cum_new);
     DC_LAUNCH_CHECK();
   }
 }

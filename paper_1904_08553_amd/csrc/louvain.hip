@@ -19,6 +19,17 @@ __device__ __forceinline__ long long pack2(int da, int dsz) {
   return (long long)dsz * 4294967296LL + (long long)da;
 }
 
+// dpack[X] += v and, on the label's first change of the sweep, X joins the
+// touched-label list.
+__device__ __forceinline__ void touch_label(int X, long long v, long long* dpack, int32_t* tflag,
+                                            int32_t* tlist, long long* stat) {
+  atomicAdd((unsigned long long*)&dpack[X], (unsigned long long)v);
+  if (atomicExch(&tflag[X], 1) == 0) {
+    const unsigned long long q = atomicAdd((unsigned long long*)&stat[ST_TOUCHED], 1ull);
+    tlist[q] = X;
+  }
+}
+
 __global__ void __launch_bounds__(TPB)
     k_apply_moves(const int32_t* __restrict__ list, int64_t cnt,
                   const int32_t* __restrict__ C, const int32_t* __restrict__ Cn,
@@ -31,6 +42,9 @@ __global__ void __launch_bounds__(TPB)
   const int wid = threadIdx.x / WAVE, lane = lane_id();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   const int64_t stride = int64_t(gridDim.x) * TPB;
+  // the block's label changes are summed in LDS over all its tiles, so a
+  // large community gets one update per block (see agg_try)
+  agg_init(agg);
   for (int64_t base = int64_t(blockIdx.x) * TPB; base < cnt; base += stride) {
     const int64_t p = base + threadIdx.x;
     int u = 0;
@@ -56,27 +70,19 @@ __global__ void __launch_bounds__(TPB)
       long long pos = bbase + __popcll(m & lt);
       for (int w = 0; w < wid; ++w) pos += wcount[w];
       movers[pos] = u;
-    }
-    agg_init(agg);
-    __syncthreads();
-    if (mover) {
       const int ku = k[u];
-      agg_put(agg, C[u], pack2(-ku, -1));
-      agg_put(agg, Cn[u], pack2(ku, 1));
+      const int from = C[u], to = Cn[u];
+      if (!agg_try(agg, from, pack2(-ku, -1))) touch_label(from, pack2(-ku, -1), dpack, tflag, tlist, stat);
+      if (!agg_try(agg, to, pack2(ku, 1))) touch_label(to, pack2(ku, 1), dpack, tflag, tlist, stat);
     }
-    __syncthreads();
-    for (int s = threadIdx.x; s < AGG_SLOTS; s += TPB) {
-      const int X = agg.keys[s];
-      if (X == EMPTY_KEY) continue;
-      const long long v = agg.vals[s];
-      if (v == 0) continue;
-      atomicAdd((unsigned long long*)&dpack[X], (unsigned long long)v);
-      if (atomicExch(&tflag[X], 1) == 0) {
-        unsigned long long q = atomicAdd((unsigned long long*)&stat[ST_TOUCHED], 1ull);
-        tlist[q] = X;
-      }
-    }
-    __syncthreads();
+    __syncthreads();  // wcount and btotal are rewritten by the next tile
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < AGG_SLOTS; s += TPB) {
+    const int X = agg.keys[s];
+    if (X == EMPTY_KEY) continue;
+    const long long v = agg.vals[s];
+    if (v != 0) touch_label(X, v, dpack, tflag, tlist, stat);
   }
 }
 
@@ -182,7 +188,7 @@ void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, in
                  long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
                  hipStream_t st) {
   const int64_t cnt = n_active > 0 ? n_active : 1;
-  k_apply_moves<<<grid_for(cnt, 2048), TPB, 0, st>>>(active, n_active, C, Cn, g.k, dpack, tflag,
+  k_apply_moves<<<grid_for(cnt, 512), TPB, 0, st>>>(active, n_active, C, Cn, g.k, dpack, tflag,
                                                      tlist, movers, stat);
   DC_LAUNCH_CHECK();
   k_delta_intra<<<grid_for(cnt * WAVE, 4096), TPB, 0, st>>>(movers, stat, g.off, g.adj, C, Cn,

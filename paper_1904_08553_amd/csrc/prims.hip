@@ -140,72 +140,90 @@ void scan_excl(const T* in, T* out, int64_t n, T* total, hipStream_t st) {
 constexpr int RS_THREADS = 256;
 constexpr int RS_ROUNDS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 2048 keys per block
-constexpr int RS_BINS = 256;
+constexpr int RS_MAX_DIGIT = 8;  // wider digits cost more per pass than they save
+constexpr int RS_BINS = 1 << RS_MAX_DIGIT;       // bins of the widest digit
 constexpr int RS_WAVES = RS_THREADS / WAVE;
 
+// Per-block digit histogram, written digit-major (hist[d * nblocks + block])
+// so one exclusive scan gives every (digit, block) its output offset.
 __global__ void __launch_bounds__(RS_THREADS)
-    k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+    k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, int bins,
                  int32_t* __restrict__ hist, int64_t nblocks) {
   __shared__ int32_t h[RS_BINS];
-  h[threadIdx.x] = 0;
+  for (int b = threadIdx.x; b < bins; b += RS_THREADS) h[b] = 0;
   __syncthreads();
-  int64_t base = int64_t(blockIdx.x) * RS_TILE;
-#pragma unroll
+  const uint64_t mask = uint64_t(bins - 1);
+  const int64_t base = int64_t(blockIdx.x) * RS_TILE;
+#pragma unroll 4
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    int64_t idx = base + int64_t(r) * RS_THREADS + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xff], 1);
+    const int64_t idx = base + int64_t(r) * RS_THREADS + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1);
   }
   __syncthreads();
-  hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
+  for (int b = threadIdx.x; b < bins; b += RS_THREADS)
+    hist[int64_t(b) * nblocks + blockIdx.x] = h[b];
 }
 
 // Stable scatter: elements are ranked in index order within the tile.  Each
 // round covers 256 consecutive elements; within a wave the rank among equal
-// digits comes from a ballot match, across waves from per-wave digit counts.
+// digits comes from a ballot match (one ballot per digit bit), across waves
+// from per-wave counts of the digits the round holds.
 __global__ void __launch_bounds__(RS_THREADS)
     k_radix_scatter(const uint64_t* __restrict__ kin,
                     const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                    uint32_t* __restrict__ vout, int64_t n, int shift,
+                    uint32_t* __restrict__ vout, int64_t n, int shift, int dbits,
                     const int32_t* __restrict__ hist_excl, int64_t nblocks) {
   __shared__ int32_t base_d[RS_BINS];
   __shared__ int32_t wcnt[RS_WAVES][RS_BINS];
   const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
-  base_d[t] = hist_excl[int64_t(t) * nblocks + blockIdx.x];
+  const int bins = 1 << dbits;
+  for (int b = t; b < bins; b += RS_THREADS) {
+    base_d[b] = hist_excl[int64_t(b) * nblocks + blockIdx.x];
 #pragma unroll
-  for (int w = 0; w < RS_WAVES; ++w) wcnt[w][t] = 0;
+    for (int w = 0; w < RS_WAVES; ++w) wcnt[w][b] = 0;
+  }
   __syncthreads();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
-  int64_t tile = int64_t(blockIdx.x) * RS_TILE;
+  const uint64_t mask = uint64_t(bins - 1);
+  const int64_t tile = int64_t(blockIdx.x) * RS_TILE;
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    int64_t idx = tile + int64_t(r) * RS_THREADS + t;
-    bool valid = idx < n;
-    uint64_t key = valid ? kin[idx] : 0;
-    uint32_t val = valid ? vin[idx] : 0;
-    int d = int((key >> shift) & 0xff);
+    const int64_t idx = tile + int64_t(r) * RS_THREADS + t;
+    const bool valid = idx < n;
+    const uint64_t key = valid ? kin[idx] : 0;
+    const uint32_t val = valid ? vin[idx] : 0;
+    const int d = int((key >> shift) & mask);
     uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      bool bit = (d >> b) & 1;
-      uint64_t bb = __ballot(valid && bit);
+    for (int b = 0; b < dbits; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t bb = __ballot(valid && bit);
       m &= bit ? bb : ~bb;
     }
-    int rank = __popcll(m & lt);
-    if (valid && rank == 0) wcnt[wid][d] = __popcll(m);
+    const int rank = __popcll(m & lt);
+    const bool leader = valid && rank == 0;
+    if (leader) wcnt[wid][d] = __popcll(m);
     __syncthreads();
+    int pos = 0;
     if (valid) {
-      int pos = base_d[d] + rank;
+      pos = base_d[d] + rank;
       for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
       kout[pos] = key;
       vout[pos] = val;
     }
     __syncthreads();
-    int add = 0;
+    // advance the bases of the digits this round held (by their leaders in
+    // wave 0 order: a digit's first holder over all waves adds the total)
+    if (leader) {
+      bool first = true;
+      for (int w = 0; w < wid; ++w) first = first && wcnt[w][d] == 0;
+      if (first) {
+        int add = 0;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) {
-      add += wcnt[w][t];
-      wcnt[w][t] = 0;
+        for (int w = 0; w < RS_WAVES; ++w) add += wcnt[w][d];
+        base_d[d] += add;
+      }
     }
-    base_d[t] += add;
+    __syncthreads();
+    if (leader) wcnt[wid][d] = 0;
     __syncthreads();
   }
 }
@@ -221,6 +239,28 @@ __global__ void k_iota(int32_t* p, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (; i < n; i += stride) p[i] = int32_t(i);
+}
+
+struct Copy4 {
+  int32_t* dst[4];
+  const int32_t* src[4];
+};
+
+__global__ void k_copy_i32(Copy4 c, int count, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    for (int j = 0; j < count; ++j) c.dst[j][i] = c.src[j][i];
+}
+
+__global__ void k_start_level(int32_t* C, int32_t* Cn, int32_t* a, int32_t* sz,
+                              const int32_t* __restrict__ k, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    C[i] = int32_t(i);
+    Cn[i] = int32_t(i);
+    a[i] = k[i];
+    sz[i] = 1;
+  }
 }
 
 inline int grid_for(int64_t n, int threads = 256) {
@@ -244,19 +284,22 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total,
 void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                       int64_t n, int bits, hipStream_t st) {
   if (n <= 1 || bits <= 0) return;
-  int passes = (bits + 7) / 8;
-  int64_t nb = ceil_div(n, RS_TILE);
+  // fewest passes with digits of at most RS_MAX_DIGIT bits, equal widths
+  const int passes = (bits + RS_MAX_DIGIT - 1) / RS_MAX_DIGIT;
+  const int dbits = (bits + passes - 1) / passes;
+  const int bins = 1 << dbits;
+  const int64_t nb = ceil_div(n, RS_TILE);
   DBuf& hb = prim_scratch().sort_hist;
-  hb.ensure(size_t(nb) * RS_BINS * sizeof(int32_t));
+  hb.ensure(size_t(nb) * size_t(bins) * sizeof(int32_t));
   int32_t* hist = hb.as<int32_t>();
   uint64_t *ka = k0, *kb = k1;
   uint32_t *va = v0, *vb = v1;
   for (int p = 0; p < passes; ++p) {
-    int shift = 8 * p;
-    k_radix_hist<<<nb, RS_THREADS, 0, st>>>(ka, n, shift, hist, nb);
+    const int shift = dbits * p;
+    k_radix_hist<<<nb, RS_THREADS, 0, st>>>(ka, n, shift, bins, hist, nb);
     DC_LAUNCH_CHECK();
-    scan_excl_i32(hist, hist, nb * RS_BINS, nullptr, st);
-    k_radix_scatter<<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, hist, nb);
+    scan_excl_i32(hist, hist, nb * bins, nullptr, st);
+    k_radix_scatter<<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, dbits, hist, nb);
     DC_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);
@@ -282,6 +325,25 @@ void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st) {
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   k_fill<uint8_t><<<grid_for(n), 256, 0, st>>>(p, v, n);
+  DC_LAUNCH_CHECK();
+}
+
+void copy_i32(int32_t* const* dst, const int32_t* const* src, int count, int64_t n,
+              hipStream_t st) {
+  if (n <= 0 || count <= 0) return;
+  Copy4 c{};
+  for (int j = 0; j < count && j < 4; ++j) {
+    c.dst[j] = dst[j];
+    c.src[j] = src[j];
+  }
+  k_copy_i32<<<grid_for(n), 256, 0, st>>>(c, count < 4 ? count : 4, n);
+  DC_LAUNCH_CHECK();
+}
+
+void start_level(int32_t* C, int32_t* Cn, int32_t* a, int32_t* sz, const int32_t* k, int64_t n,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  k_start_level<<<grid_for(n), 256, 0, st>>>(C, Cn, a, sz, k, n);
   DC_LAUNCH_CHECK();
 }
 

@@ -67,11 +67,15 @@ class EdgeSet:
         return len(self.keys)
 
     def contains(self, k):
+        k = np.asarray(k, np.int64)
         if len(self.keys) == 0:
             return np.zeros(len(k), bool)
-        pos = np.searchsorted(self.keys, k)
-        pos = np.minimum(pos, len(self.keys) - 1)
-        return self.keys[pos] == k
+        order = np.argsort(k, kind="stable")  # sorted queries search far faster
+        ks = k[order]
+        pos = np.minimum(np.searchsorted(self.keys, ks), len(self.keys) - 1)
+        out = np.empty(len(k), bool)
+        out[order] = self.keys[pos] == ks
+        return out
 
     def apply(self, b: Batch):
         if len(b.del_u):
@@ -147,9 +151,12 @@ class PlantedPartition:
     def graph(self):
         rng = _rng(self.seed, 2)
         keys = []
+        tri = {}
         for b in range(self.blocks):
             mem = self.members[b]
-            iu, ju = np.triu_indices(len(mem), 1)
+            if len(mem) not in tri:
+                tri[len(mem)] = np.triu_indices(len(mem), 1)
+            iu, ju = tri[len(mem)]
             m = rng.random(len(iu)) < self.p_in
             keys.append(_key(mem[iu[m]], mem[ju[m]]))
         sizes = np.array([len(m) for m in self.members], np.int64)
@@ -176,10 +183,11 @@ class PlantedPartition:
         ok = self.block_of[u] != self.block_of[v]
         return u[ok], v[ok]
 
-    def batches(self, steps=4, n_ins=500, intra_frac=0.7, n_del=200, weight=None):
+    def batches(self, steps=4, n_ins=500, intra_frac=0.7, n_del=200, weight=None, graph=None):
         """Per step: ``n_ins`` insertions of non-edges (``intra_frac`` inside
-        a block) and ``n_del`` deletions uniform over the current edges."""
-        u, v, w = self.graph()
+        a block) and ``n_del`` deletions uniform over the current edges.
+        ``graph``: the result of ``graph()`` when already drawn."""
+        u, v, w = self.graph() if graph is None else graph
         es = EdgeSet.from_edges(u, v, w)
         out = []
         for t in range(steps):
@@ -367,6 +375,27 @@ def temporal_stream(n=8_000_000, events=63_000_000, steps=12, ins_frac=0.85,
 
 # ---------------------------------------------------------------------------
 # Small random dynamic graphs for exhaustive checks.
+
+
+def screener_graph(seed, n=None, n_lo=100_000, n_hi=1_000_000, steps=4, ins_frac=0.073,
+                   del_frac=0.029, intra_frac=0.7):
+    """A training or evaluation graph of the learned screener: planted
+    partition with 100-vertex blocks (expected intra-community degree 4.95,
+    inter-community degree 1.9), n log-uniform in [n_lo, n_hi] unless given,
+    unit weights, and ``steps`` batches of ``ins_frac`` (70% intra-community)
+    insertions and ``del_frac`` deletions of the initial edge count.
+    Returns (n, (u, v, w), batches)."""
+    if n is None:
+        r = _rng(seed, 41)
+        n = int(round(np.exp(r.uniform(np.log(n_lo), np.log(n_hi)))))
+    n = max(200, (n // 100) * 100)
+    pp = PlantedPartition(n=n, blocks=n // 100, p_in=0.05, p_out=1.9 / (n - 100), seed=seed)
+    u, v, w = pp.graph()
+    m = len(u)
+    (u, v, w), batches = pp.batches(steps=steps, n_ins=int(round(ins_frac * m)),
+                                    intra_frac=intra_frac, n_del=int(round(del_frac * m)),
+                                    graph=(u, v, w))
+    return n, (u, v, w), batches
 
 
 def random_dynamic(n, m, steps, n_add, n_del, seed, wmax=3):
