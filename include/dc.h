@@ -50,7 +50,9 @@ enum {
   DC_E_OVERFLOW = -7,  /* 2m would reach 2^31                              */
   DC_E_OOM = -8,       /* device allocation failed                         */
   DC_E_DEVICE = -9,    /* a HIP call failed; the context is poisoned       */
-  DC_E_STATE = -10     /* the context was poisoned by an earlier failure   */
+  DC_E_STATE = -10,    /* the context was poisoned by an earlier failure   */
+  DC_PENDING = 1       /* dc_server_poll: the batch has not finished (not
+                          an error)                                       */
 };
 
 /* How the first level chooses its start partition and its active set. */
@@ -204,6 +206,75 @@ dc_status dc_num_entries(dc_ctx* ctx, int64_t* nnz);
 dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w);
 
 void dc_destroy(dc_ctx* ctx);
+
+/* Checkpoint of a context: G_t as a CSR in host memory (as dc_export_csr,
+ * sizes from dc_num_entries) and C_t[n]. */
+dc_status dc_export_state(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w,
+                          int32_t* C);
+
+/* A context resumed from a checkpoint (host memory): G_t as a CSR with rows
+ * sorted by neighbour, symmetric, no self-loops, weights >= 1, 2m < 2^31;
+ * C[n] a canonical labelling (C[C[v]] == C[v] <= v).  No levels run; the
+ * next dc_apply_batch continues from (G_t, C_t) as the original context
+ * would.  Errors: ARG (malformed checkpoint), OVERFLOW, OOM, DEVICE. */
+dc_status dc_init_from_state(dc_ctx** out, int32_t n, const int64_t* off,
+                             const int32_t* col, const int32_t* w,
+                             const int32_t* C, const dc_options* opt);
+
+/* ---- Serving many dynamic graphs (an extension: the paper treats one) ----
+ *
+ * A server keeps many graphs' state resident on one GPU and applies the
+ * batches submitted for them with continuous batching: a worker thread
+ * takes, round after round, the oldest waiting batch of up to max_inflight
+ * distinct graphs (each graph's batches in submission order); batches that
+ * arrive meanwhile join a later round.  In a round the graphs' level-0
+ * sweeps run merged: one evaluation launch per row-length bin covers every
+ * graph still sweeping (a graph leaves when its level stops), so the
+ * graphs' work shares the device.  Each result equals that of the graph's
+ * own context run alone.  Admission: a graph's device footprint (bytes of
+ * all its buffers) counts against budget_bytes while resident; to admit a
+ * graph the server moves idle graphs' state to host memory (least recently
+ * used first) and brings it back when their next batch runs; a batch whose
+ * graph cannot fit yet waits.  budget_bytes <= 0: no limit.  The options
+ * (stream ignored: the server owns one stream) apply to every graph. */
+typedef struct dc_server dc_server;
+
+typedef struct dc_server_stats {
+  int64_t graphs;          /* graphs added                                    */
+  int64_t batches;         /* batches finished                                */
+  int64_t rounds;          /* rounds run                                      */
+  int64_t merged_rounds;   /* rounds with more than one graph                 */
+  int64_t merged_graphs;   /* graphs summed over rounds                       */
+  int64_t evictions;       /* graph states moved to host memory               */
+  int64_t restores;        /* graph states brought back                       */
+  int64_t deferred;        /* times a batch waited for memory                 */
+  int64_t resident_bytes;  /* device bytes of resident graphs now             */
+  int64_t peak_resident_bytes;
+  int64_t reserved[6];
+} dc_server_stats;
+
+dc_status dc_server_create(dc_server** out, const dc_options* opt,
+                           int64_t budget_bytes, int32_t max_inflight);
+/* Adds a graph: builds G_1 and runs Static(G_1) as dc_init; blocks until
+ * done; *gid receives its id (0, 1, ...).  Errors as dc_init; OOM when the
+ * graph alone exceeds the budget. */
+dc_status dc_server_add_graph(dc_server* s, int32_t n, const dc_edges* g1,
+                              int32_t* gid);
+/* Queues a batch (copied) for graph gid; arrival_ns is the caller's
+ * CLOCK_MONOTONIC time of arrival (for latency); *ticket identifies it. */
+dc_status dc_server_submit(dc_server* s, int32_t gid, const dc_edges* add,
+                           const dc_edges* del, int64_t arrival_ns,
+                           int64_t* ticket);
+/* Result of a batch: DC_PENDING while it has not finished (wait = 0), else
+ * the batch's own status; on DC_OK, C_out[n] (host, nullable) receives
+ * C_t, stats (nullable) its statistics, times[3] (nullable) its arrival,
+ * start and finish (CLOCK_MONOTONIC ns).  A finished ticket is released by
+ * this call. */
+dc_status dc_server_poll(dc_server* s, int64_t ticket, int32_t wait,
+                         int32_t* C_out, dc_step_stats* stats, int64_t* times);
+dc_status dc_server_stats_get(dc_server* s, dc_server_stats* out);
+/* Finishes the queued batches, then frees everything. */
+void dc_server_destroy(dc_server* s);
 
 /* ---- Learned screener (an extension; the paper has no learned part) ----
  *

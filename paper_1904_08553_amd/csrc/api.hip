@@ -6,56 +6,17 @@
 // for DELTA, all vertices for ALL and STATIC), and the levels of Alg. 1 run
 // with level 0 restricted to R_t.  All work goes to the caller's stream; the
 // host waits only where a size or a convergence decision is needed.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "dc_louvain.h"
-#include "learned.h"
+#include "ctx.h"
 
 using namespace dc;
 
-struct dc_ctx {
-  int32_t n = 0;
-  dc_options opt{};
-  hipStream_t st = nullptr;
-  bool poisoned = false;
-  int64_t two_m = 0;
-  int64_t nnz = 0;
-  int cur = 0;
-  DBuf off[2], adj[2];
-  DBuf k0, C, a0, sz0;
-  // batch
-  DBuf in_au, in_av, in_aw, in_du, in_dv;
-  DBuf dkeys, dvals, dk1, dv1, dw_old;
-  DBuf akeys, avals, ak1, av1, aheads, apos, ukeys, uw;
-  DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
-  DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
-  DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
-  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc, bigrows;
-  // learned screener: touched set, features, labels, scores
-  DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
-  bool have_scr = false;
-  float theta = 0.f;
-  int64_t T_count = 0;
-  bool have_y = false, have_logits = false;
-  // levels
-  DBuf Cl, Cn, al, szl, dpack, lflag, tlist, movers, map0, cnt[2], minv[2], lab, cntf;
-  CoarseGraph cg[2];
-  DBuf stat;
-  long long* hstat = nullptr;  // pinned mirror of the status block
-  void* hbuf = nullptr;        // pinned scratch for the kernels' host reads
-  BinScratch bins;
-  CoarsenScratch cs;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::vector<dc_sweep_rec> trace;
-  dc_step_stats stats{};
-  int64_t R_count = 0;
-  bool have_R_all = true;
-};
-
-namespace {
+namespace dc_core {
 
 thread_local std::string g_last_error;
 
@@ -139,46 +100,23 @@ void read_stat(dc_ctx* c) {
   DC_HIP(hipStreamSynchronize(c->st));
 }
 
-// Synchronous sweeps of one level over the binned active set (Alg. 1 inner
-// loop); returns the level's total exact gain.  record: trace records,
-// statistics and timing of the call.
-long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t nact,
-                     const Bins& bins, int level, long long T, bool record) {
-  hipStream_t st = c->st;
-  const long long two_m = c->two_m;
-  int32_t* Cl = c->Cl.as<int32_t>();
-  int32_t* Cn = c->Cn.as<int32_t>();
-  int32_t* al = c->al.as<int32_t>();
-  int32_t* szl = c->szl.as<int32_t>();
-  dc_step_stats& S = c->stats;
-  int64_t n_eval = 0;
-  long long vol_eval = 0;
-  for (int q = 0; q < NBINS; ++q) {
-    n_eval += bins.n[q];
-    vol_eval += bins.vol[q];
-  }
-  long long level_gain = 0;
-  for (int s = 0; s < c->opt.max_sweeps; ++s) {
-    sweep_reset(c->stat.as<long long>(), st);
-    const bool timed = record && c->opt.timing && bins.n[TIMED_BIN] > 0;
-    sweep_eval(g, Cl, Cn, al, szl, two_m, c->opt.singleton_guard, bins,
-               c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,
-               timed ? c->ev1 : nullptr);
-    sweep_apply(g, act, nact, Cl, Cn, al, szl, two_m, c->movers.as<int32_t>(),
-                c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
-                c->stat.as<long long>(), st);
-    read_stat(c);
-    const long long moves = c->hstat[ST_MOVES], dN = c->hstat[ST_DN];
-    if (!record) {
-      if (moves == 0 || dN < 0) break;
-      level_gain += dN;
-      if (dN <= T) break;
-      continue;
+// Bookkeeping of one finished sweep whose status block is in c->hstat: the
+// trace record and statistics (record), the level's gain, and whether the
+// level stops (no move, a reverted sweep, a gain of at most T, or the sweep
+// limit).  timed_ms >= 0: device time of the timed launch of this sweep.
+bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& bins,
+                   long long T, bool record, float timed_ms, long long& level_gain) {
+  const long long moves = c->hstat[ST_MOVES], dN = c->hstat[ST_DN];
+  if (record) {
+    dc_step_stats& S = c->stats;
+    int64_t n_eval = 0;
+    long long vol_eval = 0;
+    for (int q = 0; q < NBINS; ++q) {
+      n_eval += bins.n[q];
+      vol_eval += bins.vol[q];
     }
-    if (timed) {
-      float ms = 0;
-      DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-      S.ms_sweep_kernel += ms;
+    if (timed_ms >= 0.f) {
+      S.ms_sweep_kernel += timed_ms;
       S.sweep_launches += 1;
       // algorithmic bytes of the timed launch: 12 B per adjacency entry
       // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
@@ -191,8 +129,8 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
     r.n_level = g.n;
     r.n_active = int32_t(n_eval);
     r.nnz_level = g.nnz;
-    r.moves = c->hstat[ST_MOVES];
-    r.dN = c->hstat[ST_DN];
+    r.moves = moves;
+    r.dN = dN;
     r.kept = int32_t(c->hstat[ST_KEEP]);
     c->trace.push_back(r);
     S.vertex_evals += n_eval;
@@ -201,35 +139,74 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
       S.level0_active += n_eval;
       S.level0_volume += vol_eval;
     }
-    if (r.moves == 0 || r.dN < 0) break;
-    S.moves += r.moves;
-    level_gain += r.dN;
-    if (r.dN <= T) break;
+    if (moves > 0 && dN >= 0) S.moves += moves;
+  }
+  if (moves == 0 || dN < 0) return true;
+  level_gain += dN;
+  return dN <= T || s + 1 >= c->opt.max_sweeps;
+}
+
+// Synchronous sweeps of one level over the binned active set (Alg. 1 inner
+// loop); returns the level's total exact gain.  record: trace records,
+// statistics and timing of the call.
+long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t nact,
+                     const Bins& bins, int level, long long T, bool record) {
+  hipStream_t st = c->st;
+  long long level_gain = 0;
+  for (int s = 0; s < c->opt.max_sweeps; ++s) {
+    sweep_reset(c->stat.as<long long>(), st);
+    const bool timed = record && c->opt.timing && bins.n[TIMED_BIN] > 0;
+    sweep_eval(g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
+               c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, bins,
+               c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,
+               timed ? c->ev1 : nullptr);
+    sweep_apply(g, act, nact, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
+                c->szl.as<int32_t>(), c->two_m, c->movers.as<int32_t>(),
+                c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
+                c->stat.as<long long>(), st);
+    read_stat(c);
+    float ms = -1.f;
+    if (timed) DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    if (sweep_account(c, g, level, s, bins, T, record, ms, level_gain)) break;
   }
   return level_gain;
 }
 
-// Alg. 1 with level 0 visiting `active` (null = every vertex).  The level-0
-// partition is (Cl, al, szl), prepared by the caller.
-void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
+// Alg. 1 in two parts around the level-0 sweeps, so that several graphs can
+// run their level-0 sweeps together: levels_begin bins R_t for level 0
+// (null = every vertex) over the level-0 partition (Cl, al, szl) the caller
+// prepared; levels_finish coarsens, runs the upper levels and writes the
+// canonical labels, the totals and N.
+
+void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& L) {
+  const long long two_m = c->two_m;
+  L.T = c->opt.tau_den > 0 ? (two_m * two_m) / c->opt.tau_den : 0;
+  L.g = LevelView{c->n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
+                  c->k0.as<int32_t>()};
+  L.act = active;
+  L.nact = n_active;
+  c->trace.clear();
+  make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st);
+}
+
+void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
   hipStream_t st = c->st;
   const long long two_m = c->two_m;
-  const long long T = c->opt.tau_den > 0 ? (two_m * two_m) / c->opt.tau_den : 0;
-  LevelView g{c->n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
-              c->k0.as<int32_t>()};
+  const long long T = L.T;
+  LevelView g = L.g;
   int32_t* Cl = c->Cl.as<int32_t>();
   int32_t* Cn = c->Cn.as<int32_t>();
   int32_t* al = c->al.as<int32_t>();
   int32_t* szl = c->szl.as<int32_t>();
-  int level = 0;
-  c->trace.clear();
   dc_step_stats& S = c->stats;
+  int level = 0;
+  long long level_gain = level0_gain;
   while (true) {
-    const int32_t* act = level == 0 ? active : nullptr;
-    const int64_t nact = level == 0 ? n_active : g.n;
-    Bins bins;
-    make_bins(act, nact, g.off, bins, c->bins, st);
-    const long long level_gain = run_sweeps(c, g, act, nact, bins, level, T, true);
+    if (level > 0) {
+      Bins bins;
+      make_bins(nullptr, g.n, g.off, bins, c->bins, st);
+      level_gain = run_sweeps(c, g, nullptr, g.n, bins, level, T, true);
+    }
     const bool stop = (level + 1 >= c->opt.max_levels) || (level >= 1 && level_gain <= T);
     if (stop && level >= 1) break;
     // coarsen (after level 0 always: it also yields the canonical labels)
@@ -259,6 +236,15 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
   S.N = two_m * c->hstat[ST_I] - c->hstat[ST_S];
   S.two_m = two_m;
   S.q = two_m == 0 ? 0.0 : double(S.N) / (double(two_m) * double(two_m));
+}
+
+// Alg. 1 with level 0 visiting `active` (null = every vertex).  The level-0
+// partition is (Cl, al, szl), prepared by the caller.
+void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
+  LevelRun L;
+  levels_begin(c, active, n_active, L);
+  const long long gain0 = run_sweeps(c, L.g, L.act, L.nact, L.bins, 0, L.T, true);
+  levels_finish(c, L, gain0);
 }
 
 void load_level0_partition(dc_ctx* c);
@@ -398,8 +384,11 @@ dc_status do_init(dc_ctx* c, const dc_edges* g1) {
   return DC_OK;
 }
 
-dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t* C_out,
-                   int32_t out_on_device, dc_step_stats* out_stats) {
+// First part of a time step: validate, merge, choose R_t; on success the
+// level-0 partition is loaded and *act / *nact give the level-0 active set
+// (null = every vertex).
+dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const int32_t** act,
+                      int64_t* nact) {
   hipStream_t st = c->st;
   const int32_t n = c->n;
   long long* stat = c->stat.as<long long>();
@@ -617,20 +606,35 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
   if (mode == DC_MODE_DELTA || mode == DC_MODE_LEARNED) {
     c->have_R_all = false;
     load_level0_partition(c);
-    run_levels(c, c->Rlist.as<int32_t>(), c->R_count);
+    *act = c->Rlist.as<int32_t>();
+    *nact = c->R_count;
   } else {
     if (mode == DC_MODE_STATIC) start_from_singletons(c);
     load_level0_partition(c);
     S.R_size = n;
     c->have_R_all = true;
-    run_levels(c, nullptr, n);
+    *act = nullptr;
+    *nact = n;
   }
-  if (C_out) {
-    DC_HIP(hipMemcpyAsync(C_out, c->C.p, size_t(n) * 4,
-                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-    DC_HIP(hipStreamSynchronize(st));
-  }
-  if (out_stats) *out_stats = S;
+  return DC_OK;
+}
+
+// Last part of a time step: C_t to the caller (device or host memory).
+void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device) {
+  if (!C_out) return;
+  DC_HIP(hipMemcpyAsync(C_out, c->C.p, size_t(c->n) * 4,
+                        out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+  DC_HIP(hipStreamSynchronize(c->st));
+}
+
+dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t* C_out,
+                   int32_t out_on_device) {
+  const int32_t* act = nullptr;
+  int64_t nact = 0;
+  const dc_status s = apply_front(c, add, del, &act, &nact);
+  if (s != DC_OK) return s;
+  run_levels(c, act, nact);
+  apply_output(c, C_out, out_on_device);
   return DC_OK;
 }
 
@@ -669,7 +673,182 @@ void destroy_ctx(dc_ctx* c) {
   delete c;
 }
 
-}  // namespace
+
+// Every device buffer of a context (the screener weights excepted: small,
+// and kept across eviction).
+template <class F>
+void for_each_buf(dc_ctx* c, F&& f) {
+  for (DBuf* b : {&c->off[0], &c->off[1], &c->adj[0], &c->adj[1], &c->k0, &c->C, &c->a0,
+                  &c->sz0, &c->in_au, &c->in_av, &c->in_aw, &c->in_du, &c->in_dv, &c->dkeys,
+                  &c->dvals, &c->dk1, &c->dv1, &c->dw_old, &c->akeys, &c->avals, &c->ak1,
+                  &c->av1, &c->aheads, &c->apos, &c->ukeys, &c->uw, &c->rkeys, &c->rvals,
+                  &c->rk1, &c->rv1, &c->rheads, &c->rpos, &c->ch_key, &c->ch_op, &c->ch_w,
+                  &c->ch_dk, &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->cptr,
+                  &c->new_deg, &c->ins_flag, &c->ins_pos, &c->ins_keys, &c->src_flag,
+                  &c->src_pos, &c->src_list, &c->dflag, &c->dpos, &c->dlist, &c->R, &c->cflag,
+                  &c->rflag, &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end, &c->chsrc,
+                  &c->bigrows, &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
+                  &c->f_g1, &c->f_g2, &c->X, &c->y, &c->logits, &c->Cl, &c->Cn, &c->al,
+                  &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],
+                  &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,
+                  &c->cg[0].off, &c->cg[0].adj, &c->cg[0].k, &c->cg[1].off, &c->cg[1].adj,
+                  &c->cg[1].k, &c->bins.lists, &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
+                  &c->bins.tab_off, &c->bins.gkeys, &c->bins.gvals, &c->cs.flag, &c->cs.rank,
+                  &c->cs.keys0, &c->cs.keys1, &c->cs.vals0, &c->cs.vals1, &c->cs.cntr,
+                  &c->cs.mstart, &c->cs.labof, &c->cs.mdeg, &c->cs.mvol, &c->cs.chead,
+                  &c->cs.cpos, &c->cs.chunks, &c->cs.mcnt, &c->cs.pk0, &c->cs.pk1, &c->cs.pv0,
+                  &c->cs.pv1, &c->cs.ph, &c->cs.pp, &c->cs.pS, &c->cs.pcnt, &c->cs.hidx,
+                  &c->cs.ukey, &c->cs.rc})
+    f(*b);
+}
+
+int64_t ctx_footprint(const dc_ctx* c) {
+  int64_t t = int64_t(c->scr_wq.bytes);
+  for_each_buf(const_cast<dc_ctx*>(c), [&](DBuf& b) { t += int64_t(b.bytes); });
+  return t;
+}
+
+void ctx_evict(dc_ctx* c, SavedState& s) {
+  hipStream_t st = c->st;
+  const size_t n = size_t(c->n);
+  s.nnz = c->nnz;
+  s.two_m = c->two_m;
+  s.off.resize(n + 1);
+  s.adj.resize(size_t(c->nnz));
+  s.k.resize(n);
+  s.C.resize(n);
+  s.a.resize(n);
+  s.sz.resize(n);
+  DC_HIP(hipMemcpyAsync(s.off.data(), c->off[c->cur].p, (n + 1) * 4, hipMemcpyDeviceToHost, st));
+  if (c->nnz > 0)
+    DC_HIP(hipMemcpyAsync(s.adj.data(), c->adj[c->cur].p, size_t(c->nnz) * 8,
+                          hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(s.k.data(), c->k0.p, n * 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(s.C.data(), c->C.p, n * 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(s.a.data(), c->a0.p, n * 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(s.sz.data(), c->sz0.p, n * 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  for_each_buf(c, [](DBuf& b) { b.release(); });
+}
+
+void ensure_vertex_state(dc_ctx* c);
+
+void ctx_restore(dc_ctx* c, const SavedState& s) {
+  hipStream_t st = c->st;
+  const size_t n = size_t(c->n);
+  ensure_vertex_state(c);
+  c->cur = 0;
+  c->nnz = s.nnz;
+  c->two_m = s.two_m;
+  c->off[0].ensure((n + 1) * 4);
+  c->adj[0].ensure(size_t(s.nnz + 1) * 8);
+  DC_HIP(hipMemcpyAsync(c->off[0].p, s.off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
+  if (s.nnz > 0)
+    DC_HIP(hipMemcpyAsync(c->adj[0].p, s.adj.data(), size_t(s.nnz) * 8, hipMemcpyHostToDevice,
+                          st));
+  DC_HIP(hipMemcpyAsync(c->k0.p, s.k.data(), n * 4, hipMemcpyHostToDevice, st));
+  DC_HIP(hipMemcpyAsync(c->C.p, s.C.data(), n * 4, hipMemcpyHostToDevice, st));
+  DC_HIP(hipMemcpyAsync(c->a0.p, s.a.data(), n * 4, hipMemcpyHostToDevice, st));
+  DC_HIP(hipMemcpyAsync(c->sz0.p, s.sz.data(), n * 4, hipMemcpyHostToDevice, st));
+  DC_HIP(hipStreamSynchronize(st));
+}
+
+void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, MergeScratch& X) {
+  if (m <= 0) return;
+  hipStream_t st = cs[0]->st;
+  for (int j = 1; j < m; ++j)
+    if (cs[j]->st != st) throw std::runtime_error("merged sweeps need one stream");
+  if (m > X.cap) throw std::runtime_error("merge scratch too small");
+  std::vector<const Bins*> bl(static_cast<size_t>(m));
+  for (int j = 0; j < m; ++j) bl[size_t(j)] = &Ls[j].bins;
+  build_multi_bins(bl.data(), m, X.mb, X.hsegs, X.segs, st);
+  X.descs.ensure(size_t(m) * sizeof(EvalArgs));
+  X.done.ensure(size_t(m) * 4);
+  for (int j = 0; j < m; ++j) {
+    dc_ctx* c = cs[j];
+    X.hdescs[j] = sweep_args(Ls[j].g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
+                             c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m,
+                             c->opt.singleton_guard);
+    X.hdone[j] = 0;
+    gains[j] = 0;
+  }
+  DC_HIP(hipMemcpyAsync(X.descs.p, X.hdescs, size_t(m) * sizeof(EvalArgs),
+                        hipMemcpyHostToDevice, st));
+  std::vector<int> sweep(static_cast<size_t>(m), 0);
+  int live = m;
+  while (live > 0) {
+    // the flags were last read by the previous round, which has completed
+    DC_HIP(hipMemcpyAsync(X.done.p, X.hdone, size_t(m) * 4, hipMemcpyHostToDevice, st));
+    for (int j = 0; j < m; ++j)
+      if (!X.hdone[j]) sweep_reset(cs[j]->stat.as<long long>(), st);
+    sweep_eval_multi(X.descs.as<EvalArgs>(), X.done.as<int32_t>(), X.mb, st);
+    for (int j = 0; j < m; ++j) {
+      if (X.hdone[j]) continue;
+      dc_ctx* c = cs[j];
+      const LevelRun& L = Ls[j];
+      sweep_eval_bin_g(L.g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
+                       c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, L.bins, st);
+      sweep_apply(L.g, L.act, L.nact, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
+                  c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m, c->movers.as<int32_t>(),
+                  c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
+                  c->stat.as<long long>(), st);
+      DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, st));
+    }
+    DC_HIP(hipStreamSynchronize(st));  // one wait for every graph of the round
+    for (int j = 0; j < m; ++j) {
+      if (X.hdone[j]) continue;
+      if (sweep_account(cs[j], Ls[j].g, 0, sweep[size_t(j)], Ls[j].bins, Ls[j].T, true, -1.f,
+                        gains[j])) {
+        X.hdone[j] = 1;
+        --live;
+      }
+      sweep[size_t(j)]++;
+    }
+  }
+}
+
+// A new context with its pinned host buffers and events; `build` fills its
+// device state.  On failure everything is released.
+template <class F>
+dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) {
+  *out = nullptr;
+  dc_ctx* c = new (std::nothrow) dc_ctx();
+  if (!c) return DC_E_OOM;
+  c->n = n;
+  c->opt = *opt;
+  c->st = static_cast<hipStream_t>(opt->stream);
+  dc_status s;
+  try {
+    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
+    DC_HIP(hipHostMalloc(&c->hbuf, 64));
+    DC_HIP(hipHostMalloc(&c->bins.host, 256));
+    DC_HIP(hipHostMalloc(&c->cs.host, 64));
+    DC_HIP(hipEventCreate(&c->ev0));
+    DC_HIP(hipEventCreate(&c->ev1));
+    double t0 = now_ms();
+    s = build(c);
+    c->stats.ms_total = now_ms() - t0;
+  } catch (const DeviceError& e) {
+    s = map_device_error(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    s = DC_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    s = DC_E_DEVICE;
+  } catch (...) {
+    s = DC_E_DEVICE;
+  }
+  if (s != DC_OK) {
+    destroy_ctx(c);
+    return s;
+  }
+  *out = c;
+  return DC_OK;
+}
+}  // namespace dc_core
+
+using namespace dc_core;
 
 extern "C" {
 
@@ -690,40 +869,75 @@ dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1, const dc_options*
   if (!out || n < 1 || !options_ok(opt)) return DC_E_ARG;
   if (g1 && g1->count < 0) return DC_E_ARG;
   if (g1 && g1->count > 0 && (!g1->u || !g1->v || !g1->w)) return DC_E_ARG;
+  return create_ctx(out, n, opt, [&](dc_ctx* c) { return do_init(c, g1); });
+}
+
+dc_status dc_init_from_state(dc_ctx** out, int32_t n, const int64_t* off, const int32_t* col,
+                             const int32_t* w, const int32_t* C, const dc_options* opt) {
+  if (!out || n < 1 || !off || !C || !options_ok(opt)) return DC_E_ARG;
   *out = nullptr;
-  dc_ctx* c = new (std::nothrow) dc_ctx();
-  if (!c) return DC_E_OOM;
-  c->n = n;
-  c->opt = *opt;
-  c->st = static_cast<hipStream_t>(opt->stream);
-  dc_status s;
+  const int64_t nnz = off[n];
+  if (off[0] != 0 || nnz < 0 || nnz > (int64_t(1) << 31) || (nnz > 0 && (!col || !w)))
+    return DC_E_ARG;
+  SavedState st;
   try {
-    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
-    DC_HIP(hipHostMalloc(&c->hbuf, 64));
-    DC_HIP(hipHostMalloc(&c->bins.host, 256));
-    DC_HIP(hipHostMalloc(&c->cs.host, 64));
-    DC_HIP(hipEventCreate(&c->ev0));
-    DC_HIP(hipEventCreate(&c->ev1));
-    double t0 = now_ms();
-    s = do_init(c, g1);
-    c->stats.ms_total = now_ms() - t0;
-  } catch (const DeviceError& e) {
-    s = map_device_error(e);
+    st.off.resize(size_t(n) + 1);
+    st.adj.resize(size_t(nnz));
+    st.k.assign(size_t(n), 0);
+    st.C.assign(C, C + n);
+    st.a.assign(size_t(n), 0);
+    st.sz.assign(size_t(n), 0);
   } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    s = DC_E_OOM;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    s = DC_E_DEVICE;
-  } catch (...) {
-    s = DC_E_DEVICE;
+    return DC_E_OOM;
   }
-  if (s != DC_OK) {
-    destroy_ctx(c);
-    return s;
+  // rows: monotone offsets, neighbours in range, sorted, no self-loop, w >= 1
+  int64_t two_m = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    if (off[u + 1] < off[u] || off[u + 1] > nnz) return DC_E_ARG;
+    st.off[size_t(u)] = int32_t(off[u]);
+    int64_t ku = 0;
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      const int32_t v = col[e];
+      if (v < 0 || v >= n || v == u || w[e] < 1) return DC_E_ARG;
+      if (e > off[u] && col[e - 1] >= v) return DC_E_ARG;
+      st.adj[size_t(e)] = make_int2(v, w[e]);
+      ku += w[e];
+    }
+    two_m += ku;
+    if (two_m >= TWO_M_LIMIT) return DC_E_OVERFLOW;
+    st.k[size_t(u)] = int32_t(ku);
   }
-  *out = c;
-  return DC_OK;
+  st.off[size_t(n)] = int32_t(nnz);
+  // symmetry: (u, v, w) needs (v, u, w)
+  for (int32_t u = 0; u < n; ++u)
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      const int32_t v = col[e];
+      const int32_t* b = col + off[v];
+      const int32_t* f = std::lower_bound(b, col + off[v + 1], u);
+      if (f == col + off[v + 1] || *f != u || w[off[v] + (f - b)] != w[e]) return DC_E_ARG;
+    }
+  // canonical labels: each community labelled by its smallest member
+  for (int32_t v = 0; v < n; ++v) {
+    const int32_t c = C[v];
+    if (c < 0 || c > v || C[c] != c) return DC_E_ARG;
+    st.a[size_t(c)] += st.k[size_t(v)];
+    st.sz[size_t(c)] += 1;
+  }
+  st.nnz = nnz;
+  st.two_m = two_m;
+  return create_ctx(out, n, opt, [&](dc_ctx* c) {
+    ctx_restore(c, st);
+    c->stats = dc_step_stats{};
+    c->stats.two_m = two_m;
+    return DC_OK;
+  });
+}
+
+dc_status dc_export_state(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w, int32_t* C) {
+  if (!C) return DC_E_ARG;
+  dc_status s = dc_export_csr(ctx, off, col, w);
+  if (s != DC_OK) return s;
+  return dc_communities(ctx, C, 0);
 }
 
 dc_status dc_apply_batch(dc_ctx* ctx, const dc_edges* add, const dc_edges* del, int32_t* C_out,
@@ -733,7 +947,7 @@ dc_status dc_apply_batch(dc_ctx* ctx, const dc_edges* add, const dc_edges* del, 
   if (del && (del->count < 0 || (del->count > 0 && (!del->u || !del->v)))) return DC_E_ARG;
   return guarded(ctx, [&] {
     double t0 = now_ms();
-    dc_status s = do_apply(ctx, add, del, C_out, out_on_device, nullptr);
+    dc_status s = do_apply(ctx, add, del, C_out, out_on_device);
     if (s == DC_OK) {
       ctx->stats.ms_total = now_ms() - t0;
       if (stats) *stats = ctx->stats;

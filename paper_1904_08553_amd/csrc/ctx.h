@@ -1,0 +1,99 @@
+// ctx.h -- the context behind dc_ctx and the phases of a time step, shared
+// by the C ABI (api.hip) and the serving loop (server.hip).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "dc_louvain.h"
+#include "learned.h"
+
+using namespace dc;
+
+struct dc_ctx {
+  int32_t n = 0;
+  dc_options opt{};
+  hipStream_t st = nullptr;
+  bool poisoned = false;
+  int64_t two_m = 0;
+  int64_t nnz = 0;
+  int cur = 0;
+  DBuf off[2], adj[2];
+  DBuf k0, C, a0, sz0;
+  // batch
+  DBuf in_au, in_av, in_aw, in_du, in_dv;
+  DBuf dkeys, dvals, dk1, dv1, dw_old;
+  DBuf akeys, avals, ak1, av1, aheads, apos, ukeys, uw;
+  DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
+  DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
+  DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
+  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc, bigrows;
+  // learned screener: touched set, features, labels, scores
+  DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
+  bool have_scr = false;
+  float theta = 0.f;
+  int64_t T_count = 0;
+  bool have_y = false, have_logits = false;
+  // levels
+  DBuf Cl, Cn, al, szl, dpack, lflag, tlist, movers, map0, cnt[2], minv[2], lab, cntf;
+  CoarseGraph cg[2];
+  DBuf stat;
+  long long* hstat = nullptr;  // pinned mirror of the status block
+  void* hbuf = nullptr;        // pinned scratch for the kernels' host reads
+  BinScratch bins;
+  CoarsenScratch cs;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<dc_sweep_rec> trace;
+  dc_step_stats stats{};
+  int64_t R_count = 0;
+  bool have_R_all = true;
+};
+
+namespace dc_core {
+
+// Level-0 run of one context between levels_begin and levels_finish.
+struct LevelRun {
+  LevelView g;
+  const int32_t* act;
+  int64_t nact;
+  long long T;
+  Bins bins;
+};
+
+// Host-side copy of a context's resident state (G_t, labels, totals).
+struct SavedState {
+  std::vector<int32_t> off;
+  std::vector<int2> adj;
+  std::vector<int32_t> k, C, a, sz;
+  int64_t nnz = 0, two_m = 0;
+  int cur = 0;
+};
+
+// Scratch of merged level-0 sweeps over several contexts.
+struct MergeScratch {
+  MultiBins mb;
+  DBuf descs, done, segs;
+  EvalArgs* hdescs = nullptr;  // pinned, cap entries
+  int32_t* hdone = nullptr;    // pinned, cap entries
+  MultiSeg* hsegs = nullptr;   // pinned, NBINS * cap entries
+  int cap = 0;
+};
+
+dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const int32_t** act,
+                      int64_t* nact);
+void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& L);
+void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain);
+void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device);
+// Level-0 sweeps of m contexts sharing one stream, merged per round: the
+// evaluation of every unfinished context in one launch per row-length bin,
+// then each context's apply, one wait per round; gains[j] receives context
+// j's level-0 gain.  Results are those of running each context alone.
+void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, MergeScratch& X);
+// Device bytes a context holds.
+int64_t ctx_footprint(const dc_ctx* c);
+// Moves the resident state to the host and frees every device buffer of the
+// context; ctx_restore brings it back (the next call rebuilds the rest).
+void ctx_evict(dc_ctx* c, SavedState& s);
+void ctx_restore(dc_ctx* c, const SavedState& s);
+
+}  // namespace dc_core

@@ -51,6 +51,35 @@ struct LevelView {
   const int32_t* k;
 };
 
+// Arguments of the evaluation kernels for one graph (one level).
+struct EvalArgs {
+  const int32_t* off;
+  const int2* adj;
+  const int32_t* k;
+  const int32_t* C;   // labels read (snapshot)
+  int32_t* Cn;        // next labels (EV_SWEEP)
+  const int32_t* a;   // community totals by label
+  const int32_t* sz;  // community sizes by label
+  long long two_m;
+  int32_t guard;
+  const int32_t* list;   // vertices (or sources) of this bin
+  const int32_t* count;  // device count of list
+  int* gkeys;            // bin G tables
+  int* gvals;
+  const long long* tab_off;
+  long long* stat;
+  const uint64_t* ins_keys;  // Alg. 2: sorted directed insertions src*n0+dst
+  const int32_t* seg_beg;    // per source vertex: its sinks are ins_keys[beg, end)
+  const int32_t* seg_end;
+  int64_t n_ins;
+  int32_t n0;
+  uint8_t* R;
+  uint8_t* cflag;
+  int32_t* f_own;  // EV_FEAT outputs, indexed by vertex
+  long long* f_g1;
+  long long* f_g2;
+};
+
 struct Bins {
   int64_t n[NBINS];
   const int32_t* list[NBINS];
@@ -94,6 +123,34 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
 void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
                   long long two_m, const Bins& bins, uint8_t* R, uint8_t* cflag,
                   long long* stat, hipStream_t st);
+
+// ---- merged sweeps of several graphs (one launch per row-length bin) ----
+// Bins S16..B of several graphs concatenated, each graph's part padded to
+// whole waves (list entry -1), with the graph index of every item.
+struct MultiBins {
+  DBuf list[NBINS - 1], gid[NBINS - 1];
+  int64_t count[NBINS - 1] = {};
+};
+struct MultiSeg {  // one graph's bin, for build_multi_bins
+  const int32_t* src;
+  int64_t n, padded, dst;
+  int32_t gid, bin;
+};
+// Sweep arguments of one graph's level (the `list`/`count` fields unused).
+EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                    const int32_t* sz, long long two_m, int guard);
+// Merges bins[0..ngraphs) (graph j's bins at position j); segs_host: pinned
+// scratch of NBINS * ngraphs MultiSeg, segs_dev: device scratch.
+void build_multi_bins(const Bins* const* bins, int ngraphs, MultiBins& mb, MultiSeg* segs_host,
+                      DBuf& segs_dev, hipStream_t st);
+// One sweep evaluation of every graph j with done[j] == 0 over the merged
+// bins (descs[j]: its sweep arguments, device memory); graph j's bin G runs
+// separately (sweep_eval_bin_g).
+void sweep_eval_multi(const EvalArgs* descs, const int32_t* done, const MultiBins& mb,
+                      hipStream_t st);
+void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                      const int32_t* sz, long long two_m, int guard, const Bins& bins,
+                      hipStream_t st);
 
 // Per listed vertex i: f_own[i] = e_{i->C(i)}, f_g1[i] / f_g2[i] = scaled
 // gains to the best / second-best other neighbouring community (score

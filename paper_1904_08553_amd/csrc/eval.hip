@@ -30,33 +30,7 @@ namespace {
 constexpr int TPB = 256;
 constexpr int NW = TPB / WAVE;
 
-struct EvalArgs {
-  const int32_t* off;
-  const int2* adj;
-  const int32_t* k;
-  const int32_t* C;   // labels read (snapshot)
-  int32_t* Cn;        // next labels (EV_SWEEP)
-  const int32_t* a;   // community totals by label
-  const int32_t* sz;  // community sizes by label
-  long long two_m;
-  int32_t guard;
-  const int32_t* list;   // vertices (or sources) of this bin
-  const int32_t* count;  // device count of list
-  int* gkeys;            // bin G tables
-  int* gvals;
-  const long long* tab_off;
-  long long* stat;
-  const uint64_t* ins_keys;  // Alg. 2: sorted directed insertions src*n0+dst
-  const int32_t* seg_beg;    // per source vertex: its sinks are ins_keys[beg, end)
-  const int32_t* seg_end;
-  int64_t n_ins;
-  int32_t n0;
-  uint8_t* R;
-  uint8_t* cflag;
-  int32_t* f_own;  // EV_FEAT outputs, indexed by vertex
-  long long* f_g1;
-  long long* f_g2;
-};
+
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -208,6 +182,96 @@ __device__ __forceinline__ int group_collect(bool valid, int key, int w, uint64_
   return r;
 }
 
+// One item of a group kernel: group (lane / GS) of the wave evaluates vertex
+// i (have = false: no vertex, the lanes still take part in the wave-wide
+// steps).  Returns the screening tests this group accepted (0 or 1).
+template <int MODE, int GS>
+__device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool have, int lane,
+                                                int gl, int gbase, uint64_t gmask) {
+  long long accepted = 0;
+  const int32_t rb = have ? A.off[i] : 0;
+  const int32_t re = have ? A.off[i + 1] : 0;
+  const int c = have ? A.C[i] : 0;
+  const long long ki = have ? A.k[i] : 0;
+  const int2 e = rb + gl < re ? A.adj[rb + gl] : make_int2(-1, 0);
+  const bool valid = e.x >= 0 && e.x != i;
+  const int key = valid ? A.C[e.x] : EMPTY_KEY;
+  int ck = EMPTY_KEY, cs = 0;
+  const int nd = group_collect<GS>(valid, key, e.y, gmask, ck, cs);
+  const bool pair = gl < nd;
+  const long long e_own = group_sum_ll<GS>(pair && ck == c ? (long long)cs : 0);
+  const long long s_own = A.two_m * e_own - ki * ((have ? A.a[c] : 0) - ki);
+  if (MODE == EV_FEAT) {
+    Best b = {NO_SCORE, NO_LABEL};
+    if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
+    const Best b1 = group_best_w<GS>(b);
+    const Best b2 = group_best_w<GS>(b.x != b1.x ? b : Best{NO_SCORE, NO_LABEL});
+    if (have && gl == 0) {
+      A.f_own[i] = int32_t(e_own);
+      A.f_g1[i] = b1.x != NO_LABEL ? b1.s - s_own : NO_GAIN;
+      A.f_g2[i] = b2.x != NO_LABEL ? b2.s - s_own : NO_GAIN;
+    }
+    return accepted;
+  }
+  if (MODE == EV_DSADD) {
+    const int q0 = have ? A.seg_beg[i] : 0;
+    const int nsk = have ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
+    const bool has = gl < nsk;
+    const int sj = has ? int(A.ins_keys[q0 + gl] - uint64_t(i) * uint64_t(A.n0)) : 0;
+    const int Xj = has ? A.C[sj] : EMPTY_KEY;
+    long long ej = 0;
+    const int ndw = wave_max(nd);
+    for (int r = 0; r < ndw; ++r) {
+      const int kr = __shfl(ck, gbase + r, WAVE);
+      const int sr = __shfl(cs, gbase + r, WAVE);
+      if (r < nd && Xj == kr) ej = sr;
+    }
+    Cand cd = {NO_SCORE, NO_LABEL, NO_LABEL};
+    if (has) {
+      long long g = Xj == c ? 0 : A.two_m * ej - ki * A.a[Xj] - s_own;
+      cd = {g, Xj, sj};
+    }
+    const Cand best = group_cand_w<GS>(cd);
+    const bool live = have && best.j != NO_LABEL && best.x != c && best.g > 0;
+    // gain2 of each live group, streamed by the whole wave (j* is often a
+    // high-degree vertex, and a 16-lane group would walk its row alone)
+    long long g2 = 0;
+    for (uint64_t lm = __ballot(live && gl == 0); lm; lm &= lm - 1) {
+      const int ld = __ffsll((unsigned long long)lm) - 1;
+      const long long r = reverse_gain(A, __shfl(best.j, ld, WAVE), __shfl(best.x, ld, WAVE),
+                                       __shfl(c, ld, WAVE));
+      if (lane / GS == ld / GS) g2 = r;
+    }
+    if (live && best.g >= g2) {
+      if (e.x >= 0) A.R[e.x] = 1;
+      if (gl == 0) {
+        A.R[i] = 1;
+        A.R[best.j] = 1;
+        A.cflag[best.x] = 1;
+        accepted++;
+      }
+    }
+    return accepted;
+  }
+  Best b = {NO_SCORE, NO_LABEL};
+  if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
+  b = group_best_w<GS>(b);
+  bool move = have && b.x != NO_LABEL && b.s > s_own;
+  if (MODE == EV_SWEEP) {
+    if (move && gl == 0) {
+      if (!(A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c)) A.Cn[i] = b.x;
+    }
+  } else if (move) {  // EV_DSDEL
+    if (e.x >= 0) A.R[e.x] = 1;
+    if (gl == 0) {
+      A.R[i] = 1;
+      A.cflag[b.x] = 1;
+      accepted++;
+    }
+  }
+  return accepted;
+}
+
 template <int MODE, int GS>
 __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
   constexpr int GPW = WAVE / GS;  // groups per wave
@@ -225,86 +289,7 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
     const int64_t idx = wb + lane / GS;
     const bool have = idx < cnt;
     const int i = have ? A.list[idx] : 0;
-    const int32_t rb = have ? A.off[i] : 0;
-    const int32_t re = have ? A.off[i + 1] : 0;
-    const int c = have ? A.C[i] : 0;
-    const long long ki = have ? A.k[i] : 0;
-    const int2 e = rb + gl < re ? A.adj[rb + gl] : make_int2(-1, 0);
-    const bool valid = e.x >= 0 && e.x != i;
-    const int key = valid ? A.C[e.x] : EMPTY_KEY;
-    int ck = EMPTY_KEY, cs = 0;
-    const int nd = group_collect<GS>(valid, key, e.y, gmask, ck, cs);
-    const bool pair = gl < nd;
-    const long long e_own = group_sum_ll<GS>(pair && ck == c ? (long long)cs : 0);
-    const long long s_own = A.two_m * e_own - ki * ((have ? A.a[c] : 0) - ki);
-    if (MODE == EV_FEAT) {
-      Best b = {NO_SCORE, NO_LABEL};
-      if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
-      const Best b1 = group_best_w<GS>(b);
-      const Best b2 = group_best_w<GS>(b.x != b1.x ? b : Best{NO_SCORE, NO_LABEL});
-      if (have && gl == 0) {
-        A.f_own[i] = int32_t(e_own);
-        A.f_g1[i] = b1.x != NO_LABEL ? b1.s - s_own : NO_GAIN;
-        A.f_g2[i] = b2.x != NO_LABEL ? b2.s - s_own : NO_GAIN;
-      }
-      continue;
-    }
-    if (MODE == EV_DSADD) {
-      const int q0 = have ? A.seg_beg[i] : 0;
-      const int nsk = have ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
-      const bool has = gl < nsk;
-      const int sj = has ? int(A.ins_keys[q0 + gl] - uint64_t(i) * uint64_t(A.n0)) : 0;
-      const int Xj = has ? A.C[sj] : EMPTY_KEY;
-      long long ej = 0;
-      const int ndw = wave_max(nd);
-      for (int r = 0; r < ndw; ++r) {
-        const int kr = __shfl(ck, gbase + r, WAVE);
-        const int sr = __shfl(cs, gbase + r, WAVE);
-        if (r < nd && Xj == kr) ej = sr;
-      }
-      Cand cd = {NO_SCORE, NO_LABEL, NO_LABEL};
-      if (has) {
-        long long g = Xj == c ? 0 : A.two_m * ej - ki * A.a[Xj] - s_own;
-        cd = {g, Xj, sj};
-      }
-      const Cand best = group_cand_w<GS>(cd);
-      const bool live = have && best.j != NO_LABEL && best.x != c && best.g > 0;
-      // gain2 of each live group, streamed by the whole wave (j* is often a
-      // high-degree vertex, and a 16-lane group would walk its row alone)
-      long long g2 = 0;
-      for (uint64_t lm = __ballot(live && gl == 0); lm; lm &= lm - 1) {
-        const int ld = __ffsll((unsigned long long)lm) - 1;
-        const long long r = reverse_gain(A, __shfl(best.j, ld, WAVE), __shfl(best.x, ld, WAVE),
-                                         __shfl(c, ld, WAVE));
-        if (lane / GS == ld / GS) g2 = r;
-      }
-      if (live && best.g >= g2) {
-        if (e.x >= 0) A.R[e.x] = 1;
-        if (gl == 0) {
-          A.R[i] = 1;
-          A.R[best.j] = 1;
-          A.cflag[best.x] = 1;
-          accepted++;
-        }
-      }
-      continue;
-    }
-    Best b = {NO_SCORE, NO_LABEL};
-    if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
-    b = group_best_w<GS>(b);
-    bool move = have && b.x != NO_LABEL && b.s > s_own;
-    if (MODE == EV_SWEEP) {
-      if (move && gl == 0) {
-        if (!(A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c)) A.Cn[i] = b.x;
-      }
-    } else if (move) {  // EV_DSDEL
-      if (e.x >= 0) A.R[e.x] = 1;
-      if (gl == 0) {
-        A.R[i] = 1;
-        A.cflag[b.x] = 1;
-        accepted++;
-      }
-    }
+    accepted += group_item<MODE, GS>(A, i, have, lane, gl, gbase, gmask);
   }
   accepted = group_sum_ll<WAVE>(accepted);
   if (MODE != EV_SWEEP && lane == 0 && accepted)
@@ -586,6 +571,88 @@ __global__ void __launch_bounds__(TPB) k_eval_gtab(EvalArgs A) {
                                   &own);
   if (MODE != EV_SWEEP && threadIdx.x == 0 && acc)
     atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC], 1ull);
+}
+
+// --------------------------------------------------------------------------
+// merged sweeps: the items of several graphs in one launch per bin.  Lists
+// are padded per graph to whole waves, so each wave (or block) works for one
+// graph and loads that graph's arguments as uniform values.
+
+struct MultiArgs {
+  const EvalArgs* descs;
+  const int32_t* list;
+  const int32_t* gid;
+  const int32_t* done;
+  int64_t count;
+};
+
+template <int GS>
+__global__ void __launch_bounds__(TPB) k_sweep_group_multi(MultiArgs M) {
+  constexpr int GPW = WAVE / GS;
+  const int lane = lane_id();
+  const int gl = lane & (GS - 1);
+  const int gbase = lane - gl;
+  const uint64_t gmask = GS == WAVE ? ~uint64_t(0) : (((uint64_t(1) << GS) - 1) << gbase);
+  const int64_t ngroups = int64_t(gridDim.x) * NW * GPW;
+  const int64_t w0 = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * GPW;
+  for (int64_t wb = w0; wb < M.count; wb += ngroups) {
+    const int g = uniform(M.gid[wb]);
+    if (M.done[g]) continue;  // uniform: this graph's level has converged
+    const EvalArgs A = M.descs[g];
+    const int i = M.list[wb + lane / GS];
+    (void)group_item<EV_SWEEP, GS>(A, i < 0 ? 0 : i, i >= 0, lane, gl, gbase, gmask);
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_sweep_wtab_multi(MultiArgs M) {
+  __shared__ int keys[NW][WTAB_SLOTS];
+  __shared__ int vals[NW][WTAB_SLOTS];
+  __shared__ GroupLds<WAVE> L[NW];
+  __shared__ int own[NW];
+  const int wid = threadIdx.x / WAVE;
+  const int64_t nwaves = int64_t(gridDim.x) * NW;
+  for (int64_t idx = int64_t(blockIdx.x) * NW + wid; idx < M.count; idx += nwaves) {
+    const int g = uniform(M.gid[idx]);
+    if (M.done[g]) continue;
+    const EvalArgs A = M.descs[g];
+    const int i = uniform(M.list[idx]);
+    const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], WTAB_SLOTS);
+    (void)eval_table<EV_SWEEP, WAVE>(A, i, keys[wid], vals[wid], cap - 1, L[wid], &own[wid]);
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_sweep_btab_multi(MultiArgs M) {
+  __shared__ int keys[BTAB_SLOTS];
+  __shared__ int vals[BTAB_SLOTS];
+  __shared__ GroupLds<TPB> L;
+  __shared__ int own;
+  for (int64_t idx = blockIdx.x; idx < M.count; idx += gridDim.x) {
+    const int g = M.gid[idx];  // uniform over the block
+    if (M.done[g]) continue;
+    const EvalArgs A = M.descs[g];
+    const int i = M.list[idx];
+    const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BTAB_SLOTS);
+    (void)eval_table<EV_SWEEP, TPB>(A, i, keys, vals, cap - 1, L, &own);
+  }
+}
+
+struct MultiDst {
+  int32_t* list[NBINS - 1];
+  int32_t* gid[NBINS - 1];
+};
+
+// block per segment: copy a graph's bin list into its merged slot, padding
+// with -1, and tag every item with the graph index
+__global__ void k_build_multi(const MultiSeg* __restrict__ segs, int nsegs, MultiDst D) {
+  for (int sidx = blockIdx.x; sidx < nsegs; sidx += gridDim.x) {
+    const MultiSeg sg = segs[sidx];
+    int32_t* lst = D.list[sg.bin] + sg.dst;
+    int32_t* gd = D.gid[sg.bin] + sg.dst;
+    for (int64_t i = threadIdx.x; i < sg.padded; i += blockDim.x) {
+      lst[i] = i < sg.n ? sg.src[i] : -1;
+      gd[i] = sg.gid;
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -908,6 +975,96 @@ void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const 
   A.R = R;
   A.cflag = cflag;
   launch_eval<EV_DSDEL>(A, bins, st, nullptr, nullptr);
+}
+
+EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                    const int32_t* sz, long long two_m, int guard) {
+  EvalArgs A{};
+  A.off = g.off;
+  A.adj = g.adj;
+  A.k = g.k;
+  A.C = C;
+  A.Cn = Cn;
+  A.a = a;
+  A.sz = sz;
+  A.two_m = two_m;
+  A.guard = guard;
+  A.n0 = g.n;
+  return A;
+}
+
+void build_multi_bins(const Bins* const* bins, int ngraphs, MultiBins& mb, MultiSeg* segs_host,
+                      DBuf& segs_dev, hipStream_t st) {
+  constexpr int PAD[NBINS - 1] = {WAVE / 16, WAVE / 32, 1, 1, 1};
+  int nsegs = 0;
+  for (int q = 0; q < NBINS - 1; ++q) {
+    int64_t off = 0;
+    for (int j = 0; j < ngraphs; ++j) {
+      const int64_t n = bins[j]->n[q];
+      if (n == 0) continue;
+      const int64_t padded = ceil_div(n, PAD[q]) * PAD[q];
+      segs_host[nsegs++] = MultiSeg{bins[j]->list[q], n, padded, off, j, q};
+      off += padded;
+    }
+    mb.count[q] = off;
+    mb.list[q].ensure(size_t(off + 1) * 4);
+    mb.gid[q].ensure(size_t(off + 1) * 4);
+  }
+  if (nsegs == 0) return;
+  segs_dev.ensure(size_t(nsegs) * sizeof(MultiSeg));
+  DC_HIP(hipMemcpyAsync(segs_dev.p, segs_host, size_t(nsegs) * sizeof(MultiSeg),
+                        hipMemcpyHostToDevice, st));
+  MultiDst D;
+  for (int q = 0; q < NBINS - 1; ++q) {
+    D.list[q] = mb.list[q].as<int32_t>();
+    D.gid[q] = mb.gid[q].as<int32_t>();
+  }
+  k_build_multi<<<nsegs, TPB, 0, st>>>(segs_dev.as<MultiSeg>(), nsegs, D);
+  DC_LAUNCH_CHECK();
+}
+
+void sweep_eval_multi(const EvalArgs* descs, const int32_t* done, const MultiBins& mb,
+                      hipStream_t st) {
+  auto args = [&](int q) {
+    return MultiArgs{descs, mb.list[q].as<int32_t>(), mb.gid[q].as<int32_t>(), done,
+                     mb.count[q]};
+  };
+  if (mb.count[0] > 0) {
+    k_sweep_group_multi<16><<<wave_grid(ceil_div(mb.count[0], 4)), TPB, 0, st>>>(args(0));
+    DC_LAUNCH_CHECK();
+  }
+  if (mb.count[1] > 0) {
+    k_sweep_group_multi<32><<<wave_grid(ceil_div(mb.count[1], 2)), TPB, 0, st>>>(args(1));
+    DC_LAUNCH_CHECK();
+  }
+  if (mb.count[2] > 0) {
+    k_sweep_group_multi<64><<<wave_grid(mb.count[2]), TPB, 0, st>>>(args(2));
+    DC_LAUNCH_CHECK();
+  }
+  if (mb.count[3] > 0) {
+    k_sweep_wtab_multi<<<wave_grid(mb.count[3]), TPB, 0, st>>>(args(3));
+    DC_LAUNCH_CHECK();
+  }
+  if (mb.count[4] > 0) {
+    const int64_t nb = mb.count[4] < 16384 ? mb.count[4] : 16384;
+    k_sweep_btab_multi<<<int(nb), TPB, 0, st>>>(args(4));
+    DC_LAUNCH_CHECK();
+  }
+}
+
+void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                      const int32_t* sz, long long two_m, int guard, const Bins& bins,
+                      hipStream_t st) {
+  constexpr int G = NBINS - 1;
+  if (bins.n[G] == 0) return;
+  EvalArgs A = sweep_args(g, C, Cn, a, sz, two_m, guard);
+  A.list = bins.list[G];
+  A.count = bins.count_dev + G;
+  A.gkeys = bins.gkeys;
+  A.gvals = bins.gvals;
+  A.tab_off = bins.tab_off;
+  k_eval_gtab<EV_SWEEP><<<bins.n[G], TPB, 0, st>>>(A);
+  DC_LAUNCH_CHECK();
 }
 
 }  // namespace dc

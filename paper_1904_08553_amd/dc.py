@@ -16,6 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdc.so")
 
 OK = 0
+PENDING = 1
 MODE_DELTA, MODE_ALL, MODE_STATIC, MODE_LEARNED = 0, 1, 2, 3
 MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 8, 64, 4801
 DEL_GAIN, DEL_CONSERVATIVE = 0, 1
@@ -71,8 +72,22 @@ EXPORTS = [
     "dc_last_R", "dc_last_trace", "dc_last_stats", "dc_num_entries", "dc_export_csr",
     "dc_destroy", "dc_strerror", "dc_last_error", "dc_screener_set", "dc_last_samples",
     "dc_mlp_create", "dc_mlp_set_weights", "dc_mlp_get_weights", "dc_mlp_forward", "dc_mlp_grad",
-    "dc_mlp_train_step", "dc_mlp_destroy",
+    "dc_mlp_train_step", "dc_mlp_destroy", "dc_export_state", "dc_init_from_state",
+    "dc_server_create", "dc_server_add_graph", "dc_server_submit", "dc_server_poll",
+    "dc_server_stats_get", "dc_server_destroy",
 ]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [
+        ("graphs", ct.c_int64), ("batches", ct.c_int64), ("rounds", ct.c_int64),
+        ("merged_rounds", ct.c_int64), ("merged_graphs", ct.c_int64), ("evictions", ct.c_int64),
+        ("restores", ct.c_int64), ("deferred", ct.c_int64), ("resident_bytes", ct.c_int64),
+        ("peak_resident_bytes", ct.c_int64), ("reserved", ct.c_int64 * 6),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 _lib = None
 
@@ -136,6 +151,22 @@ def load(path: str = LIB_PATH):
     L.dc_mlp_train_step.restype = i32
     L.dc_mlp_destroy.argtypes = [P]
     L.dc_mlp_destroy.restype = None
+    L.dc_export_state.argtypes = [P, P, P, P, P]
+    L.dc_export_state.restype = i32
+    L.dc_init_from_state.argtypes = [P, i32, P, P, P, P, P]
+    L.dc_init_from_state.restype = i32
+    L.dc_server_create.argtypes = [P, P, i64, i32]
+    L.dc_server_create.restype = i32
+    L.dc_server_add_graph.argtypes = [P, i32, P, P]
+    L.dc_server_add_graph.restype = i32
+    L.dc_server_submit.argtypes = [P, i32, P, P, i64, P]
+    L.dc_server_submit.restype = i32
+    L.dc_server_poll.argtypes = [P, i64, i32, P, P, P]
+    L.dc_server_poll.restype = i32
+    L.dc_server_stats_get.argtypes = [P, P]
+    L.dc_server_stats_get.restype = i32
+    L.dc_server_destroy.argtypes = [P]
+    L.dc_server_destroy.restype = None
     _lib = L
     return L
 
@@ -219,6 +250,35 @@ class DynamicCommunities:
         _check(load().dc_init(ct.byref(h), self.n, ct.byref(e), ct.byref(self._opt)), "dc_init")
         self._h = h
         del keep
+
+    @classmethod
+    def from_state(cls, n, off, col, w, C, **opt):
+        """Resume from a checkpoint (see export_state); runs no levels."""
+        self = cls.__new__(cls)
+        self.n = int(n)
+        self._opt = options(**opt)
+        off = np.ascontiguousarray(off, np.int64)
+        col = np.ascontiguousarray(col, np.int32)
+        w = np.ascontiguousarray(w, np.int32)
+        C = np.ascontiguousarray(C, np.int32)
+        h = ct.c_void_p()
+        _check(load().dc_init_from_state(ct.byref(h), self.n, off.ctypes.data, col.ctypes.data,
+                                         w.ctypes.data, C.ctypes.data, ct.byref(self._opt)),
+               "dc_init_from_state")
+        self._h = h
+        return self
+
+    def export_state(self):
+        """Checkpoint: (off, col, w, C) in host memory."""
+        nnz = ct.c_int64()
+        _check(load().dc_num_entries(self._h, ct.byref(nnz)), "dc_num_entries")
+        off = np.empty(self.n + 1, np.int64)
+        col = np.empty(max(nnz.value, 1), np.int32)
+        w = np.empty(max(nnz.value, 1), np.int32)
+        C = np.empty(self.n, np.int32)
+        _check(load().dc_export_state(self._h, off.ctypes.data, col.ctypes.data, w.ctypes.data,
+                                      C.ctypes.data), "dc_export_state")
+        return off, col[: nnz.value], w[: nnz.value], C
 
     def apply_batch(self, add_u=None, add_v=None, add_w=None, del_u=None, del_v=None, out=None):
         """Apply one batch; returns C_t as a numpy array (or fills ``out``,
@@ -390,6 +450,67 @@ class MLP:
     def close(self):
         if getattr(self, "_h", None):
             load().dc_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Many dynamic graphs served from one GPU by libdc.so (dc_server_*):
+    continuous batching with merged level-0 sweeps and admission of graphs
+    by device-memory footprint (budget_bytes <= 0: unlimited)."""
+
+    def __init__(self, budget_bytes=0, max_inflight=8, **opt):
+        self._opt = options(stream=None, **opt)
+        h = ct.c_void_p()
+        _check(load().dc_server_create(ct.byref(h), ct.byref(self._opt), int(budget_bytes),
+                                       int(max_inflight)), "dc_server_create")
+        self._h = h
+        self.n = {}
+
+    def add_graph(self, n, u, v, w):
+        e, keep = _edges(u, v, w)
+        gid = ct.c_int32()
+        _check(load().dc_server_add_graph(self._h, int(n), ct.byref(e), ct.byref(gid)),
+               "dc_server_add_graph")
+        self.n[gid.value] = int(n)
+        return gid.value
+
+    def submit(self, gid, add_u=(), add_v=(), add_w=(), del_u=(), del_v=(), arrival_ns=None):
+        import time
+        add, ka = _edges(add_u, add_v, add_w)
+        dele, kd = _edges(del_u, del_v)
+        t = ct.c_int64()
+        arr = time.monotonic_ns() if arrival_ns is None else int(arrival_ns)
+        _check(load().dc_server_submit(self._h, int(gid), ct.byref(add), ct.byref(dele), arr,
+                                       ct.byref(t)), "dc_server_submit")
+        return t.value
+
+    def poll(self, ticket, gid, wait=True):
+        """None while pending (wait=False); else (C, stats, (arrival, start,
+        done) ns).  Raises DCError for a failed batch."""
+        C = np.empty(self.n[gid], np.int32)
+        st = StepStats()
+        times = (ct.c_int64 * 3)()
+        s = load().dc_server_poll(self._h, int(ticket), int(bool(wait)), C.ctypes.data,
+                                  ct.byref(st), times)
+        if s == PENDING:
+            return None
+        _check(s, "dc_server_poll")
+        return C, st, tuple(times)
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().dc_server_stats_get(self._h, ct.byref(st)), "dc_server_stats_get")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dc_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

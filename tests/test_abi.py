@@ -3,6 +3,9 @@ include/dc.h (no device call is made)."""
 import os
 import re
 
+import numpy as np
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -48,3 +51,26 @@ def test_bad_arguments_rejected_without_device():
     o.max_levels = 0
     assert L.dc_init(ct.byref(h), 5, None, ct.byref(o)) == -1
     assert L.dc_apply_batch(None, None, None, None, 0, None) == -1
+
+
+def test_init_from_state_rejects_malformed_checkpoints():
+    """Host-side validation (no device work happens for a rejected state)."""
+    from paper_1904_08553_amd import dc
+    # path 0-1-2 with unit weights; C canonical
+    off = np.array([0, 1, 3, 4], np.int64)
+    col = np.array([1, 0, 2, 1], np.int32)
+    w = np.array([1, 1, 1, 1], np.int32)
+    C = np.array([0, 0, 2], np.int32)
+    bad = [
+        (off, np.array([1, 2, 0, 1], np.int32), w, C),          # row 1 unsorted
+        (off, np.array([1, 0, 2, 0], np.int32), w, C),          # asymmetric
+        (off, col, np.array([1, 2, 1, 1], np.int32), C),        # weights differ
+        (off, col, np.array([1, 0, 0, 1], np.int32), C),        # weight 0
+        (off, col, w, np.array([1, 1, 2], np.int32)),           # label not the minimum
+        (off, col, w, np.array([0, 0, 1], np.int32)),           # label of a non-root
+        (np.array([0, 1, 3, 3], np.int64), col, w, C),          # offsets cut rows
+    ]
+    for o, c, ww, cc in bad:
+        with pytest.raises(dc.DCError) as e:
+            dc.DynamicCommunities.from_state(3, o, c, ww, cc, stream=None)
+        assert e.value.status == -1
