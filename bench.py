@@ -115,6 +115,97 @@ def cpu_baseline(n, graph, batches, cpu_steps):
             "seconds": tot}
 
 
+def _serving_graph(args):
+    from paper_1904_08553_amd import workloads as W
+    seed, batches, n_lo, n_hi = args
+    return W.serving_graph(seed, batches, n_lo=n_lo, n_hi=n_hi)
+
+
+def serving_leg(graphs_k, arrivals, n_lo, n_hi, inflight, seed=0):
+    """Many resident graphs behind one server: closed-loop capacity with and
+    without merged rounds, then Poisson arrivals for per-batch latency."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import numpy as np
+    from paper_1904_08553_amd import dc
+    rng = np.random.default_rng(np.random.SeedSequence((seed, 77)))
+    pick = rng.integers(0, graphs_k, size=arrivals)
+    per = np.bincount(pick, minlength=graphs_k)
+    t0 = time.perf_counter()
+    jobs = [(1000 + g, int(per[g]), n_lo, n_hi) for g in range(graphs_k)]
+    with cf.ProcessPoolExecutor(max_workers=8, mp_context=mp.get_context("spawn")) as ex:
+        graphs = list(ex.map(_serving_graph, jobs))
+    log(f"serving: {graphs_k} graphs, {arrivals} batches drawn in "
+        f"{time.perf_counter() - t0:.1f} s")
+    order = []  # (graph, its batch index) in arrival order
+    seen = [0] * graphs_k
+    for g in pick:
+        order.append((int(g), seen[g]))
+        seen[g] += 1
+
+    def run(max_inflight, gaps_ns):
+        srv = dc.Server(max_inflight=max_inflight)
+        gids = [srv.add_graph(n, u, v, w) for n, (u, v, w), _ in graphs]
+        base = time.monotonic_ns()
+        tickets = []
+        for (g, j), at in zip(order, gaps_ns):
+            due = base + int(at)
+            while time.monotonic_ns() < due:
+                pass
+            b = graphs[g][2][j]
+            tickets.append((g, b.size, srv.submit(gids[g], b.add_u, b.add_v, b.add_w, b.del_u,
+                                                  b.del_v, arrival_ns=due)))
+        lat, changes, first, last = [], 0, None, 0
+        for g, sz, tk in tickets:
+            _, _, (arr, start, done) = srv.poll(tk, gids[g])
+            lat.append((done - arr) / 1e6)
+            changes += sz
+            first = arr if first is None else min(first, arr)
+            last = max(last, done)
+        st = srv.stats()
+        srv.close()
+        span = (last - first) / 1e9
+        return dict(edge_updates_per_s=changes / span, batches_per_s=len(tickets) / span,
+                    latency_ms={"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                                "max": max(lat)},
+                    seconds=span, rounds=st["rounds"], merged_rounds=st["merged_rounds"],
+                    graphs_per_round=st["merged_graphs"] / max(st["rounds"], 1),
+                    peak_resident_bytes=st["peak_resident_bytes"])
+
+    zero = [0] * len(order)
+    out = {"workload": f"{graphs_k} DC-SBM graphs, n log-uniform in [{n_lo}, {n_hi}], 20 "
+                       f"edges per vertex; {arrivals} batches of U[100K, 200K] changes (60/40), "
+                       f"graph uniform per arrival",
+           "closed_loop_sequential": run(1, zero),
+           "closed_loop_merged": run(inflight, zero)}
+    cap = out["closed_loop_merged"]["batches_per_s"]
+    rate = 0.7 * cap
+    gaps = np.cumsum(rng.exponential(1e9 / rate, size=arrivals))
+    poisson = run(inflight, gaps)
+    poisson["arrival_rate_per_s"] = rate
+    out["poisson_70pct_capacity"] = poisson
+    out["max_inflight"] = inflight
+    out["merged_over_sequential"] = (out["closed_loop_merged"]["edge_updates_per_s"]
+                                     / out["closed_loop_sequential"]["edge_updates_per_s"])
+    return out
+
+
+def learned_leg(seeds, workers=8):
+    """Fresh graphs of the screener's workload under full re-evaluation,
+    plain Delta-screening and the trained screener (committed weights)."""
+    from paper_1904_08553_amd import screener as S
+    w, theta, info = S.load()
+    res = S.evaluate(seeds, w, theta, workers)
+    out = S.summarize(res)
+    out["workload"] = ("planted partition, 100-vertex blocks, n log-uniform in [100K, 1M], 4 "
+                       "batches of 7.3% insertions / 2.9% deletions; fresh seeds "
+                       f"{seeds[0]}..{seeds[-1]}")
+    out["theta"] = theta
+    out["training"] = {k: info.get(k) for k in ("train_graphs", "train_samples", "epochs",
+                                                "val_recall", "val_selected_frac", "train_s")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +218,13 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-recompute replay")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-screener leg")
+    ap.add_argument("--learned-seeds", type=int, default=4)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-graphs", type=int, default=12)
+    ap.add_argument("--serving-batches", type=int, default=360)
+    ap.add_argument("--serving-nmax", type=int, default=200_000)
+    ap.add_argument("--serving-inflight", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run three plain device-to-device copies of BYTES bytes (a "
                          "reference kernel of known traffic for hardware byte counters)")
@@ -225,6 +323,13 @@ def main():
             "launches": d["k_launch"], "avg_launch_us": d["k_ms"] * 1e3 / d["k_launch"],
             "bytes_per_launch": d["k_bytes"] / d["k_launch"],
         }
+    if not args.no_learned:
+        log("learned-screener leg")
+        out["learned"] = learned_leg(list(range(10000, 10000 + args.learned_seeds)))
+    if not args.no_serving:
+        log("serving leg")
+        out["serving"] = serving_leg(args.serving_graphs, args.serving_batches, 10_000,
+                                     args.serving_nmax, args.serving_inflight)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.n, graph, batches, args.cpu_steps)

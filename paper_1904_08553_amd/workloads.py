@@ -398,6 +398,31 @@ def screener_graph(seed, n=None, n_lo=100_000, n_hi=1_000_000, steps=4, ins_frac
     return n, (u, v, w), batches
 
 
+def serving_graph(seed, batches, n=None, n_lo=10_000, n_hi=2_000_000, size_lo=100_000,
+                  size_hi=200_000, ins_frac=0.6):
+    """One graph of the serving workload: degree-corrected SBM shaped like
+    the 1M/20M stream (20 edges per vertex, max(10, n/1000) blocks), n
+    log-uniform in [n_lo, n_hi] unless given, and ``batches`` batches of
+    U[size_lo, size_hi] changes (``ins_frac`` insertions) clipped to the
+    current edge count, deletions to at most 40% of it.
+    Returns (n, (u, v, w), [Batch])."""
+    r = _rng(seed, 51)
+    if n is None:
+        n = int(round(np.exp(r.uniform(np.log(n_lo), np.log(n_hi)))))
+    gen = DCSBM(n=n, m=20 * n, blocks=max(10, n // 1000), dmax=min(5000, n // 2), seed=seed)
+    u, v, w = gen.graph()
+    es = EdgeSet.from_edges(u, v, w)
+    out = []
+    for t in range(batches):
+        size = min(int(r.integers(size_lo, size_hi + 1)), len(es))
+        n_del = min(int(round(size * (1 - ins_frac))), int(0.4 * len(es)))
+        b = gen.next_batch(es, t, frac=size / max(len(es), 1),
+                           ins_frac=1.0 - n_del / max(size, 1))
+        es.apply(b)
+        out.append(b)
+    return n, (u, v, w), out
+
+
 def random_dynamic(n, m, steps, n_add, n_del, seed, wmax=3):
     """Uniform random graph and batches (used for tiny exhaustive tests)."""
     rng = _rng(seed, 31)
