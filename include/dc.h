@@ -93,7 +93,10 @@ typedef struct dc_options {
                               samples (dc_last_samples): features of the
                               touched vertices and their move labels under a
                               full re-evaluation of level 0; default 0      */
-  int32_t pad;             /* must be zero                                   */
+  int32_t full_coarsen;    /* 1: build every level-0 compaction from all of
+                              G_t; 0 (default): from the previous step's
+                              graph of communities, the batch's changes and
+                              the level-0 movers' rows (same result)       */
   int64_t reserved[3];     /* must be zero                                   */
 } dc_options;
 

@@ -35,7 +35,7 @@ bool options_ok(const dc_options* o) {
   if (!o) return false;
   if (o->mode < DC_MODE_DELTA || o->mode > DC_MODE_LEARNED) return false;
   if (o->collect != 0 && o->collect != 1) return false;
-  if (o->pad != 0) return false;
+  if (o->full_coarsen != 0 && o->full_coarsen != 1) return false;
   if (o->max_levels < 1 || o->max_sweeps < 1) return false;
   if (o->del_rule != DC_DEL_GAIN && o->del_rule != DC_DEL_CONSERVATIVE) return false;
   if (o->tau_den < 0) return false;
@@ -213,8 +213,17 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
     const int next = level % 2;
     const int32_t* cnt_in = level == 0 ? nullptr : c->cnt[(level - 1) % 2].as<int32_t>();
     const int32_t* minv_in = level == 0 ? nullptr : c->minv[(level - 1) % 2].as<int32_t>();
-    coarsen(g, Cl, szl, al, cnt_in, minv_in, level == 0, c->n, c->map0.as<int32_t>(),
-            c->cg[next], c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, st);
+    const bool inc = level == 0 && c->inc.valid && c->inc_ready &&
+                     c->opt.mode != DC_MODE_STATIC && !c->opt.full_coarsen;
+    if (inc)
+      coarsen_first_inc(g, Cl, c->C.as<int32_t>(), szl, al, c->ch_key.as<uint64_t>(),
+                        c->ch_dk.as<int32_t>(), c->nch_last, c->map0.as<int32_t>(), c->cg[next],
+                        c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, c->inc,
+                        st);
+    else
+      coarsen(g, Cl, szl, al, cnt_in, minv_in, level == 0, c->n, c->map0.as<int32_t>(),
+              c->cg[next], c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, st);
+    if (level == 0) save_level1(c->cg[next], c->cs, c->minv[next].as<int32_t>(), c->inc, st);
     g = c->cg[next].view();
     start_level(Cl, Cn, al, szl, g.k, g.n, st);
     level++;
@@ -227,6 +236,8 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
   finalize_labels(g.n, Cl, al, szl, cntL, minvL, c->n, c->map0.as<int32_t>(),
                   c->lab.as<int32_t>(), c->cntf.as<int32_t>(), c->C.as<int32_t>(),
                   c->a0.as<int32_t>(), c->sz0.as<int32_t>(), st);
+  inc_finish(c->inc, c->C.as<int32_t>(), c->n, c->cs, st);  // H(G_t, C_t) for the next step
+  c->inc_ready = false;
   // exact numerator on the final level (coarsening preserves N)
   long long* stat = c->stat.as<long long>();
   DC_HIP(hipMemsetAsync(stat + ST_I, 0, 16, st));
@@ -379,6 +390,7 @@ dc_status do_init(dc_ctx* c, const dc_edges* g1) {
   load_level0_partition(c);
   c->stats = dc_step_stats{};
   c->stats.R_size = c->n;
+  c->inc_ready = false;
   run_levels(c, nullptr, c->n);
   c->have_R_all = true;
   return DC_OK;
@@ -462,6 +474,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   scan_excl_i32(rheads, rpos, nr, reinterpret_cast<int32_t*>(stat + ST_N1), st);
   read_stat(c);
   const int64_t nch = nr > 0 ? int32_t(hs[ST_N1]) : 0;
+  c->nch_last = nch;
   uint64_t* ch_key = c->ch_key.as<uint64_t>();
   int32_t* ch_op = c->ch_op.as<int32_t>();
   int32_t* ch_w = c->ch_w.as<int32_t>();
@@ -603,6 +616,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       S.screened = 1;
     }
   }
+  c->inc_ready = true;
   if (mode == DC_MODE_DELTA || mode == DC_MODE_LEARNED) {
     c->have_R_all = false;
     load_level0_partition(c);
@@ -698,7 +712,11 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->cs.mstart, &c->cs.labof, &c->cs.mdeg, &c->cs.mvol, &c->cs.chead,
                   &c->cs.cpos, &c->cs.chunks, &c->cs.mcnt, &c->cs.pk0, &c->cs.pk1, &c->cs.pv0,
                   &c->cs.pv1, &c->cs.ph, &c->cs.pp, &c->cs.pS, &c->cs.pcnt, &c->cs.hidx,
-                  &c->cs.ukey, &c->cs.rc})
+                  &c->cs.ukey, &c->cs.rc, &c->inc.hkey, &c->inc.hw, &c->inc.lkey, &c->inc.lw,
+                  &c->inc.lminv, &c->inc.ek0, &c->inc.ek1, &c->inc.ev0, &c->inc.ev1,
+                  &c->inc.heads, &c->inc.hpos, &c->inc.v64, &c->inc.S, &c->inc.starts,
+                  &c->inc.nz, &c->inc.npos, &c->inc.mflag, &c->inc.mvol, &c->inc.tkey,
+                  &c->inc.tw})
     f(*b);
 }
 
@@ -729,6 +747,8 @@ void ctx_evict(dc_ctx* c, SavedState& s) {
   DC_HIP(hipMemcpyAsync(s.sz.data(), c->sz0.p, n * 4, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
   for_each_buf(c, [](DBuf& b) { b.release(); });
+  c->inc.valid = false;  // the first step after restore compacts from all of G_t
+  c->inc.h = 0;
 }
 
 void ensure_vertex_state(dc_ctx* c);

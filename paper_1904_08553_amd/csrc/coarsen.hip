@@ -11,6 +11,8 @@
 // CSR with sorted rows -- no global atomics on hot rows (a hub community's
 // diagonal gets one partial per chunk).
 #include <cstring>
+#include <stdexcept>
+#include <utility>
 
 #include "dc_louvain.h"
 
@@ -314,6 +316,140 @@ __global__ void k_final_project(const int32_t* __restrict__ lab,
   GRID_STRIDE(v, n0) { C0[v] = lab[CL[map0[v]]]; }
 }
 
+
+// ---- incremental first-level compaction ----------------------------------
+
+__global__ void k_mover_vol(const int32_t* __restrict__ Cl, const int32_t* __restrict__ Cold,
+                            const int32_t* __restrict__ off, int32_t n, int32_t* mvol) {
+  GRID_STRIDE(v, n) { mvol[v] = Cl[v] != Cold[v] ? off[v + 1] - off[v] : 0; }
+}
+
+// Entry q of mover u's row (u -> v, weight w) owns four slots from
+// 4 * (mpos[u] + q): w leaves (Cold u, Cold v) and joins (Cl u, Cl v); when v
+// did not move, the mirror entry (v -> u) moves the same way (a moving v's
+// own row carries it, so its mirror slots get weight 0).
+__global__ void __launch_bounds__(TPB)
+    k_emit_movers(const int32_t* __restrict__ Cl, const int32_t* __restrict__ Cold,
+                  const int32_t* __restrict__ off, const int2* __restrict__ adj,
+                  const int32_t* __restrict__ mpos, int32_t n, uint64_t* keys, uint32_t* vals) {
+  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
+  const uint64_t N = uint64_t(n);
+  for (int64_t u = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; u < n;
+       u += nwaves) {
+    const int cu_old = Cold[u], cu_new = Cl[u];
+    if (cu_new == cu_old) continue;
+    const int32_t rb = off[u], re = off[u + 1];
+    const int64_t base = 4 * int64_t(mpos[u]);
+    for (int32_t q = rb + lane_id(); q < re; q += WAVE) {
+      const int2 e = adj[q];
+      const int vo = Cold[e.x], vn = Cl[e.x];
+      const bool still = vo == vn;
+      const int64_t at = base + 4 * int64_t(q - rb);
+      keys[at] = uint64_t(cu_old) * N + uint64_t(vo);
+      vals[at] = uint32_t(-e.y);
+      keys[at + 1] = uint64_t(cu_new) * N + uint64_t(vn);
+      vals[at + 1] = uint32_t(e.y);
+      keys[at + 2] = uint64_t(vo) * N + uint64_t(cu_old);
+      vals[at + 2] = still ? uint32_t(-e.y) : 0u;
+      keys[at + 3] = uint64_t(vn) * N + uint64_t(cu_new);
+      vals[at + 3] = still ? uint32_t(e.y) : 0u;
+    }
+  }
+}
+
+// The batch's directed changes between the old communities.
+__global__ void k_emit_changes(const uint64_t* __restrict__ ch_key,
+                               const int32_t* __restrict__ ch_dk, int64_t nch, int32_t n,
+                               const int32_t* __restrict__ Cold, uint64_t* keys, uint32_t* vals) {
+  GRID_STRIDE(i, nch) {
+    const uint64_t k = ch_key[i];
+    const int32_t u = int32_t(k / uint64_t(n)), v = int32_t(k % uint64_t(n));
+    keys[i] = uint64_t(Cold[u]) * uint64_t(n) + uint64_t(Cold[v]);
+    vals[i] = uint32_t(ch_dk[i]);
+  }
+}
+
+__global__ void k_signed_to_i64(const uint32_t* __restrict__ in, int64_t m, long long* out) {
+  GRID_STRIDE(i, m) { out[i] = (long long)int32_t(in[i]); }
+}
+
+__global__ void k_set_at(int32_t* arr, const int32_t* __restrict__ idx, int32_t v) {
+  arr[*idx] = v;
+}
+
+// Run of equal keys starting at head i: sum = S[end] - S[i] (S the exclusive
+// prefix sums); flags the runs whose sum is not zero.
+__global__ void k_run_sums(const int32_t* __restrict__ heads, const int32_t* __restrict__ hpos,
+                           const int32_t* __restrict__ starts, const long long* __restrict__ S,
+                           int64_t m, int32_t* nz, long long* rsum) {
+  GRID_STRIDE(i, m) {
+    int32_t f = 0;
+    long long w = 0;
+    if (heads[i]) {
+      w = S[starts[hpos[i] + 1]] - S[i];
+      f = w != 0 ? 1 : 0;
+    }
+    nz[i] = f;
+    rsum[i] = w;
+  }
+}
+
+__global__ void k_compact_runs(const uint64_t* __restrict__ keys, const int32_t* __restrict__ nz,
+                               const int32_t* __restrict__ npos, const long long* __restrict__ rsum,
+                               int64_t m, uint64_t* okey, int32_t* ow) {
+  GRID_STRIDE(i, m) {
+    if (nz[i]) {
+      okey[npos[i]] = keys[i];
+      ow[npos[i]] = int32_t(rsum[i]);
+    }
+  }
+}
+
+// Community-label entries to coarse ids; bad |= 1 for an entry that touches
+// an empty community or has a weight below 1 (cannot happen when H is the
+// graph of communities it claims to be).
+__global__ void k_inc_csr(const uint64_t* __restrict__ keys, const int32_t* __restrict__ w,
+                          int64_t cnt, const int32_t* __restrict__ rank,
+                          const int32_t* __restrict__ sz, int32_t n, int32_t nc, int2* adj,
+                          uint64_t* ukey, int32_t* bad) {
+  GRID_STRIDE(i, cnt) {
+    const int32_t X = int32_t(keys[i] / uint64_t(n)), Y = int32_t(keys[i] % uint64_t(n));
+    if (sz[X] <= 0 || sz[Y] <= 0 || w[i] < 1) {
+      *bad = 1;
+      adj[i] = make_int2(0, 0);
+      ukey[i] = 0;
+      continue;
+    }
+    const int32_t x = rank[X], y = rank[Y];
+    adj[i] = make_int2(y, w[i]);
+    ukey[i] = uint64_t(x) * uint64_t(nc) + uint64_t(y);
+  }
+}
+
+__global__ void k_adj_weights(const int2* __restrict__ adj, int64_t m, int32_t* w) {
+  GRID_STRIDE(i, m) { w[i] = adj[i].y; }
+}
+
+// Level-1 entries relabelled by the final labels of their vertices (the
+// final label of a level-0 community is that of any of its members);
+// broken = 1 when the new keys are not strictly increasing.
+__global__ void k_relabel(const uint64_t* __restrict__ lkey, int64_t m, int32_t nc,
+                          const int32_t* __restrict__ lminv, const int32_t* __restrict__ Ct,
+                          int32_t n, uint64_t* okey, int32_t* broken) {
+  GRID_STRIDE(i, m) {
+    const uint64_t k = lkey[i];
+    const uint64_t nk = uint64_t(Ct[lminv[int32_t(k / uint64_t(nc))]]) * uint64_t(n) +
+                        uint64_t(Ct[lminv[int32_t(k % uint64_t(nc))]]);
+    okey[i] = nk;
+    if (i > 0) {
+      const uint64_t kp = lkey[i - 1];
+      const uint64_t pk = uint64_t(Ct[lminv[int32_t(kp / uint64_t(nc))]]) * uint64_t(n) +
+                          uint64_t(Ct[lminv[int32_t(kp % uint64_t(nc))]]);
+      if (pk >= nk) *broken = 1;
+    }
+  }
+}
+
 }  // namespace
 
 void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int32_t* a,
@@ -458,6 +594,217 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
   }
   k_project<<<grid_for(n0), TPB, 0, st>>>(C, rank, n0, first_level, map0);
   DC_LAUNCH_CHECK();
+}
+
+namespace {
+
+void swap_buf(DBuf& x, DBuf& y) {
+  std::swap(x.p, y.p);
+  std::swap(x.bytes, y.bytes);
+}
+
+// Sums runs of equal keys of a sorted list (values: int32 bit patterns) into
+// (okey, ow), dropping runs that sum to zero; returns the number kept.
+int64_t reduce_sorted(const uint64_t* keys, const uint32_t* vals, int64_t m, uint64_t* okey,
+                      int32_t* ow, IncCoarsen& H, int32_t* host, hipStream_t st) {
+  if (m <= 0) return 0;
+  const size_t mm = size_t(m) + 1;
+  H.heads.ensure(mm * 4);
+  H.hpos.ensure(mm * 4);
+  H.starts.ensure(mm * 4);
+  H.nz.ensure(mm * 4);
+  H.npos.ensure(mm * 4);
+  H.v64.ensure(mm * 8);
+  H.S.ensure(mm * 8);
+  int32_t* heads = H.heads.as<int32_t>();
+  int32_t* hpos = H.hpos.as<int32_t>();
+  int32_t* starts = H.starts.as<int32_t>();
+  int32_t* nz = H.nz.as<int32_t>();
+  int32_t* npos = H.npos.as<int32_t>();
+  long long* v64 = H.v64.as<long long>();
+  long long* S = H.S.as<long long>();
+  run_heads(keys, m, heads, st);
+  scan_excl_i32(heads, hpos, m, hpos + m, st);
+  compact_index(heads, hpos, m, starts, st);
+  k_set_at<<<1, 1, 0, st>>>(starts, hpos + m, int32_t(m));
+  DC_LAUNCH_CHECK();
+  k_signed_to_i64<<<grid_for(m), TPB, 0, st>>>(vals, m, v64);
+  DC_LAUNCH_CHECK();
+  scan_excl_i64(reinterpret_cast<int64_t*>(v64), reinterpret_cast<int64_t*>(S), m,
+                reinterpret_cast<int64_t*>(S + m), st);
+  k_run_sums<<<grid_for(m), TPB, 0, st>>>(heads, hpos, starts, S, m, nz, v64);
+  DC_LAUNCH_CHECK();
+  scan_excl_i32(nz, npos, m, npos + m, st);
+  k_compact_runs<<<grid_for(m), TPB, 0, st>>>(keys, nz, npos, v64, m, okey, ow);
+  DC_LAUNCH_CHECK();
+  DC_HIP(hipMemcpyAsync(host, npos + m, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  return host[0];
+}
+
+}  // namespace
+
+void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Cold,
+                       const int32_t* sz, const int32_t* a, const uint64_t* ch_key,
+                       const int32_t* ch_dk, int64_t nch, int32_t* map0, CoarseGraph& out,
+                       int32_t* cnt_out, int32_t* minv_out, CoarsenScratch& s, IncCoarsen& H,
+                       hipStream_t st) {
+  const int32_t nl = g.n;
+  int32_t* host = static_cast<int32_t*>(s.host);
+  // ranks of the non-empty labels (as coarsen)
+  s.flag.ensure(size_t(nl + 1) * 4);
+  s.rank.ensure(size_t(nl + 1) * 4);
+  int32_t* flag = s.flag.as<int32_t>();
+  int32_t* rank = s.rank.as<int32_t>();
+  k_nonempty<<<grid_for(nl), TPB, 0, st>>>(sz, nl, flag);
+  DC_LAUNCH_CHECK();
+  scan_excl_i32(flag, rank, nl, rank + nl, st);
+  // movers' row volumes
+  H.mvol.ensure(size_t(nl + 1) * 4);
+  H.mflag.ensure(size_t(nl + 1) * 4);
+  int32_t* mvol = H.mvol.as<int32_t>();
+  int32_t* mpos = H.mflag.as<int32_t>();
+  k_mover_vol<<<grid_for(nl), TPB, 0, st>>>(Cl, Cold, g.off, nl, mvol);
+  DC_LAUNCH_CHECK();
+  scan_excl_i32(mvol, mpos, nl, mpos + nl, st);
+  DC_HIP(hipMemcpyAsync(host, rank + nl, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(host + 1, mpos + nl, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  const int32_t nc = host[0];
+  const int64_t vol = host[1];
+
+  // members grouped by coarse id: counts and smallest members (as coarsen)
+  s.keys0.ensure(size_t(nl) * 8);
+  s.keys1.ensure(size_t(nl) * 8);
+  s.vals0.ensure(size_t(nl) * 4);
+  s.vals1.ensure(size_t(nl) * 4);
+  uint64_t* rkey = s.keys0.as<uint64_t>();
+  uint32_t* members = s.vals0.as<uint32_t>();
+  s.rc.ensure(size_t(nl + 1) * 4);
+  k_member_pairs<<<grid_for(nl), TPB, 0, st>>>(Cl, rank, nl, rkey, members, s.rc.as<int32_t>());
+  DC_LAUNCH_CHECK();
+  radix_sort_pairs(rkey, members, s.keys1.as<uint64_t>(), s.vals1.as<uint32_t>(), nl,
+                   ilog2_ceil(uint64_t(nc)), st);
+  s.cntr.ensure(size_t(nc + 1) * 4);
+  s.mstart.ensure(size_t(nc + 1) * 4);
+  s.labof.ensure(size_t(nc + 1) * 4);
+  int32_t* cntr = s.cntr.as<int32_t>();
+  int32_t* mstart = s.mstart.as<int32_t>();
+  int32_t* labof = s.labof.as<int32_t>();
+  k_comm_info<<<grid_for(nl), TPB, 0, st>>>(flag, rank, sz, nl, cntr, labof);
+  DC_LAUNCH_CHECK();
+  scan_excl_i32(cntr, mstart, nc, mstart + nc, st);
+
+  // H(G_{t-1}, C_{t-1}) + the batch's changes + the movers' rows, one sort
+  const int64_t h = H.h, m = h + nch + 4 * vol;
+  H.ek0.ensure(size_t(m + 1) * 8);
+  H.ek1.ensure(size_t(m + 1) * 8);
+  H.ev0.ensure(size_t(m + 1) * 4);
+  H.ev1.ensure(size_t(m + 1) * 4);
+  uint64_t* ek = H.ek0.as<uint64_t>();
+  uint32_t* ev = H.ev0.as<uint32_t>();
+  if (h > 0) {
+    DC_HIP(hipMemcpyAsync(ek, H.hkey.p, size_t(h) * 8, hipMemcpyDeviceToDevice, st));
+    DC_HIP(hipMemcpyAsync(ev, H.hw.p, size_t(h) * 4, hipMemcpyDeviceToDevice, st));
+  }
+  if (nch > 0) {
+    k_emit_changes<<<grid_for(nch), TPB, 0, st>>>(ch_key, ch_dk, nch, nl, Cold, ek + h, ev + h);
+    DC_LAUNCH_CHECK();
+  }
+  if (vol > 0) {
+    k_emit_movers<<<grid_for(int64_t(nl) * WAVE), TPB, 0, st>>>(Cl, Cold, g.off, g.adj, mpos, nl,
+                                                              ek + h + nch, ev + h + nch);
+    DC_LAUNCH_CHECK();
+  }
+  radix_sort_pairs(ek, ev, H.ek1.as<uint64_t>(), H.ev1.as<uint32_t>(), m,
+                   ilog2_ceil(uint64_t(nl) * uint64_t(nl)), st);
+  H.tkey.ensure(size_t(m + 1) * 8);
+  H.tw.ensure(size_t(m + 1) * 4);
+  const int64_t cnnz = reduce_sorted(ek, ev, m, H.tkey.as<uint64_t>(), H.tw.as<int32_t>(), H,
+                                     host, st);
+
+  // coarse CSR over coarse ids (rows come out sorted: ranks keep label order)
+  out.off.ensure(size_t(nc + 1) * 4);
+  out.adj.ensure(size_t(cnnz + 1) * 8);
+  out.k.ensure(size_t(nc + 1) * 4);
+  s.ukey.ensure(size_t(cnnz + 1) * 8);
+  s.pcnt.ensure(8);
+  int32_t* bad = s.pcnt.as<int32_t>();
+  fill_i32(bad, 0, 1, st);
+  if (cnnz > 0) {
+    k_inc_csr<<<grid_for(cnnz), TPB, 0, st>>>(H.tkey.as<uint64_t>(), H.tw.as<int32_t>(), cnnz,
+                                              rank, sz, nl, nc, out.adj.as<int2>(),
+                                              s.ukey.as<uint64_t>(), bad);
+    DC_LAUNCH_CHECK();
+  }
+  DC_HIP(hipMemcpyAsync(host, bad, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  if (host[0]) throw std::runtime_error("incremental coarsening: inconsistent community graph");
+  row_bounds(s.ukey.as<uint64_t>(), cnnz, nc, out.off.as<int32_t>(), st);
+  k_coarse_k<<<grid_for(nc), TPB, 0, st>>>(labof, a, nc, out.k.as<int32_t>());
+  DC_LAUNCH_CHECK();
+  out.n = nc;
+  out.nnz = cnnz;
+  k_first_level_meta<<<grid_for(nc), TPB, 0, st>>>(labof, sz, mstart, members, nc, cnt_out,
+                                                   minv_out);
+  DC_LAUNCH_CHECK();
+  k_project<<<grid_for(nl), TPB, 0, st>>>(Cl, rank, nl, true, map0);
+  DC_LAUNCH_CHECK();
+}
+
+void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,
+                 IncCoarsen& H, hipStream_t st) {
+  H.lkey.ensure(size_t(out.nnz + 1) * 8);
+  H.lw.ensure(size_t(out.nnz + 1) * 4);
+  H.lminv.ensure(size_t(out.n + 1) * 4);
+  if (out.nnz > 0) {
+    DC_HIP(hipMemcpyAsync(H.lkey.p, s.ukey.p, size_t(out.nnz) * 8, hipMemcpyDeviceToDevice, st));
+    k_adj_weights<<<grid_for(out.nnz), TPB, 0, st>>>(out.adj.as<int2>(), out.nnz,
+                                                      H.lw.as<int32_t>());
+    DC_LAUNCH_CHECK();
+  }
+  if (out.n > 0)
+    DC_HIP(hipMemcpyAsync(H.lminv.p, minv, size_t(out.n) * 4, hipMemcpyDeviceToDevice, st));
+  H.lh = out.nnz;
+  H.lnc = out.n;
+}
+
+void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
+                hipStream_t st) {
+  int32_t* host = static_cast<int32_t*>(s.host);
+  const int64_t m = H.lh;
+  H.tkey.ensure(size_t(m + 1) * 8);
+  H.hw.ensure(size_t(m + 1) * 4);
+  H.mflag.ensure(8);
+  int32_t* broken = H.mflag.as<int32_t>();
+  fill_i32(broken, 0, 1, st);
+  if (m > 0) {
+    k_relabel<<<grid_for(m), TPB, 0, st>>>(H.lkey.as<uint64_t>(), m, H.lnc,
+                                           H.lminv.as<int32_t>(), Ct, n, H.tkey.as<uint64_t>(),
+                                           broken);
+    DC_LAUNCH_CHECK();
+  }
+  DC_HIP(hipMemcpyAsync(host, broken, 4, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  if (!host[0]) {
+    // the final labels keep the order: the relabelled list is H(G_t, C_t)
+    swap_buf(H.hkey, H.tkey);
+    if (m > 0)
+      DC_HIP(hipMemcpyAsync(H.hw.p, H.lw.p, size_t(m) * 4, hipMemcpyDeviceToDevice, st));
+    H.h = m;
+  } else {
+    // communities merged above level 0, or labels changed order: re-sort
+    H.ev0.ensure(size_t(m + 1) * 4);
+    H.ek1.ensure(size_t(m + 1) * 8);
+    H.ev1.ensure(size_t(m + 1) * 4);
+    H.hkey.ensure(size_t(m + 1) * 8);
+    DC_HIP(hipMemcpyAsync(H.ev0.p, H.lw.p, size_t(m) * 4, hipMemcpyDeviceToDevice, st));
+    radix_sort_pairs(H.tkey.as<uint64_t>(), H.ev0.as<uint32_t>(), H.ek1.as<uint64_t>(),
+                     H.ev1.as<uint32_t>(), m, ilog2_ceil(uint64_t(n) * uint64_t(n)), st);
+    H.h = reduce_sorted(H.tkey.as<uint64_t>(), H.ev0.as<uint32_t>(), m, H.hkey.as<uint64_t>(),
+                        H.hw.as<int32_t>(), H, host, st);
+  }
+  H.valid = true;
 }
 
 void finalize_labels(int32_t nL, const int32_t* CL, const int32_t* aL, const int32_t* szL,

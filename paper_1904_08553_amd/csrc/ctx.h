@@ -47,6 +47,10 @@ struct dc_ctx {
   dc_step_stats stats{};
   int64_t R_count = 0;
   bool have_R_all = true;
+  // graph of communities kept across steps (incremental level-0 compaction)
+  IncCoarsen inc;
+  int64_t nch_last = 0;     // change records of the current batch
+  bool inc_ready = false;   // they belong to the step being run
 };
 
 namespace dc_core {

@@ -210,6 +210,40 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
              int32_t* map0, CoarseGraph& out, int32_t* cnt_out, int32_t* minv_out,
              CoarsenScratch& s, hipStream_t st);
 
+// ---- incremental first-level compaction (coarsen.hip) ----
+// H(G, C): the graph of communities of the current graph and partition,
+// keys X*n + Y over community labels, weights > 0, sorted and unique; plus
+// the last level-1 graph (keys x*nc + y over coarse ids, weights) and the
+// smallest level-0 member of each of its vertices, from which the next H
+// is relabelled once the final labels are known.
+struct IncCoarsen {
+  DBuf hkey, hw;
+  int64_t h = 0;
+  bool valid = false;
+  DBuf lkey, lw, lminv;
+  int64_t lh = 0;
+  int32_t lnc = 0;
+  DBuf ek0, ek1, ev0, ev1, heads, hpos, v64, S, starts, nz, npos, mflag, mvol, tkey, tw;
+};
+
+// Level 0 -> 1 from H(G_{t-1}, C_{t-1}) instead of all of G_t: H plus the
+// batch's directed changes mapped by Cold = C_{t-1} (ch_key / ch_dk, nch
+// records) plus the rows of the level-0 movers (Cl != Cold) moved from their
+// old labels to their new ones, summed by one sort; the result (entries of
+// zero weight dropped) is the coarse graph of (G_t, Cl), numbered as
+// coarsen() numbers it.  Outputs as coarsen(first_level = true).
+void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Cold,
+                       const int32_t* sz, const int32_t* a, const uint64_t* ch_key,
+                       const int32_t* ch_dk, int64_t nch, int32_t* map0, CoarseGraph& out,
+                       int32_t* cnt_out, int32_t* minv_out, CoarsenScratch& s, IncCoarsen& H,
+                       hipStream_t st);
+// Keeps the level-1 graph just built (and its vertices' smallest members).
+void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,
+                 IncCoarsen& H, hipStream_t st);
+// H(G_t, C_t) from the saved level-1 graph and the final labels C_t.
+void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
+                hipStream_t st);
+
 // Canonical labels of the final partition (smallest level-0 id per
 // community), the level-0 totals and sizes by label, and C_t.
 void finalize_labels(int32_t nL, const int32_t* CL, const int32_t* aL, const int32_t* szL,

@@ -31,7 +31,7 @@ class Options(ct.Structure):
         ("mode", ct.c_int32), ("max_levels", ct.c_int32), ("max_sweeps", ct.c_int32),
         ("singleton_guard", ct.c_int32), ("del_rule", ct.c_int32), ("timing", ct.c_int32),
         ("tau_den", ct.c_int64), ("stream", ct.c_void_p), ("collect", ct.c_int32),
-        ("pad", ct.c_int32), ("reserved", ct.c_int64 * 3),
+        ("full_coarsen", ct.c_int32), ("reserved", ct.c_int64 * 3),
     ]
 
 
@@ -229,12 +229,14 @@ def current_stream():
 
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
-            del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current", collect=0):
+            del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current", collect=0,
+            full_coarsen=0):
     o = Options()
     load().dc_default_options(ct.byref(o))
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.timing, o.tau_den = singleton_guard, del_rule, timing, tau_den
     o.collect = collect
+    o.full_coarsen = full_coarsen
     o.stream = current_stream() if stream == "current" else stream
     return o
 

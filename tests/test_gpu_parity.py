@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 from gpu_common import compare, make_pair, step_pair
+from oracle import oracle as O
 from paper_1904_08553_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -147,3 +148,32 @@ def test_replace_and_duplicate_insertions():
     offo, colo, wo = o.csr()
     offg, colg, wg = g.csr()
     assert np.array_equal(offo, offg) and np.array_equal(colo, colg) and np.array_equal(wo, wg)
+
+
+@pytest.mark.parametrize("graph", ["planted", "dcsbm", "random"])
+def test_full_and_incremental_coarsening_agree(graph):
+    """Level-0 compaction from all of G_t (full_coarsen=1) and from the
+    previous graph of communities plus the batch and the movers (default)
+    give the same run, and both equal the oracle, over several steps."""
+    _log(f"case: full vs incremental compaction {graph}")
+    if graph == "planted":
+        pp = W.PlantedPartition()
+        (u, v, w), batches = pp.batches()
+        n = pp.n
+    elif graph == "dcsbm":
+        gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=5)
+        (u, v, w), it = gen.stream(4, frac=0.02)
+        batches, n = list(it), gen.n
+    else:
+        (u, v, w), batches = W.random_dynamic(40, 120, 6, 20, 12, seed=4242)
+        n = 40
+    o = O.Oracle(n, u, v, w)
+    from paper_1904_08553_amd import dc
+    gi = dc.DynamicCommunities(n, u, v, w)
+    gf = dc.DynamicCommunities(n, u, v, w, full_coarsen=1)
+    for t, b in enumerate(batches):
+        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+        for g in (gi, gf):
+            g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+            compare(o, g, f"step {t}")
+        assert gi.last_trace() == gf.last_trace()
