@@ -415,73 +415,43 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   validate_edges(du, dv, nullptr, nd, n, flags, nullptr, st);
   validate_edges(au, av, aw, na, n, flags, stat + ST_WSUM_ADD, st);
   const int bits = sort_bits(n);
-  // deletions: canonical, sorted, unique, present in G_{t-1}
-  c->dkeys.ensure(size_t(nd + 1) * 8);
-  c->dk1.ensure(size_t(nd + 1) * 8);
-  c->dvals.ensure(size_t(nd + 1) * 4);
-  c->dv1.ensure(size_t(nd + 1) * 4);
-  c->dw_old.ensure(size_t(nd + 1) * 4);
-  uint64_t* dkeys = c->dkeys.as<uint64_t>();
-  make_canonical(du, dv, nd, n, dkeys, c->dvals.as<uint32_t>(), st);
-  radix_sort_pairs(dkeys, c->dvals.as<uint32_t>(), c->dk1.as<uint64_t>(), c->dv1.as<uint32_t>(),
-                   nd, bits, st);
-  detect_dups(dkeys, nd, flags, st);
+  // every deletion and insertion as two directed records, sorted once; a
+  // run of equal keys is one directed pair of the batch
   const int32_t* off_old = c->off[c->cur].as<int32_t>();
   const int2* adj_old = c->adj[c->cur].as<int2>();
-  lookup_deleted(dkeys, nd, n, off_old, adj_old, c->dw_old.as<int32_t>(), flags,
-                 stat + ST_WSUM_DEL, st);
-  // insertions: canonical, sorted, duplicates summed
-  c->akeys.ensure(size_t(na + 1) * 8);
-  c->ak1.ensure(size_t(na + 1) * 8);
-  c->avals.ensure(size_t(na + 1) * 4);
-  c->av1.ensure(size_t(na + 1) * 4);
-  c->aheads.ensure(size_t(na + 1) * 4);
-  c->apos.ensure(size_t(na + 1) * 4);
-  uint64_t* akeys = c->akeys.as<uint64_t>();
-  uint32_t* avals = c->avals.as<uint32_t>();
-  make_canonical(au, av, na, n, akeys, avals, st);
-  radix_sort_pairs(akeys, avals, c->ak1.as<uint64_t>(), c->av1.as<uint32_t>(), na, bits, st);
-  run_heads(akeys, na, c->aheads.as<int32_t>(), st);
-  int32_t* apos = c->apos.as<int32_t>();
-  scan_excl_i32(c->aheads.as<int32_t>(), apos, na, reinterpret_cast<int32_t*>(stat + ST_N0), st);
+  const int64_t nr = 2 * (nd + na);
+  for (DBuf* b : {&c->rkeys, &c->rk1, &c->ch_key, &c->ukeys}) b->ensure(size_t(nr + 1) * 8);
+  for (DBuf* b : {&c->rvals, &c->rv1, &c->rheads, &c->rpos, &c->ch_op, &c->ch_w, &c->ch_dk,
+                  &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->ins_flag, &c->ins_pos,
+                  &c->src_flag, &c->src_pos, &c->src_list, &c->uw, &c->dw_old})
+    b->ensure(size_t(nr + 1) * 4);
+  c->ins_keys.ensure(size_t(nr + 1) * 8);
+  uint64_t* rkeys = c->rkeys.as<uint64_t>();
+  uint32_t* rvals = c->rvals.as<uint32_t>();
+  batch_records(du, dv, nd, au, av, na, n, rkeys, rvals, st);
+  radix_sort_pairs(rkeys, rvals, c->rk1.as<uint64_t>(), c->rv1.as<uint32_t>(), nr, bits, st);
+  int32_t* rheads = c->rheads.as<int32_t>();
+  int32_t* rpos = c->rpos.as<int32_t>();
+  run_heads(rkeys, nr, rheads, st);
+  int32_t* nruns = reinterpret_cast<int32_t*>(stat + ST_N1);
+  scan_excl_i32(rheads, rpos, nr, nruns, st);
+  uint64_t* ch_key = c->ch_key.as<uint64_t>();
+  int32_t* ch_op = c->ch_op.as<int32_t>();
+  int32_t* ch_w = c->ch_w.as<int32_t>();
+  int32_t* ch_dk = c->ch_dk.as<int32_t>();
+  resolve_changes(rkeys, rvals, rpos, nr, nruns, aw, n, off_old, adj_old,
+                  c->ukeys.as<uint64_t>(), c->uw.as<int32_t>(), c->dw_old.as<int32_t>(), ch_key,
+                  ch_op, ch_w, ch_dk, c->is_del.as<int32_t>(), c->is_new.as<int32_t>(), flags,
+                  stat + ST_WSUM_DEL, st);
   read_stat(c);
   // checks in the documented order; nothing has been changed yet
   if (int32_t f = int32_t(hs[ST_FLAGS])) return status_from_flags(f);
   const long long two_m_new = c->two_m - 2 * hs[ST_WSUM_DEL] + 2 * hs[ST_WSUM_ADD];
   if (two_m_new >= TWO_M_LIMIT) return DC_E_OVERFLOW;
-  const int64_t na_u = na > 0 ? int32_t(hs[ST_N0]) : 0;
 
   // ---- from here on the state changes ----
-  c->ukeys.ensure(size_t(na_u + 1) * 8);
-  c->uw.ensure(size_t(na_u + 1) * 4);
-  fill_i32(c->uw.as<int32_t>(), 0, na_u, st);
-  reduce_runs(akeys, avals, aw, apos, na, c->ukeys.as<uint64_t>(), c->uw.as<int32_t>(), st);
-  // directed change records
-  const int64_t nr = 2 * (nd + na_u);
-  for (DBuf* b : {&c->rkeys, &c->rk1, &c->ch_key}) b->ensure(size_t(nr + 1) * 8);
-  for (DBuf* b : {&c->rvals, &c->rv1, &c->rheads, &c->rpos, &c->ch_op, &c->ch_w, &c->ch_dk,
-                  &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->ins_flag, &c->ins_pos,
-                  &c->src_flag, &c->src_pos, &c->src_list})
-    b->ensure(size_t(nr + 1) * 4);
-  c->ins_keys.ensure(size_t(nr + 1) * 8);
-  uint64_t* rkeys = c->rkeys.as<uint64_t>();
-  uint32_t* rvals = c->rvals.as<uint32_t>();
-  make_change_records(dkeys, nd, c->ukeys.as<uint64_t>(), na_u, n, rkeys, rvals, st);
-  radix_sort_pairs(rkeys, rvals, c->rk1.as<uint64_t>(), c->rv1.as<uint32_t>(), nr, bits, st);
-  int32_t* rheads = c->rheads.as<int32_t>();
-  int32_t* rpos = c->rpos.as<int32_t>();
-  run_heads(rkeys, nr, rheads, st);
-  scan_excl_i32(rheads, rpos, nr, reinterpret_cast<int32_t*>(stat + ST_N1), st);
-  read_stat(c);
   const int64_t nch = nr > 0 ? int32_t(hs[ST_N1]) : 0;
   c->nch_last = nch;
-  uint64_t* ch_key = c->ch_key.as<uint64_t>();
-  int32_t* ch_op = c->ch_op.as<int32_t>();
-  int32_t* ch_w = c->ch_w.as<int32_t>();
-  int32_t* ch_dk = c->ch_dk.as<int32_t>();
-  combine_changes(rkeys, rvals, nr, rheads, rpos, n, c->dw_old.as<int32_t>(),
-                  c->uw.as<int32_t>(), off_old, adj_old, ch_key, ch_op, ch_w, ch_dk,
-                  c->is_del.as<int32_t>(), c->is_new.as<int32_t>(), st);
   int32_t* cum_del = c->cum_del.as<int32_t>();
   int32_t* cum_new = c->cum_new.as<int32_t>();
   scan_excl_i32(c->is_del.as<int32_t>(), cum_del, nch, cum_del + nch, st);

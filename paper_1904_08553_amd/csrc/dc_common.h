@@ -100,20 +100,82 @@ inline uint32_t pow2_ceil32(uint32_t x) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// Butterfly step S of a cross-lane reduction.  Steps 0-3 exchange inside a
+// 16-lane row with DPP (quad xor 1, quad xor 2, half-row mirror, row
+// mirror), step 4 swaps the 16-lane halves of each 32 lanes (ds_swizzle):
+// after steps 0..log2(G)-1 every lane of an aligned group of G <= 32 lanes
+// has combined all G values.  The two 32-lane halves of a wave are then
+// joined with two readlanes.  No step goes through ds_bpermute.
+template <int S>
+__device__ __forceinline__ int xchg(int v) {
+  if constexpr (S == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (S == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (S == 2) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+  else if constexpr (S == 3) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+  else return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+}
+
+template <int S>
+__device__ __forceinline__ long long xchg64(long long v) {
+  const int lo = xchg<S>(int(uint32_t(uint64_t(v))));
+  const int hi = xchg<S>(int(uint32_t(uint64_t(v) >> 32)));
+  return (long long)((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
+__device__ __forceinline__ long long readlane64(long long v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(v))), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(v) >> 32)), l);
+  return (long long)((uint64_t(hi) << 32) | lo);
+}
+
+// Integer wave sums and maxima (exact, so the combining order is free).
+__device__ __forceinline__ int wave_sum(int v) {
+  v += xchg<0>(v);
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  v += xchg<3>(v);
+  v += xchg<4>(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
+}
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+  v += xchg64<0>(v);
+  v += xchg64<1>(v);
+  v += xchg64<2>(v);
+  v += xchg64<3>(v);
+  v += xchg64<4>(v);
+  return readlane64(v, 0) + readlane64(v, 32);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  return (unsigned long long)wave_sum((long long)v);
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  int y;
+  y = xchg<0>(v); v = y > v ? y : v;
+  y = xchg<1>(v); v = y > v ? y : v;
+  y = xchg<2>(v); v = y > v ? y : v;
+  y = xchg<3>(v); v = y > v ? y : v;
+  y = xchg<4>(v); v = y > v ? y : v;
+  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 32);
+  return a > b ? a : b;
+}
+
+__device__ __forceinline__ int wave_or(int v) {
+  v |= xchg<0>(v);
+  v |= xchg<1>(v);
+  v |= xchg<2>(v);
+  v |= xchg<3>(v);
+  v |= xchg<4>(v);
+  return __builtin_amdgcn_readlane(v, 0) | __builtin_amdgcn_readlane(v, 32);
+}
+
+// Other types (floating point): a fixed butterfly order through shuffles.
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-
-template <class T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    T y = __shfl_xor(v, o, WAVE);
-    v = y > v ? y : v;
-  }
   return v;
 }
 
@@ -128,17 +190,17 @@ __device__ __forceinline__ bool better(long long s, int x, long long bs,
   return s > bs || (s == bs && x < bx);
 }
 
+template <int S>
+__device__ __forceinline__ Best best_step(Best b) {
+  const Best y = {xchg64<S>(b.s), xchg<S>(b.x)};
+  return better(y.s, y.x, b.s, b.x) ? y : b;
+}
+
 __device__ __forceinline__ Best wave_best(Best b) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    long long s = __shfl_xor(b.s, o, WAVE);
-    int x = __shfl_xor(b.x, o, WAVE);
-    if (better(s, x, b.s, b.x)) {
-      b.s = s;
-      b.x = x;
-    }
-  }
-  return b;
+  b = best_step<4>(best_step<3>(best_step<2>(best_step<1>(best_step<0>(b)))));
+  const Best b0 = {readlane64(b.s, 0), __builtin_amdgcn_readlane(b.x, 0)};
+  const Best b1 = {readlane64(b.s, 32), __builtin_amdgcn_readlane(b.x, 32)};
+  return better(b1.s, b1.x, b0.s, b0.x) ? b1 : b0;
 }
 
 constexpr int EMPTY_KEY = -1;

@@ -94,35 +94,27 @@ void keys_to_adj(const uint64_t* keys, const int32_t* w, int64_t m, int32_t n,
 void row_weight_sums(const int32_t* off, const int2* adj, int32_t n,
                      int32_t* k, hipStream_t st);
 
-// flags |= F_DUP if two sorted canonical keys are equal.
-void detect_dups(const uint64_t* keys, int64_t m, int32_t* flags,
-                 hipStream_t st);
-
-// For sorted canonical deletions: the weight of the edge in G (or flag
-// F_NO_EDGE); *wsum += sum of the weights found.  Skips out-of-range ids.
-void lookup_deleted(const uint64_t* keys, int64_t m, int32_t n,
-                    const int32_t* off, const int2* adj, int32_t* w_old,
-                    int32_t* flags, long long* wsum, hipStream_t st);
-
 // Change records of a batch, sorted by directed key src*n+dst.
 enum ChangeOp : int32_t { OP_DELETE = 1, OP_ADD = 2, OP_NEW = 3, OP_REPLACE = 4 };
 
-// Directed records: for canonical deletion d: keys lo*n+hi and hi*n+lo with
-// value (d<<1)|0; for canonical insertion a: value (a<<1)|1.
-void make_change_records(const uint64_t* del_keys, int64_t nd,
-                         const uint64_t* ins_keys, int64_t na, int32_t n,
-                         uint64_t* rkeys, uint32_t* rvals, hipStream_t st);
+// Directed records of a batch: deletion e gives keys u*n+v and v*n+u with
+// value (e<<1)|0, insertion e the same keys with value (e<<1)|1.
+void batch_records(const int32_t* du, const int32_t* dv, int64_t nd, const int32_t* au,
+                   const int32_t* av, int64_t na, int32_t n, uint64_t* keys, uint32_t* vals,
+                   hipStream_t st);
 
-// Combines sorted records into one change per directed key (heads/pos from
-// run_heads + scan).  Writes ch_key, ch_op, ch_w (new weight for NEW and
-// REPLACE, added weight for ADD), ch_dk (change of the row's weighted
-// degree), is_del, is_new (0/1 per change).
-void combine_changes(const uint64_t* rkeys, const uint32_t* rvals, int64_t nr,
-                     const int32_t* heads, const int32_t* pos, int32_t n,
-                     const int32_t* del_w_old, const int32_t* ins_w,
-                     const int32_t* off, const int2* adj, uint64_t* ch_key,
-                     int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
-                     int32_t* is_del, int32_t* is_new, hipStream_t st);
+// One change per run of equal sorted record keys (pos: exclusive scan of the
+// run heads, *nruns on the device): ch_key, ch_op, ch_w (new weight for NEW
+// and REPLACE, added weight for ADD), ch_dk (change of the row's weighted
+// degree), is_del, is_new; flags |= F_DUP (a pair deleted twice) and
+// F_NO_EDGE (a deletion of a pair absent from off/adj); *wsum += the old
+// weights of the deleted edges.  run_key/run_w/run_ndel: scratch of m.
+void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* pos, int64_t m,
+                     const int32_t* nruns, const int32_t* ins_w, int32_t n, const int32_t* off,
+                     const int2* adj, uint64_t* run_key, int32_t* run_w, int32_t* run_ndel,
+                     uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
+                     int32_t* is_del, int32_t* is_new, int32_t* flags, long long* wsum,
+                     hipStream_t st);
 
 // Per row: new degree and degree-weight change; k += dk; a[C[u]] += dk.
 void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk,

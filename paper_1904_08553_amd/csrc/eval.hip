@@ -11,14 +11,14 @@
 // share one or a few communities, so a hash insert per entry would pile
 // atomics onto the same slot.  Instead a wave loads 64 entries, picks the
 // label of the first unprocessed lane, finds all lanes holding it with one
-// ballot, sums their weights with a wave reduction, and parks the pair in
-// the lane numbered by the iteration: one register-only iteration per
-// distinct label.  The community totals are then gathered (or the table
+// ballot and parks the label in the lane numbered by the iteration: one
+// register-only iteration per distinct label.  Each lane then adds its
+// weight into a per-wave LDS slot of its label's rank.  The community totals are then gathered (or the table
 // inserts issued) by all pair-holding lanes at once, so no chain of
 // dependent memory accesses remains.  Rows of up to 64 entries finish this
 // way (bin S, one wave per vertex).  Longer rows collect per 64-entry chunk
 // and add the chunk's pairs to a hash table: wave-private LDS for rows up
-// to 256 entries (bin W), a block-shared LDS table up to 4096 (bin B),
+// to 512 entries (bin W), a block-shared LDS table up to 4096 (bin B),
 // global memory beyond (bin G).  A sweep writes only the next label;
 // movers are collected afterwards.
 #include "dc_louvain.h"
@@ -41,35 +41,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Groups the valid lanes by label: lane r (r < return value) receives the
-// r-th distinct label (order of first appearance) and its weight sum.  One
-// iteration per distinct label, register-only, no memory traffic, so the
-// gathers and inserts that follow run in parallel across lanes.
-__device__ __forceinline__ int wave_collect(bool valid, int key, int w, int& ck, int& cs) {
-  const int lane = lane_id();
-  uint64_t rem = __ballot(valid);
-  int r = 0;
-  while (rem) {
-    const int leader = __ffsll((unsigned long long)rem) - 1;
-    const int kl = __builtin_amdgcn_readlane(key, leader);
-    const bool mine = valid && key == kl;
-    rem &= ~__ballot(mine);
-    const int s = wave_sum(mine ? w : 0);
-    if (lane == r) {
-      ck = kl;
-      cs = s;
-    }
-    ++r;
-  }
-  return r;
-}
-
-// Weight sum of label X among the collected pairs (0 if absent).
-__device__ __forceinline__ int collected_sum(int nd, int ck, int cs, int X) {
-  const uint64_t m = __ballot(lane_id() < nd && ck == X);
-  return m ? __builtin_amdgcn_readlane(cs, __ffsll((unsigned long long)m) - 1) : 0;
-}
-
 struct Cand {  // Alg. 2 candidate: larger gain, then smaller C(j), then smaller j
   long long g;
   int x;
@@ -80,28 +51,37 @@ __device__ __forceinline__ bool cand_better(const Cand& p, const Cand& q) {
   return p.g > q.g || (p.g == q.g && (p.x < q.x || (p.x == q.x && p.j < q.j)));
 }
 
-__device__ __forceinline__ Cand wave_cand(Cand c) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    Cand y;
-    y.g = __shfl_xor(c.g, o, WAVE);
-    y.x = __shfl_xor(c.x, o, WAVE);
-    y.j = __shfl_xor(c.j, o, WAVE);
-    if (cand_better(y, c)) c = y;
-  }
-  return c;
-}
 
 // gain2 of Alg. 2: G(j* -> c), streamed over the row of j* by one wave.
+// The row is walked RG_U chunks per round: their entry loads, then their
+// label gathers, are issued before any is waited on.
+constexpr int RG_U = 4;
+
+template <int G>
+__device__ __forceinline__ void row_to_two(const EvalArgs& A, int js, int cj, int c, int t,
+                                           long long& e_to, long long& e_self) {
+  const int32_t rb = A.off[js], re = A.off[js + 1];
+  for (int32_t q0 = rb + t; q0 < re; q0 += RG_U * G) {
+    int2 e[RG_U];
+    int X[RG_U];
+#pragma unroll
+    for (int u = 0; u < RG_U; ++u) {
+      const int32_t q = q0 + u * G;
+      e[u] = q < re ? A.adj[q] : make_int2(js, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < RG_U; ++u) X[u] = e[u].x != js ? A.C[e[u].x] : EMPTY_KEY;
+#pragma unroll
+    for (int u = 0; u < RG_U; ++u) {
+      if (X[u] == c) e_to += e[u].y;
+      if (X[u] == cj) e_self += e[u].y;
+    }
+  }
+}
+
 __device__ __forceinline__ long long reverse_gain(const EvalArgs& A, int js, int cj, int c) {
   long long e_to = 0, e_self = 0;
-  for (int32_t q = A.off[js] + lane_id(); q < A.off[js + 1]; q += WAVE) {
-    int2 e = A.adj[q];
-    if (e.x == js) continue;
-    int X = A.C[e.x];
-    if (X == c) e_to += e.y;
-    if (X == cj) e_self += e.y;
-  }
+  row_to_two<WAVE>(A, js, cj, c, lane_id(), e_to, e_self);
   e_to = wave_sum(e_to);
   e_self = wave_sum(e_self);
   const long long kj = A.k[js];
@@ -113,73 +93,119 @@ __device__ __forceinline__ long long reverse_gain(const EvalArgs& A, int js, int
 // into 64/GS groups of GS lanes, each group evaluating its own vertex: wave
 // instructions cost the same for 16 or 64 busy lanes, so packing four
 // 16-entry rows into one wave divides the instruction count per vertex by
-// four.  Ballots stay wave-wide and are masked to the group; shuffles and
-// reductions run within the group.
+// four.  Ballots stay wave-wide, each group's leader label is read with a
+// scalar readlane, and reductions run within the group on DPP row
+// exchanges.
 
-template <int GS>
+template <int GS, int S = 0>
 __device__ __forceinline__ long long group_sum_ll(long long v) {
-#pragma unroll
-  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
-  return v;
+  if constexpr ((1 << S) >= GS) {
+    return v;
+  } else if constexpr (S == 5) {
+    return readlane64(v, 0) + readlane64(v, 32);
+  } else {
+    return group_sum_ll<GS, S + 1>(v + xchg64<S>(v));
+  }
 }
 
-template <int GS>
-__device__ __forceinline__ int group_sum_i(int v) {
-#pragma unroll
-  for (int o = GS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GS);
-  return v;
-}
-
-template <int GS>
+template <int GS, int S = 0>
 __device__ __forceinline__ Best group_best_w(Best b) {
-#pragma unroll
-  for (int o = GS / 2; o > 0; o >>= 1) {
-    long long s = __shfl_xor(b.s, o, GS);
-    int x = __shfl_xor(b.x, o, GS);
-    if (better(s, x, b.s, b.x)) {
-      b.s = s;
-      b.x = x;
-    }
+  if constexpr ((1 << S) >= GS) {
+    return b;
+  } else if constexpr (S == 5) {
+    const Best b0 = {readlane64(b.s, 0), __builtin_amdgcn_readlane(b.x, 0)};
+    const Best b1 = {readlane64(b.s, 32), __builtin_amdgcn_readlane(b.x, 32)};
+    return better(b1.s, b1.x, b0.s, b0.x) ? b1 : b0;
+  } else {
+    const Best y = {xchg64<S>(b.s), xchg<S>(b.x)};
+    return group_best_w<GS, S + 1>(better(y.s, y.x, b.s, b.x) ? y : b);
   }
-  return b;
 }
 
-template <int GS>
+template <int GS, int S = 0>
 __device__ __forceinline__ Cand group_cand_w(Cand c) {
-#pragma unroll
-  for (int o = GS / 2; o > 0; o >>= 1) {
-    Cand y;
-    y.g = __shfl_xor(c.g, o, GS);
-    y.x = __shfl_xor(c.x, o, GS);
-    y.j = __shfl_xor(c.j, o, GS);
-    if (cand_better(y, c)) c = y;
+  if constexpr ((1 << S) >= GS) {
+    return c;
+  } else if constexpr (S == 5) {
+    const Cand c0 = {readlane64(c.g, 0), __builtin_amdgcn_readlane(c.x, 0),
+                     __builtin_amdgcn_readlane(c.j, 0)};
+    const Cand c1 = {readlane64(c.g, 32), __builtin_amdgcn_readlane(c.x, 32),
+                     __builtin_amdgcn_readlane(c.j, 32)};
+    return cand_better(c1, c0) ? c1 : c0;
+  } else {
+    const Cand y = {xchg64<S>(c.g), xchg<S>(c.x), xchg<S>(c.j)};
+    return group_cand_w<GS, S + 1>(cand_better(y, c) ? y : c);
   }
-  return c;
+}
+
+// Value of lane r (uniform) of each lane's own group.
+template <int GS>
+__device__ __forceinline__ int group_bcast(int v, int r) {
+  constexpr int GPW = WAVE / GS;
+  int out = 0;
+#pragma unroll
+  for (int g = 0; g < GPW; ++g) {
+    const int x = __builtin_amdgcn_readlane(v, g * GS + r);
+    if (int(lane_id()) / GS == g) out = x;
+  }
+  return out;
 }
 
 // Per group: lane r of the group (r < returned count) receives the r-th
-// distinct label of the group's valid lanes and its weight sum.
+// distinct label of the group's valid lanes (order of first appearance)
+// and its weight sum.  Each iteration takes, for every group of the wave at
+// once, the label of the lowest lane not yet matched (scalar readlanes) and
+// matches it with one ballot; afterwards every valid lane adds its weight
+// into the LDS slot of its label's rank.  lsum: the wave's 64 ints, zero on
+// entry and on return.
 template <int GS>
-__device__ __forceinline__ int group_collect(bool valid, int key, int w, uint64_t gmask,
-                                             int& ck, int& cs) {
+__device__ __forceinline__ int group_collect(bool valid, int key, int w, int* lsum, int& ck,
+                                             int& cs) {
+  constexpr int GPW = WAVE / GS;
   const int lane = lane_id();
   const int gl = lane & (GS - 1);
-  uint64_t rem = __ballot(valid) & gmask;
-  int r = 0;
-  while (__ballot(rem != 0)) {
-    const bool act = rem != 0;
-    const int leader = act ? __ffsll((unsigned long long)rem) - 1 : lane;
-    const int kl = __shfl(key, leader, WAVE);
-    const bool mine = act && valid && key == kl;
-    rem &= ~(__ballot(mine) & gmask);
-    const int sum = group_sum_i<GS>(mine ? w : 0);
-    if (act && gl == r) {
-      ck = kl;
-      cs = sum;
+  const int grp = lane / GS;
+  uint64_t rem = __ballot(valid);
+  int r = 0, myr = 0;
+  while (rem) {
+    int kl = 0;
+    bool act = false;
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) {
+      uint64_t sub;
+      if constexpr (GPW == 1)
+        sub = rem;
+      else
+        sub = (rem >> (g * GS)) & ((uint64_t(1) << GS) - 1);
+      if (sub) {
+        const int kg = __builtin_amdgcn_readlane(key, g * GS + __builtin_ctzll(sub));
+        if (grp == g) {
+          kl = kg;
+          act = true;
+        }
+      }
     }
+    const bool mine = act && valid && key == kl;
+    rem &= ~__ballot(mine);
+    if (mine) myr = r;
+    if (act && gl == r) ck = kl;
     r += act ? 1 : 0;
   }
+  if (valid) atomicAdd(&lsum[lane - gl + myr], w);
+  wave_sync();
+  cs = gl < r ? lsum[lane] : 0;
+  lsum[lane] = 0;
+  wave_sync();
   return r;
+}
+
+// Sweep decision of vertex i: the group's first lane writes the next label
+// unless the singleton guard (Sec. 3.2) holds the move back.
+__device__ __forceinline__ void sweep_commit(const EvalArgs& A, int i, bool move, int c, int x,
+                                             int gl) {
+  if (move && gl == 0) {
+    if (!(A.guard && A.sz[c] == 1 && A.sz[x] == 1 && x > c)) A.Cn[i] = x;
+  }
 }
 
 // One item of a group kernel: group (lane / GS) of the wave evaluates vertex
@@ -187,7 +213,7 @@ __device__ __forceinline__ int group_collect(bool valid, int key, int w, uint64_
 // steps).  Returns the screening tests this group accepted (0 or 1).
 template <int MODE, int GS>
 __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool have, int lane,
-                                                int gl, int gbase, uint64_t gmask) {
+                                                int gl, int gbase, int* lsum) {
   long long accepted = 0;
   const int32_t rb = have ? A.off[i] : 0;
   const int32_t re = have ? A.off[i + 1] : 0;
@@ -197,7 +223,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   const bool valid = e.x >= 0 && e.x != i;
   const int key = valid ? A.C[e.x] : EMPTY_KEY;
   int ck = EMPTY_KEY, cs = 0;
-  const int nd = group_collect<GS>(valid, key, e.y, gmask, ck, cs);
+  const int nd = group_collect<GS>(valid, key, e.y, lsum, ck, cs);
   const bool pair = gl < nd;
   const long long e_own = group_sum_ll<GS>(pair && ck == c ? (long long)cs : 0);
   const long long s_own = A.two_m * e_own - ki * ((have ? A.a[c] : 0) - ki);
@@ -222,8 +248,8 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     long long ej = 0;
     const int ndw = wave_max(nd);
     for (int r = 0; r < ndw; ++r) {
-      const int kr = __shfl(ck, gbase + r, WAVE);
-      const int sr = __shfl(cs, gbase + r, WAVE);
+      const int kr = group_bcast<GS>(ck, r);
+      const int sr = group_bcast<GS>(cs, r);
       if (r < nd && Xj == kr) ej = sr;
     }
     Cand cd = {NO_SCORE, NO_LABEL, NO_LABEL};
@@ -238,8 +264,9 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     long long g2 = 0;
     for (uint64_t lm = __ballot(live && gl == 0); lm; lm &= lm - 1) {
       const int ld = __ffsll((unsigned long long)lm) - 1;
-      const long long r = reverse_gain(A, __shfl(best.j, ld, WAVE), __shfl(best.x, ld, WAVE),
-                                       __shfl(c, ld, WAVE));
+      const long long r = reverse_gain(A, __builtin_amdgcn_readlane(best.j, ld),
+                                       __builtin_amdgcn_readlane(best.x, ld),
+                                       __builtin_amdgcn_readlane(c, ld));
       if (lane / GS == ld / GS) g2 = r;
     }
     if (live && best.g >= g2) {
@@ -258,9 +285,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   b = group_best_w<GS>(b);
   bool move = have && b.x != NO_LABEL && b.s > s_own;
   if (MODE == EV_SWEEP) {
-    if (move && gl == 0) {
-      if (!(A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c)) A.Cn[i] = b.x;
-    }
+    sweep_commit(A, i, move, c, b.x, gl);
   } else if (move) {  // EV_DSDEL
     if (e.x >= 0) A.R[e.x] = 1;
     if (gl == 0) {
@@ -272,24 +297,73 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   return accepted;
 }
 
+// Two sweep items per group with their loads interleaved: every stage of
+// the chain row bounds -> entries -> neighbour labels -> community totals
+// issues both items' loads before it waits on either, so a wave keeps
+// twice the gathers in flight.  The arithmetic is group_item<EV_SWEEP>'s.
+template <int GS>
+__device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, int i1, bool h1,
+                                           int gl, int* lsum) {
+  const int32_t rb0 = h0 ? A.off[i0] : 0, re0 = h0 ? A.off[i0 + 1] : 0;
+  const int32_t rb1 = h1 ? A.off[i1] : 0, re1 = h1 ? A.off[i1 + 1] : 0;
+  const int c0 = h0 ? A.C[i0] : 0, c1 = h1 ? A.C[i1] : 0;
+  const long long k0 = h0 ? A.k[i0] : 0, k1 = h1 ? A.k[i1] : 0;
+  const int2 e0 = rb0 + gl < re0 ? A.adj[rb0 + gl] : make_int2(-1, 0);
+  const int2 e1 = rb1 + gl < re1 ? A.adj[rb1 + gl] : make_int2(-1, 0);
+  const long long ao0 = h0 ? A.a[c0] : 0, ao1 = h1 ? A.a[c1] : 0;
+  const bool v0 = e0.x >= 0 && e0.x != i0, v1 = e1.x >= 0 && e1.x != i1;
+  const int key0 = v0 ? A.C[e0.x] : EMPTY_KEY;
+  const int key1 = v1 ? A.C[e1.x] : EMPTY_KEY;
+  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0;
+  const int nd0 = group_collect<GS>(v0, key0, e0.y, lsum, ck0, cs0);
+  const int nd1 = group_collect<GS>(v1, key1, e1.y, lsum, ck1, cs1);
+  const bool p0 = gl < nd0 && ck0 != c0, p1 = gl < nd1 && ck1 != c1;
+  const long long ak0 = p0 ? A.a[ck0] : 0;
+  const long long ak1 = p1 ? A.a[ck1] : 0;
+  const long long own0 = group_sum_ll<GS>(gl < nd0 && ck0 == c0 ? (long long)cs0 : 0);
+  const long long own1 = group_sum_ll<GS>(gl < nd1 && ck1 == c1 ? (long long)cs1 : 0);
+  const long long s0 = A.two_m * own0 - k0 * (ao0 - k0);
+  const long long s1 = A.two_m * own1 - k1 * (ao1 - k1);
+  Best b0 = {NO_SCORE, NO_LABEL}, b1 = {NO_SCORE, NO_LABEL};
+  if (p0) b0 = {A.two_m * cs0 - k0 * ak0, ck0};
+  if (p1) b1 = {A.two_m * cs1 - k1 * ak1, ck1};
+  b0 = group_best_w<GS>(b0);
+  b1 = group_best_w<GS>(b1);
+  sweep_commit(A, i0, h0 && b0.x != NO_LABEL && b0.s > s0, c0, b0.x, gl);
+  sweep_commit(A, i1, h1 && b1.x != NO_LABEL && b1.s > s1, c1, b1.x, gl);
+}
+
 template <int MODE, int GS>
 __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
   constexpr int GPW = WAVE / GS;  // groups per wave
   const int lane = lane_id();
   const int gl = lane & (GS - 1);
   const int gbase = lane - gl;
-  const uint64_t gmask = GS == WAVE ? ~uint64_t(0) : (((uint64_t(1) << GS) - 1) << gbase);
+  __shared__ int lsum_all[NW][WAVE];
+  int* ls = lsum_all[threadIdx.x / WAVE];
+  ls[lane] = 0;
+  wave_sync();
   const int64_t cnt = *A.count;
   const int64_t ngroups = int64_t(gridDim.x) * NW * GPW;
   long long accepted = 0;
   const int64_t g0 = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * GPW + lane / GS;
   // every group of a wave runs the same number of iterations (wave-uniform)
   const int64_t w0 = g0 - lane / GS;
+  if constexpr (MODE == EV_SWEEP) {
+    for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
+      const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
+      const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
+      const int i0 = h0 ? A.list[idx0] : 0;
+      const int i1 = h1 ? A.list[idx1] : 0;
+      sweep_pair<GS>(A, i0, h0, i1, h1, gl, ls);
+    }
+    return;
+  }
   for (int64_t wb = w0; wb < cnt; wb += ngroups) {
     const int64_t idx = wb + lane / GS;
     const bool have = idx < cnt;
     const int i = have ? A.list[idx] : 0;
-    accepted += group_item<MODE, GS>(A, i, have, lane, gl, gbase, gmask);
+    accepted += group_item<MODE, GS>(A, i, have, lane, gl, gbase, ls);
   }
   accepted = group_sum_ll<WAVE>(accepted);
   if (MODE != EV_SWEEP && lane == 0 && accepted)
@@ -333,7 +407,7 @@ __device__ __forceinline__ Best group_best(Best b, GroupLds<G>& L) {
 
 template <int G>
 __device__ __forceinline__ Cand group_cand(Cand c, GroupLds<G>& L) {
-  c = wave_cand(c);
+  c = group_cand_w<WAVE>(c);
   if (G == WAVE) return c;
   const int wid = threadIdx.x / WAVE;
   if (lane_id() == 0) L.cand[wid] = c;
@@ -372,13 +446,7 @@ __device__ __forceinline__ long long group_reverse_gain(const EvalArgs& A, int j
                                                         GroupLds<G>& L) {
   if (G == WAVE) return reverse_gain(A, js, cj, c);
   long long e_to = 0, e_self = 0;
-  for (int32_t q = A.off[js] + threadIdx.x; q < A.off[js + 1]; q += G) {
-    int2 e = A.adj[q];
-    if (e.x == js) continue;
-    int X = A.C[e.x];
-    if (X == c) e_to += e.y;
-    if (X == cj) e_self += e.y;
-  }
+  row_to_two<G>(A, js, cj, c, int(threadIdx.x), e_to, e_self);
   e_to = wave_sum(e_to);
   e_self = wave_sum(e_self);
   const int wid = threadIdx.x / WAVE;
@@ -407,6 +475,40 @@ __device__ __forceinline__ uint32_t table_cap(int deg, uint32_t max_slots) {
   return cap < max_slots ? cap : max_slots;
 }
 
+constexpr int TAB_UI = 4;  // row chunks per insertion round
+constexpr int TAB_US = 8;  // table slots per thread per scan round
+
+// This thread's best (score, label) over its slots of the table, skipping
+// label `skip`; the community totals of TAB_US slots are gathered together.
+template <int G>
+__device__ __forceinline__ Best table_best(const EvalArgs& A, const int* keys, const int* vals,
+                                           uint32_t mask, long long ki, int skip, int t) {
+  Best b = {NO_SCORE, NO_LABEL};
+  for (uint32_t s0 = t; s0 <= mask; s0 += TAB_US * G) {
+    int X[TAB_US], V[TAB_US];
+    long long AX[TAB_US];
+#pragma unroll
+    for (int u = 0; u < TAB_US; ++u) {
+      const uint32_t s = s0 + uint32_t(u * G);
+      X[u] = s <= mask ? keys[s] : EMPTY_KEY;
+      V[u] = s <= mask ? vals[s] : 0;
+      if (X[u] == skip) X[u] = EMPTY_KEY;
+    }
+#pragma unroll
+    for (int u = 0; u < TAB_US; ++u) AX[u] = X[u] != EMPTY_KEY ? A.a[X[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < TAB_US; ++u) {
+      if (X[u] == EMPTY_KEY) continue;
+      const long long sc = A.two_m * V[u] - ki * AX[u];
+      if (better(sc, X[u], b.s, b.x)) {
+        b.s = sc;
+        b.x = X[u];
+      }
+    }
+  }
+  return b;
+}
+
 // One group (a wave, or the whole block) evaluates vertex i with table
 // (keys, vals, mask).  Returns the number of accepted screening tests (0/1)
 // in thread 0 of the group.
@@ -425,17 +527,32 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   group_sync<G>();
   // the own community (usually most of the row) is summed in registers;
   // every other entry goes straight into the table, one lane per entry
+  // (UI chunks per round: their entry loads, then their label gathers, are
+  // issued before any is waited on)
   long long own_part = 0;
   const int w0 = (G == WAVE) ? 0 : int(threadIdx.x) / WAVE;
-  for (int32_t c0 = rb + w0 * WAVE; c0 < re; c0 += G) {
-    bool valid = c0 + lane < re;
-    int2 e = valid ? A.adj[c0 + lane] : make_int2(0, 0);
-    if (e.x == i) valid = false;
-    const int key = valid ? A.C[e.x] : EMPTY_KEY;
-    if (key == c)
-      own_part += e.y;
-    else if (valid)
-      table_add(keys, vals, mask, key, e.y);
+  for (int32_t c0 = rb + w0 * WAVE; c0 < re; c0 += TAB_UI * G) {
+    int2 e[TAB_UI];
+    bool valid[TAB_UI];
+    int key[TAB_UI];
+#pragma unroll
+    for (int u = 0; u < TAB_UI; ++u) {
+      const int32_t q = c0 + u * G + lane;
+      valid[u] = q < re;
+      e[u] = valid[u] ? A.adj[q] : make_int2(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < TAB_UI; ++u) {
+      if (e[u].x == i) valid[u] = false;
+      key[u] = valid[u] ? A.C[e[u].x] : EMPTY_KEY;
+    }
+#pragma unroll
+    for (int u = 0; u < TAB_UI; ++u) {
+      if (key[u] == c)
+        own_part += e[u].y;
+      else if (valid[u])
+        table_add(keys, vals, mask, key[u], e[u].y);
+    }
   }
   long long e_own = own_part, unused = 0;
   group_sum2<G>(e_own, unused, L);
@@ -470,31 +587,13 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
     group_sync<G>();  // the table is reused by the next item of this group
     return accepted;
   }
-  Best b = {NO_SCORE, NO_LABEL};
-  for (uint32_t s = t; s <= mask; s += G) {
-    const int X = keys[s];
-    if (X == EMPTY_KEY) continue;
-    const long long sc = A.two_m * vals[s] - ki * A.a[X];
-    if (better(sc, X, b.s, b.x)) {
-      b.s = sc;
-      b.x = X;
-    }
-  }
+  Best b = table_best<G>(A, keys, vals, mask, ki, EMPTY_KEY, t);
   b = group_best<G>(b, L);
   group_sync<G>();
   const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
   if (MODE == EV_FEAT) {
     // the table holds only foreign labels; a second scan skips the best
-    Best b2 = {NO_SCORE, NO_LABEL};
-    for (uint32_t s = t; s <= mask; s += G) {
-      const int X = keys[s];
-      if (X == EMPTY_KEY || X == b.x) continue;
-      const long long sc = A.two_m * vals[s] - ki * A.a[X];
-      if (better(sc, X, b2.s, b2.x)) {
-        b2.s = sc;
-        b2.x = X;
-      }
-    }
+    Best b2 = table_best<G>(A, keys, vals, mask, ki, b.x, t);
     b2 = group_best<G>(b2, L);
     if (t == 0) {
       A.f_own[i] = int32_t(e_own);
@@ -592,7 +691,10 @@ __global__ void __launch_bounds__(TPB) k_sweep_group_multi(MultiArgs M) {
   const int lane = lane_id();
   const int gl = lane & (GS - 1);
   const int gbase = lane - gl;
-  const uint64_t gmask = GS == WAVE ? ~uint64_t(0) : (((uint64_t(1) << GS) - 1) << gbase);
+  __shared__ int lsum_all[NW][WAVE];
+  int* ls = lsum_all[threadIdx.x / WAVE];
+  ls[lane] = 0;
+  wave_sync();
   const int64_t ngroups = int64_t(gridDim.x) * NW * GPW;
   const int64_t w0 = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * GPW;
   for (int64_t wb = w0; wb < M.count; wb += ngroups) {
@@ -600,7 +702,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_group_multi(MultiArgs M) {
     if (M.done[g]) continue;  // uniform: this graph's level has converged
     const EvalArgs A = M.descs[g];
     const int i = M.list[wb + lane / GS];
-    (void)group_item<EV_SWEEP, GS>(A, i < 0 ? 0 : i, i >= 0, lane, gl, gbase, gmask);
+    (void)group_item<EV_SWEEP, GS>(A, i < 0 ? 0 : i, i >= 0, lane, gl, gbase, ls);
   }
 }
 

@@ -36,7 +36,7 @@ __global__ void k_validate(const int32_t* __restrict__ u,
     }
   }
   // combine per wave, one atomic per wave
-  for (int o = WAVE / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, WAVE);
+  f = wave_or(f);
   s = wave_sum(s);
   if (lane_id() == 0) {
     if (f) atomicOr(flags, f);
@@ -125,16 +125,6 @@ __global__ void k_row_weight_sums(const int32_t* __restrict__ off,
   if (lane == 0) k[row] = s;
 }
 
-__global__ void k_detect_dups(const uint64_t* __restrict__ keys, int64_t m,
-                              int32_t* flags) {
-  int32_t f = 0;
-  GRID_STRIDE(i, m) {
-    if (i > 0 && keys[i] == keys[i - 1]) f = F_DUP;
-  }
-  for (int o = WAVE / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, WAVE);
-  if (lane_id() == 0 && f) atomicOr(flags, f);
-}
-
 __device__ __forceinline__ int32_t find_in_row(const int2* adj, int32_t b,
                                                int32_t e, int32_t c) {
   // first position p in [b, e) with adj[p].x >= c
@@ -148,89 +138,95 @@ __device__ __forceinline__ int32_t find_in_row(const int2* adj, int32_t b,
   return b;
 }
 
-__global__ void k_lookup_deleted(const uint64_t* __restrict__ keys, int64_t m,
-                                 int32_t n, const int32_t* __restrict__ off,
-                                 const int2* __restrict__ adj, int32_t* w_old,
-                                 int32_t* flags, long long* wsum) {
+// Directed change records straight from the batch: deletion e gives keys
+// u*n+v and v*n+u with value 2e, insertion e the same keys with value 2e+1.
+__global__ void k_batch_records(const int32_t* __restrict__ du, const int32_t* __restrict__ dv,
+                                int64_t nd, const int32_t* __restrict__ au,
+                                const int32_t* __restrict__ av, int64_t na, int32_t n,
+                                uint64_t* keys, uint32_t* vals) {
+  GRID_STRIDE(i, nd + na) {
+    const bool del = i < nd;
+    const int64_t j = del ? i : i - nd;
+    const uint64_t a = uint32_t(del ? du[j] : au[j]), b = uint32_t(del ? dv[j] : av[j]);
+    const uint32_t val = (uint32_t(j) << 1) | (del ? 0u : 1u);
+    keys[2 * i] = a * uint64_t(n) + b;
+    keys[2 * i + 1] = b * uint64_t(n) + a;
+    vals[2 * i] = val;
+    vals[2 * i + 1] = val;
+  }
+}
+
+// Per sorted record: its run (pos = exclusive scan of the run heads) gets
+// the record's insertion weight, or one more deletion.  run_w and run_ndel
+// must be zeroed.
+__global__ void k_run_accumulate(const uint64_t* __restrict__ keys,
+                                 const uint32_t* __restrict__ vals,
+                                 const int32_t* __restrict__ pos, int64_t m,
+                                 const int32_t* __restrict__ ins_w, uint64_t* run_key,
+                                 int32_t* run_w, int32_t* run_ndel) {
+  GRID_STRIDE(i, m) {
+    const bool head = i == 0 || keys[i] != keys[i - 1];
+    const int32_t r = head ? pos[i] : pos[i] - 1;
+    if (head) run_key[r] = keys[i];
+    const uint32_t v = vals[i];
+    if (v & 1u)
+      atomicAdd(&run_w[r], ins_w[v >> 1]);
+    else
+      atomicAdd(&run_ndel[r], 1);
+  }
+}
+
+// One change per directed pair (run r < *nruns): two deletions of one pair
+// flag F_DUP, a deletion of a pair absent from G_{t-1} flags F_NO_EDGE;
+// *wsum += the old weights of the deleted pairs (counted once, at src < dst).
+// A deletion with insertions is a REPLACE (new weight = their sum), a
+// deletion alone a DELETE, insertions alone an ADD to an existing pair or a
+// NEW one.  Ids out of range are skipped (their batch fails on F_RANGE).
+__global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
+                               const int32_t* __restrict__ run_w,
+                               const int32_t* __restrict__ run_ndel,
+                               const int32_t* __restrict__ nruns, int32_t n,
+                               const int32_t* __restrict__ off, const int2* __restrict__ adj,
+                               uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
+                               int32_t* is_del, int32_t* is_new, int32_t* flags,
+                               long long* wsum) {
+  const int64_t cnt = *nruns;
   int32_t f = 0;
   long long s = 0;
-  GRID_STRIDE(i, m) {
-    uint64_t key = keys[i];
-    uint64_t lo = key / uint64_t(n), hi = key % uint64_t(n);
+  GRID_STRIDE(r, cnt) {
+    const uint64_t key = run_key[r];
+    const uint64_t src = key / uint64_t(n), dst = key % uint64_t(n);
+    const int32_t nd = run_ndel[r], wi = run_w[r];
     int32_t wo = 0;
-    if (lo < uint64_t(n) && hi < uint64_t(n)) {
-      int32_t b = off[lo], e = off[lo + 1];
-      int32_t p = find_in_row(adj, b, e, int32_t(hi));
-      if (p < e && adj[p].x == int32_t(hi)) wo = adj[p].y;
+    bool exists = false;
+    if (src < uint64_t(n) && dst < uint64_t(n)) {
+      // G is symmetric: search the shorter of the two rows (a hub's
+      // neighbours find their pair in their own short row)
+      const int32_t bs = off[src], es = off[src + 1], bd = off[dst], ed = off[dst + 1];
+      const bool own = es - bs <= ed - bd;
+      const int32_t b = own ? bs : bd, e = own ? es : ed;
+      const int32_t x = own ? int32_t(dst) : int32_t(src);
+      const int32_t p = find_in_row(adj, b, e, x);
+      exists = p < e && adj[p].x == x;
+      wo = exists ? adj[p].y : 0;
     }
-    if (wo == 0) f |= F_NO_EDGE;
-    w_old[i] = wo;
-    s += wo;
-  }
-  for (int o = WAVE / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, WAVE);
-  s = wave_sum(s);
-  if (lane_id() == 0) {
-    if (f) atomicOr(flags, f);
-    if (s) atomicAdd((unsigned long long*)wsum, (unsigned long long)s);
-  }
-}
-
-__global__ void k_make_change_records(const uint64_t* __restrict__ del_keys,
-                                      int64_t nd,
-                                      const uint64_t* __restrict__ ins_keys,
-                                      int64_t na, int32_t n, uint64_t* rkeys,
-                                      uint32_t* rvals) {
-  GRID_STRIDE(i, nd + na) {
-    bool is_del = i < nd;
-    int64_t j = is_del ? i : i - nd;
-    uint64_t key = is_del ? del_keys[j] : ins_keys[j];
-    uint64_t lo = key / uint64_t(n), hi = key % uint64_t(n);
-    uint32_t val = (uint32_t(j) << 1) | (is_del ? 0u : 1u);
-    rkeys[2 * i] = lo * uint64_t(n) + hi;
-    rkeys[2 * i + 1] = hi * uint64_t(n) + lo;
-    rvals[2 * i] = val;
-    rvals[2 * i + 1] = val;
-  }
-}
-
-__global__ void k_combine_changes(
-    const uint64_t* __restrict__ rkeys, const uint32_t* __restrict__ rvals,
-    int64_t nr, const int32_t* __restrict__ heads,
-    const int32_t* __restrict__ pos, int32_t n,
-    const int32_t* __restrict__ del_w_old, const int32_t* __restrict__ ins_w,
-    const int32_t* __restrict__ off, const int2* __restrict__ adj,
-    uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
-    int32_t* is_del, int32_t* is_new) {
-  GRID_STRIDE(i, nr) {
-    if (!heads[i]) continue;
-    uint64_t key = rkeys[i];
-    int32_t w_del = -1, w_ins = -1;
-    for (int64_t j = i; j < nr && j < i + 2 && rkeys[j] == key; ++j) {
-      uint32_t v = rvals[j];
-      if (v & 1u)
-        w_ins = ins_w[v >> 1];
-      else
-        w_del = del_w_old[v >> 1];
-    }
+    if (nd > 1) f |= F_DUP;
+    if (nd > 0 && !exists) f |= F_NO_EDGE;
+    if (nd > 0 && src < dst) s += wo;
     int32_t op, w, dk;
-    if (w_del >= 0 && w_ins >= 0) {
+    if (nd > 0 && wi > 0) {
       op = OP_REPLACE;
-      w = w_ins;
-      dk = w_ins - w_del;
-    } else if (w_del >= 0) {
+      w = wi;
+      dk = wi - wo;
+    } else if (nd > 0) {
       op = OP_DELETE;
       w = 0;
-      dk = -w_del;
+      dk = -wo;
     } else {
-      uint64_t src = key / uint64_t(n), dst = key % uint64_t(n);
-      int32_t b = off[src], e = off[src + 1];
-      int32_t p = find_in_row(adj, b, e, int32_t(dst));
-      bool exists = p < e && adj[p].x == int32_t(dst);
       op = exists ? OP_ADD : OP_NEW;
-      w = w_ins;
-      dk = w_ins;
+      w = wi;
+      dk = wi;
     }
-    int32_t r = pos[i];
     ch_key[r] = key;
     ch_op[r] = op;
     ch_w[r] = w;
@@ -238,7 +234,26 @@ __global__ void k_combine_changes(
     is_del[r] = op == OP_DELETE ? 1 : 0;
     is_new[r] = op == OP_NEW ? 1 : 0;
   }
+  // one update per block (same-address atomics serialise)
+  __shared__ int bf[TPB / WAVE];
+  __shared__ long long bs[TPB / WAVE];
+  f = wave_or(f);
+  s = wave_sum(s);
+  if (lane_id() == 0) {
+    bf[threadIdx.x / WAVE] = f;
+    bs[threadIdx.x / WAVE] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < TPB / WAVE; ++w) {
+      f |= bf[w];
+      s += bs[w];
+    }
+    if (f) atomicOr(flags, f);
+    if (s) atomicAdd((unsigned long long*)wsum, (unsigned long long)s);
+  }
 }
+
 
 // Thread per row: new degree, k += the row's weight change, and the label
 // totals a[C(u)] += the same change.  A block walks many rows and sums the
@@ -354,12 +369,19 @@ __device__ void merge_row_search(int32_t row, int32_t n, const int2* __restrict_
   }
 }
 
-constexpr int BIG_ROW = 1024;       // rows longer than this are merged by a block
-constexpr int BIG_CHANGES = 4096;   // changes staged in LDS per big row
+constexpr int WROW_CH = 4;                 // row chunks a wave holds in registers
+constexpr int BIG_ROW = 1024;              // longer rows are merged by a block
+constexpr int BIG_CHANGES = 4096;          // changes staged in LDS per big row
+constexpr int BIG_SEG = BIG_CHANGES / TPB; // histogram bins per thread in the scan
+constexpr int BIG_U = 4;                   // row chunks per load round of a block
 
-// Long changed rows: one block per row.  The row's change neighbours and the
-// cumulative shift before each change are staged in LDS, so every old entry
-// finds its place by a binary search on chip.
+// Long changed rows (more than BIG_ROW entries or more than WAVE changes):
+// one block per row.  The row's change neighbours and the shift before each
+// change (insertions minus deletions before it) are staged in LDS; each old
+// entry finds its rank lo among the changes by a binary search on chip and
+// counts itself in bin lo of an LDS histogram.  An insertion at change k
+// lands after the old entries with a smaller neighbour, which are exactly
+// those of rank <= k: the histogram's prefix sum at k.
 __global__ void __launch_bounds__(TPB)
     k_merge_big(const int32_t* __restrict__ big,
                 const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
@@ -369,7 +391,9 @@ __global__ void __launch_bounds__(TPB)
                 const int32_t* __restrict__ cum_del, const int32_t* __restrict__ cum_new) {
   __shared__ int ldst[BIG_CHANGES];
   __shared__ int lsh[BIG_CHANGES + 1];
-  const int64_t nrows = big[0];  // rows longer than BIG_ROW, listed from big[1]
+  __shared__ int hcnt[BIG_CHANGES + 1];
+  __shared__ int part[TPB];
+  const int64_t nrows = big[0];  // rows listed from big[1]
   for (int64_t p = blockIdx.x; p < nrows; p += gridDim.x) {
     const int32_t row = big[1 + p];
     const int32_t ob = off_old[row], oe = off_old[row + 1];
@@ -387,119 +411,205 @@ __global__ void __launch_bounds__(TPB)
     for (int k = threadIdx.x; k <= nchg; k += TPB) {
       if (k < nchg) ldst[k] = int32_t(ch_key[cb + k] - base);
       lsh[k] = (cum_new[cb + k] - new0) - (cum_del[cb + k] - del0);
+      hcnt[k] = 0;
     }
     __syncthreads();
-    for (int32_t j = threadIdx.x; j < oe - ob; j += TPB) {
-      int2 e = adj_old[ob + j];
-      int lo = 0, hi = nchg;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (ldst[mid] < e.x)
-          lo = mid + 1;
-        else
-          hi = mid;
+    const int32_t deg = oe - ob;
+    for (int32_t j0 = threadIdx.x; j0 < deg; j0 += BIG_U * TPB) {
+      int2 e[BIG_U];
+#pragma unroll
+      for (int u = 0; u < BIG_U; ++u) {
+        const int32_t j = j0 + u * TPB;
+        e[u] = j < deg ? adj_old[ob + j] : make_int2(0, 0);
       }
-      if (lo < nchg && ldst[lo] == e.x) {
-        const int32_t op = ch_op[cb + lo];
-        if (op == OP_DELETE) continue;
-        if (op == OP_ADD) e.y += ch_w[cb + lo];
-        if (op == OP_REPLACE) e.y = ch_w[cb + lo];
+#pragma unroll
+      for (int u = 0; u < BIG_U; ++u) {
+        const int32_t j = j0 + u * TPB;
+        if (j >= deg) continue;
+        int lo = 0, hi = nchg;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (ldst[mid] < e[u].x)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        atomicAdd(&hcnt[lo], 1);
+        if (lo < nchg && ldst[lo] == e[u].x) {
+          const int32_t op = ch_op[cb + lo];
+          if (op == OP_DELETE) continue;
+          if (op == OP_ADD) e[u].y += ch_w[cb + lo];
+          if (op == OP_REPLACE) e[u].y = ch_w[cb + lo];
+        }
+        adj_new[nb + j + lsh[lo]] = e[u];
       }
-      adj_new[nb + j + lsh[lo]] = e;
+    }
+    __syncthreads();
+    // inclusive prefix sums of hcnt: per-thread segments of BIG_SEG bins,
+    // then a scan of the TPB segment totals
+    const int sb = int(threadIdx.x) * BIG_SEG;
+    int tot = 0;
+    for (int q = 0; q < BIG_SEG; ++q)
+      if (sb + q <= nchg) tot += hcnt[sb + q];
+    part[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < TPB; o <<= 1) {
+      const int add = int(threadIdx.x) >= o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
     }
     for (int k = threadIdx.x; k < nchg; k += TPB) {
       if (ch_op[cb + k] != OP_NEW) continue;
-      const int32_t pos = find_in_row(adj_old, ob, oe, ldst[k]) - ob;
-      adj_new[nb + pos + lsh[k]] = make_int2(ldst[k], ch_w[cb + k]);
+      const int seg = k / BIG_SEG;
+      int less = seg > 0 ? part[seg - 1] : 0;
+      for (int q = seg * BIG_SEG; q <= k; ++q) less += hcnt[q];
+      adj_new[nb + less + lsh[k]] = make_int2(ldst[k], ch_w[cb + k]);
     }
     __syncthreads();
   }
 }
 
-__global__ void k_merge_changed(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
-                                const int32_t* __restrict__ off_old,
-                                const int2* __restrict__ adj_old,
-                                const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
-                                const int32_t* __restrict__ cptr,
-                                const uint64_t* __restrict__ ch_key,
-                                const int32_t* __restrict__ ch_op,
-                                const int32_t* __restrict__ ch_w,
-                                const int32_t* __restrict__ cum_del,
-                                const int32_t* __restrict__ cum_new, int32_t* big) {
+// Changed rows of at most BIG_ROW entries and at most WAVE changes: one
+// wave per row, everything in registers.  The row's entries sit in windows
+// of WROW_CH chunks of one per lane and its changes (sorted by neighbour) one
+// per lane; a loop over the changes, each broadcast by readlane, gives every
+// old entry its shift (insertions minus deletions before it) and its fate,
+// and every change the number of old entries with a smaller neighbour (one
+// ballot per chunk), which places the insertions.  A wave takes two rows
+// per iteration and issues both rows' loads before it waits on either.
+// Other rows are listed for k_merge_big.
+struct MergeRow {
+  int32_t ob, deg, nb, nchg;
+  bool live;
+  int dst, op, cw;
+  int2 e[WROW_CH];
+};
+
+__device__ __forceinline__ void merge_head(MergeRow& r, int32_t row, bool have,
+                                           const int32_t* __restrict__ off_old,
+                                           const int32_t* __restrict__ off_new,
+                                           const int32_t* __restrict__ cptr, int32_t* cb_out) {
+  r.live = false;
+  r.ob = r.deg = r.nb = r.nchg = 0;
+  *cb_out = 0;
+  if (!have) return;
+  const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
+  const int32_t cb = cptr[row], ce = cptr[row + 1];
+  r.ob = ob;
+  r.deg = oe - ob;
+  r.nb = nb;
+  r.nchg = ce - cb;
+  r.live = true;
+  *cb_out = cb;
+}
+
+__device__ __forceinline__ void merge_load(MergeRow& r, int32_t row, int32_t cb, int32_t n,
+                                           const int2* __restrict__ adj_old,
+                                           const uint64_t* __restrict__ ch_key,
+                                           const int32_t* __restrict__ ch_op,
+                                           const int32_t* __restrict__ ch_w, int lane) {
+  const bool hq = r.live && lane < r.nchg;
+  const uint64_t base = uint64_t(row) * uint64_t(n);
+  r.dst = hq ? int32_t(ch_key[cb + lane] - base) : 0x7fffffff;
+  r.op = hq ? ch_op[cb + lane] : 0;
+  r.cw = hq ? ch_w[cb + lane] : 0;
+#pragma unroll
+  for (int u = 0; u < WROW_CH; ++u) {
+    const int32_t j = u * WAVE + lane;
+    r.e[u] = r.live && j < r.deg ? adj_old[r.ob + j] : make_int2(0x7fffffff, 0);
+  }
+}
+
+// The row is walked in windows of WROW_CH chunks: window 0 was loaded by
+// merge_load, later windows are loaded here.
+__device__ __forceinline__ void merge_finish(MergeRow& r, const int2* __restrict__ adj_old,
+                                             int2* adj_new, int lane, uint64_t lt) {
+  if (!r.live) return;  // uniform
+  const int nck = (r.deg + WAVE - 1) / WAVE;
+  int less = 0;
+  for (int w0 = 0; w0 == 0 || w0 < nck; w0 += WROW_CH) {
+    if (w0 > 0) {
+#pragma unroll
+      for (int u = 0; u < WROW_CH; ++u) {
+        const int32_t j = (w0 + u) * WAVE + lane;
+        r.e[u] = j < r.deg ? adj_old[r.ob + j] : make_int2(0x7fffffff, 0);
+      }
+    }
+    int shift[WROW_CH];
+    bool drop[WROW_CH];
+#pragma unroll
+    for (int u = 0; u < WROW_CH; ++u) {
+      shift[u] = 0;
+      drop[u] = false;
+    }
+    for (int k = 0; k < r.nchg; ++k) {
+      const int dk = __builtin_amdgcn_readlane(r.dst, k);
+      const int ok = __builtin_amdgcn_readlane(r.op, k);
+      const int wk = __builtin_amdgcn_readlane(r.cw, k);
+      const int dsh = ok == OP_NEW ? 1 : (ok == OP_DELETE ? -1 : 0);
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < WROW_CH; ++u) {
+        if (w0 + u >= nck) break;
+        if (dk < r.e[u].x) {
+          shift[u] += dsh;
+        } else if (dk == r.e[u].x) {
+          if (ok == OP_DELETE) drop[u] = true;
+          if (ok == OP_ADD) r.e[u].y += wk;
+          if (ok == OP_REPLACE) r.e[u].y = wk;
+        }
+        cnt += __popcll(__ballot(r.e[u].x < dk));
+      }
+      if (lane == k) less += cnt;
+    }
+#pragma unroll
+    for (int u = 0; u < WROW_CH; ++u) {
+      const int32_t j = (w0 + u) * WAVE + lane;
+      if (w0 + u < nck && j < r.deg && !drop[u]) adj_new[r.nb + j + shift[u]] = r.e[u];
+    }
+  }
+  // insertion k: after `less` old entries, minus the deletions and plus
+  // the insertions among the changes before it
+  const bool hq = lane < r.nchg;
+  const bool isnew = hq && r.op == OP_NEW;
+  const uint64_t mnew = __ballot(isnew), mdel = __ballot(hq && r.op == OP_DELETE);
+  if (isnew)
+    adj_new[r.nb + less + __popcll(mnew & lt) - __popcll(mdel & lt)] = make_int2(r.dst, r.cw);
+}
+
+__global__ void __launch_bounds__(TPB)
+    k_merge_changed(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
+                    const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
+                    const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
+                    const int32_t* __restrict__ cptr, const uint64_t* __restrict__ ch_key,
+                    const int32_t* __restrict__ ch_op, const int32_t* __restrict__ ch_w,
+                    int32_t* big) {
   const int64_t nrows = *nrows_dev;
   const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / WAVE);
   const int lane = lane_id();
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
   for (int64_t p = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE; p < nrows;
-       p += nwaves) {
-    const int32_t row = rows[p];
-    const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
-    const int32_t cb = cptr[row], ce = cptr[row + 1];
-    if (oe - ob > BIG_ROW) {  // merged by k_merge_big
-      if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = row;
-      continue;
+       p += 2 * nwaves) {
+    const bool hb = p + nwaves < nrows;
+    const int32_t rowA = rows[p];
+    const int32_t rowB = hb ? rows[p + nwaves] : 0;
+    MergeRow A, B;
+    int32_t cbA, cbB;
+    merge_head(A, rowA, true, off_old, off_new, cptr, &cbA);
+    merge_head(B, rowB, hb, off_old, off_new, cptr, &cbB);
+    if (A.deg > BIG_ROW || A.nchg > WAVE) {
+      if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = rowA;
+      A.live = false;
     }
-    if (int64_t(ce - cb) * ceil_div(oe - ob + 1, WAVE) > WAVE) {
-      merge_row_search(row, n, adj_old, ob, oe, nb, cb, ce, adj_new, ch_key, ch_op, ch_w,
-                       cum_del, cum_new);
-      continue;
+    if (B.live && (B.deg > BIG_ROW || B.nchg > WAVE)) {
+      if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = rowB;
+      B.live = false;
     }
-    const uint64_t base = uint64_t(row) * uint64_t(n);
-    // old entries: final position = nb + j - (#DELETE with dst < col) + (#NEW with dst < col)
-    for (int32_t j0 = 0; j0 < oe - ob; j0 += WAVE) {
-      const int32_t j = j0 + lane;
-      const bool live = j < oe - ob;
-      int2 e = live ? adj_old[ob + j] : make_int2(0x7fffffff, 0);
-      int shift = 0;
-      bool drop = false;
-      for (int32_t w0 = cb; w0 < ce; w0 += WAVE) {
-        const int32_t q = w0 + lane;
-        const bool hq = q < ce;
-        const int dst = hq ? int32_t(ch_key[q] - base) : 0x7fffffff;
-        const int op = hq ? ch_op[q] : 0;
-        const int cw = hq ? ch_w[q] : 0;
-        const int nw = ce - w0 < WAVE ? ce - w0 : WAVE;
-        for (int k = 0; k < nw; ++k) {
-          const int dk = __builtin_amdgcn_readlane(dst, k);
-          const int ok = __builtin_amdgcn_readlane(op, k);
-          if (dk < e.x) {
-            shift += ok == OP_NEW ? 1 : (ok == OP_DELETE ? -1 : 0);
-          } else if (dk == e.x) {
-            const int wk = __builtin_amdgcn_readlane(cw, k);
-            if (ok == OP_DELETE) drop = true;
-            if (ok == OP_ADD) e.y += wk;
-            if (ok == OP_REPLACE) e.y = wk;
-          }
-        }
-      }
-      if (live && !drop) adj_new[nb + j + shift] = e;
-    }
-    // new entries: position = nb + (#old with col < dst) - (#DELETE before) + (#NEW before)
-    for (int32_t w0 = cb; w0 < ce; w0 += WAVE) {
-      const int32_t q = w0 + lane;
-      const bool hq = q < ce && ch_op[q] == OP_NEW;
-      const int dst = q < ce ? int32_t(ch_key[q] - base) : 0x7fffffff;
-      const int nw0 = ce - w0 < WAVE ? ce - w0 : WAVE;
-      int pos = 0;
-      for (int32_t j0 = 0; j0 < oe - ob; j0 += WAVE) {
-        const int col = j0 + lane < oe - ob ? adj_old[ob + j0 + lane].x : 0x7fffffff;
-        for (int k = 0; k < nw0; ++k) {
-          const int c = __popcll(__ballot(col < __builtin_amdgcn_readlane(dst, k)));
-          if (lane == k) pos += c;
-        }
-      }
-      for (int32_t v0 = cb; v0 < ce; v0 += WAVE) {
-        const int32_t qq = v0 + lane;
-        const int d2 = qq < ce ? int32_t(ch_key[qq] - base) : 0x7fffffff;
-        const int o2 = qq < ce ? ch_op[qq] : 0;
-        const int nw = ce - v0 < WAVE ? ce - v0 : WAVE;
-        for (int k = 0; k < nw; ++k) {
-          const int dk = __builtin_amdgcn_readlane(d2, k);
-          const int ok = __builtin_amdgcn_readlane(o2, k);
-          if (dk < dst) pos += ok == OP_NEW ? 1 : (ok == OP_DELETE ? -1 : 0);
-        }
-      }
-      if (hq) adj_new[nb + pos] = make_int2(dst, ch_w[q]);
-    }
+    merge_load(A, rowA, cbA, n, adj_old, ch_key, ch_op, ch_w, lane);
+    merge_load(B, rowB, cbB, n, adj_old, ch_key, ch_op, ch_w, lane);
+    merge_finish(A, adj_old, adj_new, lane, lt);
+    merge_finish(B, adj_old, adj_new, lane, lt);
   }
 }
 
@@ -612,40 +722,29 @@ void row_weight_sums(const int32_t* off, const int2* adj, int32_t n, int32_t* k,
   DC_LAUNCH_CHECK();
 }
 
-void detect_dups(const uint64_t* keys, int64_t m, int32_t* flags,
-                 hipStream_t st) {
-  if (m <= 1) return;
-  k_detect_dups<<<grid_for(m), TPB, 0, st>>>(keys, m, flags);
-  DC_LAUNCH_CHECK();
-}
-
-void lookup_deleted(const uint64_t* keys, int64_t m, int32_t n,
-                    const int32_t* off, const int2* adj, int32_t* w_old,
-                    int32_t* flags, long long* wsum, hipStream_t st) {
-  if (m <= 0) return;
-  k_lookup_deleted<<<grid_for(m), TPB, 0, st>>>(keys, m, n, off, adj, w_old, flags, wsum);
-  DC_LAUNCH_CHECK();
-}
-
-void make_change_records(const uint64_t* del_keys, int64_t nd,
-                         const uint64_t* ins_keys, int64_t na, int32_t n,
-                         uint64_t* rkeys, uint32_t* rvals, hipStream_t st) {
+void batch_records(const int32_t* du, const int32_t* dv, int64_t nd, const int32_t* au,
+                   const int32_t* av, int64_t na, int32_t n, uint64_t* keys, uint32_t* vals,
+                   hipStream_t st) {
   if (nd + na <= 0) return;
-  k_make_change_records<<<grid_for(nd + na), TPB, 0, st>>>(del_keys, nd, ins_keys, na, n,
-                                                           rkeys, rvals);
+  k_batch_records<<<grid_for(nd + na), TPB, 0, st>>>(du, dv, nd, au, av, na, n, keys, vals);
   DC_LAUNCH_CHECK();
 }
 
-void combine_changes(const uint64_t* rkeys, const uint32_t* rvals, int64_t nr,
-                     const int32_t* heads, const int32_t* pos, int32_t n,
-                     const int32_t* del_w_old, const int32_t* ins_w,
-                     const int32_t* off, const int2* adj, uint64_t* ch_key,
-                     int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
-                     int32_t* is_del, int32_t* is_new, hipStream_t st) {
-  if (nr <= 0) return;
-  k_combine_changes<<<grid_for(nr), TPB, 0, st>>>(rkeys, rvals, nr, heads, pos, n, del_w_old,
-                                                  ins_w, off, adj, ch_key, ch_op, ch_w, ch_dk,
-                                                  is_del, is_new);
+void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* pos, int64_t m,
+                     const int32_t* nruns, const int32_t* ins_w, int32_t n, const int32_t* off,
+                     const int2* adj, uint64_t* run_key, int32_t* run_w, int32_t* run_ndel,
+                     uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
+                     int32_t* is_del, int32_t* is_new, int32_t* flags, long long* wsum,
+                     hipStream_t st) {
+  if (m <= 0) return;
+  fill_i32(run_w, 0, m, st);
+  fill_i32(run_ndel, 0, m, st);
+  k_run_accumulate<<<grid_for(m), TPB, 0, st>>>(keys, vals, pos, m, ins_w, run_key, run_w,
+                                                run_ndel);
+  DC_LAUNCH_CHECK();
+  k_resolve_runs<<<grid_for(m), TPB, 0, st>>>(run_key, run_w, run_ndel, nruns, n, off, adj,
+                                              ch_key, ch_op, ch_w, ch_dk, is_del, is_new, flags,
+                                              wsum);
   DC_LAUNCH_CHECK();
 }
 
@@ -673,11 +772,11 @@ void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
   if (nrows_max > 0) {
     fill_i32(big, 0, 1, st);
     k_merge_changed<<<grid_for(nrows_max * WAVE, TPB, 16384), TPB, 0, st>>>(
-        rows, nrows_dev, off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w,
-        cum_del, cum_new, big);
+        rows, nrows_dev, off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w, big);
     DC_LAUNCH_CHECK();
-    k_merge_big<<<256, TPB, 0, st>>>(big, off_old, adj_old, off_new, adj_new, n, cptr, ch_key,
-                                     ch_op, ch_w, cum_del, cum_new);
+    const int nbig = int(nrows_max < 2048 ? nrows_max : 2048);
+    k_merge_big<<<nbig, TPB, 0, st>>>(big, off_old, adj_old, off_new, adj_new, n, cptr, ch_key,
+                                      ch_op, ch_w, cum_del, cum_new);
     DC_LAUNCH_CHECK();
   }
 }

@@ -177,3 +177,83 @@ def test_full_and_incremental_coarsening_agree(graph):
             g.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
             compare(o, g, f"step {t}")
         assert gi.last_trace() == gf.last_trace()
+
+
+def _merge_case(seed):
+    """A graph whose batch reaches every way a changed row is merged: a hub
+    row of 6000 entries with more than 4096 changes, a 600-entry row and a
+    300-entry row with 80 changes (one block per row), a 200-entry row with
+    40 changes (one wave, entries in registers), replacements, and a sparse
+    background with a few changes per row."""
+    rng = np.random.default_rng(seed)
+    n = 12000
+    pairs = set()
+
+    def star(c, lo, hi):
+        for x in range(lo, hi):
+            pairs.add((min(c, x), max(c, x)))
+
+    star(0, 1, 6001)
+    star(7000, 7001, 7601)
+    star(8000, 8001, 8301)
+    star(9000, 9001, 9201)
+    while len(pairs) < 6000 + 600 + 300 + 200 + 30000:
+        a, b = (int(x) for x in rng.integers(0, n, 2))
+        if a != b:
+            pairs.add((min(a, b), max(a, b)))
+    edges = sorted(pairs)
+    u = np.array([p[0] for p in edges], np.int32)
+    v = np.array([p[1] for p in edges], np.int32)
+    w = rng.integers(1, 9, len(edges)).astype(np.int32)
+    add, dele, rep = [], [], []
+
+    def fresh(a, cands):
+        out = []
+        for b in cands:
+            p = (min(a, int(b)), max(a, int(b)))
+            if a != int(b) and p not in pairs:
+                pairs.add(p)
+                out.append(p)
+        return out
+
+    add += fresh(0, range(6001, 10601))                              # 4600 insertions
+    dele += [(0, int(x)) for x in rng.choice(np.arange(1, 6001), 200, replace=False)]
+    rep += [(0, int(x)) for x in rng.choice(np.arange(1, 6001), 50, replace=False)
+            if (0, int(x)) not in dele]
+    add += fresh(7000, rng.choice(np.arange(10601, n), 20, replace=False))
+    dele += [(7000, int(x)) for x in rng.choice(np.arange(7001, 7601), 10, replace=False)]
+    add += fresh(8000, rng.choice(np.arange(10601, n), 50, replace=False))
+    dele += [(8000, int(x)) for x in rng.choice(np.arange(8001, 8301), 30, replace=False)]
+    add += fresh(9000, rng.choice(np.arange(10601, n), 25, replace=False))
+    dele += [(9000, int(x)) for x in rng.choice(np.arange(9001, 9201), 15, replace=False)]
+    rep += [(9000, 9199), (8000, 8299)]
+    bg = [e for e in edges[6000 + 600 + 300 + 200:] if e[0] not in (0, 7000, 8000, 9000)]
+    idx = rng.choice(len(bg), 300, replace=False)
+    dele += [bg[i] for i in idx[:200]]
+    rep += [bg[i] for i in idx[200:]]
+    add += fresh(int(rng.integers(0, n)), rng.integers(0, n, 400))
+    dset = set(dele)
+    rep = [p for p in rep if p not in dset]
+    add_u = [p[0] for p in add] + [p[1] for p in rep]
+    add_v = [p[1] for p in add] + [p[0] for p in rep]
+    add_w = list(rng.integers(1, 9, len(add))) + [9] * len(rep)
+    del_u = [p[1] for p in dele] + [p[0] for p in rep]
+    del_v = [p[0] for p in dele] + [p[1] for p in rep]
+    return n, (u, v, w), (add_u, add_v, add_w, del_u, del_v)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_merge_paths_csr_equal(seed):
+    """G_t's CSR after a batch equals the oracle's entry for entry on rows
+    merged by every path (register wave, LDS block, binary search)."""
+    _log(f"case: merge paths seed={seed}")
+    n, (u, v, w), b = _merge_case(seed)
+    o, g = make_pair(n, u, v, w)
+    compare(o, g, "init")
+    o.apply_batch(*b)
+    g.apply_batch(*b)
+    offo, colo, wo = o.csr()
+    offg, colg, wg = g.csr()
+    assert np.array_equal(offo, offg), "row offsets differ"
+    assert np.array_equal(colo, colg) and np.array_equal(wo, wg), "entries differ"
+    compare(o, g, "after batch")
