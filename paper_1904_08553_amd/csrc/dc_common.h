@@ -171,6 +171,37 @@ __device__ __forceinline__ int wave_or(int v) {
   return __builtin_amdgcn_readlane(v, 0) | __builtin_amdgcn_readlane(v, 32);
 }
 
+// One global update per block instead of one per wave: same-address
+// atomics serialise in L2, so a kernel of thousands of waves that each add
+// to one counter queues thousands of them.  The waves reduce with DPP, their
+// results meet in LDS, and thread 0 issues the atomic.  Every thread of the
+// block must call these (no early exit before them).
+__device__ __forceinline__ void block_add(long long v, long long* dst) {
+  __shared__ long long part[16];
+  v = wave_sum(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (unsigned w = 0; w < blockDim.x / WAVE; ++w) t += part[w];
+    if (t) atomicAdd((unsigned long long*)dst, (unsigned long long)t);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_or(int v, int* dst) {
+  __shared__ int part[16];
+  v = wave_or(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (unsigned w = 0; w < blockDim.x / WAVE; ++w) t |= part[w];
+    if (t) atomicOr(dst, t);
+  }
+  __syncthreads();
+}
+
 // Other types (floating point): a fixed butterfly order through shuffles.
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -376,9 +376,10 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
 
 template <int G>
 struct GroupLds {
-  Best best[NW];
-  Cand cand[NW];
-  long long s0[NW], s1[NW];
+  static constexpr int W = G / WAVE;  // waves of the group
+  Best best[W];
+  Cand cand[W];
+  long long s0[W], s1[W];
   int own;
 };
 
@@ -399,7 +400,7 @@ __device__ __forceinline__ Best group_best(Best b, GroupLds<G>& L) {
   __syncthreads();
   Best r = L.best[0];
 #pragma unroll
-  for (int w = 1; w < NW; ++w)
+  for (int w = 1; w < G / WAVE; ++w)
     if (better(L.best[w].s, L.best[w].x, r.s, r.x)) r = L.best[w];
   __syncthreads();
   return r;
@@ -414,7 +415,7 @@ __device__ __forceinline__ Cand group_cand(Cand c, GroupLds<G>& L) {
   __syncthreads();
   Cand r = L.cand[0];
 #pragma unroll
-  for (int w = 1; w < NW; ++w)
+  for (int w = 1; w < G / WAVE; ++w)
     if (cand_better(L.cand[w], r)) r = L.cand[w];
   __syncthreads();
   return r;
@@ -434,7 +435,7 @@ __device__ __forceinline__ void group_sum2(long long& x, long long& y, GroupLds<
   x = 0;
   y = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
+  for (int w = 0; w < G / WAVE; ++w) {
     x += L.s0[w];
     y += L.s1[w];
   }
@@ -458,7 +459,7 @@ __device__ __forceinline__ long long group_reverse_gain(const EvalArgs& A, int j
   e_to = 0;
   e_self = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
+  for (int w = 0; w < G / WAVE; ++w) {
     e_to += L.s0[w];
     e_self += L.s1[w];
   }
@@ -475,29 +476,29 @@ __device__ __forceinline__ uint32_t table_cap(int deg, uint32_t max_slots) {
   return cap < max_slots ? cap : max_slots;
 }
 
-constexpr int TAB_UI = 4;  // row chunks per insertion round
-constexpr int TAB_US = 8;  // table slots per thread per scan round
+constexpr int GTPB = 1024;  // threads of a bin-G block (one hub row per block)
+constexpr int WTAB_UI = WTAB_MAX / WAVE;   // bin W: the whole row in one load round
+constexpr int WTAB_US = 8;                 // and its table in rounds of 8 slots
 
 // This thread's best (score, label) over its slots of the table, skipping
-// label `skip`; the community totals of TAB_US slots are gathered together.
-template <int G>
+// label `skip`; the community totals of US slots are gathered together.
+template <int G, int US>
 __device__ __forceinline__ Best table_best(const EvalArgs& A, const int* keys, const int* vals,
                                            uint32_t mask, long long ki, int skip, int t) {
   Best b = {NO_SCORE, NO_LABEL};
-  for (uint32_t s0 = t; s0 <= mask; s0 += TAB_US * G) {
-    int X[TAB_US], V[TAB_US];
-    long long AX[TAB_US];
+  for (uint32_t s0 = t; s0 <= mask; s0 += US * G) {
+    int X[US], V[US], AX[US];
 #pragma unroll
-    for (int u = 0; u < TAB_US; ++u) {
+    for (int u = 0; u < US; ++u) {
       const uint32_t s = s0 + uint32_t(u * G);
       X[u] = s <= mask ? keys[s] : EMPTY_KEY;
       V[u] = s <= mask ? vals[s] : 0;
       if (X[u] == skip) X[u] = EMPTY_KEY;
     }
 #pragma unroll
-    for (int u = 0; u < TAB_US; ++u) AX[u] = X[u] != EMPTY_KEY ? A.a[X[u]] : 0;
+    for (int u = 0; u < US; ++u) AX[u] = X[u] != EMPTY_KEY ? A.a[X[u]] : 0;
 #pragma unroll
-    for (int u = 0; u < TAB_US; ++u) {
+    for (int u = 0; u < US; ++u) {
       if (X[u] == EMPTY_KEY) continue;
       const long long sc = A.two_m * V[u] - ki * AX[u];
       if (better(sc, X[u], b.s, b.x)) {
@@ -512,7 +513,7 @@ __device__ __forceinline__ Best table_best(const EvalArgs& A, const int* keys, c
 // One group (a wave, or the whole block) evaluates vertex i with table
 // (keys, vals, mask).  Returns the number of accepted screening tests (0/1)
 // in thread 0 of the group.
-template <int MODE, int G>
+template <int MODE, int G, int UI, int US>
 __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32_t mask,
                           GroupLds<G>& L, int* own) {
   const int t = (G == WAVE) ? lane_id() : int(threadIdx.x);
@@ -531,23 +532,23 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   // issued before any is waited on)
   long long own_part = 0;
   const int w0 = (G == WAVE) ? 0 : int(threadIdx.x) / WAVE;
-  for (int32_t c0 = rb + w0 * WAVE; c0 < re; c0 += TAB_UI * G) {
-    int2 e[TAB_UI];
-    bool valid[TAB_UI];
-    int key[TAB_UI];
+  for (int32_t c0 = rb + w0 * WAVE; c0 < re; c0 += UI * G) {
+    int2 e[UI];
+    bool valid[UI];
+    int key[UI];
 #pragma unroll
-    for (int u = 0; u < TAB_UI; ++u) {
+    for (int u = 0; u < UI; ++u) {
       const int32_t q = c0 + u * G + lane;
       valid[u] = q < re;
       e[u] = valid[u] ? A.adj[q] : make_int2(0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < TAB_UI; ++u) {
+    for (int u = 0; u < UI; ++u) {
       if (e[u].x == i) valid[u] = false;
       key[u] = valid[u] ? A.C[e[u].x] : EMPTY_KEY;
     }
 #pragma unroll
-    for (int u = 0; u < TAB_UI; ++u) {
+    for (int u = 0; u < UI; ++u) {
       if (key[u] == c)
         own_part += e[u].y;
       else if (valid[u])
@@ -587,13 +588,13 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
     group_sync<G>();  // the table is reused by the next item of this group
     return accepted;
   }
-  Best b = table_best<G>(A, keys, vals, mask, ki, EMPTY_KEY, t);
+  Best b = table_best<G, US>(A, keys, vals, mask, ki, EMPTY_KEY, t);
   b = group_best<G>(b, L);
   group_sync<G>();
   const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
   if (MODE == EV_FEAT) {
     // the table holds only foreign labels; a second scan skips the best
-    Best b2 = table_best<G>(A, keys, vals, mask, ki, b.x, t);
+    Best b2 = table_best<G, US>(A, keys, vals, mask, ki, b.x, t);
     b2 = group_best<G>(b2, L);
     if (t == 0) {
       A.f_own[i] = int32_t(e_own);
@@ -634,7 +635,8 @@ __global__ void __launch_bounds__(TPB) k_eval_wtab(EvalArgs A) {
   for (int64_t idx = int64_t(blockIdx.x) * NW + wid; idx < cnt; idx += nwaves) {
     const int i = uniform(A.list[idx]);
     const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], WTAB_SLOTS);
-    accepted += eval_table<MODE, WAVE>(A, i, keys[wid], vals[wid], cap - 1, L[wid], &own[wid]);
+    accepted += eval_table<MODE, WAVE, WTAB_UI, WTAB_US>(A, i, keys[wid], vals[wid], cap - 1,
+                                                         L[wid], &own[wid]);
   }
   if (MODE != EV_SWEEP && lane_id() == 0 && accepted)
     atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC],
@@ -652,22 +654,22 @@ __global__ void __launch_bounds__(TPB) k_eval_btab(EvalArgs A) {
   if (idx >= *A.count) return;  // uniform over the block
   const int i = A.list[idx];
   const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BTAB_SLOTS);
-  int acc = eval_table<MODE, TPB>(A, i, keys, vals, cap - 1, L, &own);
+  int acc = eval_table<MODE, TPB, 4, 8>(A, i, keys, vals, cap - 1, L, &own);
   if (MODE != EV_SWEEP && threadIdx.x == 0 && acc)
     atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC], 1ull);
 }
 
 // bin G: one block per vertex, table in global memory (>= 2 slots per entry)
 template <int MODE>
-__global__ void __launch_bounds__(TPB) k_eval_gtab(EvalArgs A) {
-  __shared__ GroupLds<TPB> L;
+__global__ void __launch_bounds__(GTPB) k_eval_gtab(EvalArgs A) {
+  __shared__ GroupLds<GTPB> L;
   __shared__ int own;
   const int64_t idx = blockIdx.x;
   if (idx >= *A.count) return;
   const int i = A.list[idx];
   const long long o0 = A.tab_off[idx], o1 = A.tab_off[idx + 1];
-  int acc = eval_table<MODE, TPB>(A, i, A.gkeys + o0, A.gvals + o0, uint32_t(o1 - o0) - 1, L,
-                                  &own);
+  int acc = eval_table<MODE, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0,
+                                         uint32_t(o1 - o0) - 1, L, &own);
   if (MODE != EV_SWEEP && threadIdx.x == 0 && acc)
     atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC], 1ull);
 }
@@ -719,7 +721,8 @@ __global__ void __launch_bounds__(TPB) k_sweep_wtab_multi(MultiArgs M) {
     const EvalArgs A = M.descs[g];
     const int i = uniform(M.list[idx]);
     const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], WTAB_SLOTS);
-    (void)eval_table<EV_SWEEP, WAVE>(A, i, keys[wid], vals[wid], cap - 1, L[wid], &own[wid]);
+    (void)eval_table<EV_SWEEP, WAVE, WTAB_UI, WTAB_US>(A, i, keys[wid], vals[wid], cap - 1,
+                                                       L[wid], &own[wid]);
   }
 }
 
@@ -734,7 +737,7 @@ __global__ void __launch_bounds__(TPB) k_sweep_btab_multi(MultiArgs M) {
     const EvalArgs A = M.descs[g];
     const int i = M.list[idx];
     const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BTAB_SLOTS);
-    (void)eval_table<EV_SWEEP, TPB>(A, i, keys, vals, cap - 1, L, &own);
+    (void)eval_table<EV_SWEEP, TPB, 4, 8>(A, i, keys, vals, cap - 1, L, &own);
   }
 }
 
@@ -938,7 +941,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     A.gkeys = bins.gkeys;
     A.gvals = bins.gvals;
     A.tab_off = bins.tab_off;
-    k_eval_gtab<MODE><<<bins.n[5], TPB, 0, st>>>(A);
+    k_eval_gtab<MODE><<<bins.n[5], GTPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
 }
@@ -1165,7 +1168,7 @@ void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const i
   A.gkeys = bins.gkeys;
   A.gvals = bins.gvals;
   A.tab_off = bins.tab_off;
-  k_eval_gtab<EV_SWEEP><<<bins.n[G], TPB, 0, st>>>(A);
+  k_eval_gtab<EV_SWEEP><<<bins.n[G], GTPB, 0, st>>>(A);
   DC_LAUNCH_CHECK();
 }
 

@@ -35,13 +35,8 @@ __global__ void k_validate(const int32_t* __restrict__ u,
       s += x;
     }
   }
-  // combine per wave, one atomic per wave
-  f = wave_or(f);
-  s = wave_sum(s);
-  if (lane_id() == 0) {
-    if (f) atomicOr(flags, f);
-    if (w && s) atomicAdd((unsigned long long*)wsum, (unsigned long long)s);
-  }
+  block_or(f, flags);
+  if (w) block_add(s, wsum);
 }
 
 __global__ void k_make_directed(const int32_t* __restrict__ u,
@@ -234,24 +229,8 @@ __global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
     is_del[r] = op == OP_DELETE ? 1 : 0;
     is_new[r] = op == OP_NEW ? 1 : 0;
   }
-  // one update per block (same-address atomics serialise)
-  __shared__ int bf[TPB / WAVE];
-  __shared__ long long bs[TPB / WAVE];
-  f = wave_or(f);
-  s = wave_sum(s);
-  if (lane_id() == 0) {
-    bf[threadIdx.x / WAVE] = f;
-    bs[threadIdx.x / WAVE] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < TPB / WAVE; ++w) {
-      f |= bf[w];
-      s += bs[w];
-    }
-    if (f) atomicOr(flags, f);
-    if (s) atomicAdd((unsigned long long*)wsum, (unsigned long long)s);
-  }
+  block_or(f, flags);
+  block_add(s, wsum);
 }
 
 
@@ -629,8 +608,7 @@ __global__ void k_intra_weight(const int32_t* __restrict__ off,
       if (C[e.x] == c) s += e.y;
     }
   }
-  s = wave_sum(s);
-  if (lane == 0 && s) atomicAdd((unsigned long long*)I, (unsigned long long)s);
+  block_add(s, I);
 }
 
 __global__ void __launch_bounds__(TPB)
@@ -659,8 +637,7 @@ __global__ void k_sum_squares(const int32_t* __restrict__ a, int32_t n,
     long long x = a[i];
     s += x * x;
   }
-  s = wave_sum(s);
-  if (lane_id() == 0 && s) atomicAdd((unsigned long long*)S, (unsigned long long)s);
+  block_add(s, S);
 }
 
 }  // namespace

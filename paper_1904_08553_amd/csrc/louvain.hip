@@ -106,8 +106,7 @@ __global__ void __launch_bounds__(TPB)
       if (d) s += (long long)e.y * d * (cy != ny ? 1 : 2);
     }
   }
-  s = wave_sum(s);
-  if (lane == 0 && s) atomicAdd((unsigned long long*)&stat_w[ST_DI], (unsigned long long)s);
+  block_add(s, &stat_w[ST_DI]);
 }
 
 __device__ __forceinline__ int unpack_lo(long long d) { return int(uint32_t(uint64_t(d))); }
@@ -127,8 +126,7 @@ __global__ void k_delta_squares(const int32_t* __restrict__ tlist,
     long long an = ao + unpack_lo(dpack[X]);
     s += an * an - ao * ao;
   }
-  s = wave_sum(s);
-  if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&stat[ST_DS], (unsigned long long)s);
+  block_add(s, &stat[ST_DS]);
 }
 
 __global__ void k_finalize(long long* stat, long long two_m) {

@@ -25,6 +25,7 @@ namespace {
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;  // 2048
+constexpr int64_t SCAN_RAW_MAX = 1024;  // tiles whose offsets are summed in-kernel
 
 template <class T>
 __device__ T block_excl_scan(T v, T* lds, T* total) {
@@ -65,12 +66,23 @@ __global__ void __launch_bounds__(SCAN_THREADS)
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// Each thread owns SCAN_ITEMS consecutive elements (blocked layout).
+// Each thread owns SCAN_ITEMS consecutive elements (blocked layout).  The
+// tile's offset is part[blockIdx.x] when part holds exclusive prefixes
+// (raw = 0), or the sum of part[0, blockIdx.x) when it holds the raw tile
+// totals (raw = 1, used for at most SCAN_RAW_MAX tiles).
 template <class T>
 __global__ void __launch_bounds__(SCAN_THREADS)
-    k_tile_scan(const T* in, T* out, int64_t n, const T* __restrict__ part_excl,
+    k_tile_scan(const T* in, T* out, int64_t n, const T* __restrict__ part, int raw,
                 T* total, int64_t nblocks) {
   __shared__ T lds[SCAN_THREADS / WAVE];
+  T off = 0;
+  if (part && raw) {
+    T acc = 0;
+    for (int64_t b = threadIdx.x; b < int64_t(blockIdx.x); b += SCAN_THREADS) acc += part[b];
+    (void)block_excl_scan<T>(acc, lds, &off);
+  } else if (part) {
+    off = part[blockIdx.x];
+  }
   int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
   T v[SCAN_ITEMS];
   T s = 0;
@@ -82,7 +94,6 @@ __global__ void __launch_bounds__(SCAN_THREADS)
   }
   T tot;
   T pre = block_excl_scan<T>(s, lds, &tot);
-  T off = part_excl ? part_excl[blockIdx.x] : T(0);
   T run = off + pre;
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) {
@@ -110,7 +121,7 @@ void scan_excl_impl(const T* in, T* out, int64_t n, T* total, hipStream_t st,
   }
   int64_t nb = ceil_div(n, SCAN_TILE);
   if (nb == 1) {
-    k_tile_scan<T><<<1, SCAN_THREADS, 0, st>>>(in, out, n, nullptr, total, 1);
+    k_tile_scan<T><<<1, SCAN_THREADS, 0, st>>>(in, out, n, nullptr, 0, total, 1);
     DC_LAUNCH_CHECK();
     return;
   }
@@ -118,9 +129,15 @@ void scan_excl_impl(const T* in, T* out, int64_t n, T* total, hipStream_t st,
   T* part = tmp;
   k_tile_reduce<T><<<nb, SCAN_THREADS, 0, st>>>(in, n, part);
   DC_LAUNCH_CHECK();
+  if (nb <= SCAN_RAW_MAX) {
+    // each tile sums the totals before it (at most SCAN_RAW_MAX reads)
+    k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, 1, total, nb);
+    DC_LAUNCH_CHECK();
+    return;
+  }
   // exclusive scan of the block partials in place (recursion on the tail)
   scan_excl_impl<T>(part, part, nb, nullptr, st, tmp + nb, tmp_elems - size_t(nb));
-  k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, total, nb);
+  k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, 0, total, nb);
   DC_LAUNCH_CHECK();
 }
 
