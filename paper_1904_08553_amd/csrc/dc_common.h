@@ -100,6 +100,13 @@ inline uint32_t pow2_ceil32(uint32_t x) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// Orders LDS traffic among the lanes of one wave (no cross-wave barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Butterfly step S of a cross-lane reduction.  Steps 0-3 exchange inside a
 // 16-lane row with DPP (quad xor 1, quad xor 2, half-row mirror, row
 // mirror), step 4 swaps the 16-lane halves of each 32 lanes (ds_swizzle):

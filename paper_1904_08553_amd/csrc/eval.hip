@@ -34,12 +34,6 @@ constexpr int NW = TPB / WAVE;
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Orders LDS traffic among the lanes of one wave (no cross-wave barrier).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 struct Cand {  // Alg. 2 candidate: larger gain, then smaller C(j), then smaller j
   long long g;

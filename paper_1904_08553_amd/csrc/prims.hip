@@ -171,10 +171,16 @@ __global__ void __launch_bounds__(RS_THREADS)
   __syncthreads();
   const uint64_t mask = uint64_t(bins - 1);
   const int64_t base = int64_t(blockIdx.x) * RS_TILE;
-#pragma unroll 4
+  uint64_t k[RS_ROUNDS];
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t idx = base + int64_t(r) * RS_THREADS + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1);
+    k[r] = idx < n ? keys[idx] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t idx = base + int64_t(r) * RS_THREADS + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(k[r] >> shift) & mask], 1);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < bins; b += RS_THREADS)
@@ -203,11 +209,21 @@ __global__ void __launch_bounds__(RS_THREADS)
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   const uint64_t mask = uint64_t(bins - 1);
   const int64_t tile = int64_t(blockIdx.x) * RS_TILE;
+  // the tile's keys and values, all rounds loaded before the first is ranked
+  uint64_t kr[RS_ROUNDS];
+  uint32_t vr[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t idx = tile + int64_t(r) * RS_THREADS + t;
+    kr[r] = idx < n ? kin[idx] : 0;
+    vr[r] = idx < n ? vin[idx] : 0;
+  }
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t idx = tile + int64_t(r) * RS_THREADS + t;
     const bool valid = idx < n;
-    const uint64_t key = valid ? kin[idx] : 0;
-    const uint32_t val = valid ? vin[idx] : 0;
+    const uint64_t key = kr[r];
+    const uint32_t val = vr[r];
     const int d = int((key >> shift) & mask);
     uint64_t m = __ballot(valid);
     for (int b = 0; b < dbits; ++b) {
