@@ -285,6 +285,11 @@ def main():
                     help="also run the paper-scale temporal stream (minutes of host time)")
     ap.add_argument("--temporal-n", type=int, default=8_000_000)
     ap.add_argument("--temporal-events", type=int, default=63_000_000)
+    ap.add_argument("--resolution", action="store_true",
+                    help="also run the temporal-resolution study (cuts of the temporal "
+                         "stream into 2..28 steps; minutes of host time)")
+    ap.add_argument("--resolution-n", type=int, default=8_000_000)
+    ap.add_argument("--resolution-events", type=int, default=63_000_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run three plain device-to-device copies of BYTES bytes (a "
                          "reference kernel of known traffic for hardware byte counters)")
@@ -397,6 +402,17 @@ def main():
         log("temporal-stream leg")
         out["temporal"] = temporal_leg(args.temporal_n, args.temporal_events, 12,
                                        max(10, args.temporal_n // 1000))
+    if args.resolution:
+        log("temporal-resolution leg")
+        from paper_1904_08553_amd import resolution as RS
+        t0 = time.perf_counter()
+        stream = W.temporal_events(n=args.resolution_n, events=args.resolution_events,
+                                   blocks=max(10, args.resolution_n // 1000))
+        log(f"resolution: {len(stream)} events drawn in {time.perf_counter() - t0:.0f} s")
+        out["resolution"] = {
+            "workload": f"temporal stream of {args.resolution_events} unit-weight events over "
+                        f"{args.resolution_n} vertices, cut into K equal-count steps",
+            "rows": RS.study(stream)}
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.n, graph, batches, args.cpu_steps)

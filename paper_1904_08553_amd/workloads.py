@@ -373,8 +373,86 @@ def temporal_stream(n=8_000_000, events=63_000_000, steps=12, ins_frac=0.85,
     return (u, v, w), gen()
 
 
+@dataclass
+class EventStream:
+    """Time-ordered unit-weight edge events: event e inserts (op[e] = 1) or
+    deletes (op[e] = -1) the pair (u[e], v[e]).  The events of one pair
+    alternate, starting with an insertion."""
+    n: int
+    u: np.ndarray
+    v: np.ndarray
+    op: np.ndarray
+
+    def __len__(self):
+        return len(self.u)
+
+
+def temporal_events(n=8_000_000, events=63_000_000, slices=12, seed=0, **kw) -> EventStream:
+    """The stream of ``temporal_stream`` as one event sequence: the initial
+    graph's insertions, then each later slice's insertions and deletions,
+    every slice in a random order (a slice never holds two events of one
+    pair)."""
+    (u0, v0, _), it = temporal_stream(n=n, events=events, steps=slices, seed=seed, **kw)
+    r = _rng(seed, 23)
+    perm = r.permutation(len(u0))
+    us, vs, ops = [u0[perm]], [v0[perm]], [np.ones(len(u0), np.int8)]
+    for t, b in enumerate(it, start=1):
+        r = _rng(seed, 23, t)
+        u = np.concatenate([b.add_u, b.del_u])
+        v = np.concatenate([b.add_v, b.del_v])
+        op = np.concatenate([np.ones(len(b.add_u), np.int8), -np.ones(len(b.del_u), np.int8)])
+        perm = r.permutation(len(u))
+        us.append(u[perm])
+        vs.append(v[perm])
+        ops.append(op[perm])
+    return EventStream(n, np.concatenate(us).astype(np.int32), np.concatenate(vs).astype(np.int32),
+                       np.concatenate(ops))
+
+
+def bin_bounds(count: int, steps: int):
+    """Event index bounds of ``steps`` bins of equal count: bin j holds
+    events [floor(j count / steps), floor((j + 1) count / steps)), so the
+    bins of s steps nest in those of any multiple of s."""
+    return [(j * count) // steps for j in range(steps + 1)]
+
+
+def _net(stream: EventStream, a: int, b: int):
+    """Pairs inserted and deleted on balance by events [a, b)."""
+    if b <= a:
+        e = np.empty(0, np.int64)
+        return e, e
+    k = _key(stream.u[a:b], stream.v[a:b])
+    uk, inv = np.unique(k, return_inverse=True)
+    s = np.bincount(inv, weights=stream.op[a:b].astype(np.float64), minlength=len(uk))
+    if np.any(np.abs(s) > 1):
+        raise ValueError("the events of a pair do not alternate")
+    return uk[s > 0], uk[s < 0]
+
+
+def rebin(stream: EventStream, steps: int):
+    """The stream cut into ``steps`` time steps (``bin_bounds``).  Returns
+    the initial graph (the first bin's pairs inserted on balance, unit
+    weights) and an iterator over the later bins' batches: a pair with more
+    insertions than deletions inside the bin is an insertion (it was absent
+    before the bin), the reverse a deletion, equal counts no change."""
+    bounds = bin_bounds(len(stream), steps)
+    ins0, del0 = _net(stream, bounds[0], bounds[1])
+    if len(del0):
+        raise ValueError("the first bin deletes a pair it never inserted")
+    u, v = _unkey(ins0)
+
+    def gen():
+        for j in range(1, steps):
+            ins, dele = _net(stream, bounds[j], bounds[j + 1])
+            au, av = _unkey(ins)
+            du, dv = _unkey(dele)
+            yield Batch(au, av, np.ones(len(au), np.int32), du, dv)
+
+    return (u, v, np.ones(len(u), np.int32)), gen()
+
+
 # ---------------------------------------------------------------------------
-# Small random dynamic graphs for exhaustive checks.
+# Learned-screener and serving workloads.
 
 
 def screener_graph(seed, n=None, n_lo=100_000, n_hi=1_000_000, steps=4, ins_frac=0.073,
