@@ -550,7 +550,7 @@ static int options_ok(const orc_options* o) {
           o->mode == ORC_MODE_STATIC || o->mode == ORC_MODE_LEARNED) &&
          (o->collect == 0 || o->collect == 1) &&
          (o->del_rule == ORC_DEL_GAIN || o->del_rule == ORC_DEL_CONSERVATIVE) &&
-         o->tau_den >= 0;
+         o->tau_den >= 0 && o->cascade_num >= 0 && o->cascade_den >= 0;
 }
 
 static void fill_info(orc_step_info* info, const trace_t* tr, int32_t levels,
@@ -696,7 +696,7 @@ static void screen_additions(const csr_t* g, const int32_t* C,
                              const int64_t* k, const int64_t* a,
                              int64_t two_m, int64_t na, const int32_t* au,
                              const int32_t* av, uint8_t* R, uint8_t* cflag,
-                             agg_t* ag, orc_step_info* info) {
+                             uint8_t* acc, agg_t* ag, orc_step_info* info) {
   int32_t n = g->n;
   /* directed pairs (source, sink), sorted by source then sink */
   int64_t* dir = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * na + 1));
@@ -741,6 +741,7 @@ static void screen_additions(const csr_t* g, const int32_t* C,
     }
     if (g1 >= g2 && g1 > 0) {
       if (info) info->ds_accepted++;
+      if (acc) acc[i] = 1;
       R[i] = 1;
       R[jstar] = 1;
       for (int64_t e = g->off[i]; e < g->off[i + 1]; ++e) R[g->col[e]] = 1;
@@ -750,6 +751,58 @@ static void screen_additions(const csr_t* g, const int32_t* C,
   }
   (void)n;
   free(dir);
+}
+
+/* Cascade-aware screening (an extension).  After the proof of Lemma 3.2 the
+ * paper notes an indirect effect it does not screen: a neighbour i1 of an
+ * accepted source i that migrates in turn can pull its own neighbours along.
+ * For every accepted addition source i and every neighbour v != i of i with
+ * C(v) = C(i): G1(v) is the gain of v's best move to a neighbouring
+ * community other than C(v) (the largest score over those communities minus
+ * the score of C(v)); when G1(v) >= -theta * 2m * k_v, theta = num/den
+ * (compared exactly in 128-bit integers), v and Gamma_t(v) join R.  A v with
+ * no neighbouring community other than its own is skipped.  Same state as
+ * Alg. 2: G_t, C_{t-1}, totals on G_t. */
+static void screen_cascade(const csr_t* g, const int32_t* C, const int64_t* k,
+                           const int64_t* a, int64_t two_m, const uint8_t* acc,
+                           int64_t num, int64_t den, uint8_t* R, agg_t* ag,
+                           orc_step_info* info) {
+  int32_t n = g->n;
+  uint8_t* cand = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!cand) return;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!acc[i]) continue;
+    for (int64_t e = g->off[i]; e < g->off[i + 1]; ++e) {
+      int32_t v = g->col[e];
+      if (v != i && C[v] == C[i]) cand[v] = 1;
+    }
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    if (!cand[v]) continue;
+    if (info) info->cascade_candidates++;
+    int32_t c = C[v];
+    aggregate(g, C, v, ag);
+    int64_t s_own = score(two_m, ag->seen[c] ? ag->acc[c] : 0, k[v], a[c], 1);
+    int have = 0;
+    int64_t bs = 0;
+    for (int32_t t = 0; t < ag->nt; ++t) {
+      int32_t X = ag->touched[t];
+      if (X == c) continue;
+      int64_t sX = score(two_m, ag->acc[X], k[v], a[X], 0);
+      if (!have || sX > bs) bs = sX;
+      have = 1;
+    }
+    agg_clear(ag);
+    if (!have) continue;
+    __int128 lhs = (__int128)(bs - s_own) * den;
+    __int128 rhs = -(__int128)num * two_m * k[v];
+    if (lhs >= rhs) {
+      if (info) info->cascade_expanded++;
+      R[v] = 1;
+      for (int64_t e = g->off[v]; e < g->off[v + 1]; ++e) R[g->col[e]] = 1;
+    }
+  }
+  free(cand);
 }
 
 /* Deletions (extension; the paper covers additions only).  A source i that
@@ -983,16 +1036,20 @@ int32_t orc_stage_batch(orc_state* s, int64_t na, const int32_t* au,
   int64_t* size = (int64_t*)malloc(sizeof(int64_t) * nn);
   int64_t* touch = (int64_t*)calloc(nn, sizeof(int64_t));
   uint8_t* src = (uint8_t*)calloc(nn, 1);
+  uint8_t* acc = (uint8_t*)calloc(nn, 1);
   int64_t* pairs = (int64_t*)malloc(sizeof(int64_t) * (size_t)(na + nd + 1));
   agg_t ag;
   int have_ag = agg_alloc(&ag, n);
-  int ok = s->R && cflag && k && a && size && touch && src && pairs && have_ag;
+  int ok = s->R && cflag && k && a && size && touch && src && acc && pairs && have_ag;
   if (ok) {
     csr_degrees(&s->g, k);
     totals(&s->g, s->C, k, a, size);
     if (screen) {
       screen_additions(&s->g, s->C, k, a, s->two_m, na, au, av, s->R, cflag,
-                       &ag, &s->sinfo);
+                       acc, &ag, &s->sinfo);
+      if (s->opt.cascade_den > 0)
+        screen_cascade(&s->g, s->C, k, a, s->two_m, acc, s->opt.cascade_num,
+                       s->opt.cascade_den, s->R, &ag, &s->sinfo);
       screen_deletions(&s->g, s->C, k, a, size, s->two_m, nd, du, dv,
                        s->opt.del_rule, s->R, cflag, &ag, &s->sinfo);
       for (int32_t v = 0; v < n; ++v)
@@ -1025,6 +1082,7 @@ int32_t orc_stage_batch(orc_state* s, int64_t na, const int32_t* au,
   free(size);
   free(touch);
   free(src);
+  free(acc);
   free(pairs);
   free(kprev);
   if (!ok) {

@@ -59,6 +59,8 @@ typedef struct orc_options {
   int32_t del_rule;        /* ORC_DEL_* */
   int32_t collect;         /* 1: record screener samples every batch */
   int64_t tau_den;         /* T = floor((2m)^2 / tau_den); 0 means T = 0 */
+  int64_t cascade_num;     /* cascade-aware screening (extension): with     */
+  int64_t cascade_den;     /* den > 0, theta = num/den >= 0; den = 0: off   */
 } orc_options;
 
 /* Screener samples of one batch (the learned screener; not in the paper).
@@ -99,6 +101,9 @@ typedef struct orc_step_info {
   int64_t ds_accepted;    /* addition sources whose test passed */
   int64_t del_sources;    /* deletion sources examined (intra-community) */
   int64_t del_accepted;
+  int64_t cascade_candidates; /* same-community neighbours of accepted
+                                 addition sources examined by the cascade */
+  int64_t cascade_expanded;   /* those whose neighbourhood joined R */
   int32_t levels;         /* levels run */
   int32_t n_sweeps;       /* records written */
   int64_t N;              /* final exact numerator */

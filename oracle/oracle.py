@@ -46,6 +46,7 @@ class Options(ct.Structure):
         ("mode", ct.c_int32), ("max_levels", ct.c_int32),
         ("max_sweeps", ct.c_int32), ("singleton_guard", ct.c_int32),
         ("del_rule", ct.c_int32), ("collect", ct.c_int32), ("tau_den", ct.c_int64),
+        ("cascade_num", ct.c_int64), ("cascade_den", ct.c_int64),
     ]
 
 
@@ -62,7 +63,8 @@ class StepInfo(ct.Structure):
     _fields_ = [
         ("R_size", ct.c_int64), ("ds_sources", ct.c_int64),
         ("ds_accepted", ct.c_int64), ("del_sources", ct.c_int64),
-        ("del_accepted", ct.c_int64), ("levels", ct.c_int32),
+        ("del_accepted", ct.c_int64), ("cascade_candidates", ct.c_int64),
+        ("cascade_expanded", ct.c_int64), ("levels", ct.c_int32),
         ("n_sweeps", ct.c_int32), ("N", ct.c_int64), ("two_m", ct.c_int64),
     ]
 
@@ -118,11 +120,15 @@ def _p(a):
 
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
-            del_rule=DEL_GAIN, tau_den=1000000, collect=0) -> Options:
+            del_rule=DEL_GAIN, tau_den=1000000, collect=0, cascade=None) -> Options:
+    """cascade: None (off) or (num, den), theta = num/den (cascade-aware
+    screening, an extension; see screen_cascade in dc_oracle.c)."""
     o = Options()
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.tau_den = singleton_guard, del_rule, tau_den
     o.collect = collect
+    if cascade is not None:
+        o.cascade_num, o.cascade_den = int(cascade[0]), int(cascade[1])
     return o
 
 

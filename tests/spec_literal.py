@@ -136,9 +136,14 @@ def run_levels(adj0, C0, active0, max_levels=32, max_sweeps=100, tau_den=10**6, 
     return {v: groups[final[v]] for v in final}, trace, level + 1
 
 
-def screen(adj, C, add_pairs, del_pairs, del_rule="gain"):
-    """Alg. 2 on additions plus the deletion extension; returns R_t."""
+def screen(adj, C, add_pairs, del_pairs, del_rule="gain", cascade=None):
+    """Alg. 2 on additions plus the deletion extension; returns R_t.
+    cascade = (num, den): the cascade extension -- every neighbour v of an
+    accepted source i with C(v) = C(i) whose best move to another
+    neighbouring community has Delta Q >= -2 theta k_v / 2m (theta = num/den)
+    adds v and its neighbours."""
     R = set()
+    accepted = []
     sinks = {}
     for a, b in add_pairs:
         sinks.setdefault(a, set()).add(b)
@@ -153,7 +158,19 @@ def screen(adj, C, add_pairs, del_pairs, del_rule="gain"):
         _, js, g1 = best
         g2 = gain(adj, C, js, C[i])
         if g1 >= g2 and g1 > 0:
+            accepted.append(i)
             R |= {i, js} | set(adj[i]) | {v for v in adj if C[v] == C[js]}
+    if cascade is not None:
+        theta = Fraction(cascade[0], cascade[1])
+        tm = two_m(adj)
+        cand = {v for i in accepted for v in adj[i] if v != i and C[v] == C[i]}
+        for v in sorted(cand):
+            others = {C[j] for j in adj[v] if j != v} - {C[v]}
+            if not others:
+                continue
+            best = max(gain(adj, C, v, D) for D in others)
+            if best >= -2 * theta * degree(adj, v) / tm:
+                R |= {v} | set(adj[v])
     srcs = set()
     for a, b in del_pairs:
         if C[a] == C[b]:
@@ -171,10 +188,11 @@ def screen(adj, C, add_pairs, del_pairs, del_rule="gain"):
 class Literal:
     """Dynamic driver mirroring the incremental procedure of Sec. 3.4."""
 
-    def __init__(self, n, u, v, w, mode="delta", del_rule="gain", **lv):
+    def __init__(self, n, u, v, w, mode="delta", del_rule="gain", cascade=None, **lv):
         self.n = n
         self.adj = adjacency(n, u, v, w)
         self.mode, self.del_rule, self.lv = mode, del_rule, lv
+        self.cascade = cascade
         C0 = {i: i for i in range(n)}
         self.C, self.trace, self.levels = run_levels(self.adj, C0, set(range(n)), **lv)
         self.R = set(range(n))
@@ -190,7 +208,8 @@ class Literal:
             self.adj[b][a] = self.adj[b].get(a, 0) + x
         if self.mode == "delta":
             R = screen(self.adj, self.C, list(zip(map(int, au), map(int, av))),
-                       list(zip(map(int, du), map(int, dv))), self.del_rule)
+                       list(zip(map(int, du), map(int, dv))), self.del_rule,
+                       self.cascade)
             C0 = dict(self.C)
         elif self.mode == "all":
             R, C0 = set(range(self.n)), dict(self.C)

@@ -48,6 +48,21 @@ MUTANTS.update({
 })
 
 
+# mistakes in the cascade-aware screening, caught by its pins
+CASCADE = "test_oracle_cascade.py"
+MUTANTS.update({
+    "cascade candidates outside C(i)": ("      if (v != i && C[v] == C[i]) cand[v] = 1;",
+                                         "      if (v != i && C[v] != C[i]) cand[v] = 1;", CASCADE),
+    "cascade threshold flipped": ("    if (lhs >= rhs) {", "    if (lhs <= rhs) {", CASCADE),
+    "cascade forgets Gamma(v)": (
+        "      R[v] = 1;\n      for (int64_t e = g->off[v]; e < g->off[v + 1]; ++e) R[g->col[e]] = 1;\n    }\n  }\n  free(cand);",
+        "      R[v] = 1;\n    }\n  }\n  free(cand);", CASCADE),
+    "cascade best includes the own community": (
+        "      if (X == c) continue;\n      int64_t sX = score(",
+        "      int64_t sX = score(", CASCADE),
+})
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_reject_planted_mistake(name, tmp_path):
     old, new, *target = MUTANTS[name]
