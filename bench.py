@@ -53,12 +53,12 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=float), p)) if xs else None
 
 
-def run_mode(mode, n, graph, batches_dev, warmup, steps, timing):
+def run_mode(mode, n, graph, batches_dev, warmup, steps, timing, **opt):
     import torch
     from paper_1904_08553_amd import dc
     u, v, w = graph
     t0 = time.perf_counter()
-    g = dc.DynamicCommunities(n, u, v, w, mode=mode, timing=timing)
+    g = dc.DynamicCommunities(n, u, v, w, mode=mode, timing=timing, **opt)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t0) * 1e3
     init_stats = g.last_stats()
@@ -248,10 +248,11 @@ def temporal_leg(n, events, steps, blocks):
 
 def learned_leg(seeds, workers=8):
     """Fresh graphs of the screener's workload under full re-evaluation,
-    plain Delta-screening and the trained screener (committed weights)."""
+    plain Delta-screening, Delta-screening with the cascade extension and the
+    trained screener (committed weights)."""
     from paper_1904_08553_amd import screener as S
     w, theta, info = S.load()
-    res = S.evaluate(seeds, w, theta, workers)
+    res = S.evaluate(seeds, w, theta, workers, modes=("all", "delta", "cascade", "learned"))
     out = S.summarize(res)
     out["workload"] = ("planted partition, 100-vertex blocks, n log-uniform in [100K, 1M], 4 "
                        "batches of 7.3% insertions / 2.9% deletions; fresh seeds "
@@ -277,6 +278,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-screener leg")
     ap.add_argument("--learned-seeds", type=int, default=4)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-cascade", action="store_true",
+                    help="skip the cascade-aware screening replay of the main batches")
     ap.add_argument("--serving-graphs", type=int, default=12)
     ap.add_argument("--serving-batches", type=int, default=360)
     ap.add_argument("--serving-nmax", type=int, default=200_000)
@@ -338,6 +341,13 @@ def main():
     else:
         d["g"].close()
 
+    res_casc = None
+    if not args.no_cascade:
+        log("cascade-aware screening run")
+        res_casc = run_mode(dc.MODE_DELTA, args.n, graph, batches_dev, args.warmup, args.steps, 0,
+                            cascade=(1, 20))
+        res_casc["g"].close()
+
     value = d["changes"] / d["total_s"]
     out = {
         "metric": METRIC,
@@ -380,6 +390,16 @@ def main():
             "speedup_delta_over_full": f["total_s"] / d["total_s"],
             "max_rel_q_diff": max(rel),
             "matched_modularity_within_0.1pct": bool(max(rel) <= 1e-3),
+        }
+    if res_casc is not None:
+        cz = res_casc
+        out["cascade"] = {
+            "theta": [1, 20],
+            "value": cz["changes"] / cz["total_s"],
+            "ms_per_step": cz["total_s"] * 1e3 / args.steps,
+            "R_frac_mean": float(np.mean(cz["R_frac"])),
+            "q": cz["q"],
+            "max_rel_q_diff_vs_delta": max(abs(a - b) / abs(b) for a, b in zip(cz["q"], d["q"])),
         }
     if d["k_launch"] > 0 and d["k_ms"] > 0:
         ach = d["k_bytes"] / (d["k_ms"] * 1e-3) / 1e9

@@ -97,7 +97,18 @@ typedef struct dc_options {
                               G_t; 0 (default): from the previous step's
                               graph of communities, the batch's changes and
                               the level-0 movers' rows (same result)       */
-  int64_t reserved[3];     /* must be zero                                   */
+  int64_t cascade_num;     /* cascade-aware screening (an extension for the
+                              indirect effect noted after the proof of
+                              Lemma 3.2): with cascade_den > 0 and theta =
+                              cascade_num / cascade_den, every neighbour v of
+                              an accepted addition source i with
+                              C_{t-1}(v) = C_{t-1}(i) whose best move to
+                              another neighbouring community has scaled gain
+                              G1(v) >= -theta * 2m * k_v adds v and its
+                              neighbours to R_t (DELTA and the screening pass
+                              of LEARNED / collect); both >= 0              */
+  int64_t cascade_den;     /* 0 (default): no cascade                        */
+  int64_t reserved[1];     /* must be zero                                   */
 } dc_options;
 
 /* An edge list: count entries (u[e], v[e], w[e]).  w is ignored (may be
@@ -153,7 +164,9 @@ typedef struct dc_step_stats {
   int64_t touched;        /* touched vertices of the batch (LEARNED mode or
                              collect = 1), else 0                          */
   int64_t screened;       /* 1 when the screener network chose R_t         */
-  int64_t reserved[2];
+  int64_t cascade_candidates; /* same-community neighbours of accepted
+                                 addition sources examined by the cascade  */
+  int64_t cascade_expanded;   /* those whose neighbourhood joined R_t      */
 } dc_step_stats;
 
 typedef struct dc_ctx dc_ctx;

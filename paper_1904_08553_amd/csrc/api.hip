@@ -39,8 +39,8 @@ bool options_ok(const dc_options* o) {
   if (o->max_levels < 1 || o->max_sweeps < 1) return false;
   if (o->del_rule != DC_DEL_GAIN && o->del_rule != DC_DEL_CONSERVATIVE) return false;
   if (o->tau_den < 0) return false;
-  for (int i = 0; i < 3; ++i)
-    if (o->reserved[i] != 0) return false;
+  if (o->cascade_num < 0 || o->cascade_den < 0) return false;
+  if (o->reserved[0] != 0) return false;
   return true;
 }
 
@@ -526,29 +526,85 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     int32_t* dflag = c->dflag.as<int32_t>();
     fill_i32(dflag, 0, n, st);
     deletion_sources(ch_key, ch_op, nch, n, c->C.as<int32_t>(), dflag, st);
-    int32_t* dpos = c->dpos.as<int32_t>();
-    scan_excl_i32(dflag, dpos, n, dpos + n, st);
-    compact_index(dflag, dpos, n, c->dlist.as<int32_t>(), st);
-    DC_HIP(hipMemcpyAsync(c->hbuf, dpos + n, 4, hipMemcpyDeviceToHost, st));
-    read_stat(c);
-    const int64_t n_src = n_ins > 0 ? int32_t(hs[ST_N3]) : 0;
-    const int64_t n_dsrc = *static_cast<int32_t*>(c->hbuf);
-    if (n_src > 0) {
-      Bins b;
-      make_bins(c->src_list.as<int32_t>(), n_src, g0.off, b, c->bins, st);
-      ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
-                   c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), b, R, cflag, stat, st);
+    const bool fused = c->opt.del_rule == DC_DEL_GAIN;
+    const bool cascade = c->opt.cascade_den > 0;
+    uint8_t* accflag = nullptr;
+    if (cascade) {
+      c->accflag.ensure(size_t(n) + 1);
+      accflag = c->accflag.as<uint8_t>();
+      fill_u8(accflag, 0, n, st);
     }
-    if (n_dsrc > 0) {
-      if (c->opt.del_rule == DC_DEL_CONSERVATIVE) {
-        mark_neighbourhoods(c->dlist.as<int32_t>(), n_dsrc, g0.off, g0.adj, R, st);
-      } else {
+    int64_t n_src = 0, n_dsrc = 0;
+    if (fused) {
+      // one evaluation pass over the insertion sources and the deletion
+      // endpoints together (Alg. 2 and the deletion rule read the same state)
+      c->uflag.ensure(size_t(n) + 1);
+      c->ulist.ensure(size_t(n + 1) * 4);
+      uint8_t* uflag = c->uflag.as<uint8_t>();
+      int32_t* f32 = c->rflag.as<int32_t>();
+      int32_t* p32 = c->rpos2.as<int32_t>();
+      fill_u8(uflag, 0, n, st);
+      union_flags(c->src_list.as<int32_t>(), reinterpret_cast<int32_t*>(stat + ST_N3), n_ins,
+                  dflag, n, uflag, f32, stat + ST_DEL_SRC, st);
+      scan_excl_i32(f32, p32, n, reinterpret_cast<int32_t*>(stat + ST_N0), st);
+      compact_index(f32, p32, n, c->ulist.as<int32_t>(), st);
+      read_stat(c);
+      n_src = n_ins > 0 ? int32_t(hs[ST_N3]) : 0;
+      n_dsrc = hs[ST_DEL_SRC];
+      const int64_t n_u = int32_t(hs[ST_N0]);
+      if (n_u > 0) {
         Bins b;
-        make_bins(c->dlist.as<int32_t>(), n_dsrc, g0.off, b, c->bins, st);
-        ds_deletions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->sz0.as<int32_t>(),
-                     c->two_m, b, R, cflag, stat, st);
+        make_bins(c->ulist.as<int32_t>(), n_u, g0.off, b, c->bins, st);
+        ds_both(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
+                c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), uflag, b, R, cflag, accflag,
+                stat, st);
+      }
+    } else {
+      int32_t* dpos = c->dpos.as<int32_t>();
+      scan_excl_i32(dflag, dpos, n, dpos + n, st);
+      compact_index(dflag, dpos, n, c->dlist.as<int32_t>(), st);
+      DC_HIP(hipMemcpyAsync(c->hbuf, dpos + n, 4, hipMemcpyDeviceToHost, st));
+      read_stat(c);
+      n_src = n_ins > 0 ? int32_t(hs[ST_N3]) : 0;
+      n_dsrc = *static_cast<int32_t*>(c->hbuf);
+      if (n_src > 0) {
+        Bins b;
+        make_bins(c->src_list.as<int32_t>(), n_src, g0.off, b, c->bins, st);
+        ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
+                     c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), b, R, cflag, accflag,
+                     stat, st);
       }
     }
+    if (cascade && n_src > 0) {
+      // same-community neighbours of the accepted sources, their best gains
+      // to another community (EV_FEAT), and the neighbourhoods that join R
+      c->cascand.ensure(size_t(n) + 1);
+      c->clist.ensure(size_t(n + 1) * 4);
+      uint8_t* cand = c->cascand.as<uint8_t>();
+      fill_u8(cand, 0, n, st);
+      cascade_candidates(c->src_list.as<int32_t>(), n_src, accflag, g0.off, g0.adj,
+                         c->C.as<int32_t>(), cand, st);
+      int32_t* f32 = c->rflag.as<int32_t>();
+      int32_t* p32 = c->rpos2.as<int32_t>();
+      merge_flags(cand, nullptr, n, f32, st);
+      scan_excl_i32(f32, p32, n, reinterpret_cast<int32_t*>(stat + ST_CASC_CAND), st);
+      compact_index(f32, p32, n, c->clist.as<int32_t>(), st);
+      read_stat(c);
+      const int64_t n_cand = int32_t(hs[ST_CASC_CAND]);
+      S.cascade_candidates = n_cand;
+      if (n_cand > 0) {
+        ensure_sample_state(c);
+        Bins b;
+        make_bins(c->clist.as<int32_t>(), n_cand, g0.off, b, c->bins, st);
+        feat_eval(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, b,
+                  c->f_own.as<int32_t>(), c->f_g1.as<long long>(), c->f_g2.as<long long>(), st);
+        cascade_mark(c->clist.as<int32_t>(), n_cand, c->f_g1.as<long long>(), g0.k, c->two_m,
+                     c->opt.cascade_num, c->opt.cascade_den, g0.off, g0.adj, R,
+                     stat + ST_CASC_EXP, st);
+      }
+    }
+    if (n_dsrc > 0 && !fused)
+      mark_neighbourhoods(c->dlist.as<int32_t>(), n_dsrc, g0.off, g0.adj, R, st);
     int32_t* rflag = c->rflag.as<int32_t>();
     int32_t* rpos2 = c->rpos2.as<int32_t>();
     materialize_R(R, cflag, c->C.as<int32_t>(), n, rflag, st);
@@ -562,7 +618,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     S.del_sources = n_dsrc;
     S.del_accepted = c->opt.del_rule == DC_DEL_CONSERVATIVE ? n_dsrc : hs[ST_DEL_ACC];
     S.R_size = c->R_count;
-    S.vertex_evals += S.ds_sources + S.del_sources;
+    S.cascade_expanded = hs[ST_CASC_EXP];
+    S.vertex_evals += S.ds_sources + S.del_sources + S.cascade_candidates;
   }
   if (samples) {
     const bool score = mode == DC_MODE_LEARNED && c->have_scr;
@@ -671,6 +728,7 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->new_deg, &c->ins_flag, &c->ins_pos, &c->ins_keys, &c->src_flag,
                   &c->src_pos, &c->src_list, &c->dflag, &c->dpos, &c->dlist, &c->R, &c->cflag,
                   &c->rflag, &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end, &c->chsrc,
+                  &c->accflag, &c->cascand, &c->clist, &c->uflag, &c->ulist,
                   &c->bigrows, &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
                   &c->f_g1, &c->f_g2, &c->X, &c->y, &c->logits, &c->Cl, &c->Cn, &c->al,
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],

@@ -28,6 +28,8 @@ struct dc_ctx {
   DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
   DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
   DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc, bigrows;
+  DBuf accflag, cascand, clist;  // cascade-aware screening
+  DBuf uflag, ulist;             // union of insertion sources and deletion endpoints
   // learned screener: touched set, features, labels, scores
   DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
   bool have_scr = false;

@@ -26,12 +26,16 @@ enum StatSlot : int {
   ST_FLAGS = 16,   // batch validation flags (int32 in the low half)
   ST_WSUM_ADD = 17,
   ST_WSUM_DEL = 18,
+  ST_CASC_CAND = 19,  // cascade candidates (int32 in the low half)
+  ST_CASC_EXP = 20,   // cascade candidates whose neighbourhood joined R
   ST_COUNT = 24
 };
 
 // EV_FEAT: e_{i->C(i)} and the gains to the best and second-best other
 // neighbouring community, the integer inputs of the screener features.
-enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2, EV_FEAT = 3 };
+// EV_DSBOTH: Alg. 2 and the deletion rule in one pass over the union of
+// the insertion sources and the deletion endpoints (EvalArgs::uflag).
+enum EvalMode : int { EV_SWEEP = 0, EV_DSADD = 1, EV_DSDEL = 2, EV_FEAT = 3, EV_DSBOTH = 4 };
 constexpr long long NO_GAIN = (long long)0x8000000000000000ull;
 
 // Row-length bins of the evaluation kernels (eval.hip): rows of at most 16,
@@ -75,6 +79,8 @@ struct EvalArgs {
   int32_t n0;
   uint8_t* R;
   uint8_t* cflag;
+  uint8_t* accflag;  // EV_DSADD: accepted sources flagged here (null: not kept)
+  const uint8_t* uflag;  // EV_DSBOTH: bit 0 insertion source, bit 1 deletion endpoint
   int32_t* f_own;  // EV_FEAT outputs, indexed by vertex
   long long* f_g1;
   long long* f_g2;
@@ -119,10 +125,38 @@ void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, in
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                   const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
                   const int32_t* seg_end, const Bins& bins, uint8_t* R, uint8_t* cflag,
-                  long long* stat, hipStream_t st);
-void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
-                  long long two_m, const Bins& bins, uint8_t* R, uint8_t* cflag,
-                  long long* stat, hipStream_t st);
+                  uint8_t* accflag, long long* stat, hipStream_t st);
+
+// Alg. 2 over the insertion sources and the deletion rule over the deletion
+// endpoints in one evaluation pass: bins hold the union, uflag[v] bit 0
+// marks an insertion source (its sinks in ins_keys[seg_beg[v], seg_end[v])),
+// bit 1 a deletion endpoint (the deletion rule, extension: a move with a
+// positive gain adds the endpoint, its neighbours and the members of its best
+// community).  Same effect as running the two screenings one after the other.
+void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
+             const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
+             const int32_t* seg_end, const uint8_t* uflag, const Bins& bins, uint8_t* R,
+             uint8_t* cflag, uint8_t* accflag, long long* stat, hipStream_t st);
+// uflag[v] |= 1 for v in list[0, *count) (count on the device); then
+// uflag[v] |= 2 where dflag[v] != 0, flag[v] = uflag[v] != 0, and
+// *ndel += the number of such v.
+void union_flags(const int32_t* list, const int32_t* count, int64_t max_count,
+                 const int32_t* dflag, int32_t n, uint8_t* uflag, int32_t* flag, long long* ndel,
+                 hipStream_t st);
+
+// Cascade-aware screening (extension of Alg. 2; see dc_options.cascade_*):
+// cand[v] = 1 for every neighbour v != i of a flagged accepted source i of
+// list[0, cnt) with C[v] == C[i].
+void cascade_candidates(const int32_t* list, int64_t cnt, const uint8_t* accflag,
+                        const int32_t* off, const int2* adj, const int32_t* C, uint8_t* cand,
+                        hipStream_t st);
+// For v in list[0, cnt) with f_g1[v] != NO_GAIN and
+// f_g1[v] * den >= -num * two_m * k[v] (exact, 128-bit): R[v] = 1 and R of
+// its neighbours = 1; *expanded += the number of such v.
+void cascade_mark(const int32_t* list, int64_t cnt, const long long* f_g1, const int32_t* k,
+                  long long two_m, long long num, long long den, const int32_t* off,
+                  const int2* adj, uint8_t* R, long long* expanded, hipStream_t st);
+
 
 // ---- merged sweeps of several graphs (one launch per row-length bin) ----
 // Bins S16..B of several graphs concatenated, each graph's part padded to

@@ -49,7 +49,7 @@ __device__ __forceinline__ bool cand_better(const Cand& p, const Cand& q) {
 // gain2 of Alg. 2: G(j* -> c), streamed over the row of j* by one wave.
 // The row is walked RG_U chunks per round: their entry loads, then their
 // label gathers, are issued before any is waited on.
-constexpr int RG_U = 4;
+constexpr int RG_U = 8;
 
 template <int G>
 __device__ __forceinline__ void row_to_two(const EvalArgs& A, int js, int cj, int c, int t,
@@ -193,6 +193,17 @@ __device__ __forceinline__ int group_collect(bool valid, int key, int w, int* ls
   return r;
 }
 
+// Accepted screening tests, counted in one integer: insertion sources (Alg.
+// 2) in the low 32 bits, deletion endpoints in the high 32 bits.
+constexpr long long ACC_ADD = 1;
+constexpr long long ACC_DEL = 1ll << 32;
+
+__device__ __forceinline__ void add_accepted(long long* stat, long long acc) {
+  const long long add = acc & 0xffffffffll, del = acc >> 32;
+  if (add) atomicAdd((unsigned long long*)&stat[ST_DS_ACC], (unsigned long long)add);
+  if (del) atomicAdd((unsigned long long*)&stat[ST_DEL_ACC], (unsigned long long)del);
+}
+
 // Sweep decision of vertex i: the group's first lane writes the next label
 // unless the singleton guard (Sec. 3.2) holds the move back.
 __device__ __forceinline__ void sweep_commit(const EvalArgs& A, int i, bool move, int c, int x,
@@ -233,9 +244,13 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     }
     return accepted;
   }
-  if (MODE == EV_DSADD) {
-    const int q0 = have ? A.seg_beg[i] : 0;
-    const int nsk = have ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
+  // EV_DSBOTH: the Alg. 2 test for insertion sources (flag bit 0) and the
+  // deletion rule for deletion endpoints (bit 1) on the same aggregation
+  const int uf = MODE == EV_DSBOTH ? (have ? int(A.uflag[i]) : 0) : (MODE == EV_DSADD ? 1 : 2);
+  if (MODE == EV_DSADD || MODE == EV_DSBOTH) {
+    const bool ins = have && (uf & 1);
+    const int q0 = ins ? A.seg_beg[i] : 0;
+    const int nsk = ins ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
     const bool has = gl < nsk;
     const int sj = has ? int(A.ins_keys[q0 + gl] - uint64_t(i) * uint64_t(A.n0)) : 0;
     const int Xj = has ? A.C[sj] : EMPTY_KEY;
@@ -252,7 +267,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
       cd = {g, Xj, sj};
     }
     const Cand best = group_cand_w<GS>(cd);
-    const bool live = have && best.j != NO_LABEL && best.x != c && best.g > 0;
+    const bool live = ins && best.j != NO_LABEL && best.x != c && best.g > 0;
     // gain2 of each live group, streamed by the whole wave (j* is often a
     // high-degree vertex, and a 16-lane group would walk its row alone)
     long long g2 = 0;
@@ -269,10 +284,11 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
         A.R[i] = 1;
         A.R[best.j] = 1;
         A.cflag[best.x] = 1;
-        accepted++;
+        if (A.accflag) A.accflag[i] = 1;
+        accepted += ACC_ADD;
       }
     }
-    return accepted;
+    if (MODE == EV_DSADD) return accepted;
   }
   Best b = {NO_SCORE, NO_LABEL};
   if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
@@ -280,12 +296,12 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   bool move = have && b.x != NO_LABEL && b.s > s_own;
   if (MODE == EV_SWEEP) {
     sweep_commit(A, i, move, c, b.x, gl);
-  } else if (move) {  // EV_DSDEL
+  } else if (move && (uf & 2)) {  // EV_DSDEL, EV_DSBOTH
     if (e.x >= 0) A.R[e.x] = 1;
     if (gl == 0) {
       A.R[i] = 1;
       A.cflag[b.x] = 1;
-      accepted++;
+      accepted += ACC_DEL;
     }
   }
   return accepted;
@@ -360,9 +376,7 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
     accepted += group_item<MODE, GS>(A, i, have, lane, gl, gbase, ls);
   }
   accepted = group_sum_ll<WAVE>(accepted);
-  if (MODE != EV_SWEEP && lane == 0 && accepted)
-    atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC],
-              (unsigned long long)accepted);
+  if (MODE != EV_SWEEP && lane == 0 && accepted) add_accepted(A.stat, accepted);
 }
 
 // --------------------------------------------------------------------------
@@ -508,8 +522,8 @@ __device__ __forceinline__ Best table_best(const EvalArgs& A, const int* keys, c
 // (keys, vals, mask).  Returns the number of accepted screening tests (0/1)
 // in thread 0 of the group.
 template <int MODE, int G, int UI, int US>
-__device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32_t mask,
-                          GroupLds<G>& L, int* own) {
+__device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32_t mask,
+                                GroupLds<G>& L, int* own) {
   const int t = (G == WAVE) ? lane_id() : int(threadIdx.x);
   const int lane = lane_id();
   const int32_t rb = A.off[i], re = A.off[i + 1];
@@ -552,8 +566,11 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   long long e_own = own_part, unused = 0;
   group_sum2<G>(e_own, unused, L);
   group_sync<G>();
-  int accepted = 0;
-  if (MODE == EV_DSADD) {
+  long long accepted = 0;
+  // EV_DSBOTH: Alg. 2 for an insertion source (flag bit 0), then the
+  // deletion rule for a deletion endpoint (bit 1), on the same table
+  const int uf = MODE == EV_DSBOTH ? int(A.uflag[i]) : (MODE == EV_DSADD ? 1 : 2);
+  if ((MODE == EV_DSADD || MODE == EV_DSBOTH) && (uf & 1)) {
     const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
     const int64_t q0 = A.seg_beg[i], q1 = A.seg_end[i];
     const uint64_t base = uint64_t(i) * uint64_t(A.n0);
@@ -575,13 +592,14 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
           A.R[i] = 1;
           A.R[best.j] = 1;
           A.cflag[best.x] = 1;
-          accepted = 1;
+          if (A.accflag) A.accflag[i] = 1;
+          accepted = ACC_ADD;
         }
       }
     }
-    group_sync<G>();  // the table is reused by the next item of this group
-    return accepted;
+    group_sync<G>();  // the table is reused (by the deletion rule or the next item)
   }
+  if (MODE == EV_DSADD || (MODE == EV_DSBOTH && !(uf & 2))) return accepted;
   Best b = table_best<G, US>(A, keys, vals, mask, ki, EMPTY_KEY, t);
   b = group_best<G>(b, L);
   group_sync<G>();
@@ -602,12 +620,12 @@ __device__ int eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32
   if (MODE == EV_SWEEP) {
     if (move && A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c) move = false;
     if (move && t == 0) A.Cn[i] = b.x;
-  } else if (move) {  // EV_DSDEL
+  } else if (move) {  // EV_DSDEL, EV_DSBOTH
     for (int32_t q = rb + t; q < re; q += G) A.R[A.adj[q].x] = 1;
     if (t == 0) {
       A.R[i] = 1;
       A.cflag[b.x] = 1;
-      accepted = 1;
+      accepted += ACC_DEL;
     }
   }
   // the table is reused by the next item of this group
@@ -632,9 +650,7 @@ __global__ void __launch_bounds__(TPB) k_eval_wtab(EvalArgs A) {
     accepted += eval_table<MODE, WAVE, WTAB_UI, WTAB_US>(A, i, keys[wid], vals[wid], cap - 1,
                                                          L[wid], &own[wid]);
   }
-  if (MODE != EV_SWEEP && lane_id() == 0 && accepted)
-    atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC],
-              (unsigned long long)accepted);
+  if (MODE != EV_SWEEP && lane_id() == 0 && accepted) add_accepted(A.stat, accepted);
 }
 
 // bin B: one block per vertex, block-shared LDS table
@@ -648,9 +664,8 @@ __global__ void __launch_bounds__(TPB) k_eval_btab(EvalArgs A) {
   if (idx >= *A.count) return;  // uniform over the block
   const int i = A.list[idx];
   const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BTAB_SLOTS);
-  int acc = eval_table<MODE, TPB, 4, 8>(A, i, keys, vals, cap - 1, L, &own);
-  if (MODE != EV_SWEEP && threadIdx.x == 0 && acc)
-    atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC], 1ull);
+  const long long acc = eval_table<MODE, TPB, 4, 8>(A, i, keys, vals, cap - 1, L, &own);
+  if (MODE != EV_SWEEP && threadIdx.x == 0 && acc) add_accepted(A.stat, acc);
 }
 
 // bin G: one block per vertex, table in global memory (>= 2 slots per entry)
@@ -662,10 +677,9 @@ __global__ void __launch_bounds__(GTPB) k_eval_gtab(EvalArgs A) {
   if (idx >= *A.count) return;
   const int i = A.list[idx];
   const long long o0 = A.tab_off[idx], o1 = A.tab_off[idx + 1];
-  int acc = eval_table<MODE, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0,
-                                         uint32_t(o1 - o0) - 1, L, &own);
-  if (MODE != EV_SWEEP && threadIdx.x == 0 && acc)
-    atomicAdd((unsigned long long*)&A.stat[MODE == EV_DSADD ? ST_DS_ACC : ST_DEL_ACC], 1ull);
+  const long long acc = eval_table<MODE, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0,
+                                                     uint32_t(o1 - o0) - 1, L, &own);
+  if (MODE != EV_SWEEP && threadIdx.x == 0 && acc) add_accepted(A.stat, acc);
 }
 
 // --------------------------------------------------------------------------
@@ -1022,7 +1036,7 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                   const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
                   const int32_t* seg_end, const Bins& bins, uint8_t* R, uint8_t* cflag,
-                  long long* stat, hipStream_t st) {
+                  uint8_t* accflag, long long* stat, hipStream_t st) {
   EvalArgs A{};
   A.off = g.off;
   A.adj = g.adj;
@@ -1038,7 +1052,32 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
   A.n0 = g.n;
   A.R = R;
   A.cflag = cflag;
+  A.accflag = accflag;
   launch_eval<EV_DSADD>(A, bins, st, nullptr, nullptr);
+}
+
+void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
+             const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
+             const int32_t* seg_end, const uint8_t* uflag, const Bins& bins, uint8_t* R,
+             uint8_t* cflag, uint8_t* accflag, long long* stat, hipStream_t st) {
+  EvalArgs A{};
+  A.off = g.off;
+  A.adj = g.adj;
+  A.k = g.k;
+  A.C = C;
+  A.a = a;
+  A.two_m = two_m;
+  A.stat = stat;
+  A.ins_keys = ins_keys;
+  A.seg_beg = seg_beg;
+  A.seg_end = seg_end;
+  A.n_ins = n_ins;
+  A.n0 = g.n;
+  A.R = R;
+  A.cflag = cflag;
+  A.accflag = accflag;
+  A.uflag = uflag;
+  launch_eval<EV_DSBOTH>(A, bins, st, nullptr, nullptr);
 }
 
 void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
@@ -1056,24 +1095,6 @@ void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long
   A.f_g1 = f_g1;
   A.f_g2 = f_g2;
   launch_eval<EV_FEAT>(A, bins, st, nullptr, nullptr);
-}
-
-void ds_deletions(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
-                  long long two_m, const Bins& bins, uint8_t* R, uint8_t* cflag,
-                  long long* stat, hipStream_t st) {
-  EvalArgs A{};
-  A.off = g.off;
-  A.adj = g.adj;
-  A.k = g.k;
-  A.C = C;
-  A.a = a;
-  A.sz = sz;
-  A.two_m = two_m;
-  A.stat = stat;
-  A.n0 = g.n;
-  A.R = R;
-  A.cflag = cflag;
-  launch_eval<EV_DSDEL>(A, bins, st, nullptr, nullptr);
 }
 
 EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,

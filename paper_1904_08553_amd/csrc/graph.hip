@@ -270,11 +270,13 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
+constexpr int MC_ROWS = 4;  // unchanged rows a wave copies per round
+
 // Untouched rows move as a block: entry e of row r goes to
 // e + off_new[r] - off_old[r].  A wave takes 64 consecutive rows: one
 // coalesced load brings each row's bounds, shift and changed-flag into a
-// lane, then the wave copies the rows one after another with contiguous
-// reads and writes.
+// lane, then the wave copies the unchanged rows MC_ROWS at a time with
+// contiguous reads and writes.
 __global__ void __launch_bounds__(TPB)
     k_merge_copy(const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
                  const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
@@ -292,13 +294,37 @@ __global__ void __launch_bounds__(TPB)
       shift = off_new[r] - beg;
       skip = cptr[r] != cptr[r + 1];
     }
-    // rows to copy, in lane order
-    for (uint64_t todo = __ballot(!skip && end > beg); todo; todo &= todo - 1) {
-      const int l = __ffsll((unsigned long long)todo) - 1;
-      const int b = __builtin_amdgcn_readlane(beg, l);
-      const int e = __builtin_amdgcn_readlane(end, l);
-      const int sh = __builtin_amdgcn_readlane(shift, l);
-      for (int q = b + lane; q < e; q += WAVE) adj_new[q + sh] = adj_old[q];
+    // rows to copy, in lane order, MC_ROWS per round: the rounds' loads are
+    // issued before their stores
+    uint64_t todo = __ballot(!skip && end > beg);
+    while (todo) {
+      int b[MC_ROWS], e[MC_ROWS], sh[MC_ROWS];
+      int longest = 0;
+#pragma unroll
+      for (int k = 0; k < MC_ROWS; ++k) {
+        b[k] = e[k] = sh[k] = 0;
+        if (todo) {
+          const int l = __ffsll((unsigned long long)todo) - 1;
+          todo &= todo - 1;
+          b[k] = __builtin_amdgcn_readlane(beg, l);
+          e[k] = __builtin_amdgcn_readlane(end, l);
+          sh[k] = __builtin_amdgcn_readlane(shift, l);
+          longest = e[k] - b[k] > longest ? e[k] - b[k] : longest;
+        }
+      }
+      for (int o = 0; o < longest; o += WAVE) {
+        int2 v[MC_ROWS];
+#pragma unroll
+        for (int k = 0; k < MC_ROWS; ++k) {
+          const int q = b[k] + o + lane;
+          v[k] = q < e[k] ? adj_old[q] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < MC_ROWS; ++k) {
+          const int q = b[k] + o + lane;
+          if (q < e[k]) adj_new[q + sh[k]] = v[k];
+        }
+      }
     }
   }
 }
@@ -350,6 +376,7 @@ __device__ void merge_row_search(int32_t row, int32_t n, const int2* __restrict_
 
 constexpr int WROW_CH = 4;                 // row chunks a wave holds in registers
 constexpr int BIG_ROW = 1024;              // longer rows are merged by a block
+constexpr int MERGE_ROWS = 4;              // rows a wave merges per iteration
 constexpr int BIG_CHANGES = 4096;          // changes staged in LDS per big row
 constexpr int BIG_SEG = BIG_CHANGES / TPB; // histogram bins per thread in the scan
 constexpr int BIG_U = 4;                   // row chunks per load round of a block
@@ -455,8 +482,9 @@ __global__ void __launch_bounds__(TPB)
 // per lane; a loop over the changes, each broadcast by readlane, gives every
 // old entry its shift (insertions minus deletions before it) and its fate,
 // and every change the number of old entries with a smaller neighbour (one
-// ballot per chunk), which places the insertions.  A wave takes two rows
-// per iteration and issues both rows' loads before it waits on either.
+// ballot per chunk), which places the insertions.  A wave takes
+// MERGE_ROWS rows per iteration and issues all their loads before it waits
+// on any.
 // Other rows are listed for k_merge_big.
 struct MergeRow {
   int32_t ob, deg, nb, nchg;
@@ -569,26 +597,27 @@ __global__ void __launch_bounds__(TPB)
   const int lane = lane_id();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   for (int64_t p = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE; p < nrows;
-       p += 2 * nwaves) {
-    const bool hb = p + nwaves < nrows;
-    const int32_t rowA = rows[p];
-    const int32_t rowB = hb ? rows[p + nwaves] : 0;
-    MergeRow A, B;
-    int32_t cbA, cbB;
-    merge_head(A, rowA, true, off_old, off_new, cptr, &cbA);
-    merge_head(B, rowB, hb, off_old, off_new, cptr, &cbB);
-    if (A.deg > BIG_ROW || A.nchg > WAVE) {
-      if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = rowA;
-      A.live = false;
+       p += MERGE_ROWS * nwaves) {
+    MergeRow M[MERGE_ROWS];
+    int32_t row[MERGE_ROWS], cb[MERGE_ROWS];
+#pragma unroll
+    for (int r = 0; r < MERGE_ROWS; ++r) {
+      const bool h = p + r * nwaves < nrows;
+      row[r] = h ? rows[p + r * nwaves] : 0;
+      merge_head(M[r], row[r], h, off_old, off_new, cptr, &cb[r]);
     }
-    if (B.live && (B.deg > BIG_ROW || B.nchg > WAVE)) {
-      if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = rowB;
-      B.live = false;
+#pragma unroll
+    for (int r = 0; r < MERGE_ROWS; ++r) {
+      if (M[r].live && (M[r].deg > BIG_ROW || M[r].nchg > WAVE)) {
+        if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = row[r];
+        M[r].live = false;
+      }
     }
-    merge_load(A, rowA, cbA, n, adj_old, ch_key, ch_op, ch_w, lane);
-    merge_load(B, rowB, cbB, n, adj_old, ch_key, ch_op, ch_w, lane);
-    merge_finish(A, adj_old, adj_new, lane, lt);
-    merge_finish(B, adj_old, adj_new, lane, lt);
+#pragma unroll
+    for (int r = 0; r < MERGE_ROWS; ++r)
+      merge_load(M[r], row[r], cb[r], n, adj_old, ch_key, ch_op, ch_w, lane);
+#pragma unroll
+    for (int r = 0; r < MERGE_ROWS; ++r) merge_finish(M[r], adj_old, adj_new, lane, lt);
   }
 }
 

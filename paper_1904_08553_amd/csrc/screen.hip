@@ -104,6 +104,76 @@ __global__ void k_materialize_R(uint8_t* R, const uint8_t* __restrict__ cflag,
 
 }  // namespace
 
+// Cascade-aware screening (an extension for the indirect effect noted after
+// the proof of Lemma 3.2).  One wave per source of the list: the neighbours
+// of an accepted source in its own community C_{t-1}(i) become candidates.
+__global__ void __launch_bounds__(TPB)
+    k_cascade_candidates(const int32_t* __restrict__ list, int64_t cnt,
+                         const uint8_t* __restrict__ accflag, const int32_t* __restrict__ off,
+                         const int2* __restrict__ adj, const int32_t* __restrict__ C,
+                         uint8_t* cand) {
+  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
+  const int lane = lane_id();
+  for (int64_t p = (int64_t(blockIdx.x) * TPB + threadIdx.x) / WAVE; p < cnt; p += nwaves) {
+    const int i = list[p];
+    if (!accflag[i]) continue;  // uniform: one source per wave
+    const int ci = C[i];
+    for (int32_t q = off[i] + lane; q < off[i + 1]; q += WAVE) {
+      const int v = adj[q].x;
+      if (v != i && C[v] == ci) cand[v] = 1;
+    }
+  }
+}
+
+// One wave per candidate v: with G1(v) the scaled gain of v's best move to
+// another neighbouring community (f_g1, NO_GAIN when there is none), v and
+// its neighbours join R when G1(v) * den >= -num * 2m * k_v, compared in
+// 128-bit integers.
+__global__ void __launch_bounds__(TPB)
+    k_cascade_mark(const int32_t* __restrict__ list, int64_t cnt,
+                   const long long* __restrict__ f_g1, const int32_t* __restrict__ k,
+                   long long two_m, long long num, long long den,
+                   const int32_t* __restrict__ off, const int2* __restrict__ adj, uint8_t* R,
+                   long long* expanded) {
+  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
+  const int lane = lane_id();
+  long long cntx = 0;
+  for (int64_t p = (int64_t(blockIdx.x) * TPB + threadIdx.x) / WAVE; p < cnt; p += nwaves) {
+    const int v = list[p];
+    const long long g1 = f_g1[v];
+    if (g1 == NO_GAIN) continue;  // uniform
+    const __int128 lhs = (__int128)g1 * den;
+    const __int128 rhs = -(__int128)num * two_m * k[v];
+    if (lhs < rhs) continue;
+    if (lane == 0) {
+      R[v] = 1;
+      cntx++;
+    }
+    for (int32_t q = off[v] + lane; q < off[v + 1]; q += WAVE) R[adj[q].x] = 1;
+  }
+  block_add(cntx, expanded);
+}
+
+__global__ void k_src_bits(const int32_t* __restrict__ list, const int32_t* __restrict__ count,
+                           uint8_t* uflag) {
+  const int64_t cnt = *count;
+  GRID_STRIDE(p, cnt) { uflag[list[p]] = 1; }
+}
+
+__global__ void __launch_bounds__(TPB)
+    k_union_flags(const int32_t* __restrict__ dflag, int32_t n, uint8_t* uflag, int32_t* flag,
+                  long long* ndel) {
+  long long c = 0;
+  GRID_STRIDE(v, n) {
+    const bool d = dflag[v] != 0;
+    const uint8_t f = uint8_t(uflag[v] | (d ? 2 : 0));
+    uflag[v] = f;
+    flag[v] = f != 0 ? 1 : 0;
+    c += d ? 1 : 0;
+  }
+  block_add(c, ndel);
+}
+
 void compact_index(const int32_t* flag, const int32_t* pos, int64_t n, int32_t* out,
                    hipStream_t st) {
   if (n <= 0) return;
@@ -162,6 +232,36 @@ void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n
                    int32_t* rflag, hipStream_t st) {
   if (n <= 0) return;
   k_materialize_R<<<grid_for(n), TPB, 0, st>>>(R, cflag, C, n, rflag);
+  DC_LAUNCH_CHECK();
+}
+
+void cascade_candidates(const int32_t* list, int64_t cnt, const uint8_t* accflag,
+                        const int32_t* off, const int2* adj, const int32_t* C, uint8_t* cand,
+                        hipStream_t st) {
+  if (cnt <= 0) return;
+  k_cascade_candidates<<<grid_for(cnt * WAVE), TPB, 0, st>>>(list, cnt, accflag, off,
+                                                                       adj, C, cand);
+  DC_LAUNCH_CHECK();
+}
+
+void cascade_mark(const int32_t* list, int64_t cnt, const long long* f_g1, const int32_t* k,
+                  long long two_m, long long num, long long den, const int32_t* off,
+                  const int2* adj, uint8_t* R, long long* expanded, hipStream_t st) {
+  if (cnt <= 0) return;
+  k_cascade_mark<<<grid_for(cnt * WAVE), TPB, 0, st>>>(list, cnt, f_g1, k, two_m, num,
+                                                                 den, off, adj, R, expanded);
+  DC_LAUNCH_CHECK();
+}
+
+void union_flags(const int32_t* list, const int32_t* count, int64_t max_count,
+                 const int32_t* dflag, int32_t n, uint8_t* uflag, int32_t* flag, long long* ndel,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  if (max_count > 0) {
+    k_src_bits<<<grid_for(max_count), TPB, 0, st>>>(list, count, uflag);
+    DC_LAUNCH_CHECK();
+  }
+  k_union_flags<<<grid_for(n, 512), TPB, 0, st>>>(dflag, n, uflag, flag, ndel);
   DC_LAUNCH_CHECK();
 }
 

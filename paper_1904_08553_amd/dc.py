@@ -31,7 +31,8 @@ class Options(ct.Structure):
         ("mode", ct.c_int32), ("max_levels", ct.c_int32), ("max_sweeps", ct.c_int32),
         ("singleton_guard", ct.c_int32), ("del_rule", ct.c_int32), ("timing", ct.c_int32),
         ("tau_den", ct.c_int64), ("stream", ct.c_void_p), ("collect", ct.c_int32),
-        ("full_coarsen", ct.c_int32), ("reserved", ct.c_int64 * 3),
+        ("full_coarsen", ct.c_int32), ("cascade_num", ct.c_int64), ("cascade_den", ct.c_int64),
+        ("reserved", ct.c_int64 * 1),
     ]
 
 
@@ -60,7 +61,7 @@ class StepStats(ct.Structure):
         ("sweep_launches", ct.c_int64), ("sweep_bytes", ct.c_int64),
         ("level0_sweeps", ct.c_int64), ("level0_active", ct.c_int64),
         ("level0_volume", ct.c_int64), ("touched", ct.c_int64), ("screened", ct.c_int64),
-        ("reserved", ct.c_int64 * 2),
+        ("cascade_candidates", ct.c_int64), ("cascade_expanded", ct.c_int64),
     ]
 
     def as_dict(self):
@@ -230,13 +231,17 @@ def current_stream():
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
             del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current", collect=0,
-            full_coarsen=0):
+            full_coarsen=0, cascade=None):
+    """cascade: None (off) or (num, den) for the cascade-aware screening
+    threshold theta = num/den."""
     o = Options()
     load().dc_default_options(ct.byref(o))
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.timing, o.tau_den = singleton_guard, del_rule, timing, tau_den
     o.collect = collect
     o.full_coarsen = full_coarsen
+    if cascade is not None:
+        o.cascade_num, o.cascade_den = int(cascade[0]), int(cascade[1])
     o.stream = current_stream() if stream == "current" else stream
     return o
 

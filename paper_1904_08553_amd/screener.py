@@ -160,17 +160,24 @@ def load(path=WEIGHTS):
     return w, float(d["theta"]), d.get("info", {})
 
 
+CASCADE = (1, 20)  # theta of the cascade-aware screening compared here
+
+
 def evaluate(seeds, w, theta, workers=8, modes=("all", "delta", "learned"), n=None):
     """Each graph's four batches under full re-evaluation (ALL), plain
-    Delta-screening and LEARNED; per mode the batch times (each call returns
-    after C_t is written), changes, Q per batch, level-0 evaluations."""
+    Delta-screening, Delta-screening with the cascade extension (mode
+    "cascade", threshold CASCADE) and LEARNED; per mode the batch times (each
+    call returns after C_t is written), changes, Q per batch, level-0
+    evaluations."""
     import torch
-    code = {"all": dc.MODE_ALL, "delta": dc.MODE_DELTA, "learned": dc.MODE_LEARNED}
+    code = {"all": dc.MODE_ALL, "delta": dc.MODE_DELTA, "cascade": dc.MODE_DELTA,
+            "learned": dc.MODE_LEARNED}
     out = {m: dict(ms=[], changes=0, q=[], level0=0, R=0, touched=0) for m in modes}
     for s, nn, (u, v, w_), batches in graphs(seeds, workers, n):
         dev = _dev_batches(batches)
         for m in modes:
-            g = dc.DynamicCommunities(nn, u, v, w_, mode=code[m])
+            extra = {"cascade": CASCADE} if m == "cascade" else {}
+            g = dc.DynamicCommunities(nn, u, v, w_, mode=code[m], **extra)
             if m == "learned":
                 g.set_screener(w, theta)
             torch.cuda.synchronize()
@@ -204,6 +211,10 @@ def summarize(res):
     if "delta" in s and "learned" in s:
         s["learned_speedup_over_delta"] = (s["learned"]["edge_updates_per_s"]
                                            / s["delta"]["edge_updates_per_s"])
+    if "delta" in s and "cascade" in s:
+        s["cascade_speedup_over_delta"] = (s["cascade"]["edge_updates_per_s"]
+                                           / s["delta"]["edge_updates_per_s"])
+        s["cascade_theta"] = list(CASCADE)
     return s
 
 

@@ -12,13 +12,13 @@ MODES = {"delta": (O.MODE_DELTA, dc.MODE_DELTA), "all": (O.MODE_ALL, dc.MODE_ALL
 
 
 def make_pair(n, u, v, w, mode="delta", max_levels=32, max_sweeps=100, guard=1,
-              del_rule=0, tau_den=1_000_000):
+              del_rule=0, tau_den=1_000_000, cascade=None):
     om, gm = MODES[mode]
     o = O.Oracle(n, u, v, w, mode=om, max_levels=max_levels, max_sweeps=max_sweeps,
-                 singleton_guard=guard, del_rule=del_rule, tau_den=tau_den)
+                 singleton_guard=guard, del_rule=del_rule, tau_den=tau_den, cascade=cascade)
     g = dc.DynamicCommunities(n, u, v, w, mode=gm, max_levels=max_levels,
                               max_sweeps=max_sweeps, singleton_guard=guard, del_rule=del_rule,
-                              tau_den=tau_den)
+                              tau_den=tau_den, cascade=cascade)
     return o, g
 
 
