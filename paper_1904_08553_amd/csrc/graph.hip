@@ -376,7 +376,7 @@ __device__ void merge_row_search(int32_t row, int32_t n, const int2* __restrict_
 
 constexpr int WROW_CH = 4;                 // row chunks a wave holds in registers
 constexpr int BIG_ROW = 1024;              // longer rows are merged by a block
-constexpr int MERGE_ROWS = 4;              // rows a wave merges per iteration
+constexpr int MERGE_ROWS = 2;              // rows a wave merges per iteration
 constexpr int BIG_CHANGES = 4096;          // changes staged in LDS per big row
 constexpr int BIG_SEG = BIG_CHANGES / TPB; // histogram bins per thread in the scan
 constexpr int BIG_U = 4;                   // row chunks per load round of a block

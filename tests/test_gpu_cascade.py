@@ -57,3 +57,16 @@ def test_cascade_with_hubs():
         step_pair(o, g, b)
         compare(o, g, f"step {t}")
         _check_counts(o, g, f"step {t}")
+
+
+def test_cascade_with_conservative_deletion_rule():
+    """The conservative deletion rule keeps separate screening passes; the
+    cascade runs on the accepted insertion sources there too."""
+    _log("case: cascade + conservative deletions")
+    pp = W.PlantedPartition()
+    (u, v, w), batches = pp.batches()
+    o, g = make_pair(pp.n, u, v, w, cascade=(1, 4), del_rule=1)
+    for t, b in enumerate(batches):
+        step_pair(o, g, b)
+        compare(o, g, f"step {t}")
+        _check_counts(o, g, f"step {t}")
