@@ -157,7 +157,7 @@ void scan_excl(const T* in, T* out, int64_t n, T* total, hipStream_t st) {
 constexpr int RS_THREADS = 256;
 constexpr int RS_ROUNDS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 2048 keys per block
-constexpr int RS_MAX_DIGIT = 8;  // wider digits cost more per pass than they save
+constexpr int RS_MAX_DIGIT = 10;  // 40-bit keys in 4 passes
 constexpr int RS_BINS = 1 << RS_MAX_DIGIT;       // bins of the widest digit
 constexpr int RS_WAVES = RS_THREADS / WAVE;
 
