@@ -67,6 +67,8 @@ struct EvalArgs {
   long long two_m;
   int32_t guard;
   const int32_t* list;   // vertices (or sources) of this bin
+  const int32_t* list_rb;  // their row starts (set for bins built by make_bins)
+  int64_t nnz;             // adjacency entries of the level graph
   const int32_t* count;  // device count of list
   int* gkeys;            // bin G tables
   int* gvals;
@@ -89,6 +91,7 @@ struct EvalArgs {
 struct Bins {
   int64_t n[NBINS];
   const int32_t* list[NBINS];
+  const int32_t* list_rb[NBINS];  // row start (off[v]) of each listed vertex
   long long vol[NBINS];       // adjacency entries of each bin
   const int32_t* count_dev;   // NBINS device counts
   int* gkeys;
@@ -97,7 +100,7 @@ struct Bins {
 };
 
 struct BinScratch {
-  DBuf lists, bcnt, boff, counts, tab_off, gkeys, gvals;
+  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals;
   void* host = nullptr;  // pinned, 256 bytes
 };
 

@@ -311,17 +311,19 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
 // the chain row bounds -> entries -> neighbour labels -> community totals
 // issues both items' loads before it waits on either, so a wave keeps
 // twice the gathers in flight.  The arithmetic is group_item<EV_SWEEP>'s.
+// The row starts come with the bin list, so the entry loads are issued
+// with the row-end loads: a lane past its row's end reads another row's
+// entry (any index below nnz) and drops it once the row end is known.
 template <int GS>
-__device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, int i1, bool h1,
-                                           int gl, int* lsum) {
-  const int32_t rb0 = h0 ? A.off[i0] : 0, re0 = h0 ? A.off[i0 + 1] : 0;
-  const int32_t rb1 = h1 ? A.off[i1] : 0, re1 = h1 ? A.off[i1 + 1] : 0;
+__device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0,
+                                           int i1, bool h1, int32_t rb1, int gl, int* lsum) {
+  const int32_t re0 = h0 ? A.off[i0 + 1] : 0, re1 = h1 ? A.off[i1 + 1] : 0;
   const int c0 = h0 ? A.C[i0] : 0, c1 = h1 ? A.C[i1] : 0;
   const long long k0 = h0 ? A.k[i0] : 0, k1 = h1 ? A.k[i1] : 0;
-  const int2 e0 = rb0 + gl < re0 ? A.adj[rb0 + gl] : make_int2(-1, 0);
-  const int2 e1 = rb1 + gl < re1 ? A.adj[rb1 + gl] : make_int2(-1, 0);
+  const int2 e0 = h0 && rb0 + gl < A.nnz ? A.adj[rb0 + gl] : make_int2(-1, 0);
+  const int2 e1 = h1 && rb1 + gl < A.nnz ? A.adj[rb1 + gl] : make_int2(-1, 0);
   const long long ao0 = h0 ? A.a[c0] : 0, ao1 = h1 ? A.a[c1] : 0;
-  const bool v0 = e0.x >= 0 && e0.x != i0, v1 = e1.x >= 0 && e1.x != i1;
+  const bool v0 = rb0 + gl < re0 && e0.x != i0, v1 = rb1 + gl < re1 && e1.x != i1;
   const int key0 = v0 ? A.C[e0.x] : EMPTY_KEY;
   const int key1 = v1 ? A.C[e1.x] : EMPTY_KEY;
   int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0;
@@ -365,7 +367,9 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
       const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
       const int i0 = h0 ? A.list[idx0] : 0;
       const int i1 = h1 ? A.list[idx1] : 0;
-      sweep_pair<GS>(A, i0, h0, i1, h1, gl, ls);
+      const int32_t rb0 = h0 ? A.list_rb[idx0] : 0;
+      const int32_t rb1 = h1 ? A.list_rb[idx1] : 0;
+      sweep_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
     }
     return;
   }
@@ -832,7 +836,7 @@ __global__ void __launch_bounds__(TPB)
 __global__ void __launch_bounds__(TPB)
     k_bin_scatter(const int32_t* __restrict__ list, int64_t cnt,
                   const int32_t* __restrict__ off, const int32_t* __restrict__ boff,
-                  int64_t nblocks, int32_t* out) {
+                  int64_t nblocks, int32_t* out, int32_t* out_rb) {
   __shared__ int base[NBINS];
   __shared__ int wc[NW][NBINS];
   const int wid = threadIdx.x / WAVE, lane = lane_id();
@@ -842,10 +846,11 @@ __global__ void __launch_bounds__(TPB)
   for (int r = 0; r < BIN_ITEMS; ++r) {
     int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
     const bool valid = p < cnt;
-    int u = 0, b = -1;
+    int u = 0, b = -1, rb = 0;
     if (valid) {
       u = list ? list[p] : int(p);
-      b = bin_of(off[u + 1] - off[u]);
+      rb = off[u];
+      b = bin_of(off[u + 1] - rb);
     }
     int rank = 0;
 #pragma unroll
@@ -859,6 +864,7 @@ __global__ void __launch_bounds__(TPB)
       int pos = base[b] + rank;
       for (int w = 0; w < wid; ++w) pos += wc[w][b];
       out[pos] = u;
+      out_rb[pos] = rb;
     }
     __syncthreads();
     if (threadIdx.x < NBINS) {
@@ -915,6 +921,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   EvalArgs A = base;
   auto setbin = [&](int q) {
     A.list = bins.list[q];
+    A.list_rb = bins.list_rb[q];
     A.count = bins.count_dev + q;
   };
   if (bins.n[0] > 0) {
@@ -961,6 +968,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   const int64_t nb = count > 0 ? ceil_div(count, BIN_TILE) : 1;
   const int64_t cap = count > 0 ? count : 1;
   s.lists.ensure(size_t(cap) * sizeof(int32_t));
+  s.lists_rb.ensure(size_t(cap) * sizeof(int32_t));
   s.bcnt.ensure(size_t(NBINS * nb + 1) * sizeof(int32_t));
   s.boff.ensure(size_t(NBINS * nb + 1) * sizeof(int32_t));
   constexpr size_t META = 32 * sizeof(int32_t) + NBINS * sizeof(long long);
@@ -985,9 +993,11 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   const int32_t* hc = static_cast<const int32_t*>(s.host);
   const long long* hv = reinterpret_cast<const long long*>(hc + 32);
   int32_t* lists = s.lists.as<int32_t>();
+  int32_t* lists_rb = s.lists_rb.as<int32_t>();
   for (int q = 0; q < NBINS; ++q) {
     b.n[q] = hc[q];
     b.list[q] = lists + hc[NBINS + q];
+    b.list_rb[q] = lists_rb + hc[NBINS + q];
     b.vol[q] = hv[q];
   }
   b.count_dev = counts;
@@ -995,7 +1005,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.gvals = nullptr;
   b.tab_off = nullptr;
   if (count > 0) {
-    k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, boff, nb, lists);
+    k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, boff, nb, lists, lists_rb);
     DC_LAUNCH_CHECK();
   }
   constexpr int G = NBINS - 1;
@@ -1020,6 +1030,7 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
                 long long* stat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   EvalArgs A{};
   A.off = g.off;
+  A.nnz = g.nnz;
   A.adj = g.adj;
   A.k = g.k;
   A.C = C;
@@ -1039,6 +1050,7 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
                   uint8_t* accflag, long long* stat, hipStream_t st) {
   EvalArgs A{};
   A.off = g.off;
+  A.nnz = g.nnz;
   A.adj = g.adj;
   A.k = g.k;
   A.C = C;
@@ -1062,6 +1074,7 @@ void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, long long t
              uint8_t* cflag, uint8_t* accflag, long long* stat, hipStream_t st) {
   EvalArgs A{};
   A.off = g.off;
+  A.nnz = g.nnz;
   A.adj = g.adj;
   A.k = g.k;
   A.C = C;
@@ -1085,6 +1098,7 @@ void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long
                hipStream_t st) {
   EvalArgs A{};
   A.off = g.off;
+  A.nnz = g.nnz;
   A.adj = g.adj;
   A.k = g.k;
   A.C = C;
@@ -1101,6 +1115,7 @@ EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int
                     const int32_t* sz, long long two_m, int guard) {
   EvalArgs A{};
   A.off = g.off;
+  A.nnz = g.nnz;
   A.adj = g.adj;
   A.k = g.k;
   A.C = C;
