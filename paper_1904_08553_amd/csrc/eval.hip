@@ -145,6 +145,26 @@ __device__ __forceinline__ int group_bcast(int v, int r) {
   return out;
 }
 
+// The value of the lane of each lane's own group whose flag is set (at most
+// one per group), 0 when none is: one ballot and a readlane per group.
+template <int GS>
+__device__ __forceinline__ int group_pick(bool flag, int v) {
+  constexpr int GPW = WAVE / GS;
+  const uint64_t m = __ballot(flag);
+  int out = 0;
+#pragma unroll
+  for (int g = 0; g < GPW; ++g) {
+    uint64_t sub;
+    if constexpr (GPW == 1)
+      sub = m;
+    else
+      sub = (m >> (g * GS)) & ((uint64_t(1) << GS) - 1);
+    const int x = sub ? __builtin_amdgcn_readlane(v, g * GS + __builtin_ctzll(sub)) : 0;
+    if (int(lane_id()) / GS == g) out = x;
+  }
+  return out;
+}
+
 // Per group: lane r of the group (r < returned count) receives the r-th
 // distinct label of the group's valid lanes (order of first appearance)
 // and its weight sum.  Each iteration takes, for every group of the wave at
@@ -154,14 +174,15 @@ __device__ __forceinline__ int group_bcast(int v, int r) {
 // entry and on return.
 template <int GS>
 __device__ __forceinline__ int group_collect(bool valid, int key, int w, int* lsum, int& ck,
-                                             int& cs) {
+                                             int& cs, int* iters = nullptr) {
   constexpr int GPW = WAVE / GS;
   const int lane = lane_id();
   const int gl = lane & (GS - 1);
   const int grp = lane / GS;
   uint64_t rem = __ballot(valid);
-  int r = 0, myr = 0;
+  int r = 0, myr = 0, it = 0;
   while (rem) {
+    ++it;
     int kl = 0;
     bool act = false;
 #pragma unroll
@@ -190,7 +211,26 @@ __device__ __forceinline__ int group_collect(bool valid, int key, int w, int* ls
   cs = gl < r ? lsum[lane] : 0;
   lsum[lane] = 0;
   wave_sync();
+  if (iters) *iters = it;  // wave-uniform: the largest count of any group
   return r;
+}
+
+// Best (score, label) of lanes [0, 2^steps) of each group, in the group's
+// first lane (the other lanes hold partial results): candidates sit in the
+// first nd lanes of a group, so ceil(log2(nd)) butterfly steps suffice.
+template <int GS>
+__device__ __forceinline__ Best group_best_first(Best b, int nd_max) {
+  if (nd_max > 1) b = best_step<0>(b);
+  if (nd_max > 2) b = best_step<1>(b);
+  if (nd_max > 4) b = best_step<2>(b);
+  if (GS > 8 && nd_max > 8) b = best_step<3>(b);
+  if (GS > 16 && nd_max > 16) b = best_step<4>(b);
+  if (GS > 32 && nd_max > 32) {
+    const Best y = {readlane64(b.s, 32), __builtin_amdgcn_readlane(b.x, 32)};
+    const Best z = {readlane64(b.s, 0), __builtin_amdgcn_readlane(b.x, 0)};
+    b = better(y.s, y.x, z.s, z.x) ? y : z;
+  }
+  return b;
 }
 
 // Accepted screening tests, counted in one integer: insertion sources (Alg.
@@ -314,33 +354,42 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
 // The row starts come with the bin list, so the entry loads are issued
 // with the row-end loads: a lane past its row's end reads another row's
 // entry (any index below nnz) and drops it once the row end is known.
+// Loads use clamped indices (every index is valid memory; an absent item
+// reads entry 0) so that no load needs a branch: the kernel is bound by
+// vector-instruction issue, not by memory.
 template <int GS>
 __device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0,
                                            int i1, bool h1, int32_t rb1, int gl, int* lsum) {
-  const int32_t re0 = h0 ? A.off[i0 + 1] : 0, re1 = h1 ? A.off[i1 + 1] : 0;
-  const int c0 = h0 ? A.C[i0] : 0, c1 = h1 ? A.C[i1] : 0;
-  const long long k0 = h0 ? A.k[i0] : 0, k1 = h1 ? A.k[i1] : 0;
-  const int2 e0 = h0 && rb0 + gl < A.nnz ? A.adj[rb0 + gl] : make_int2(-1, 0);
-  const int2 e1 = h1 && rb1 + gl < A.nnz ? A.adj[rb1 + gl] : make_int2(-1, 0);
-  const long long ao0 = h0 ? A.a[c0] : 0, ao1 = h1 ? A.a[c1] : 0;
+  const int32_t x0 = A.off[i0 + 1], x1 = A.off[i1 + 1];
+  const int32_t re0 = h0 ? x0 : 0, re1 = h1 ? x1 : 0;
+  const int c0 = A.C[i0], c1 = A.C[i1];
+  const int k0 = A.k[i0], k1 = A.k[i1];
+  const int64_t last = A.nnz > 0 ? A.nnz - 1 : 0;
+  const int2 e0 = A.adj[rb0 + gl < last ? rb0 + gl : last];
+  const int2 e1 = A.adj[rb1 + gl < last ? rb1 + gl : last];
+  const int ao0 = A.a[c0], ao1 = A.a[c1];
   const bool v0 = rb0 + gl < re0 && e0.x != i0, v1 = rb1 + gl < re1 && e1.x != i1;
-  const int key0 = v0 ? A.C[e0.x] : EMPTY_KEY;
-  const int key1 = v1 ? A.C[e1.x] : EMPTY_KEY;
-  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0;
-  const int nd0 = group_collect<GS>(v0, key0, e0.y, lsum, ck0, cs0);
-  const int nd1 = group_collect<GS>(v1, key1, e1.y, lsum, ck1, cs1);
+  const int y0 = A.C[v0 ? e0.x : 0], y1 = A.C[v1 ? e1.x : 0];  // e.x is only valid in-row
+  const int key0 = v0 ? y0 : EMPTY_KEY;
+  const int key1 = v1 ? y1 : EMPTY_KEY;
+  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0, it0 = 0, it1 = 0;
+  const int nd0 = group_collect<GS>(v0, key0, e0.y, lsum, ck0, cs0, &it0);
+  const int nd1 = group_collect<GS>(v1, key1, e1.y, lsum, ck1, cs1, &it1);
   const bool p0 = gl < nd0 && ck0 != c0, p1 = gl < nd1 && ck1 != c1;
-  const long long ak0 = p0 ? A.a[ck0] : 0;
-  const long long ak1 = p1 ? A.a[ck1] : 0;
-  const long long own0 = group_sum_ll<GS>(gl < nd0 && ck0 == c0 ? (long long)cs0 : 0);
-  const long long own1 = group_sum_ll<GS>(gl < nd1 && ck1 == c1 ? (long long)cs1 : 0);
-  const long long s0 = A.two_m * own0 - k0 * (ao0 - k0);
-  const long long s1 = A.two_m * own1 - k1 * (ao1 - k1);
+  const int ak0 = A.a[p0 ? ck0 : 0];
+  const int ak1 = A.a[p1 ? ck1 : 0];
+  // e_{i->C(i)}: the weight sum parked in the one lane holding label C(i)
+  const int own0 = group_pick<GS>(gl < nd0 && ck0 == c0, cs0);
+  const int own1 = group_pick<GS>(gl < nd1 && ck1 == c1, cs1);
+  // 2m < 2^31, so every factor fits in 32 bits: one 32x32->64 product each
+  const int tm = int(A.two_m);
+  const long long s0 = (long long)tm * own0 - (long long)k0 * (ao0 - k0);
+  const long long s1 = (long long)tm * own1 - (long long)k1 * (ao1 - k1);
   Best b0 = {NO_SCORE, NO_LABEL}, b1 = {NO_SCORE, NO_LABEL};
-  if (p0) b0 = {A.two_m * cs0 - k0 * ak0, ck0};
-  if (p1) b1 = {A.two_m * cs1 - k1 * ak1, ck1};
-  b0 = group_best_w<GS>(b0);
-  b1 = group_best_w<GS>(b1);
+  if (p0) b0 = {(long long)tm * cs0 - (long long)k0 * ak0, ck0};
+  if (p1) b1 = {(long long)tm * cs1 - (long long)k1 * ak1, ck1};
+  b0 = group_best_first<GS>(b0, it0);
+  b1 = group_best_first<GS>(b1, it1);
   sweep_commit(A, i0, h0 && b0.x != NO_LABEL && b0.s > s0, c0, b0.x, gl);
   sweep_commit(A, i1, h1 && b1.x != NO_LABEL && b1.s > s1, c1, b1.x, gl);
 }
@@ -365,10 +414,10 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
     for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
       const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
       const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
-      const int i0 = h0 ? A.list[idx0] : 0;
-      const int i1 = h1 ? A.list[idx1] : 0;
-      const int32_t rb0 = h0 ? A.list_rb[idx0] : 0;
-      const int32_t rb1 = h1 ? A.list_rb[idx1] : 0;
+      const int64_t j0 = h0 ? idx0 : 0, j1 = h1 ? idx1 : 0;  // valid indices
+      const int i0 = h0 ? A.list[j0] : 0;
+      const int i1 = h1 ? A.list[j1] : 0;
+      const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
       sweep_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
     }
     return;
@@ -512,7 +561,8 @@ __device__ __forceinline__ Best table_best(const EvalArgs& A, const int* keys, c
 #pragma unroll
     for (int u = 0; u < US; ++u) {
       if (X[u] == EMPTY_KEY) continue;
-      const long long sc = A.two_m * V[u] - ki * AX[u];
+      // 2m < 2^31: 32x32->64 products
+      const long long sc = (long long)int(A.two_m) * V[u] - (long long)int(ki) * AX[u];
       if (better(sc, X[u], b.s, b.x)) {
         b.s = sc;
         b.x = X[u];
