@@ -270,11 +270,12 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   int ck = EMPTY_KEY, cs = 0;
   const int nd = group_collect<GS>(valid, key, e.y, lsum, ck, cs);
   const bool pair = gl < nd;
-  const long long e_own = group_sum_ll<GS>(pair && ck == c ? (long long)cs : 0);
-  const long long s_own = A.two_m * e_own - ki * ((have ? A.a[c] : 0) - ki);
+  const long long e_own = group_pick<GS>(pair && ck == c, cs);
+  const int tm = int(A.two_m);  // 2m < 2^31: 32x32->64 products
+  const long long s_own = (long long)tm * e_own - ki * ((have ? A.a[c] : 0) - ki);
   if (MODE == EV_FEAT) {
     Best b = {NO_SCORE, NO_LABEL};
-    if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
+    if (pair && ck != c) b = {(long long)tm * cs - (long long)int(ki) * A.a[ck], ck};
     const Best b1 = group_best_w<GS>(b);
     const Best b2 = group_best_w<GS>(b.x != b1.x ? b : Best{NO_SCORE, NO_LABEL});
     if (have && gl == 0) {
@@ -303,7 +304,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     }
     Cand cd = {NO_SCORE, NO_LABEL, NO_LABEL};
     if (has) {
-      long long g = Xj == c ? 0 : A.two_m * ej - ki * A.a[Xj] - s_own;
+      long long g = Xj == c ? 0 : (long long)tm * int(ej) - (long long)int(ki) * A.a[Xj] - s_own;
       cd = {g, Xj, sj};
     }
     const Cand best = group_cand_w<GS>(cd);
@@ -331,7 +332,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     if (MODE == EV_DSADD) return accepted;
   }
   Best b = {NO_SCORE, NO_LABEL};
-  if (pair && ck != c) b = {A.two_m * cs - ki * A.a[ck], ck};
+  if (pair && ck != c) b = {(long long)tm * cs - (long long)int(ki) * A.a[ck], ck};
   b = group_best_w<GS>(b);
   bool move = have && b.x != NO_LABEL && b.s > s_own;
   if (MODE == EV_SWEEP) {
