@@ -30,6 +30,24 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = os.path.join(ROOT, "profiles", "k_eval_group32_dcsbm_1M_20M_traffic.json")
 
 
+ISSUE = os.path.join(ROOT, "profiles", "k_eval_group32_dcsbm_1M_20M_issue.json")
+
+
+def measured_issue():
+    """Share of the chip's vector-instruction issue capacity the timed kernel
+    used, from the counter pass recorded in profiles/ (None once the kernel
+    source has changed)."""
+    import hashlib
+    try:
+        rec = json.load(open(ISSUE))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return {"valu_issue_frac": rec["valu_issue_frac"], "summary": rec["summary"]}
+
+
 def measured_traffic():
     """HBM bytes per launch of the timed kernel from the counter passes
     recorded in profiles/, or None once the kernel source has changed."""
@@ -410,6 +428,7 @@ def main():
             "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "launches": d["k_launch"], "avg_launch_us": d["k_ms"] * 1e3 / d["k_launch"],
             "bytes_per_launch": d["k_bytes"] / d["k_launch"],
+            "instruction_issue": measured_issue(),
         }
     if not args.no_learned:
         log("learned-screener leg")
