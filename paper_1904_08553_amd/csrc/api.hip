@@ -720,8 +720,7 @@ void destroy_ctx(dc_ctx* c) {
 template <class F>
 void for_each_buf(dc_ctx* c, F&& f) {
   for (DBuf* b : {&c->off[0], &c->off[1], &c->adj[0], &c->adj[1], &c->k0, &c->C, &c->a0,
-                  &c->sz0, &c->in_au, &c->in_av, &c->in_aw, &c->in_du, &c->in_dv, &c->dkeys,
-                  &c->dvals, &c->dk1, &c->dv1, &c->dw_old, &c->akeys, &c->avals, &c->ak1,
+                  &c->sz0, &c->in_au, &c->in_av, &c->in_aw, &c->in_du, &c->in_dv, &c->dw_old, &c->akeys, &c->avals, &c->ak1,
                   &c->av1, &c->aheads, &c->apos, &c->ukeys, &c->uw, &c->rkeys, &c->rvals,
                   &c->rk1, &c->rv1, &c->rheads, &c->rpos, &c->ch_key, &c->ch_op, &c->ch_w,
                   &c->ch_dk, &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->cptr,

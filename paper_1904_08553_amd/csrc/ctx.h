@@ -22,7 +22,7 @@ struct dc_ctx {
   DBuf k0, C, a0, sz0;
   // batch
   DBuf in_au, in_av, in_aw, in_du, in_dv;
-  DBuf dkeys, dvals, dk1, dv1, dw_old;
+  DBuf dw_old;
   DBuf akeys, avals, ak1, av1, aheads, apos, ukeys, uw;
   DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
   DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;

@@ -89,12 +89,6 @@ inline int ilog2_ceil(uint64_t x) {
   return b;
 }
 
-inline uint32_t pow2_ceil32(uint32_t x) {
-  uint32_t p = 1;
-  while (p < x) p <<= 1;
-  return p;
-}
-
 // ---------------------------------------------------------------------------
 // device helpers
 

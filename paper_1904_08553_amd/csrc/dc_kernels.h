@@ -68,10 +68,6 @@ void make_directed(const int32_t* u, const int32_t* v, const int32_t* w,
                    int64_t m, int32_t n, uint64_t* keys, uint32_t* vals,
                    hipStream_t st);
 
-// Canonical keys min*n+max with the input index as value.
-void make_canonical(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
-                    uint64_t* keys, uint32_t* vals, hipStream_t st);
-
 // flag[i] = 1 if keys[i] starts a run of equal keys.
 void run_heads(const uint64_t* keys, int64_t m, int32_t* flag, hipStream_t st);
 

@@ -52,17 +52,6 @@ __global__ void k_make_directed(const int32_t* __restrict__ u,
   }
 }
 
-__global__ void k_make_canonical(const int32_t* __restrict__ u,
-                                 const int32_t* __restrict__ v, int64_t m,
-                                 int32_t n, uint64_t* keys, uint32_t* vals) {
-  GRID_STRIDE(e, m) {
-    uint32_t a = uint32_t(u[e]), b = uint32_t(v[e]);
-    uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
-    keys[e] = lo * uint64_t(n) + hi;
-    vals[e] = uint32_t(e);
-  }
-}
-
 __global__ void k_run_heads(const uint64_t* __restrict__ keys, int64_t m,
                             int32_t* flag) {
   GRID_STRIDE(i, m) { flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0; }
@@ -684,13 +673,6 @@ void make_directed(const int32_t* u, const int32_t* v, const int32_t* w,
                    hipStream_t st) {
   if (m <= 0) return;
   k_make_directed<<<grid_for(m), TPB, 0, st>>>(u, v, w, m, n, keys, vals);
-  DC_LAUNCH_CHECK();
-}
-
-void make_canonical(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
-                    uint64_t* keys, uint32_t* vals, hipStream_t st) {
-  if (m <= 0) return;
-  k_make_canonical<<<grid_for(m), TPB, 0, st>>>(u, v, m, n, keys, vals);
   DC_LAUNCH_CHECK();
 }
 
