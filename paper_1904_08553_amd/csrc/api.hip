@@ -422,7 +422,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   const int64_t nr = 2 * (nd + na);
   for (DBuf* b : {&c->rkeys, &c->rk1, &c->ch_key, &c->ukeys}) b->ensure(size_t(nr + 1) * 8);
   for (DBuf* b : {&c->rvals, &c->rv1, &c->rheads, &c->rpos, &c->ch_op, &c->ch_w, &c->ch_dk,
-                  &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->ins_flag, &c->ins_pos,
+                  &c->dnet, &c->cnet, &c->ins_flag, &c->ins_pos,
                   &c->src_flag, &c->src_pos, &c->src_list, &c->uw, &c->dw_old})
     b->ensure(size_t(nr + 1) * 4);
   c->ins_keys.ensure(size_t(nr + 1) * 8);
@@ -441,7 +441,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   int32_t* ch_dk = c->ch_dk.as<int32_t>();
   resolve_changes(rkeys, rvals, rpos, nr, nruns, aw, n, off_old, adj_old,
                   c->ukeys.as<uint64_t>(), c->uw.as<int32_t>(), c->dw_old.as<int32_t>(), ch_key,
-                  ch_op, ch_w, ch_dk, c->is_del.as<int32_t>(), c->is_new.as<int32_t>(), flags,
+                  ch_op, ch_w, ch_dk, c->dnet.as<int32_t>(), flags,
                   stat + ST_WSUM_DEL, st);
   read_stat(c);
   // checks in the documented order; nothing has been changed yet
@@ -452,10 +452,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   // ---- from here on the state changes ----
   const int64_t nch = nr > 0 ? int32_t(hs[ST_N1]) : 0;
   c->nch_last = nch;
-  int32_t* cum_del = c->cum_del.as<int32_t>();
-  int32_t* cum_new = c->cum_new.as<int32_t>();
-  scan_excl_i32(c->is_del.as<int32_t>(), cum_del, nch, cum_del + nch, st);
-  scan_excl_i32(c->is_new.as<int32_t>(), cum_new, nch, cum_new + nch, st);
+  int32_t* cnet = c->cnet.as<int32_t>();
+  scan_excl_i32(c->dnet.as<int32_t>(), cnet, nch, cnet + nch, st);
   c->cptr.ensure(size_t(n + 1) * 4);
   c->new_deg.ensure(size_t(n + 1) * 4);
   int32_t* cptr = c->cptr.as<int32_t>();
@@ -468,8 +466,9 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     ensure_sample_state(c);
     DC_HIP(hipMemcpyAsync(c->kprev.p, c->k0.p, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
   }
+  c->tile_row.ensure(size_t(ceil_div(c->nnz, MERGE_TILE) + 1) * 4);
   row_changes(cptr, ch_op, ch_dk, off_old, n, c->new_deg.as<int32_t>(), c->k0.as<int32_t>(),
-              c->C.as<int32_t>(), c->a0.as<int32_t>(), st);
+              c->C.as<int32_t>(), c->a0.as<int32_t>(), c->tile_row.as<int32_t>(), st);
   const int nxt = c->cur ^ 1;
   c->off[nxt].ensure(size_t(n + 1) * 4);
   int32_t* off_new = c->off[nxt].as<int32_t>();
@@ -483,18 +482,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   const int64_t nnz_new = *static_cast<int32_t*>(c->hbuf);
   const int64_t n_ins = nch > 0 ? int32_t(hs[ST_N2]) : 0;
   c->adj[nxt].ensure(size_t(nnz_new + 1) * 8);
-  // rows with changes: the distinct sources of the change list
-  int32_t* crow_flag = c->rheads.as<int32_t>();
-  int32_t* crow_pos = c->rpos.as<int32_t>();
-  c->chsrc.ensure(size_t(nr + 1) * 4);
-  int32_t* crows = c->chsrc.as<int32_t>();
-  source_heads(ch_key, nch, n, crow_flag, st);
-  scan_excl_i32(crow_flag, crow_pos, nch, crow_pos + nch, st);
-  gather_sources(ch_key, crow_flag, crow_pos, nch, n, crows, st);
-  c->bigrows.ensure(size_t(nch + 2) * 4);
-  merge_rows(off_old, adj_old, c->nnz, off_new, c->adj[nxt].as<int2>(), n, cptr, crows,
-             crow_pos + nch, nch, ch_key, ch_op, ch_w, cum_del, cum_new,
-             c->bigrows.as<int32_t>(), st);
+  merge_rows(off_old, adj_old, c->nnz, off_new, c->adj[nxt].as<int2>(), n, cptr,
+             c->tile_row.as<int32_t>(), ch_key, ch_op, ch_w, cnet, nch, st);
   c->cur = nxt;
   c->nnz = nnz_new;
   c->two_m = two_m_new;
@@ -505,7 +494,15 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   LevelView g0{n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
                c->k0.as<int32_t>()};
   if (samples) {
-    // endpoints of the changed pairs and their neighbours in G_t
+    // endpoints of the changed pairs (the distinct sources of the change
+    // list) and their neighbours in G_t
+    int32_t* crow_flag = c->rheads.as<int32_t>();
+    int32_t* crow_pos = c->rpos.as<int32_t>();
+    c->chsrc.ensure(size_t(nr + 1) * 4);
+    int32_t* crows = c->chsrc.as<int32_t>();
+    source_heads(ch_key, nch, n, crow_flag, st);
+    scan_excl_i32(crow_flag, crow_pos, nch, crow_pos + nch, st);
+    gather_sources(ch_key, crow_flag, crow_pos, nch, n, crows, st);
     fill_u8(c->tmark.as<uint8_t>(), 0, n, st);
     mark_touched(crows, crow_pos + nch, nch, g0.off, g0.adj, c->tmark.as<uint8_t>(), st);
   }
@@ -723,12 +720,11 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->sz0, &c->in_au, &c->in_av, &c->in_aw, &c->in_du, &c->in_dv, &c->dw_old, &c->akeys, &c->avals, &c->ak1,
                   &c->av1, &c->aheads, &c->apos, &c->ukeys, &c->uw, &c->rkeys, &c->rvals,
                   &c->rk1, &c->rv1, &c->rheads, &c->rpos, &c->ch_key, &c->ch_op, &c->ch_w,
-                  &c->ch_dk, &c->is_del, &c->is_new, &c->cum_del, &c->cum_new, &c->cptr,
-                  &c->new_deg, &c->ins_flag, &c->ins_pos, &c->ins_keys, &c->src_flag,
+                  &c->ch_dk, &c->dnet, &c->cnet, &c->cptr, &c->new_deg, &c->tile_row, &c->ins_flag, &c->ins_pos, &c->ins_keys, &c->src_flag,
                   &c->src_pos, &c->src_list, &c->dflag, &c->dpos, &c->dlist, &c->R, &c->cflag,
                   &c->rflag, &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end, &c->chsrc,
                   &c->accflag, &c->cascand, &c->clist, &c->uflag, &c->ulist,
-                  &c->bigrows, &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
+                  &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
                   &c->f_g1, &c->f_g2, &c->X, &c->y, &c->logits, &c->Cl, &c->Cn, &c->al,
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],
                   &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,

@@ -25,9 +25,9 @@ struct dc_ctx {
   DBuf dw_old;
   DBuf akeys, avals, ak1, av1, aheads, apos, ukeys, uw;
   DBuf rkeys, rvals, rk1, rv1, rheads, rpos;
-  DBuf ch_key, ch_op, ch_w, ch_dk, is_del, is_new, cum_del, cum_new, cptr, new_deg;
+  DBuf ch_key, ch_op, ch_w, ch_dk, dnet, cnet, cptr, new_deg, tile_row;
   DBuf ins_flag, ins_pos, ins_keys, src_flag, src_pos, src_list, dflag, dpos, dlist;
-  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc, bigrows;
+  DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc;
   DBuf accflag, cascand, clist;  // cascade-aware screening
   DBuf uflag, ulist;             // union of insertion sources and deletion endpoints
   // learned screener: touched set, features, labels, scores

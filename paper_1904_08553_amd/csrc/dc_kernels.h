@@ -102,32 +102,35 @@ void batch_records(const int32_t* du, const int32_t* dv, int64_t nd, const int32
 // One change per run of equal sorted record keys (pos: exclusive scan of the
 // run heads, *nruns on the device): ch_key, ch_op, ch_w (new weight for NEW
 // and REPLACE, added weight for ADD), ch_dk (change of the row's weighted
-// degree), is_del, is_new; flags |= F_DUP (a pair deleted twice) and
+// degree), dnet (+1 for NEW, -1 for DELETE, else 0); flags |= F_DUP (a pair
+// deleted twice) and
 // F_NO_EDGE (a deletion of a pair absent from off/adj); *wsum += the old
 // weights of the deleted edges.  run_key/run_w/run_ndel: scratch of m.
 void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* pos, int64_t m,
                      const int32_t* nruns, const int32_t* ins_w, int32_t n, const int32_t* off,
                      const int2* adj, uint64_t* run_key, int32_t* run_w, int32_t* run_ndel,
                      uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
-                     int32_t* is_del, int32_t* is_new, int32_t* flags, long long* wsum,
-                     hipStream_t st);
+                     int32_t* dnet, int32_t* flags, long long* wsum, hipStream_t st);
+
+// Old CSR entries per block of the merge.
+constexpr int MERGE_TILE = 1024;
 
 // Per row: new degree and degree-weight change; k += dk; a[C[u]] += dk.
+// tile_row (ceil(off[n] / MERGE_TILE) + 1 ints): the row holding entry
+// t * MERGE_TILE for each tile t, then the row holding the last entry.
 void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk,
                  const int32_t* off, int32_t n, int32_t* new_deg, int32_t* k,
-                 const int32_t* C, int32_t* a, hipStream_t st);
+                 const int32_t* C, int32_t* a, int32_t* tile_row, hipStream_t st);
 
-// Merge G_{t-1} with the sorted change list into G_t: rows without changes
-// are copied entry-parallel with their offset shift; the rows listed in
-// `rows` (device count nrows_dev, at most nrows_max) are merged one wave
-// per row, rows longer than 1024 entries one block per row.  big: scratch
-// of nrows_max + 1 ints (the long rows' list and its count).
+// Merge G_{t-1} with the sorted change list (ch_*, nch entries, row bounds
+// cptr) into G_t: one launch, tiles of MERGE_TILE old entries (tile_row from
+// row_changes) plus blocks that place the NEW pairs.  cnet: exclusive prefix
+// sum of dnet over the change list (nch + 1 ints).  off_new must already
+// hold G_t's offsets.
 void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
                 const int32_t* off_new, int2* adj_new, int32_t n, const int32_t* cptr,
-                const int32_t* rows, const int32_t* nrows_dev, int64_t nrows_max,
-                const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ch_w,
-                const int32_t* cum_del, const int32_t* cum_new, int32_t* big,
-                hipStream_t st);
+                const int32_t* tile_row, const uint64_t* ch_key, const int32_t* ch_op,
+                const int32_t* ch_w, const int32_t* cnet, int64_t nch, hipStream_t st);
 
 // Exact numerator pieces of Eq. (1) over a CSR with labels C:
 // *I += sum of intra-community entry weights; a_tmp (zeroed, n) receives

@@ -1,6 +1,6 @@
 // graph.hip -- the dynamic graph G_t (Sec. 3.1): CSR construction, batch
 // validation, and the sorted merge of a batch of additions and deletions into
-// the next CSR (a streaming pass, one wave per row).
+// the next CSR (a streaming pass over tiles of old entries).
 #include "dc_kernels.h"
 
 namespace dc {
@@ -172,8 +172,7 @@ __global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
                                const int32_t* __restrict__ nruns, int32_t n,
                                const int32_t* __restrict__ off, const int2* __restrict__ adj,
                                uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
-                               int32_t* is_del, int32_t* is_new, int32_t* flags,
-                               long long* wsum) {
+                               int32_t* dnet, int32_t* flags, long long* wsum) {
   const int64_t cnt = *nruns;
   int32_t f = 0;
   long long s = 0;
@@ -215,16 +214,16 @@ __global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
     ch_op[r] = op;
     ch_w[r] = w;
     ch_dk[r] = dk;
-    is_del[r] = op == OP_DELETE ? 1 : 0;
-    is_new[r] = op == OP_NEW ? 1 : 0;
+    dnet[r] = op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
   }
   block_or(f, flags);
   block_add(s, wsum);
 }
 
 
-// Thread per row: new degree, k += the row's weight change, and the label
-// totals a[C(u)] += the same change.  A block walks many rows and sums the
+// Thread per row: new degree, k += the row's weight change, the label
+// totals a[C(u)] += the same change, and the rows that begin the merge's
+// tiles.  A block walks many rows and sums the
 // label changes in its LDS table first, so a large community receives one
 // update per block instead of one per row (same-address atomics serialise).
 __global__ void __launch_bounds__(TPB)
@@ -232,20 +231,29 @@ __global__ void __launch_bounds__(TPB)
                   const int32_t* __restrict__ ch_op,
                   const int32_t* __restrict__ ch_dk,
                   const int32_t* __restrict__ off, int32_t n, int32_t* new_deg,
-                  int32_t* k, const int32_t* __restrict__ C, int32_t* a) {
+                  int32_t* k, const int32_t* __restrict__ C, int32_t* a,
+                  int32_t* tile_row) {
   __shared__ AggLds agg;
   agg_init(agg);
   __syncthreads();
+  const int32_t nnz = off[n];
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n; u += stride) {
     const int32_t b = cptr[u], e = cptr[u + 1];
+    const int32_t ob = off[u], oe = off[u + 1];
     int32_t dd = 0, dk = 0;
     for (int32_t q = b; q < e; ++q) {
       const int32_t op = ch_op[q];
       dd += op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
       dk += ch_dk[q];
     }
-    new_deg[u] = off[u + 1] - off[u] + dd;
+    new_deg[u] = oe - ob + dd;
+    // merge tiles: the row holding each tile's first entry, and after the
+    // last tile the row holding the last entry
+    if (oe > ob) {
+      for (int64_t t = ceil_div(ob, MERGE_TILE); t * MERGE_TILE < oe; ++t) tile_row[t] = int32_t(u);
+      if (oe == nnz) tile_row[ceil_div(nnz, MERGE_TILE)] = int32_t(u);
+    }
     if (dk != 0) {
       k[u] += dk;
       const int c = C[u];
@@ -259,354 +267,141 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
-constexpr int MC_ROWS = 4;  // unchanged rows a wave copies per round
+constexpr int MT_PER = MERGE_TILE / TPB;    // old entries per thread
+constexpr int MT_SEGS = MERGE_TILE / WAVE;  // wave-wide segments of a tile
+constexpr int MT_CH = 512;                  // changes of a tile staged in LDS
 
-// Untouched rows move as a block: entry e of row r goes to
-// e + off_new[r] - off_old[r].  A wave takes 64 consecutive rows: one
-// coalesced load brings each row's bounds, shift and changed-flag into a
-// lane, then the wave copies the unchanged rows MC_ROWS at a time with
-// contiguous reads and writes.
+// first k in [a, b) with keys[k] >= key
+__device__ __forceinline__ int change_rank(const uint64_t* keys, int a, int b, uint64_t key) {
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (keys[mid] < key)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  return a;
+}
+
+// G_{t-1} -> G_t in one launch over the old entries, cut into tiles of
+// MERGE_TILE consecutive entries regardless of where rows begin, so every
+// block streams the same amount of contiguous memory.
+//
+// Old entry j of row r lands at off_new[r] + (j - off_old[r]) + the
+// insertions minus the deletions among r's changes with a smaller neighbour
+// id: cnet (the exclusive prefix sum of +1 per NEW, -1 per DELETE over the
+// change list, which is sorted by (row, neighbour)) at the entry's rank
+// among the row's changes, minus cnet at the row's first change.  A DELETE
+// of the entry drops it, ADD / REPLACE change its weight.
+//
+// A tile block first puts, at each row's first entry inside the tile, that
+// row's id, offset shift and change range into LDS, together with the
+// tile's slice of the change list (the rows of a tile own one contiguous
+// slice).  An entry finds its row's slot by a ballot over the row-start
+// marks of its 64-entry segment (the nearest mark at or before the lane),
+// or from the slot recorded for the segment's first entry.
+//
+// The first `nib` blocks instead place the insertions: NEW change q of row
+// r goes after the old entries of r with a smaller neighbour (binary search
+// in the old row), shifted by cnet[q] - cnet[cptr[r]].  The two kinds of
+// block write disjoint slots.
 __global__ void __launch_bounds__(TPB)
-    k_merge_copy(const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
-                 const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
-                 const int32_t* __restrict__ cptr) {
-  const int64_t nbatch = ceil_div(n, WAVE);
-  const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
+    k_merge_tiles(const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
+                  int64_t nnz_old, const int32_t* __restrict__ off_new, int2* adj_new,
+                  int32_t n, const int32_t* __restrict__ cptr,
+                  const int32_t* __restrict__ tile_row, const uint64_t* __restrict__ ch_key,
+                  const int32_t* __restrict__ ch_op, const int32_t* __restrict__ ch_w,
+                  const int32_t* __restrict__ cnet, int64_t nch, int nib) {
+  __shared__ int32_t s_row[MERGE_TILE];  // at a row's first entry in the tile: the row
+  __shared__ int32_t s_sh[MERGE_TILE];   // ... off_new[r] - off_old[r]
+  __shared__ int32_t s_cb[MERGE_TILE];   // ... cptr[r]
+  __shared__ int32_t s_ce[MERGE_TILE];   // ... cptr[r + 1]
+  __shared__ int32_t s_seg[MT_SEGS];     // slot of the row holding entry q * WAVE
+  __shared__ uint64_t s_key[MT_CH];
+  __shared__ int32_t s_net[MT_CH + 1];
+
+  if (int(blockIdx.x) < nib) {
+    for (int64_t q = int64_t(blockIdx.x) * TPB + threadIdx.x; q < nch; q += int64_t(nib) * TPB) {
+      if (ch_op[q] != OP_NEW) continue;
+      const uint64_t key = ch_key[q];
+      const int32_t src = int32_t(key / uint64_t(n));
+      const int32_t dst = int32_t(key - uint64_t(src) * uint64_t(n));
+      const int32_t ob = off_old[src], oe = off_old[src + 1];
+      const int32_t less = find_in_row(adj_old, ob, oe, dst) - ob;
+      adj_new[off_new[src] + less + cnet[q] - cnet[cptr[src]]] = make_int2(dst, ch_w[q]);
+    }
+    return;  // block-uniform
+  }
+
+  const int64_t tile = int64_t(blockIdx.x) - nib;
+  const int64_t t0 = tile * MERGE_TILE;
+  const int64_t t1 = t0 + MERGE_TILE < nnz_old ? t0 + MERGE_TILE : nnz_old;
+  const int len = int(t1 - t0);
   const int lane = lane_id();
-  for (int64_t bt = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; bt < nbatch;
-       bt += nwaves) {
-    const int64_t r = bt * WAVE + lane;
-    int beg = 0, end = 0, shift = 0, skip = 1;
-    if (r < n) {
-      beg = off_old[r];
-      end = off_old[r + 1];
-      shift = off_new[r] - beg;
-      skip = cptr[r] != cptr[r + 1];
-    }
-    // rows to copy, in lane order, MC_ROWS per round: the rounds' loads are
-    // issued before their stores
-    uint64_t todo = __ballot(!skip && end > beg);
-    while (todo) {
-      int b[MC_ROWS], e[MC_ROWS], sh[MC_ROWS];
-      int longest = 0;
+  const int wbase = int(threadIdx.x / WAVE) * (WAVE * MT_PER);
+  int2 e[MT_PER];
 #pragma unroll
-      for (int k = 0; k < MC_ROWS; ++k) {
-        b[k] = e[k] = sh[k] = 0;
-        if (todo) {
-          const int l = __ffsll((unsigned long long)todo) - 1;
-          todo &= todo - 1;
-          b[k] = __builtin_amdgcn_readlane(beg, l);
-          e[k] = __builtin_amdgcn_readlane(end, l);
-          sh[k] = __builtin_amdgcn_readlane(shift, l);
-          longest = e[k] - b[k] > longest ? e[k] - b[k] : longest;
-        }
-      }
-      for (int o = 0; o < longest; o += WAVE) {
-        int2 v[MC_ROWS];
-#pragma unroll
-        for (int k = 0; k < MC_ROWS; ++k) {
-          const int q = b[k] + o + lane;
-          v[k] = q < e[k] ? adj_old[q] : make_int2(0, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < MC_ROWS; ++k) {
-          const int q = b[k] + o + lane;
-          if (q < e[k]) adj_new[q + sh[k]] = v[k];
-        }
-      }
+  for (int q = 0; q < MT_PER; ++q) {
+    const int i = wbase + q * WAVE + lane;
+    e[q] = i < len ? adj_old[t0 + i] : make_int2(0, 0);
+  }
+  for (int i = threadIdx.x; i < MERGE_TILE; i += TPB) s_row[i] = -1;
+  const int32_t r0 = tile_row[tile], r1 = tile_row[tile + 1];
+  const int32_t c0 = cptr[r0], nloc = cptr[r1 + 1] - c0;
+  const bool staged = nloc <= MT_CH;  // block-uniform
+  if (staged) {
+    for (int k = threadIdx.x; k <= nloc; k += TPB) {
+      if (k < nloc) s_key[k] = ch_key[c0 + k];
+      s_net[k] = cnet[c0 + k];
     }
   }
-}
-
-// Rows with changes: one wave per row.  For a row with few changes relative
-// to its length the changes (sorted by neighbour) sit one per lane, and the
-// number of deletions and insertions before a neighbour id comes from a
-// register loop instead of searches in memory; other rows use searches.
-// Long rows with many changes: every old entry and every insertion finds
-// its place by binary search (changes with a smaller neighbour id, counted
-// through the prefix sums of the DELETE / NEW flags).
-__device__ void merge_row_search(int32_t row, int32_t n, const int2* __restrict__ adj_old,
-                                 int32_t ob, int32_t oe, int32_t nb, int32_t cb, int32_t ce,
-                                 int2* adj_new, const uint64_t* __restrict__ ch_key,
-                                 const int32_t* __restrict__ ch_op,
-                                 const int32_t* __restrict__ ch_w,
-                                 const int32_t* __restrict__ cum_del,
-                                 const int32_t* __restrict__ cum_new) {
-  const int lane = lane_id();
-  const uint64_t base = uint64_t(row) * uint64_t(n);
-  const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
-  for (int32_t j = lane; j < oe - ob; j += WAVE) {
-    int2 e = adj_old[ob + j];
-    int32_t lo = cb, hi = ce;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (int32_t(ch_key[mid] - base) < e.x)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    const int32_t shift = (cum_new[lo] - new0) - (cum_del[lo] - del0);
-    if (lo < ce && int32_t(ch_key[lo] - base) == e.x) {
-      const int32_t op = ch_op[lo];
-      if (op == OP_DELETE) continue;
-      if (op == OP_ADD) e.y += ch_w[lo];
-      if (op == OP_REPLACE) e.y = ch_w[lo];
-    }
-    adj_new[nb + j + shift] = e;
-  }
-  for (int32_t q = cb + lane; q < ce; q += WAVE) {
-    if (ch_op[q] != OP_NEW) continue;
-    const int32_t c = int32_t(ch_key[q] - base);
-    const int32_t pos = find_in_row(adj_old, ob, oe, c) - ob;
-    const int32_t shift = (cum_new[q] - new0) - (cum_del[q] - del0);
-    adj_new[nb + pos + shift] = make_int2(c, ch_w[q]);
-  }
-}
-
-constexpr int WROW_CH = 4;                 // row chunks a wave holds in registers
-constexpr int BIG_ROW = 1024;              // longer rows are merged by a block
-constexpr int MERGE_ROWS = 2;              // rows a wave merges per iteration
-constexpr int BIG_CHANGES = 4096;          // changes staged in LDS per big row
-constexpr int BIG_SEG = BIG_CHANGES / TPB; // histogram bins per thread in the scan
-constexpr int BIG_U = 4;                   // row chunks per load round of a block
-
-// Long changed rows (more than BIG_ROW entries or more than WAVE changes):
-// one block per row.  The row's change neighbours and the shift before each
-// change (insertions minus deletions before it) are staged in LDS; each old
-// entry finds its rank lo among the changes by a binary search on chip and
-// counts itself in bin lo of an LDS histogram.  An insertion at change k
-// lands after the old entries with a smaller neighbour, which are exactly
-// those of rank <= k: the histogram's prefix sum at k.
-__global__ void __launch_bounds__(TPB)
-    k_merge_big(const int32_t* __restrict__ big,
-                const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
-                const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
-                const int32_t* __restrict__ cptr, const uint64_t* __restrict__ ch_key,
-                const int32_t* __restrict__ ch_op, const int32_t* __restrict__ ch_w,
-                const int32_t* __restrict__ cum_del, const int32_t* __restrict__ cum_new) {
-  __shared__ int ldst[BIG_CHANGES];
-  __shared__ int lsh[BIG_CHANGES + 1];
-  __shared__ int hcnt[BIG_CHANGES + 1];
-  __shared__ int part[TPB];
-  const int64_t nrows = big[0];  // rows listed from big[1]
-  for (int64_t p = blockIdx.x; p < nrows; p += gridDim.x) {
-    const int32_t row = big[1 + p];
-    const int32_t ob = off_old[row], oe = off_old[row + 1];
-    const int32_t nb = off_new[row], cb = cptr[row], ce = cptr[row + 1];
-    const int32_t nchg = ce - cb;
-    if (nchg > BIG_CHANGES) {
-      if (threadIdx.x < WAVE)
-        merge_row_search(row, n, adj_old, ob, oe, nb, cb, ce, adj_new, ch_key, ch_op, ch_w,
-                         cum_del, cum_new);
-      __syncthreads();
-      continue;
-    }
-    const uint64_t base = uint64_t(row) * uint64_t(n);
-    const int32_t del0 = cum_del[cb], new0 = cum_new[cb];
-    for (int k = threadIdx.x; k <= nchg; k += TPB) {
-      if (k < nchg) ldst[k] = int32_t(ch_key[cb + k] - base);
-      lsh[k] = (cum_new[cb + k] - new0) - (cum_del[cb + k] - del0);
-      hcnt[k] = 0;
-    }
-    __syncthreads();
-    const int32_t deg = oe - ob;
-    for (int32_t j0 = threadIdx.x; j0 < deg; j0 += BIG_U * TPB) {
-      int2 e[BIG_U];
-#pragma unroll
-      for (int u = 0; u < BIG_U; ++u) {
-        const int32_t j = j0 + u * TPB;
-        e[u] = j < deg ? adj_old[ob + j] : make_int2(0, 0);
-      }
-#pragma unroll
-      for (int u = 0; u < BIG_U; ++u) {
-        const int32_t j = j0 + u * TPB;
-        if (j >= deg) continue;
-        int lo = 0, hi = nchg;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (ldst[mid] < e[u].x)
-            lo = mid + 1;
-          else
-            hi = mid;
-        }
-        atomicAdd(&hcnt[lo], 1);
-        if (lo < nchg && ldst[lo] == e[u].x) {
-          const int32_t op = ch_op[cb + lo];
-          if (op == OP_DELETE) continue;
-          if (op == OP_ADD) e[u].y += ch_w[cb + lo];
-          if (op == OP_REPLACE) e[u].y = ch_w[cb + lo];
-        }
-        adj_new[nb + j + lsh[lo]] = e[u];
-      }
-    }
-    __syncthreads();
-    // inclusive prefix sums of hcnt: per-thread segments of BIG_SEG bins,
-    // then a scan of the TPB segment totals
-    const int sb = int(threadIdx.x) * BIG_SEG;
-    int tot = 0;
-    for (int q = 0; q < BIG_SEG; ++q)
-      if (sb + q <= nchg) tot += hcnt[sb + q];
-    part[threadIdx.x] = tot;
-    __syncthreads();
-    for (int o = 1; o < TPB; o <<= 1) {
-      const int add = int(threadIdx.x) >= o ? part[threadIdx.x - o] : 0;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
-    }
-    for (int k = threadIdx.x; k < nchg; k += TPB) {
-      if (ch_op[cb + k] != OP_NEW) continue;
-      const int seg = k / BIG_SEG;
-      int less = seg > 0 ? part[seg - 1] : 0;
-      for (int q = seg * BIG_SEG; q <= k; ++q) less += hcnt[q];
-      adj_new[nb + less + lsh[k]] = make_int2(ldst[k], ch_w[cb + k]);
-    }
-    __syncthreads();
-  }
-}
-
-// Changed rows of at most BIG_ROW entries and at most WAVE changes: one
-// wave per row, everything in registers.  The row's entries sit in windows
-// of WROW_CH chunks of one per lane and its changes (sorted by neighbour) one
-// per lane; a loop over the changes, each broadcast by readlane, gives every
-// old entry its shift (insertions minus deletions before it) and its fate,
-// and every change the number of old entries with a smaller neighbour (one
-// ballot per chunk), which places the insertions.  A wave takes
-// MERGE_ROWS rows per iteration and issues all their loads before it waits
-// on any.
-// Other rows are listed for k_merge_big.
-struct MergeRow {
-  int32_t ob, deg, nb, nchg;
-  bool live;
-  int dst, op, cw;
-  int2 e[WROW_CH];
-};
-
-__device__ __forceinline__ void merge_head(MergeRow& r, int32_t row, bool have,
-                                           const int32_t* __restrict__ off_old,
-                                           const int32_t* __restrict__ off_new,
-                                           const int32_t* __restrict__ cptr, int32_t* cb_out) {
-  r.live = false;
-  r.ob = r.deg = r.nb = r.nchg = 0;
-  *cb_out = 0;
-  if (!have) return;
-  const int32_t ob = off_old[row], oe = off_old[row + 1], nb = off_new[row];
-  const int32_t cb = cptr[row], ce = cptr[row + 1];
-  r.ob = ob;
-  r.deg = oe - ob;
-  r.nb = nb;
-  r.nchg = ce - cb;
-  r.live = true;
-  *cb_out = cb;
-}
-
-__device__ __forceinline__ void merge_load(MergeRow& r, int32_t row, int32_t cb, int32_t n,
-                                           const int2* __restrict__ adj_old,
-                                           const uint64_t* __restrict__ ch_key,
-                                           const int32_t* __restrict__ ch_op,
-                                           const int32_t* __restrict__ ch_w, int lane) {
-  const bool hq = r.live && lane < r.nchg;
-  const uint64_t base = uint64_t(row) * uint64_t(n);
-  r.dst = hq ? int32_t(ch_key[cb + lane] - base) : 0x7fffffff;
-  r.op = hq ? ch_op[cb + lane] : 0;
-  r.cw = hq ? ch_w[cb + lane] : 0;
-#pragma unroll
-  for (int u = 0; u < WROW_CH; ++u) {
-    const int32_t j = u * WAVE + lane;
-    r.e[u] = r.live && j < r.deg ? adj_old[r.ob + j] : make_int2(0x7fffffff, 0);
-  }
-}
-
-// The row is walked in windows of WROW_CH chunks: window 0 was loaded by
-// merge_load, later windows are loaded here.
-__device__ __forceinline__ void merge_finish(MergeRow& r, const int2* __restrict__ adj_old,
-                                             int2* adj_new, int lane, uint64_t lt) {
-  if (!r.live) return;  // uniform
-  const int nck = (r.deg + WAVE - 1) / WAVE;
-  int less = 0;
-  for (int w0 = 0; w0 == 0 || w0 < nck; w0 += WROW_CH) {
-    if (w0 > 0) {
-#pragma unroll
-      for (int u = 0; u < WROW_CH; ++u) {
-        const int32_t j = (w0 + u) * WAVE + lane;
-        r.e[u] = j < r.deg ? adj_old[r.ob + j] : make_int2(0x7fffffff, 0);
-      }
-    }
-    int shift[WROW_CH];
-    bool drop[WROW_CH];
-#pragma unroll
-    for (int u = 0; u < WROW_CH; ++u) {
-      shift[u] = 0;
-      drop[u] = false;
-    }
-    for (int k = 0; k < r.nchg; ++k) {
-      const int dk = __builtin_amdgcn_readlane(r.dst, k);
-      const int ok = __builtin_amdgcn_readlane(r.op, k);
-      const int wk = __builtin_amdgcn_readlane(r.cw, k);
-      const int dsh = ok == OP_NEW ? 1 : (ok == OP_DELETE ? -1 : 0);
-      int cnt = 0;
-#pragma unroll
-      for (int u = 0; u < WROW_CH; ++u) {
-        if (w0 + u >= nck) break;
-        if (dk < r.e[u].x) {
-          shift[u] += dsh;
-        } else if (dk == r.e[u].x) {
-          if (ok == OP_DELETE) drop[u] = true;
-          if (ok == OP_ADD) r.e[u].y += wk;
-          if (ok == OP_REPLACE) r.e[u].y = wk;
-        }
-        cnt += __popcll(__ballot(r.e[u].x < dk));
-      }
-      if (lane == k) less += cnt;
-    }
-#pragma unroll
-    for (int u = 0; u < WROW_CH; ++u) {
-      const int32_t j = (w0 + u) * WAVE + lane;
-      if (w0 + u < nck && j < r.deg && !drop[u]) adj_new[r.nb + j + shift[u]] = r.e[u];
+  __syncthreads();
+  for (int32_t r = r0 + int32_t(threadIdx.x); r <= r1; r += TPB) {
+    const int32_t b = off_old[r], en = off_old[r + 1];
+    const int32_t sh = off_new[r] - b, cb = cptr[r], ce = cptr[r + 1];
+    const int64_t lo = b > t0 ? int64_t(b) : t0, hi = en < t1 ? int64_t(en) : t1;
+    if (lo < hi) {
+      const int p = int(lo - t0);
+      s_row[p] = r;
+      s_sh[p] = sh;
+      s_cb[p] = cb;
+      s_ce[p] = ce;
+      for (int s = int(ceil_div(p, WAVE)) * WAVE; s < int(hi - t0); s += WAVE) s_seg[s / WAVE] = p;
     }
   }
-  // insertion k: after `less` old entries, minus the deletions and plus
-  // the insertions among the changes before it
-  const bool hq = lane < r.nchg;
-  const bool isnew = hq && r.op == OP_NEW;
-  const uint64_t mnew = __ballot(isnew), mdel = __ballot(hq && r.op == OP_DELETE);
-  if (isnew)
-    adj_new[r.nb + less + __popcll(mnew & lt) - __popcll(mdel & lt)] = make_int2(r.dst, r.cw);
-}
-
-__global__ void __launch_bounds__(TPB)
-    k_merge_changed(const int32_t* __restrict__ rows, const int32_t* nrows_dev,
-                    const int32_t* __restrict__ off_old, const int2* __restrict__ adj_old,
-                    const int32_t* __restrict__ off_new, int2* adj_new, int32_t n,
-                    const int32_t* __restrict__ cptr, const uint64_t* __restrict__ ch_key,
-                    const int32_t* __restrict__ ch_op, const int32_t* __restrict__ ch_w,
-                    int32_t* big) {
-  const int64_t nrows = *nrows_dev;
-  const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / WAVE);
-  const int lane = lane_id();
-  const uint64_t lt = (uint64_t(1) << lane) - 1;
-  for (int64_t p = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE; p < nrows;
-       p += MERGE_ROWS * nwaves) {
-    MergeRow M[MERGE_ROWS];
-    int32_t row[MERGE_ROWS], cb[MERGE_ROWS];
+  __syncthreads();
+  const uint64_t upto = (uint64_t(2) << lane) - 1;  // lanes <= this one
 #pragma unroll
-    for (int r = 0; r < MERGE_ROWS; ++r) {
-      const bool h = p + r * nwaves < nrows;
-      row[r] = h ? rows[p + r * nwaves] : 0;
-      merge_head(M[r], row[r], h, off_old, off_new, cptr, &cb[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < MERGE_ROWS; ++r) {
-      if (M[r].live && (M[r].deg > BIG_ROW || M[r].nchg > WAVE)) {
-        if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = row[r];
-        M[r].live = false;
+  for (int q = 0; q < MT_PER; ++q) {
+    const int i = wbase + q * WAVE + lane;
+    const uint64_t marks = __ballot(s_row[i] >= 0) & upto;
+    if (i >= len) continue;
+    const int p = marks ? i - lane + 63 - __clzll((long long)marks) : s_seg[i / WAVE];
+    const int32_t r = s_row[p], cb = s_cb[p], ce = s_ce[p];
+    int32_t shift = s_sh[p];
+    int2 v = e[q];
+    if (cb != ce) {
+      const uint64_t key = uint64_t(r) * uint64_t(n) + uint64_t(uint32_t(v.x));
+      int k;
+      bool eq;
+      if (staged) {
+        k = change_rank(s_key, cb - c0, ce - c0, key);
+        eq = k < ce - c0 && s_key[k] == key;
+        shift += s_net[k] - s_net[cb - c0];
+        k += c0;
+      } else {
+        k = change_rank(ch_key, cb, ce, key);
+        eq = k < ce && ch_key[k] == key;
+        shift += cnet[k] - cnet[cb];
+      }
+      if (eq) {
+        const int32_t op = ch_op[k];
+        if (op == OP_DELETE) continue;
+        if (op == OP_ADD) v.y += ch_w[k];
+        if (op == OP_REPLACE) v.y = ch_w[k];
       }
     }
-#pragma unroll
-    for (int r = 0; r < MERGE_ROWS; ++r)
-      merge_load(M[r], row[r], cb[r], n, adj_old, ch_key, ch_op, ch_w, lane);
-#pragma unroll
-    for (int r = 0; r < MERGE_ROWS; ++r) merge_finish(M[r], adj_old, adj_new, lane, lt);
+    adj_new[t0 + i + shift] = v;
   }
 }
 
@@ -722,8 +517,7 @@ void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* 
                      const int32_t* nruns, const int32_t* ins_w, int32_t n, const int32_t* off,
                      const int2* adj, uint64_t* run_key, int32_t* run_w, int32_t* run_ndel,
                      uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
-                     int32_t* is_del, int32_t* is_new, int32_t* flags, long long* wsum,
-                     hipStream_t st) {
+                     int32_t* dnet, int32_t* flags, long long* wsum, hipStream_t st) {
   if (m <= 0) return;
   fill_i32(run_w, 0, m, st);
   fill_i32(run_ndel, 0, m, st);
@@ -731,42 +525,31 @@ void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* 
                                                 run_ndel);
   DC_LAUNCH_CHECK();
   k_resolve_runs<<<grid_for(m), TPB, 0, st>>>(run_key, run_w, run_ndel, nruns, n, off, adj,
-                                              ch_key, ch_op, ch_w, ch_dk, is_del, is_new, flags,
-                                              wsum);
+                                              ch_key, ch_op, ch_w, ch_dk, dnet, flags, wsum);
   DC_LAUNCH_CHECK();
 }
 
 void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk,
                  const int32_t* off, int32_t n, int32_t* new_deg, int32_t* k,
-                 const int32_t* C, int32_t* a, hipStream_t st) {
+                 const int32_t* C, int32_t* a, int32_t* tile_row, hipStream_t st) {
   if (n <= 0) return;
   k_row_changes<<<grid_for(n, TPB, 512), TPB, 0, st>>>(cptr, ch_op, ch_dk, off, n, new_deg, k,
-                                                       C, a);
+                                                       C, a, tile_row);
   DC_LAUNCH_CHECK();
 }
 
 void merge_rows(const int32_t* off_old, const int2* adj_old, int64_t nnz_old,
                 const int32_t* off_new, int2* adj_new, int32_t n, const int32_t* cptr,
-                const int32_t* rows, const int32_t* nrows_dev, int64_t nrows_max,
-                const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ch_w,
-                const int32_t* cum_del, const int32_t* cum_new, int32_t* big,
-                hipStream_t st) {
+                const int32_t* tile_row, const uint64_t* ch_key, const int32_t* ch_op,
+                const int32_t* ch_w, const int32_t* cnet, int64_t nch, hipStream_t st) {
   if (n <= 0) return;
-  if (nnz_old > 0) {
-    k_merge_copy<<<grid_for(ceil_div(n, WAVE) * WAVE, TPB, 16384), TPB, 0, st>>>(
-        off_old, adj_old, off_new, adj_new, n, cptr);
-    DC_LAUNCH_CHECK();
-  }
-  if (nrows_max > 0) {
-    fill_i32(big, 0, 1, st);
-    k_merge_changed<<<grid_for(nrows_max * WAVE, TPB, 16384), TPB, 0, st>>>(
-        rows, nrows_dev, off_old, adj_old, off_new, adj_new, n, cptr, ch_key, ch_op, ch_w, big);
-    DC_LAUNCH_CHECK();
-    const int nbig = int(nrows_max < 2048 ? nrows_max : 2048);
-    k_merge_big<<<nbig, TPB, 0, st>>>(big, off_old, adj_old, off_new, adj_new, n, cptr, ch_key,
-                                      ch_op, ch_w, cum_del, cum_new);
-    DC_LAUNCH_CHECK();
-  }
+  const int64_t ntiles = ceil_div(nnz_old, MERGE_TILE);
+  const int nib = nch > 0 ? grid_for(nch, TPB, 1024) : 0;
+  if (ntiles + nib == 0) return;
+  k_merge_tiles<<<int(ntiles + nib), TPB, 0, st>>>(off_old, adj_old, nnz_old, off_new, adj_new,
+                                                   n, cptr, tile_row, ch_key, ch_op, ch_w, cnet,
+                                                   nch, nib);
+  DC_LAUNCH_CHECK();
 }
 
 void intra_weight(const int32_t* off, const int2* adj, const int32_t* C,
