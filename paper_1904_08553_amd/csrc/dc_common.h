@@ -258,6 +258,35 @@ __device__ __forceinline__ void table_add(int* keys, int* vals, uint32_t mask,
   }
 }
 
+// table_add for a table that may hold too few slots: a new key first
+// reserves one of `limit` claims (*claimed counts them; a claim whose CAS
+// then loses the slot to another key is simply spent), so at most `limit`
+// slots are ever taken and every probe sequence ends.  Past the limit the
+// key is dropped and *ovf is set: the table is incomplete.
+__device__ __forceinline__ void table_add_bounded(int* keys, int* vals, uint32_t mask, int key,
+                                                  int w, int* claimed, int* ovf, int limit) {
+  uint32_t h = hash_slot(key, mask);
+  while (true) {
+    const int k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == key) {
+      atomicAdd(&vals[h], w);
+      return;
+    }
+    if (k == EMPTY_KEY) {
+      if (atomicAdd(claimed, 1) >= limit) {
+        *ovf = 1;
+        return;
+      }
+      const int prev = atomicCAS(&keys[h], EMPTY_KEY, key);
+      if (prev == EMPTY_KEY || prev == key) {
+        atomicAdd(&vals[h], w);
+        return;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+}
+
 __device__ __forceinline__ int table_get(const int* keys, const int* vals,
                                          uint32_t mask, int key) {
   uint32_t h = hash_slot(key, mask);

@@ -42,7 +42,8 @@ constexpr long long NO_GAIN = (long long)0x8000000000000000ull;
 // 32 and 64 entries (4, 2 and 1 vertices per wave, no table), then
 constexpr int NBINS = 6;
 constexpr int WTAB_MAX = 512;     // one wave, wave-private LDS table
-constexpr int WTAB_SLOTS = 1024;
+constexpr int WTAB_SLOTS = 1024;  // (merged sweeps; single graphs use 512 slots
+                                  // and a full-table retry on overflow)
 constexpr int BTAB_MAX = 4096;    // one block, block LDS table
 constexpr int BTAB_SLOTS = 8192;  // beyond: one block, global table
 constexpr int TIMED_BIN = 1;      // the bin whose launches the timing option brackets
@@ -73,6 +74,8 @@ struct EvalArgs {
   int* gkeys;            // bin G tables
   int* gvals;
   const long long* tab_off;
+  int32_t* ovf_list;     // bins W and B: vertices whose labels overflowed the
+  int32_t* ovf_count;    // small LDS table (device count)
   long long* stat;
   const uint64_t* ins_keys;  // Alg. 2: sorted directed insertions src*n0+dst
   const int32_t* seg_beg;    // per source vertex: its sinks are ins_keys[beg, end)
@@ -97,10 +100,13 @@ struct Bins {
   int* gkeys;
   int* gvals;
   const long long* tab_off;
+  int32_t* ovf_list;   // rows of bins W and B re-evaluated with the full table
+  int32_t* ovf_count;  // their device count (cleared by the re-evaluation)
+  int32_t* ovf_done;   // blocks of the re-evaluation that have finished
 };
 
 struct BinScratch {
-  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals;
+  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf;
   void* host = nullptr;  // pinned, 256 bytes
 };
 

@@ -539,6 +539,7 @@ __device__ __forceinline__ uint32_t table_cap(int deg, uint32_t max_slots) {
 }
 
 constexpr int GTPB = 1024;  // threads of a bin-G block (one hub row per block)
+constexpr int GT_UI = 16;    // bin G: row chunks per load round
 constexpr int WTAB_UI = WTAB_MAX / WAVE;   // bin W: the whole row in one load round
 constexpr int WTAB_US = 8;                 // and its table in rounds of 8 slots
 
@@ -575,10 +576,14 @@ __device__ __forceinline__ Best table_best(const EvalArgs& A, const int* keys, c
 
 // One group (a wave, or the whole block) evaluates vertex i with table
 // (keys, vals, mask).  Returns the number of accepted screening tests (0/1)
-// in thread 0 of the group.
-template <int MODE, int G, int UI, int US>
+// in thread 0 of the group.  BOUNDED: the table may be too small (at most
+// (mask + 1) / 2 distinct labels fit); tstate holds two ints of group
+// scratch, and if the row brings more labels the call returns TABLE_FULL
+// to every thread before it has written anything outside the group.
+constexpr long long TABLE_FULL = -1;
+template <int MODE, int G, int UI, int US, bool BOUNDED = false>
 __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, uint32_t mask,
-                                GroupLds<G>& L, int* own) {
+                                GroupLds<G>& L, int* own, int* tstate = nullptr) {
   const int t = (G == WAVE) ? lane_id() : int(threadIdx.x);
   const int lane = lane_id();
   const int32_t rb = A.off[i], re = A.off[i + 1];
@@ -588,6 +593,7 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
     keys[s] = EMPTY_KEY;
     vals[s] = 0;
   }
+  if (BOUNDED && t == 0) tstate[0] = tstate[1] = 0;
   group_sync<G>();
   // the own community (usually most of the row) is summed in registers;
   // every other entry goes straight into the table, one lane per entry
@@ -614,13 +620,19 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
     for (int u = 0; u < UI; ++u) {
       if (key[u] == c)
         own_part += e[u].y;
-      else if (valid[u])
-        table_add(keys, vals, mask, key[u], e[u].y);
+      else if (valid[u]) {
+        if (BOUNDED)
+          table_add_bounded(keys, vals, mask, key[u], e[u].y, &tstate[0], &tstate[1],
+                            int((mask + 1) / 2));
+        else
+          table_add(keys, vals, mask, key[u], e[u].y);
+      }
     }
   }
   long long e_own = own_part, unused = 0;
   group_sum2<G>(e_own, unused, L);
   group_sync<G>();
+  if (BOUNDED && tstate[1]) return TABLE_FULL;  // group-uniform after the sync
   long long accepted = 0;
   // EV_DSBOTH: Alg. 2 for an insertion source (flag bit 0), then the
   // deletion rule for a deletion endpoint (bit 1), on the same table
@@ -688,22 +700,36 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
   return accepted;
 }
 
+// Bins W and B evaluate with small LDS tables (more blocks fit a CU): a row
+// of at most a quarter as many entries as slots always fits; a longer row
+// whose foreign labels overflow the table is listed for k_eval_ovf, which
+// evaluates it again with the full table.  Overflow is detected before
+// anything outside the group is written.
+constexpr int WT_SLOTS = 512;   // bin W: per-wave table
+constexpr int BT_SLOTS = 2048;  // bin B: per-block table
+
 // bin W: one wave per vertex, wave-private LDS table
 template <int MODE>
 __global__ void __launch_bounds__(TPB) k_eval_wtab(EvalArgs A) {
-  __shared__ int keys[NW][WTAB_SLOTS];
-  __shared__ int vals[NW][WTAB_SLOTS];
+  __shared__ int keys[NW][WT_SLOTS];
+  __shared__ int vals[NW][WT_SLOTS];
   __shared__ GroupLds<WAVE> L[NW];
   __shared__ int own[NW];
+  __shared__ int tst[NW][2];
   const int wid = threadIdx.x / WAVE;
   const int64_t cnt = *A.count;
   const int64_t nwaves = int64_t(gridDim.x) * NW;
   long long accepted = 0;
   for (int64_t idx = int64_t(blockIdx.x) * NW + wid; idx < cnt; idx += nwaves) {
     const int i = uniform(A.list[idx]);
-    const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], WTAB_SLOTS);
-    accepted += eval_table<MODE, WAVE, WTAB_UI, WTAB_US>(A, i, keys[wid], vals[wid], cap - 1,
-                                                         L[wid], &own[wid]);
+    const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], WT_SLOTS);
+    const long long acc = eval_table<MODE, WAVE, WTAB_UI, WTAB_US, true>(
+        A, i, keys[wid], vals[wid], cap - 1, L[wid], &own[wid], tst[wid]);
+    if (acc == TABLE_FULL) {
+      if (lane_id() == 0) A.ovf_list[atomicAdd(A.ovf_count, 1)] = i;
+    } else {
+      accepted += acc;
+    }
   }
   if (MODE != EV_SWEEP && lane_id() == 0 && accepted) add_accepted(A.stat, accepted);
 }
@@ -711,29 +737,71 @@ __global__ void __launch_bounds__(TPB) k_eval_wtab(EvalArgs A) {
 // bin B: one block per vertex, block-shared LDS table
 template <int MODE>
 __global__ void __launch_bounds__(TPB) k_eval_btab(EvalArgs A) {
+  __shared__ int keys[BT_SLOTS];
+  __shared__ int vals[BT_SLOTS];
+  __shared__ GroupLds<TPB> L;
+  __shared__ int own;
+  __shared__ int tst[2];
+  const int64_t idx = blockIdx.x;
+  if (idx >= *A.count) return;  // uniform over the block
+  const int i = A.list[idx];
+  const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BT_SLOTS);
+  const long long acc =
+      eval_table<MODE, TPB, 4, 8, true>(A, i, keys, vals, cap - 1, L, &own, tst);
+  if (threadIdx.x != 0) return;
+  if (acc == TABLE_FULL)
+    A.ovf_list[atomicAdd(A.ovf_count, 1)] = i;
+  else if (MODE != EV_SWEEP && acc)
+    add_accepted(A.stat, acc);
+}
+
+// The rows of bins W and B that overflowed their small table, with the
+// full one (rows of at most BTAB_MAX entries always fit).  A fixed grid
+// loops over the list; the last block to finish clears the list for the
+// next launch.
+template <int MODE>
+__global__ void __launch_bounds__(TPB) k_eval_ovf(EvalArgs A, int32_t* done) {
   __shared__ int keys[BTAB_SLOTS];
   __shared__ int vals[BTAB_SLOTS];
   __shared__ GroupLds<TPB> L;
   __shared__ int own;
-  const int64_t idx = blockIdx.x;
-  if (idx >= *A.count) return;  // uniform over the block
-  const int i = A.list[idx];
-  const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BTAB_SLOTS);
-  const long long acc = eval_table<MODE, TPB, 4, 8>(A, i, keys, vals, cap - 1, L, &own);
-  if (MODE != EV_SWEEP && threadIdx.x == 0 && acc) add_accepted(A.stat, acc);
+  const int64_t cnt = *A.ovf_count;
+  long long accepted = 0;
+  for (int64_t idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
+    const int i = A.ovf_list[idx];
+    const uint32_t cap = table_cap(A.off[i + 1] - A.off[i], BTAB_SLOTS);
+    accepted += eval_table<MODE, TPB, 4, 8>(A, i, keys, vals, cap - 1, L, &own);
+  }
+  if (MODE != EV_SWEEP && threadIdx.x == 0 && accepted) add_accepted(A.stat, accepted);
+  __syncthreads();  // every thread of the block has read the count
+  if (threadIdx.x == 0 && atomicAdd(done, 1) == int(gridDim.x) - 1) {
+    *A.ovf_count = 0;
+    *done = 0;
+  }
 }
 
-// bin G: one block per vertex, table in global memory (>= 2 slots per entry)
+// bin G: one block per vertex.  The row's foreign labels usually fit the
+// LDS table (a hub's neighbours mostly share a few communities), and the
+// whole row is loaded in one round; a row with more labels than that
+// table takes is evaluated again with its table in global memory (>= 2
+// slots per entry).
 template <int MODE>
 __global__ void __launch_bounds__(GTPB) k_eval_gtab(EvalArgs A) {
+  __shared__ int keys[BTAB_SLOTS];
+  __shared__ int vals[BTAB_SLOTS];
   __shared__ GroupLds<GTPB> L;
   __shared__ int own;
+  __shared__ int tstate[2];
   const int64_t idx = blockIdx.x;
   if (idx >= *A.count) return;
   const int i = A.list[idx];
-  const long long o0 = A.tab_off[idx], o1 = A.tab_off[idx + 1];
-  const long long acc = eval_table<MODE, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0,
-                                                     uint32_t(o1 - o0) - 1, L, &own);
+  long long acc = eval_table<MODE, GTPB, GT_UI, 8, true>(A, i, keys, vals, BTAB_SLOTS - 1, L,
+                                                         &own, tstate);
+  if (acc == TABLE_FULL) {
+    const long long o0 = A.tab_off[idx], o1 = A.tab_off[idx + 1];
+    acc = eval_table<MODE, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0, uint32_t(o1 - o0) - 1,
+                                       L, &own);
+  }
   if (MODE != EV_SWEEP && threadIdx.x == 0 && acc) add_accepted(A.stat, acc);
 }
 
@@ -966,10 +1034,14 @@ inline int wave_grid(int64_t items) {
   return int(g < 1 ? 1 : g);
 }
 
+constexpr int64_t OVF_GRID = 512;  // blocks of k_eval_ovf
+
 template <int MODE>
 void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEvent_t ev0,
                  hipEvent_t ev1) {
   EvalArgs A = base;
+  A.ovf_list = bins.ovf_list;
+  A.ovf_count = bins.ovf_count;
   auto setbin = [&](int q) {
     A.list = bins.list[q];
     A.list_rb = bins.list_rb[q];
@@ -1000,6 +1072,11 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   if (bins.n[4] > 0) {
     setbin(4);
     k_eval_btab<MODE><<<bins.n[4], TPB, 0, st>>>(A);
+    DC_LAUNCH_CHECK();
+  }
+  if (bins.n[3] + bins.n[4] > 0) {
+    const int64_t g = bins.n[3] + bins.n[4] < OVF_GRID ? bins.n[3] + bins.n[4] : OVF_GRID;
+    k_eval_ovf<MODE><<<int(g), TPB, 0, st>>>(A, bins.ovf_done);
     DC_LAUNCH_CHECK();
   }
   if (bins.n[5] > 0) {
@@ -1052,6 +1129,12 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
     b.vol[q] = hv[q];
   }
   b.count_dev = counts;
+  // overflow list of bins W and B; its count and finished-block counter sit
+  // in the zeroed metadata and are cleared again by each k_eval_ovf
+  s.ovf.ensure(size_t(cap) * sizeof(int32_t));
+  b.ovf_list = s.ovf.as<int32_t>();
+  b.ovf_count = counts + 16;
+  b.ovf_done = counts + 17;
   b.gkeys = nullptr;
   b.gvals = nullptr;
   b.tab_off = nullptr;

@@ -226,6 +226,8 @@ __global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
 // tiles.  A block walks many rows and sums the
 // label changes in its LDS table first, so a large community receives one
 // update per block instead of one per row (same-address atomics serialise).
+constexpr int RC_U = 4;     // rows a thread takes per iteration
+constexpr int RC_MANY = 8;  // rows with more changes are summed by a wave
 __global__ void __launch_bounds__(TPB)
     k_row_changes(const int32_t* __restrict__ cptr,
                   const int32_t* __restrict__ ch_op,
@@ -238,26 +240,67 @@ __global__ void __launch_bounds__(TPB)
   __syncthreads();
   const int32_t nnz = off[n];
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u < n; u += stride) {
-    const int32_t b = cptr[u], e = cptr[u + 1];
-    const int32_t ob = off[u], oe = off[u + 1];
-    int32_t dd = 0, dk = 0;
-    for (int32_t q = b; q < e; ++q) {
-      const int32_t op = ch_op[q];
-      dd += op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
-      dk += ch_dk[q];
+  // RC_U rows per iteration, their loads issued before any is used; the
+  // loop runs while the wave's first row is in range, so whole waves take
+  // part in the wave sums below
+  for (int64_t u0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; u0 - lane_id() < n;
+       u0 += RC_U * stride) {
+    int32_t b[RC_U], e[RC_U], ob[RC_U], oe[RC_U], cu[RC_U];
+#pragma unroll
+    for (int r = 0; r < RC_U; ++r) {
+      const int64_t u = u0 + r * stride;
+      const bool h = u < n;
+      b[r] = h ? cptr[u] : 0;
+      e[r] = h ? cptr[u + 1] : 0;
+      ob[r] = h ? off[u] : 0;
+      oe[r] = h ? off[u + 1] : 0;
+      cu[r] = h ? C[u] : 0;
     }
-    new_deg[u] = oe - ob + dd;
-    // merge tiles: the row holding each tile's first entry, and after the
-    // last tile the row holding the last entry
-    if (oe > ob) {
-      for (int64_t t = ceil_div(ob, MERGE_TILE); t * MERGE_TILE < oe; ++t) tile_row[t] = int32_t(u);
-      if (oe == nnz) tile_row[ceil_div(nnz, MERGE_TILE)] = int32_t(u);
-    }
-    if (dk != 0) {
-      k[u] += dk;
-      const int c = C[u];
-      if (!agg_try(agg, c, dk)) atomicAdd(&a[c], dk);
+#pragma unroll
+    for (int r = 0; r < RC_U; ++r) {
+      const int64_t u = u0 + r * stride;
+      int32_t dd = 0, dk = 0;
+      // a row with many changes (a hub) is summed by the whole wave, one
+      // such row after the other; the others by their own thread
+      uint64_t many = __ballot(e[r] - b[r] > RC_MANY);
+      while (many) {
+        const int l = __ffsll((unsigned long long)many) - 1;
+        many &= many - 1;
+        const int32_t qb = __builtin_amdgcn_readlane(b[r], l);
+        const int32_t qe = __builtin_amdgcn_readlane(e[r], l);
+        int32_t sd = 0, sk = 0;
+        for (int32_t q = qb + lane_id(); q < qe; q += WAVE) {
+          const int32_t op = ch_op[q];
+          sd += op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
+          sk += ch_dk[q];
+        }
+        sd = wave_sum(sd);
+        sk = wave_sum(sk);
+        if (lane_id() == l) {
+          dd = sd;
+          dk = sk;
+        }
+      }
+      if (e[r] - b[r] <= RC_MANY) {
+        for (int32_t q = b[r]; q < e[r]; ++q) {
+          const int32_t op = ch_op[q];
+          dd += op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
+          dk += ch_dk[q];
+        }
+      }
+      if (u >= n) continue;
+      new_deg[u] = oe[r] - ob[r] + dd;
+      // merge tiles: the row holding each tile's first entry, and after
+      // the last tile the row holding the last entry
+      if (oe[r] > ob[r]) {
+        for (int64_t t = ceil_div(ob[r], MERGE_TILE); t * MERGE_TILE < oe[r]; ++t)
+          tile_row[t] = int32_t(u);
+        if (oe[r] == nnz) tile_row[ceil_div(nnz, MERGE_TILE)] = int32_t(u);
+      }
+      if (dk != 0) {
+        k[u] += dk;
+        if (!agg_try(agg, cu[r], dk)) atomicAdd(&a[cu[r]], dk);
+      }
     }
   }
   __syncthreads();

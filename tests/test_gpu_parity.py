@@ -82,13 +82,17 @@ def test_planted_partition_2000(mode):
 
 @pytest.mark.parametrize("seed", [0, 2])
 def test_dcsbm_with_hubs(seed):
-    """Power-law degrees up to thousands: all three row-length bins and
-    multi-chunk coarsening are exercised; several steps of 1% batches."""
+    """Power-law degrees up to thousands: all row-length bins and
+    multi-chunk coarsening are exercised; several steps of 1% batches.  The
+    first sweep from singletons gives rows of 257-512 and 1025-4096 entries
+    more distinct labels than their small LDS tables hold, so those rows are
+    evaluated again with the full table."""
     _log(f"case: dcsbm hubs seed={seed}")
     gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=seed)
     (u, v, w), it = gen.stream(3, frac=0.01)
     deg = np.bincount(np.concatenate([u, v]), minlength=gen.n)
     assert deg.max() > 2048 and ((deg > 128) & (deg <= 2048)).any()
+    assert ((deg > 256) & (deg <= 512)).any() and ((deg > 1024) & (deg <= 4096)).any()
     o, g = make_pair(gen.n, u, v, w)
     compare(o, g, "init")
     for t, b in enumerate(it):
@@ -180,10 +184,9 @@ def test_full_and_incremental_coarsening_agree(graph):
 
 
 def _merge_case(seed):
-    """A graph whose batch reaches every way a changed row is merged: a hub
-    row of 6000 entries with more than 4096 changes, a 600-entry row and a
-    300-entry row with 80 changes (one block per row), a 200-entry row with
-    40 changes (one wave, entries in registers), replacements, and a sparse
+    """A batch with a hub row of 6000 entries (several merge tiles) taking
+    more than 4096 changes (more than a tile stages in LDS), rows of 600,
+    300 and 200 entries with tens of changes, replacements, and a sparse
     background with a few changes per row."""
     rng = np.random.default_rng(seed)
     n = 12000
@@ -244,8 +247,7 @@ def _merge_case(seed):
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_merge_paths_csr_equal(seed):
-    """G_t's CSR after a batch equals the oracle's entry for entry on rows
-    merged by every path (register wave, LDS block, binary search)."""
+    """G_t's CSR after a batch equals the oracle's entry for entry."""
     _log(f"case: merge paths seed={seed}")
     n, (u, v, w), b = _merge_case(seed)
     o, g = make_pair(n, u, v, w)
@@ -257,3 +259,49 @@ def test_merge_paths_csr_equal(seed):
     assert np.array_equal(offo, offg), "row offsets differ"
     assert np.array_equal(colo, colg) and np.array_equal(wo, wg), "entries differ"
     compare(o, g, "after batch")
+
+
+def test_merge_tile_edges():
+    """Merge corner cases: insertions into rows that were empty, a row that
+    loses every entry, a 2500-entry row spanning three merge tiles whose
+    600 changes (more than a tile stages in LDS) include a new neighbour
+    below all old ones, new ones above all, and deletions of its first and
+    last entries; then a second batch on the merged graph."""
+    _log("case: merge tile edges")
+    rng = np.random.default_rng(7)
+    n = 5000
+    pairs = {(1, x) for x in range(2, 2502)}
+    while len(pairs) < 2500 + 20000:
+        a, b = (int(x) for x in rng.integers(2, 4990, 2))
+        if a != b:
+            pairs.add((min(a, b), max(a, b)))
+    edges = sorted(pairs)
+    u = np.array([p[0] for p in edges], np.int32)
+    v = np.array([p[1] for p in edges], np.int32)
+    w = rng.integers(1, 9, len(edges)).astype(np.int32)
+    deg = np.bincount(np.concatenate([u, v]), minlength=n)
+    assert (deg[4990:] == 0).all() and deg[0] == 0
+    victim = next(x for x in range(2502, 4990) if 2 <= deg[x] <= 6)
+    add = [(4990, 4991), (4990, 4992), (4993, 10), (4999, 0), (0, 1), (4998, 4999)]
+    add += [(1, x) for x in range(4990, 4998)]
+    dele = [(1, 2), (1, 2501)] + [p for p in edges if victim in p]
+    dele += [(1, int(x)) for x in rng.choice(np.arange(3, 2501), 300, replace=False)]
+    dset = set(dele)
+    rep = [(1, int(x)) for x in rng.choice(np.arange(3, 2501), 400, replace=False)
+           if (1, int(x)) not in dset][:280]
+    add_u = [p[0] for p in add] + [p[1] for p in rep]
+    add_v = [p[1] for p in add] + [p[0] for p in rep]
+    add_w = [3] * len(add) + [7] * len(rep)
+    del_u = [p[1] for p in dele] + [p[0] for p in rep]
+    del_v = [p[0] for p in dele] + [p[1] for p in rep]
+    o, g = make_pair(n, u, v, w)
+    compare(o, g, "init")
+    for t, b in enumerate([(add_u, add_v, add_w, del_u, del_v),
+                           ([4990, 0], [4999, 4993], [2, 2], [4990, 1], [4991, 0])]):
+        o.apply_batch(*b)
+        g.apply_batch(*b)
+        offo, colo, wo = o.csr()
+        offg, colg, wg = g.csr()
+        assert np.array_equal(offo, offg), f"batch {t}: row offsets differ"
+        assert np.array_equal(colo, colg) and np.array_equal(wo, wg), f"batch {t}: entries differ"
+        compare(o, g, f"after batch {t}")
