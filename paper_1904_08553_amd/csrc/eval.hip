@@ -1034,7 +1034,7 @@ inline int wave_grid(int64_t items) {
   return int(g < 1 ? 1 : g);
 }
 
-constexpr int64_t OVF_GRID = 512;  // blocks of k_eval_ovf
+constexpr int64_t OVF_GRID = 128;  // blocks of k_eval_ovf
 
 template <int MODE>
 void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEvent_t ev0,

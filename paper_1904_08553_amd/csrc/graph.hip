@@ -390,6 +390,11 @@ __global__ void __launch_bounds__(TPB)
   }
   for (int i = threadIdx.x; i < MERGE_TILE; i += TPB) s_row[i] = -1;
   const int32_t r0 = tile_row[tile], r1 = tile_row[tile + 1];
+  // the bounds of this thread's first row are loaded before the barrier
+  const int32_t rf = r0 + int32_t(threadIdx.x);
+  const bool hf = rf <= r1;
+  const int32_t fb = hf ? off_old[rf] : 0, fen = hf ? off_old[rf + 1] : 0;
+  const int32_t fnb = hf ? off_new[rf] : 0, fcb = hf ? cptr[rf] : 0, fce = hf ? cptr[rf + 1] : 0;
   const int32_t c0 = cptr[r0], nloc = cptr[r1 + 1] - c0;
   const bool staged = nloc <= MT_CH;  // block-uniform
   if (staged) {
@@ -399,9 +404,7 @@ __global__ void __launch_bounds__(TPB)
     }
   }
   __syncthreads();
-  for (int32_t r = r0 + int32_t(threadIdx.x); r <= r1; r += TPB) {
-    const int32_t b = off_old[r], en = off_old[r + 1];
-    const int32_t sh = off_new[r] - b, cb = cptr[r], ce = cptr[r + 1];
+  auto put = [&](int32_t r, int32_t b, int32_t en, int32_t sh, int32_t cb, int32_t ce) {
     const int64_t lo = b > t0 ? int64_t(b) : t0, hi = en < t1 ? int64_t(en) : t1;
     if (lo < hi) {
       const int p = int(lo - t0);
@@ -411,6 +414,11 @@ __global__ void __launch_bounds__(TPB)
       s_ce[p] = ce;
       for (int s = int(ceil_div(p, WAVE)) * WAVE; s < int(hi - t0); s += WAVE) s_seg[s / WAVE] = p;
     }
+  };
+  if (hf) put(rf, fb, fen, fnb - fb, fcb, fce);
+  for (int32_t r = rf + TPB; r <= r1; r += TPB) {
+    const int32_t b = off_old[r];
+    put(r, b, off_old[r + 1], off_new[r] - b, cptr[r], cptr[r + 1]);
   }
   __syncthreads();
   const uint64_t upto = (uint64_t(2) << lane) - 1;  // lanes <= this one
