@@ -708,6 +708,12 @@ void destroy_ctx(dc_ctx* c) {
   if (c->cs.host) (void)hipHostFree(c->cs.host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->bins.side) {
+    (void)hipStreamSynchronize(c->bins.side);
+    (void)hipStreamDestroy(c->bins.side);
+  }
+  if (c->bins.fork) (void)hipEventDestroy(c->bins.fork);
+  if (c->bins.join) (void)hipEventDestroy(c->bins.join);
   delete c;
 }
 
@@ -729,7 +735,8 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],
                   &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,
                   &c->cg[0].off, &c->cg[0].adj, &c->cg[0].k, &c->cg[1].off, &c->cg[1].adj,
-                  &c->cg[1].k, &c->bins.lists, &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
+                  &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf,
+                  &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
                   &c->bins.tab_off, &c->bins.gkeys, &c->bins.gvals, &c->cs.flag, &c->cs.rank,
                   &c->cs.keys0, &c->cs.keys1, &c->cs.vals0, &c->cs.vals1, &c->cs.cntr,
                   &c->cs.mstart, &c->cs.labof, &c->cs.mdeg, &c->cs.mvol, &c->cs.chead,
@@ -850,8 +857,8 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
   }
 }
 
-// A new context with its pinned host buffers and events; `build` fills its
-// device state.  On failure everything is released.
+// A new context with its pinned host buffers, events and second stream;
+// `build` fills its device state.  On failure everything is released.
 template <class F>
 dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) {
   *out = nullptr;
@@ -868,6 +875,9 @@ dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) 
     DC_HIP(hipHostMalloc(&c->cs.host, 64));
     DC_HIP(hipEventCreate(&c->ev0));
     DC_HIP(hipEventCreate(&c->ev1));
+    DC_HIP(hipStreamCreateWithFlags(&c->bins.side, hipStreamNonBlocking));
+    DC_HIP(hipEventCreateWithFlags(&c->bins.fork, hipEventDisableTiming));
+    DC_HIP(hipEventCreateWithFlags(&c->bins.join, hipEventDisableTiming));
     double t0 = now_ms();
     s = build(c);
     c->stats.ms_total = now_ms() - t0;

@@ -103,11 +103,17 @@ struct Bins {
   int32_t* ovf_list;   // rows of bins W and B re-evaluated with the full table
   int32_t* ovf_count;  // their device count (cleared by the re-evaluation)
   int32_t* ovf_done;   // blocks of the re-evaluation that have finished
+  hipStream_t side;    // the hub-row bin runs here, overlapping the other
+  hipEvent_t fork;     // bins (null: on the caller's stream)
+  hipEvent_t join;
 };
 
 struct BinScratch {
   DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf;
   void* host = nullptr;  // pinned, 256 bytes
+  hipStream_t side = nullptr;  // second stream and fork / join events of the
+  hipEvent_t fork = nullptr;   // evaluation launches (owned by the context)
+  hipEvent_t join = nullptr;
 };
 
 // Splits a vertex list (null = all of [0, count)) into the row-length bins,

@@ -1059,6 +1059,24 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     DC_LAUNCH_CHECK();
     if (ev1) DC_HIP(hipEventRecord(ev1, st));
   }
+  // hub rows: few long blocks, so they run on the second stream beside the
+  // other bins (all read one snapshot and write disjoint labels; shared
+  // flags and counters are written as idempotent stores or atomics)
+  const bool fork = bins.n[5] > 0 && bins.side;
+  if (fork) {
+    EvalArgs G = A;
+    G.list = bins.list[5];
+    G.list_rb = bins.list_rb[5];
+    G.count = bins.count_dev + 5;
+    G.gkeys = bins.gkeys;
+    G.gvals = bins.gvals;
+    G.tab_off = bins.tab_off;
+    DC_HIP(hipEventRecord(bins.fork, st));
+    DC_HIP(hipStreamWaitEvent(bins.side, bins.fork, 0));
+    k_eval_gtab<MODE><<<bins.n[5], GTPB, 0, bins.side>>>(G);
+    DC_LAUNCH_CHECK();
+    DC_HIP(hipEventRecord(bins.join, bins.side));
+  }
   if (bins.n[2] > 0) {
     setbin(2);
     k_eval_group<MODE, 64><<<wave_grid(bins.n[2]), TPB, 0, st>>>(A);
@@ -1079,7 +1097,9 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     k_eval_ovf<MODE><<<int(g), TPB, 0, st>>>(A, bins.ovf_done);
     DC_LAUNCH_CHECK();
   }
-  if (bins.n[5] > 0) {
+  if (fork) {
+    DC_HIP(hipStreamWaitEvent(st, bins.join, 0));
+  } else if (bins.n[5] > 0) {
     setbin(5);
     A.gkeys = bins.gkeys;
     A.gvals = bins.gvals;
@@ -1135,6 +1155,9 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.ovf_list = s.ovf.as<int32_t>();
   b.ovf_count = counts + 16;
   b.ovf_done = counts + 17;
+  b.side = s.side;
+  b.fork = s.fork;
+  b.join = s.join;
   b.gkeys = nullptr;
   b.gvals = nullptr;
   b.tab_off = nullptr;
