@@ -710,7 +710,7 @@ constexpr int BT_SLOTS = 2048;  // bin B: per-block table
 
 // bin W: one wave per vertex, wave-private LDS table
 template <int MODE>
-__global__ void __launch_bounds__(TPB) k_eval_wtab(EvalArgs A) {
+__global__ void __launch_bounds__(TPB, MODE == EV_SWEEP ? 8 : 7) k_eval_wtab(EvalArgs A) {
   __shared__ int keys[NW][WT_SLOTS];
   __shared__ int vals[NW][WT_SLOTS];
   __shared__ GroupLds<WAVE> L[NW];
