@@ -327,32 +327,44 @@ __global__ void k_mover_vol(const int32_t* __restrict__ Cl, const int32_t* __res
 // Entry q of mover u's row (u -> v, weight w) owns four slots from
 // 4 * (mpos[u] + q): w leaves (Cold u, Cold v) and joins (Cl u, Cl v); when v
 // did not move, the mirror entry (v -> u) moves the same way (a moving v's
-// own row carries it, so its mirror slots get weight 0).
+// own row carries it, so its mirror slots get weight 0).  A wave checks 64
+// consecutive vertices with one load and emits the movers' rows one after
+// the other, all lanes on each row.
 __global__ void __launch_bounds__(TPB)
     k_emit_movers(const int32_t* __restrict__ Cl, const int32_t* __restrict__ Cold,
                   const int32_t* __restrict__ off, const int2* __restrict__ adj,
                   const int32_t* __restrict__ mpos, int32_t n, uint64_t* keys, uint32_t* vals) {
+  const int64_t nbatch = ceil_div(n, WAVE);
   const int64_t nwaves = int64_t(gridDim.x) * (TPB / WAVE);
   const uint64_t N = uint64_t(n);
-  for (int64_t u = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; u < n;
-       u += nwaves) {
-    const int cu_old = Cold[u], cu_new = Cl[u];
-    if (cu_new == cu_old) continue;
-    const int32_t rb = off[u], re = off[u + 1];
-    const int64_t base = 4 * int64_t(mpos[u]);
-    for (int32_t q = rb + lane_id(); q < re; q += WAVE) {
-      const int2 e = adj[q];
-      const int vo = Cold[e.x], vn = Cl[e.x];
-      const bool still = vo == vn;
-      const int64_t at = base + 4 * int64_t(q - rb);
-      keys[at] = uint64_t(cu_old) * N + uint64_t(vo);
-      vals[at] = uint32_t(-e.y);
-      keys[at + 1] = uint64_t(cu_new) * N + uint64_t(vn);
-      vals[at + 1] = uint32_t(e.y);
-      keys[at + 2] = uint64_t(vo) * N + uint64_t(cu_old);
-      vals[at + 2] = still ? uint32_t(-e.y) : 0u;
-      keys[at + 3] = uint64_t(vn) * N + uint64_t(cu_new);
-      vals[at + 3] = still ? uint32_t(e.y) : 0u;
+  const int lane = lane_id();
+  for (int64_t bt = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; bt < nbatch;
+       bt += nwaves) {
+    const int64_t u = bt * WAVE + lane;
+    const int co = u < n ? Cold[u] : 0, cn = u < n ? Cl[u] : 0;
+    const bool mover = u < n && co != cn;
+    const int32_t rb = mover ? off[u] : 0, re = mover ? off[u + 1] : 0;
+    const int32_t mp = mover ? mpos[u] : 0;
+    for (uint64_t m = __ballot(mover); m; m &= m - 1) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      const int cu_old = __builtin_amdgcn_readlane(co, l);
+      const int cu_new = __builtin_amdgcn_readlane(cn, l);
+      const int32_t b = __builtin_amdgcn_readlane(rb, l), e = __builtin_amdgcn_readlane(re, l);
+      const int64_t base = 4 * int64_t(__builtin_amdgcn_readlane(mp, l));
+      for (int32_t q = b + lane; q < e; q += WAVE) {
+        const int2 en = adj[q];
+        const int vo = Cold[en.x], vn = Cl[en.x];
+        const bool still = vo == vn;
+        const int64_t at = base + 4 * int64_t(q - b);
+        keys[at] = uint64_t(cu_old) * N + uint64_t(vo);
+        vals[at] = uint32_t(-en.y);
+        keys[at + 1] = uint64_t(cu_new) * N + uint64_t(vn);
+        vals[at + 1] = uint32_t(en.y);
+        keys[at + 2] = uint64_t(vo) * N + uint64_t(cu_old);
+        vals[at + 2] = still ? uint32_t(-en.y) : 0u;
+        keys[at + 3] = uint64_t(vn) * N + uint64_t(cu_new);
+        vals[at + 3] = still ? uint32_t(en.y) : 0u;
+      }
     }
   }
 }
@@ -712,7 +724,7 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
     DC_LAUNCH_CHECK();
   }
   if (vol > 0) {
-    k_emit_movers<<<grid_for(int64_t(nl) * WAVE), TPB, 0, st>>>(Cl, Cold, g.off, g.adj, mpos, nl,
+    k_emit_movers<<<grid_for(ceil_div(nl, WAVE) * WAVE), TPB, 0, st>>>(Cl, Cold, g.off, g.adj, mpos, nl,
                                                               ek + h + nch, ev + h + nch);
     DC_LAUNCH_CHECK();
   }
