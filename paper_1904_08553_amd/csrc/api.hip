@@ -350,7 +350,7 @@ dc_status do_init(dc_ctx* c, const dc_edges* g1) {
   read_stat(c);
   int32_t f = int32_t(c->hstat[ST_FLAGS]);
   if (f) return status_from_flags(f);
-  const long long wsum = c->hstat[ST_WSUM_ADD];
+  const long long wsum = slot_total(c->hstat, ST_WSUM_ADD);
   if (2 * wsum >= TWO_M_LIMIT) return DC_E_OVERFLOW;
   // directed entries, sorted, duplicates summed
   const int64_t md = 2 * m;
@@ -446,7 +446,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   read_stat(c);
   // checks in the documented order; nothing has been changed yet
   if (int32_t f = int32_t(hs[ST_FLAGS])) return status_from_flags(f);
-  const long long two_m_new = c->two_m - 2 * hs[ST_WSUM_DEL] + 2 * hs[ST_WSUM_ADD];
+  const long long two_m_new =
+      c->two_m - 2 * slot_total(hs, ST_WSUM_DEL) + 2 * slot_total(hs, ST_WSUM_ADD);
   if (two_m_new >= TWO_M_LIMIT) return DC_E_OVERFLOW;
 
   // ---- from here on the state changes ----

@@ -57,7 +57,13 @@ __device__ __forceinline__ bool agg_try(AggLds& s, int key, long long v) {
 // ---- graph.hip -----------------------------------------------------------
 enum EdgeFlag : int32_t { F_RANGE = 1, F_SELF = 2, F_WEIGHT = 4, F_DUP = 8, F_NO_EDGE = 16 };
 
-// flags |= F_RANGE / F_SELF / F_WEIGHT (w may be null); *wsum += sum of w.
+// Weight sums that thousands of blocks add to are spread over SUM_SLOTS
+// counters (block b adds to slot b % SUM_SLOTS; the reader adds them up):
+// same-address atomics serialise.
+constexpr int SUM_SLOTS = 64;
+
+// flags |= F_RANGE / F_SELF / F_WEIGHT (w may be null); wsum (SUM_SLOTS
+// counters) += sum of w.
 void validate_edges(const int32_t* u, const int32_t* v, const int32_t* w,
                     int64_t m, int32_t n, int32_t* flags, long long* wsum,
                     hipStream_t st);
@@ -103,9 +109,9 @@ void batch_records(const int32_t* du, const int32_t* dv, int64_t nd, const int32
 // run heads, *nruns on the device): ch_key, ch_op, ch_w (new weight for NEW
 // and REPLACE, added weight for ADD), ch_dk (change of the row's weighted
 // degree), dnet (+1 for NEW, -1 for DELETE, else 0); flags |= F_DUP (a pair
-// deleted twice) and
-// F_NO_EDGE (a deletion of a pair absent from off/adj); *wsum += the old
-// weights of the deleted edges.  run_key/run_w/run_ndel: scratch of m.
+// deleted twice) and F_NO_EDGE (a deletion of a pair absent from off/adj);
+// wsum (SUM_SLOTS counters) += the old weights of the deleted edges.
+// run_key/run_w/run_ndel: scratch of m.
 void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* pos, int64_t m,
                      const int32_t* nruns, const int32_t* ins_w, int32_t n, const int32_t* off,
                      const int2* adj, uint64_t* run_key, int32_t* run_w, int32_t* run_ndel,

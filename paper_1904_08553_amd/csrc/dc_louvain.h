@@ -24,12 +24,19 @@ enum StatSlot : int {
   ST_N2 = 14,
   ST_N3 = 15,
   ST_FLAGS = 16,   // batch validation flags (int32 in the low half)
-  ST_WSUM_ADD = 17,
-  ST_WSUM_DEL = 18,
   ST_CASC_CAND = 19,  // cascade candidates (int32 in the low half)
   ST_CASC_EXP = 20,   // cascade candidates whose neighbourhood joined R
-  ST_COUNT = 24
+  ST_WSUM_ADD = 24,   // inserted weight: SUM_SLOTS counters
+  ST_WSUM_DEL = ST_WSUM_ADD + SUM_SLOTS,  // deleted weight: SUM_SLOTS counters
+  ST_COUNT = ST_WSUM_DEL + SUM_SLOTS
 };
+
+// The total of the SUM_SLOTS counters from `base` of a status block copy.
+inline long long slot_total(const long long* h, int base) {
+  long long t = 0;
+  for (int i = 0; i < SUM_SLOTS; ++i) t += h[base + i];
+  return t;
+}
 
 // EV_FEAT: e_{i->C(i)} and the gains to the best and second-best other
 // neighbouring community, the integer inputs of the screener features.

@@ -36,7 +36,7 @@ __global__ void k_validate(const int32_t* __restrict__ u,
     }
   }
   block_or(f, flags);
-  if (w) block_add(s, wsum);
+  if (w) block_add(s, wsum + blockIdx.x % SUM_SLOTS);
 }
 
 __global__ void k_make_directed(const int32_t* __restrict__ u,
@@ -73,19 +73,29 @@ __global__ void k_reduce_runs(const uint64_t* __restrict__ keys,
   }
 }
 
-__global__ void k_row_bounds(const uint64_t* __restrict__ keys, int64_t m,
-                             int32_t n, int32_t* row_ptr) {
-  GRID_STRIDE(uu, int64_t(n) + 1) {
-    uint64_t target = uint64_t(uu) * uint64_t(n);
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (keys[mid] < target)
-        lo = mid + 1;
-      else
-        hi = mid;
+// row_ptr[r] = index of the first key of row r or a later row (row = key /
+// n, keys sorted), row_ptr[n] = m.  Thread per key, plus one past the end:
+// the first key of a row writes the bounds of the rows from the previous
+// key's row (exclusive) to its own; a long run of empty rows is written by
+// the whole wave.
+__global__ void __launch_bounds__(TPB)
+    k_row_bounds(const uint64_t* __restrict__ keys, int64_t m, int32_t n, int32_t* row_ptr) {
+  const int lane = lane_id();
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  // the loop runs while the wave's first thread is in range (whole waves)
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q - lane <= m; q += stride) {
+    const bool h = q <= m;
+    const long long r1 = !h ? 0 : (q < m ? (long long)(keys[q] / uint64_t(n)) : (long long)n);
+    const long long r0 = !h ? 0 : (q > 0 ? (long long)(keys[q - 1] / uint64_t(n)) : -1);
+    const bool wide = h && r1 - r0 > WAVE;
+    if (h && !wide)
+      for (long long r = r0 + 1; r <= r1; ++r) row_ptr[r] = int32_t(q);
+    for (uint64_t wm = __ballot(wide); wm; wm &= wm - 1) {
+      const int l = __ffsll((unsigned long long)wm) - 1;
+      const long long a = readlane64(r0, l) + 1, b = readlane64(r1, l);
+      const int32_t qv = __builtin_amdgcn_readlane(int32_t(q), l);
+      for (long long r = a + lane; r <= b; r += WAVE) row_ptr[r] = qv;
     }
-    row_ptr[uu] = int32_t(lo);
   }
 }
 
@@ -217,7 +227,7 @@ __global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
     dnet[r] = op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
   }
   block_or(f, flags);
-  block_add(s, wsum);
+  block_add(s, wsum + blockIdx.x % SUM_SLOTS);
 }
 
 
@@ -538,7 +548,7 @@ void reduce_runs(const uint64_t* keys, const uint32_t* vals,
 
 void row_bounds(const uint64_t* keys, int64_t m, int32_t n, int32_t* row_ptr,
                 hipStream_t st) {
-  k_row_bounds<<<grid_for(int64_t(n) + 1), TPB, 0, st>>>(keys, m, n, row_ptr);
+  k_row_bounds<<<grid_for(m + 1), TPB, 0, st>>>(keys, m, n, row_ptr);
   DC_LAUNCH_CHECK();
 }
 
