@@ -736,7 +736,7 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],
                   &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,
                   &c->cg[0].off, &c->cg[0].adj, &c->cg[0].k, &c->cg[1].off, &c->cg[1].adj,
-                  &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf,
+                  &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf, &c->bins.defer,
                   &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
                   &c->bins.tab_off, &c->bins.gkeys, &c->bins.gvals, &c->cs.flag, &c->cs.rank,
                   &c->cs.keys0, &c->cs.keys1, &c->cs.vals0, &c->cs.vals1, &c->cs.cntr,

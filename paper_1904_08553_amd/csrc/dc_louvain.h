@@ -63,6 +63,13 @@ struct LevelView {
   const int32_t* k;
 };
 
+// Alg. 2 source whose gain2 walk over the long row of j* was left to a
+// block of its own: i, j*, C(i), C(j*) and gain1.
+struct DeferItem {
+  int32_t i, j, c, x;
+  long long g;
+};
+
 // Arguments of the evaluation kernels for one graph (one level).
 struct EvalArgs {
   const int32_t* off;
@@ -83,6 +90,8 @@ struct EvalArgs {
   const long long* tab_off;
   int32_t* ovf_list;     // bins W and B: vertices whose labels overflowed the
   int32_t* ovf_count;    // small LDS table (device count)
+  DeferItem* defer;      // Alg. 2: sources of the short-row bins whose j* has a
+  int32_t* defer_count;  // long row (null: walk every row in place)
   long long* stat;
   const uint64_t* ins_keys;  // Alg. 2: sorted directed insertions src*n0+dst
   const int32_t* seg_beg;    // per source vertex: its sinks are ins_keys[beg, end)
@@ -110,13 +119,15 @@ struct Bins {
   int32_t* ovf_list;   // rows of bins W and B re-evaluated with the full table
   int32_t* ovf_count;  // their device count (cleared by the re-evaluation)
   int32_t* ovf_done;   // blocks of the re-evaluation that have finished
+  DeferItem* defer;    // deferred gain2 walks (filled once per binning)
+  int32_t* defer_count;
   hipStream_t side;    // the hub-row bin runs here, overlapping the other
   hipEvent_t fork;     // bins (null: on the caller's stream)
   hipEvent_t join;
 };
 
 struct BinScratch {
-  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf;
+  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf, defer;
   void* host = nullptr;  // pinned, 256 bytes
   hipStream_t side = nullptr;  // second stream and fork / join events of the
   hipEvent_t fork = nullptr;   // evaluation launches (owned by the context)

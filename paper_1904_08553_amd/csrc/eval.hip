@@ -46,6 +46,11 @@ __device__ __forceinline__ bool cand_better(const Cand& p, const Cand& q) {
 }
 
 
+// Alg. 2 sources of the short-row bins whose j* has more entries than this
+// are finished by k_ds_deferred; a gain2 above any gain1 stands for them.
+constexpr int32_t DEFER_ROW = 512;
+constexpr long long NO_ACCEPT = 0x7fffffffffffffffll;
+
 // gain2 of Alg. 2: G(j* -> c), streamed over the row of j* by one wave.
 // The row is walked RG_U chunks per round: their entry loads, then their
 // label gathers, are issued before any is waited on.
@@ -314,9 +319,17 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     long long g2 = 0;
     for (uint64_t lm = __ballot(live && gl == 0); lm; lm &= lm - 1) {
       const int ld = __ffsll((unsigned long long)lm) - 1;
-      const long long r = reverse_gain(A, __builtin_amdgcn_readlane(best.j, ld),
-                                       __builtin_amdgcn_readlane(best.x, ld),
-                                       __builtin_amdgcn_readlane(c, ld));
+      const int js = __builtin_amdgcn_readlane(best.j, ld);
+      const int cj = __builtin_amdgcn_readlane(best.x, ld);
+      const int ci = __builtin_amdgcn_readlane(c, ld);
+      long long r;
+      if (A.defer && A.off[js + 1] - A.off[js] > DEFER_ROW) {
+        // j*'s row is long: its walk goes to a block of its own (k_ds_deferred)
+        if (lane == ld) A.defer[atomicAdd(A.defer_count, 1)] = DeferItem{i, js, ci, cj, best.g};
+        r = NO_ACCEPT;
+      } else {
+        r = reverse_gain(A, js, cj, ci);
+      }
       if (lane / GS == ld / GS) g2 = r;
     }
     if (live && best.g >= g2) {
@@ -1034,7 +1047,34 @@ inline int wave_grid(int64_t items) {
   return int(g < 1 ? 1 : g);
 }
 
+// Alg. 2 for the deferred sources: gain2 over j*'s long row by a whole
+// block, then the same acceptance as in place (R gets i, j* and i's
+// neighbours, C(j*) is flagged).
+template <int MODE>
+__global__ void __launch_bounds__(TPB) k_ds_deferred(EvalArgs A) {
+  __shared__ GroupLds<TPB> L;
+  const int64_t cnt = *A.defer_count;
+  long long accepted = 0;
+  for (int64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const DeferItem d = A.defer[q];
+    const long long g2 = group_reverse_gain<TPB>(A, d.j, d.x, d.c, L);
+    if (d.g >= g2) {  // block-uniform
+      const int32_t rb = A.off[d.i], re = A.off[d.i + 1];
+      for (int32_t p = rb + int32_t(threadIdx.x); p < re; p += TPB) A.R[A.adj[p].x] = 1;
+      if (threadIdx.x == 0) {
+        A.R[d.i] = 1;
+        A.R[d.j] = 1;
+        A.cflag[d.x] = 1;
+        if (A.accflag) A.accflag[d.i] = 1;
+        accepted += ACC_ADD;
+      }
+    }
+  }
+  if (threadIdx.x == 0 && accepted) add_accepted(A.stat, accepted);
+}
+
 constexpr int64_t OVF_GRID = 128;  // blocks of k_eval_ovf
+constexpr int DEFER_GRID = 256;    // blocks of k_ds_deferred
 
 template <int MODE>
 void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEvent_t ev0,
@@ -1042,6 +1082,9 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   EvalArgs A = base;
   A.ovf_list = bins.ovf_list;
   A.ovf_count = bins.ovf_count;
+  constexpr bool ALG2 = MODE == EV_DSADD || MODE == EV_DSBOTH;
+  A.defer = ALG2 ? bins.defer : nullptr;
+  A.defer_count = ALG2 ? bins.defer_count : nullptr;
   auto setbin = [&](int q) {
     A.list = bins.list[q];
     A.list_rb = bins.list_rb[q];
@@ -1107,6 +1150,10 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     k_eval_gtab<MODE><<<bins.n[5], GTPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
+  if (ALG2 && bins.n[0] + bins.n[1] + bins.n[2] > 0) {
+    k_ds_deferred<MODE><<<DEFER_GRID, TPB, 0, st>>>(A);
+    DC_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace
@@ -1122,7 +1169,8 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   constexpr size_t META = 32 * sizeof(int32_t) + NBINS * sizeof(long long);
   static_assert(META <= 256, "bin metadata must fit the pinned host buffer");
   s.counts.ensure(META);
-  // [0, NBINS) counts, [NBINS, 2 NBINS) starts, [2 NBINS] total
+  // [0, NBINS) counts, [NBINS, 2 NBINS) starts, [2 NBINS] total, [16, 19)
+  // overflow count, finished blocks, deferred count
   int32_t* counts = s.counts.as<int32_t>();
   long long* vol = reinterpret_cast<long long*>(counts + 32);
   int32_t* bcnt = s.bcnt.as<int32_t>();
@@ -1155,6 +1203,11 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.ovf_list = s.ovf.as<int32_t>();
   b.ovf_count = counts + 16;
   b.ovf_done = counts + 17;
+  // deferred gain2 walks of the short-row bins: at most one per listed vertex;
+  // the count is cleared with the metadata, so one Alg. 2 pass per binning
+  s.defer.ensure(size_t(cap) * sizeof(DeferItem));
+  b.defer = reinterpret_cast<DeferItem*>(s.defer.p);
+  b.defer_count = counts + 18;
   b.side = s.side;
   b.fork = s.fork;
   b.join = s.join;
