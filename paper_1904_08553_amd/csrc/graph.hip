@@ -236,9 +236,11 @@ __global__ void k_resolve_runs(const uint64_t* __restrict__ run_key,
 // tiles.  A block walks many rows and sums the
 // label changes in its LDS table first, so a large community receives one
 // update per block instead of one per row (same-address atomics serialise).
-constexpr int RC_U = 4;     // rows a thread takes per iteration
-constexpr int RC_MANY = 8;  // rows with more changes are summed by a wave
-__global__ void __launch_bounds__(TPB)
+constexpr int RC_U = 4;        // rows a thread takes per iteration
+constexpr int RC_MANY = 8;     // rows with more changes are summed by a wave
+constexpr int RC_TPB = 1024;   // one large block per CU: fewer flushes per label
+constexpr int RC_BLOCKS = 256;
+__global__ void __launch_bounds__(RC_TPB)
     k_row_changes(const int32_t* __restrict__ cptr,
                   const int32_t* __restrict__ ch_op,
                   const int32_t* __restrict__ ch_dk,
@@ -594,7 +596,7 @@ void row_changes(const int32_t* cptr, const int32_t* ch_op, const int32_t* ch_dk
                  const int32_t* off, int32_t n, int32_t* new_deg, int32_t* k,
                  const int32_t* C, int32_t* a, int32_t* tile_row, hipStream_t st) {
   if (n <= 0) return;
-  k_row_changes<<<grid_for(n, TPB, 512), TPB, 0, st>>>(cptr, ch_op, ch_dk, off, n, new_deg, k,
+  k_row_changes<<<grid_for(n, RC_TPB, RC_BLOCKS), RC_TPB, 0, st>>>(cptr, ch_op, ch_dk, off, n, new_deg, k,
                                                        C, a, tile_row);
   DC_LAUNCH_CHECK();
 }
