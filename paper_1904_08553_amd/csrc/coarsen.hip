@@ -443,22 +443,14 @@ __global__ void k_adj_weights(const int2* __restrict__ adj, int64_t m, int32_t* 
 }
 
 // Level-1 entries relabelled by the final labels of their vertices (the
-// final label of a level-0 community is that of any of its members);
-// broken = 1 when the new keys are not strictly increasing.
+// final label of a level-0 community is that of any of its members).
 __global__ void k_relabel(const uint64_t* __restrict__ lkey, int64_t m, int32_t nc,
                           const int32_t* __restrict__ lminv, const int32_t* __restrict__ Ct,
-                          int32_t n, uint64_t* okey, int32_t* broken) {
+                          int32_t n, uint64_t* okey) {
   GRID_STRIDE(i, m) {
     const uint64_t k = lkey[i];
-    const uint64_t nk = uint64_t(Ct[lminv[int32_t(k / uint64_t(nc))]]) * uint64_t(n) +
-                        uint64_t(Ct[lminv[int32_t(k % uint64_t(nc))]]);
-    okey[i] = nk;
-    if (i > 0) {
-      const uint64_t kp = lkey[i - 1];
-      const uint64_t pk = uint64_t(Ct[lminv[int32_t(kp / uint64_t(nc))]]) * uint64_t(n) +
-                          uint64_t(Ct[lminv[int32_t(kp % uint64_t(nc))]]);
-      if (pk >= nk) *broken = 1;
-    }
+    okey[i] = uint64_t(Ct[lminv[int32_t(k / uint64_t(nc))]]) * uint64_t(n) +
+              uint64_t(Ct[lminv[int32_t(k % uint64_t(nc))]]);
   }
 }
 
@@ -783,39 +775,17 @@ void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t*
 
 void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
                 hipStream_t st) {
-  int32_t* host = static_cast<int32_t*>(s.host);
+  (void)s;
   const int64_t m = H.lh;
-  H.tkey.ensure(size_t(m + 1) * 8);
+  H.hkey.ensure(size_t(m + 1) * 8);
   H.hw.ensure(size_t(m + 1) * 4);
-  H.mflag.ensure(8);
-  int32_t* broken = H.mflag.as<int32_t>();
-  fill_i32(broken, 0, 1, st);
   if (m > 0) {
     k_relabel<<<grid_for(m), TPB, 0, st>>>(H.lkey.as<uint64_t>(), m, H.lnc,
-                                           H.lminv.as<int32_t>(), Ct, n, H.tkey.as<uint64_t>(),
-                                           broken);
+                                           H.lminv.as<int32_t>(), Ct, n, H.hkey.as<uint64_t>());
     DC_LAUNCH_CHECK();
+    DC_HIP(hipMemcpyAsync(H.hw.p, H.lw.p, size_t(m) * 4, hipMemcpyDeviceToDevice, st));
   }
-  DC_HIP(hipMemcpyAsync(host, broken, 4, hipMemcpyDeviceToHost, st));
-  DC_HIP(hipStreamSynchronize(st));
-  if (!host[0]) {
-    // the final labels keep the order: the relabelled list is H(G_t, C_t)
-    swap_buf(H.hkey, H.tkey);
-    if (m > 0)
-      DC_HIP(hipMemcpyAsync(H.hw.p, H.lw.p, size_t(m) * 4, hipMemcpyDeviceToDevice, st));
-    H.h = m;
-  } else {
-    // communities merged above level 0, or labels changed order: re-sort
-    H.ev0.ensure(size_t(m + 1) * 4);
-    H.ek1.ensure(size_t(m + 1) * 8);
-    H.ev1.ensure(size_t(m + 1) * 4);
-    H.hkey.ensure(size_t(m + 1) * 8);
-    DC_HIP(hipMemcpyAsync(H.ev0.p, H.lw.p, size_t(m) * 4, hipMemcpyDeviceToDevice, st));
-    radix_sort_pairs(H.tkey.as<uint64_t>(), H.ev0.as<uint32_t>(), H.ek1.as<uint64_t>(),
-                     H.ev1.as<uint32_t>(), m, ilog2_ceil(uint64_t(n) * uint64_t(n)), st);
-    H.h = reduce_sorted(H.tkey.as<uint64_t>(), H.ev0.as<uint32_t>(), m, H.hkey.as<uint64_t>(),
-                        H.hw.as<int32_t>(), H, host, st);
-  }
+  H.h = m;
   H.valid = true;
 }
 

@@ -307,7 +307,10 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
 // Keeps the level-1 graph just built (and its vertices' smallest members).
 void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,
                  IncCoarsen& H, hipStream_t st);
-// H(G_t, C_t) from the saved level-1 graph and the final labels C_t.
+// H(G_t, C_t) from the saved level-1 graph and the final labels C_t: its
+// entries relabelled, neither sorted nor merged (communities that merged
+// above level 0 leave repeated keys); the next step's sort orders them and
+// sums equal keys with the batch's and the movers' entries.
 void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
                 hipStream_t st);
 
