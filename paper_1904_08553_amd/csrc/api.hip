@@ -508,10 +508,25 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     mark_touched(crows, crow_pos + nch, nch, g0.off, g0.adj, c->tmark.as<uint8_t>(), st);
   }
   if (mode == DC_MODE_DELTA || samples) {
+    const bool fused = c->opt.del_rule == DC_DEL_GAIN;
+    const bool cascade = c->opt.cascade_den > 0;
+    if (cascade) c->accflag.ensure(size_t(n) + 1);
+    if (fused) {
+      c->uflag.ensure(size_t(n) + 1);
+      c->ulist.ensure(size_t(n + 1) * 4);
+    }
     uint8_t* R = c->R.as<uint8_t>();
     uint8_t* cflag = c->cflag.as<uint8_t>();
-    fill_u8(R, 0, n, st);
-    fill_u8(cflag, 0, n, st);
+    int32_t* dflag = c->dflag.as<int32_t>();
+    uint8_t* accflag = cascade ? c->accflag.as<uint8_t>() : nullptr;
+    {
+      // R, the community flags, the deletion-source flags, the accepted
+      // flags (cascade) and the union flags (fused) start at zero
+      void* zp[5] = {R, cflag, dflag, accflag, fused ? c->uflag.p : nullptr};
+      const int64_t zb[5] = {n, n, 4 * int64_t(n), cascade ? int64_t(n) : 0,
+                             fused ? int64_t(n) : 0};
+      zero_buffers(zp, zb, 5, st);
+    }
     uint64_t* ins_keys = c->ins_keys.as<uint64_t>();
     gather_u64(ch_key, c->ins_flag.as<int32_t>(), c->ins_pos.as<int32_t>(), nch, ins_keys, st);
     int32_t* src_flag = c->src_flag.as<int32_t>();
@@ -521,27 +536,14 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     gather_sources(ins_keys, src_flag, src_pos, n_ins, n, c->src_list.as<int32_t>(), st);
     source_segments(ins_keys, n_ins, n, c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), st);
     // deletion sources (labels C_{t-1})
-    int32_t* dflag = c->dflag.as<int32_t>();
-    fill_i32(dflag, 0, n, st);
     deletion_sources(ch_key, ch_op, nch, n, c->C.as<int32_t>(), dflag, st);
-    const bool fused = c->opt.del_rule == DC_DEL_GAIN;
-    const bool cascade = c->opt.cascade_den > 0;
-    uint8_t* accflag = nullptr;
-    if (cascade) {
-      c->accflag.ensure(size_t(n) + 1);
-      accflag = c->accflag.as<uint8_t>();
-      fill_u8(accflag, 0, n, st);
-    }
     int64_t n_src = 0, n_dsrc = 0;
     if (fused) {
       // one evaluation pass over the insertion sources and the deletion
       // endpoints together (Alg. 2 and the deletion rule read the same state)
-      c->uflag.ensure(size_t(n) + 1);
-      c->ulist.ensure(size_t(n + 1) * 4);
       uint8_t* uflag = c->uflag.as<uint8_t>();
       int32_t* f32 = c->rflag.as<int32_t>();
       int32_t* p32 = c->rpos2.as<int32_t>();
-      fill_u8(uflag, 0, n, st);
       union_flags(c->src_list.as<int32_t>(), reinterpret_cast<int32_t*>(stat + ST_N3), n_ins,
                   dflag, n, uflag, f32, stat + ST_DEL_SRC, st);
       scan_excl_i32(f32, p32, n, reinterpret_cast<int32_t*>(stat + ST_N0), st);

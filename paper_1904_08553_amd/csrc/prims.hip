@@ -361,6 +361,39 @@ void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st) {
   DC_LAUNCH_CHECK();
 }
 
+constexpr int ZERO_MAX = 6;
+struct ZeroSet {
+  uint8_t* p[ZERO_MAX];
+  int64_t bytes[ZERO_MAX];
+  int count;
+};
+
+__global__ void k_zero_buffers(ZeroSet z) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int j = 0; j < z.count; ++j) {
+    const int64_t nv = z.bytes[j] / 16;
+    uint4* q = reinterpret_cast<uint4*>(z.p[j]);
+    for (int64_t i = t; i < nv; i += stride) q[i] = make_uint4(0, 0, 0, 0);
+    for (int64_t i = nv * 16 + t; i < z.bytes[j]; i += stride) z.p[j][i] = 0;
+  }
+}
+
+void zero_buffers(void* const* p, const int64_t* bytes, int count, hipStream_t st) {
+  ZeroSet z{};
+  int64_t most = 0;
+  for (int j = 0; j < count && j < ZERO_MAX; ++j) {
+    if (bytes[j] <= 0) continue;
+    z.p[z.count] = static_cast<uint8_t*>(p[j]);
+    z.bytes[z.count] = bytes[j];
+    ++z.count;
+    most = bytes[j] / 16 > most ? bytes[j] / 16 : most;
+  }
+  if (z.count == 0) return;
+  k_zero_buffers<<<grid_for(most + 1), 256, 0, st>>>(z);
+  DC_LAUNCH_CHECK();
+}
+
 void copy_i32(int32_t* const* dst, const int32_t* const* src, int count, int64_t n,
               hipStream_t st) {
   if (n <= 0 || count <= 0) return;
