@@ -161,8 +161,9 @@ constexpr int RS_MAX_DIGIT = 10;  // 40-bit keys in 4 passes
 constexpr int RS_BINS = 1 << RS_MAX_DIGIT;       // bins of the widest digit
 constexpr int RS_WAVES = RS_THREADS / WAVE;
 
-// Per-block digit histogram, written digit-major (hist[d * nblocks + block])
-// so one exclusive scan gives every (digit, block) its output offset.
+// Per-block digit histogram, written digit-major (hist[d * nblocks + block]):
+// a scan of each digit's column plus the totals of the smaller digits give
+// every (digit, block) its output offset.
 __global__ void __launch_bounds__(RS_THREADS)
     k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, int bins,
                  int32_t* __restrict__ hist, int64_t nblocks) {
@@ -187,6 +188,35 @@ __global__ void __launch_bounds__(RS_THREADS)
     hist[int64_t(b) * nblocks + blockIdx.x] = h[b];
 }
 
+// Column scan of the digit-major histogram, one block per digit: the
+// tiles' counts of digit d become their exclusive prefix in place, and the
+// digit's total goes to dtot[d] (the digit bases are summed by the scatter).
+static_assert(RS_THREADS == SCAN_THREADS, "the radix kernels use the scan's block scan");
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_radix_colscan(int32_t* hist, int64_t nblocks, int32_t* dtot) {
+  __shared__ int32_t lds[SCAN_THREADS / WAVE];
+  int32_t* col = hist + int64_t(blockIdx.x) * nblocks;
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += SCAN_THREADS * 4) {
+    const int64_t base = b0 + int64_t(threadIdx.x) * 4;
+    int32_t v[4], s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i] = base + i < nblocks ? col[base + i] : 0;
+      s += v[i];
+    }
+    int32_t tot;
+    int32_t run = carry + block_excl_scan<int32_t>(s, lds, &tot);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (base + i < nblocks) col[base + i] = run;
+      run += v[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
 // Stable scatter: elements are ranked in index order within the tile.  Each
 // round covers 256 consecutive elements; within a wave the rank among equal
 // digits comes from a ballot match (one ballot per digit bit), across waves
@@ -195,13 +225,35 @@ __global__ void __launch_bounds__(RS_THREADS)
     k_radix_scatter(const uint64_t* __restrict__ kin,
                     const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
                     uint32_t* __restrict__ vout, int64_t n, int shift, int dbits,
-                    const int32_t* __restrict__ hist_excl, int64_t nblocks) {
+                    const int32_t* __restrict__ colscan, const int32_t* __restrict__ dtot,
+                    int64_t nblocks) {
   __shared__ int32_t base_d[RS_BINS];
   __shared__ int32_t wcnt[RS_WAVES][RS_BINS];
+  __shared__ int32_t lds[RS_WAVES];
   const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
   const int bins = 1 << dbits;
+  // output base of each digit in this tile: the totals of the smaller
+  // digits (a block scan, RS_BINS / RS_THREADS digits per thread) plus the
+  // digit's count in the tiles before this one
+  {
+    constexpr int DPT = RS_BINS / RS_THREADS;
+    int32_t dv[DPT], s = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const int d = t * DPT + i;
+      dv[i] = d < bins ? dtot[d] : 0;
+      s += dv[i];
+    }
+    int32_t tot;
+    int32_t run = block_excl_scan<int32_t>(s, lds, &tot);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const int d = t * DPT + i;
+      if (d < bins) base_d[d] = run + colscan[int64_t(d) * nblocks + blockIdx.x];
+      run += dv[i];
+    }
+  }
   for (int b = t; b < bins; b += RS_THREADS) {
-    base_d[b] = hist_excl[int64_t(b) * nblocks + blockIdx.x];
 #pragma unroll
     for (int w = 0; w < RS_WAVES; ++w) wcnt[w][b] = 0;
   }
@@ -323,16 +375,18 @@ void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
   const int bins = 1 << dbits;
   const int64_t nb = ceil_div(n, RS_TILE);
   DBuf& hb = prim_scratch().sort_hist;
-  hb.ensure(size_t(nb) * size_t(bins) * sizeof(int32_t));
+  hb.ensure((size_t(nb) + 1) * size_t(bins) * sizeof(int32_t));
   int32_t* hist = hb.as<int32_t>();
+  int32_t* dtot = hist + size_t(nb) * size_t(bins);  // digit totals
   uint64_t *ka = k0, *kb = k1;
   uint32_t *va = v0, *vb = v1;
   for (int p = 0; p < passes; ++p) {
     const int shift = dbits * p;
     k_radix_hist<<<nb, RS_THREADS, 0, st>>>(ka, n, shift, bins, hist, nb);
     DC_LAUNCH_CHECK();
-    scan_excl_i32(hist, hist, nb * bins, nullptr, st);
-    k_radix_scatter<<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, dbits, hist, nb);
+    k_radix_colscan<<<bins, SCAN_THREADS, 0, st>>>(hist, nb, dtot);
+    DC_LAUNCH_CHECK();
+    k_radix_scatter<<<nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n, shift, dbits, hist, dtot, nb);
     DC_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);
