@@ -402,6 +402,94 @@ class DynamicCommunities:
             pass
 
 
+# ---------------------------------------------------------------------------
+# Durable checkpoint files: G_t (CSR) and C_t, as exported by export_state.
+
+CKPT_VERSION = 1
+
+
+class CheckpointError(RuntimeError):
+    """A checkpoint file that is not a complete, intact checkpoint."""
+
+
+def _ckpt_digest(n, off, col, w, C):
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.int64(n).tobytes())
+    for a in (off, col, w, C):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return np.frombuffer(h.digest(), np.uint8)
+
+
+def write_checkpoint(path, n, off, col, w, C):
+    """Write a checkpoint of (n, off, col, w, C) to ``path``: the arrays go
+    to a temporary file in the same directory, which is flushed to disk and
+    then renamed over ``path`` (so a crash leaves the old file or the new
+    one, never a torn one); a SHA-256 digest of the arrays is stored with
+    them.  Plain arrays only (numpy .npz, nothing pickled)."""
+    off = np.ascontiguousarray(off, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    w = np.ascontiguousarray(w, np.int32)
+    C = np.ascontiguousarray(C, np.int32)
+    path = os.fspath(path)
+    d = os.path.dirname(os.path.abspath(path))
+    tmp = os.path.join(d, f".{os.path.basename(path)}.{os.getpid()}.tmp")
+    try:
+        with open(tmp, "wb") as f:
+            np.savez(f, version=np.array([CKPT_VERSION], np.int64), n=np.array([n], np.int64),
+                     off=off, col=col, w=w, C=C, digest=_ckpt_digest(n, off, col, w, C))
+            f.flush()
+            os.fsync(f.fileno())
+        os.replace(tmp, path)
+    finally:
+        if os.path.exists(tmp):
+            os.unlink(tmp)
+    try:
+        fd = os.open(d, os.O_RDONLY)
+    except OSError:
+        return
+    try:
+        os.fsync(fd)
+    finally:
+        os.close(fd)
+
+
+def read_checkpoint(path):
+    """(n, off, col, w, C) of a checkpoint file; CheckpointError when the
+    file is not a complete checkpoint of this version or its digest fails."""
+    try:
+        with np.load(os.fspath(path), allow_pickle=False) as z:
+            need = ("version", "n", "off", "col", "w", "C", "digest")
+            if any(k not in z.files for k in need):
+                raise CheckpointError(f"{path}: missing arrays")
+            if int(z["version"][0]) != CKPT_VERSION:
+                raise CheckpointError(f"{path}: version {int(z['version'][0])}")
+            n = int(z["n"][0])
+            off, col, w, C = z["off"], z["col"], z["w"], z["C"]
+            digest = z["digest"]
+    except CheckpointError:
+        raise
+    except Exception as e:  # unreadable zip, truncated file, bad array
+        raise CheckpointError(f"{path}: {e}") from e
+    if off.shape != (n + 1,) or C.shape != (n,) or col.shape != w.shape:
+        raise CheckpointError(f"{path}: array shapes do not match n = {n}")
+    if not np.array_equal(digest, _ckpt_digest(n, off, col, w, C)):
+        raise CheckpointError(f"{path}: digest mismatch")
+    return n, off, col, w, C
+
+
+def save_checkpoint(g, path):
+    """Durable checkpoint file of a DynamicCommunities (see write_checkpoint)."""
+    write_checkpoint(path, g.n, *g.export_state())
+
+
+def load_checkpoint(path, **opt):
+    """A DynamicCommunities resumed from a checkpoint file (options as for
+    DynamicCommunities; the state itself is validated again by the library)."""
+    n, off, col, w, C = read_checkpoint(path)
+    return DynamicCommunities.from_state(n, off, col, w, C, **opt)
+
+
 class MLP:
     """The screener network on the GPU (libdc.so's dc_mlp): forward, loss
     gradient and Adam steps over device tensors of bfloat16 feature bits."""

@@ -64,7 +64,7 @@ def _mix(streams, budget, max_inflight, order_seed):
     return out, stats
 
 
-def test_checkpoint_resume_matches_oracle():
+def test_checkpoint_resume_matches_oracle(tmp_path):
     _log("case: checkpoint and resume")
     gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=4)
     (u, v, w), it = gen.stream(3, frac=0.01)
@@ -77,7 +77,9 @@ def test_checkpoint_resume_matches_oracle():
     oo, oc, ow = o.csr()
     assert np.array_equal(off, oo) and np.array_equal(col, oc) and np.array_equal(wt, ow)
     assert np.array_equal(C, o.C)
-    r = dc.DynamicCommunities.from_state(gen.n, off, col, wt, C)
+    # through a checkpoint file
+    dc.save_checkpoint(g, tmp_path / "g.npz")
+    r = dc.load_checkpoint(tmp_path / "g.npz")
     assert r.modularity() == g.modularity()
     for t, b in enumerate(batches[1:]):
         o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
