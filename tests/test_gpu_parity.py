@@ -305,3 +305,24 @@ def test_merge_tile_edges():
         assert np.array_equal(offo, offg), f"batch {t}: row offsets differ"
         assert np.array_equal(colo, colg) and np.array_equal(wo, wg), f"batch {t}: entries differ"
         compare(o, g, f"after batch {t}")
+
+
+@pytest.mark.parametrize("mode", ["delta", "all"])
+def test_empty_batch_and_deleting_every_edge(mode):
+    """Degenerate batches: nothing at all (no change list, nothing to
+    merge), then every edge deleted (G_t left without entries), then edges
+    added back to the empty graph."""
+    _log(f"case: empty and delete-all batches mode={mode}")
+    (u, v, w), _ = W.random_dynamic(40, 90, 1, 1, 1, seed=77)
+    o, g = make_pair(40, u, v, w, mode=mode)
+    compare(o, g, "init")
+    step_batch = lambda *b: (o.apply_batch(*b), g.apply_batch(*b))
+    step_batch([], [], [], [], [])
+    compare(o, g, "empty batch")
+    step_batch([], [], [], list(u), list(v))
+    compare(o, g, "every edge deleted")
+    offo, colo, _ = o.csr()
+    offg, colg, _ = g.csr()
+    assert offg[-1] == 0 and np.array_equal(offo, offg) and len(colg) == len(colo) == 0
+    step_batch(list(u[:30]), list(v[:30]), list(w[:30]), [], [])
+    compare(o, g, "edges added back")
