@@ -1,6 +1,6 @@
 // prims.hip -- scan, stable LSD radix sort, fills.  Hand-written for gfx950:
 // 256-thread blocks of four 64-wide waves, wave prefix sums by shuffles,
-// radix ranking by eight 64-bit ballots per round.
+// radix ranking by one 64-bit ballot per digit bit, running digit counts per wave.
 #include <cstdlib>
 
 #include "dc_common.h"
@@ -217,10 +217,16 @@ __global__ void __launch_bounds__(SCAN_THREADS)
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// Stable scatter: elements are ranked in index order within the tile.  Each
-// round covers 256 consecutive elements; within a wave the rank among equal
-// digits comes from a ballot match (one ballot per digit bit), across waves
-// from per-wave counts of the digits the round holds.
+// Stable scatter: wave w ranks the tile's elements [w * RS_WCHUNK,
+// (w + 1) * RS_WCHUNK) in index order, RS_ROUNDS rounds of WAVE consecutive
+// elements.  Within a round the rank among equal digits comes from a ballot
+// match (one ballot per digit bit); across rounds the wave keeps running
+// digit counts in its own LDS row (the group's first lane adds the group's
+// size and hands the old count to the group), so ranking needs no block
+// barrier.  A scan of each digit's per-wave counts then gives every wave its
+// digit offsets.
+constexpr int RS_WCHUNK = RS_ROUNDS * WAVE;
+static_assert(RS_WCHUNK * RS_WAVES == RS_TILE, "waves cover the tile");
 __global__ void __launch_bounds__(RS_THREADS)
     k_radix_scatter(const uint64_t* __restrict__ kin,
                     const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
@@ -260,56 +266,56 @@ __global__ void __launch_bounds__(RS_THREADS)
   __syncthreads();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   const uint64_t mask = uint64_t(bins - 1);
-  const int64_t tile = int64_t(blockIdx.x) * RS_TILE;
-  // the tile's keys and values, all rounds loaded before the first is ranked
+  const int64_t wbase = int64_t(blockIdx.x) * RS_TILE + int64_t(wid) * RS_WCHUNK;
+  // the wave's keys and values, all rounds loaded before the first is ranked
   uint64_t kr[RS_ROUNDS];
   uint32_t vr[RS_ROUNDS];
+  int32_t rk[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t idx = tile + int64_t(r) * RS_THREADS + t;
+    const int64_t idx = wbase + int64_t(r) * WAVE + lane;
     kr[r] = idx < n ? kin[idx] : 0;
     vr[r] = idx < n ? vin[idx] : 0;
   }
+  int32_t* own = wcnt[wid];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t idx = tile + int64_t(r) * RS_THREADS + t;
-    const bool valid = idx < n;
-    const uint64_t key = kr[r];
-    const uint32_t val = vr[r];
-    const int d = int((key >> shift) & mask);
+    const bool valid = wbase + int64_t(r) * WAVE + lane < n;
+    const int d = int((kr[r] >> shift) & mask);
     uint64_t m = __ballot(valid);
     for (int b = 0; b < dbits; ++b) {
       const bool bit = (d >> b) & 1;
       const uint64_t bb = __ballot(valid && bit);
       m &= bit ? bb : ~bb;
     }
-    const int rank = __popcll(m & lt);
-    const bool leader = valid && rank == 0;
-    if (leader) wcnt[wid][d] = __popcll(m);
-    __syncthreads();
-    int pos = 0;
-    if (valid) {
-      pos = base_d[d] + rank;
-      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    // advance the bases of the digits this round held (by their leaders in
-    // wave 0 order: a digit's first holder over all waves adds the total)
-    if (leader) {
-      bool first = true;
-      for (int w = 0; w < wid; ++w) first = first && wcnt[w][d] == 0;
-      if (first) {
-        int add = 0;
+    // m holds this lane's digit group when valid (it is then nonzero)
+    const int first = valid ? __ffsll((unsigned long long)m) - 1 : lane;
+    int32_t old = 0;
+    if (valid && first == lane) old = atomicAdd(&own[d], __popcll(m));
+    old = __shfl(old, first);
+    rk[r] = old + __popcll(m & lt);
+  }
+  __syncthreads();
+  // per digit: the waves' counts become their exclusive prefix on top of
+  // the digit's base in this tile
+  for (int b = t; b < bins; b += RS_THREADS) {
+    int32_t run = base_d[b];
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) add += wcnt[w][d];
-        base_d[d] += add;
-      }
+    for (int w = 0; w < RS_WAVES; ++w) {
+      const int32_t c = wcnt[w][b];
+      wcnt[w][b] = run;
+      run += c;
     }
-    __syncthreads();
-    if (leader) wcnt[wid][d] = 0;
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    if (wbase + int64_t(r) * WAVE + lane < n) {
+      const int d = int((kr[r] >> shift) & mask);
+      const int32_t pos = own[d] + rk[r];
+      kout[pos] = kr[r];
+      vout[pos] = vr[r];
+    }
   }
 }
 
