@@ -105,7 +105,8 @@ void read_stat(dc_ctx* c) {
 // level stops (no move, a reverted sweep, a gain of at most T, or the sweep
 // limit).  timed_ms >= 0: device time of the timed launch of this sweep.
 bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& bins,
-                   long long T, bool record, float timed_ms, long long& level_gain) {
+                   long long T, bool record, float timed_ms, long long& level_gain,
+                   int64_t n_active = -1) {
   const long long moves = c->hstat[ST_MOVES], dN = c->hstat[ST_DN];
   if (record) {
     dc_step_stats& S = c->stats;
@@ -127,7 +128,7 @@ bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& 
     r.level = level;
     r.sweep = s;
     r.n_level = g.n;
-    r.n_active = int32_t(n_eval);
+    r.n_active = int32_t(n_active >= 0 ? n_active : n_eval);
     r.nnz_level = g.nnz;
     r.moves = moves;
     r.dN = dN;
@@ -148,12 +149,17 @@ bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& 
 
 // Synchronous sweeps of one level over the binned active set (Alg. 1 inner
 // loop); returns the level's total exact gain.  record: trace records,
-// statistics and timing of the call.
+// statistics and timing of the call.  pre_done: the first sweep evaluates
+// only the first parts of the bins (the active vertices whose first-sweep
+// labels are already in Cn are binned last); later sweeps take whole bins.
 long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t nact,
-                     const Bins& bins, int level, long long T, bool record) {
+                     const Bins& all_bins, int level, long long T, bool record,
+                     bool pre_done = false) {
   hipStream_t st = c->st;
   long long level_gain = 0;
+  Bins bins = pre_done ? first_part(all_bins) : all_bins;
   for (int s = 0; s < c->opt.max_sweeps; ++s) {
+    if (s == 1) bins = all_bins;
     sweep_reset(c->stat.as<long long>(), st);
     const bool timed = record && c->opt.timing && bins.n[TIMED_BIN] > 0;
     sweep_eval(g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
@@ -167,7 +173,7 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
     read_stat(c);
     float ms = -1.f;
     if (timed) DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    if (sweep_account(c, g, level, s, bins, T, record, ms, level_gain)) break;
+    if (sweep_account(c, g, level, s, bins, T, record, ms, level_gain, nact)) break;
   }
   return level_gain;
 }
@@ -178,7 +184,9 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
 // prepared; levels_finish coarsens, runs the upper levels and writes the
 // canonical labels, the totals and N.
 
-void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& L) {
+void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& L,
+                  const uint8_t* skip) {
+  c->pre_count = 0;  // the screening's first-sweep labels serve run_levels only
   const long long two_m = c->two_m;
   L.T = c->opt.tau_den > 0 ? (two_m * two_m) / c->opt.tau_den : 0;
   L.g = LevelView{c->n, c->nnz, c->off[c->cur].as<int32_t>(), c->adj[c->cur].as<int2>(),
@@ -186,7 +194,7 @@ void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& 
   L.act = active;
   L.nact = n_active;
   c->trace.clear();
-  make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st);
+  make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st, skip);
 }
 
 void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
@@ -253,8 +261,18 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
 // partition is (Cl, al, szl), prepared by the caller.
 void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
   LevelRun L;
-  levels_begin(c, active, n_active, L);
-  const long long gain0 = run_sweeps(c, L.g, L.act, L.nact, L.bins, 0, L.T, true);
+  // Screening evaluated its vertices on the state the first level-0 sweep
+  // reads (labels C_{t-1}, totals and sizes on G_t): their decisions go
+  // into Cn and the first sweep evaluates only the rest of R_t.
+  const int64_t npre = active ? c->pre_count : 0;
+  const uint8_t* skip = nullptr;
+  if (npre > 0) {
+    apply_pre(c->ulist.as<int32_t>(), npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(),
+              c->Cn.as<int32_t>(), c->st);
+    skip = c->uflag.as<uint8_t>();
+  }
+  levels_begin(c, active, n_active, L, skip);
+  const long long gain0 = run_sweeps(c, L.g, L.act, L.nact, L.bins, 0, L.T, true, npre > 0);
   levels_finish(c, L, gain0);
 }
 
@@ -406,6 +424,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   long long* stat = c->stat.as<long long>();
   long long* hs = c->hstat;
   DC_HIP(hipMemsetAsync(stat, 0, ST_COUNT * 8, st));
+  c->pre_count = 0;
   const int32_t *au, *av, *aw, *du, *dv, *dw;
   stage_edges(c, add, true, c->in_au, c->in_av, c->in_aw, &au, &av, &aw);
   stage_edges(c, del, false, c->in_du, c->in_dv, c->in_aw, &du, &dv, &dw);
@@ -555,9 +574,15 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       if (n_u > 0) {
         Bins b;
         make_bins(c->ulist.as<int32_t>(), n_u, g0.off, b, c->bins, st);
-        ds_both(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
-                c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), uflag, b, R, cflag, accflag,
-                stat, st);
+        int32_t* pre = nullptr;
+        if (mode == DC_MODE_DELTA) {
+          c->pre.ensure(size_t(n) * 4);
+          pre = c->pre.as<int32_t>();
+        }
+        ds_both(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->sz0.as<int32_t>(),
+                c->opt.singleton_guard, c->two_m, ins_keys, n_ins, c->seg_beg.as<int32_t>(),
+                c->seg_end.as<int32_t>(), uflag, b, R, cflag, accflag, pre, stat, st);
+        c->pre_count = pre ? n_u : 0;
       }
     } else {
       int32_t* dpos = c->dpos.as<int32_t>();
@@ -732,7 +757,7 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->ch_dk, &c->dnet, &c->cnet, &c->cptr, &c->new_deg, &c->tile_row, &c->ins_flag, &c->ins_pos, &c->ins_keys, &c->src_flag,
                   &c->src_pos, &c->src_list, &c->dflag, &c->dpos, &c->dlist, &c->R, &c->cflag,
                   &c->rflag, &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end, &c->chsrc,
-                  &c->accflag, &c->cascand, &c->clist, &c->uflag, &c->ulist,
+                  &c->accflag, &c->cascand, &c->clist, &c->uflag, &c->ulist, &c->pre,
                   &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
                   &c->f_g1, &c->f_g2, &c->X, &c->y, &c->logits, &c->Cl, &c->Cn, &c->al,
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],

@@ -30,6 +30,8 @@ struct dc_ctx {
   DBuf R, cflag, rflag, rpos2, Rlist, seg_beg, seg_end, chsrc;
   DBuf accflag, cascand, clist;  // cascade-aware screening
   DBuf uflag, ulist;             // union of insertion sources and deletion endpoints
+  DBuf pre;                      // first-sweep labels taken by the screening pass
+  int64_t pre_count = 0;         // ulist entries that hold them (0: none)
   // learned screener: touched set, features, labels, scores
   DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
   bool have_scr = false;
@@ -87,7 +89,8 @@ struct MergeScratch {
 
 dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const int32_t** act,
                       int64_t* nact);
-void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& L);
+void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& L,
+                  const uint8_t* skip = nullptr);
 void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain);
 void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device);
 // Level-0 sweeps of m contexts sharing one stream, merged per round: the

@@ -102,6 +102,7 @@ struct EvalArgs {
   uint8_t* cflag;
   uint8_t* accflag;  // EV_DSADD: accepted sources flagged here (null: not kept)
   const uint8_t* uflag;  // EV_DSBOTH: bit 0 insertion source, bit 1 deletion endpoint
+  int32_t* pre;  // EV_DSBOTH (may be null): each evaluated vertex's first-sweep label
   int32_t* f_own;  // EV_FEAT outputs, indexed by vertex
   long long* f_g1;
   long long* f_g2;
@@ -113,6 +114,11 @@ struct Bins {
   const int32_t* list_rb[NBINS];  // row start (off[v]) of each listed vertex
   long long vol[NBINS];       // adjacency entries of each bin
   const int32_t* count_dev;   // NBINS device counts
+  // each bin's list starts with the vertices that make_bins' skip flags
+  // leave unset: their number, volume and device counts
+  int64_t n_first[NBINS];
+  long long vol_first[NBINS];
+  const int32_t* count_first_dev;
   int* gkeys;
   int* gvals;
   const long long* tab_off;
@@ -126,6 +132,17 @@ struct Bins {
   hipEvent_t join;
 };
 
+// The bins restricted to their first parts (the vertices not skipped).
+inline Bins first_part(const Bins& b) {
+  Bins f = b;
+  for (int q = 0; q < NBINS; ++q) {
+    f.n[q] = b.n_first[q];
+    f.vol[q] = b.vol_first[q];
+  }
+  f.count_dev = b.count_first_dev;
+  return f;
+}
+
 struct BinScratch {
   DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf, defer;
   void* host = nullptr;  // pinned, 256 bytes
@@ -136,8 +153,10 @@ struct BinScratch {
 
 // Splits a vertex list (null = all of [0, count)) into the row-length bins,
 // keeping list order within a bin; synchronises to read the bin sizes.
+// skip (may be null): vertices v with skip[v] != 0 go to the end of their
+// bin, after the first part (first_part gives the bins without them).
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
-               hipStream_t st);
+               hipStream_t st, const uint8_t* skip = nullptr);
 
 void sweep_reset(long long* stat, hipStream_t st);
 void sweep_reset(long long* stat, hipStream_t st);
@@ -166,10 +185,14 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
 // bit 1 a deletion endpoint (the deletion rule, extension: a move with a
 // positive gain adds the endpoint, its neighbours and the members of its best
 // community).  Same effect as running the two screenings one after the other.
-void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
-             const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
-             const int32_t* seg_end, const uint8_t* uflag, const Bins& bins, uint8_t* R,
-             uint8_t* cflag, uint8_t* accflag, long long* stat, hipStream_t st);
+// pre (may be null): every listed vertex's decision of the first level-0
+// sweep from the same state (labels C, totals a, sizes sz, singleton guard
+// as guard): the best community if it moves, else its own label.
+void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
+             int32_t guard, long long two_m, const uint64_t* ins_keys, int64_t n_ins,
+             const int32_t* seg_beg, const int32_t* seg_end, const uint8_t* uflag,
+             const Bins& bins, uint8_t* R, uint8_t* cflag, uint8_t* accflag, int32_t* pre,
+             long long* stat, hipStream_t st);
 // uflag[v] |= 1 for v in list[0, *count) (count on the device); then
 // uflag[v] |= 2 where dflag[v] != 0, flag[v] = uflag[v] != 0, and
 // *ndel += the number of such v.
@@ -250,6 +273,10 @@ void mark_neighbourhoods(const int32_t* list, int64_t cnt, const int32_t* off, c
 // R[v] |= cflag[C[v]]; rflag[v] = R[v].
 void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n,
                    int32_t* rflag, hipStream_t st);
+// Cn[v] = pre[v] for every listed v with R[v] != 0: the first sweep's
+// decisions that the screening pass already took.
+void apply_pre(const int32_t* list, int64_t cnt, const uint8_t* R, const int32_t* pre,
+               int32_t* Cn, hipStream_t st);
 
 // ---- coarsen.hip ----
 struct CoarsenScratch {

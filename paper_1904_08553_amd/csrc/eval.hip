@@ -258,6 +258,13 @@ __device__ __forceinline__ void sweep_commit(const EvalArgs& A, int i, bool move
   }
 }
 
+// The same decision kept for the first level-0 sweep (EV_DSBOTH with pre):
+// the label it would write, or the vertex's own label when it stays.
+__device__ __forceinline__ void pre_commit(const EvalArgs& A, int i, bool move, int c, int x) {
+  const bool held = move && A.guard && A.sz[c] == 1 && A.sz[x] == 1 && x > c;
+  A.pre[i] = move && !held ? x : c;
+}
+
 // One item of a group kernel: group (lane / GS) of the wave evaluates vertex
 // i (have = false: no vertex, the lanes still take part in the wave-wide
 // steps).  Returns the screening tests this group accepted (0 or 1).
@@ -348,6 +355,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   if (pair && ck != c) b = {(long long)tm * cs - (long long)int(ki) * A.a[ck], ck};
   b = group_best_w<GS>(b);
   bool move = have && b.x != NO_LABEL && b.s > s_own;
+  if (MODE == EV_DSBOTH && A.pre && have && gl == 0) pre_commit(A, i, move, c, b.x);
   if (MODE == EV_SWEEP) {
     sweep_commit(A, i, move, c, b.x, gl);
   } else if (move && (uf & 2)) {  // EV_DSDEL, EV_DSBOTH
@@ -679,7 +687,7 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
     }
     group_sync<G>();  // the table is reused (by the deletion rule or the next item)
   }
-  if (MODE == EV_DSADD || (MODE == EV_DSBOTH && !(uf & 2))) return accepted;
+  if (MODE == EV_DSADD || (MODE == EV_DSBOTH && !(uf & 2) && !A.pre)) return accepted;
   Best b = table_best<G, US>(A, keys, vals, mask, ki, EMPTY_KEY, t);
   b = group_best<G>(b, L);
   group_sync<G>();
@@ -697,10 +705,11 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
     return 0;
   }
   bool move = b.x != NO_LABEL && b.s > s_own;
+  if (MODE == EV_DSBOTH && A.pre && t == 0) pre_commit(A, i, move, c, b.x);
   if (MODE == EV_SWEEP) {
     if (move && A.guard && A.sz[c] == 1 && A.sz[b.x] == 1 && b.x > c) move = false;
     if (move && t == 0) A.Cn[i] = b.x;
-  } else if (move) {  // EV_DSDEL, EV_DSBOTH
+  } else if (move && (MODE != EV_DSBOTH || (uf & 2))) {  // EV_DSDEL, EV_DSBOTH
     for (int32_t q = rb + t; q < re; q += G) A.R[A.adj[q].x] = 1;
     if (t == 0) {
       A.R[i] = 1;
@@ -914,32 +923,38 @@ __device__ __forceinline__ int bin_of(int d) {
   return d <= 16 ? 0 : d <= 32 ? 1 : d <= 64 ? 2 : d <= WTAB_MAX ? 3 : d <= BTAB_MAX ? 4 : 5;
 }
 
+// Rows of the binning: bin q of a vertex v is split into row 2q (evaluated
+// by every sweep) and row 2q + 1 (skip[v] != 0: left out of the first
+// sweep), so that each bin's list holds its first-sweep vertices first.
+constexpr int NROWS = 2 * NBINS;
+
 __global__ void __launch_bounds__(TPB)
     k_bin_count(const int32_t* __restrict__ list, int64_t cnt, const int32_t* __restrict__ off,
-                int32_t* bcnt, long long* vol, int64_t nblocks) {
-  __shared__ int c[NBINS];
-  __shared__ long long v[NBINS];
-  if (threadIdx.x < NBINS) {
+                const uint8_t* __restrict__ skip, int32_t* bcnt, long long* vol,
+                int64_t nblocks) {
+  __shared__ int c[NROWS];
+  __shared__ long long v[NROWS];
+  if (threadIdx.x < NROWS) {
     c[threadIdx.x] = 0;
     v[threadIdx.x] = 0;
   }
   __syncthreads();
-  int lc[NBINS];
-  long long lv[NBINS];
+  int lc[NROWS];
+  long long lv[NROWS];
 #pragma unroll
-  for (int q = 0; q < NBINS; ++q) {
+  for (int q = 0; q < NROWS; ++q) {
     lc[q] = 0;
     lv[q] = 0;
   }
   for (int r = 0; r < BIN_ITEMS; ++r) {
     int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
     if (p < cnt) {
-      int u = list ? list[p] : int(p);
-      int d = off[u + 1] - off[u];
-      int b = bin_of(d);
+      const int u = list ? list[p] : int(p);
+      const int d = off[u + 1] - off[u];
+      const int row = 2 * bin_of(d) + (skip && skip[u] ? 1 : 0);
 #pragma unroll
-      for (int q = 0; q < NBINS; ++q) {
-        if (b == q) {
+      for (int q = 0; q < NROWS; ++q) {
+        if (row == q) {
           lc[q]++;
           lv[q] += d;
         }
@@ -947,7 +962,7 @@ __global__ void __launch_bounds__(TPB)
     }
   }
 #pragma unroll
-  for (int b = 0; b < NBINS; ++b) {
+  for (int b = 0; b < NROWS; ++b) {
     int x = wave_sum(lc[b]);
     long long y = wave_sum(lv[b]);
     if (lane_id() == 0) {
@@ -956,50 +971,51 @@ __global__ void __launch_bounds__(TPB)
     }
   }
   __syncthreads();
-  if (threadIdx.x < NBINS) {
+  if (threadIdx.x < NROWS) {
     bcnt[int64_t(threadIdx.x) * nblocks + blockIdx.x] = c[threadIdx.x];
     if (v[threadIdx.x])
       atomicAdd((unsigned long long*)&vol[threadIdx.x], (unsigned long long)v[threadIdx.x]);
   }
 }
 
-// out[boff[b][block] + rank] = vertex: bins are contiguous segments of out,
-// in list order within each bin
+// out[boff[row][block] + rank] = vertex: rows are contiguous segments of
+// out, in list order within each row
 __global__ void __launch_bounds__(TPB)
     k_bin_scatter(const int32_t* __restrict__ list, int64_t cnt,
-                  const int32_t* __restrict__ off, const int32_t* __restrict__ boff,
-                  int64_t nblocks, int32_t* out, int32_t* out_rb) {
-  __shared__ int base[NBINS];
-  __shared__ int wc[NW][NBINS];
+                  const int32_t* __restrict__ off, const uint8_t* __restrict__ skip,
+                  const int32_t* __restrict__ boff, int64_t nblocks, int32_t* out,
+                  int32_t* out_rb) {
+  __shared__ int base[NROWS];
+  __shared__ int wc[NW][NROWS];
   const int wid = threadIdx.x / WAVE, lane = lane_id();
-  if (threadIdx.x < NBINS) base[threadIdx.x] = boff[int64_t(threadIdx.x) * nblocks + blockIdx.x];
+  if (threadIdx.x < NROWS) base[threadIdx.x] = boff[int64_t(threadIdx.x) * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   for (int r = 0; r < BIN_ITEMS; ++r) {
     int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
     const bool valid = p < cnt;
-    int u = 0, b = -1, rb = 0;
+    int u = 0, row = -1, rb = 0;
     if (valid) {
       u = list ? list[p] : int(p);
       rb = off[u];
-      b = bin_of(off[u + 1] - rb);
+      row = 2 * bin_of(off[u + 1] - rb) + (skip && skip[u] ? 1 : 0);
     }
     int rank = 0;
 #pragma unroll
-    for (int q = 0; q < NBINS; ++q) {
-      uint64_t m = __ballot(b == q);
+    for (int q = 0; q < NROWS; ++q) {
+      uint64_t m = __ballot(row == q);
       if (lane == 0) wc[wid][q] = __popcll(m);
-      if (b == q) rank = __popcll(m & lt);
+      if (row == q) rank = __popcll(m & lt);
     }
     __syncthreads();
     if (valid) {
-      int pos = base[b] + rank;
-      for (int w = 0; w < wid; ++w) pos += wc[w][b];
+      int pos = base[row] + rank;
+      for (int w = 0; w < wid; ++w) pos += wc[w][row];
       out[pos] = u;
       out_rb[pos] = rb;
     }
     __syncthreads();
-    if (threadIdx.x < NBINS) {
+    if (threadIdx.x < NROWS) {
       int add = 0;
       for (int w = 0; w < NW; ++w) add += wc[w][threadIdx.x];
       base[threadIdx.x] += add;
@@ -1008,18 +1024,21 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
-__global__ void k_bin_starts(const int32_t* boff, int64_t nblocks, int64_t total_entries,
-                             const int32_t* total, int32_t* bin_start, int32_t* counts) {
-  // boff is the exclusive scan of bcnt laid out bin-major: bin b starts at
-  // boff[b * nblocks]
+// Bin q starts at its row 2q; counts[q] = its size, counts[NBINS + q] = the
+// size of its first part (row 2q).
+__global__ void k_bin_starts(const int32_t* boff, int64_t nblocks, const int32_t* total,
+                             int32_t* bin_start, int32_t* counts) {
+  // boff is the exclusive scan of bcnt laid out row-major: row r starts at
+  // boff[r * nblocks]
   if (threadIdx.x < NBINS) {
-    int b = threadIdx.x;
-    int s = boff[int64_t(b) * nblocks];
-    int e = (b + 1 < NBINS) ? boff[int64_t(b + 1) * nblocks] : *total;
-    bin_start[b] = s;
-    counts[b] = e - s;
+    const int q = threadIdx.x;
+    const int s0 = boff[int64_t(2 * q) * nblocks];
+    const int s1 = boff[int64_t(2 * q + 1) * nblocks];
+    const int e = (q + 1 < NBINS) ? boff[int64_t(2 * q + 2) * nblocks] : *total;
+    bin_start[q] = s0;
+    counts[q] = e - s0;
+    counts[NBINS + q] = s1 - s0;
   }
-  (void)total_entries;
 }
 
 __global__ void k_table_caps(const int32_t* __restrict__ list, const int32_t* __restrict__ off,
@@ -1159,29 +1178,32 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
 }  // namespace
 
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
-               hipStream_t st) {
+               hipStream_t st, const uint8_t* skip) {
   const int64_t nb = count > 0 ? ceil_div(count, BIN_TILE) : 1;
   const int64_t cap = count > 0 ? count : 1;
   s.lists.ensure(size_t(cap) * sizeof(int32_t));
   s.lists_rb.ensure(size_t(cap) * sizeof(int32_t));
-  s.bcnt.ensure(size_t(NBINS * nb + 1) * sizeof(int32_t));
-  s.boff.ensure(size_t(NBINS * nb + 1) * sizeof(int32_t));
-  constexpr size_t META = 32 * sizeof(int32_t) + NBINS * sizeof(long long);
+  s.bcnt.ensure(size_t(NROWS * nb + 1) * sizeof(int32_t));
+  s.boff.ensure(size_t(NROWS * nb + 1) * sizeof(int32_t));
+  // int32 slots: [0, NBINS) bin sizes, [NBINS, 2 NBINS) first-part sizes,
+  // [2 NBINS, 3 NBINS) bin starts, [3 NBINS] total, then the overflow count,
+  // the finished blocks and the deferred count; NROWS row volumes (int64)
+  // from slot 32 on
+  constexpr int M_START = 2 * NBINS, M_TOTAL = 3 * NBINS, M_OVF = 3 * NBINS + 1;
+  constexpr size_t META = 32 * sizeof(int32_t) + NROWS * sizeof(long long);
+  static_assert(M_OVF + 3 <= 32, "bin metadata slots overlap the volumes");
   static_assert(META <= 256, "bin metadata must fit the pinned host buffer");
   s.counts.ensure(META);
-  // [0, NBINS) counts, [NBINS, 2 NBINS) starts, [2 NBINS] total, [16, 19)
-  // overflow count, finished blocks, deferred count
   int32_t* counts = s.counts.as<int32_t>();
   long long* vol = reinterpret_cast<long long*>(counts + 32);
   int32_t* bcnt = s.bcnt.as<int32_t>();
   int32_t* boff = s.boff.as<int32_t>();
   DC_HIP(hipMemsetAsync(counts, 0, META, st));
   if (count > 0) {
-    k_bin_count<<<nb, TPB, 0, st>>>(list, count, off, bcnt, vol, nb);
+    k_bin_count<<<nb, TPB, 0, st>>>(list, count, off, skip, bcnt, vol, nb);
     DC_LAUNCH_CHECK();
-    scan_excl_i32(bcnt, boff, NBINS * nb, counts + 2 * NBINS, st);
-    k_bin_starts<<<1, 64, 0, st>>>(boff, nb, NBINS * nb, counts + 2 * NBINS, counts + NBINS,
-                                   counts);
+    scan_excl_i32(bcnt, boff, NROWS * nb, counts + M_TOTAL, st);
+    k_bin_starts<<<1, 64, 0, st>>>(boff, nb, counts + M_TOTAL, counts + M_START, counts);
     DC_LAUNCH_CHECK();
   }
   DC_HIP(hipMemcpyAsync(s.host, counts, META, hipMemcpyDeviceToHost, st));
@@ -1192,22 +1214,25 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   int32_t* lists_rb = s.lists_rb.as<int32_t>();
   for (int q = 0; q < NBINS; ++q) {
     b.n[q] = hc[q];
-    b.list[q] = lists + hc[NBINS + q];
-    b.list_rb[q] = lists_rb + hc[NBINS + q];
-    b.vol[q] = hv[q];
+    b.n_first[q] = hc[NBINS + q];
+    b.list[q] = lists + hc[M_START + q];
+    b.list_rb[q] = lists_rb + hc[M_START + q];
+    b.vol[q] = hv[2 * q] + hv[2 * q + 1];
+    b.vol_first[q] = hv[2 * q];
   }
   b.count_dev = counts;
+  b.count_first_dev = counts + NBINS;
   // overflow list of bins W and B; its count and finished-block counter sit
   // in the zeroed metadata and are cleared again by each k_eval_ovf
   s.ovf.ensure(size_t(cap) * sizeof(int32_t));
   b.ovf_list = s.ovf.as<int32_t>();
-  b.ovf_count = counts + 16;
-  b.ovf_done = counts + 17;
+  b.ovf_count = counts + M_OVF;
+  b.ovf_done = counts + M_OVF + 1;
   // deferred gain2 walks of the short-row bins: at most one per listed vertex;
   // the count is cleared with the metadata, so one Alg. 2 pass per binning
   s.defer.ensure(size_t(cap) * sizeof(DeferItem));
   b.defer = reinterpret_cast<DeferItem*>(s.defer.p);
-  b.defer_count = counts + 18;
+  b.defer_count = counts + M_OVF + 2;
   b.side = s.side;
   b.fork = s.fork;
   b.join = s.join;
@@ -1215,7 +1240,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.gvals = nullptr;
   b.tab_off = nullptr;
   if (count > 0) {
-    k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, boff, nb, lists, lists_rb);
+    k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, skip, boff, nb, lists, lists_rb);
     DC_LAUNCH_CHECK();
   }
   constexpr int G = NBINS - 1;
@@ -1226,7 +1251,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
     DC_LAUNCH_CHECK();
     scan_excl_i64(reinterpret_cast<int64_t*>(caps), reinterpret_cast<int64_t*>(caps), b.n[G],
                   reinterpret_cast<int64_t*>(caps + b.n[G]), st);
-    const size_t slots = size_t(4 * hv[G] + 2 * b.n[G] + 16);
+    const size_t slots = size_t(4 * b.vol[G] + 2 * b.n[G] + 16);
     s.gkeys.ensure(slots * sizeof(int));
     s.gvals.ensure(slots * sizeof(int));
     b.gkeys = s.gkeys.as<int>();
@@ -1278,11 +1303,15 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
   launch_eval<EV_DSADD>(A, bins, st, nullptr, nullptr);
 }
 
-void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
-             const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
-             const int32_t* seg_end, const uint8_t* uflag, const Bins& bins, uint8_t* R,
-             uint8_t* cflag, uint8_t* accflag, long long* stat, hipStream_t st) {
+void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
+             int32_t guard, long long two_m, const uint64_t* ins_keys, int64_t n_ins,
+             const int32_t* seg_beg, const int32_t* seg_end, const uint8_t* uflag,
+             const Bins& bins, uint8_t* R, uint8_t* cflag, uint8_t* accflag, int32_t* pre,
+             long long* stat, hipStream_t st) {
   EvalArgs A{};
+  A.sz = sz;
+  A.guard = guard;
+  A.pre = pre;
   A.off = g.off;
   A.nnz = g.nnz;
   A.adj = g.adj;

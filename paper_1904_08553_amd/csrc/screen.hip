@@ -102,6 +102,15 @@ __global__ void k_materialize_R(uint8_t* R, const uint8_t* __restrict__ cflag,
   }
 }
 
+__global__ void k_apply_pre(const int32_t* __restrict__ list, int64_t cnt,
+                            const uint8_t* __restrict__ R, const int32_t* __restrict__ pre,
+                            int32_t* __restrict__ Cn) {
+  GRID_STRIDE(p, cnt) {
+    const int32_t v = list[p];
+    if (R[v]) Cn[v] = pre[v];
+  }
+}
+
 }  // namespace
 
 // Cascade-aware screening (an extension for the indirect effect noted after
@@ -232,6 +241,13 @@ void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n
                    int32_t* rflag, hipStream_t st) {
   if (n <= 0) return;
   k_materialize_R<<<grid_for(n), TPB, 0, st>>>(R, cflag, C, n, rflag);
+  DC_LAUNCH_CHECK();
+}
+
+void apply_pre(const int32_t* list, int64_t cnt, const uint8_t* R, const int32_t* pre,
+               int32_t* Cn, hipStream_t st) {
+  if (cnt <= 0) return;
+  k_apply_pre<<<grid_for(cnt), TPB, 0, st>>>(list, cnt, R, pre, Cn);
   DC_LAUNCH_CHECK();
 }
 
