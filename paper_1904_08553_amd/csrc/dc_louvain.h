@@ -158,7 +158,7 @@ struct BinScratch {
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
                hipStream_t st, const uint8_t* skip = nullptr);
 
-void sweep_reset(long long* stat, hipStream_t st);
+// Clears the per-sweep counters of the status block.
 void sweep_reset(long long* stat, hipStream_t st);
 // Writes the next label of every active vertex that moves.  ev0/ev1 (may be
 // null) bracket the launch of bin TIMED_BIN (rows of 17 to 32 entries, two
