@@ -326,3 +326,42 @@ def test_empty_batch_and_deleting_every_edge(mode):
     assert offg[-1] == 0 and np.array_equal(offo, offg) and len(colg) == len(colo) == 0
     step_batch(list(u[:30]), list(v[:30]), list(w[:30]), [], [])
     compare(o, g, "edges added back")
+
+
+@pytest.mark.parametrize("mode", ["delta", "all"])
+def test_weights_near_the_2m_limit(mode):
+    """Weights of 2^21..2^22 and one edge that brings 2m to 2^31 - 2, the
+    largest total the int64 gains allow (products of 2m and e near 2^62);
+    one more unit of weight is refused on both sides, state unchanged."""
+    from paper_1904_08553_amd.dc import DCError
+    _log(f"case: weights near the 2m limit mode={mode}")
+    (u, v, w), batches = W.random_dynamic(60, 200, 3, 30, 20, seed=5, wmax=2 ** 22)
+    w = np.maximum(w, 2 ** 21).astype(np.int32)
+    o, g = make_pair(60, u, v, w, mode=mode)
+    compare(o, g, "init")
+    for t, b in enumerate(batches):
+        b.add_w[:] = np.maximum(b.add_w, 2 ** 21)
+        step_pair(o, g, b)
+        compare(o, g, f"step {t}")
+    two_m = o.modularity()[2]
+    off, col, _ = o.csr()
+    a, b = next((a, b) for a in range(60) for b in range(a + 1, 60)
+                if b not in col[off[a]:off[a + 1]])
+    heavy = (2 ** 31 - 2 - two_m) // 2
+    assert 1 <= heavy < 2 ** 31
+    step_pair(o, g, W.Batch(np.array([a], np.int32), np.array([b], np.int32),
+                            np.array([heavy], np.int32), np.empty(0, np.int32),
+                            np.empty(0, np.int32)))
+    compare(o, g, "2m = 2^31 - 2")
+    assert g.modularity()[2] == 2 ** 31 - 2
+    C0, q0 = g.communities().copy(), g.modularity()
+    c, d = next((c, d) for c in range(60) for d in range(c + 1, 60)
+                if (c, d) != (a, b) and d not in col[off[c]:off[c + 1]])
+    with pytest.raises(DCError) as e:
+        g.apply_batch([c], [d], [1])
+    assert e.value.status == -7
+    with pytest.raises(O.OracleError) as eo:
+        o.apply_batch([c], [d], [1])
+    assert eo.value.status == -7
+    assert np.array_equal(g.communities(), C0) and g.modularity() == q0
+    assert np.array_equal(o.C, C0) and o.modularity()[1:] == q0[1:]
