@@ -85,6 +85,21 @@ def test_modularity_brute_force(oracle_mod, seed, n, selfloops):
     assert Q_of(N, tm) <= best
 
 
+@pytest.mark.parametrize("seed", [11, 12])
+def test_modularity_brute_force_heavy_weights(oracle_mod, seed):
+    """Weights up to 2^25 (2m close to 2^31, numerators near 2^61): the exact
+    int64 numerator still equals Eq. (1) in rationals for every partition."""
+    rng = np.random.default_rng(seed)
+    adj = rand_adj(rng, 7, 0.5, wmax=2 ** 25)
+    off, col, w = csr_from_adj(adj)
+    assert int(w.sum()) < 2 ** 31
+    for part in set_partitions(7):
+        C = np.array(part, np.int32)
+        N, tm = oracle_mod.csr_modularity(off, col, w, C)
+        assert tm == int(w.sum())
+        assert Q_of(N, tm) == L.modularity(adj, {i: part[i] for i in range(7)})
+
+
 def test_modularity_closed_forms(oracle_mod):
     # two disjoint cliques K5, each its own community: Q = 1/2
     adj = {i: {} for i in range(10)}
@@ -115,12 +130,14 @@ def test_modularity_closed_forms(oracle_mod):
 # gain
 
 
+@pytest.mark.parametrize("wmax", [4, 2 ** 24])
 @pytest.mark.parametrize("seed", range(6))
-def test_gain_is_half_exact_delta_N(oracle_mod, seed):
+def test_gain_is_half_exact_delta_N(oracle_mod, seed, wmax):
     rng = np.random.default_rng(100 + seed)
     n = 9
-    adj = rand_adj(rng, n, 0.4, selfloops=(seed % 2 == 1))
+    adj = rand_adj(rng, n, 0.4, wmax=wmax, selfloops=(seed % 2 == 1))
     off, col, w = csr_from_adj(adj)
+    assert int(w.sum()) < 2 ** 31
     for _ in range(40):
         C = rng.integers(0, 4, n).astype(np.int32)
         i = int(rng.integers(n))
