@@ -8,6 +8,7 @@
 // host waits only where a size or a convergence decision is needed.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -764,6 +765,7 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,
                   &c->cg[0].off, &c->cg[0].adj, &c->cg[0].k, &c->cg[1].off, &c->cg[1].adj,
                   &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf, &c->bins.defer,
+                  &c->bins.dkeys, &c->bins.dvals, &c->bins.dflag, &c->bins.dpos, &c->bins.dseg,
                   &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
                   &c->bins.tab_off, &c->bins.gkeys, &c->bins.gvals, &c->cs.flag, &c->cs.rank,
                   &c->cs.keys0, &c->cs.keys1, &c->cs.vals0, &c->cs.vals1, &c->cs.cntr,
@@ -900,6 +902,10 @@ dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) 
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
     DC_HIP(hipHostMalloc(&c->hbuf, 64));
     DC_HIP(hipHostMalloc(&c->bins.host, 256));
+    std::memset(c->bins.host, 0, 256);  // no deferred walks seen yet
+    // walks deferred by the previous Alg. 2 pass from which they are grouped
+    // by j* (a setting for tests: 0 always groups them)
+    if (const char* e = std::getenv("DC_DEFER_GROUP_MIN")) c->bins.group_min = std::atoll(e);
     DC_HIP(hipHostMalloc(&c->cs.host, 64));
     DC_HIP(hipEventCreate(&c->ev0));
     DC_HIP(hipEventCreate(&c->ev1));

@@ -108,6 +108,8 @@ struct EvalArgs {
   long long* f_g2;
 };
 
+struct BinScratch;
+
 struct Bins {
   int64_t n[NBINS];
   const int32_t* list[NBINS];
@@ -130,6 +132,7 @@ struct Bins {
   hipStream_t side;    // the hub-row bin runs here, overlapping the other
   hipEvent_t fork;     // bins (null: on the caller's stream)
   hipEvent_t join;
+  BinScratch* scratch;  // buffers of the deferred walks (the binning's own)
 };
 
 // The bins restricted to their first parts (the vertices not skipped).
@@ -145,6 +148,8 @@ inline Bins first_part(const Bins& b) {
 
 struct BinScratch {
   DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf, defer;
+  DBuf dkeys, dvals, dflag, dpos, dseg;  // deferred walks sorted by (j*, C(i))
+  int64_t group_min = 2048;  // deferred walks of the previous pass that group them
   void* host = nullptr;  // pinned, 256 bytes
   hipStream_t side = nullptr;  // second stream and fork / join events of the
   hipEvent_t fork = nullptr;   // evaluation launches (owned by the context)

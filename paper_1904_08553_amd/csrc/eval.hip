@@ -47,7 +47,7 @@ __device__ __forceinline__ bool cand_better(const Cand& p, const Cand& q) {
 
 
 // Alg. 2 sources of the short-row bins whose j* has more entries than this
-// are finished by k_ds_deferred; a gain2 above any gain1 stands for them.
+// are finished by k_defer_walk; a gain2 above any gain1 stands for them.
 constexpr int32_t DEFER_ROW = 512;
 constexpr long long NO_ACCEPT = 0x7fffffffffffffffll;
 
@@ -331,7 +331,7 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
       const int ci = __builtin_amdgcn_readlane(c, ld);
       long long r;
       if (A.defer && A.off[js + 1] - A.off[js] > DEFER_ROW) {
-        // j*'s row is long: its walk goes to a block of its own (k_ds_deferred)
+        // j*'s row is long: its walk is grouped with the others of j* (k_defer_walk)
         if (lane == ld) A.defer[atomicAdd(A.defer_count, 1)] = DeferItem{i, js, ci, cj, best.g};
         r = NO_ACCEPT;
       } else {
@@ -1066,9 +1066,9 @@ inline int wave_grid(int64_t items) {
   return int(g < 1 ? 1 : g);
 }
 
-// Alg. 2 for the deferred sources: gain2 over j*'s long row by a whole
-// block, then the same acceptance as in place (R gets i, j* and i's
-// neighbours, C(j*) is flagged).
+// Alg. 2 for the deferred sources, one block per item: gain2 over j*'s long
+// row, then the same acceptance as in place (R gets i, j* and i's
+// neighbours, C(j*) is flagged).  Used when few walks were deferred.
 template <int MODE>
 __global__ void __launch_bounds__(TPB) k_ds_deferred(EvalArgs A) {
   __shared__ GroupLds<TPB> L;
@@ -1092,8 +1092,162 @@ __global__ void __launch_bounds__(TPB) k_ds_deferred(EvalArgs A) {
   if (threadIdx.x == 0 && accepted) add_accepted(A.stat, accepted);
 }
 
+
+// Alg. 2 for the deferred sources, grouped by j*: the items are sorted by
+// the key j* n + C(i), so each run of one j* lists its items by C(i).  A
+// block walks j*'s row once per chunk of up to DG_CAP items: every entry's
+// weight goes to e_{j* -> C(j*)} or, found by binary search among the
+// chunk's sorted C(i), to that label's first slot in LDS.  Each item then
+// takes gain2 = G(j* -> C(i)) from the sums and the same acceptance as in
+// place (R gets i, j* and i's neighbours, C(j*) is flagged).  Many sources
+// share one high-degree j*, whose row is read once instead of once each.
+constexpr int DG_CAP = 2048;
+
+__global__ void k_defer_keys(const DeferItem* __restrict__ items, int64_t cnt, int32_t n,
+                             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < cnt; q += stride) {
+    keys[q] = uint64_t(items[q].j) * uint64_t(n) + uint64_t(items[q].c);
+    vals[q] = uint32_t(q);
+  }
+}
+
+// flag[q] = 1 where sorted item q starts a run of one j*
+__global__ void k_defer_heads(const uint64_t* __restrict__ keys, int64_t cnt, int32_t n,
+                              int32_t* __restrict__ flag) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < cnt; q += stride)
+    flag[q] = q == 0 || keys[q] / uint64_t(n) != keys[q - 1] / uint64_t(n);
+}
+
+// first index p in [0, m) with s[p] >= x (m if none)
+__device__ __forceinline__ int lds_lower_bound(const int32_t* s, int m, int32_t x) {
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(TPB)
+    k_defer_walk(EvalArgs A, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                 const int32_t* __restrict__ seg, const int32_t* __restrict__ nseg, int64_t cnt) {
+  __shared__ int32_t s_c[DG_CAP];  // the chunk's C(i), ascending
+  __shared__ int32_t s_e[DG_CAP];  // e_{j* -> s_c[p]} at each label's first slot
+  __shared__ long long s_self[NW];
+  __shared__ long long s_acc[NW];
+  const int64_t ns = *nseg;
+  const uint64_t n = uint64_t(A.n0);
+  const int wid = threadIdx.x / WAVE;
+  long long accepted = 0;
+  for (int64_t r = blockIdx.x; r < ns; r += gridDim.x) {  // block-uniform
+    const int64_t r0 = seg[r], r1 = r + 1 < ns ? seg[r + 1] : cnt;
+    const int j = int(keys[r0] / n);
+    const int x = A.C[j];
+    const int32_t rb = A.off[j], re = A.off[j + 1];
+    const long long kj = A.k[j];
+    for (int64_t p0 = r0; p0 < r1; p0 += DG_CAP) {
+      const int m = int(r1 - p0 < DG_CAP ? r1 - p0 : DG_CAP);
+      for (int t = threadIdx.x; t < m; t += TPB) {
+        s_c[t] = int32_t(keys[p0 + t] % n);
+        s_e[t] = 0;
+      }
+      __syncthreads();
+      long long self = 0;
+      for (int32_t q = rb + int32_t(threadIdx.x); q < re; q += TPB) {
+        const int2 e = A.adj[q];
+        if (e.x == j) continue;
+        const int X = A.C[e.x];
+        if (X == x) {
+          self += e.y;
+        } else {
+          const int p = lds_lower_bound(s_c, m, X);
+          if (p < m && s_c[p] == X) atomicAdd(&s_e[p], e.y);
+        }
+      }
+      self = wave_sum(self);
+      if (lane_id() == 0) s_self[wid] = self;
+      __syncthreads();
+      self = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) self += s_self[w];
+      const long long s_own = A.two_m * self - kj * (A.a[x] - kj);
+      for (int t = threadIdx.x; t < m; t += TPB) {
+        const DeferItem d = A.defer[vals[p0 + t]];
+        const long long e_to = s_e[lds_lower_bound(s_c, m, d.c)];
+        const long long g2 = (A.two_m * e_to - kj * A.a[d.c]) - s_own;
+        if (d.g >= g2) {
+          for (int32_t q = A.off[d.i]; q < A.off[d.i + 1]; ++q) A.R[A.adj[q].x] = 1;
+          A.R[d.i] = 1;
+          A.R[j] = 1;
+          A.cflag[x] = 1;
+          if (A.accflag) A.accflag[d.i] = 1;
+          accepted += ACC_ADD;
+        }
+      }
+      __syncthreads();  // s_c, s_e and s_self are refilled by the next chunk
+    }
+  }
+  accepted = wave_sum(accepted);
+  if (lane_id() == 0) s_acc[wid] = accepted;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    for (int w = 0; w < NW; ++w) acc += s_acc[w];
+    if (acc) add_accepted(A.stat, acc);
+  }
+}
+
 constexpr int64_t OVF_GRID = 128;  // blocks of k_eval_ovf
-constexpr int DEFER_GRID = 256;    // blocks of k_ds_deferred
+constexpr int DEFER_GRID = 256;    // blocks of k_defer_walk
+
+// Deferred walks of one Alg. 2 pass.  The previous pass's count (copied to
+// the last word of the pinned buffer without a wait) picks the path: below
+// the binning scratch's group_min (2048 unless set), one block per item;
+// otherwise the count is read (a host wait), the items are sorted by
+// (j*, C(i)) and each j*'s row is walked once per chunk.  Both paths take
+// the same decisions.
+constexpr int DEFER_SEEN = 63;  // int32 slot of the pinned buffer (past the bin metadata)
+
+template <int MODE>
+void defer_walks(const EvalArgs& A, const Bins& bins, hipStream_t st) {
+  BinScratch& s = *bins.scratch;
+  int32_t* hc = static_cast<int32_t*>(s.host);
+  const bool grouped = hc[DEFER_SEEN] >= s.group_min;
+  DC_HIP(hipMemcpyAsync(hc + DEFER_SEEN, bins.defer_count, sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  if (!grouped) {
+    k_ds_deferred<MODE><<<DEFER_GRID, TPB, 0, st>>>(A);
+    DC_LAUNCH_CHECK();
+    return;
+  }
+  DC_HIP(hipStreamSynchronize(st));
+  const int64_t cnt = hc[DEFER_SEEN];
+  if (cnt <= 0) return;
+  s.dkeys.ensure(size_t(2 * cnt) * sizeof(uint64_t));
+  s.dvals.ensure(size_t(2 * cnt) * sizeof(uint32_t));
+  s.dflag.ensure(size_t(cnt + 1) * sizeof(int32_t));
+  s.dpos.ensure(size_t(cnt + 1) * sizeof(int32_t));
+  s.dseg.ensure(size_t(cnt + 1) * sizeof(int32_t));
+  uint64_t* k0 = s.dkeys.as<uint64_t>();
+  uint32_t* v0 = s.dvals.as<uint32_t>();
+  int32_t* flag = s.dflag.as<int32_t>();
+  int32_t* pos = s.dpos.as<int32_t>();
+  int32_t* seg = s.dseg.as<int32_t>();
+  const int g = grid_for(cnt);
+  k_defer_keys<<<g, TPB, 0, st>>>(A.defer, cnt, A.n0, k0, v0);
+  DC_LAUNCH_CHECK();
+  radix_sort_pairs(k0, v0, k0 + cnt, v0 + cnt, cnt,
+                   ilog2_ceil(uint64_t(A.n0) * uint64_t(A.n0)), st);
+  k_defer_heads<<<g, TPB, 0, st>>>(k0, cnt, A.n0, flag);
+  DC_LAUNCH_CHECK();
+  scan_excl_i32(flag, pos, cnt, pos + cnt, st);  // pos[cnt]: number of runs
+  compact_index(flag, pos, cnt, seg, st);
+  k_defer_walk<<<DEFER_GRID, TPB, 0, st>>>(A, k0, v0, seg, pos + cnt, cnt);
+  DC_LAUNCH_CHECK();
+}
 
 template <int MODE>
 void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEvent_t ev0,
@@ -1169,10 +1323,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     k_eval_gtab<MODE><<<bins.n[5], GTPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
-  if (ALG2 && bins.n[0] + bins.n[1] + bins.n[2] > 0) {
-    k_ds_deferred<MODE><<<DEFER_GRID, TPB, 0, st>>>(A);
-    DC_LAUNCH_CHECK();
-  }
+  if (ALG2 && bins.n[0] + bins.n[1] + bins.n[2] > 0) defer_walks<MODE>(A, bins, st);
 }
 
 }  // namespace
@@ -1193,6 +1344,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   constexpr size_t META = 32 * sizeof(int32_t) + NROWS * sizeof(long long);
   static_assert(M_OVF + 3 <= 32, "bin metadata slots overlap the volumes");
   static_assert(META <= 256, "bin metadata must fit the pinned host buffer");
+  static_assert(META <= DEFER_SEEN * sizeof(int32_t), "bin metadata overlaps the deferred count");
   s.counts.ensure(META);
   int32_t* counts = s.counts.as<int32_t>();
   long long* vol = reinterpret_cast<long long*>(counts + 32);
@@ -1233,6 +1385,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   s.defer.ensure(size_t(cap) * sizeof(DeferItem));
   b.defer = reinterpret_cast<DeferItem*>(s.defer.p);
   b.defer_count = counts + M_OVF + 2;
+  b.scratch = &s;
   b.side = s.side;
   b.fork = s.fork;
   b.join = s.join;

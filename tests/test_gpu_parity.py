@@ -365,3 +365,19 @@ def test_weights_near_the_2m_limit(mode):
     assert eo.value.status == -7
     assert np.array_equal(g.communities(), C0) and g.modularity() == q0
     assert np.array_equal(o.C, C0) and o.modularity()[1:] == q0[1:]
+
+
+@pytest.mark.parametrize("group_min", ["0", "1000000000"])
+def test_deferred_walks_grouped_and_per_item(group_min, monkeypatch):
+    """Alg. 2 sources whose best sink j* has a long row: their gain2 walks
+    grouped by j* (one row walk per chunk of sources) or one block per
+    source give the same R_t, labels and traces as the oracle."""
+    _log(f"case: deferred walks group_min={group_min}")
+    monkeypatch.setenv("DC_DEFER_GROUP_MIN", group_min)
+    gen = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=3)
+    (u, v, w), it = gen.stream(3, frac=0.02)
+    o, g = make_pair(gen.n, u, v, w)
+    compare(o, g, "init")
+    for t, b in enumerate(it):
+        step_pair(o, g, b)
+        compare(o, g, f"step {t}")
