@@ -178,7 +178,10 @@ void dc_default_options(dc_options* opt);
  * runs Static(G_1) (Sec. 3.4 step 1): Alg. 1 from singletons with every
  * vertex active.  *out receives the context; C_1 is read with
  * dc_communities.  Errors: ARG, RANGE, SELF_LOOP, WEIGHT, OVERFLOW, OOM,
- * DEVICE. */
+ * DEVICE.  The environment variable DC_DEFER_GROUP_MIN, read here, sets how
+ * many gain2 walks of Alg. 2 over long rows a screening pass must have
+ * deferred before the next pass groups them by j* (default 2048; 0 always
+ * groups them); it changes speed only, never a result. */
 dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1,
                   const dc_options* opt);
 
