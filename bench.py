@@ -317,9 +317,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (the method is measured on one "
-              "MI355X; multi-GPU sharding is described in DESIGN.md, not implemented)",
-              file=sys.stderr)
+        print("bench.py: runs on exactly one GPU (the method is measured on one MI355X; "
+              "multi-GPU sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
