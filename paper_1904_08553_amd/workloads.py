@@ -25,6 +25,19 @@ def _rng(seed: int, *tags: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence((int(seed),) + tuple(int(t) for t in tags))))
 
 
+def _searchsorted(a, x, side="left"):
+    """np.searchsorted(a, x, side) for unsorted queries x, issued in sorted
+    order (the binary searches then walk the table in one direction, far
+    faster on large tables); the result is the same array."""
+    x = np.asarray(x)
+    if len(x) < 4096:
+        return np.searchsorted(a, x, side=side)
+    order = np.argsort(x, kind="stable")
+    out = np.empty(len(x), np.intp)
+    out[order] = np.searchsorted(a, x[order], side=side)
+    return out
+
+
 def _key(u, v):
     u = np.asarray(u, np.int64)
     v = np.asarray(v, np.int64)
@@ -268,12 +281,12 @@ class DCSBM:
 
     def _draw_global(self, rng, k):
         x = rng.random(k) * self.cum_all[-1]
-        return np.minimum(np.searchsorted(self.cum_all, x, side="right"), self.n - 1).astype(np.int32)
+        return np.minimum(_searchsorted(self.cum_all, x, side="right"), self.n - 1).astype(np.int32)
 
     def _draw_in_block(self, rng, b):
         lo, hi = self.bmass_lo[b], self.bmass_hi[b]
         x = lo + rng.random(len(b)) * (hi - lo)
-        pos = np.searchsorted(self.cum_sorted, x, side="right")
+        pos = _searchsorted(self.cum_sorted, x, side="right")
         pos = np.clip(pos, self.bstart[b], self.bstart[b + 1] - 1)
         return self.order[pos]
 
