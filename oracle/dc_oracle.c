@@ -16,6 +16,7 @@
  *   Sec. 3.1 gain, Appendix A algebra ........ score / csr_gain
  *   Sec. 3.2 Louvain move rule ............... decide
  *   Sec. 3.2 Alg. 1 (sweeps, compaction) ..... level_sweeps, coarsen, run_levels
+ *   Sec. 3.4 SLM host (dSLM) ................. induced, run_levels_slm
  *   Sec. 3.4 incremental procedure ........... orc_stage_batch / orc_finish_batch
  *   learned screener samples (extension) ..... collect_samples, features_of
  *   Sec. 3.5 Alg. 2 (Delta-screening) ........ screen_additions
@@ -196,7 +197,8 @@ static void trace_push(trace_t* tr, const orc_sweep_rec* r) {
 static int64_t level_sweeps(const csr_t* g, int64_t two_m, int64_t T,
                             int32_t* C, const uint8_t* active,
                             const orc_options* opt, int32_t level,
-                            trace_t* tr, int* oom) {
+                            trace_t* tr, int* oom, const int64_t* k_ext,
+                            int32_t phase) {
   int32_t n = g->n;
   size_t nn = (size_t)(n > 0 ? n : 1);
   int64_t* k = (int64_t*)malloc(sizeof(int64_t) * nn);
@@ -211,7 +213,12 @@ static int64_t level_sweeps(const csr_t* g, int64_t two_m, int64_t T,
     *oom = 1;
     goto done;
   }
-  csr_degrees(g, k);
+  /* k_ext: the vertex weights of a larger graph g is a part of (SLM
+   * refinement: degrees in the whole level graph) */
+  if (k_ext)
+    memcpy(k, k_ext, sizeof(int64_t) * nn);
+  else
+    csr_degrees(g, k);
   int32_t n_active = 0;
   for (int32_t u = 0; u < n; ++u) n_active += active[u] ? 1 : 0;
   int64_t N0 = csr_numerator(g, C, two_m, k, a2);
@@ -241,6 +248,7 @@ static int64_t level_sweeps(const csr_t* g, int64_t two_m, int64_t T,
     r.moves = moves;
     r.dN = dN;
     r.kept = (moves > 0 && dN >= 0) ? 1 : 0;
+    r.phase = phase;
     trace_push(tr, &r);
     if (moves == 0) break;
     if (dN < 0) break; /* revert: C keeps the snapshot, the level ends */
@@ -351,9 +359,15 @@ static int coarsen(const csr_t* g, const int32_t* C, int32_t* rank,
 /* ------------------------------------------------------------------------ */
 /* Levels (Alg. 1 outer loop) and projection to canonical labels.            */
 
+static int run_levels_slm(const csr_t* g0, int32_t* C0, const uint8_t* active0,
+                          const orc_options* opt, trace_t* tr, int32_t* levels_out,
+                          int64_t* N_out);
+
 static int run_levels(const csr_t* g0, int32_t* C0, const uint8_t* active0,
                       const orc_options* opt, trace_t* tr, int32_t* levels_out,
                       int64_t* N_out) {
+  if (opt->algorithm == ORC_ALGO_SLM)
+    return run_levels_slm(g0, C0, active0, opt, tr, levels_out, N_out);
   int32_t n0 = g0->n;
   size_t nn = (size_t)(n0 > 0 ? n0 : 1);
   int64_t two_m = csr_two_m(g0);
@@ -380,7 +394,7 @@ static int run_levels(const csr_t* g0, int32_t* C0, const uint8_t* active0,
   int32_t level = 0;
   for (;;) {
     const uint8_t* act = level == 0 ? active0 : all;
-    int64_t gain = level_sweeps(&cur, two_m, T, C, act, opt, level, tr, &oom);
+    int64_t gain = level_sweeps(&cur, two_m, T, C, act, opt, level, tr, &oom, NULL, 0);
     if (oom) break;
     int stop = (level + 1 >= opt->max_levels) || (level >= 1 && gain <= T);
     if (stop) break;
@@ -426,6 +440,175 @@ static int run_levels(const csr_t* g0, int32_t* C0, const uint8_t* active0,
   free(C);
   free(rank);
   free(all);
+  return !oom;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Levels of the smart local moving method (the paper's second host method,
+ * Sec. 3.4; the steps are those of its reference [waltman2013smart]):
+ *   1. local moving on the level graph from the level's start partition
+ *      (level 0: the inherited partition over the active set R; above: every
+ *      vertex), the same synchronous sweeps as Louvain;
+ *   2. if every vertex ended alone, or this is the last level allowed, the
+ *      partition is final;
+ *   3. refinement: inside each community, local moving from singletons on
+ *      the subgraph the community induces (every vertex active; vertex
+ *      weights and 2m those of the whole level graph, so a move's gain and
+ *      the exact Delta N are the whole graph's);
+ *   4. compaction of the level graph by the refined communities; if that
+ *      does not reduce the graph the partition of step 1 is final;
+ *   5. the next level starts from the communities of step 1: every coarse
+ *      vertex (a refined community) joins its parent community, labelled by
+ *      the smallest coarse id among the parent's refined communities.
+ * The final partition of a level-0 vertex is the last level's partition of
+ * the coarse vertex it belongs to. */
+
+/* The entries of g inside one community of C (diagonal entries included). */
+static int induced(const csr_t* g, const int32_t* C, csr_t* out) {
+  int32_t n = g->n;
+  out->n = n;
+  out->off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!out->off) return 0;
+  int64_t nnz = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    out->off[u] = nnz;
+    for (int64_t e = g->off[u]; e < g->off[u + 1]; ++e)
+      if (C[g->col[e]] == C[u]) nnz++;
+  }
+  out->off[n] = nnz;
+  out->nnz = nnz;
+  out->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  out->w = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+  if (!out->col || !out->w) return 0;
+  int64_t q = 0;
+  for (int32_t u = 0; u < n; ++u)
+    for (int64_t e = g->off[u]; e < g->off[u + 1]; ++e)
+      if (C[g->col[e]] == C[u]) {
+        out->col[q] = g->col[e];
+        out->w[q] = g->w[e];
+        q++;
+      }
+  return 1;
+}
+
+static int run_levels_slm(const csr_t* g0, int32_t* C0, const uint8_t* active0,
+                          const orc_options* opt, trace_t* tr, int32_t* levels_out,
+                          int64_t* N_out) {
+  int32_t n0 = g0->n;
+  size_t nn = (size_t)(n0 > 0 ? n0 : 1);
+  int64_t two_m = csr_two_m(g0);
+  int64_t T = opt->tau_den > 0 ? (two_m * two_m) / opt->tau_den : 0;
+  int oom = 0;
+  int32_t* map = (int32_t*)malloc(sizeof(int32_t) * nn); /* level-0 -> current */
+  int32_t* C = (int32_t*)malloc(sizeof(int32_t) * nn);   /* step-1 partition */
+  int32_t* Rf = (int32_t*)malloc(sizeof(int32_t) * nn);  /* refined partition */
+  int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * nn);
+  int32_t* first = (int32_t*)malloc(sizeof(int32_t) * nn);
+  int64_t* k = (int64_t*)malloc(sizeof(int64_t) * nn);
+  uint8_t* all = (uint8_t*)malloc(nn);
+  uint8_t* used = (uint8_t*)malloc(nn);
+  if (!map || !C || !Rf || !rank || !first || !k || !all || !used) {
+    oom = 1;
+    goto out;
+  }
+  memset(all, 1, nn);
+  for (int32_t v = 0; v < n0; ++v) {
+    map[v] = v;
+    C[v] = C0[v];
+  }
+  csr_t cur = *g0; /* borrowed at level 0 */
+  int owns = 0;
+  int32_t level = 0;
+  for (;;) {
+    /* 1. local moving (R at level 0) */
+    const uint8_t* act = (level > 0) ? all : active0;
+    (void)level_sweeps(&cur, two_m, T, C, act, opt, level, tr, &oom, NULL, 0);
+    if (oom) break;
+    /* 2. every vertex alone, or no level left */
+    memset(used, 0, nn);
+    int32_t ncomm = 0;
+    for (int32_t u = 0; u < cur.n; ++u)
+      if (!used[C[u]]) {
+        used[C[u]] = 1;
+        ncomm++;
+      }
+    if (ncomm == cur.n || level + 1 >= opt->max_levels) break;
+    /* 3. refinement inside each community, from singletons */
+    csr_t sub;
+    memset(&sub, 0, sizeof(sub));
+    if (!induced(&cur, C, &sub)) {
+      csr_free(&sub);
+      oom = 1;
+      break;
+    }
+    csr_degrees(&cur, k);
+    for (int32_t u = 0; u < cur.n; ++u) Rf[u] = u;
+    (void)level_sweeps(&sub, two_m, T, Rf, all, opt, level, tr, &oom, k, 1);
+    csr_free(&sub);
+    if (oom) break;
+    /* 4. compaction by the refined communities */
+    csr_t nxt;
+    memset(&nxt, 0, sizeof(nxt));
+    if (!coarsen(&cur, Rf, rank, &nxt)) {
+      oom = 1;
+      break;
+    }
+    if (nxt.n == cur.n) {
+      csr_free(&nxt);
+      break;
+    }
+    /* 5. start partition of the next level: the parent communities */
+    for (int32_t x = 0; x < cur.n; ++x) first[x] = -1;
+    for (int32_t u = 0; u < cur.n; ++u) {
+      int32_t y = rank[Rf[u]];
+      if (first[C[u]] < 0 || y < first[C[u]]) first[C[u]] = y;
+    }
+    int32_t* Cn = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nxt.n > 0 ? (size_t)nxt.n : 1));
+    if (!Cn) {
+      csr_free(&nxt);
+      oom = 1;
+      break;
+    }
+    for (int32_t u = 0; u < cur.n; ++u) Cn[rank[Rf[u]]] = first[C[u]];
+    for (int32_t v = 0; v < n0; ++v) map[v] = rank[Rf[map[v]]];
+    for (int32_t y = 0; y < nxt.n; ++y) C[y] = Cn[y];
+    free(Cn);
+    if (owns) csr_free(&cur);
+    cur = nxt;
+    owns = 1;
+    level++;
+  }
+  if (!oom) {
+    /* canonical labels: smallest member vertex id of each final community */
+    int32_t* lab = rank;
+    for (int32_t x = 0; x < n0; ++x) lab[x] = -1;
+    for (int32_t v = 0; v < n0; ++v) {
+      int32_t f = C[map[v]];
+      if (lab[f] < 0) lab[f] = v;
+      C0[v] = lab[f];
+    }
+    if (N_out) {
+      int64_t* a = (int64_t*)malloc(sizeof(int64_t) * nn);
+      if (a) {
+        csr_degrees(g0, k);
+        *N_out = csr_numerator(g0, C0, two_m, k, a);
+      } else {
+        oom = 1;
+      }
+      free(a);
+    }
+  }
+  if (owns) csr_free(&cur);
+  if (levels_out) *levels_out = level + 1;
+out:
+  free(map);
+  free(C);
+  free(Rf);
+  free(rank);
+  free(first);
+  free(k);
+  free(all);
+  free(used);
   return !oom;
 }
 
@@ -550,7 +733,8 @@ static int options_ok(const orc_options* o) {
           o->mode == ORC_MODE_STATIC || o->mode == ORC_MODE_LEARNED) &&
          (o->collect == 0 || o->collect == 1) &&
          (o->del_rule == ORC_DEL_GAIN || o->del_rule == ORC_DEL_CONSERVATIVE) &&
-         o->tau_den >= 0 && o->cascade_num >= 0 && o->cascade_den >= 0;
+         o->tau_den >= 0 && o->cascade_num >= 0 && o->cascade_den >= 0 &&
+         (o->algorithm == ORC_ALGO_LOUVAIN || o->algorithm == ORC_ALGO_SLM);
 }
 
 static void fill_info(orc_step_info* info, const trace_t* tr, int32_t levels,
@@ -922,7 +1106,7 @@ static int collect_samples(orc_state* s, const csr_t* g, const int64_t* k,
   memset(all, 1, nn);
   int64_t Tthr = s->opt.tau_den > 0 ? (two_m * two_m) / s->opt.tau_den : 0;
   int oom = 0;
-  (void)level_sweeps(g, two_m, Tthr, Cl, all, &s->opt, 0, NULL, &oom);
+  (void)level_sweeps(g, two_m, Tthr, Cl, all, &s->opt, 0, NULL, &oom, NULL, 0);
   if (oom) {
     free(T);
     free(Cl);

@@ -50,6 +50,11 @@ enum {
  * caller then passes the active set it chose to orc_finish_batch. */
 enum { ORC_MODE_DELTA = 0, ORC_MODE_ALL = 1, ORC_MODE_STATIC = 2, ORC_MODE_LEARNED = 3 };
 enum { ORC_DEL_GAIN = 0, ORC_DEL_CONSERVATIVE = 1 };
+/* The multi-level method Delta-screening is plugged into (Sec. 3.4): the
+ * Louvain method, or the smart local moving (SLM) method of the paper's
+ * reference [waltman2013smart], whose levels refine every community before
+ * the compaction. */
+enum { ORC_ALGO_LOUVAIN = 0, ORC_ALGO_SLM = 1 };
 
 typedef struct orc_options {
   int32_t mode;            /* ORC_MODE_* */
@@ -61,6 +66,8 @@ typedef struct orc_options {
   int64_t tau_den;         /* T = floor((2m)^2 / tau_den); 0 means T = 0 */
   int64_t cascade_num;     /* cascade-aware screening (extension): with     */
   int64_t cascade_den;     /* den > 0, theta = num/den >= 0; den = 0: off   */
+  int32_t algorithm;       /* ORC_ALGO_* */
+  int32_t pad;
 } orc_options;
 
 /* Screener samples of one batch (the learned screener; not in the paper).
@@ -92,7 +99,7 @@ typedef struct orc_sweep_rec {
   int64_t moves;
   int64_t dN;        /* exact change of N over the sweep */
   int32_t kept;      /* 1 if applied, 0 if reverted */
-  int32_t pad;
+  int32_t phase; /* 0 local moving; 1 SLM refinement inside communities */
 } orc_sweep_rec;
 
 typedef struct orc_step_info {

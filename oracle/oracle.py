@@ -18,6 +18,7 @@ SRC = os.path.join(HERE, "dc_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 MODE_DELTA, MODE_ALL, MODE_STATIC, MODE_LEARNED = 0, 1, 2, 3
+ALGO_LOUVAIN, ALGO_SLM = 0, 1
 FEATURES = 8
 NO_GAIN = -(1 << 63)
 DEL_GAIN, DEL_CONSERVATIVE = 0, 1
@@ -47,6 +48,7 @@ class Options(ct.Structure):
         ("max_sweeps", ct.c_int32), ("singleton_guard", ct.c_int32),
         ("del_rule", ct.c_int32), ("collect", ct.c_int32), ("tau_den", ct.c_int64),
         ("cascade_num", ct.c_int64), ("cascade_den", ct.c_int64),
+        ("algorithm", ct.c_int32), ("pad", ct.c_int32),
     ]
 
 
@@ -55,7 +57,7 @@ class SweepRec(ct.Structure):
         ("level", ct.c_int32), ("sweep", ct.c_int32), ("n_level", ct.c_int32),
         ("n_active", ct.c_int32), ("nnz_level", ct.c_int64),
         ("moves", ct.c_int64), ("dN", ct.c_int64), ("kept", ct.c_int32),
-        ("pad", ct.c_int32),
+        ("phase", ct.c_int32),
     ]
 
 
@@ -120,10 +122,13 @@ def _p(a):
 
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
-            del_rule=DEL_GAIN, tau_den=1000000, collect=0, cascade=None) -> Options:
+            del_rule=DEL_GAIN, tau_den=1000000, collect=0, cascade=None,
+            algorithm=ALGO_LOUVAIN) -> Options:
     """cascade: None (off) or (num, den), theta = num/den (cascade-aware
-    screening, an extension; see screen_cascade in dc_oracle.c)."""
+    screening, an extension; see screen_cascade in dc_oracle.c).
+    algorithm: ALGO_LOUVAIN or ALGO_SLM (the host method, Sec. 3.4)."""
     o = Options()
+    o.algorithm = algorithm
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.tau_den = singleton_guard, del_rule, tau_den
     o.collect = collect
@@ -258,8 +263,9 @@ def _trace(recs, count, cap):
     out = []
     for r in range(min(count, cap)):
         x = recs[r]
-        out.append((x.level, x.sweep, x.n_level, x.n_active, x.nnz_level,
-                    x.moves, x.dN, x.kept))
+        rec = (x.level, x.sweep, x.n_level, x.n_active, x.nnz_level, x.moves, x.dN, x.kept)
+        # SLM refinement sweeps carry their phase as a ninth field
+        out.append(rec + (x.phase,) if x.phase else rec)
     return out
 
 

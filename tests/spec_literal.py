@@ -136,6 +136,101 @@ def run_levels(adj0, C0, active0, max_levels=32, max_sweeps=100, tau_den=10**6, 
     return {v: groups[final[v]] for v in final}, trace, level + 1
 
 
+# ---------------------------------------------------------------------------
+# Smart local moving (the paper's second host method, Sec. 3.4; steps of its
+# reference [waltman2013smart]): local moving, refinement of every community
+# from singletons on the subnetwork it induces, compaction by the refined
+# communities, next level from the parent communities.
+
+
+def weighted_modularity(sub, C, weight, tm):
+    """Eq. (1) on a subnetwork whose vertex weights and total weight are those
+    of the larger graph it is part of: intra-community weight of `sub` over
+    tm, minus the squared community weights over tm^2."""
+    if tm == 0:
+        return Fraction(0)
+    intra = sum(x for i in sub for j, x in sub[i].items() if C[j] == C[i])
+    a = {}
+    for i in sub:
+        a[C[i]] = a.get(C[i], 0) + weight[i]
+    return Fraction(intra, tm) - Fraction(sum(y * y for y in a.values()), tm * tm)
+
+
+def refine(sub, weight, tm, max_sweeps, T, guard, level, trace):
+    """Local moving on the subnetwork from singletons (every vertex active),
+    the Louvain rule with gains from weighted_modularity; returns labels."""
+    C = {i: i for i in sub}
+    for s in range(max_sweeps):
+        C2 = dict(C)
+        moves = 0
+        size = {}
+        for x in C.values():
+            size[x] = size.get(x, 0) + 1
+        base = weighted_modularity(sub, C, weight, tm)
+        for i in sorted(sub):
+            c = C[i]
+            cands = sorted({C[j] for j in sub[i] if j != i} - {c})
+            if weight[i] == 0 or not cands:
+                continue
+            best, bg = None, None
+            for D in cands:
+                Ct = dict(C)
+                Ct[i] = D
+                g = weighted_modularity(sub, Ct, weight, tm) - base
+                if bg is None or g > bg:
+                    best, bg = D, g
+            if bg <= 0:
+                continue
+            if guard and size[c] == 1 and size[best] == 1 and best > c:
+                continue
+            C2[i] = best
+            moves += 1
+        dN = (weighted_modularity(sub, C2, weight, tm) - base) * tm * tm
+        assert dN.denominator == 1
+        kept = moves > 0 and dN >= 0
+        trace.append((level, s, len(sub), len(sub), moves, int(dN), int(kept), 1))
+        if moves == 0 or dN < 0:
+            break
+        C = C2
+        if dN <= T:
+            break
+    return C
+
+
+def run_levels_slm(adj0, C0, active0, max_levels=32, max_sweeps=100, tau_den=10**6,
+                   guard=True):
+    tm = two_m(adj0)
+    T = (tm * tm) // tau_den if tau_den else 0
+    adj = adj0
+    C = dict(C0)
+    member_of = {v: v for v in adj0}  # level-0 vertex -> current level vertex
+    trace = []
+    level = 0
+    while True:
+        act = active0 if level == 0 else set(adj)
+        sweeps(adj, C, act, max_sweeps, T, guard, level, trace)
+        if len(set(C.values())) == len(adj) or level + 1 >= max_levels:
+            break
+        sub = {i: {j: x for j, x in adj[i].items() if C[j] == C[i]} for i in adj}
+        weight = {i: degree(adj, i) for i in adj}
+        Rf = refine(sub, weight, tm, max_sweeps, T, guard, level, trace)
+        H, rank = coarsen(adj, Rf)
+        if len(H) == len(adj):
+            break
+        parent_of = {rank[Rf[i]]: C[i] for i in adj}
+        first = {}
+        for x, p in parent_of.items():
+            first[p] = min(first.get(p, x), x)
+        member_of = {v: rank[Rf[x]] for v, x in member_of.items()}
+        adj, C = H, {x: first[p] for x, p in parent_of.items()}
+        level += 1
+    final = {v: C[x] for v, x in member_of.items()}
+    groups = {}
+    for v in sorted(final):
+        groups.setdefault(final[v], v)
+    return {v: groups[final[v]] for v in final}, trace, level + 1
+
+
 def screen(adj, C, add_pairs, del_pairs, del_rule="gain", cascade=None):
     """Alg. 2 on additions plus the deletion extension; returns R_t.
     cascade = (num, den): the cascade extension -- every neighbour v of an
@@ -188,13 +283,15 @@ def screen(adj, C, add_pairs, del_pairs, del_rule="gain", cascade=None):
 class Literal:
     """Dynamic driver mirroring the incremental procedure of Sec. 3.4."""
 
-    def __init__(self, n, u, v, w, mode="delta", del_rule="gain", cascade=None, **lv):
+    def __init__(self, n, u, v, w, mode="delta", del_rule="gain", cascade=None,
+                 algorithm="louvain", **lv):
         self.n = n
         self.adj = adjacency(n, u, v, w)
         self.mode, self.del_rule, self.lv = mode, del_rule, lv
         self.cascade = cascade
+        self.levels_fn = run_levels_slm if algorithm == "slm" else run_levels
         C0 = {i: i for i in range(n)}
-        self.C, self.trace, self.levels = run_levels(self.adj, C0, set(range(n)), **lv)
+        self.C, self.trace, self.levels = self.levels_fn(self.adj, C0, set(range(n)), **lv)
         self.R = set(range(n))
 
     def apply_batch(self, au, av, aw, du, dv):
@@ -216,7 +313,7 @@ class Literal:
         else:
             R, C0 = set(range(self.n)), {i: i for i in range(self.n)}
         self.R = R
-        self.C, self.trace, self.levels = run_levels(self.adj, C0, R, **self.lv)
+        self.C, self.trace, self.levels = self.levels_fn(self.adj, C0, R, **self.lv)
         return self.C
 
     def modularity(self):

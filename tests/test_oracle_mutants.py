@@ -63,6 +63,27 @@ MUTANTS.update({
 })
 
 
+# mistakes in the smart local moving levels (dSLM), caught by their pins
+SLM = "test_oracle_slm.py"
+MUTANTS.update({
+    "SLM refinement starts from the communities": (
+        "    for (int32_t u = 0; u < cur.n; ++u) Rf[u] = u;\n",
+        "    for (int32_t u = 0; u < cur.n; ++u) Rf[u] = C[u];\n", SLM),
+    "SLM refinement crosses communities": (
+        "      if (C[g->col[e]] == C[u]) nnz++;", "      nnz++;", SLM),
+    "SLM refinement weights from the subgraph": (
+        "(void)level_sweeps(&sub, two_m, T, Rf, all, opt, level, tr, &oom, k, 1);",
+        "(void)level_sweeps(&sub, two_m, T, Rf, all, opt, level, tr, &oom, NULL, 1);", SLM),
+    "SLM next level from singletons": (
+        "    for (int32_t u = 0; u < cur.n; ++u) Cn[rank[Rf[u]]] = first[C[u]];",
+        "    for (int32_t u = 0; u < cur.n; ++u) Cn[rank[Rf[u]]] = rank[Rf[u]];", SLM),
+    "SLM compaction by the unrefined communities": (
+        "    if (!coarsen(&cur, Rf, rank, &nxt)) {", "    if (!coarsen(&cur, C, rank, &nxt)) {", SLM),
+    "SLM level 0 ignores R": ("    const uint8_t* act = (level > 0) ? all : active0;",
+                              "    const uint8_t* act = all;", SLM),
+})
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_reject_planted_mistake(name, tmp_path):
     old, new, *target = MUTANTS[name]
