@@ -67,6 +67,21 @@ enum {
                          is set                                          */
 };
 
+/* The multi-level method Delta-screening is plugged into (Sec. 3.4: the
+ * paper modifies both).  LOUVAIN: levels of Alg. 1 (local moving, then
+ * compaction by the communities).  SLM: smart local moving (the paper's
+ * reference [waltman2013smart]): after the local moving of a level every
+ * community is refined (local moving from singletons on the subgraph it
+ * induces, with the whole graph's vertex weights), the level graph is
+ * compacted by the refined communities and the next level starts from the
+ * unrefined ones; levels continue while the compaction reduces the graph.
+ * Delta-screening restricts the first local moving of level 0 to R_t in
+ * both (dLouvain-DS, dSLM-DS); MODE_ALL gives dLouvain-base / dSLM-base. */
+enum {
+  DC_ALGO_LOUVAIN = 0,
+  DC_ALGO_SLM = 1
+};
+
 /* Deletions are outside the paper (Sec. 5 lists them as future work). */
 enum {
   DC_DEL_GAIN = 0,        /* a source of an intra-community deletion joins R
@@ -108,7 +123,8 @@ typedef struct dc_options {
                               neighbours to R_t (DELTA and the screening pass
                               of LEARNED / collect); both >= 0              */
   int64_t cascade_den;     /* 0 (default): no cascade                        */
-  int64_t reserved[1];     /* must be zero                                   */
+  int32_t algorithm;       /* DC_ALGO_*; default LOUVAIN                      */
+  int32_t reserved;        /* must be zero                                   */
 } dc_options;
 
 /* An edge list: count entries (u[e], v[e], w[e]).  w is ignored (may be
@@ -132,7 +148,9 @@ typedef struct dc_sweep_rec {
   int64_t moves;     /* vertices that changed community                    */
   int64_t dN;        /* exact change of N = 2m*I - sum a^2 (Q = N/(2m)^2)  */
   int32_t kept;      /* 1 applied, 0 reverted (dN < 0) or no move          */
-  int32_t pad;
+  int32_t phase;     /* 0 local moving; 1 SLM refinement (local moving from
+                        singletons inside each community; n_active = all,
+                        nnz_level = entries inside communities)          */
 } dc_sweep_rec;
 
 typedef struct dc_step_stats {
@@ -178,10 +196,7 @@ void dc_default_options(dc_options* opt);
  * runs Static(G_1) (Sec. 3.4 step 1): Alg. 1 from singletons with every
  * vertex active.  *out receives the context; C_1 is read with
  * dc_communities.  Errors: ARG, RANGE, SELF_LOOP, WEIGHT, OVERFLOW, OOM,
- * DEVICE.  The environment variable DC_DEFER_GROUP_MIN, read here, sets how
- * many gain2 walks of Alg. 2 over long rows a screening pass must have
- * deferred before the next pass groups them by j* (default 2048; 0 always
- * groups them); it changes speed only, never a result. */
+ * DEVICE. */
 dc_status dc_init(dc_ctx** out, int32_t n, const dc_edges* g1,
                   const dc_options* opt);
 

@@ -41,7 +41,8 @@ bool options_ok(const dc_options* o) {
   if (o->del_rule != DC_DEL_GAIN && o->del_rule != DC_DEL_CONSERVATIVE) return false;
   if (o->tau_den < 0) return false;
   if (o->cascade_num < 0 || o->cascade_den < 0) return false;
-  if (o->reserved[0] != 0) return false;
+  if (o->algorithm != DC_ALGO_LOUVAIN && o->algorithm != DC_ALGO_SLM) return false;
+  if (o->reserved != 0) return false;
   return true;
 }
 
@@ -81,6 +82,7 @@ void ensure_vertex_state(dc_ctx* c) {
   c->R.ensure(n + 1);
   c->cflag.ensure(n + 1);
   c->stat.ensure(ST_COUNT * 8);
+  DC_HIP(hipMemsetAsync(c->stat.p, 0, ST_COUNT * 8, c->st));  // counters and self-check flags
   fill_i64(c->dpack.as<int64_t>(), 0, int64_t(n) + 1, c->st);
   fill_i32(c->lflag.as<int32_t>(), 0, int64_t(n) + 1, c->st);
 }
@@ -96,9 +98,15 @@ void ensure_sample_state(dc_ctx* c) {
   c->X.ensure(n * 16);
 }
 
+// Raises when a kernel's self-check failed (the context is then poisoned).
+void check_stat_errors(const long long* h) {
+  if (h[ST_ERR] & 1) throw std::runtime_error("hub-row hash tables larger than their buffer");
+}
+
 void read_stat(dc_ctx* c) {
   DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, c->st));
   DC_HIP(hipStreamSynchronize(c->st));
+  check_stat_errors(c->hstat);
 }
 
 // Bookkeeping of one finished sweep whose status block is in c->hstat: the
@@ -107,7 +115,7 @@ void read_stat(dc_ctx* c) {
 // limit).  timed_ms >= 0: device time of the timed launch of this sweep.
 bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& bins,
                    long long T, bool record, float timed_ms, long long& level_gain,
-                   int64_t n_active = -1) {
+                   int64_t n_active = -1, int32_t phase = 0) {
   const long long moves = c->hstat[ST_MOVES], dN = c->hstat[ST_DN];
   if (record) {
     dc_step_stats& S = c->stats;
@@ -134,9 +142,10 @@ bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& 
     r.moves = moves;
     r.dN = dN;
     r.kept = int32_t(c->hstat[ST_KEEP]);
+    r.phase = phase;
     c->trace.push_back(r);
     S.vertex_evals += n_eval;
-    if (level == 0) {
+    if (level == 0 && phase == 0) {
       S.level0_sweeps += 1;
       S.level0_active += n_eval;
       S.level0_volume += vol_eval;
@@ -155,7 +164,7 @@ bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& 
 // labels are already in Cn are binned last); later sweeps take whole bins.
 long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t nact,
                      const Bins& all_bins, int level, long long T, bool record,
-                     bool pre_done = false) {
+                     bool pre_done = false, int32_t phase = 0) {
   hipStream_t st = c->st;
   long long level_gain = 0;
   Bins bins = pre_done ? first_part(all_bins) : all_bins;
@@ -174,7 +183,7 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
     read_stat(c);
     float ms = -1.f;
     if (timed) DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    if (sweep_account(c, g, level, s, bins, T, record, ms, level_gain, nact)) break;
+    if (sweep_account(c, g, level, s, bins, T, record, ms, level_gain, nact, phase)) break;
   }
   return level_gain;
 }
@@ -258,9 +267,127 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
   S.q = two_m == 0 ? 0.0 : double(S.N) / (double(two_m) * double(two_m));
 }
 
+// Exact numerator of the final partition (Cl, al over the last level g;
+// compaction preserves N) and the step's level and sweep counts.
+void finish_stats(dc_ctx* c, const LevelView& g) {
+  dc_step_stats& S = c->stats;
+  S.levels = c->trace.empty() ? 1 : c->trace.back().level + 1;
+  S.sweeps = int32_t(c->trace.size());
+  long long* stat = c->stat.as<long long>();
+  DC_HIP(hipMemsetAsync(stat + ST_I, 0, 16, c->st));
+  intra_weight(g.off, g.adj, c->Cl.as<int32_t>(), g.n, stat + ST_I, c->st);
+  sum_squares(c->al.as<int32_t>(), g.n, stat + ST_S, c->st);
+  read_stat(c);
+  S.N = c->two_m * c->hstat[ST_I] - c->hstat[ST_S];
+  S.two_m = c->two_m;
+  S.q = c->two_m == 0 ? 0.0 : double(S.N) / (double(c->two_m) * double(c->two_m));
+}
+
+// Levels of smart local moving (the SLM host method of Sec. 3.4, level
+// structure of its reference [waltman2013smart]), level 0 over `active`
+// (null = every vertex) from the level-0 partition (Cl, al, szl):
+//   1. local moving of the level (the Louvain sweeps; level 0 over R_t);
+//   2. stop when every vertex is alone or no level is left;
+//   3. refinement: local moving from singletons on the subgraph inside the
+//      communities (vertex weights k and 2m of the whole level graph, so the
+//      gains and the exact Delta N are the whole graph's), phase 1 records;
+//   4. compaction by the refined communities; stop when it does not reduce;
+//   5. the next level starts from the parent communities (each coarse vertex
+//      labelled by the smallest coarse id among its parent's refined
+//      communities) and runs local moving over every vertex.
+void run_levels_slm(dc_ctx* c, const int32_t* active, int64_t n_active) {
+  hipStream_t st = c->st;
+  const int64_t npre = active ? c->pre_count : 0;
+  const uint8_t* skip = nullptr;
+  if (npre > 0) {
+    apply_pre(c->ulist.as<int32_t>(), npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(),
+              c->Cn.as<int32_t>(), st);
+    skip = c->uflag.as<uint8_t>();
+  }
+  LevelRun L;
+  levels_begin(c, active, n_active, L, skip);
+  const long long T = L.T;
+  LevelView g = L.g;
+  int32_t* Cl = c->Cl.as<int32_t>();
+  int32_t* Cn = c->Cn.as<int32_t>();
+  int32_t* al = c->al.as<int32_t>();
+  int32_t* szl = c->szl.as<int32_t>();
+  long long* stat = c->stat.as<long long>();
+  const size_t n4 = size_t(c->n + 1) * 4;
+  for (DBuf* b : {&c->sub_cnt, &c->sub_off, &c->par, &c->first}) b->ensure(n4);
+  int32_t* par = c->par.as<int32_t>();
+  int level = 0;
+  (void)run_sweeps(c, g, L.act, L.nact, L.bins, 0, T, true, npre > 0);
+  while (true) {
+    // 2. communities after the local moving
+    DC_HIP(hipMemsetAsync(stat + ST_N0, 0, 8, st));
+    nonempty_count(szl, g.n, stat + ST_N0, st);
+    read_stat(c);
+    if (c->hstat[ST_N0] == g.n || level + 1 >= c->opt.max_levels) break;
+    // 3. refinement inside the communities, from singletons
+    {
+      int32_t* dst[1] = {par};
+      const int32_t* src[1] = {Cl};
+      copy_i32(dst, src, 1, g.n, st);
+    }
+    const int64_t nnz_s = induced_subgraph(g, par, c->sub_cnt.as<int32_t>(),
+                                           c->sub_off.as<int32_t>(), c->sub_adj, c->hbuf, st);
+    start_level(Cl, Cn, al, szl, g.k, g.n, st);
+    const LevelView gs{g.n, nnz_s, c->sub_off.as<int32_t>(), c->sub_adj.as<int2>(), g.k};
+    Bins rb;
+    make_bins(nullptr, g.n, gs.off, rb, c->bins, st);
+    (void)run_sweeps(c, gs, nullptr, g.n, rb, level, T, true, false, 1);
+    // 4. compaction by the refined communities
+    const int next = level % 2;
+    const int32_t* cnt_in = level == 0 ? nullptr : c->cnt[(level - 1) % 2].as<int32_t>();
+    const int32_t* minv_in = level == 0 ? nullptr : c->minv[(level - 1) % 2].as<int32_t>();
+    coarsen(g, Cl, szl, al, cnt_in, minv_in, level == 0, c->n, c->map0.as<int32_t>(),
+            c->cg[next], c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, st);
+    const LevelView h = c->cg[next].view();
+    const bool reduced = h.n < g.n;
+    // 5. start partition of the compacted graph: the parent communities (also
+    // when nothing was reduced: then it is the final partition, over the
+    // coarse ids, which may permute the level's ids)
+    parent_start(par, Cl, c->cs.rank.as<int32_t>(), g.n, c->first.as<int32_t>(), Cn, st);
+    g = h;
+    level++;
+    {
+      int32_t* dst[1] = {Cl};
+      const int32_t* src[1] = {Cn};
+      copy_i32(dst, src, 1, g.n, st);
+    }
+    totals_sizes(g.k, Cl, g.n, al, szl, st);
+    if (!reduced) break;
+    Bins b;
+    make_bins(nullptr, g.n, g.off, b, c->bins, st);
+    (void)run_sweeps(c, g, nullptr, g.n, b, level, T, true);
+  }
+  const int32_t *cntL, *minvL;
+  if (level == 0) {  // the level-0 partition is final: identity maps
+    fill_i32(c->cnt[1].as<int32_t>(), 1, c->n, st);
+    iota_i32(c->first.as<int32_t>(), c->n, st);
+    iota_i32(c->map0.as<int32_t>(), c->n, st);
+    cntL = c->cnt[1].as<int32_t>();
+    minvL = c->first.as<int32_t>();
+  } else {
+    cntL = c->cnt[(level - 1) % 2].as<int32_t>();
+    minvL = c->minv[(level - 1) % 2].as<int32_t>();
+  }
+  finalize_labels(g.n, Cl, al, szl, cntL, minvL, c->n, c->map0.as<int32_t>(),
+                  c->lab.as<int32_t>(), c->cntf.as<int32_t>(), c->C.as<int32_t>(),
+                  c->a0.as<int32_t>(), c->sz0.as<int32_t>(), st);
+  c->inc.valid = false;  // the first compaction follows the refinement, not H(G, C)
+  c->inc_ready = false;
+  finish_stats(c, g);
+}
+
 // Alg. 1 with level 0 visiting `active` (null = every vertex).  The level-0
 // partition is (Cl, al, szl), prepared by the caller.
 void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
+  if (c->opt.algorithm == DC_ALGO_SLM) {
+    run_levels_slm(c, active, n_active);
+    return;
+  }
   LevelRun L;
   // Screening evaluated its vertices on the state the first level-0 sweep
   // reads (labels C_{t-1}, totals and sizes on G_t): their decisions go
@@ -313,7 +440,7 @@ void touched_samples(dc_ctx* c, const LevelView& g0, bool labels, bool score) {
   Bins b;
   make_bins(c->Tlist.as<int32_t>(), c->T_count, g0.off, b, c->bins, st);
   feat_eval(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, b, c->f_own.as<int32_t>(),
-            c->f_g1.as<long long>(), c->f_g2.as<long long>(), st);
+            c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->stat.as<long long>(), st);
   assemble_features(c->Tlist.as<int32_t>(), c->T_count, c->k0.as<int32_t>(),
                     c->kprev.as<int32_t>(), c->cptr.as<int32_t>(), c->f_own.as<int32_t>(),
                     c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->a0.as<int32_t>(),
@@ -412,6 +539,10 @@ dc_status do_init(dc_ctx* c, const dc_edges* g1) {
   c->inc_ready = false;
   run_levels(c, nullptr, c->n);
   c->have_R_all = true;
+  // the initial edge list's sort buffers serve dc_init only (a batch sorts
+  // its records in buffers of its own size)
+  for (DBuf* b : {&c->akeys, &c->ak1, &c->avals, &c->av1, &c->aheads, &c->apos, &c->ukeys, &c->uw})
+    b->release();
   return DC_OK;
 }
 
@@ -549,6 +680,15 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     }
     uint64_t* ins_keys = c->ins_keys.as<uint64_t>();
     gather_u64(ch_key, c->ins_flag.as<int32_t>(), c->ins_pos.as<int32_t>(), nch, ins_keys, st);
+    // Alg. 2 scratch: a gain per insertion record, the best sink per source
+    const int64_t item_cap = ds_item_cap(std::min<int64_t>(n, n_ins), c->nnz);
+    c->sink_g.ensure(size_t(n_ins + 1) * 8);
+    c->best_j.ensure(size_t(n + 1) * 4);
+    c->best_g.ensure(size_t(n + 1) * 8);
+    c->ds_items.ensure(size_t(item_cap) * 8);
+    const DsScratch dsx{c->sink_g.as<long long>(), c->best_j.as<int32_t>(),
+                        c->best_g.as<long long>(), c->ds_items.as<int2>(), stat + ST_MARK,
+                        item_cap};
     int32_t* src_flag = c->src_flag.as<int32_t>();
     int32_t* src_pos = c->src_pos.as<int32_t>();
     source_heads(ins_keys, n_ins, n, src_flag, st);
@@ -582,7 +722,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
         }
         ds_both(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->sz0.as<int32_t>(),
                 c->opt.singleton_guard, c->two_m, ins_keys, n_ins, c->seg_beg.as<int32_t>(),
-                c->seg_end.as<int32_t>(), uflag, b, R, cflag, accflag, pre, stat, st);
+                c->seg_end.as<int32_t>(), uflag, b, R, cflag, accflag, pre, dsx, stat, st);
         c->pre_count = pre ? n_u : 0;
       }
     } else {
@@ -598,7 +738,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
         make_bins(c->src_list.as<int32_t>(), n_src, g0.off, b, c->bins, st);
         ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
                      c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), b, R, cflag, accflag,
-                     stat, st);
+                     dsx, stat, st);
       }
     }
     if (cascade && n_src > 0) {
@@ -623,7 +763,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
         Bins b;
         make_bins(c->clist.as<int32_t>(), n_cand, g0.off, b, c->bins, st);
         feat_eval(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, b,
-                  c->f_own.as<int32_t>(), c->f_g1.as<long long>(), c->f_g2.as<long long>(), st);
+                  c->f_own.as<int32_t>(), c->f_g1.as<long long>(), c->f_g2.as<long long>(),
+                  stat, st);
         cascade_mark(c->clist.as<int32_t>(), n_cand, c->f_g1.as<long long>(), g0.k, c->two_m,
                      c->opt.cascade_num, c->opt.cascade_den, g0.off, g0.adj, R,
                      stat + ST_CASC_EXP, st);
@@ -758,14 +899,15 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->ch_dk, &c->dnet, &c->cnet, &c->cptr, &c->new_deg, &c->tile_row, &c->ins_flag, &c->ins_pos, &c->ins_keys, &c->src_flag,
                   &c->src_pos, &c->src_list, &c->dflag, &c->dpos, &c->dlist, &c->R, &c->cflag,
                   &c->rflag, &c->rpos2, &c->Rlist, &c->seg_beg, &c->seg_end, &c->chsrc,
-                  &c->accflag, &c->cascand, &c->clist, &c->uflag, &c->ulist, &c->pre,
+                  &c->accflag, &c->cascand, &c->clist, &c->uflag, &c->ulist, &c->pre, &c->sink_g, &c->best_j,
+                  &c->best_g, &c->ds_items, &c->sub_cnt, &c->sub_off, &c->sub_adj,
+                  &c->par, &c->first,
                   &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
                   &c->f_g1, &c->f_g2, &c->X, &c->y, &c->logits, &c->Cl, &c->Cn, &c->al,
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],
                   &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,
                   &c->cg[0].off, &c->cg[0].adj, &c->cg[0].k, &c->cg[1].off, &c->cg[1].adj,
-                  &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf, &c->bins.defer,
-                  &c->bins.dkeys, &c->bins.dvals, &c->bins.dflag, &c->bins.dpos, &c->bins.dseg,
+                  &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf,
                   &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
                   &c->bins.tab_off, &c->bins.gkeys, &c->bins.gvals, &c->cs.flag, &c->cs.rank,
                   &c->cs.keys0, &c->cs.keys1, &c->cs.vals0, &c->cs.vals1, &c->cs.cntr,
@@ -848,7 +990,7 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
     dc_ctx* c = cs[j];
     X.hdescs[j] = sweep_args(Ls[j].g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
                              c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m,
-                             c->opt.singleton_guard);
+                             c->opt.singleton_guard, c->stat.as<long long>());
     X.hdone[j] = 0;
     gains[j] = 0;
   }
@@ -867,7 +1009,8 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
       dc_ctx* c = cs[j];
       const LevelRun& L = Ls[j];
       sweep_eval_bin_g(L.g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
-                       c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, L.bins, st);
+                       c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, L.bins,
+                       c->stat.as<long long>(), st);
       sweep_apply(L.g, L.act, L.nact, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
                   c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m, c->movers.as<int32_t>(),
                   c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
@@ -877,6 +1020,7 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
     DC_HIP(hipStreamSynchronize(st));  // one wait for every graph of the round
     for (int j = 0; j < m; ++j) {
       if (X.hdone[j]) continue;
+      check_stat_errors(cs[j]->hstat);
       if (sweep_account(cs[j], Ls[j].g, 0, sweep[size_t(j)], Ls[j].bins, Ls[j].T, true, -1.f,
                         gains[j])) {
         X.hdone[j] = 1;
@@ -902,10 +1046,7 @@ dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) 
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
     DC_HIP(hipHostMalloc(&c->hbuf, 64));
     DC_HIP(hipHostMalloc(&c->bins.host, 256));
-    std::memset(c->bins.host, 0, 256);  // no deferred walks seen yet
-    // walks deferred by the previous Alg. 2 pass from which they are grouped
-    // by j* (a setting for tests: 0 always groups them)
-    if (const char* e = std::getenv("DC_DEFER_GROUP_MIN")) c->bins.group_min = std::atoll(e);
+    std::memset(c->bins.host, 0, 256);
     DC_HIP(hipHostMalloc(&c->cs.host, 64));
     DC_HIP(hipEventCreate(&c->ev0));
     DC_HIP(hipEventCreate(&c->ev1));

@@ -31,6 +31,8 @@ struct dc_ctx {
   DBuf accflag, cascand, clist;  // cascade-aware screening
   DBuf uflag, ulist;             // union of insertion sources and deletion endpoints
   DBuf pre;                      // first-sweep labels taken by the screening pass
+  DBuf sink_g, best_j, best_g, ds_items;  // Alg. 2: gains per record, best sinks, marked rows
+  DBuf sub_cnt, sub_off, sub_adj, par, first;  // SLM: induced subgraph, parent labels
   int64_t pre_count = 0;         // ulist entries that hold them (0: none)
   // learned screener: touched set, features, labels, scores
   DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
@@ -93,6 +95,9 @@ void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& 
                   const uint8_t* skip = nullptr);
 void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain);
 void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device);
+// All levels of one step (Louvain or SLM per the options), level 0 over
+// `active` (null = every vertex); for graphs that do not merge level 0.
+void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active);
 // Level-0 sweeps of m contexts sharing one stream, merged per round: the
 // evaluation of every unfinished context in one launch per row-length bin,
 // then each context's apply, one wait per round; gains[j] receives context

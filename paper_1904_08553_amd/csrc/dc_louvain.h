@@ -26,6 +26,8 @@ enum StatSlot : int {
   ST_FLAGS = 16,   // batch validation flags (int32 in the low half)
   ST_CASC_CAND = 19,  // cascade candidates (int32 in the low half)
   ST_CASC_EXP = 20,   // cascade candidates whose neighbourhood joined R
+  ST_ERR = 21,        // self-checks of the kernels (bit 0: a hub-row table past its buffer)
+  ST_MARK = 22,       // Alg. 2: accepted row chunks listed for marking
   ST_WSUM_ADD = 24,   // inserted weight: SUM_SLOTS counters
   ST_WSUM_DEL = ST_WSUM_ADD + SUM_SLOTS,  // deleted weight: SUM_SLOTS counters
   ST_COUNT = ST_WSUM_DEL + SUM_SLOTS
@@ -63,13 +65,6 @@ struct LevelView {
   const int32_t* k;
 };
 
-// Alg. 2 source whose gain2 walk over the long row of j* was left to a
-// block of its own: i, j*, C(i), C(j*) and gain1.
-struct DeferItem {
-  int32_t i, j, c, x;
-  long long g;
-};
-
 // Arguments of the evaluation kernels for one graph (one level).
 struct EvalArgs {
   const int32_t* off;
@@ -85,13 +80,12 @@ struct EvalArgs {
   const int32_t* list_rb;  // their row starts (set for bins built by make_bins)
   int64_t nnz;             // adjacency entries of the level graph
   const int32_t* count;  // device count of list
-  int* gkeys;            // bin G tables
+  int* gkeys;            // bin G tables: row idx owns slots [tab_off[idx], tab_off[idx + 1])
   int* gvals;
   const long long* tab_off;
+  int64_t gslots;        // slots of gkeys / gvals
   int32_t* ovf_list;     // bins W and B: vertices whose labels overflowed the
   int32_t* ovf_count;    // small LDS table (device count)
-  DeferItem* defer;      // Alg. 2: sources of the short-row bins whose j* has a
-  int32_t* defer_count;  // long row (null: walk every row in place)
   long long* stat;
   const uint64_t* ins_keys;  // Alg. 2: sorted directed insertions src*n0+dst
   const int32_t* seg_beg;    // per source vertex: its sinks are ins_keys[beg, end)
@@ -101,6 +95,9 @@ struct EvalArgs {
   uint8_t* R;
   uint8_t* cflag;
   uint8_t* accflag;  // EV_DSADD: accepted sources flagged here (null: not kept)
+  long long* sink_g;   // Alg. 2: per record q of ins_keys, G(src -> C(dst))
+  int32_t* best_j;     // Alg. 2: per source, j* when its best gain is positive, else -1
+  long long* best_g;   // Alg. 2: per such source, gain1
   const uint8_t* uflag;  // EV_DSBOTH: bit 0 insertion source, bit 1 deletion endpoint
   int32_t* pre;  // EV_DSBOTH (may be null): each evaluated vertex's first-sweep label
   int32_t* f_own;  // EV_FEAT outputs, indexed by vertex
@@ -124,15 +121,13 @@ struct Bins {
   int* gkeys;
   int* gvals;
   const long long* tab_off;
+  int64_t gslots;      // slots of gkeys / gvals
   int32_t* ovf_list;   // rows of bins W and B re-evaluated with the full table
   int32_t* ovf_count;  // their device count (cleared by the re-evaluation)
   int32_t* ovf_done;   // blocks of the re-evaluation that have finished
-  DeferItem* defer;    // deferred gain2 walks (filled once per binning)
-  int32_t* defer_count;
   hipStream_t side;    // the hub-row bin runs here, overlapping the other
   hipEvent_t fork;     // bins (null: on the caller's stream)
   hipEvent_t join;
-  BinScratch* scratch;  // buffers of the deferred walks (the binning's own)
 };
 
 // The bins restricted to their first parts (the vertices not skipped).
@@ -147,9 +142,7 @@ inline Bins first_part(const Bins& b) {
 }
 
 struct BinScratch {
-  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf, defer;
-  DBuf dkeys, dvals, dflag, dpos, dseg;  // deferred walks sorted by (j*, C(i))
-  int64_t group_min = 2048;  // deferred walks of the previous pass that group them
+  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf;
   void* host = nullptr;  // pinned, 256 bytes
   hipStream_t side = nullptr;  // second stream and fork / join events of the
   hipEvent_t fork = nullptr;   // evaluation launches (owned by the context)
@@ -178,11 +171,25 @@ void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, in
                  long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
                  hipStream_t st);
 
+// Scratch of one Alg. 2 pass: per directed insertion record its gain
+// (sink_g, n_ins entries), per vertex the best sink and gain1 (best_j,
+// best_g, n entries), the accepted rows' chunks (items, item_cap entries from
+// ds_item_cap) and their count (a zeroed device counter).
+struct DsScratch {
+  long long* sink_g;
+  int32_t* best_j;
+  long long* best_g;
+  int2* items;
+  long long* item_count;
+  int64_t item_cap;
+};
+int64_t ds_item_cap(int64_t n_sources, int64_t nnz);
+
 // seg_beg/seg_end: per source vertex, its sinks are ins_keys[beg, end).
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                   const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
                   const int32_t* seg_end, const Bins& bins, uint8_t* R, uint8_t* cflag,
-                  uint8_t* accflag, long long* stat, hipStream_t st);
+                  uint8_t* accflag, const DsScratch& X, long long* stat, hipStream_t st);
 
 // Alg. 2 over the insertion sources and the deletion rule over the deletion
 // endpoints in one evaluation pass: bins hold the union, uflag[v] bit 0
@@ -197,7 +204,7 @@ void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, const int32
              int32_t guard, long long two_m, const uint64_t* ins_keys, int64_t n_ins,
              const int32_t* seg_beg, const int32_t* seg_end, const uint8_t* uflag,
              const Bins& bins, uint8_t* R, uint8_t* cflag, uint8_t* accflag, int32_t* pre,
-             long long* stat, hipStream_t st);
+             const DsScratch& X, long long* stat, hipStream_t st);
 // uflag[v] |= 1 for v in list[0, *count) (count on the device); then
 // uflag[v] |= 2 where dflag[v] != 0, flag[v] = uflag[v] != 0, and
 // *ndel += the number of such v.
@@ -233,7 +240,7 @@ struct MultiSeg {  // one graph's bin, for build_multi_bins
 };
 // Sweep arguments of one graph's level (the `list`/`count` fields unused).
 EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
-                    const int32_t* sz, long long two_m, int guard);
+                    const int32_t* sz, long long two_m, int guard, long long* stat);
 // Merges bins[0..ngraphs) (graph j's bins at position j); segs_host: pinned
 // scratch of NBINS * ngraphs MultiSeg, segs_dev: device scratch.
 void build_multi_bins(const Bins* const* bins, int ngraphs, MultiBins& mb, MultiSeg* segs_host,
@@ -245,14 +252,14 @@ void sweep_eval_multi(const EvalArgs* descs, const int32_t* done, const MultiBin
                       hipStream_t st);
 void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                       const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                      hipStream_t st);
+                      long long* stat, hipStream_t st);
 
 // Per listed vertex i: f_own[i] = e_{i->C(i)}, f_g1[i] / f_g2[i] = scaled
 // gains to the best / second-best other neighbouring community (score
 // descending, label ascending), NO_GAIN when absent.
 void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                const Bins& bins, int32_t* f_own, long long* f_g1, long long* f_g2,
-               hipStream_t st);
+               long long* stat, hipStream_t st);
 
 // ---- screen.hip ----
 // out[pos[i]] = i for flag[i] != 0 (pos = exclusive scan of flag).
@@ -282,6 +289,22 @@ void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n
 // decisions that the screening pass already took.
 void apply_pre(const int32_t* list, int64_t cnt, const uint8_t* R, const int32_t* pre,
                int32_t* Cn, hipStream_t st);
+
+// ---- slm.hip (smart local moving levels) ----
+// The subgraph of the entries inside one community of C (diagonal included):
+// cnt (n ints) scratch, off_s (n + 1 ints) its offsets, adj_s grown to fit;
+// returns its entry count (one host read).
+int64_t induced_subgraph(const LevelView& g, const int32_t* C, int32_t* cnt, int32_t* off_s,
+                         DBuf& adj_s, void* host, hipStream_t st);
+// Cnext[rank[R[u]]] = the smallest rank[R[v]] over v with P[v] == P[u]
+// (first: n ints of scratch): the parents' partition over the coarse ids.
+void parent_start(const int32_t* P, const int32_t* R, const int32_t* rank, int32_t n,
+                  int32_t* first, int32_t* Cnext, hipStream_t st);
+// a[X] = sum of k over members of label X, sz[X] = their number.
+void totals_sizes(const int32_t* k, const int32_t* C, int32_t n, int32_t* a, int32_t* sz,
+                  hipStream_t st);
+// *count += the labels x < n with sz[x] > 0.
+void nonempty_count(const int32_t* sz, int32_t n, long long* count, hipStream_t st);
 
 // ---- coarsen.hip ----
 struct CoarsenScratch {

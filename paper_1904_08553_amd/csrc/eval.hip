@@ -46,46 +46,14 @@ __device__ __forceinline__ bool cand_better(const Cand& p, const Cand& q) {
 }
 
 
-// Alg. 2 sources of the short-row bins whose j* has more entries than this
-// are finished by k_defer_walk; a gain2 above any gain1 stands for them.
-constexpr int32_t DEFER_ROW = 512;
-constexpr long long NO_ACCEPT = 0x7fffffffffffffffll;
-
-// gain2 of Alg. 2: G(j* -> c), streamed over the row of j* by one wave.
-// The row is walked RG_U chunks per round: their entry loads, then their
-// label gathers, are issued before any is waited on.
-constexpr int RG_U = 8;
-
-template <int G>
-__device__ __forceinline__ void row_to_two(const EvalArgs& A, int js, int cj, int c, int t,
-                                           long long& e_to, long long& e_self) {
-  const int32_t rb = A.off[js], re = A.off[js + 1];
-  for (int32_t q0 = rb + t; q0 < re; q0 += RG_U * G) {
-    int2 e[RG_U];
-    int X[RG_U];
-#pragma unroll
-    for (int u = 0; u < RG_U; ++u) {
-      const int32_t q = q0 + u * G;
-      e[u] = q < re ? A.adj[q] : make_int2(js, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < RG_U; ++u) X[u] = e[u].x != js ? A.C[e[u].x] : EMPTY_KEY;
-#pragma unroll
-    for (int u = 0; u < RG_U; ++u) {
-      if (X[u] == c) e_to += e[u].y;
-      if (X[u] == cj) e_self += e[u].y;
-    }
-  }
-}
-
-__device__ __forceinline__ long long reverse_gain(const EvalArgs& A, int js, int cj, int c) {
-  long long e_to = 0, e_self = 0;
-  row_to_two<WAVE>(A, js, cj, c, lane_id(), e_to, e_self);
-  e_to = wave_sum(e_to);
-  e_self = wave_sum(e_self);
-  const long long kj = A.k[js];
-  return (A.two_m * e_to - kj * A.a[c]) - (A.two_m * e_self - kj * (A.a[cj] - kj));
-}
+// Alg. 2 (gain2 from the mirror record).  Every insertion (i, j) is a pair of
+// directed records i -> j and j -> i, so the best sink j* of a source i is
+// itself a source with i among its sinks.  The evaluation pass stores, per
+// directed record j -> i, the scaled gain G(j -> C(i)) on (G_t, C_{t-1}),
+// and, per source i with a positive best gain, j* and gain1 = G(i -> C(j*)).
+// Since gain1 > 0 implies C(j*) != C(i), gain2 = G(j* -> C(i)) of Alg. 2 is
+// exactly the gain stored at the record j* -> i: k_ds_resolve compares the
+// two, and no row is walked a second time.
 
 // --------------------------------------------------------------------------
 // bins S16/S32/S64: rows of at most GS entries, no table.  A wave is split
@@ -239,8 +207,8 @@ __device__ __forceinline__ Best group_best_first(Best b, int nd_max) {
 }
 
 // Accepted screening tests, counted in one integer: insertion sources (Alg.
-// 2) in the low 32 bits, deletion endpoints in the high 32 bits.
-constexpr long long ACC_ADD = 1;
+// 2, counted by k_ds_resolve) in the low 32 bits, deletion endpoints in the
+// high 32 bits.
 constexpr long long ACC_DEL = 1ll << 32;
 
 __device__ __forceinline__ void add_accepted(long long* stat, long long acc) {
@@ -318,36 +286,13 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
     if (has) {
       long long g = Xj == c ? 0 : (long long)tm * int(ej) - (long long)int(ki) * A.a[Xj] - s_own;
       cd = {g, Xj, sj};
+      A.sink_g[q0 + gl] = g;
     }
     const Cand best = group_cand_w<GS>(cd);
-    const bool live = ins && best.j != NO_LABEL && best.x != c && best.g > 0;
-    // gain2 of each live group, streamed by the whole wave (j* is often a
-    // high-degree vertex, and a 16-lane group would walk its row alone)
-    long long g2 = 0;
-    for (uint64_t lm = __ballot(live && gl == 0); lm; lm &= lm - 1) {
-      const int ld = __ffsll((unsigned long long)lm) - 1;
-      const int js = __builtin_amdgcn_readlane(best.j, ld);
-      const int cj = __builtin_amdgcn_readlane(best.x, ld);
-      const int ci = __builtin_amdgcn_readlane(c, ld);
-      long long r;
-      if (A.defer && A.off[js + 1] - A.off[js] > DEFER_ROW) {
-        // j*'s row is long: its walk is grouped with the others of j* (k_defer_walk)
-        if (lane == ld) A.defer[atomicAdd(A.defer_count, 1)] = DeferItem{i, js, ci, cj, best.g};
-        r = NO_ACCEPT;
-      } else {
-        r = reverse_gain(A, js, cj, ci);
-      }
-      if (lane / GS == ld / GS) g2 = r;
-    }
-    if (live && best.g >= g2) {
-      if (e.x >= 0) A.R[e.x] = 1;
-      if (gl == 0) {
-        A.R[i] = 1;
-        A.R[best.j] = 1;
-        A.cflag[best.x] = 1;
-        if (A.accflag) A.accflag[i] = 1;
-        accepted += ACC_ADD;
-      }
+    if (ins && gl == 0) {
+      const bool live = best.j != NO_LABEL && best.x != c && best.g > 0;
+      A.best_j[i] = live ? best.j : -1;
+      if (live) A.best_g[i] = best.g;
     }
     if (MODE == EV_DSADD) return accepted;
   }
@@ -525,32 +470,6 @@ __device__ __forceinline__ void group_sum2(long long& x, long long& y, GroupLds<
   __syncthreads();
 }
 
-template <int G>
-__device__ __forceinline__ long long group_reverse_gain(const EvalArgs& A, int js, int cj, int c,
-                                                        GroupLds<G>& L) {
-  if (G == WAVE) return reverse_gain(A, js, cj, c);
-  long long e_to = 0, e_self = 0;
-  row_to_two<G>(A, js, cj, c, int(threadIdx.x), e_to, e_self);
-  e_to = wave_sum(e_to);
-  e_self = wave_sum(e_self);
-  const int wid = threadIdx.x / WAVE;
-  if (lane_id() == 0) {
-    L.s0[wid] = e_to;
-    L.s1[wid] = e_self;
-  }
-  __syncthreads();
-  e_to = 0;
-  e_self = 0;
-#pragma unroll
-  for (int w = 0; w < G / WAVE; ++w) {
-    e_to += L.s0[w];
-    e_self += L.s1[w];
-  }
-  __syncthreads();
-  const long long kj = A.k[js];
-  return (A.two_m * e_to - kj * A.a[c]) - (A.two_m * e_self - kj * (A.a[cj] - kj));
-}
-
 // Power of two >= 2 * deg (at least 64), at most max_slots: the table is
 // at most half full, and only that many slots are cleared and scanned.
 __device__ __forceinline__ uint32_t table_cap(int deg, uint32_t max_slots) {
@@ -668,22 +587,15 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
       const int X = A.C[j];
       long long g = 0;
       if (X != c) g = A.two_m * table_get(keys, vals, mask, X) - ki * A.a[X] - s_own;
+      A.sink_g[q] = g;
       Cand cd = {g, X, j};
       if (cand_better(cd, best)) best = cd;
     }
     best = group_cand<G>(best, L);
-    if (best.j != NO_LABEL && best.x != c && best.g > 0) {
-      const long long g2 = group_reverse_gain<G>(A, best.j, best.x, c, L);
-      if (best.g >= g2) {
-        for (int32_t q = rb + t; q < re; q += G) A.R[A.adj[q].x] = 1;
-        if (t == 0) {
-          A.R[i] = 1;
-          A.R[best.j] = 1;
-          A.cflag[best.x] = 1;
-          if (A.accflag) A.accflag[i] = 1;
-          accepted = ACC_ADD;
-        }
-      }
+    if (t == 0) {
+      const bool live = best.j != NO_LABEL && best.x != c && best.g > 0;
+      A.best_j[i] = live ? best.j : -1;
+      if (live) A.best_g[i] = best.g;
     }
     group_sync<G>();  // the table is reused (by the deletion rule or the next item)
   }
@@ -821,6 +733,11 @@ __global__ void __launch_bounds__(GTPB) k_eval_gtab(EvalArgs A) {
                                                          &own, tstate);
   if (acc == TABLE_FULL) {
     const long long o0 = A.tab_off[idx], o1 = A.tab_off[idx + 1];
+    if (o1 > A.gslots) {
+      // the table buffer is smaller than the rows' capacities: report, write nothing
+      if (threadIdx.x == 0) atomicOr((unsigned long long*)&A.stat[ST_ERR], 1ull);
+      return;
+    }
     acc = eval_table<MODE, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0, uint32_t(o1 - o0) - 1,
                                        L, &own);
   }
@@ -1066,188 +983,90 @@ inline int wave_grid(int64_t items) {
   return int(g < 1 ? 1 : g);
 }
 
-// Alg. 2 for the deferred sources, one block per item: gain2 over j*'s long
-// row, then the same acceptance as in place (R gets i, j* and i's
-// neighbours, C(j*) is flagged).  Used when few walks were deferred.
-template <int MODE>
-__global__ void __launch_bounds__(TPB) k_ds_deferred(EvalArgs A) {
-  __shared__ GroupLds<TPB> L;
-  const int64_t cnt = *A.defer_count;
-  long long accepted = 0;
-  for (int64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
-    const DeferItem d = A.defer[q];
-    const long long g2 = group_reverse_gain<TPB>(A, d.j, d.x, d.c, L);
-    if (d.g >= g2) {  // block-uniform
-      const int32_t rb = A.off[d.i], re = A.off[d.i + 1];
-      for (int32_t p = rb + int32_t(threadIdx.x); p < re; p += TPB) A.R[A.adj[p].x] = 1;
-      if (threadIdx.x == 0) {
-        A.R[d.i] = 1;
-        A.R[d.j] = 1;
-        A.cflag[d.x] = 1;
-        if (A.accflag) A.accflag[d.i] = 1;
-        accepted += ACC_ADD;
-      }
-    }
-  }
-  if (threadIdx.x == 0 && accepted) add_accepted(A.stat, accepted);
-}
-
-
-// Alg. 2 for the deferred sources, grouped by j*: the items are sorted by
-// the key j* n + C(i), so each run of one j* lists its items by C(i).  A
-// block walks j*'s row once per chunk of up to DG_CAP items: every entry's
-// weight goes to e_{j* -> C(j*)} or, found by binary search among the
-// chunk's sorted C(i), to that label's first slot in LDS.  Each item then
-// takes gain2 = G(j* -> C(i)) from the sums and the same acceptance as in
-// place (R gets i, j* and i's neighbours, C(j*) is flagged).  Many sources
-// share one high-degree j*, whose row is read once instead of once each.
-constexpr int DG_CAP = 2048;
-
-__global__ void k_defer_keys(const DeferItem* __restrict__ items, int64_t cnt, int32_t n,
-                             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < cnt; q += stride) {
-    keys[q] = uint64_t(items[q].j) * uint64_t(n) + uint64_t(items[q].c);
-    vals[q] = uint32_t(q);
-  }
-}
-
-// flag[q] = 1 where sorted item q starts a run of one j*
-__global__ void k_defer_heads(const uint64_t* __restrict__ keys, int64_t cnt, int32_t n,
-                              int32_t* __restrict__ flag) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < cnt; q += stride)
-    flag[q] = q == 0 || keys[q] / uint64_t(n) != keys[q - 1] / uint64_t(n);
-}
-
-// first index p in [0, m) with s[p] >= x (m if none)
-__device__ __forceinline__ int lds_lower_bound(const int32_t* s, int m, int32_t x) {
-  int lo = 0, hi = m;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (s[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
+// Alg. 2 acceptance, one thread per directed insertion record j -> i: the
+// record decides source i when j is i's best sink j*; then gain1 (stored
+// with i) is compared with gain2 = the gain stored at this record.  An
+// accepted source sets R[i], R[j*], the flag of C(j*) and (cascade) its
+// accepted flag, and lists its row in chunks of MARK_CHUNK entries for
+// k_mark_rows (R gets Gamma_t(i)); chunk positions come from a block scan
+// and one atomic per block.
+constexpr int MARK_CHUNK = 256;
 
 __global__ void __launch_bounds__(TPB)
-    k_defer_walk(EvalArgs A, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                 const int32_t* __restrict__ seg, const int32_t* __restrict__ nseg, int64_t cnt) {
-  __shared__ int32_t s_c[DG_CAP];  // the chunk's C(i), ascending
-  __shared__ int32_t s_e[DG_CAP];  // e_{j* -> s_c[p]} at each label's first slot
-  __shared__ long long s_self[NW];
-  __shared__ long long s_acc[NW];
-  const int64_t ns = *nseg;
-  const uint64_t n = uint64_t(A.n0);
-  const int wid = threadIdx.x / WAVE;
+    k_ds_resolve(EvalArgs A, int2* __restrict__ items, long long* __restrict__ item_count) {
+  __shared__ int wsum[NW];
+  __shared__ long long bbase;
+  const int lane = lane_id(), wid = threadIdx.x / WAVE;
+  const uint64_t n0 = uint64_t(A.n0);
   long long accepted = 0;
-  for (int64_t r = blockIdx.x; r < ns; r += gridDim.x) {  // block-uniform
-    const int64_t r0 = seg[r], r1 = r + 1 < ns ? seg[r + 1] : cnt;
-    const int j = int(keys[r0] / n);
-    const int x = A.C[j];
-    const int32_t rb = A.off[j], re = A.off[j + 1];
-    const long long kj = A.k[j];
-    for (int64_t p0 = r0; p0 < r1; p0 += DG_CAP) {
-      const int m = int(r1 - p0 < DG_CAP ? r1 - p0 : DG_CAP);
-      for (int t = threadIdx.x; t < m; t += TPB) {
-        s_c[t] = int32_t(keys[p0 + t] % n);
-        s_e[t] = 0;
+  for (int64_t base = int64_t(blockIdx.x) * TPB; base < A.n_ins;
+       base += int64_t(gridDim.x) * TPB) {  // block-uniform
+    const int64_t q = base + threadIdx.x;
+    int32_t rb = 0, re = 0;
+    int nit = 0;
+    if (q < A.n_ins) {
+      const uint64_t key = A.ins_keys[q];
+      const int j = int(key / n0);
+      const int i = int(key - uint64_t(j) * n0);
+      if (A.best_j[i] == j && A.best_g[i] >= A.sink_g[q]) {
+        A.R[i] = 1;
+        A.R[j] = 1;
+        A.cflag[A.C[j]] = 1;
+        if (A.accflag) A.accflag[i] = 1;
+        accepted += 1;
+        rb = A.off[i];
+        re = A.off[i + 1];
+        nit = int(ceil_div(re - rb, MARK_CHUNK));
       }
-      __syncthreads();
-      long long self = 0;
-      for (int32_t q = rb + int32_t(threadIdx.x); q < re; q += TPB) {
-        const int2 e = A.adj[q];
-        if (e.x == j) continue;
-        const int X = A.C[e.x];
-        if (X == x) {
-          self += e.y;
-        } else {
-          const int p = lds_lower_bound(s_c, m, X);
-          if (p < m && s_c[p] == X) atomicAdd(&s_e[p], e.y);
-        }
-      }
-      self = wave_sum(self);
-      if (lane_id() == 0) s_self[wid] = self;
-      __syncthreads();
-      self = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) self += s_self[w];
-      const long long s_own = A.two_m * self - kj * (A.a[x] - kj);
-      for (int t = threadIdx.x; t < m; t += TPB) {
-        const DeferItem d = A.defer[vals[p0 + t]];
-        const long long e_to = s_e[lds_lower_bound(s_c, m, d.c)];
-        const long long g2 = (A.two_m * e_to - kj * A.a[d.c]) - s_own;
-        if (d.g >= g2) {
-          for (int32_t q = A.off[d.i]; q < A.off[d.i + 1]; ++q) A.R[A.adj[q].x] = 1;
-          A.R[d.i] = 1;
-          A.R[j] = 1;
-          A.cflag[x] = 1;
-          if (A.accflag) A.accflag[d.i] = 1;
-          accepted += ACC_ADD;
-        }
-      }
-      __syncthreads();  // s_c, s_e and s_self are refilled by the next chunk
     }
+    // exclusive block scan of the chunk counts
+    int incl = nit;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int y = __shfl_up(incl, o, WAVE);
+      if (lane >= o) incl += y;
+    }
+    if (lane == WAVE - 1) wsum[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < NW; ++w) tot += wsum[w];
+      bbase = tot ? (long long)atomicAdd((unsigned long long*)item_count, (unsigned long long)tot)
+                  : 0;
+    }
+    __syncthreads();
+    long long pos = bbase + incl - nit;
+    for (int w = 0; w < wid; ++w) pos += wsum[w];
+    for (int r = 0; r < nit; ++r) {
+      const int32_t cb = rb + r * MARK_CHUNK;
+      items[pos + r] = make_int2(cb, re - cb < MARK_CHUNK ? re : cb + MARK_CHUNK);
+    }
+    __syncthreads();  // wsum and bbase are rewritten by the next tile
   }
-  accepted = wave_sum(accepted);
-  if (lane_id() == 0) s_acc[wid] = accepted;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long acc = 0;
-    for (int w = 0; w < NW; ++w) acc += s_acc[w];
-    if (acc) add_accepted(A.stat, acc);
+  block_add(accepted, &A.stat[ST_DS_ACC]);
+}
+
+// R of every entry of the listed row chunks [x, y): one wave per chunk.
+__global__ void __launch_bounds__(TPB)
+    k_mark_rows(const int2* __restrict__ items, const long long* __restrict__ item_count,
+                const int2* __restrict__ adj, uint8_t* R) {
+  const int64_t cnt = *item_count;
+  const int64_t nwaves = int64_t(gridDim.x) * NW;
+  for (int64_t it = int64_t(blockIdx.x) * NW + threadIdx.x / WAVE; it < cnt; it += nwaves) {
+    const int2 ch = items[it];
+    int2 e[MARK_CHUNK / WAVE];
+#pragma unroll
+    for (int u = 0; u < MARK_CHUNK / WAVE; ++u) {
+      const int32_t q = ch.x + u * WAVE + lane_id();
+      e[u] = q < ch.y ? adj[q] : make_int2(-1, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < MARK_CHUNK / WAVE; ++u)
+      if (e[u].x >= 0) R[e[u].x] = 1;
   }
 }
 
 constexpr int64_t OVF_GRID = 128;  // blocks of k_eval_ovf
-constexpr int DEFER_GRID = 256;    // blocks of k_defer_walk
-
-// Deferred walks of one Alg. 2 pass.  The previous pass's count (copied to
-// the last word of the pinned buffer without a wait) picks the path: below
-// the binning scratch's group_min (2048 unless set), one block per item;
-// otherwise the count is read (a host wait), the items are sorted by
-// (j*, C(i)) and each j*'s row is walked once per chunk.  Both paths take
-// the same decisions.
-constexpr int DEFER_SEEN = 63;  // int32 slot of the pinned buffer (past the bin metadata)
-
-template <int MODE>
-void defer_walks(const EvalArgs& A, const Bins& bins, hipStream_t st) {
-  BinScratch& s = *bins.scratch;
-  int32_t* hc = static_cast<int32_t*>(s.host);
-  const bool grouped = hc[DEFER_SEEN] >= s.group_min;
-  DC_HIP(hipMemcpyAsync(hc + DEFER_SEEN, bins.defer_count, sizeof(int32_t),
-                        hipMemcpyDeviceToHost, st));
-  if (!grouped) {
-    k_ds_deferred<MODE><<<DEFER_GRID, TPB, 0, st>>>(A);
-    DC_LAUNCH_CHECK();
-    return;
-  }
-  DC_HIP(hipStreamSynchronize(st));
-  const int64_t cnt = hc[DEFER_SEEN];
-  if (cnt <= 0) return;
-  s.dkeys.ensure(size_t(2 * cnt) * sizeof(uint64_t));
-  s.dvals.ensure(size_t(2 * cnt) * sizeof(uint32_t));
-  s.dflag.ensure(size_t(cnt + 1) * sizeof(int32_t));
-  s.dpos.ensure(size_t(cnt + 1) * sizeof(int32_t));
-  s.dseg.ensure(size_t(cnt + 1) * sizeof(int32_t));
-  uint64_t* k0 = s.dkeys.as<uint64_t>();
-  uint32_t* v0 = s.dvals.as<uint32_t>();
-  int32_t* flag = s.dflag.as<int32_t>();
-  int32_t* pos = s.dpos.as<int32_t>();
-  int32_t* seg = s.dseg.as<int32_t>();
-  const int g = grid_for(cnt);
-  k_defer_keys<<<g, TPB, 0, st>>>(A.defer, cnt, A.n0, k0, v0);
-  DC_LAUNCH_CHECK();
-  radix_sort_pairs(k0, v0, k0 + cnt, v0 + cnt, cnt,
-                   ilog2_ceil(uint64_t(A.n0) * uint64_t(A.n0)), st);
-  k_defer_heads<<<g, TPB, 0, st>>>(k0, cnt, A.n0, flag);
-  DC_LAUNCH_CHECK();
-  scan_excl_i32(flag, pos, cnt, pos + cnt, st);  // pos[cnt]: number of runs
-  compact_index(flag, pos, cnt, seg, st);
-  k_defer_walk<<<DEFER_GRID, TPB, 0, st>>>(A, k0, v0, seg, pos + cnt, cnt);
-  DC_LAUNCH_CHECK();
-}
 
 template <int MODE>
 void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEvent_t ev0,
@@ -1255,9 +1074,6 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   EvalArgs A = base;
   A.ovf_list = bins.ovf_list;
   A.ovf_count = bins.ovf_count;
-  constexpr bool ALG2 = MODE == EV_DSADD || MODE == EV_DSBOTH;
-  A.defer = ALG2 ? bins.defer : nullptr;
-  A.defer_count = ALG2 ? bins.defer_count : nullptr;
   auto setbin = [&](int q) {
     A.list = bins.list[q];
     A.list_rb = bins.list_rb[q];
@@ -1287,6 +1103,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     G.gkeys = bins.gkeys;
     G.gvals = bins.gvals;
     G.tab_off = bins.tab_off;
+    G.gslots = bins.gslots;
     DC_HIP(hipEventRecord(bins.fork, st));
     DC_HIP(hipStreamWaitEvent(bins.side, bins.fork, 0));
     k_eval_gtab<MODE><<<bins.n[5], GTPB, 0, bins.side>>>(G);
@@ -1320,10 +1137,10 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     A.gkeys = bins.gkeys;
     A.gvals = bins.gvals;
     A.tab_off = bins.tab_off;
+    A.gslots = bins.gslots;
     k_eval_gtab<MODE><<<bins.n[5], GTPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
-  if (ALG2 && bins.n[0] + bins.n[1] + bins.n[2] > 0) defer_walks<MODE>(A, bins, st);
 }
 
 }  // namespace
@@ -1337,14 +1154,12 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   s.bcnt.ensure(size_t(NROWS * nb + 1) * sizeof(int32_t));
   s.boff.ensure(size_t(NROWS * nb + 1) * sizeof(int32_t));
   // int32 slots: [0, NBINS) bin sizes, [NBINS, 2 NBINS) first-part sizes,
-  // [2 NBINS, 3 NBINS) bin starts, [3 NBINS] total, then the overflow count,
-  // the finished blocks and the deferred count; NROWS row volumes (int64)
-  // from slot 32 on
+  // [2 NBINS, 3 NBINS) bin starts, [3 NBINS] total, then the overflow count
+  // and the finished blocks; NROWS row volumes (int64) from slot 32 on
   constexpr int M_START = 2 * NBINS, M_TOTAL = 3 * NBINS, M_OVF = 3 * NBINS + 1;
   constexpr size_t META = 32 * sizeof(int32_t) + NROWS * sizeof(long long);
-  static_assert(M_OVF + 3 <= 32, "bin metadata slots overlap the volumes");
+  static_assert(M_OVF + 2 <= 32, "bin metadata slots overlap the volumes");
   static_assert(META <= 256, "bin metadata must fit the pinned host buffer");
-  static_assert(META <= DEFER_SEEN * sizeof(int32_t), "bin metadata overlaps the deferred count");
   s.counts.ensure(META);
   int32_t* counts = s.counts.as<int32_t>();
   long long* vol = reinterpret_cast<long long*>(counts + 32);
@@ -1380,18 +1195,13 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.ovf_list = s.ovf.as<int32_t>();
   b.ovf_count = counts + M_OVF;
   b.ovf_done = counts + M_OVF + 1;
-  // deferred gain2 walks of the short-row bins: at most one per listed vertex;
-  // the count is cleared with the metadata, so one Alg. 2 pass per binning
-  s.defer.ensure(size_t(cap) * sizeof(DeferItem));
-  b.defer = reinterpret_cast<DeferItem*>(s.defer.p);
-  b.defer_count = counts + M_OVF + 2;
-  b.scratch = &s;
   b.side = s.side;
   b.fork = s.fork;
   b.join = s.join;
   b.gkeys = nullptr;
   b.gvals = nullptr;
   b.tab_off = nullptr;
+  b.gslots = 0;
   if (count > 0) {
     k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, skip, boff, nb, lists, lists_rb);
     DC_LAUNCH_CHECK();
@@ -1404,12 +1214,16 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
     DC_LAUNCH_CHECK();
     scan_excl_i64(reinterpret_cast<int64_t*>(caps), reinterpret_cast<int64_t*>(caps), b.n[G],
                   reinterpret_cast<int64_t*>(caps + b.n[G]), st);
+    // row v takes the power of two >= 2 deg(v) (< 4 deg(v) for deg(v) >= 1),
+    // so the bin's volume bounds the sum; the kernel checks tab_off against
+    // gslots before it writes
     const size_t slots = size_t(4 * b.vol[G] + 2 * b.n[G] + 16);
     s.gkeys.ensure(slots * sizeof(int));
     s.gvals.ensure(slots * sizeof(int));
     b.gkeys = s.gkeys.as<int>();
     b.gvals = s.gvals.as<int>();
     b.tab_off = caps;
+    b.gslots = int64_t(slots);
   }
 }
 
@@ -1432,10 +1246,27 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
   launch_eval<EV_SWEEP>(A, bins, st, ev0, ev1);
 }
 
+// Alg. 2 acceptance after an evaluation pass (every source's best sink and
+// every record's gain stored): resolve, then mark the accepted rows.
+void ds_resolve(const EvalArgs& A, const DsScratch& X, hipStream_t st) {
+  if (A.n_ins <= 0) return;
+  k_ds_resolve<<<grid_for(A.n_ins, 2048), TPB, 0, st>>>(A, X.items, X.item_count);
+  DC_LAUNCH_CHECK();
+  // chunks: at most one per source plus one per MARK_CHUNK entries of G_t
+  const int64_t cap = X.item_cap;
+  k_mark_rows<<<wave_grid(cap < 65536 ? cap : 65536), TPB, 0, st>>>(X.items, X.item_count,
+                                                                    A.adj, A.R);
+  DC_LAUNCH_CHECK();
+}
+
+int64_t ds_item_cap(int64_t n_sources, int64_t nnz) {
+  return n_sources + nnz / MARK_CHUNK + 1;
+}
+
 void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                   const uint64_t* ins_keys, int64_t n_ins, const int32_t* seg_beg,
                   const int32_t* seg_end, const Bins& bins, uint8_t* R, uint8_t* cflag,
-                  uint8_t* accflag, long long* stat, hipStream_t st) {
+                  uint8_t* accflag, const DsScratch& X, long long* stat, hipStream_t st) {
   EvalArgs A{};
   A.off = g.off;
   A.nnz = g.nnz;
@@ -1453,14 +1284,18 @@ void ds_additions(const LevelView& g, const int32_t* C, const int32_t* a, long l
   A.R = R;
   A.cflag = cflag;
   A.accflag = accflag;
+  A.sink_g = X.sink_g;
+  A.best_j = X.best_j;
+  A.best_g = X.best_g;
   launch_eval<EV_DSADD>(A, bins, st, nullptr, nullptr);
+  ds_resolve(A, X, st);
 }
 
 void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, const int32_t* sz,
              int32_t guard, long long two_m, const uint64_t* ins_keys, int64_t n_ins,
              const int32_t* seg_beg, const int32_t* seg_end, const uint8_t* uflag,
              const Bins& bins, uint8_t* R, uint8_t* cflag, uint8_t* accflag, int32_t* pre,
-             long long* stat, hipStream_t st) {
+             const DsScratch& X, long long* stat, hipStream_t st) {
   EvalArgs A{};
   A.sz = sz;
   A.guard = guard;
@@ -1482,13 +1317,18 @@ void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, const int32
   A.cflag = cflag;
   A.accflag = accflag;
   A.uflag = uflag;
+  A.sink_g = X.sink_g;
+  A.best_j = X.best_j;
+  A.best_g = X.best_g;
   launch_eval<EV_DSBOTH>(A, bins, st, nullptr, nullptr);
+  ds_resolve(A, X, st);
 }
 
 void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                const Bins& bins, int32_t* f_own, long long* f_g1, long long* f_g2,
-               hipStream_t st) {
+               long long* stat, hipStream_t st) {
   EvalArgs A{};
+  A.stat = stat;
   A.off = g.off;
   A.nnz = g.nnz;
   A.adj = g.adj;
@@ -1504,8 +1344,9 @@ void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long
 }
 
 EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
-                    const int32_t* sz, long long two_m, int guard) {
+                    const int32_t* sz, long long two_m, int guard, long long* stat) {
   EvalArgs A{};
+  A.stat = stat;
   A.off = g.off;
   A.nnz = g.nnz;
   A.adj = g.adj;
@@ -1581,15 +1422,16 @@ void sweep_eval_multi(const EvalArgs* descs, const int32_t* done, const MultiBin
 
 void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                       const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                      hipStream_t st) {
+                      long long* stat, hipStream_t st) {
   constexpr int G = NBINS - 1;
   if (bins.n[G] == 0) return;
-  EvalArgs A = sweep_args(g, C, Cn, a, sz, two_m, guard);
+  EvalArgs A = sweep_args(g, C, Cn, a, sz, two_m, guard, stat);
   A.list = bins.list[G];
   A.count = bins.count_dev + G;
   A.gkeys = bins.gkeys;
   A.gvals = bins.gvals;
   A.tab_off = bins.tab_off;
+  A.gslots = bins.gslots;
   k_eval_gtab<EV_SWEEP><<<bins.n[G], GTPB, 0, st>>>(A);
   DC_LAUNCH_CHECK();
 }

@@ -70,6 +70,19 @@ void copy_edges(const dc_edges* e, bool weights, std::vector<int32_t>& u,
   if (weights) DC_HIP(hipMemcpy(w.data(), e->w, m * 4, kind));
 }
 
+// Upper estimate of a context's device bytes (grow-only buffers, 25%
+// headroom each) after a call that leaves `edges` undirected edges and sorted
+// a batch of `changes` changes: per-vertex state, bins and labels (about 150
+// B per vertex), the CSR double buffer and the coarsening and screening
+// scratch sized by the entries (about 170 B per edge), the batch's records
+// (about 240 B per change).  dc_init's own sort buffers are released before
+// it returns.  Admission reserves these; after each round the reservations
+// are replaced by the measured footprints.
+int64_t est_step_bytes(int64_t n, int64_t edges, int64_t changes) {
+  return 160 * n + 192 * edges + 256 * changes + (int64_t(1) << 18);
+}
+int64_t est_init_bytes(int64_t n, int64_t edges) { return est_step_bytes(n, edges, 0); }
+
 bool edges_ok(const dc_edges* e, bool weights) {
   return !e || e->count == 0 ||
          (e->count > 0 && e->u && e->v && (!weights || e->w));
@@ -160,10 +173,10 @@ void dc_server::run() {
     for (Request* r : round) {
       Graph& g = *all[size_t(r->gid)];
       try {
+        // every admitted request reserves its estimated bytes, so several
+        // requests of one round never share the same headroom
         if (r->init) {
-          // estimate of a new graph's footprint: its CSR twice, its
-          // per-vertex arrays and batch scratch
-          const int64_t need = 24 * int64_t(2 * g.edges) + 160 * int64_t(r->n);
+          const int64_t need = est_init_bytes(r->n, g.edges);
           if (budget > 0 && need > budget) {
             finish(r, DC_E_OOM);
             continue;
@@ -172,20 +185,28 @@ void dc_server::run() {
             deferred.push_back(r);
             continue;
           }
-        } else if (!g.resident) {
+          resident_bytes += need;
+        } else {
+          const int64_t changes = int64_t(r->au.size() + r->du.size());
+          int64_t want = est_step_bytes(r->n, g.edges + int64_t(r->au.size()), changes);
+          if (want < g.footprint) want = g.footprint;
           if (budget > 0 && g.footprint > budget) {
             finish(r, DC_E_OOM);
             continue;
           }
-          if (!admit(g, g.footprint, all)) {
+          if (budget > 0 && want > budget) want = budget;  // runs with nothing else resident
+          const int64_t need = g.resident ? want - g.footprint : want;
+          if (!admit(g, need, all)) {
             deferred.push_back(r);
             continue;
           }
-          ctx_restore(g.ctx, g.saved);
-          g.saved = SavedState{};
-          g.resident = true;
-          resident_bytes += g.footprint;
-          stats.restores++;
+          resident_bytes += need;
+          if (!g.resident) {
+            ctx_restore(g.ctx, g.saved);
+            g.saved = SavedState{};
+            g.resident = true;
+            stats.restores++;
+          }
         }
         r->start_ns = mono_ns();
         run_now.push_back(r);
@@ -233,6 +254,19 @@ void dc_server::run() {
           finish(r, s);
           continue;
         }
+        if (c->opt.algorithm == DC_ALGO_SLM) {
+          // SLM refines level 0 after its local moving: its levels run whole
+          run_levels(c, act, nact);
+          r->C.resize(size_t(c->n));
+          apply_output(c, r->C.data(), 0);
+          c->stats.ms_total = std::chrono::duration<double, std::milli>(
+                                  std::chrono::steady_clock::now().time_since_epoch())
+                                  .count() -
+                              r->t0_ms;
+          r->stats = c->stats;
+          finish(r, DC_OK);
+          continue;
+        }
         LevelRun L;
         levels_begin(c, act, nact, L);
         cs.push_back(c);
@@ -274,6 +308,7 @@ void dc_server::run() {
           finish(r, DC_E_DEVICE);
         }
       }
+      for (size_t j = 0; j < swept.size(); ++j) all[size_t(swept[j]->gid)]->edges = cs[j]->nnz / 2;
       if (swept.size() > 1) stats.merged_rounds++;
       stats.merged_graphs += int64_t(swept.size());
     }

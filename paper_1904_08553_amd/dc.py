@@ -20,6 +20,7 @@ PENDING = 1
 MODE_DELTA, MODE_ALL, MODE_STATIC, MODE_LEARNED = 0, 1, 2, 3
 MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 8, 64, 4801
 DEL_GAIN, DEL_CONSERVATIVE = 0, 1
+ALGO_LOUVAIN, ALGO_SLM = 0, 1
 STATUS = {
     0: "OK", -1: "ARG", -2: "RANGE", -3: "SELF_LOOP", -4: "WEIGHT", -5: "NO_EDGE",
     -6: "DUP", -7: "OVERFLOW", -8: "OOM", -9: "DEVICE", -10: "STATE",
@@ -32,7 +33,7 @@ class Options(ct.Structure):
         ("singleton_guard", ct.c_int32), ("del_rule", ct.c_int32), ("timing", ct.c_int32),
         ("tau_den", ct.c_int64), ("stream", ct.c_void_p), ("collect", ct.c_int32),
         ("full_coarsen", ct.c_int32), ("cascade_num", ct.c_int64), ("cascade_den", ct.c_int64),
-        ("reserved", ct.c_int64 * 1),
+        ("algorithm", ct.c_int32), ("reserved", ct.c_int32),
     ]
 
 
@@ -47,7 +48,7 @@ class SweepRec(ct.Structure):
     _fields_ = [
         ("level", ct.c_int32), ("sweep", ct.c_int32), ("n_level", ct.c_int32),
         ("n_active", ct.c_int32), ("nnz_level", ct.c_int64), ("moves", ct.c_int64),
-        ("dN", ct.c_int64), ("kept", ct.c_int32), ("pad", ct.c_int32),
+        ("dN", ct.c_int64), ("kept", ct.c_int32), ("phase", ct.c_int32),
     ]
 
 
@@ -231,11 +232,14 @@ def current_stream():
 
 def options(mode=MODE_DELTA, max_levels=32, max_sweeps=100, singleton_guard=1,
             del_rule=DEL_GAIN, timing=0, tau_den=1_000_000, stream="current", collect=0,
-            full_coarsen=0, cascade=None):
+            full_coarsen=0, cascade=None, algorithm=None):
     """cascade: None (off) or (num, den) for the cascade-aware screening
-    threshold theta = num/den."""
+    threshold theta = num/den.  algorithm: ALGO_LOUVAIN (default) or
+    ALGO_SLM, the host method of the levels."""
     o = Options()
     load().dc_default_options(ct.byref(o))
+    if algorithm is not None:
+        o.algorithm = algorithm
     o.mode, o.max_levels, o.max_sweeps = mode, max_levels, max_sweeps
     o.singleton_guard, o.del_rule, o.timing, o.tau_den = singleton_guard, del_rule, timing, tau_den
     o.collect = collect
@@ -328,8 +332,9 @@ class DynamicCommunities:
         _check(load().dc_last_trace(self._h, None, 0, ct.byref(cnt)), "dc_last_trace")
         recs = (SweepRec * max(cnt.value, 1))()
         _check(load().dc_last_trace(self._h, recs, cnt.value, ct.byref(cnt)), "dc_last_trace")
+        # SLM refinement sweeps carry their phase as a ninth field
         return [(r.level, r.sweep, r.n_level, r.n_active, r.nnz_level, r.moves, r.dN, r.kept)
-                for r in recs[: cnt.value]]
+                + ((r.phase,) if r.phase else ()) for r in recs[: cnt.value]]
 
     def last_stats(self):
         st = StepStats()

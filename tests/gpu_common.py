@@ -12,13 +12,17 @@ MODES = {"delta": (O.MODE_DELTA, dc.MODE_DELTA), "all": (O.MODE_ALL, dc.MODE_ALL
 
 
 def make_pair(n, u, v, w, mode="delta", max_levels=32, max_sweeps=100, guard=1,
-              del_rule=0, tau_den=1_000_000, cascade=None):
+              del_rule=0, tau_den=1_000_000, cascade=None, slm=False):
+    """The oracle and the GPU library on the same graph and options (slm:
+    the smart local moving levels instead of Louvain's)."""
     om, gm = MODES[mode]
     o = O.Oracle(n, u, v, w, mode=om, max_levels=max_levels, max_sweeps=max_sweeps,
-                 singleton_guard=guard, del_rule=del_rule, tau_den=tau_den, cascade=cascade)
+                 singleton_guard=guard, del_rule=del_rule, tau_den=tau_den, cascade=cascade,
+                 algorithm=O.ALGO_SLM if slm else O.ALGO_LOUVAIN)
     g = dc.DynamicCommunities(n, u, v, w, mode=gm, max_levels=max_levels,
                               max_sweeps=max_sweeps, singleton_guard=guard, del_rule=del_rule,
-                              tau_den=tau_den, cascade=cascade)
+                              tau_den=tau_den, cascade=cascade,
+                              algorithm=dc.ALGO_SLM if slm else dc.ALGO_LOUVAIN)
     return o, g
 
 

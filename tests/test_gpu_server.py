@@ -116,17 +116,42 @@ def test_server_small_budget_evicts_and_matches():
     assert stats["evictions"] > 0 and stats["restores"] > 0
 
 
-def test_server_matches_oracle():
-    """One graph of the mix followed by the oracle, batch by batch."""
-    sizes = [2500, 6000, 4000]
-    _log("case: server vs oracle")
+def _oracle_labels(streams):
+    """Every graph's C_t after each batch, from the CPU oracle alone."""
+    res = []
+    for n, (u, v, w), batches in streams:
+        o = O.Oracle(n, u, v, w)
+        cs = []
+        for b in batches:
+            o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+            cs.append(o.C.copy())
+        o.close()
+        res.append(cs)
+    return res
+
+
+@pytest.mark.parametrize("budget_frac", [0.0, 0.5])
+def test_server_matches_oracle(budget_frac):
+    """Every graph of a merged mix (several graphs' level-0 sweeps in one
+    launch per bin, and with a small budget also evicted and restored)
+    equals the oracle batch by batch."""
+    sizes = [2500, 6000, 4000, 9000, 3000]
+    _log(f"case: server vs oracle, every graph, budget fraction {budget_frac}")
     streams = _streams(sizes, 3, seed0=970)
-    mix, _ = _mix(streams, 0, 3, order_seed=4)
-    n, (u, v, w), batches = streams[0]
-    o = O.Oracle(n, u, v, w)
-    for t, b in enumerate(batches):
-        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
-        assert np.array_equal(mix[0][t], o.C), f"batch {t}"
+    budget = 0
+    if budget_frac > 0:
+        _, full = _mix(streams, 0, 5, order_seed=5)
+        budget = int(budget_frac * full["peak_resident_bytes"])
+    mix, stats = _mix(streams, budget, 5, order_seed=4)
+    _log(f"  stats {stats}")
+    want = _oracle_labels(streams)
+    for j in range(len(streams)):
+        for t in range(3):
+            assert np.array_equal(mix[j][t], want[j][t]), f"graph {j} batch {t}"
+    assert stats["merged_rounds"] > 0
+    if budget > 0:
+        assert stats["evictions"] > 0 and stats["restores"] > 0
+        assert stats["peak_resident_bytes"] <= budget
 
 
 def test_server_batch_error_and_recovery():
