@@ -371,6 +371,21 @@ dc_status dc_mlp_forward(dc_mlp* m, const uint16_t* X, int64_t n, float* logits)
  * arrays grad[DC_MLP_PARAMS] and *loss (either may be NULL).  No update. */
 dc_status dc_mlp_grad(dc_mlp* m, const uint16_t* X, const uint8_t* y, int64_t n,
                       float pos_weight, float* grad, double* loss);
+/* dc_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, the same result bit for bit, but the
+ * per-block partial sums and the reduced gradient live in a fixed device
+ * array of the library (2.5 MB per device: 128 blocks of DC_MLP_PARAMS + 1
+ * floats plus the gradient), held by each device the library runs on until
+ * the process ends; nothing is allocated.  The gradient kernel launches at
+ * most 128 blocks for any n, so every n >= 1 fits; a scratch need above the
+ * array would be rejected with DC_E_ARG (dc_last_error names the sizes).
+ * Inputs and outputs as dc_mlp_grad (X, y on the device; grad, loss on the
+ * host, either may be NULL).  All calls on one device share that array:
+ * calls that overlap on one device (other host threads, other streams)
+ * race and must be serialised by the caller. */
+dc_status dc_mlp_grad_noalloc(dc_mlp* m, const uint16_t* X, const uint8_t* y, int64_t n,
+                              float pos_weight, float* grad, double* loss);
 /* One Adam step of learning rate lr on the same loss; *loss (may be NULL)
  * receives the loss before the step. */
 dc_status dc_mlp_train_step(dc_mlp* m, const uint16_t* X, const uint8_t* y,

@@ -15,6 +15,9 @@
 // permutation, so no transpose is needed between layers.  The weight
 // gradients contract over samples and go through a 2 KB LDS transpose per
 // operand.
+#include <mutex>
+#include <string>
+
 #include "learned.h"
 
 #include <cmath>
@@ -413,10 +416,12 @@ inline int grid_for(int64_t n, int64_t cap = 16384) {
   return int(g < 1 ? 1 : g);
 }
 
+constexpr int GRAD_BLOCKS_MAX = 128;
+
 inline int grad_blocks(int64_t n) {
   // a fixed function of n, so the summation order (and the result) is too
   int64_t b = ceil_div(ceil_div(n, 16), NW);
-  if (b > 128) b = 128;
+  if (b > GRAD_BLOCKS_MAX) b = GRAD_BLOCKS_MAX;
   return int(b < 1 ? 1 : b);
 }
 
@@ -493,6 +498,40 @@ void mlp_adam(float* w, float* m, float* v, const float* grad, int step, float l
 
 using namespace dc;
 
+namespace {
+
+// Scratch of dc_mlp_grad_noalloc, a file-scope device array: the per-block
+// partial sums (at most GRAD_BLOCKS_MAX blocks of GRAD_SLOTS floats, the most
+// the gradient kernel launches for any n) followed by the reduced gradient.
+// Every device that runs the library holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel: it stands for
+// a host-side symbol there; the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_dev.
+constexpr size_t NOALLOC_PARTIAL = size_t(GRAD_BLOCKS_MAX) * GRAD_SLOTS;
+constexpr size_t NOALLOC_FLOATS = NOALLOC_PARTIAL + GRAD_SLOTS;
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[MAX_DEVICES] = {};
+
+// The current device's address of `scratch` (looked up on the first call
+// on that device, with that device current).
+float* scratch_on_current_device() {
+  int dev = 0;
+  DC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw std::runtime_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    DC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = static_cast<float*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+
+}  // namespace
+
 struct dc_mlp {
   hipStream_t st = nullptr;
   DBuf w, m, v, wq, grad, partial;
@@ -500,9 +539,11 @@ struct dc_mlp {
   int step = 0;
 };
 
-namespace {
+namespace dc_core {
+extern thread_local std::string g_last_error;  // text of dc_last_error (api.hip)
+}  // namespace dc_core
 
-thread_local std::string g_mlp_error;
+namespace {
 
 template <class F>
 dc_status mlp_guarded(dc_mlp* m, F&& f) {
@@ -510,7 +551,7 @@ dc_status mlp_guarded(dc_mlp* m, F&& f) {
   try {
     return f();
   } catch (const DeviceError& e) {
-    g_mlp_error = e.what();
+    dc_core::g_last_error = e.what();
     return (e.code == hipErrorOutOfMemory || e.code == hipErrorMemoryAllocation) ? DC_E_OOM
                                                                                 : DC_E_DEVICE;
   } catch (const std::bad_alloc&) {
@@ -553,6 +594,7 @@ dc_status dc_mlp_create(dc_mlp** out, const float* w, void* stream) {
   m->st = static_cast<hipStream_t>(stream);
   dc_status s = mlp_guarded(m, [&] {
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&m->hgrad), GRAD_SLOTS * 4));
+    (void)scratch_on_current_device();  // set-up of dc_mlp_grad_noalloc's scratch
     upload_weights(m, w);
     return DC_OK;
   });
@@ -596,6 +638,28 @@ dc_status dc_mlp_grad(dc_mlp* m, const uint16_t* X, const uint8_t* y, int64_t n,
   return mlp_guarded(m, [&] {
     run_grad(m, X, y, n, pos_weight);
     DC_HIP(hipMemcpyAsync(m->hgrad, m->grad.p, GRAD_SLOTS * 4, hipMemcpyDeviceToHost, m->st));
+    DC_HIP(hipStreamSynchronize(m->st));
+    if (grad) std::memcpy(grad, m->hgrad, MLP_P * 4);
+    if (loss) *loss = double(m->hgrad[MLP_P]) / double(n);
+    return DC_OK;
+  });
+}
+
+dc_status dc_mlp_grad_noalloc(dc_mlp* m, const uint16_t* X, const uint8_t* y, int64_t n,
+                              float pos_weight, float* grad, double* loss) {
+  if (n < 1 || !X || !y || !(pos_weight > 0.f)) return DC_E_ARG;
+  return mlp_guarded(m, [&] {
+    const int64_t partial = mlp_partial_floats(n);
+    if (partial > int64_t(NOALLOC_PARTIAL)) {
+      dc_core::g_last_error = "dc_mlp_grad_noalloc: " + std::to_string(partial) +
+                    " partial sums exceed the fixed scratch of " +
+                    std::to_string(NOALLOC_PARTIAL);
+      return DC_E_ARG;
+    }
+    float* base = scratch_on_current_device();
+    float* g = base + NOALLOC_PARTIAL;
+    mlp_grad(m->wq.as<uint16_t>(), X, y, n, pos_weight, base, g, m->st);
+    DC_HIP(hipMemcpyAsync(m->hgrad, g, GRAD_SLOTS * 4, hipMemcpyDeviceToHost, m->st));
     DC_HIP(hipStreamSynchronize(m->st));
     if (grad) std::memcpy(grad, m->hgrad, MLP_P * 4);
     if (loss) *loss = double(m->hgrad[MLP_P]) / double(n);

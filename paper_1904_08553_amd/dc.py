@@ -74,7 +74,7 @@ EXPORTS = [
     "dc_last_R", "dc_last_trace", "dc_last_stats", "dc_num_entries", "dc_export_csr",
     "dc_destroy", "dc_strerror", "dc_last_error", "dc_screener_set", "dc_last_samples",
     "dc_mlp_create", "dc_mlp_set_weights", "dc_mlp_get_weights", "dc_mlp_forward", "dc_mlp_grad",
-    "dc_mlp_train_step", "dc_mlp_destroy", "dc_export_state", "dc_init_from_state",
+    "dc_mlp_grad_noalloc", "dc_mlp_train_step", "dc_mlp_destroy", "dc_export_state", "dc_init_from_state",
     "dc_server_create", "dc_server_add_graph", "dc_server_submit", "dc_server_poll",
     "dc_server_stats_get", "dc_server_destroy",
 ]
@@ -149,6 +149,8 @@ def load(path: str = LIB_PATH):
     L.dc_mlp_forward.restype = i32
     L.dc_mlp_grad.argtypes = [P, P, P, i64, f32, P, f64p]
     L.dc_mlp_grad.restype = i32
+    L.dc_mlp_grad_noalloc.argtypes = [P, P, P, i64, f32, P, f64p]
+    L.dc_mlp_grad_noalloc.restype = i32
     L.dc_mlp_train_step.argtypes = [P, P, P, i64, f32, f32, f64p]
     L.dc_mlp_train_step.restype = i32
     L.dc_mlp_destroy.argtypes = [P]
@@ -537,6 +539,17 @@ class MLP:
         _check(load().dc_mlp_grad(self._h, self._dev(X, "X"), self._dev(y, "y"), X.shape[0],
                                   float(pos_weight), g.ctypes.data, ct.byref(loss)),
                "dc_mlp_grad")
+        return loss.value, g
+
+    def grad_noalloc(self, X, y, pos_weight):
+        """grad() through dc_mlp_grad_noalloc: the library's fixed device
+        scratch instead of allocated buffers (same result)."""
+        g = np.empty(MLP_PARAMS, np.float32)
+        loss = ct.c_double()
+        _check(load().dc_mlp_grad_noalloc(self._h, self._dev(X, "X"), self._dev(y, "y"),
+                                          X.shape[0], float(pos_weight), g.ctypes.data,
+                                          ct.byref(loss)),
+               "dc_mlp_grad_noalloc")
         return loss.value, g
 
     def train_step(self, X, y, pos_weight, lr, want_loss=False):
