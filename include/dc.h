@@ -185,6 +185,25 @@ typedef struct dc_step_stats {
   int64_t cascade_candidates; /* same-community neighbours of accepted
                                  addition sources examined by the cascade  */
   int64_t cascade_expanded;   /* those whose neighbourhood joined R_t      */
+  /* timing = 1, dc_apply_batch only: device time (hipEvents on the call's
+     stream) and algorithmic HBM bytes of the step's phases:
+       [0] batch ingest and graph update: 12 B per change read + 16 B per
+           change placed as two directed entries (the merge's rewrite of
+           the whole CSR is implementation traffic, not counted);
+       [1] screening (DELTA): 12 B per entry of the screened vertices' rows
+           + 32 B per screened vertex + 20 B per insertion record (the
+           gain2 of the mirror record) + 8 B per entry of the accepted
+           sources' rows + 5 B per vertex and 4 B per member of R_t;
+       [2] level-0 sweeps: 12 B per entry of the evaluated rows + 32 B per
+           evaluated vertex (apply and Delta N included in the time);
+       [3] compaction, levels >= 1 and the canonical labels: 12 B per entry
+           and 32 B per vertex of every sweep above level 0 + 12 B per
+           level-0 vertex for the labels.                               */
+  double ms_phase[4];
+  int64_t bytes_phase[4];
+  int64_t screen_volume;      /* entries of the screened vertices' rows      */
+  int64_t screen_vertices;    /* vertices the screening pass evaluated       */
+  int64_t accepted_volume;    /* entries of the accepted sources' rows       */
 } dc_step_stats;
 
 typedef struct dc_ctx dc_ctx;

@@ -98,6 +98,11 @@ void ensure_sample_state(dc_ctx* c) {
   c->X.ensure(n * 16);
 }
 
+// Phase boundary k of a timed step (see dc_step_stats.ms_phase).
+void mark_phase(dc_ctx* c, int k) {
+  if (c->phase_timing) DC_HIP(hipEventRecord(c->evp[k], c->st));
+}
+
 // Raises when a kernel's self-check failed (the context is then poisoned).
 void check_stat_errors(const long long* h) {
   if (h[ST_ERR] & 1) throw std::runtime_error("hub-row hash tables larger than their buffer");
@@ -318,6 +323,7 @@ void run_levels_slm(dc_ctx* c, const int32_t* active, int64_t n_active) {
   int32_t* par = c->par.as<int32_t>();
   int level = 0;
   (void)run_sweeps(c, g, L.act, L.nact, L.bins, 0, T, true, npre > 0);
+  mark_phase(c, 3);
   while (true) {
     // 2. communities after the local moving
     DC_HIP(hipMemsetAsync(stat + ST_N0, 0, 8, st));
@@ -401,6 +407,7 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
   }
   levels_begin(c, active, n_active, L, skip);
   const long long gain0 = run_sweeps(c, L.g, L.act, L.nact, L.bins, 0, L.T, true, npre > 0);
+  mark_phase(c, 3);
   levels_finish(c, L, gain0);
 }
 
@@ -555,6 +562,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   const int32_t n = c->n;
   long long* stat = c->stat.as<long long>();
   long long* hs = c->hstat;
+  mark_phase(c, 0);
   DC_HIP(hipMemsetAsync(stat, 0, ST_COUNT * 8, st));
   c->pre_count = 0;
   const int32_t *au, *av, *aw, *du, *dv, *dw;
@@ -633,9 +641,11 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   read_stat(c);
   const int64_t nnz_new = *static_cast<int32_t*>(c->hbuf);
   const int64_t n_ins = nch > 0 ? int32_t(hs[ST_N2]) : 0;
+  c->n_ins_last = n_ins;
   c->adj[nxt].ensure(size_t(nnz_new + 1) * 8);
   merge_rows(off_old, adj_old, c->nnz, off_new, c->adj[nxt].as<int2>(), n, cptr,
              c->tile_row.as<int32_t>(), ch_key, ch_op, ch_w, cnet, nch, st);
+  mark_phase(c, 1);
   c->cur = nxt;
   c->nnz = nnz_new;
   c->two_m = two_m_new;
@@ -715,6 +725,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       if (n_u > 0) {
         Bins b;
         make_bins(c->ulist.as<int32_t>(), n_u, g0.off, b, c->bins, st);
+        for (int q = 0; q < NBINS; ++q) S.screen_volume += b.vol[q];
+        S.screen_vertices = n_u;
         int32_t* pre = nullptr;
         if (mode == DC_MODE_DELTA) {
           c->pre.ensure(size_t(n) * 4);
@@ -736,6 +748,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       if (n_src > 0) {
         Bins b;
         make_bins(c->src_list.as<int32_t>(), n_src, g0.off, b, c->bins, st);
+        for (int q = 0; q < NBINS; ++q) S.screen_volume += b.vol[q];
+        S.screen_vertices = n_src;
         ds_additions(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, ins_keys, n_ins,
                      c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), b, R, cflag, accflag,
                      dsx, stat, st);
@@ -786,6 +800,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     S.del_accepted = c->opt.del_rule == DC_DEL_CONSERVATIVE ? n_dsrc : hs[ST_DEL_ACC];
     S.R_size = c->R_count;
     S.cascade_expanded = hs[ST_CASC_EXP];
+    S.accepted_volume = hs[ST_ACCVOL];
     S.vertex_evals += S.ds_sources + S.del_sources + S.cascade_candidates;
   }
   if (samples) {
@@ -811,6 +826,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     }
   }
   c->inc_ready = true;
+  mark_phase(c, 2);
   if (mode == DC_MODE_DELTA || mode == DC_MODE_LEARNED) {
     c->have_R_all = false;
     load_level0_partition(c);
@@ -835,14 +851,43 @@ void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device) {
   DC_HIP(hipStreamSynchronize(c->st));
 }
 
+// Device time and algorithmic bytes of a timed step's phases (the bytes of
+// each phase as documented with dc_step_stats.ms_phase).
+void phase_stats(dc_ctx* c) {
+  dc_step_stats& S = c->stats;
+  DC_HIP(hipEventSynchronize(c->evp[4]));
+  for (int k = 0; k < 4; ++k) {
+    float ms = 0.f;
+    DC_HIP(hipEventElapsedTime(&ms, c->evp[k], c->evp[k + 1]));
+    S.ms_phase[k] = ms;
+  }
+  S.bytes_phase[0] = 28 * S.changes;
+  if (c->opt.mode == DC_MODE_DELTA) {
+    S.bytes_phase[1] = 12 * S.screen_volume + 32 * S.screen_vertices + 20 * c->n_ins_last +
+                       8 * S.accepted_volume + 5 * int64_t(c->n) + 4 * S.R_size;
+  }
+  S.bytes_phase[2] = 12 * S.level0_volume + 32 * S.level0_active;
+  int64_t upper = 12 * int64_t(c->n);
+  for (const dc_sweep_rec& r : c->trace)
+    if (r.level > 0 || r.phase != 0) upper += 12 * r.nnz_level + 32 * int64_t(r.n_active);
+  S.bytes_phase[3] = upper;
+}
+
 dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t* C_out,
                    int32_t out_on_device) {
   const int32_t* act = nullptr;
   int64_t nact = 0;
+  c->phase_timing = c->opt.timing != 0;
   const dc_status s = apply_front(c, add, del, &act, &nact);
-  if (s != DC_OK) return s;
+  if (s != DC_OK) {
+    c->phase_timing = false;
+    return s;
+  }
   run_levels(c, act, nact);
   apply_output(c, C_out, out_on_device);
+  mark_phase(c, 4);
+  if (c->phase_timing) phase_stats(c);
+  c->phase_timing = false;
   return DC_OK;
 }
 
@@ -878,6 +923,8 @@ void destroy_ctx(dc_ctx* c) {
   if (c->cs.host) (void)hipHostFree(c->cs.host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->evp)
+    if (e) (void)hipEventDestroy(e);
   if (c->bins.side) {
     (void)hipStreamSynchronize(c->bins.side);
     (void)hipStreamDestroy(c->bins.side);
@@ -984,49 +1031,94 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
   std::vector<const Bins*> bl(static_cast<size_t>(m));
   for (int j = 0; j < m; ++j) bl[size_t(j)] = &Ls[j].bins;
   build_multi_bins(bl.data(), m, X.mb, X.hsegs, X.segs, st);
+  int max_sw = 1;
+  int64_t max_nact = 1;
+  for (int j = 0; j < m; ++j) {
+    max_sw = std::max(max_sw, cs[j]->opt.max_sweeps);
+    max_nact = std::max<int64_t>(max_nact, Ls[j].nact);
+  }
   X.descs.ensure(size_t(m) * sizeof(EvalArgs));
+  X.gdesc.ensure(size_t(m) * sizeof(MergedGraph));
   X.done.ensure(size_t(m) * 4);
+  X.sweeps.ensure(size_t(m) * 4);
+  X.rec.ensure(size_t(m) * size_t(max_sw) * 3 * 8);
+  long long* rec = X.rec.as<long long>();
   for (int j = 0; j < m; ++j) {
     dc_ctx* c = cs[j];
-    X.hdescs[j] = sweep_args(Ls[j].g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
-                             c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m,
-                             c->opt.singleton_guard, c->stat.as<long long>());
-    X.hdone[j] = 0;
+    const LevelRun& L = Ls[j];
+    X.hdescs[j] = sweep_args_bins(L.g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
+                                  c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m,
+                                  c->opt.singleton_guard, c->stat.as<long long>(), L.bins);
+    MergedGraph& G = X.hgdesc[j];
+    G.off = L.g.off;
+    G.adj = L.g.adj;
+    G.k = L.g.k;
+    G.C = c->Cl.as<int32_t>();
+    G.Cn = c->Cn.as<int32_t>();
+    G.a = c->al.as<int32_t>();
+    G.sz = c->szl.as<int32_t>();
+    G.act = L.act;
+    G.nact = L.nact;
+    G.dpack = c->dpack.as<long long>();
+    G.tflag = c->lflag.as<int32_t>();
+    G.tlist = c->tlist.as<int32_t>();
+    G.movers = c->movers.as<int32_t>();
+    G.stat = c->stat.as<long long>();
+    G.two_m = c->two_m;
+    G.T = L.T;
+    G.max_sweeps = c->opt.max_sweeps;
+    G.pad = 0;
+    G.rec = rec + size_t(j) * size_t(max_sw) * 3;
     gains[j] = 0;
   }
   DC_HIP(hipMemcpyAsync(X.descs.p, X.hdescs, size_t(m) * sizeof(EvalArgs),
                         hipMemcpyHostToDevice, st));
-  std::vector<int> sweep(static_cast<size_t>(m), 0);
-  int live = m;
-  while (live > 0) {
-    // the flags were last read by the previous round, which has completed
-    DC_HIP(hipMemcpyAsync(X.done.p, X.hdone, size_t(m) * 4, hipMemcpyHostToDevice, st));
-    for (int j = 0; j < m; ++j)
-      if (!X.hdone[j]) sweep_reset(cs[j]->stat.as<long long>(), st);
-    sweep_eval_multi(X.descs.as<EvalArgs>(), X.done.as<int32_t>(), X.mb, st);
-    for (int j = 0; j < m; ++j) {
-      if (X.hdone[j]) continue;
-      dc_ctx* c = cs[j];
-      const LevelRun& L = Ls[j];
-      sweep_eval_bin_g(L.g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
-                       c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, L.bins,
-                       c->stat.as<long long>(), st);
-      sweep_apply(L.g, L.act, L.nact, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(),
-                  c->al.as<int32_t>(), c->szl.as<int32_t>(), c->two_m, c->movers.as<int32_t>(),
-                  c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
-                  c->stat.as<long long>(), st);
-      DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipMemcpyAsync(X.gdesc.p, X.hgdesc, size_t(m) * sizeof(MergedGraph),
+                        hipMemcpyHostToDevice, st));
+  int32_t* state = X.done.as<int32_t>();
+  int32_t* sweeps = X.sweeps.as<int32_t>();
+  const MergedGraph* G = X.gdesc.as<MergedGraph>();
+  {
+    void* zp[2] = {state, sweeps};
+    const int64_t zb[2] = {4 * int64_t(m), 4 * int64_t(m)};
+    zero_buffers(zp, zb, 2, st);
+  }
+  // Rounds run without host waits: convergence is decided on the device
+  // (the state words); the host reads the states every `batch` rounds.
+  int32_t* hstate = X.hdone;
+  int32_t* hsweeps = X.hdone + m;
+  int batch = 2, rounds = 0;
+  while (true) {
+    for (int r = 0; r < batch; ++r) {
+      merged_reset(G, m, state, st);
+      sweep_eval_multi(X.descs.as<EvalArgs>(), state, X.mb, st);
+      merged_apply(G, m, max_nact, state, sweeps, st);
     }
-    DC_HIP(hipStreamSynchronize(st));  // one wait for every graph of the round
-    for (int j = 0; j < m; ++j) {
-      if (X.hdone[j]) continue;
-      check_stat_errors(cs[j]->hstat);
-      if (sweep_account(cs[j], Ls[j].g, 0, sweep[size_t(j)], Ls[j].bins, Ls[j].T, true, -1.f,
-                        gains[j])) {
-        X.hdone[j] = 1;
-        --live;
-      }
-      sweep[size_t(j)]++;
+    rounds += batch;
+    DC_HIP(hipMemcpyAsync(hstate, state, size_t(m) * 4, hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    bool all = true;
+    for (int j = 0; j < m; ++j) all = all && hstate[j] != 0;
+    if (all || rounds >= max_sw) break;
+    batch = std::min(2 * batch, max_sw - rounds);
+  }
+  // the sweep records and the status blocks (self-check bits), one wait
+  DC_HIP(hipMemcpyAsync(hsweeps, sweeps, size_t(m) * 4, hipMemcpyDeviceToHost, st));
+  std::vector<long long> hrec(size_t(m) * size_t(max_sw) * 3);
+  DC_HIP(hipMemcpyAsync(hrec.data(), rec, hrec.size() * 8, hipMemcpyDeviceToHost, st));
+  for (int j = 0; j < m; ++j)
+    DC_HIP(hipMemcpyAsync(cs[j]->hstat, cs[j]->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < m; ++j) {
+    dc_ctx* c = cs[j];
+    check_stat_errors(c->hstat);
+    const long long* r = hrec.data() + size_t(j) * size_t(max_sw) * 3;
+    for (int s = 0; s < hsweeps[j]; ++s) {
+      c->hstat[ST_MOVES] = r[3 * s];
+      c->hstat[ST_DN] = r[3 * s + 1];
+      c->hstat[ST_KEEP] = r[3 * s + 2];
+      (void)sweep_account(c, Ls[j].g, 0, s, Ls[j].bins, Ls[j].T, true, -1.f, gains[j],
+                          Ls[j].nact);
     }
   }
 }
@@ -1050,6 +1142,7 @@ dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) 
     DC_HIP(hipHostMalloc(&c->cs.host, 64));
     DC_HIP(hipEventCreate(&c->ev0));
     DC_HIP(hipEventCreate(&c->ev1));
+    for (hipEvent_t& e : c->evp) DC_HIP(hipEventCreate(&e));
     DC_HIP(hipStreamCreateWithFlags(&c->bins.side, hipStreamNonBlocking));
     DC_HIP(hipEventCreateWithFlags(&c->bins.fork, hipEventDisableTiming));
     DC_HIP(hipEventCreateWithFlags(&c->bins.join, hipEventDisableTiming));

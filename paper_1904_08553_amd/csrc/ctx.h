@@ -49,6 +49,8 @@ struct dc_ctx {
   BinScratch bins;
   CoarsenScratch cs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evp[5] = {};      // phase boundaries of a timed dc_apply_batch
+  bool phase_timing = false;   // record them (dc_apply_batch with timing = 1)
   std::vector<dc_sweep_rec> trace;
   dc_step_stats stats{};
   int64_t R_count = 0;
@@ -56,6 +58,7 @@ struct dc_ctx {
   // graph of communities kept across steps (incremental level-0 compaction)
   IncCoarsen inc;
   int64_t nch_last = 0;     // change records of the current batch
+  int64_t n_ins_last = 0;   // its directed insertion records
   bool inc_ready = false;   // they belong to the step being run
 };
 
@@ -82,10 +85,11 @@ struct SavedState {
 // Scratch of merged level-0 sweeps over several contexts.
 struct MergeScratch {
   MultiBins mb;
-  DBuf descs, done, segs;
-  EvalArgs* hdescs = nullptr;  // pinned, cap entries
-  int32_t* hdone = nullptr;    // pinned, cap entries
-  MultiSeg* hsegs = nullptr;   // pinned, NBINS * cap entries
+  DBuf descs, done, segs, gdesc, sweeps, rec;
+  EvalArgs* hdescs = nullptr;     // pinned, cap entries
+  int32_t* hdone = nullptr;       // pinned, 2 * cap entries: states, then sweep counts
+  MultiSeg* hsegs = nullptr;      // pinned, NBINS * cap entries
+  MergedGraph* hgdesc = nullptr;  // pinned, cap entries
   int cap = 0;
 };
 

@@ -28,6 +28,7 @@ enum StatSlot : int {
   ST_CASC_EXP = 20,   // cascade candidates whose neighbourhood joined R
   ST_ERR = 21,        // self-checks of the kernels (bit 0: a hub-row table past its buffer)
   ST_MARK = 22,       // Alg. 2: accepted row chunks listed for marking
+  ST_ACCVOL = 23,     // Alg. 2: entries of the accepted sources' rows
   ST_WSUM_ADD = 24,   // inserted weight: SUM_SLOTS counters
   ST_WSUM_DEL = ST_WSUM_ADD + SUM_SLOTS,  // deleted weight: SUM_SLOTS counters
   ST_COUNT = ST_WSUM_DEL + SUM_SLOTS
@@ -227,12 +228,46 @@ void cascade_mark(const int32_t* list, int64_t cnt, const long long* f_g1, const
 
 
 // ---- merged sweeps of several graphs (one launch per row-length bin) ----
-// Bins S16..B of several graphs concatenated, each graph's part padded to
-// whole waves (list entry -1), with the graph index of every item.
+// The bins of several graphs concatenated, each graph's part padded to whole
+// waves (list entry -1), with the graph index of every item; for the
+// hub-row bin also the item's index within its graph's bin (its hash-table
+// slice).
 struct MultiBins {
-  DBuf list[NBINS - 1], gid[NBINS - 1];
-  int64_t count[NBINS - 1] = {};
+  DBuf list[NBINS], gid[NBINS], lidx;
+  int64_t count[NBINS] = {};
 };
+
+// One graph's level-0 sweep state for the merged bookkeeping kernels
+// (merged.hip): its level graph, labels, totals, active list, scratch of the
+// moves, status block, threshold T, sweep limit and the device record of
+// its sweeps (moves, Delta N, kept: three int64 per sweep).
+struct MergedGraph {
+  const int32_t* off;
+  const int2* adj;
+  const int32_t* k;
+  int32_t* C;
+  int32_t* Cn;
+  int32_t* a;
+  int32_t* sz;
+  const int32_t* act;  // null: every vertex of [0, nact)
+  int64_t nact;
+  long long* dpack;
+  int32_t* tflag;
+  int32_t* tlist;
+  int32_t* movers;
+  long long* stat;
+  long long two_m;
+  long long T;
+  int32_t max_sweeps;
+  int32_t pad;
+  long long* rec;
+};
+// state[j]: 0 running, 1 stopped in the current round, 2 stopped.
+void merged_reset(const MergedGraph* G, int m, int32_t* state, hipStream_t st);
+// Apply, exact Delta N, keep / revert / stop and commit of one sweep of every
+// running graph (max_nact: the longest active list).
+void merged_apply(const MergedGraph* G, int m, int64_t max_nact, int32_t* state,
+                  int32_t* sweeps, hipStream_t st);
 struct MultiSeg {  // one graph's bin, for build_multi_bins
   const int32_t* src;
   int64_t n, padded, dst;
@@ -246,13 +281,15 @@ EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int
 void build_multi_bins(const Bins* const* bins, int ngraphs, MultiBins& mb, MultiSeg* segs_host,
                       DBuf& segs_dev, hipStream_t st);
 // One sweep evaluation of every graph j with done[j] == 0 over the merged
-// bins (descs[j]: its sweep arguments, device memory); graph j's bin G runs
-// separately (sweep_eval_bin_g).
+// bins, the hub-row bin included (descs[j]: its sweep arguments with its
+// hub-row tables, device memory).
 void sweep_eval_multi(const EvalArgs* descs, const int32_t* done, const MultiBins& mb,
                       hipStream_t st);
-void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
-                      const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                      long long* stat, hipStream_t st);
+// The sweep arguments of graph j's level with its hub-row tables.
+EvalArgs sweep_args_bins(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                         const int32_t* sz, long long two_m, int guard, long long* stat,
+                         const Bins& bins);
+
 
 // Per listed vertex i: f_own[i] = e_{i->C(i)}, f_g1[i] / f_g2[i] = scaled
 // gains to the best / second-best other neighbouring community (score

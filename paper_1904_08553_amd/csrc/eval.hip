@@ -811,9 +811,39 @@ __global__ void __launch_bounds__(TPB) k_sweep_btab_multi(MultiArgs M) {
   }
 }
 
+// bin G: one 1024-thread block per hub row of any graph (k_eval_gtab's
+// evaluation; the row's global-table slice from its graph's own tables)
+__global__ void __launch_bounds__(GTPB)
+    k_sweep_gtab_multi(MultiArgs M, const int32_t* __restrict__ lidx) {
+  __shared__ int keys[BTAB_SLOTS];
+  __shared__ int vals[BTAB_SLOTS];
+  __shared__ GroupLds<GTPB> L;
+  __shared__ int own;
+  __shared__ int tstate[2];
+  const int64_t idx = blockIdx.x;
+  if (idx >= M.count) return;
+  const int g = M.gid[idx];  // uniform over the block
+  if (M.done[g]) return;
+  const EvalArgs A = M.descs[g];
+  const int i = M.list[idx];
+  const int64_t q = lidx[idx];
+  const long long acc = eval_table<EV_SWEEP, GTPB, GT_UI, 8, true>(A, i, keys, vals,
+                                                                    BTAB_SLOTS - 1, L, &own, tstate);
+  if (acc == TABLE_FULL) {
+    const long long o0 = A.tab_off[q], o1 = A.tab_off[q + 1];
+    if (o1 > A.gslots) {
+      if (threadIdx.x == 0) atomicOr((unsigned long long*)&A.stat[ST_ERR], 1ull);
+      return;
+    }
+    (void)eval_table<EV_SWEEP, GTPB, 4, 8>(A, i, A.gkeys + o0, A.gvals + o0,
+                                           uint32_t(o1 - o0) - 1, L, &own);
+  }
+}
+
 struct MultiDst {
-  int32_t* list[NBINS - 1];
-  int32_t* gid[NBINS - 1];
+  int32_t* list[NBINS];
+  int32_t* gid[NBINS];
+  int32_t* lidx;  // bin G: position in the graph's own bin
 };
 
 // block per segment: copy a graph's bin list into its merged slot, padding
@@ -826,6 +856,7 @@ __global__ void k_build_multi(const MultiSeg* __restrict__ segs, int nsegs, Mult
     for (int64_t i = threadIdx.x; i < sg.padded; i += blockDim.x) {
       lst[i] = i < sg.n ? sg.src[i] : -1;
       gd[i] = sg.gid;
+      if (sg.bin == NBINS - 1) D.lidx[sg.dst + i] = int32_t(i);
     }
   }
 }
@@ -998,7 +1029,7 @@ __global__ void __launch_bounds__(TPB)
   __shared__ long long bbase;
   const int lane = lane_id(), wid = threadIdx.x / WAVE;
   const uint64_t n0 = uint64_t(A.n0);
-  long long accepted = 0;
+  long long accepted = 0, accvol = 0;
   for (int64_t base = int64_t(blockIdx.x) * TPB; base < A.n_ins;
        base += int64_t(gridDim.x) * TPB) {  // block-uniform
     const int64_t q = base + threadIdx.x;
@@ -1016,6 +1047,7 @@ __global__ void __launch_bounds__(TPB)
         accepted += 1;
         rb = A.off[i];
         re = A.off[i + 1];
+        accvol += re - rb;
         nit = int(ceil_div(re - rb, MARK_CHUNK));
       }
     }
@@ -1044,6 +1076,7 @@ __global__ void __launch_bounds__(TPB)
     __syncthreads();  // wsum and bbase are rewritten by the next tile
   }
   block_add(accepted, &A.stat[ST_DS_ACC]);
+  block_add(accvol, &A.stat[ST_ACCVOL]);
 }
 
 // R of every entry of the listed row chunks [x, y): one wave per chunk.
@@ -1363,9 +1396,9 @@ EvalArgs sweep_args(const LevelView& g, const int32_t* C, int32_t* Cn, const int
 
 void build_multi_bins(const Bins* const* bins, int ngraphs, MultiBins& mb, MultiSeg* segs_host,
                       DBuf& segs_dev, hipStream_t st) {
-  constexpr int PAD[NBINS - 1] = {WAVE / 16, WAVE / 32, 1, 1, 1};
+  constexpr int PAD[NBINS] = {WAVE / 16, WAVE / 32, 1, 1, 1, 1};
   int nsegs = 0;
-  for (int q = 0; q < NBINS - 1; ++q) {
+  for (int q = 0; q < NBINS; ++q) {
     int64_t off = 0;
     for (int j = 0; j < ngraphs; ++j) {
       const int64_t n = bins[j]->n[q];
@@ -1378,15 +1411,17 @@ void build_multi_bins(const Bins* const* bins, int ngraphs, MultiBins& mb, Multi
     mb.list[q].ensure(size_t(off + 1) * 4);
     mb.gid[q].ensure(size_t(off + 1) * 4);
   }
+  mb.lidx.ensure(size_t(mb.count[NBINS - 1] + 1) * 4);
   if (nsegs == 0) return;
   segs_dev.ensure(size_t(nsegs) * sizeof(MultiSeg));
   DC_HIP(hipMemcpyAsync(segs_dev.p, segs_host, size_t(nsegs) * sizeof(MultiSeg),
                         hipMemcpyHostToDevice, st));
   MultiDst D;
-  for (int q = 0; q < NBINS - 1; ++q) {
+  for (int q = 0; q < NBINS; ++q) {
     D.list[q] = mb.list[q].as<int32_t>();
     D.gid[q] = mb.gid[q].as<int32_t>();
   }
+  D.lidx = mb.lidx.as<int32_t>();
   k_build_multi<<<nsegs, TPB, 0, st>>>(segs_dev.as<MultiSeg>(), nsegs, D);
   DC_LAUNCH_CHECK();
 }
@@ -1418,22 +1453,21 @@ void sweep_eval_multi(const EvalArgs* descs, const int32_t* done, const MultiBin
     k_sweep_btab_multi<<<int(nb), TPB, 0, st>>>(args(4));
     DC_LAUNCH_CHECK();
   }
+  if (mb.count[5] > 0) {
+    k_sweep_gtab_multi<<<int(mb.count[5]), GTPB, 0, st>>>(args(5), mb.lidx.as<int32_t>());
+    DC_LAUNCH_CHECK();
+  }
 }
 
-void sweep_eval_bin_g(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
-                      const int32_t* sz, long long two_m, int guard, const Bins& bins,
-                      long long* stat, hipStream_t st) {
-  constexpr int G = NBINS - 1;
-  if (bins.n[G] == 0) return;
+EvalArgs sweep_args_bins(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
+                         const int32_t* sz, long long two_m, int guard, long long* stat,
+                         const Bins& bins) {
   EvalArgs A = sweep_args(g, C, Cn, a, sz, two_m, guard, stat);
-  A.list = bins.list[G];
-  A.count = bins.count_dev + G;
   A.gkeys = bins.gkeys;
   A.gvals = bins.gvals;
   A.tab_off = bins.tab_off;
   A.gslots = bins.gslots;
-  k_eval_gtab<EV_SWEEP><<<bins.n[G], GTPB, 0, st>>>(A);
-  DC_LAUNCH_CHECK();
+  return A;
 }
 
 }  // namespace dc

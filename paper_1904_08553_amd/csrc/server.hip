@@ -360,7 +360,9 @@ dc_status dc_server_create(dc_server** out, const dc_options* opt, int64_t budge
     s->X.cap = max_inflight;
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hdescs),
                          size_t(max_inflight) * sizeof(EvalArgs)));
-    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hdone), size_t(max_inflight) * 4));
+    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hdone), size_t(max_inflight) * 8));
+    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hgdesc),
+                         size_t(max_inflight) * sizeof(MergedGraph)));
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hsegs),
                          size_t(NBINS) * size_t(max_inflight) * sizeof(MultiSeg)));
   } catch (const DeviceError&) {
@@ -482,6 +484,7 @@ void dc_server_destroy(dc_server* s) {
   if (s->X.hdescs) (void)hipHostFree(s->X.hdescs);
   if (s->X.hdone) (void)hipHostFree(s->X.hdone);
   if (s->X.hsegs) (void)hipHostFree(s->X.hsegs);
+  if (s->X.hgdesc) (void)hipHostFree(s->X.hgdesc);
   if (s->st) (void)hipStreamDestroy(s->st);
   delete s;
 }

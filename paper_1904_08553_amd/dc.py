@@ -63,10 +63,17 @@ class StepStats(ct.Structure):
         ("level0_sweeps", ct.c_int64), ("level0_active", ct.c_int64),
         ("level0_volume", ct.c_int64), ("touched", ct.c_int64), ("screened", ct.c_int64),
         ("cascade_candidates", ct.c_int64), ("cascade_expanded", ct.c_int64),
+        ("ms_phase", ct.c_double * 4), ("bytes_phase", ct.c_int64 * 4),
+        ("screen_volume", ct.c_int64), ("screen_vertices", ct.c_int64),
+        ("accepted_volume", ct.c_int64),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        out = {}
+        for f, _ in self._fields_:
+            x = getattr(self, f)
+            out[f] = list(x) if isinstance(x, ct.Array) else x
+        return out
 
 
 EXPORTS = [
