@@ -89,6 +89,7 @@ def run_mode(mode, n, graph, batches_dev, warmup, steps, timing, **opt):
     lat, qs, rs, evals, changes = [], [], [], 0, 0
     k_ms = k_bytes = k_launch = 0
     sweeps = 0
+    ph_ms, ph_bytes = [0.0] * 4, [0] * 4
     t_start = time.perf_counter()
     for b in batches_dev[warmup:warmup + steps]:
         t = time.perf_counter()
@@ -103,6 +104,9 @@ def run_mode(mode, n, graph, batches_dev, warmup, steps, timing, **opt):
         k_ms += st.ms_sweep_kernel
         k_bytes += st.sweep_bytes
         k_launch += st.sweep_launches
+        for k in range(4):
+            ph_ms[k] += st.ms_phase[k]
+            ph_bytes[k] += st.bytes_phase[k]
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
     # the PCIe leg a host consumer of C_t adds per step (outside the timing)
@@ -113,108 +117,215 @@ def run_mode(mode, n, graph, batches_dev, warmup, steps, timing, **opt):
     copy_ms = (time.perf_counter() - t) * 1e3 / 5
     out = dict(g=g, init_ms=init_ms, init_q=init_stats.q, lat=lat, q=qs, R_frac=rs,
                evals=evals, changes=changes, total_s=total_s, sweeps=sweeps,
-               k_ms=k_ms, k_bytes=k_bytes, k_launch=k_launch, copy_ms=copy_ms)
+               k_ms=k_ms, k_bytes=k_bytes, k_launch=k_launch, copy_ms=copy_ms,
+               ph_ms=ph_ms, ph_bytes=ph_bytes)
     return out
 
 
+PHASES = ("ingest and graph update", "screening (Alg. 2 and the deletion rule)",
+          "level-0 sweeps (evaluate, apply, exact Delta N)",
+          "compaction, levels >= 1, canonical labels")
+
+
+def phase_table(r, steps):
+    """Per phase of a step: device time (hipEvents), algorithmic bytes and
+    the fraction of the 8 TB/s HBM peak they reach."""
+    out = []
+    for k, name in enumerate(PHASES):
+        ms = r["ph_ms"][k] / steps
+        b = r["ph_bytes"][k] / steps
+        gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out.append({"phase": name, "ms_per_step": ms, "bytes_per_step": b,
+                    "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS})
+    return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, graph, batches, cpu_steps):
-    """The oracle as it stands, one host thread, on the first batches."""
+    """The oracle as it stands, single-threaded and pinned to one host core,
+    on the first batches of the same stream, under Delta-screening and under
+    the full recompute (each after its own static run, which is not timed)."""
     from oracle import oracle as O
     if not os.path.exists(O.LIB):
         O.build()
     u, v, w = graph
-    t0 = time.perf_counter()
-    o = O.Oracle(n, u, v, w)
-    init_s = time.perf_counter() - t0
-    log(f"oracle init {init_s:.1f} s")
-    tot, ch = 0.0, 0
-    for b in batches[:cpu_steps]:
-        t = time.perf_counter()
-        o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
-        tot += time.perf_counter() - t
-        ch += b.size
-        log(f"oracle step {time.perf_counter() - t:.1f} s")
-    o.close()
-    return {"value": ch / tot, "unit": "edge updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"single-threaded oracle applying the first {cpu_steps} batch(es) "
-                      f"({ch} changes) of the same stream after its own static run on "
-                      f"G_1 ({init_s:.1f} s, not counted)",
-            "seconds": tot}
+    prev = os.sched_getaffinity(0)
+    core = min(prev)
+    os.sched_setaffinity(0, {core})
+    legs = {}
+    try:
+        for name, mode in (("delta", O.MODE_DELTA), ("all", O.MODE_ALL)):
+            t0 = time.perf_counter()
+            o = O.Oracle(n, u, v, w, mode=mode)
+            init_s = time.perf_counter() - t0
+            log(f"oracle {name}: static run {init_s:.1f} s")
+            tot, ch = 0.0, 0
+            for b in batches[:cpu_steps]:
+                t = time.perf_counter()
+                o.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+                tot += time.perf_counter() - t
+                ch += b.size
+                log(f"oracle {name}: step {time.perf_counter() - t:.1f} s")
+            o.close()
+            legs[name] = {"edge_updates_per_s": ch / tot, "seconds": tot, "changes": ch,
+                          "static_run_s": init_s}
+    finally:
+        os.sched_setaffinity(0, prev)
+    return {"value": legs["delta"]["edge_updates_per_s"], "unit": "edge updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"single-threaded oracle pinned to host core {core}, applying the first "
+                      f"{cpu_steps} batches ({legs['delta']['changes']} changes) of the same "
+                      f"stream after its own static run on G_1 (not counted); value = "
+                      f"Delta-screening, full_recompute = mode ALL on the same batches",
+            "full_recompute": legs["all"]["edge_updates_per_s"],
+            "legs": legs, "cpu_model": _cpu_model(), "host_cores": os.cpu_count()}
 
 
 def _serving_graph(args):
+    """Worker: one serving graph's G_1 and its batches, written as .npy files
+    into a shared-memory folder (the main process maps them)."""
+    import numpy as np
     from paper_1904_08553_amd import workloads as W
-    seed, batches, n_lo, n_hi = args
-    return W.serving_graph(seed, batches, n_lo=n_lo, n_hi=n_hi)
+    seed, batches, n_lo, n_hi, folder = args
+    s = W.ServingStream(seed, n_lo=n_lo, n_hi=n_hi)
+    u, v, w = s.graph()
+    bs = [s.next_batch() for _ in range(batches)]
+    cat = lambda f: np.concatenate([getattr(b, f) for b in bs]) if bs else np.empty(0, np.int32)
+    parts = {"u": u, "v": v, "w": w, "au": cat("add_u"), "av": cat("add_v"), "aw": cat("add_w"),
+             "du": cat("del_u"), "dv": cat("del_v"),
+             "na": np.array([len(b.add_u) for b in bs], np.int64),
+             "nd": np.array([len(b.del_u) for b in bs], np.int64)}
+    for k, a in parts.items():
+        np.save(os.path.join(folder, f"g{seed}_{k}.npy"), a)
+    return seed, s.n
 
 
-def serving_leg(graphs_k, arrivals, n_lo, n_hi, inflight, seed=0):
-    """Many resident graphs behind one server: closed-loop capacity with and
-    without merged rounds, then Poisson arrivals for per-batch latency."""
+def _load_serving_graph(folder, seed, n):
+    import numpy as np
+    from paper_1904_08553_amd import workloads as W
+    ld = lambda k: np.load(os.path.join(folder, f"g{seed}_{k}.npy"), mmap_mode="r")
+    na, nd = ld("na"), ld("nd")
+    ao = np.concatenate([[0], np.cumsum(na)])
+    do = np.concatenate([[0], np.cumsum(nd)])
+    au, av, aw, du, dv = ld("au"), ld("av"), ld("aw"), ld("du"), ld("dv")
+    bs = [W.Batch(au[ao[j]:ao[j + 1]], av[ao[j]:ao[j + 1]], aw[ao[j]:ao[j + 1]],
+                  du[do[j]:do[j + 1]], dv[do[j]:do[j + 1]]) for j in range(len(na))]
+    return n, (ld("u"), ld("v"), ld("w")), bs
+
+
+def serving_leg(graphs_k, arrivals, n_lo, n_hi, inflight, rate, warmup=None, budget_batches=600,
+                seed=0, workers=16):
+    """Many resident graphs behind one server (the serving workload: graphs_k
+    DC-SBM graphs, n log-uniform in [n_lo, n_hi], 20 edges per vertex,
+    batches of U[100K, 200K] changes, 60/40): closed-loop capacity one graph
+    per round and merged, Poisson arrivals at `rate` per second for latency
+    from arrival to C_t, and a run under a small memory budget (a quarter of
+    the unlimited run's peak) for admission and eviction."""
     import concurrent.futures as cf
     import multiprocessing as mp
+    import shutil
+    import tempfile
     import numpy as np
     from paper_1904_08553_amd import dc
     rng = np.random.default_rng(np.random.SeedSequence((seed, 77)))
-    pick = rng.integers(0, graphs_k, size=arrivals)
+    warmup = graphs_k if warmup is None else warmup
+    total = warmup + arrivals
+    # every graph gets one warm-up batch first (its buffers grow to their size),
+    # then the timed arrivals pick a graph uniformly
+    pick = np.concatenate([np.arange(graphs_k) % graphs_k if warmup == graphs_k
+                           else rng.integers(0, graphs_k, size=warmup),
+                           rng.integers(0, graphs_k, size=arrivals)])
     per = np.bincount(pick, minlength=graphs_k)
     t0 = time.perf_counter()
-    jobs = [(1000 + g, int(per[g]), n_lo, n_hi) for g in range(graphs_k)]
-    with cf.ProcessPoolExecutor(max_workers=8, mp_context=mp.get_context("spawn")) as ex:
-        graphs = list(ex.map(_serving_graph, jobs))
-    log(f"serving: {graphs_k} graphs, {arrivals} batches drawn in "
-        f"{time.perf_counter() - t0:.1f} s")
-    order = []  # (graph, its batch index) in arrival order
-    seen = [0] * graphs_k
-    for g in pick:
-        order.append((int(g), seen[g]))
-        seen[g] += 1
+    folder = tempfile.mkdtemp(prefix="dc_serving_", dir="/dev/shm" if os.path.isdir("/dev/shm")
+                              else None)
+    try:
+        jobs = [(1000 + g, int(per[g]), n_lo, n_hi, folder) for g in range(graphs_k)]
+        with cf.ProcessPoolExecutor(max_workers=workers,
+                                    mp_context=mp.get_context("spawn")) as ex:
+            sizes = dict(ex.map(_serving_graph, jobs))
+        graphs = [_load_serving_graph(folder, 1000 + g, sizes[1000 + g]) for g in range(graphs_k)]
+        ns = np.array([g[0] for g in graphs])
+        edges0 = int(sum(len(g[1][0]) for g in graphs))
+        log(f"serving: {graphs_k} graphs ({ns.sum()} vertices, {edges0} edges), {total} batches "
+            f"drawn in {time.perf_counter() - t0:.1f} s")
+        order = []  # (graph, its batch index) in arrival order
+        seen = [0] * graphs_k
+        for g in pick:
+            order.append((int(g), seen[g]))
+            seen[g] += 1
 
-    def run(max_inflight, gaps_ns):
-        srv = dc.Server(max_inflight=max_inflight)
-        gids = [srv.add_graph(n, u, v, w) for n, (u, v, w), _ in graphs]
-        base = time.monotonic_ns()
-        tickets = []
-        for (g, j), at in zip(order, gaps_ns):
-            due = base + int(at)
-            while time.monotonic_ns() < due:
-                pass
-            b = graphs[g][2][j]
-            tickets.append((g, b.size, srv.submit(gids[g], b.add_u, b.add_v, b.add_w, b.del_u,
-                                                  b.del_v, arrival_ns=due)))
-        lat, changes, first, last = [], 0, None, 0
-        for g, sz, tk in tickets:
-            _, _, (arr, start, done) = srv.poll(tk, gids[g])
-            lat.append((done - arr) / 1e6)
-            changes += sz
-            first = arr if first is None else min(first, arr)
-            last = max(last, done)
-        st = srv.stats()
-        srv.close()
-        span = (last - first) / 1e9
-        return dict(edge_updates_per_s=changes / span, batches_per_s=len(tickets) / span,
-                    latency_ms={"p50": percentile(lat, 50), "p99": percentile(lat, 99),
-                                "max": max(lat)},
-                    seconds=span, rounds=st["rounds"], merged_rounds=st["merged_rounds"],
-                    graphs_per_round=st["merged_graphs"] / max(st["rounds"], 1),
-                    peak_resident_bytes=st["peak_resident_bytes"])
+        def run(max_inflight, gaps_ns, budget=0, count=None):
+            srv = dc.Server(max_inflight=max_inflight, budget_bytes=budget)
+            gids = [srv.add_graph(n, u, v, w) for n, (u, v, w), _ in graphs]
+            events = order[:warmup + (arrivals if count is None else count)]
+            # warm-up batches, then the timed ones
+            for g, j in events[:warmup]:
+                b = graphs[g][2][j]
+                srv.poll(srv.submit(gids[g], b.add_u, b.add_v, b.add_w, b.del_u, b.del_v),
+                         gids[g])
+            st0 = srv.stats()
+            base = time.monotonic_ns()
+            tickets = []
+            for (g, j), at in zip(events[warmup:], gaps_ns):
+                due = base + int(at)
+                while time.monotonic_ns() < due:
+                    pass
+                b = graphs[g][2][j]
+                tickets.append((g, b.size, srv.submit(gids[g], b.add_u, b.add_v, b.add_w,
+                                                      b.del_u, b.del_v, arrival_ns=due)))
+            lat, changes, first, last = [], 0, None, 0
+            for g, sz, tk in tickets:
+                _, _, (arr, start, done) = srv.poll(tk, gids[g])
+                lat.append((done - arr) / 1e6)
+                changes += sz
+                first = arr if first is None else min(first, arr)
+                last = max(last, done)
+            st = srv.stats()
+            srv.close()
+            span = (last - first) / 1e9
+            rounds = st["rounds"] - st0["rounds"]
+            return dict(batches=len(tickets), changes=changes,
+                        edge_updates_per_s=changes / span, batches_per_s=len(tickets) / span,
+                        latency_ms={"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                                    "max": max(lat)},
+                        seconds=span, rounds=rounds,
+                        merged_rounds=st["merged_rounds"] - st0["merged_rounds"],
+                        graphs_per_round=(st["merged_graphs"] - st0["merged_graphs"])
+                        / max(rounds, 1),
+                        evictions=st["evictions"], restores=st["restores"],
+                        peak_resident_bytes=st["peak_resident_bytes"], budget_bytes=budget)
 
-    zero = [0] * len(order)
-    out = {"workload": f"{graphs_k} DC-SBM graphs, n log-uniform in [{n_lo}, {n_hi}], 20 "
-                       f"edges per vertex; {arrivals} batches of U[100K, 200K] changes (60/40), "
-                       f"graph uniform per arrival",
-           "closed_loop_sequential": run(1, zero),
-           "closed_loop_merged": run(inflight, zero)}
-    cap = out["closed_loop_merged"]["batches_per_s"]
-    rate = 0.7 * cap
-    gaps = np.cumsum(rng.exponential(1e9 / rate, size=arrivals))
-    poisson = run(inflight, gaps)
-    poisson["arrival_rate_per_s"] = rate
-    out["poisson_70pct_capacity"] = poisson
-    out["max_inflight"] = inflight
-    out["merged_over_sequential"] = (out["closed_loop_merged"]["edge_updates_per_s"]
-                                     / out["closed_loop_sequential"]["edge_updates_per_s"])
-    return out
+        zero = [0] * arrivals
+        out = {"workload": f"{graphs_k} DC-SBM graphs, n log-uniform in [{n_lo}, {n_hi}] "
+                           f"({int(ns.min())}..{int(ns.max())}, {int(ns.sum())} vertices, "
+                           f"{edges0} edges), 20 edges per vertex; {arrivals} timed batches of "
+                           f"U[100K, 200K] changes (60/40) after {warmup} warm-up batches, "
+                           f"graph uniform per arrival",
+               "closed_loop_sequential": run(1, zero),
+               "closed_loop_merged": run(inflight, zero)}
+        gaps = np.cumsum(rng.exponential(1e9 / rate, size=arrivals))
+        poisson = run(inflight, gaps)
+        poisson["arrival_rate_per_s"] = rate
+        out["poisson"] = poisson
+        budget = out["closed_loop_merged"]["peak_resident_bytes"] // 4
+        out["small_budget"] = run(inflight, zero[:budget_batches], budget=budget,
+                                  count=budget_batches)
+        out["max_inflight"] = inflight
+        out["merged_over_sequential"] = (out["closed_loop_merged"]["edge_updates_per_s"]
+                                         / out["closed_loop_sequential"]["edge_updates_per_s"])
+        return out
+    finally:
+        shutil.rmtree(folder, ignore_errors=True)
 
 
 def temporal_leg(n, events, steps, blocks):
@@ -292,16 +403,18 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-full", action="store_true", help="skip the full-recompute replay")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-screener leg")
-    ap.add_argument("--learned-seeds", type=int, default=4)
+    ap.add_argument("--learned-seeds", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-cascade", action="store_true",
                     help="skip the cascade-aware screening replay of the main batches")
-    ap.add_argument("--serving-graphs", type=int, default=12)
-    ap.add_argument("--serving-batches", type=int, default=360)
-    ap.add_argument("--serving-nmax", type=int, default=200_000)
+    ap.add_argument("--serving-graphs", type=int, default=64)
+    ap.add_argument("--serving-batches", type=int, default=5000)
+    ap.add_argument("--serving-nmax", type=int, default=2_000_000)
     ap.add_argument("--serving-inflight", type=int, default=8)
+    ap.add_argument("--serving-rate", type=float, default=500.0,
+                    help="Poisson arrivals per second of the serving leg")
     ap.add_argument("--temporal", action="store_true",
                     help="also run the paper-scale temporal stream (minutes of host time)")
     ap.add_argument("--temporal-n", type=int, default=8_000_000)
@@ -353,7 +466,7 @@ def main():
     if not args.no_full:
         d["g"].close()
         log("full-recompute run")
-        res_full = run_mode(dc.MODE_ALL, args.n, graph, batches_dev, args.warmup, args.steps, 0)
+        res_full = run_mode(dc.MODE_ALL, args.n, graph, batches_dev, args.warmup, args.steps, 1)
         res_full["g"].close()
     else:
         d["g"].close()
@@ -428,14 +541,17 @@ def main():
             "launches": d["k_launch"], "avg_launch_us": d["k_ms"] * 1e3 / d["k_launch"],
             "bytes_per_launch": d["k_bytes"] / d["k_launch"],
             "instruction_issue": measured_issue(),
+            "phases_delta": phase_table(d, args.steps),
         }
+        if res_full is not None:
+            out["roofline"]["phases_full"] = phase_table(res_full, args.steps)
     if not args.no_learned:
         log("learned-screener leg")
         out["learned"] = learned_leg(list(range(10000, 10000 + args.learned_seeds)))
     if not args.no_serving:
         log("serving leg")
         out["serving"] = serving_leg(args.serving_graphs, args.serving_batches, 10_000,
-                                     args.serving_nmax, args.serving_inflight)
+                                     args.serving_nmax, args.serving_inflight, args.serving_rate)
     if args.temporal:
         log("temporal-stream leg")
         out["temporal"] = temporal_leg(args.temporal_n, args.temporal_events, 12,

@@ -514,6 +514,87 @@ def serving_graph(seed, batches, n=None, n_lo=10_000, n_hi=2_000_000, size_lo=10
     return n, (u, v, w), out
 
 
+def _distinct_pairs(sampler, count, rng):
+    """``count`` distinct canonical pairs (no self-loops) from ``sampler``,
+    in a seeded random order."""
+    got = np.empty(0, np.int64)
+    for _ in range(64):
+        need = count - len(got)
+        if need <= 0:
+            break
+        u, v = sampler(rng, int(need * 1.3) + 64)
+        ok = u != v
+        got = np.union1d(got, _key(u[ok], v[ok]))
+    if len(got) < count:
+        raise RuntimeError("could not draw enough distinct pairs")
+    return got[rng.permutation(len(got))[:count]]
+
+
+class ServingStream:
+    """One graph of the serving workload at full scale, drawn in time
+    proportional to each batch.  A universe of distinct pairs is drawn once
+    from the degree-corrected SBM of the 1M/20M stream (20 edges per vertex,
+    max(10, n/1000) blocks, weights in [1, 8]): the first 20 n pairs form G_1,
+    the other ``reserve`` x 20 n are absent and form the pool new edges come
+    from.  A batch of U[size_lo, size_hi] changes (``ins_frac`` insertions;
+    deletions at most 40% of the current edges; insertions at most the pool)
+    deletes present pairs and inserts absent ones, each chosen uniformly, so
+    every insertion is a non-edge of the current graph and every deletion an
+    edge of it; deleted pairs return to the pool."""
+
+    def __init__(self, seed, n=None, n_lo=10_000, n_hi=2_000_000, reserve=0.5):
+        r = _rng(seed, 61)
+        if n is None:
+            n = int(round(np.exp(r.uniform(np.log(n_lo), np.log(n_hi)))))
+        self.n = int(n)
+        gen = DCSBM(n=self.n, m=0, blocks=max(10, self.n // 1000), dmax=min(5000, self.n // 2),
+                    seed=seed)
+        m0 = 20 * self.n
+        total = int(round(m0 * (1 + reserve)))
+        keys = _distinct_pairs(gen._sampler, total, _rng(seed, 62))
+        self.u, self.v = _unkey(keys)
+        self.w = _rng(seed, 63).integers(1, 9, total).astype(np.int32)
+        # present / absent pairs as index lists with room for every pair
+        self.present = np.empty(total, np.int64)
+        self.absent = np.empty(total, np.int64)
+        self.present[:m0] = np.arange(m0)
+        self.absent[: total - m0] = np.arange(m0, total)
+        self.np_, self.na_ = m0, total - m0
+        self.rng = _rng(seed, 64)
+
+    def graph(self):
+        idx = self.present[: self.np_]
+        return self.u[idx], self.v[idx], self.w[idx]
+
+    @staticmethod
+    def _take(arr, length, k, rng):
+        """k uniform distinct entries of arr[:length]; the hole they leave is
+        filled from the tail.  Returns (taken, new length)."""
+        if k <= 0:
+            return np.empty(0, np.int64), length
+        pos = np.sort(rng.choice(length, size=k, replace=False))
+        taken = arr[pos].copy()
+        new_len = length - k
+        holes = pos[pos < new_len]
+        tail = np.arange(new_len, length)
+        movers = tail[~np.isin(tail, pos, assume_unique=True)]
+        arr[holes] = arr[movers]
+        return taken, new_len
+
+    def next_batch(self, size_lo=100_000, size_hi=200_000, ins_frac=0.6):
+        r = self.rng
+        size = min(int(r.integers(size_lo, size_hi + 1)), self.np_)
+        n_del = min(int(round(size * (1 - ins_frac))), int(0.4 * self.np_))
+        n_ins = min(size - n_del, self.na_)
+        di, self.np_ = self._take(self.present, self.np_, n_del, r)
+        ai, self.na_ = self._take(self.absent, self.na_, n_ins, r)
+        self.present[self.np_: self.np_ + len(ai)] = ai
+        self.np_ += len(ai)
+        self.absent[self.na_: self.na_ + len(di)] = di
+        self.na_ += len(di)
+        return Batch(self.u[ai], self.v[ai], self.w[ai], self.u[di], self.v[di])
+
+
 def random_dynamic(n, m, steps, n_add, n_del, seed, wmax=3):
     """Uniform random graph and batches (used for tiny exhaustive tests)."""
     rng = _rng(seed, 31)
