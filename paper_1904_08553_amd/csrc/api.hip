@@ -701,27 +701,48 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
                         item_cap};
     int32_t* src_flag = c->src_flag.as<int32_t>();
     int32_t* src_pos = c->src_pos.as<int32_t>();
-    source_heads(ins_keys, n_ins, n, src_flag, st);
-    scan_excl_i32(src_flag, src_pos, n_ins, reinterpret_cast<int32_t*>(stat + ST_N3), st);
-    gather_sources(ins_keys, src_flag, src_pos, n_ins, n, c->src_list.as<int32_t>(), st);
-    source_segments(ins_keys, n_ins, n, c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(), st);
-    // deletion sources (labels C_{t-1})
-    deletion_sources(ch_key, ch_op, nch, n, c->C.as<int32_t>(), dflag, st);
+    // without the cascade the fused pass needs no list of insertion sources:
+    // its vertex set comes straight from the change list
+    const bool direct = fused && !cascade;
+    if (!direct) {
+      source_heads(ins_keys, n_ins, n, src_flag, st);
+      scan_excl_i32(src_flag, src_pos, n_ins, reinterpret_cast<int32_t*>(stat + ST_N3), st);
+      gather_sources(ins_keys, src_flag, src_pos, n_ins, n, c->src_list.as<int32_t>(), st);
+      source_segments(ins_keys, n_ins, n, c->seg_beg.as<int32_t>(), c->seg_end.as<int32_t>(),
+                      st);
+      // deletion sources (labels C_{t-1})
+      deletion_sources(ch_key, ch_op, nch, n, c->C.as<int32_t>(), dflag, st);
+    }
     int64_t n_src = 0, n_dsrc = 0;
     if (fused) {
       // one evaluation pass over the insertion sources and the deletion
       // endpoints together (Alg. 2 and the deletion rule read the same state)
       uint8_t* uflag = c->uflag.as<uint8_t>();
-      int32_t* f32 = c->rflag.as<int32_t>();
-      int32_t* p32 = c->rpos2.as<int32_t>();
-      union_flags(c->src_list.as<int32_t>(), reinterpret_cast<int32_t*>(stat + ST_N3), n_ins,
-                  dflag, n, uflag, f32, stat + ST_DEL_SRC, st);
-      scan_excl_i32(f32, p32, n, reinterpret_cast<int32_t*>(stat + ST_N0), st);
-      compact_index(f32, p32, n, c->ulist.as<int32_t>(), st);
-      read_stat(c);
-      n_src = n_ins > 0 ? int32_t(hs[ST_N3]) : 0;
-      n_dsrc = hs[ST_DEL_SRC];
-      const int64_t n_u = int32_t(hs[ST_N0]);
+      int64_t n_u = 0;
+      if (direct) {
+        // uflag, sink segments and the heads of the flagged sources in one
+        // pass over the sorted changes; the union list is the heads' sources
+        screen_union(ch_key, ch_op, c->ins_pos.as<int32_t>(), ins_keys, n_ins, nch, n,
+                     c->C.as<int32_t>(), dflag, uflag, c->seg_beg.as<int32_t>(),
+                     c->seg_end.as<int32_t>(), src_flag, stat + ST_NSRC, stat + ST_NDSRC, st);
+        scan_excl_i32(src_flag, src_pos, nch, reinterpret_cast<int32_t*>(stat + ST_N0), st);
+        gather_sources(ch_key, src_flag, src_pos, nch, n, c->ulist.as<int32_t>(), st);
+        read_stat(c);
+        n_src = slot_total(hs, ST_NSRC);
+        n_dsrc = slot_total(hs, ST_NDSRC);
+        n_u = nch > 0 ? int32_t(hs[ST_N0]) : 0;
+      } else {
+        int32_t* f32 = c->rflag.as<int32_t>();
+        int32_t* p32 = c->rpos2.as<int32_t>();
+        union_flags(c->src_list.as<int32_t>(), reinterpret_cast<int32_t*>(stat + ST_N3), n_ins,
+                    dflag, n, uflag, f32, stat + ST_DEL_SRC, st);
+        scan_excl_i32(f32, p32, n, reinterpret_cast<int32_t*>(stat + ST_N0), st);
+        compact_index(f32, p32, n, c->ulist.as<int32_t>(), st);
+        read_stat(c);
+        n_src = n_ins > 0 ? int32_t(hs[ST_N3]) : 0;
+        n_dsrc = hs[ST_DEL_SRC];
+        n_u = int32_t(hs[ST_N0]);
+      }
       if (n_u > 0) {
         Bins b;
         make_bins(c->ulist.as<int32_t>(), n_u, g0.off, b, c->bins, st);

@@ -31,7 +31,9 @@ enum StatSlot : int {
   ST_ACCVOL = 23,     // Alg. 2: entries of the accepted sources' rows
   ST_WSUM_ADD = 24,   // inserted weight: SUM_SLOTS counters
   ST_WSUM_DEL = ST_WSUM_ADD + SUM_SLOTS,  // deleted weight: SUM_SLOTS counters
-  ST_COUNT = ST_WSUM_DEL + SUM_SLOTS
+  ST_NSRC = ST_WSUM_DEL + SUM_SLOTS,      // screening set: Alg. 2 sources (SUM_SLOTS)
+  ST_NDSRC = ST_NSRC + SUM_SLOTS,         // and deletion endpoints (SUM_SLOTS)
+  ST_COUNT = ST_NDSRC + SUM_SLOTS
 };
 
 // The total of the SUM_SLOTS counters from `base` of a status block copy.
@@ -316,6 +318,18 @@ void source_segments(const uint64_t* keys, int64_t m, int32_t n, int32_t* seg_be
 // dflag[src] = 1 for deleted pairs inside one community.
 void deletion_sources(const uint64_t* ch_key, const int32_t* ch_op, int64_t nch, int32_t n,
                       const int32_t* C, int32_t* dflag, hipStream_t st);
+// The fused screening set from the sorted change list (labels C = C_{t-1}):
+// per source, uflag bit 0 (an insertion record: an Alg. 2 source, its sinks
+// ins_keys[seg_beg, seg_end), ins_pos locating each record there) and bit
+// 1 (an intra-community deletion); hflag[q] = 1 at the first change of
+// each flagged source (nch entries); n_src / n_dsrc (SUM_SLOTS counters
+// each) += the sources of each kind.  sbits (n ints) and uflag must be zero
+// beforehand.
+void screen_union(const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ins_pos,
+                  const uint64_t* ins_keys, int64_t n_ins, int64_t nch, int32_t n,
+                  const int32_t* C, int32_t* sbits, uint8_t* uflag, int32_t* seg_beg,
+                  int32_t* seg_end, int32_t* hflag, long long* n_src, long long* n_dsrc,
+                  hipStream_t st);
 // R[i] = 1 and R[Gamma(i)] = 1 for every listed vertex.
 void mark_neighbourhoods(const int32_t* list, int64_t cnt, const int32_t* off, const int2* adj,
                          uint8_t* R, hipStream_t st);

@@ -206,6 +206,31 @@ __device__ __forceinline__ Best group_best_first(Best b, int nd_max) {
   return b;
 }
 
+// Best Alg. 2 candidate of lanes [0, 2^steps) of each group, in the group's
+// first lane, as group_best_first: candidates sit in the first n lanes of a
+// group, n <= n_max (wave-uniform).
+template <int GS>
+__device__ __forceinline__ Cand group_cand_first(Cand c, int n_max) {
+  auto step = [](Cand v, auto s) {
+    constexpr int S = decltype(s)::value;
+    const Cand y = {xchg64<S>(v.g), xchg<S>(v.x), xchg<S>(v.j)};
+    return cand_better(y, v) ? y : v;
+  };
+  if (n_max > 1) c = step(c, std::integral_constant<int, 0>{});
+  if (n_max > 2) c = step(c, std::integral_constant<int, 1>{});
+  if (n_max > 4) c = step(c, std::integral_constant<int, 2>{});
+  if (GS > 8 && n_max > 8) c = step(c, std::integral_constant<int, 3>{});
+  if (GS > 16 && n_max > 16) c = step(c, std::integral_constant<int, 4>{});
+  if (GS > 32 && n_max > 32) {
+    const Cand y = {readlane64(c.g, 32), __builtin_amdgcn_readlane(c.x, 32),
+                    __builtin_amdgcn_readlane(c.j, 32)};
+    const Cand z = {readlane64(c.g, 0), __builtin_amdgcn_readlane(c.x, 0),
+                    __builtin_amdgcn_readlane(c.j, 0)};
+    c = cand_better(y, z) ? y : z;
+  }
+  return c;
+}
+
 // Accepted screening tests, counted in one integer: insertion sources (Alg.
 // 2, counted by k_ds_resolve) in the low 32 bits, deletion endpoints in the
 // high 32 bits.
@@ -361,6 +386,129 @@ __device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, i
   sweep_commit(A, i1, h1 && b1.x != NO_LABEL && b1.s > s1, c1, b1.x, gl);
 }
 
+// e_{i->X} for each lane that asks for label X (want): the rank of X among
+// its group's distinct labels (ck in the first nd lanes, their sums cs) is
+// found in LDS (lkey: the wave's 64 ints, overwritten), the sum read from
+// that lane; 0 when X is not among them.  iters: wave-uniform bound on nd.
+template <int GS>
+__device__ __forceinline__ int label_sum(int* lkey, int nd, int ck, int cs, bool want, int X,
+                                         int iters, int gl) {
+  const int lane = lane_id();
+  const int gbase = lane - gl;
+  lkey[lane] = gl < nd ? ck : EMPTY_KEY;
+  wave_sync();
+  int r = -1;
+  for (int t = 0; t < iters; ++t)
+    if (want && lkey[gbase + t] == X) r = t;
+  const int s = __shfl(cs, gbase + (r < 0 ? 0 : r), WAVE);
+  return r < 0 ? 0 : s;
+}
+
+// The screening pass (EV_DSBOTH) for two items per group, loads interleaved
+// as in sweep_pair: everything indexed by a vertex -- its row end, label,
+// degree, flags and sink segment -- is loaded with its row's entries, and
+// the sinks' labels with the entries' labels, before either item's labels
+// are grouped.  The arithmetic and the writes are group_item<EV_DSBOTH>'s:
+// per insertion source the gain toward each sink's label (stored per
+// record) and the best sink, the first-sweep decision when asked (pre), and
+// the deletion rule for a deletion endpoint.  Returns the deletion tests
+// accepted (in the groups' first lanes).
+template <int GS>
+__device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0,
+                                                 int i1, bool h1, int32_t rb1, int gl,
+                                                 int* lsum, int* lkey) {
+  const int32_t x0 = A.off[i0 + 1], x1 = A.off[i1 + 1];
+  const int c0 = A.C[i0], c1 = A.C[i1];
+  const int k0 = A.k[i0], k1 = A.k[i1];
+  const int uf0 = h0 ? int(A.uflag[i0]) : 0, uf1 = h1 ? int(A.uflag[i1]) : 0;
+  const int32_t sb0 = A.seg_beg[i0], se0 = A.seg_end[i0];
+  const int32_t sb1 = A.seg_beg[i1], se1 = A.seg_end[i1];
+  const int64_t last = A.nnz > 0 ? A.nnz - 1 : 0;
+  const int2 e0 = A.adj[rb0 + gl < last ? rb0 + gl : last];
+  const int2 e1 = A.adj[rb1 + gl < last ? rb1 + gl : last];
+  const int32_t re0 = h0 ? x0 : 0, re1 = h1 ? x1 : 0;
+  const bool in0 = rb0 + gl < re0, in1 = rb1 + gl < re1;
+  const bool v0 = in0 && e0.x != i0, v1 = in1 && e1.x != i1;
+  // an insertion source's sinks are row entries, so there are at most GS
+  const int ns0 = (uf0 & 1) ? se0 - sb0 : 0, ns1 = (uf1 & 1) ? se1 - sb1 : 0;
+  const bool s0 = gl < ns0, s1 = gl < ns1;
+  const uint64_t kq0 = A.ins_keys[s0 ? sb0 + gl : 0];
+  const uint64_t kq1 = A.ins_keys[s1 ? sb1 + gl : 0];
+  const int ao0 = A.a[c0], ao1 = A.a[c1];
+  const int y0 = A.C[v0 ? e0.x : 0], y1 = A.C[v1 ? e1.x : 0];
+  const int j0 = s0 ? int(kq0 - uint64_t(i0) * uint64_t(A.n0)) : 0;
+  const int j1 = s1 ? int(kq1 - uint64_t(i1) * uint64_t(A.n0)) : 0;
+  const int X0 = A.C[j0], X1 = A.C[j1];
+  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0, it0 = 0, it1 = 0;
+  const int nd0 = group_collect<GS>(v0, v0 ? y0 : EMPTY_KEY, e0.y, lsum, ck0, cs0, &it0);
+  const int nd1 = group_collect<GS>(v1, v1 ? y1 : EMPTY_KEY, e1.y, lsum, ck1, cs1, &it1);
+  const bool p0 = gl < nd0 && ck0 != c0, p1 = gl < nd1 && ck1 != c1;
+  const int ak0 = A.a[p0 ? ck0 : 0], ak1 = A.a[p1 ? ck1 : 0];
+  const int ax0 = A.a[X0], ax1 = A.a[X1];
+  const int own0 = group_pick<GS>(gl < nd0 && ck0 == c0, cs0);
+  const int own1 = group_pick<GS>(gl < nd1 && ck1 == c1, cs1);
+  const int tm = int(A.two_m);  // 2m < 2^31: 32x32->64 products
+  const long long so0 = (long long)tm * own0 - (long long)k0 * (ao0 - k0);
+  const long long so1 = (long long)tm * own1 - (long long)k1 * (ao1 - k1);
+  // Alg. 2: each sink's gain, stored per record, and the best sink per source
+  if (__ballot((uf0 | uf1) & 1)) {  // wave-uniform
+    const int ej0 = label_sum<GS>(lkey, nd0, ck0, cs0, s0, X0, it0, gl);
+    const int ej1 = label_sum<GS>(lkey + WAVE, nd1, ck1, cs1, s1, X1, it1, gl);
+    Cand d0 = {NO_SCORE, NO_LABEL, NO_LABEL}, d1 = {NO_SCORE, NO_LABEL, NO_LABEL};
+    if (s0) {
+      const long long g = X0 == c0 ? 0 : (long long)tm * ej0 - (long long)k0 * ax0 - so0;
+      A.sink_g[sb0 + gl] = g;
+      d0 = {g, X0, j0};
+    }
+    if (s1) {
+      const long long g = X1 == c1 ? 0 : (long long)tm * ej1 - (long long)k1 * ax1 - so1;
+      A.sink_g[sb1 + gl] = g;
+      d1 = {g, X1, j1};
+    }
+    d0 = group_cand_first<GS>(d0, wave_max(ns0));
+    d1 = group_cand_first<GS>(d1, wave_max(ns1));
+    if ((uf0 & 1) && gl == 0) {
+      const bool live = d0.j != NO_LABEL && d0.x != c0 && d0.g > 0;
+      A.best_j[i0] = live ? d0.j : -1;
+      if (live) A.best_g[i0] = d0.g;
+    }
+    if ((uf1 & 1) && gl == 0) {
+      const bool live = d1.j != NO_LABEL && d1.x != c1 && d1.g > 0;
+      A.best_j[i1] = live ? d1.j : -1;
+      if (live) A.best_g[i1] = d1.g;
+    }
+  }
+  // the best move: the first-sweep decision and the deletion rule
+  Best b0 = {NO_SCORE, NO_LABEL}, b1 = {NO_SCORE, NO_LABEL};
+  if (p0) b0 = {(long long)tm * cs0 - (long long)k0 * ak0, ck0};
+  if (p1) b1 = {(long long)tm * cs1 - (long long)k1 * ak1, ck1};
+  // (decided in each group's first lane)
+  b0 = group_best_first<GS>(b0, it0);
+  b1 = group_best_first<GS>(b1, it1);
+  const bool m0 = h0 && b0.x != NO_LABEL && b0.s > so0;
+  const bool m1 = h1 && b1.x != NO_LABEL && b1.s > so1;
+  if (A.pre && h0 && gl == 0) pre_commit(A, i0, m0, c0, b0.x);
+  if (A.pre && h1 && gl == 0) pre_commit(A, i1, m1, c1, b1.x);
+  long long accepted = 0;
+  const bool d0 = gl == 0 && m0 && (uf0 & 2), d1 = gl == 0 && m1 && (uf1 & 2);
+  if (__ballot(d0 || d1)) {  // wave-uniform; a deletion endpoint that would move
+    // its group's lanes mark the row (the leader's decision, broadcast)
+    if (group_pick<GS>(d0, 1) && in0) A.R[e0.x] = 1;
+    if (group_pick<GS>(d1, 1) && in1) A.R[e1.x] = 1;
+    if (d0) {
+      A.R[i0] = 1;
+      A.cflag[b0.x] = 1;
+      accepted += ACC_DEL;
+    }
+    if (d1) {
+      A.R[i1] = 1;
+      A.cflag[b1.x] = 1;
+      accepted += ACC_DEL;
+    }
+  }
+  return accepted;
+}
+
 template <int MODE, int GS>
 __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
   constexpr int GPW = WAVE / GS;  // groups per wave
@@ -387,6 +535,22 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
       const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
       sweep_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
     }
+    return;
+  }
+  if constexpr (MODE == EV_DSBOTH) {
+    __shared__ int lkey_all[NW][2 * WAVE];
+    for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
+      const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
+      const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
+      const int64_t j0 = h0 ? idx0 : 0, j1 = h1 ? idx1 : 0;
+      const int i0 = h0 ? A.list[j0] : 0;
+      const int i1 = h1 ? A.list[j1] : 0;
+      const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
+      accepted += screen_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls,
+                                  lkey_all[threadIdx.x / WAVE]);
+    }
+    accepted = group_sum_ll<WAVE>(accepted);
+    if (lane == 0 && accepted) add_accepted(A.stat, accepted);
     return;
   }
   for (int64_t wb = w0; wb < cnt; wb += ngroups) {
@@ -479,7 +643,7 @@ __device__ __forceinline__ uint32_t table_cap(int deg, uint32_t max_slots) {
 }
 
 constexpr int GTPB = 1024;  // threads of a bin-G block (one hub row per block)
-constexpr int GT_UI = 16;    // bin G: row chunks per load round
+constexpr int GT_UI = 8;     // bin G: row chunks per load round
 constexpr int WTAB_UI = WTAB_MAX / WAVE;   // bin W: the whole row in one load round
 constexpr int WTAB_US = 8;                 // and its table in rounds of 8 slots
 
@@ -529,6 +693,19 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
   const int32_t rb = A.off[i], re = A.off[i + 1];
   const int c = A.C[i];
   const long long ki = A.k[i];
+  // loaded now, used after the table is built: the own community's total
+  // and, for an insertion source, the sink segment and the labels and
+  // totals of its first G sinks
+  const int ac = A.a[c];
+  // EV_DSBOTH: bit 0 an insertion source (Alg. 2), bit 1 a deletion endpoint
+  const int uf = MODE == EV_DSBOTH ? int(A.uflag[i]) : (MODE == EV_DSADD ? 1 : 2);
+  const bool dsadd = (MODE == EV_DSADD || MODE == EV_DSBOTH) && (uf & 1);
+  const int64_t q0 = dsadd ? A.seg_beg[i] : 0, q1 = dsadd ? A.seg_end[i] : 0;
+  const uint64_t base = uint64_t(i) * uint64_t(A.n0);
+  const bool pf = q0 + t < q1;
+  const int pj = pf ? int(A.ins_keys[q0 + t] - base) : 0;
+  const int pX = pf ? A.C[pj] : 0;
+  const int paX = pf ? A.a[pX] : 0;
   for (uint32_t s = t; s <= mask; s += G) {
     keys[s] = EMPTY_KEY;
     vals[s] = 0;
@@ -570,28 +747,33 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
     }
   }
   long long e_own = own_part, unused = 0;
-  group_sum2<G>(e_own, unused, L);
+  if constexpr (G == WAVE)
+    e_own = wave_sum(int(own_part));  // at most k_i < 2m < 2^31: exact in 32 bits
+  else
+    group_sum2<G>(e_own, unused, L);
   group_sync<G>();
   if (BOUNDED && tstate[1]) return TABLE_FULL;  // group-uniform after the sync
   long long accepted = 0;
   // EV_DSBOTH: Alg. 2 for an insertion source (flag bit 0), then the
   // deletion rule for a deletion endpoint (bit 1), on the same table
-  const int uf = MODE == EV_DSBOTH ? int(A.uflag[i]) : (MODE == EV_DSADD ? 1 : 2);
-  if ((MODE == EV_DSADD || MODE == EV_DSBOTH) && (uf & 1)) {
-    const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
-    const int64_t q0 = A.seg_beg[i], q1 = A.seg_end[i];
-    const uint64_t base = uint64_t(i) * uint64_t(A.n0);
+  if (dsadd) {
+    const long long s_own = A.two_m * e_own - ki * (ac - ki);
     Cand best = {NO_SCORE, NO_LABEL, NO_LABEL};
     for (int64_t q = q0 + t; q < q1; q += G) {
-      const int j = int(A.ins_keys[q] - base);
-      const int X = A.C[j];
+      const bool first = q == q0 + t;  // the prefetched sink
+      const int j = first ? pj : int(A.ins_keys[q] - base);
+      const int X = first ? pX : A.C[j];
+      const int aX = first ? paX : A.a[X];
       long long g = 0;
-      if (X != c) g = A.two_m * table_get(keys, vals, mask, X) - ki * A.a[X] - s_own;
+      if (X != c) g = A.two_m * table_get(keys, vals, mask, X) - ki * aX - s_own;
       A.sink_g[q] = g;
       Cand cd = {g, X, j};
       if (cand_better(cd, best)) best = cd;
     }
-    best = group_cand<G>(best, L);
+    if constexpr (G == WAVE)  // the sinks sit in the first lanes (one vertex per wave)
+      best = group_cand_first<WAVE>(best, q1 - q0 < WAVE ? int(q1 - q0) : WAVE);
+    else
+      best = group_cand<G>(best, L);
     if (t == 0) {
       const bool live = best.j != NO_LABEL && best.x != c && best.g > 0;
       A.best_j[i] = live ? best.j : -1;
@@ -603,7 +785,7 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
   Best b = table_best<G, US>(A, keys, vals, mask, ki, EMPTY_KEY, t);
   b = group_best<G>(b, L);
   group_sync<G>();
-  const long long s_own = A.two_m * e_own - ki * (A.a[c] - ki);
+  const long long s_own = A.two_m * e_own - ki * (ac - ki);
   if (MODE == EV_FEAT) {
     // the table holds only foreign labels; a second scan skips the best
     Best b2 = table_best<G, US>(A, keys, vals, mask, ki, b.x, t);
@@ -1112,15 +1294,18 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     A.list_rb = bins.list_rb[q];
     A.count = bins.count_dev + q;
   };
+  // items a group takes per loop round: two in the sweep and the screening
+  // pass (their loads interleaved); a wave holds 64 / GS groups
+  constexpr int PAIR = (MODE == EV_SWEEP || MODE == EV_DSBOTH) ? 2 : 1;
   if (bins.n[0] > 0) {
     setbin(0);
-    k_eval_group<MODE, 16><<<wave_grid(ceil_div(bins.n[0], 4)), TPB, 0, st>>>(A);
+    k_eval_group<MODE, 16><<<wave_grid(ceil_div(bins.n[0], 4 * PAIR)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
   if (bins.n[1] > 0) {
     setbin(1);
     if (ev0) DC_HIP(hipEventRecord(ev0, st));
-    k_eval_group<MODE, 32><<<wave_grid(ceil_div(bins.n[1], 2)), TPB, 0, st>>>(A);
+    k_eval_group<MODE, 32><<<wave_grid(ceil_div(bins.n[1], 2 * PAIR)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
     if (ev1) DC_HIP(hipEventRecord(ev1, st));
   }
@@ -1145,7 +1330,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   }
   if (bins.n[2] > 0) {
     setbin(2);
-    k_eval_group<MODE, 64><<<wave_grid(bins.n[2]), TPB, 0, st>>>(A);
+    k_eval_group<MODE, 64><<<wave_grid(ceil_div(bins.n[2], PAIR)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
   if (bins.n[3] > 0) {
@@ -1283,7 +1468,8 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
 // every record's gain stored): resolve, then mark the accepted rows.
 void ds_resolve(const EvalArgs& A, const DsScratch& X, hipStream_t st) {
   if (A.n_ins <= 0) return;
-  k_ds_resolve<<<grid_for(A.n_ins, 2048), TPB, 0, st>>>(A, X.items, X.item_count);
+  // (each block adds its counts with one atomic per counter: few blocks)
+  k_ds_resolve<<<grid_for(A.n_ins, 512), TPB, 0, st>>>(A, X.items, X.item_count);
   DC_LAUNCH_CHECK();
   // chunks: at most one per source plus one per MARK_CHUNK entries of G_t
   const int64_t cap = X.item_cap;

@@ -79,6 +79,62 @@ __global__ void k_deletion_sources(const uint64_t* __restrict__ key,
   }
 }
 
+// The screening set of the fused pass straight from the sorted change list,
+// one thread per change.  First pass: the change's kind goes into its
+// source's word sbits (bit 0: an insertion record, op != OP_DELETE, so the
+// source is an Alg. 2 source; bit 1: the deletion or replacement of a pair
+// inside one community C_{t-1}), and an insertion record at either end of
+// its source's run of insertion keys sets that end of the sink segment
+// [seg_beg, seg_end).  Second pass: the head of each source's run of
+// changes copies the word into uflag, marks itself in hflag when it is
+// non-zero (the union list, ascending, is the heads' compaction) and
+// counts the two kinds of sources (block b adds to counter b % SUM_SLOTS:
+// with a single counter the blocks' atomics would serialise).
+__global__ void k_screen_kinds(const uint64_t* __restrict__ key, const int32_t* __restrict__ op,
+                               const int32_t* __restrict__ ins_pos,
+                               const uint64_t* __restrict__ ins_keys, int64_t n_ins,
+                               int64_t nch, int32_t n, const int32_t* __restrict__ C,
+                               int32_t* sbits, int32_t* seg_beg, int32_t* seg_end) {
+  GRID_STRIDE(q, nch) {
+    const uint64_t kq = key[q];
+    const int32_t s = int32_t(kq / uint64_t(n));
+    const int32_t o = op[q];
+    int b = 0;
+    if (o != OP_DELETE) {
+      b |= 1;
+      const int64_t p = ins_pos[q];
+      if (p == 0 || int32_t(ins_keys[p - 1] / uint64_t(n)) != s) seg_beg[s] = int32_t(p);
+      if (p == n_ins - 1 || int32_t(ins_keys[p + 1] / uint64_t(n)) != s)
+        seg_end[s] = int32_t(p + 1);
+    }
+    if ((o == OP_DELETE || o == OP_REPLACE) && C[int32_t(kq % uint64_t(n))] == C[s]) b |= 2;
+    if (b) atomicOr(&sbits[s], b);
+  }
+}
+
+__global__ void __launch_bounds__(TPB)
+    k_screen_heads(const uint64_t* __restrict__ key, int64_t nch, int32_t n,
+                   const int32_t* __restrict__ sbits, uint8_t* uflag, int32_t* hflag,
+                   long long* n_src, long long* n_dsrc) {
+  long long ns = 0, nd = 0;
+  GRID_STRIDE(q, nch) {
+    const int32_t s = int32_t(key[q] / uint64_t(n));
+    int32_t head = 0;
+    if (q == 0 || int32_t(key[q - 1] / uint64_t(n)) != s) {
+      const int bits = sbits[s];
+      if (bits) {
+        uflag[s] = uint8_t(bits);
+        head = 1;
+        ns += bits & 1;
+        nd += bits >> 1;
+      }
+    }
+    hflag[q] = head;
+  }
+  block_add(ns, n_src + blockIdx.x % SUM_SLOTS);
+  block_add(nd, n_dsrc + blockIdx.x % SUM_SLOTS);
+}
+
 // one wave per listed vertex
 __global__ void k_mark_neighbourhoods(const int32_t* __restrict__ list,
                                       int64_t cnt, const int32_t* __restrict__ off,
@@ -227,6 +283,20 @@ void deletion_sources(const uint64_t* ch_key, const int32_t* ch_op, int64_t nch,
                       const int32_t* C, int32_t* dflag, hipStream_t st) {
   if (nch <= 0) return;
   k_deletion_sources<<<grid_for(nch), TPB, 0, st>>>(ch_key, ch_op, nch, n, C, dflag);
+  DC_LAUNCH_CHECK();
+}
+
+void screen_union(const uint64_t* ch_key, const int32_t* ch_op, const int32_t* ins_pos,
+                  const uint64_t* ins_keys, int64_t n_ins, int64_t nch, int32_t n,
+                  const int32_t* C, int32_t* sbits, uint8_t* uflag, int32_t* seg_beg,
+                  int32_t* seg_end, int32_t* hflag, long long* n_src, long long* n_dsrc,
+                  hipStream_t st) {
+  if (nch <= 0) return;
+  k_screen_kinds<<<grid_for(nch), TPB, 0, st>>>(ch_key, ch_op, ins_pos, ins_keys, n_ins, nch, n,
+                                                C, sbits, seg_beg, seg_end);
+  DC_LAUNCH_CHECK();
+  k_screen_heads<<<grid_for(nch), TPB, 0, st>>>(ch_key, nch, n, sbits, uflag, hflag,
+                                                      n_src, n_dsrc);
   DC_LAUNCH_CHECK();
 }
 
