@@ -108,6 +108,8 @@ void check_stat_errors(const long long* h) {
   if (h[ST_ERR] & 1) throw std::runtime_error("hub-row hash tables larger than their buffer");
 }
 
+void screening_counts(dc_ctx* c);
+
 void read_stat(dc_ctx* c) {
   DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, c->st));
   DC_HIP(hipStreamSynchronize(c->st));
@@ -209,6 +211,18 @@ void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& 
   L.act = active;
   L.nact = n_active;
   c->trace.clear();
+  if (active && c->R_dcount) {
+    // R_t from the screening pass: binned by its device length, which comes
+    // back with the binning's wait together with the screening counters
+    DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, c->st));
+    make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st, skip, c->R_dcount);
+    check_stat_errors(c->hstat);
+    c->R_dcount = nullptr;
+    c->R_count = L.bins.total;
+    L.nact = L.bins.total;
+    screening_counts(c);
+    return;
+  }
   make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st, skip);
 }
 
@@ -559,6 +573,7 @@ dc_status do_init(dc_ctx* c, const dc_edges* g1) {
 dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const int32_t** act,
                       int64_t* nact) {
   hipStream_t st = c->st;
+  c->R_dcount = nullptr;
   const int32_t n = c->n;
   long long* stat = c->stat.as<long long>();
   long long* hs = c->hstat;
@@ -719,18 +734,26 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       // endpoints together (Alg. 2 and the deletion rule read the same state)
       uint8_t* uflag = c->uflag.as<uint8_t>();
       int64_t n_u = 0;
+      Bins b;
+      bool binned = false;
       if (direct) {
         // uflag, sink segments and the heads of the flagged sources in one
-        // pass over the sorted changes; the union list is the heads' sources
+        // pass over the sorted changes; the union list is the heads' sources,
+        // binned by its device count (at most nch) with the counters copied
+        // back before the binning's wait
         screen_union(ch_key, ch_op, c->ins_pos.as<int32_t>(), ins_keys, n_ins, nch, n,
                      c->C.as<int32_t>(), dflag, uflag, c->seg_beg.as<int32_t>(),
                      c->seg_end.as<int32_t>(), src_flag, stat + ST_NSRC, stat + ST_NDSRC, st);
         scan_excl_i32(src_flag, src_pos, nch, reinterpret_cast<int32_t*>(stat + ST_N0), st);
         gather_sources(ch_key, src_flag, src_pos, nch, n, c->ulist.as<int32_t>(), st);
-        read_stat(c);
+        DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, st));
+        make_bins(c->ulist.as<int32_t>(), nch, g0.off, b, c->bins, st, nullptr,
+                  reinterpret_cast<const int32_t*>(stat + ST_N0));
+        check_stat_errors(hs);
+        binned = true;
         n_src = slot_total(hs, ST_NSRC);
         n_dsrc = slot_total(hs, ST_NDSRC);
-        n_u = nch > 0 ? int32_t(hs[ST_N0]) : 0;
+        n_u = b.total;
       } else {
         int32_t* f32 = c->rflag.as<int32_t>();
         int32_t* p32 = c->rpos2.as<int32_t>();
@@ -744,8 +767,7 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
         n_u = int32_t(hs[ST_N0]);
       }
       if (n_u > 0) {
-        Bins b;
-        make_bins(c->ulist.as<int32_t>(), n_u, g0.off, b, c->bins, st);
+        if (!binned) make_bins(c->ulist.as<int32_t>(), n_u, g0.off, b, c->bins, st);
         for (int q = 0; q < NBINS; ++q) S.screen_volume += b.vol[q];
         S.screen_vertices = n_u;
         int32_t* pre = nullptr;
@@ -812,17 +834,20 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     materialize_R(R, cflag, c->C.as<int32_t>(), n, rflag, st);
     scan_excl_i32(rflag, rpos2, n, rpos2 + n, st);
     compact_index(rflag, rpos2, n, c->Rlist.as<int32_t>(), st);
-    DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
-    read_stat(c);
-    c->R_count = *static_cast<int32_t*>(c->hbuf);
     S.ds_sources = n_src;
-    S.ds_accepted = hs[ST_DS_ACC];
     S.del_sources = n_dsrc;
-    S.del_accepted = c->opt.del_rule == DC_DEL_CONSERVATIVE ? n_dsrc : hs[ST_DEL_ACC];
-    S.R_size = c->R_count;
-    S.cascade_expanded = hs[ST_CASC_EXP];
-    S.accepted_volume = hs[ST_ACCVOL];
     S.vertex_evals += S.ds_sources + S.del_sources + S.cascade_candidates;
+    if (mode == DC_MODE_DELTA && !samples) {
+      // R_t goes to level 0 as is: its length and the screening counters
+      // are read with the level-0 binning's wait (levels_begin)
+      c->R_dcount = rpos2 + n;
+      c->R_count = n;
+    } else {
+      DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
+      read_stat(c);
+      c->R_count = *static_cast<int32_t*>(c->hbuf);
+      screening_counts(c);
+    }
   }
   if (samples) {
     const bool score = mode == DC_MODE_LEARNED && c->have_scr;
@@ -862,6 +887,18 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     *nact = n;
   }
   return DC_OK;
+}
+
+// Statistics of the screening pass from the status block copy in hstat
+// (R_count known).
+void screening_counts(dc_ctx* c) {
+  dc_step_stats& S = c->stats;
+  const long long* hs = c->hstat;
+  S.ds_accepted = hs[ST_DS_ACC];
+  S.del_accepted = c->opt.del_rule == DC_DEL_CONSERVATIVE ? S.del_sources : hs[ST_DEL_ACC];
+  S.R_size = c->R_count;
+  S.cascade_expanded = hs[ST_CASC_EXP];
+  S.accepted_volume = hs[ST_ACCVOL];
 }
 
 // Last part of a time step: C_t to the caller (device or host memory).

@@ -54,6 +54,7 @@ struct dc_ctx {
   std::vector<dc_sweep_rec> trace;
   dc_step_stats stats{};
   int64_t R_count = 0;
+  const int32_t* R_dcount = nullptr;  // |R_t| in device memory, not yet read back
   bool have_R_all = true;
   // graph of communities kept across steps (incremental level-0 compaction)
   IncCoarsen inc;

@@ -115,6 +115,7 @@ struct Bins {
   const int32_t* list[NBINS];
   const int32_t* list_rb[NBINS];  // row start (off[v]) of each listed vertex
   long long vol[NBINS];       // adjacency entries of each bin
+  int64_t total = 0;          // vertices binned (the sum of n)
   const int32_t* count_dev;   // NBINS device counts
   // each bin's list starts with the vertices that make_bins' skip flags
   // leave unset: their number, volume and device counts
@@ -156,8 +157,11 @@ struct BinScratch {
 // keeping list order within a bin; synchronises to read the bin sizes.
 // skip (may be null): vertices v with skip[v] != 0 go to the end of their
 // bin, after the first part (first_part gives the bins without them).
+// dcount (may be null): the list's length in device memory, count then
+// being a bound of it; the length is known after the call as b.total, so
+// the caller needs no wait of its own to read it.
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
-               hipStream_t st, const uint8_t* skip = nullptr);
+               hipStream_t st, const uint8_t* skip = nullptr, const int32_t* dcount = nullptr);
 
 // Clears the per-sweep counters of the status block.
 void sweep_reset(long long* stat, hipStream_t st);

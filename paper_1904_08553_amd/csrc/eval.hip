@@ -1059,9 +1059,10 @@ __device__ __forceinline__ int bin_of(int d) {
 constexpr int NROWS = 2 * NBINS;
 
 __global__ void __launch_bounds__(TPB)
-    k_bin_count(const int32_t* __restrict__ list, int64_t cnt, const int32_t* __restrict__ off,
-                const uint8_t* __restrict__ skip, int32_t* bcnt, long long* vol,
-                int64_t nblocks) {
+    k_bin_count(const int32_t* __restrict__ list, int64_t cnt, const int32_t* __restrict__ dcnt,
+                const int32_t* __restrict__ off, const uint8_t* __restrict__ skip, int32_t* bcnt,
+                long long* vol, int64_t nblocks) {
+  if (dcnt) cnt = *dcnt;  // the list's length on the device (cnt: its bound)
   __shared__ int c[NROWS];
   __shared__ long long v[NROWS];
   if (threadIdx.x < NROWS) {
@@ -1112,9 +1113,10 @@ __global__ void __launch_bounds__(TPB)
 // out, in list order within each row
 __global__ void __launch_bounds__(TPB)
     k_bin_scatter(const int32_t* __restrict__ list, int64_t cnt,
-                  const int32_t* __restrict__ off, const uint8_t* __restrict__ skip,
-                  const int32_t* __restrict__ boff, int64_t nblocks, int32_t* out,
-                  int32_t* out_rb) {
+                  const int32_t* __restrict__ dcnt, const int32_t* __restrict__ off,
+                  const uint8_t* __restrict__ skip, const int32_t* __restrict__ boff,
+                  int64_t nblocks, int32_t* out, int32_t* out_rb) {
+  if (dcnt) cnt = *dcnt;
   __shared__ int base[NROWS];
   __shared__ int wc[NW][NROWS];
   const int wid = threadIdx.x / WAVE, lane = lane_id();
@@ -1364,7 +1366,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
 }  // namespace
 
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
-               hipStream_t st, const uint8_t* skip) {
+               hipStream_t st, const uint8_t* skip, const int32_t* dcount) {
   const int64_t nb = count > 0 ? ceil_div(count, BIN_TILE) : 1;
   const int64_t cap = count > 0 ? count : 1;
   s.lists.ensure(size_t(cap) * sizeof(int32_t));
@@ -1385,7 +1387,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   int32_t* boff = s.boff.as<int32_t>();
   DC_HIP(hipMemsetAsync(counts, 0, META, st));
   if (count > 0) {
-    k_bin_count<<<nb, TPB, 0, st>>>(list, count, off, skip, bcnt, vol, nb);
+    k_bin_count<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, bcnt, vol, nb);
     DC_LAUNCH_CHECK();
     scan_excl_i32(bcnt, boff, NROWS * nb, counts + M_TOTAL, st);
     k_bin_starts<<<1, 64, 0, st>>>(boff, nb, counts + M_TOTAL, counts + M_START, counts);
@@ -1397,8 +1399,10 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   const long long* hv = reinterpret_cast<const long long*>(hc + 32);
   int32_t* lists = s.lists.as<int32_t>();
   int32_t* lists_rb = s.lists_rb.as<int32_t>();
+  b.total = 0;
   for (int q = 0; q < NBINS; ++q) {
     b.n[q] = hc[q];
+    b.total += hc[q];
     b.n_first[q] = hc[NBINS + q];
     b.list[q] = lists + hc[M_START + q];
     b.list_rb[q] = lists_rb + hc[M_START + q];
@@ -1421,7 +1425,8 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.tab_off = nullptr;
   b.gslots = 0;
   if (count > 0) {
-    k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, off, skip, boff, nb, lists, lists_rb);
+    k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, boff, nb, lists,
+                                      lists_rb);
     DC_LAUNCH_CHECK();
   }
   constexpr int G = NBINS - 1;
