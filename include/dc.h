@@ -361,7 +361,9 @@ void dc_server_destroy(dc_server* s);
 
 /* Sets (w != NULL: DC_MLP_PARAMS host floats, copied) or clears (w = NULL)
  * the screener of a context.  In LEARNED mode R_t becomes the touched
- * vertices whose logit is >= theta. */
+ * vertices whose logit is >= theta.  Setting a screener also allocates the
+ * per-vertex buffers of the scoring pass (about 60 bytes per vertex), so
+ * the first scored batch does not. */
 dc_status dc_screener_set(dc_ctx* ctx, const float* w, float theta);
 
 /* Samples of the last dc_apply_batch (LEARNED mode or collect = 1): *count

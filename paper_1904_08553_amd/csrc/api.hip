@@ -1445,6 +1445,7 @@ dc_status dc_screener_set(dc_ctx* ctx, const float* w, float theta) {
     DC_HIP(hipStreamSynchronize(ctx->st));
     ctx->theta = theta;
     ctx->have_scr = true;
+    ensure_sample_state(ctx);  // the scoring buffers, sized once here
     return DC_OK;
   });
 }

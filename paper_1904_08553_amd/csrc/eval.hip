@@ -386,6 +386,55 @@ __device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, i
   sweep_commit(A, i1, h1 && b1.x != NO_LABEL && b1.s > s1, c1, b1.x, gl);
 }
 
+// Screener features (EV_FEAT) for two items per group, loads interleaved as
+// in sweep_pair: e_{i->C(i)} and the gains to the best and the second-best
+// other neighbouring community (group_item<EV_FEAT>'s values), the best
+// taken over the group's distinct labels, then again without it.
+template <int GS>
+__device__ __forceinline__ void feat_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0, int i1,
+                                          bool h1, int32_t rb1, int gl, int* lsum) {
+  const int32_t x0 = A.off[i0 + 1], x1 = A.off[i1 + 1];
+  const int32_t re0 = h0 ? x0 : 0, re1 = h1 ? x1 : 0;
+  const int c0 = A.C[i0], c1 = A.C[i1];
+  const int k0 = A.k[i0], k1 = A.k[i1];
+  const int64_t last = A.nnz > 0 ? A.nnz - 1 : 0;
+  const int2 e0 = A.adj[rb0 + gl < last ? rb0 + gl : last];
+  const int2 e1 = A.adj[rb1 + gl < last ? rb1 + gl : last];
+  const int ao0 = A.a[c0], ao1 = A.a[c1];
+  const bool v0 = rb0 + gl < re0 && e0.x != i0, v1 = rb1 + gl < re1 && e1.x != i1;
+  const int y0 = A.C[v0 ? e0.x : 0], y1 = A.C[v1 ? e1.x : 0];
+  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0, it0 = 0, it1 = 0;
+  const int nd0 = group_collect<GS>(v0, v0 ? y0 : EMPTY_KEY, e0.y, lsum, ck0, cs0, &it0);
+  const int nd1 = group_collect<GS>(v1, v1 ? y1 : EMPTY_KEY, e1.y, lsum, ck1, cs1, &it1);
+  const bool p0 = gl < nd0 && ck0 != c0, p1 = gl < nd1 && ck1 != c1;
+  const int ak0 = A.a[p0 ? ck0 : 0], ak1 = A.a[p1 ? ck1 : 0];
+  const int own0 = group_pick<GS>(gl < nd0 && ck0 == c0, cs0);
+  const int own1 = group_pick<GS>(gl < nd1 && ck1 == c1, cs1);
+  const int tm = int(A.two_m);  // 2m < 2^31: 32x32->64 products
+  const long long s0 = (long long)tm * own0 - (long long)k0 * (ao0 - k0);
+  const long long s1 = (long long)tm * own1 - (long long)k1 * (ao1 - k1);
+  Best b0 = {NO_SCORE, NO_LABEL}, b1 = {NO_SCORE, NO_LABEL};
+  if (p0) b0 = {(long long)tm * cs0 - (long long)k0 * ak0, ck0};
+  if (p1) b1 = {(long long)tm * cs1 - (long long)k1 * ak1, ck1};
+  const Best f0 = group_best_first<GS>(b0, it0), f1 = group_best_first<GS>(b1, it1);
+  // second best: the same candidates without the best label
+  const int x0b = group_bcast<GS>(f0.x, 0), x1b = group_bcast<GS>(f1.x, 0);
+  const Best g0 = group_best_first<GS>(b0.x != x0b ? b0 : Best{NO_SCORE, NO_LABEL}, it0);
+  const Best g1 = group_best_first<GS>(b1.x != x1b ? b1 : Best{NO_SCORE, NO_LABEL}, it1);
+  if (gl == 0) {
+    if (h0) {
+      A.f_own[i0] = own0;
+      A.f_g1[i0] = f0.x != NO_LABEL ? f0.s - s0 : NO_GAIN;
+      A.f_g2[i0] = g0.x != NO_LABEL ? g0.s - s0 : NO_GAIN;
+    }
+    if (h1) {
+      A.f_own[i1] = own1;
+      A.f_g1[i1] = f1.x != NO_LABEL ? f1.s - s1 : NO_GAIN;
+      A.f_g2[i1] = g1.x != NO_LABEL ? g1.s - s1 : NO_GAIN;
+    }
+  }
+}
+
 // e_{i->X} for each lane that asks for label X (want): the rank of X among
 // its group's distinct labels (ck in the first nd lanes, their sums cs) is
 // found in LDS (lkey: the wave's 64 ints, overwritten), the sum read from
@@ -534,6 +583,18 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
       const int i1 = h1 ? A.list[j1] : 0;
       const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
       sweep_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
+    }
+    return;
+  }
+  if constexpr (MODE == EV_FEAT) {
+    for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
+      const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
+      const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
+      const int64_t j0 = h0 ? idx0 : 0, j1 = h1 ? idx1 : 0;
+      const int i0 = h0 ? A.list[j0] : 0;
+      const int i1 = h1 ? A.list[j1] : 0;
+      const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
+      feat_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
     }
     return;
   }
@@ -1296,9 +1357,10 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     A.list_rb = bins.list_rb[q];
     A.count = bins.count_dev + q;
   };
-  // items a group takes per loop round: two in the sweep and the screening
-  // pass (their loads interleaved); a wave holds 64 / GS groups
-  constexpr int PAIR = (MODE == EV_SWEEP || MODE == EV_DSBOTH) ? 2 : 1;
+  // items a group takes per loop round: two in the sweep, the screening pass
+  // and the feature pass (their loads interleaved); a wave holds 64 / GS
+  // groups
+  constexpr int PAIR = (MODE == EV_SWEEP || MODE == EV_DSBOTH || MODE == EV_FEAT) ? 2 : 1;
   if (bins.n[0] > 0) {
     setbin(0);
     k_eval_group<MODE, 16><<<wave_grid(ceil_div(bins.n[0], 4 * PAIR)), TPB, 0, st>>>(A);
