@@ -454,12 +454,11 @@ void touched_samples(dc_ctx* c, const LevelView& g0, bool labels, bool score) {
   merge_flags(c->R.as<uint8_t>(), c->tmark.as<uint8_t>(), n, tflag, st);
   scan_excl_i32(tflag, tpos, n, tpos + n, st);
   compact_index(tflag, tpos, n, c->Tlist.as<int32_t>(), st);
-  DC_HIP(hipMemcpyAsync(c->hbuf, tpos + n, 4, hipMemcpyDeviceToHost, st));
-  DC_HIP(hipStreamSynchronize(st));
-  c->T_count = *static_cast<int32_t*>(c->hbuf);
-  if (c->T_count == 0) return;
+  // binned by its device length, which comes back with the binning's wait
   Bins b;
-  make_bins(c->Tlist.as<int32_t>(), c->T_count, g0.off, b, c->bins, st);
+  make_bins(c->Tlist.as<int32_t>(), n, g0.off, b, c->bins, st, nullptr, tpos + n);
+  c->T_count = b.total;
+  if (c->T_count == 0) return;
   feat_eval(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, b, c->f_own.as<int32_t>(),
             c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->stat.as<long long>(), st);
   assemble_features(c->Tlist.as<int32_t>(), c->T_count, c->k0.as<int32_t>(),
@@ -842,6 +841,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       // are read with the level-0 binning's wait (levels_begin)
       c->R_dcount = rpos2 + n;
       c->R_count = n;
+    } else if (mode == DC_MODE_LEARNED && c->have_scr) {
+      // the scores choose R_t below; the counters come back with its binning
     } else {
       DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
       read_stat(c);
@@ -864,10 +865,9 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
       merge_flags(R, nullptr, n, rflag, st);
       scan_excl_i32(rflag, rpos2, n, rpos2 + n, st);
       compact_index(rflag, rpos2, n, c->Rlist.as<int32_t>(), st);
-      DC_HIP(hipMemcpyAsync(c->hbuf, rpos2 + n, 4, hipMemcpyDeviceToHost, st));
-      DC_HIP(hipStreamSynchronize(st));
-      c->R_count = *static_cast<int32_t*>(c->hbuf);
-      S.R_size = c->R_count;
+      // its length is read with the level-0 binning's wait (levels_begin)
+      c->R_dcount = rpos2 + n;
+      c->R_count = n;
       S.screened = 1;
     }
   }
