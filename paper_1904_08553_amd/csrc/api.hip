@@ -319,9 +319,9 @@ void run_levels_slm(dc_ctx* c, const int32_t* active, int64_t n_active) {
   const int64_t npre = active ? c->pre_count : 0;
   const uint8_t* skip = nullptr;
   if (npre > 0) {
-    apply_pre(c->ulist.as<int32_t>(), npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(),
-              c->Cn.as<int32_t>(), st);
-    skip = c->uflag.as<uint8_t>();
+    apply_pre(c->pre_list, npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(), c->Cn.as<int32_t>(),
+              st);
+    skip = c->pre_skip;
   }
   LevelRun L;
   levels_begin(c, active, n_active, L, skip);
@@ -415,9 +415,9 @@ void run_levels(dc_ctx* c, const int32_t* active, int64_t n_active) {
   const int64_t npre = active ? c->pre_count : 0;
   const uint8_t* skip = nullptr;
   if (npre > 0) {
-    apply_pre(c->ulist.as<int32_t>(), npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(),
-              c->Cn.as<int32_t>(), c->st);
-    skip = c->uflag.as<uint8_t>();
+    apply_pre(c->pre_list, npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(), c->Cn.as<int32_t>(),
+              c->st);
+    skip = c->pre_skip;
   }
   levels_begin(c, active, n_active, L, skip);
   const long long gain0 = run_sweeps(c, L.g, L.act, L.nact, L.bins, 0, L.T, true, npre > 0);
@@ -459,8 +459,22 @@ void touched_samples(dc_ctx* c, const LevelView& g0, bool labels, bool score) {
   make_bins(c->Tlist.as<int32_t>(), n, g0.off, b, c->bins, st, nullptr, tpos + n);
   c->T_count = b.total;
   if (c->T_count == 0) return;
+  // a scored batch keeps each touched vertex's first-sweep decision: the
+  // features are taken on the state the first level-0 sweep reads, and R_t
+  // is a subset of the touched set
+  int32_t* pre = nullptr;
+  if (score) {
+    c->pre.ensure(size_t(n) * 4);
+    pre = c->pre.as<int32_t>();
+  }
   feat_eval(g0, c->C.as<int32_t>(), c->a0.as<int32_t>(), c->two_m, b, c->f_own.as<int32_t>(),
-            c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->stat.as<long long>(), st);
+            c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->stat.as<long long>(), st,
+            c->sz0.as<int32_t>(), c->opt.singleton_guard, pre);
+  if (score) {
+    c->pre_count = c->T_count;
+    c->pre_list = c->Tlist.as<int32_t>();
+    c->pre_skip = c->R.as<uint8_t>();  // R_t, once the scores have chosen it
+  }
   assemble_features(c->Tlist.as<int32_t>(), c->T_count, c->k0.as<int32_t>(),
                     c->kprev.as<int32_t>(), c->cptr.as<int32_t>(), c->f_own.as<int32_t>(),
                     c->f_g1.as<long long>(), c->f_g2.as<long long>(), c->a0.as<int32_t>(),
@@ -778,6 +792,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
                 c->opt.singleton_guard, c->two_m, ins_keys, n_ins, c->seg_beg.as<int32_t>(),
                 c->seg_end.as<int32_t>(), uflag, b, R, cflag, accflag, pre, dsx, stat, st);
         c->pre_count = pre ? n_u : 0;
+        c->pre_list = c->ulist.as<int32_t>();
+        c->pre_skip = uflag;
       }
     } else {
       int32_t* dpos = c->dpos.as<int32_t>();

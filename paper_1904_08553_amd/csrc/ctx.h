@@ -33,7 +33,9 @@ struct dc_ctx {
   DBuf pre;                      // first-sweep labels taken by the screening pass
   DBuf sink_g, best_j, best_g, ds_items;  // Alg. 2: gains per record, best sinks, marked rows
   DBuf sub_cnt, sub_off, sub_adj, par, first;  // SLM: induced subgraph, parent labels
-  int64_t pre_count = 0;         // ulist entries that hold them (0: none)
+  int64_t pre_count = 0;         // entries of pre_list that hold them (0: none)
+  const int32_t* pre_list = nullptr;  // the vertices evaluated on the first sweep's state
+  const uint8_t* pre_skip = nullptr;  // their flags (binned after the others at level 0)
   // learned screener: touched set, features, labels, scores
   DBuf kprev, tmark, tflag, tpos, Tlist, f_own, f_g1, f_g2, X, y, logits, scr_wq;
   bool have_scr = false;

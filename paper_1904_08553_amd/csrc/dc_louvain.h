@@ -299,10 +299,13 @@ EvalArgs sweep_args_bins(const LevelView& g, const int32_t* C, int32_t* Cn, cons
 
 // Per listed vertex i: f_own[i] = e_{i->C(i)}, f_g1[i] / f_g2[i] = scaled
 // gains to the best / second-best other neighbouring community (score
-// descending, label ascending), NO_GAIN when absent.
+// descending, label ascending), NO_GAIN when absent.  pre (may be null):
+// also the label a sweep on the same state would give i (the singleton
+// guard applied when guard is set, with the sizes sz).
 void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                const Bins& bins, int32_t* f_own, long long* f_g1, long long* f_g2,
-               long long* stat, hipStream_t st);
+               long long* stat, hipStream_t st, const int32_t* sz = nullptr, int guard = 0,
+               int32_t* pre = nullptr);
 
 // ---- screen.hip ----
 // out[pos[i]] = i for flag[i] != 0 (pos = exclusive scan of flag).

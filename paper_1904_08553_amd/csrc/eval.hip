@@ -389,7 +389,8 @@ __device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, i
 // Screener features (EV_FEAT) for two items per group, loads interleaved as
 // in sweep_pair: e_{i->C(i)} and the gains to the best and the second-best
 // other neighbouring community (group_item<EV_FEAT>'s values), the best
-// taken over the group's distinct labels, then again without it.
+// taken over the group's distinct labels, then again without it; with pre,
+// also the first level-0 sweep's decision (the same state is read).
 template <int GS>
 __device__ __forceinline__ void feat_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0, int i1,
                                           bool h1, int32_t rb1, int gl, int* lsum) {
@@ -426,11 +427,13 @@ __device__ __forceinline__ void feat_pair(const EvalArgs& A, int i0, bool h0, in
       A.f_own[i0] = own0;
       A.f_g1[i0] = f0.x != NO_LABEL ? f0.s - s0 : NO_GAIN;
       A.f_g2[i0] = g0.x != NO_LABEL ? g0.s - s0 : NO_GAIN;
+      if (A.pre) pre_commit(A, i0, f0.x != NO_LABEL && f0.s > s0, c0, f0.x);
     }
     if (h1) {
       A.f_own[i1] = own1;
       A.f_g1[i1] = f1.x != NO_LABEL ? f1.s - s1 : NO_GAIN;
       A.f_g2[i1] = g1.x != NO_LABEL ? g1.s - s1 : NO_GAIN;
+      if (A.pre) pre_commit(A, i1, f1.x != NO_LABEL && f1.s > s1, c1, f1.x);
     }
   }
 }
@@ -855,6 +858,7 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
       A.f_own[i] = int32_t(e_own);
       A.f_g1[i] = b.x != NO_LABEL ? b.s - s_own : NO_GAIN;
       A.f_g2[i] = b2.x != NO_LABEL ? b2.s - s_own : NO_GAIN;
+      if (A.pre) pre_commit(A, i, b.x != NO_LABEL && b.s > s_own, c, b.x);
     }
     group_sync<G>();  // the table is reused by the next item of this group
     return 0;
@@ -1612,9 +1616,12 @@ void ds_both(const LevelView& g, const int32_t* C, const int32_t* a, const int32
 
 void feat_eval(const LevelView& g, const int32_t* C, const int32_t* a, long long two_m,
                const Bins& bins, int32_t* f_own, long long* f_g1, long long* f_g2,
-               long long* stat, hipStream_t st) {
+               long long* stat, hipStream_t st, const int32_t* sz, int guard, int32_t* pre) {
   EvalArgs A{};
   A.stat = stat;
+  A.sz = sz;
+  A.guard = guard;
+  A.pre = pre;
   A.off = g.off;
   A.nnz = g.nnz;
   A.adj = g.adj;
