@@ -1102,9 +1102,19 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
   for (int j = 1; j < m; ++j)
     if (cs[j]->st != st) throw std::runtime_error("merged sweeps need one stream");
   if (m > X.cap) throw std::runtime_error("merge scratch too small");
-  std::vector<const Bins*> bl(static_cast<size_t>(m));
-  for (int j = 0; j < m; ++j) bl[size_t(j)] = &Ls[j].bins;
+  std::vector<const Bins*> bl(static_cast<size_t>(m)), bl0(static_cast<size_t>(m));
+  std::vector<Bins> firsts(static_cast<size_t>(m));
+  bool any_pre = false;
+  for (int j = 0; j < m; ++j) {
+    bl[size_t(j)] = &Ls[j].bins;
+    firsts[size_t(j)] = Ls[j].pre_done ? first_part(Ls[j].bins) : Ls[j].bins;
+    bl0[size_t(j)] = &firsts[size_t(j)];
+    any_pre = any_pre || Ls[j].pre_done;
+  }
   build_multi_bins(bl.data(), m, X.mb, X.hsegs, X.segs, st);
+  // the first round evaluates only what the screening pass has not decided
+  if (any_pre)
+    build_multi_bins(bl0.data(), m, X.mb0, X.hsegs + size_t(NBINS) * size_t(X.cap), X.segs0, st);
   int max_sw = 1;
   int64_t max_nact = 1;
   for (int j = 0; j < m; ++j) {
@@ -1165,7 +1175,8 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
   while (true) {
     for (int r = 0; r < batch; ++r) {
       merged_reset(G, m, state, st);
-      sweep_eval_multi(X.descs.as<EvalArgs>(), state, X.mb, st);
+      sweep_eval_multi(X.descs.as<EvalArgs>(), state, rounds + r == 0 && any_pre ? X.mb0 : X.mb,
+                       st);
       merged_apply(G, m, max_nact, state, sweeps, st);
     }
     rounds += batch;
@@ -1191,8 +1202,8 @@ void level0_merged(dc_ctx* const* cs, LevelRun* Ls, long long* gains, int m, Mer
       c->hstat[ST_MOVES] = r[3 * s];
       c->hstat[ST_DN] = r[3 * s + 1];
       c->hstat[ST_KEEP] = r[3 * s + 2];
-      (void)sweep_account(c, Ls[j].g, 0, s, Ls[j].bins, Ls[j].T, true, -1.f, gains[j],
-                          Ls[j].nact);
+      (void)sweep_account(c, Ls[j].g, 0, s, s == 0 ? firsts[size_t(j)] : Ls[j].bins, Ls[j].T,
+                          true, -1.f, gains[j], Ls[j].nact);
     }
   }
 }

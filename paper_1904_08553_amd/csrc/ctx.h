@@ -74,6 +74,7 @@ struct LevelRun {
   int64_t nact;
   long long T;
   Bins bins;
+  bool pre_done = false;  // the first sweep takes only the bins' first parts
 };
 
 // Host-side copy of a context's resident state (G_t, labels, totals).
@@ -87,11 +88,12 @@ struct SavedState {
 
 // Scratch of merged level-0 sweeps over several contexts.
 struct MergeScratch {
-  MultiBins mb;
-  DBuf descs, done, segs, gdesc, sweeps, rec;
+  MultiBins mb, mb0;              // every round's lists; the first round's when some
+                                  // graph's screened vertices have their decisions
+  DBuf descs, done, segs, segs0, gdesc, sweeps, rec;
   EvalArgs* hdescs = nullptr;     // pinned, cap entries
   int32_t* hdone = nullptr;       // pinned, 2 * cap entries: states, then sweep counts
-  MultiSeg* hsegs = nullptr;      // pinned, NBINS * cap entries
+  MultiSeg* hsegs = nullptr;      // pinned, 2 * NBINS * cap entries (mb, then mb0)
   MergedGraph* hgdesc = nullptr;  // pinned, cap entries
   int cap = 0;
 };

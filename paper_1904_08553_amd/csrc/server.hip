@@ -267,8 +267,17 @@ void dc_server::run() {
           finish(r, DC_OK);
           continue;
         }
+        // the screening pass's first-sweep decisions, as in run_levels
+        const int64_t npre = act ? c->pre_count : 0;
+        const uint8_t* skip = nullptr;
+        if (npre > 0) {
+          apply_pre(c->pre_list, npre, c->R.as<uint8_t>(), c->pre.as<int32_t>(),
+                    c->Cn.as<int32_t>(), c->st);
+          skip = c->pre_skip;
+        }
         LevelRun L;
-        levels_begin(c, act, nact, L);
+        levels_begin(c, act, nact, L, skip);
+        L.pre_done = skip != nullptr;
         cs.push_back(c);
         Ls.push_back(L);
         swept.push_back(r);
@@ -364,7 +373,7 @@ dc_status dc_server_create(dc_server** out, const dc_options* opt, int64_t budge
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hgdesc),
                          size_t(max_inflight) * sizeof(MergedGraph)));
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->X.hsegs),
-                         size_t(NBINS) * size_t(max_inflight) * sizeof(MultiSeg)));
+                         2 * size_t(NBINS) * size_t(max_inflight) * sizeof(MultiSeg)));
   } catch (const DeviceError&) {
     dc_server_destroy(s);
     return DC_E_DEVICE;
