@@ -145,15 +145,18 @@ __device__ __forceinline__ int group_pick(bool flag, int v) {
 // matches it with one ballot; afterwards every valid lane adds its weight
 // into the LDS slot of its label's rank.  lsum: the wave's 64 ints, zero on
 // entry and on return.
+// probe / prank (may be null): each lane's rank of label `probe` among its
+// group's distinct labels, -1 when absent (found as the labels are taken).
 template <int GS>
 __device__ __forceinline__ int group_collect(bool valid, int key, int w, int* lsum, int& ck,
-                                             int& cs, int* iters = nullptr) {
+                                             int& cs, int* iters = nullptr, int probe = 0,
+                                             int* prank = nullptr) {
   constexpr int GPW = WAVE / GS;
   const int lane = lane_id();
   const int gl = lane & (GS - 1);
   const int grp = lane / GS;
   uint64_t rem = __ballot(valid);
-  int r = 0, myr = 0, it = 0;
+  int r = 0, myr = 0, it = 0, pr = -1;
   while (rem) {
     ++it;
     int kl = 0;
@@ -177,8 +180,10 @@ __device__ __forceinline__ int group_collect(bool valid, int key, int w, int* ls
     rem &= ~__ballot(mine);
     if (mine) myr = r;
     if (act && gl == r) ck = kl;
+    if (prank && act && probe == kl) pr = r;
     r += act ? 1 : 0;
   }
+  if (prank) *prank = pr;
   if (valid) atomicAdd(&lsum[lane - gl + myr], w);
   wave_sync();
   cs = gl < r ? lsum[lane] : 0;
@@ -206,22 +211,23 @@ __device__ __forceinline__ Best group_best_first(Best b, int nd_max) {
   return b;
 }
 
-// Best Alg. 2 candidate of lanes [0, 2^steps) of each group, in the group's
-// first lane, as group_best_first: candidates sit in the first n lanes of a
-// group, n <= n_max (wave-uniform).
+// Best Alg. 2 candidate of each group, in the group's first lane, as
+// group_best_first: candidates sit in the first n lanes of a group (n, the
+// group's candidate count, held by every lane of the group), so a step runs
+// only when some group of the wave needs it.
 template <int GS>
-__device__ __forceinline__ Cand group_cand_first(Cand c, int n_max) {
+__device__ __forceinline__ Cand group_cand_first(Cand c, int n) {
   auto step = [](Cand v, auto s) {
     constexpr int S = decltype(s)::value;
     const Cand y = {xchg64<S>(v.g), xchg<S>(v.x), xchg<S>(v.j)};
     return cand_better(y, v) ? y : v;
   };
-  if (n_max > 1) c = step(c, std::integral_constant<int, 0>{});
-  if (n_max > 2) c = step(c, std::integral_constant<int, 1>{});
-  if (n_max > 4) c = step(c, std::integral_constant<int, 2>{});
-  if (GS > 8 && n_max > 8) c = step(c, std::integral_constant<int, 3>{});
-  if (GS > 16 && n_max > 16) c = step(c, std::integral_constant<int, 4>{});
-  if (GS > 32 && n_max > 32) {
+  if (__ballot(n > 1)) c = step(c, std::integral_constant<int, 0>{});
+  if (__ballot(n > 2)) c = step(c, std::integral_constant<int, 1>{});
+  if (__ballot(n > 4)) c = step(c, std::integral_constant<int, 2>{});
+  if (GS > 8 && __ballot(n > 8)) c = step(c, std::integral_constant<int, 3>{});
+  if (GS > 16 && __ballot(n > 16)) c = step(c, std::integral_constant<int, 4>{});
+  if (GS > 32 && __ballot(n > 32)) {
     const Cand y = {readlane64(c.g, 32), __builtin_amdgcn_readlane(c.x, 32),
                     __builtin_amdgcn_readlane(c.j, 32)};
     const Cand z = {readlane64(c.g, 0), __builtin_amdgcn_readlane(c.x, 0),
@@ -438,24 +444,6 @@ __device__ __forceinline__ void feat_pair(const EvalArgs& A, int i0, bool h0, in
   }
 }
 
-// e_{i->X} for each lane that asks for label X (want): the rank of X among
-// its group's distinct labels (ck in the first nd lanes, their sums cs) is
-// found in LDS (lkey: the wave's 64 ints, overwritten), the sum read from
-// that lane; 0 when X is not among them.  iters: wave-uniform bound on nd.
-template <int GS>
-__device__ __forceinline__ int label_sum(int* lkey, int nd, int ck, int cs, bool want, int X,
-                                         int iters, int gl) {
-  const int lane = lane_id();
-  const int gbase = lane - gl;
-  lkey[lane] = gl < nd ? ck : EMPTY_KEY;
-  wave_sync();
-  int r = -1;
-  for (int t = 0; t < iters; ++t)
-    if (want && lkey[gbase + t] == X) r = t;
-  const int s = __shfl(cs, gbase + (r < 0 ? 0 : r), WAVE);
-  return r < 0 ? 0 : s;
-}
-
 // The screening pass (EV_DSBOTH) for two items per group, loads interleaved
 // as in sweep_pair: everything indexed by a vertex -- its row end, label,
 // degree, flags and sink segment -- is loaded with its row's entries, and
@@ -468,7 +456,7 @@ __device__ __forceinline__ int label_sum(int* lkey, int nd, int ck, int cs, bool
 template <int GS>
 __device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0,
                                                  int i1, bool h1, int32_t rb1, int gl,
-                                                 int* lsum, int* lkey) {
+                                                 int* lsum) {
   const int32_t x0 = A.off[i0 + 1], x1 = A.off[i1 + 1];
   const int c0 = A.C[i0], c1 = A.C[i1];
   const int k0 = A.k[i0], k1 = A.k[i1];
@@ -491,9 +479,18 @@ __device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool
   const int j0 = s0 ? int(kq0 - uint64_t(i0) * uint64_t(A.n0)) : 0;
   const int j1 = s1 ? int(kq1 - uint64_t(i1) * uint64_t(A.n0)) : 0;
   const int X0 = A.C[j0], X1 = A.C[j1];
-  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0, it0 = 0, it1 = 0;
-  const int nd0 = group_collect<GS>(v0, v0 ? y0 : EMPTY_KEY, e0.y, lsum, ck0, cs0, &it0);
-  const int nd1 = group_collect<GS>(v1, v1 ? y1 : EMPTY_KEY, e1.y, lsum, ck1, cs1, &it1);
+  // the labels are grouped as in the sweep; a sink lane also learns the rank
+  // of its sink's label among them (a sink is an entry of the row, so its
+  // label is there), and reads that label's weight from the lane holding it
+  int ck0 = EMPTY_KEY, cs0 = 0, ck1 = EMPTY_KEY, cs1 = 0, it0 = 0, it1 = 0, xr0 = -1, xr1 = -1;
+  const int nd0 = group_collect<GS>(v0, v0 ? y0 : EMPTY_KEY, e0.y, lsum, ck0, cs0, &it0,
+                                    s0 ? X0 : EMPTY_KEY, &xr0);
+  const int nd1 = group_collect<GS>(v1, v1 ? y1 : EMPTY_KEY, e1.y, lsum, ck1, cs1, &it1,
+                                    s1 ? X1 : EMPTY_KEY, &xr1);
+  const int gbase = lane_id() - gl;
+  const int sx0 = __shfl(cs0, gbase + (xr0 < 0 ? 0 : xr0), WAVE);
+  const int sx1 = __shfl(cs1, gbase + (xr1 < 0 ? 0 : xr1), WAVE);
+  const int ej0 = xr0 < 0 ? 0 : sx0, ej1 = xr1 < 0 ? 0 : sx1;
   const bool p0 = gl < nd0 && ck0 != c0, p1 = gl < nd1 && ck1 != c1;
   const int ak0 = A.a[p0 ? ck0 : 0], ak1 = A.a[p1 ? ck1 : 0];
   const int ax0 = A.a[X0], ax1 = A.a[X1];
@@ -504,8 +501,6 @@ __device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool
   const long long so1 = (long long)tm * own1 - (long long)k1 * (ao1 - k1);
   // Alg. 2: each sink's gain, stored per record, and the best sink per source
   if (__ballot((uf0 | uf1) & 1)) {  // wave-uniform
-    const int ej0 = label_sum<GS>(lkey, nd0, ck0, cs0, s0, X0, it0, gl);
-    const int ej1 = label_sum<GS>(lkey + WAVE, nd1, ck1, cs1, s1, X1, it1, gl);
     Cand d0 = {NO_SCORE, NO_LABEL, NO_LABEL}, d1 = {NO_SCORE, NO_LABEL, NO_LABEL};
     if (s0) {
       const long long g = X0 == c0 ? 0 : (long long)tm * ej0 - (long long)k0 * ax0 - so0;
@@ -517,8 +512,8 @@ __device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool
       A.sink_g[sb1 + gl] = g;
       d1 = {g, X1, j1};
     }
-    d0 = group_cand_first<GS>(d0, wave_max(ns0));
-    d1 = group_cand_first<GS>(d1, wave_max(ns1));
+    d0 = group_cand_first<GS>(d0, ns0);
+    d1 = group_cand_first<GS>(d1, ns1);
     if ((uf0 & 1) && gl == 0) {
       const bool live = d0.j != NO_LABEL && d0.x != c0 && d0.g > 0;
       A.best_j[i0] = live ? d0.j : -1;
@@ -602,7 +597,6 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
     return;
   }
   if constexpr (MODE == EV_DSBOTH) {
-    __shared__ int lkey_all[NW][2 * WAVE];
     for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
       const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
       const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
@@ -610,8 +604,7 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
       const int i0 = h0 ? A.list[j0] : 0;
       const int i1 = h1 ? A.list[j1] : 0;
       const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
-      accepted += screen_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls,
-                                  lkey_all[threadIdx.x / WAVE]);
+      accepted += screen_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
     }
     accepted = group_sum_ll<WAVE>(accepted);
     if (lane == 0 && accepted) add_accepted(A.stat, accepted);
@@ -835,7 +828,7 @@ __device__ long long eval_table(const EvalArgs& A, int i, int* keys, int* vals, 
       if (cand_better(cd, best)) best = cd;
     }
     if constexpr (G == WAVE)  // the sinks sit in the first lanes (one vertex per wave)
-      best = group_cand_first<WAVE>(best, q1 - q0 < WAVE ? int(q1 - q0) : WAVE);
+      best = group_cand_first<WAVE>(best, int(q1 - q0 < WAVE ? q1 - q0 : WAVE));
     else
       best = group_cand<G>(best, L);
     if (t == 0) {
