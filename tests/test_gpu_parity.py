@@ -5,6 +5,7 @@ import pytest
 
 from gpu_common import compare, make_pair, step_pair
 from oracle import oracle as O
+from paper_1904_08553_amd import dc
 from paper_1904_08553_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -380,3 +381,52 @@ def test_alg2_sinks_with_long_rows(seed):
     for t, b in enumerate(it):
         step_pair(o, g, b)
         compare(o, g, f"step {t}")
+
+
+@pytest.mark.parametrize("mode", ["delta", "learned_fallback"])
+def test_screening_set_kinds(mode):
+    """Batches whose screening set is empty or one-sided: only deletions
+    between communities of C_{t-1} (no Alg. 2 source, no intra-community
+    deletion: the screening set and R_t are empty while the graph changes),
+    only deletions inside communities (deletion endpoints alone), only
+    insertions (Alg. 2 sources alone), and weight increases of existing
+    pairs (insertion records that change no row's length)."""
+    _log(f"case: screening set kinds mode={mode}")
+    pp = W.PlantedPartition(n=400, blocks=4, p_in=0.12, p_out=0.01, seed=21)
+    (u, v, w), _ = pp.batches(steps=1, n_ins=1, n_del=1)
+    u, v, w = np.asarray(u), np.asarray(v), np.asarray(w)
+    o, g = make_pair(pp.n, u, v, w, mode="delta")
+    if mode == "learned_fallback":  # LEARNED without a screener runs Alg. 2 itself
+        g.close()
+        g = dc.DynamicCommunities(pp.n, u, v, w, mode=dc.MODE_LEARNED)
+    compare(o, g, "init")
+    rng = np.random.default_rng(5)
+    live = {(int(a), int(b)): int(c) for a, b, c in zip(u, v, w)}
+
+    def step(au, av, aw, du, dv, where):
+        o.apply_batch(au, av, aw, du, dv)
+        g.apply_batch(au, av, aw, du, dv)
+        for a, b in zip(du, dv):
+            live.pop((a, b), None)
+        for a, b, c in zip(au, av, aw):
+            live[(a, b)] = live.get((a, b), 0) + c
+        compare(o, g, where)
+
+    C = o.C.copy()
+    inter = [e for e in live if C[e[0]] != C[e[1]]]
+    pick = [inter[i] for i in rng.choice(len(inter), size=min(6, len(inter)), replace=False)]
+    step([], [], [], [e[0] for e in pick], [e[1] for e in pick], "inter-community deletions only")
+    assert int(g.last_R().sum()) == int(o.R.sum())
+    C = o.C.copy()
+    intra = [e for e in live if C[e[0]] == C[e[1]]]
+    pick = [intra[i] for i in rng.choice(len(intra), size=8, replace=False)]
+    step([], [], [], [e[0] for e in pick], [e[1] for e in pick], "intra-community deletions only")
+    new = []
+    while len(new) < 10:
+        a, b = sorted(int(x) for x in rng.choice(pp.n, size=2, replace=False))
+        if (a, b) not in live and (a, b) not in new:
+            new.append((a, b))
+    step([e[0] for e in new], [e[1] for e in new], [2] * len(new), [], [], "insertions only")
+    have = list(live)[:12]
+    step([e[0] for e in have], [e[1] for e in have], [3] * len(have), [], [],
+         "weight increases of existing pairs")
