@@ -409,6 +409,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-cascade", action="store_true",
                     help="skip the cascade-aware screening replay of the main batches")
+    ap.add_argument("--no-slm", action="store_true",
+                    help="skip the dSLM-DS / dSLM-base replay of the main batches")
     ap.add_argument("--serving-graphs", type=int, default=64)
     ap.add_argument("--serving-batches", type=int, default=5000)
     ap.add_argument("--serving-nmax", type=int, default=2_000_000)
@@ -478,6 +480,17 @@ def main():
                             cascade=(1, 20))
         res_casc["g"].close()
 
+    res_slm = None
+    if not args.no_slm:
+        # dSLM-DS and dSLM-base (Sec. 3.4): the same batches with smart local
+        # moving levels, from R_t and from every vertex
+        log("dSLM runs")
+        res_slm = {}
+        for name, mode in (("delta", dc.MODE_DELTA), ("base", dc.MODE_ALL)):
+            res_slm[name] = run_mode(mode, args.n, graph, batches_dev, args.warmup, args.steps,
+                                     0, algorithm=dc.ALGO_SLM)
+            res_slm[name]["g"].close()
+
     value = d["changes"] / d["total_s"]
     out = {
         "metric": METRIC,
@@ -530,6 +543,20 @@ def main():
             "R_frac_mean": float(np.mean(cz["R_frac"])),
             "q": cz["q"],
             "max_rel_q_diff_vs_delta": max(abs(a - b) / abs(b) for a, b in zip(cz["q"], d["q"])),
+        }
+    if res_slm is not None:
+        sd, sb = res_slm["delta"], res_slm["base"]
+        out["slm"] = {
+            "delta": {"value": sd["changes"] / sd["total_s"],
+                      "ms_per_step": sd["total_s"] * 1e3 / args.steps, "q": sd["q"],
+                      "R_frac_mean": float(np.mean(sd["R_frac"])), "init_ms": sd["init_ms"],
+                      "sweeps_per_step": sd["sweeps"] / args.steps},
+            "base": {"value": sb["changes"] / sb["total_s"],
+                     "ms_per_step": sb["total_s"] * 1e3 / args.steps, "q": sb["q"],
+                     "init_ms": sb["init_ms"], "sweeps_per_step": sb["sweeps"] / args.steps},
+            "speedup_delta_over_base": sb["total_s"] / sd["total_s"],
+            "max_rel_q_diff": max(abs(a - b) / abs(b) for a, b in zip(sd["q"], sb["q"])),
+            "mean_q_vs_louvain_delta": float(np.mean(sd["q"]) - np.mean(d["q"])),
         }
     if d["k_launch"] > 0 and d["k_ms"] > 0:
         ach = d["k_bytes"] / (d["k_ms"] * 1e-3) / 1e9
