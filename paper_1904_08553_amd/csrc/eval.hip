@@ -266,10 +266,16 @@ __device__ __forceinline__ void pre_commit(const EvalArgs& A, int i, bool move, 
 
 // One item of a group kernel: group (lane / GS) of the wave evaluates vertex
 // i (have = false: no vertex, the lanes still take part in the wave-wide
-// steps).  Returns the screening tests this group accepted (0 or 1).
+// steps).  EV_SWEEP: the sweep decision (the merged multi-graph sweep);
+// EV_DSADD: Alg. 2 for an insertion source (its gain toward each sink's
+// label, stored per record, and its best sink); EV_DSDEL: the deletion rule
+// for a deletion endpoint (the conservative-rule path runs the two tests in
+// separate passes).  Returns the deletion tests accepted (0 or ACC_DEL).
 template <int MODE, int GS>
 __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool have, int lane,
                                                 int gl, int gbase, int* lsum) {
+  static_assert(MODE == EV_SWEEP || MODE == EV_DSADD || MODE == EV_DSDEL,
+                "the paired kernels take the other modes");
   long long accepted = 0;
   const int32_t rb = have ? A.off[i] : 0;
   const int32_t re = have ? A.off[i + 1] : 0;
@@ -284,25 +290,9 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
   const long long e_own = group_pick<GS>(pair && ck == c, cs);
   const int tm = int(A.two_m);  // 2m < 2^31: 32x32->64 products
   const long long s_own = (long long)tm * e_own - ki * ((have ? A.a[c] : 0) - ki);
-  if (MODE == EV_FEAT) {
-    Best b = {NO_SCORE, NO_LABEL};
-    if (pair && ck != c) b = {(long long)tm * cs - (long long)int(ki) * A.a[ck], ck};
-    const Best b1 = group_best_w<GS>(b);
-    const Best b2 = group_best_w<GS>(b.x != b1.x ? b : Best{NO_SCORE, NO_LABEL});
-    if (have && gl == 0) {
-      A.f_own[i] = int32_t(e_own);
-      A.f_g1[i] = b1.x != NO_LABEL ? b1.s - s_own : NO_GAIN;
-      A.f_g2[i] = b2.x != NO_LABEL ? b2.s - s_own : NO_GAIN;
-    }
-    return accepted;
-  }
-  // EV_DSBOTH: the Alg. 2 test for insertion sources (flag bit 0) and the
-  // deletion rule for deletion endpoints (bit 1) on the same aggregation
-  const int uf = MODE == EV_DSBOTH ? (have ? int(A.uflag[i]) : 0) : (MODE == EV_DSADD ? 1 : 2);
-  if (MODE == EV_DSADD || MODE == EV_DSBOTH) {
-    const bool ins = have && (uf & 1);
-    const int q0 = ins ? A.seg_beg[i] : 0;
-    const int nsk = ins ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
+  if (MODE == EV_DSADD) {
+    const int q0 = have ? A.seg_beg[i] : 0;
+    const int nsk = have ? A.seg_end[i] - q0 : 0;  // sinks are neighbours: <= GS
     const bool has = gl < nsk;
     const int sj = has ? int(A.ins_keys[q0 + gl] - uint64_t(i) * uint64_t(A.n0)) : 0;
     const int Xj = has ? A.C[sj] : EMPTY_KEY;
@@ -320,21 +310,20 @@ __device__ __forceinline__ long long group_item(const EvalArgs& A, int i, bool h
       A.sink_g[q0 + gl] = g;
     }
     const Cand best = group_cand_w<GS>(cd);
-    if (ins && gl == 0) {
+    if (have && gl == 0) {
       const bool live = best.j != NO_LABEL && best.x != c && best.g > 0;
       A.best_j[i] = live ? best.j : -1;
       if (live) A.best_g[i] = best.g;
     }
-    if (MODE == EV_DSADD) return accepted;
+    return accepted;
   }
   Best b = {NO_SCORE, NO_LABEL};
   if (pair && ck != c) b = {(long long)tm * cs - (long long)int(ki) * A.a[ck], ck};
   b = group_best_w<GS>(b);
-  bool move = have && b.x != NO_LABEL && b.s > s_own;
-  if (MODE == EV_DSBOTH && A.pre && have && gl == 0) pre_commit(A, i, move, c, b.x);
+  const bool move = have && b.x != NO_LABEL && b.s > s_own;
   if (MODE == EV_SWEEP) {
     sweep_commit(A, i, move, c, b.x, gl);
-  } else if (move && (uf & 2)) {  // EV_DSDEL, EV_DSBOTH
+  } else if (move) {  // EV_DSDEL
     if (e.x >= 0) A.R[e.x] = 1;
     if (gl == 0) {
       A.R[i] = 1;
@@ -393,10 +382,11 @@ __device__ __forceinline__ void sweep_pair(const EvalArgs& A, int i0, bool h0, i
 }
 
 // Screener features (EV_FEAT) for two items per group, loads interleaved as
-// in sweep_pair: e_{i->C(i)} and the gains to the best and the second-best
-// other neighbouring community (group_item<EV_FEAT>'s values), the best
-// taken over the group's distinct labels, then again without it; with pre,
-// also the first level-0 sweep's decision (the same state is read).
+// in sweep_pair: f_own = e_{i->C(i)}, and f_g1 / f_g2 the scaled gains to
+// the best and the second-best other neighbouring community (score
+// descending, label ascending; NO_GAIN when absent), the best taken over
+// the group's distinct labels, then again without it; with pre, also the
+// first level-0 sweep's decision (the same state is read).
 template <int GS>
 __device__ __forceinline__ void feat_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0, int i1,
                                           bool h1, int32_t rb1, int gl, int* lsum) {
@@ -448,11 +438,13 @@ __device__ __forceinline__ void feat_pair(const EvalArgs& A, int i0, bool h0, in
 // as in sweep_pair: everything indexed by a vertex -- its row end, label,
 // degree, flags and sink segment -- is loaded with its row's entries, and
 // the sinks' labels with the entries' labels, before either item's labels
-// are grouped.  The arithmetic and the writes are group_item<EV_DSBOTH>'s:
-// per insertion source the gain toward each sink's label (stored per
-// record) and the best sink, the first-sweep decision when asked (pre), and
-// the deletion rule for a deletion endpoint.  Returns the deletion tests
-// accepted (in the groups' first lanes).
+// are grouped.  Per vertex, by its flags (uflag): for an insertion source
+// (bit 0) Alg. 2's gain toward each sink's label, stored per record
+// (sink_g), and its best sink with gain1 (best_j, best_g); for a deletion
+// endpoint (bit 1) the deletion rule (a move would mark the vertex, its row
+// and the target community); for every vertex the first-sweep decision
+// when asked (pre).  Returns the deletion tests accepted (in the groups'
+// first lanes).
 template <int GS>
 __device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool h0, int32_t rb0,
                                                  int i1, bool h1, int32_t rb1, int gl,
@@ -572,7 +564,8 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
   const int64_t g0 = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * GPW + lane / GS;
   // every group of a wave runs the same number of iterations (wave-uniform)
   const int64_t w0 = g0 - lane / GS;
-  if constexpr (MODE == EV_SWEEP) {
+  if constexpr (MODE == EV_SWEEP || MODE == EV_FEAT || MODE == EV_DSBOTH) {
+    // two items per group and round (their loads interleaved)
     for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
       const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
       const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
@@ -580,44 +573,25 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
       const int i0 = h0 ? A.list[j0] : 0;
       const int i1 = h1 ? A.list[j1] : 0;
       const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
-      sweep_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
+      if constexpr (MODE == EV_SWEEP)
+        sweep_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
+      else if constexpr (MODE == EV_FEAT)
+        feat_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
+      else
+        accepted += screen_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
     }
-    return;
+  } else {
+    for (int64_t wb = w0; wb < cnt; wb += ngroups) {
+      const int64_t idx = wb + lane / GS;
+      const bool have = idx < cnt;
+      const int i = have ? A.list[idx] : 0;
+      accepted += group_item<MODE, GS>(A, i, have, lane, gl, gbase, ls);
+    }
   }
-  if constexpr (MODE == EV_FEAT) {
-    for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
-      const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
-      const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
-      const int64_t j0 = h0 ? idx0 : 0, j1 = h1 ? idx1 : 0;
-      const int i0 = h0 ? A.list[j0] : 0;
-      const int i1 = h1 ? A.list[j1] : 0;
-      const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
-      feat_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
-    }
-    return;
-  }
-  if constexpr (MODE == EV_DSBOTH) {
-    for (int64_t wb = w0; wb < cnt; wb += 2 * ngroups) {
-      const int64_t idx0 = wb + lane / GS, idx1 = wb + ngroups + lane / GS;
-      const bool h0 = idx0 < cnt, h1 = idx1 < cnt;
-      const int64_t j0 = h0 ? idx0 : 0, j1 = h1 ? idx1 : 0;
-      const int i0 = h0 ? A.list[j0] : 0;
-      const int i1 = h1 ? A.list[j1] : 0;
-      const int32_t rb0 = A.list_rb[j0], rb1 = A.list_rb[j1];
-      accepted += screen_pair<GS>(A, i0, h0, rb0, i1, h1, rb1, gl, ls);
-    }
+  if constexpr (MODE != EV_SWEEP && MODE != EV_FEAT) {
     accepted = group_sum_ll<WAVE>(accepted);
     if (lane == 0 && accepted) add_accepted(A.stat, accepted);
-    return;
   }
-  for (int64_t wb = w0; wb < cnt; wb += ngroups) {
-    const int64_t idx = wb + lane / GS;
-    const bool have = idx < cnt;
-    const int i = have ? A.list[idx] : 0;
-    accepted += group_item<MODE, GS>(A, i, have, lane, gl, gbase, ls);
-  }
-  accepted = group_sum_ll<WAVE>(accepted);
-  if (MODE != EV_SWEEP && lane == 0 && accepted) add_accepted(A.stat, accepted);
 }
 
 // --------------------------------------------------------------------------
