@@ -83,6 +83,8 @@ void ensure_vertex_state(dc_ctx* c) {
   c->cflag.ensure(n + 1);
   c->stat.ensure(ST_COUNT * 8);
   DC_HIP(hipMemsetAsync(c->stat.p, 0, ST_COUNT * 8, c->st));  // counters and self-check flags
+  c->done.ensure(DONE_WORDS * 4);
+  DC_HIP(hipMemsetAsync(c->done.p, 0, DONE_WORDS * 4, c->st));
   fill_i64(c->dpack.as<int64_t>(), 0, int64_t(n) + 1, c->st);
   fill_i32(c->lflag.as<int32_t>(), 0, int64_t(n) + 1, c->st);
 }
@@ -177,7 +179,7 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
   Bins bins = pre_done ? first_part(all_bins) : all_bins;
   for (int s = 0; s < c->opt.max_sweeps; ++s) {
     if (s == 1) bins = all_bins;
-    sweep_reset(c->stat.as<long long>(), st);
+    if (s == 0) sweep_reset(c->stat.as<long long>(), st);  // later: cleared by sweep_apply
     const bool timed = record && c->opt.timing && bins.n[TIMED_BIN] > 0;
     sweep_eval(g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
                c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, bins,
@@ -186,8 +188,10 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
     sweep_apply(g, act, nact, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
                 c->szl.as<int32_t>(), c->two_m, c->movers.as<int32_t>(),
                 c->dpack.as<long long>(), c->lflag.as<int32_t>(), c->tlist.as<int32_t>(),
-                c->stat.as<long long>(), st);
-    read_stat(c);
+                c->stat.as<long long>(), c->done.as<unsigned>(), c->hstat_dev, st);
+    // the status block reaches c->hstat from the sweep's last kernel
+    DC_HIP(hipStreamSynchronize(st));
+    check_stat_errors(c->hstat);
     float ms = -1.f;
     if (timed) DC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     if (sweep_account(c, g, level, s, bins, T, record, ms, level_gain, nact, phase)) break;
@@ -214,8 +218,8 @@ void levels_begin(dc_ctx* c, const int32_t* active, int64_t n_active, LevelRun& 
   if (active && c->R_dcount) {
     // R_t from the screening pass: binned by its device length, which comes
     // back with the binning's wait together with the screening counters
-    DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, c->st));
-    make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st, skip, c->R_dcount);
+    make_bins(active, n_active, L.g.off, L.bins, c->bins, c->st, skip, c->R_dcount,
+              c->stat.as<long long>(), c->hstat_dev, ST_COUNT);
     check_stat_errors(c->hstat);
     c->R_dcount = nullptr;
     c->R_count = L.bins.total;
@@ -759,9 +763,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
                      c->seg_end.as<int32_t>(), src_flag, stat + ST_NSRC, stat + ST_NDSRC, st);
         scan_excl_i32(src_flag, src_pos, nch, reinterpret_cast<int32_t*>(stat + ST_N0), st);
         gather_sources(ch_key, src_flag, src_pos, nch, n, c->ulist.as<int32_t>(), st);
-        DC_HIP(hipMemcpyAsync(c->hstat, c->stat.p, ST_COUNT * 8, hipMemcpyDeviceToHost, st));
         make_bins(c->ulist.as<int32_t>(), nch, g0.off, b, c->bins, st, nullptr,
-                  reinterpret_cast<const int32_t*>(stat + ST_N0));
+                  reinterpret_cast<const int32_t*>(stat + ST_N0), stat, c->hstat_dev, ST_COUNT);
         check_stat_errors(hs);
         binned = true;
         n_src = slot_total(hs, ST_NSRC);
@@ -1026,7 +1029,7 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->kprev, &c->tmark, &c->tflag, &c->tpos, &c->Tlist, &c->f_own,
                   &c->f_g1, &c->f_g2, &c->X, &c->y, &c->logits, &c->Cl, &c->Cn, &c->al,
                   &c->szl, &c->dpack, &c->lflag, &c->tlist, &c->movers, &c->map0, &c->cnt[0],
-                  &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat,
+                  &c->cnt[1], &c->minv[0], &c->minv[1], &c->lab, &c->cntf, &c->stat, &c->done,
                   &c->cg[0].off, &c->cg[0].adj, &c->cg[0].k, &c->cg[1].off, &c->cg[1].adj,
                   &c->cg[1].k, &c->bins.lists, &c->bins.lists_rb, &c->bins.ovf,
                   &c->bins.bcnt, &c->bins.boff, &c->bins.counts,
@@ -1221,6 +1224,7 @@ dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) 
   dc_status s;
   try {
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
+    DC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hstat_dev), c->hstat, 0));
     DC_HIP(hipHostMalloc(&c->hbuf, 64));
     DC_HIP(hipHostMalloc(&c->bins.host, 256));
     std::memset(c->bins.host, 0, 256);

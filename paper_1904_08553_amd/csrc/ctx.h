@@ -47,6 +47,8 @@ struct dc_ctx {
   CoarseGraph cg[2];
   DBuf stat;
   long long* hstat = nullptr;  // pinned mirror of the status block
+  long long* hstat_dev = nullptr;  // its address for the kernels that write it
+  DBuf done;                   // finished-block counters (DONE_WORDS, zero between launches)
   void* hbuf = nullptr;        // pinned scratch for the kernels' host reads
   BinScratch bins;
   CoarsenScratch cs;

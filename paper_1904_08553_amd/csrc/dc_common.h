@@ -203,6 +203,50 @@ __device__ __forceinline__ void block_or(int v, int* dst) {
   __syncthreads();
 }
 
+// A store to pinned host memory that the host reads after its next wait on
+// the stream: a system-scope store, written through the caches.  (A
+// system-scope fence instead would write back the whole L2.)
+template <class T>
+__device__ __forceinline__ void host_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Finished blocks of a launch: true in exactly one block, the last to get
+// here, once every block has passed the call, so the others' reads before
+// it are done (the barrier waits for them).  Their stores are not made
+// visible to it: that would take a device-scope release per block, which
+// on this chip writes back the L2 of the block's die.  The blocks count
+// first in DONE_GROUPS counters (block b in counter b % DONE_GROUPS) and the
+// last of each group in one more: a single word that thousands of blocks
+// add to would queue them all behind each other.  ctr: DONE_WORDS words,
+// zero before the launch and zero again after it.  Every thread of every
+// block must call it (no early exit).
+constexpr int DONE_GROUPS = 16;
+constexpr int DONE_STRIDE = 32;  // words between two counters (128 B)
+constexpr int DONE_WORDS = (DONE_GROUPS + 1) * DONE_STRIDE;
+
+__device__ __forceinline__ bool last_block(unsigned* ctr) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned nb = gridDim.x, g = blockIdx.x % DONE_GROUPS;
+    const unsigned gsize = (nb - g + DONE_GROUPS - 1) / DONE_GROUPS;  // blocks of group g
+    const unsigned ngroups = nb < unsigned(DONE_GROUPS) ? nb : unsigned(DONE_GROUPS);
+    int l = 0;
+    unsigned* gc = ctr + (1 + g) * DONE_STRIDE;
+    if (atomicAdd(gc, 1u) == gsize - 1u) {
+      atomicExch(gc, 0u);
+      if (atomicAdd(ctr, 1u) == ngroups - 1u) {
+        atomicExch(ctr, 0u);
+        l = 1;
+      }
+    }
+    last = l;
+  }
+  __syncthreads();
+  return last != 0;
+}
+
 // Other types (floating point): a fixed butterfly order through shuffles.
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {

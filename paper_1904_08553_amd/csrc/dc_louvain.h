@@ -146,8 +146,9 @@ inline Bins first_part(const Bins& b) {
 }
 
 struct BinScratch {
-  DBuf lists, lists_rb, bcnt, boff, counts, tab_off, gkeys, gvals, ovf;
-  void* host = nullptr;  // pinned, 256 bytes
+  DBuf lists, lists_rb, bcnt, boff, bvol, counts, tab_off, gkeys, gvals, ovf;
+  void* host = nullptr;      // pinned, 256 bytes
+  void* host_dev = nullptr;  // its address for the kernels that write it
   hipStream_t side = nullptr;  // second stream and fork / join events of the
   hipEvent_t fork = nullptr;   // evaluation launches (owned by the context)
   hipEvent_t join = nullptr;
@@ -159,11 +160,16 @@ struct BinScratch {
 // bin, after the first part (first_part gives the bins without them).
 // dcount (may be null): the list's length in device memory, count then
 // being a bound of it; the length is known after the call as b.total, so
-// the caller needs no wait of its own to read it.
+// the caller needs no wait of its own to read it.  copy_src (may be null):
+// copy_n int64 slots copied to copy_dst (device-visible pinned host memory)
+// before the same wait, e.g. a status block the caller reads with the bins.
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
-               hipStream_t st, const uint8_t* skip = nullptr, const int32_t* dcount = nullptr);
+               hipStream_t st, const uint8_t* skip = nullptr, const int32_t* dcount = nullptr,
+               const long long* copy_src = nullptr, long long* copy_dst = nullptr,
+               int copy_n = 0);
 
-// Clears the per-sweep counters of the status block.
+// Clears the per-sweep counters of the status block (before the first
+// sweep of a level; each sweep_apply clears them again for the next one).
 void sweep_reset(long long* stat, hipStream_t st);
 // Writes the next label of every active vertex that moves.  ev0/ev1 (may be
 // null) bracket the launch of bin TIMED_BIN (rows of 17 to 32 entries, two
@@ -173,10 +179,14 @@ void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t
                 long long* stat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 // Collects movers from the active list (null = all of [0, n_active)),
 // applies them, computes the exact Delta N and keeps or reverts the sweep.
+// The sweep's status block (ST_COUNT slots, ST_DN and ST_KEEP filled in)
+// is written to host_stat, a device-visible address of pinned host memory,
+// by the last kernel: after a wait on the stream it is there, with no copy.
+// done: DONE_WORDS zeroed words (finished-block counters).
 void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, int32_t* C,
                  int32_t* Cn, int32_t* a, int32_t* sz, long long two_m, int32_t* movers,
                  long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
-                 hipStream_t st);
+                 unsigned* done, long long* host_stat, hipStream_t st);
 
 // Scratch of one Alg. 2 pass: per directed insertion record its gain
 // (sink_g, n_ins entries), per vertex the best sink and gain1 (best_j,

@@ -1093,7 +1093,7 @@ constexpr int NROWS = 2 * NBINS;
 __global__ void __launch_bounds__(TPB)
     k_bin_count(const int32_t* __restrict__ list, int64_t cnt, const int32_t* __restrict__ dcnt,
                 const int32_t* __restrict__ off, const uint8_t* __restrict__ skip, int32_t* bcnt,
-                long long* vol, int64_t nblocks) {
+                long long* bvol, int64_t nblocks) {
   if (dcnt) cnt = *dcnt;  // the list's length on the device (cnt: its bound)
   __shared__ int c[NROWS];
   __shared__ long long v[NROWS];
@@ -1136,8 +1136,7 @@ __global__ void __launch_bounds__(TPB)
   __syncthreads();
   if (threadIdx.x < NROWS) {
     bcnt[int64_t(threadIdx.x) * nblocks + blockIdx.x] = c[threadIdx.x];
-    if (v[threadIdx.x])
-      atomicAdd((unsigned long long*)&vol[threadIdx.x], (unsigned long long)v[threadIdx.x]);
+    bvol[int64_t(threadIdx.x) * nblocks + blockIdx.x] = v[threadIdx.x];
   }
 }
 
@@ -1188,21 +1187,115 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
-// Bin q starts at its row 2q; counts[q] = its size, counts[NBINS + q] = the
-// size of its first part (row 2q).
-__global__ void k_bin_starts(const int32_t* boff, int64_t nblocks, const int32_t* total,
-                             int32_t* bin_start, int32_t* counts) {
-  // boff is the exclusive scan of bcnt laid out row-major: row r starts at
-  // boff[r * nblocks]
-  if (threadIdx.x < NBINS) {
-    const int q = threadIdx.x;
+// Metadata of a binning (int32 slots): [0, NBINS) bin sizes, [NBINS,
+// 2 NBINS) first-part sizes (row 2q), [2 NBINS, 3 NBINS) bin starts, then
+// the total, the overflow count and the overflow pass's finished blocks
+// (both zero); from slot 32 on the NROWS row volumes (int64).
+constexpr int M_START = 2 * NBINS, M_TOTAL = 3 * NBINS, M_OVF = 3 * NBINS + 1;
+constexpr int META_WORDS = 32 + 2 * NROWS;
+static_assert(M_OVF + 2 <= 32, "bin metadata slots overlap the volumes");
+static_assert(META_WORDS * 4 <= 256, "bin metadata must fit the pinned host buffer");
+
+constexpr int META_TPB = 1024;
+constexpr int META_PER = 32;                    // counts per thread in the scan
+constexpr int META_SCAN_MAX = META_TPB * META_PER;
+
+// Inclusive prefix sum over a wave (shuffles: 6 steps).
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int y = __shfl_up(v, o, WAVE);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// One block after k_bin_count: with scan, the exclusive scan of the per-block
+// row counts bcnt (row-major, NROWS * nblocks of them, at most META_SCAN_MAX)
+// into boff; without, boff and its total (counts[M_TOTAL]) are given.  Then
+// the metadata, written to counts and to host (device-visible pinned host
+// memory), and copy_n slots of copy_src copied to copy_dst (host memory too)
+// so that the caller's one wait brings back both.
+__global__ void __launch_bounds__(META_TPB)
+    k_bin_meta(const int32_t* __restrict__ bcnt, int32_t* boff,
+               const long long* __restrict__ bvol, int64_t nblocks, int scan, int32_t* counts,
+               int32_t* host, const long long* __restrict__ copy_src, long long* copy_dst,
+               int copy_n) {
+  __shared__ int wtot[META_TPB / WAVE];
+  __shared__ long long vrow[NROWS];
+  __shared__ int meta[META_WORDS];
+  const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
+  const int64_t M = int64_t(NROWS) * nblocks;
+  if (t < NROWS) vrow[t] = 0;
+  if (t < META_WORDS) meta[t] = 0;
+  __syncthreads();
+  // row volumes: each thread sums its strided entries row by row
+  {
+    long long acc = 0;
+    int row = -1;
+    for (int64_t k = t; k < M; k += META_TPB) {
+      const int r = int(k / nblocks);
+      if (r != row) {
+        if (row >= 0 && acc) atomicAdd((unsigned long long*)&vrow[row], (unsigned long long)acc);
+        row = r;
+        acc = 0;
+      }
+      acc += bvol[k];
+    }
+    if (row >= 0 && acc) atomicAdd((unsigned long long*)&vrow[row], (unsigned long long)acc);
+  }
+  if (scan) {
+    // thread t scans the contiguous chunk [t * per, (t + 1) * per)
+    const int per = int(ceil_div(M, META_TPB));
+    const int64_t b0 = int64_t(t) * per;
+    int sum = 0;
+    for (int i = 0; i < per; ++i)
+      if (b0 + i < M) sum += bcnt[b0 + i];
+    const int incl = wave_incl_scan(sum);
+    if (lane == WAVE - 1) wtot[wid] = incl;
+    __syncthreads();
+    if (t == 0) {
+      int run = 0;
+      for (int w = 0; w < META_TPB / WAVE; ++w) {
+        const int x = wtot[w];
+        wtot[w] = run;
+        run += x;
+      }
+      meta[M_TOTAL] = run;
+    }
+    __syncthreads();
+    int run = wtot[wid] + incl - sum;
+    for (int i = 0; i < per; ++i)
+      if (b0 + i < M) {
+        boff[b0 + i] = run;
+        run += bcnt[b0 + i];
+      }
+  } else if (t == 0) {
+    meta[M_TOTAL] = counts[M_TOTAL];
+  }
+  __syncthreads();  // boff (global, this block's writes) and the total
+  if (t < NBINS && M > 0) {
+    // boff is row-major: row r starts at boff[r * nblocks]
+    const int q = t;
     const int s0 = boff[int64_t(2 * q) * nblocks];
     const int s1 = boff[int64_t(2 * q + 1) * nblocks];
-    const int e = (q + 1 < NBINS) ? boff[int64_t(2 * q + 2) * nblocks] : *total;
-    bin_start[q] = s0;
-    counts[q] = e - s0;
-    counts[NBINS + q] = s1 - s0;
+    const int e = (q + 1 < NBINS) ? boff[int64_t(2 * q + 2) * nblocks] : meta[M_TOTAL];
+    meta[M_START + q] = s0;
+    meta[q] = e - s0;
+    meta[NBINS + q] = s1 - s0;
   }
+  if (t < NROWS) {
+    const long long v = vrow[t];
+    meta[32 + 2 * t] = int(uint32_t(uint64_t(v)));
+    meta[32 + 2 * t + 1] = int(uint32_t(uint64_t(v) >> 32));
+  }
+  __syncthreads();
+  if (t < META_WORDS) {
+    counts[t] = meta[t];
+    host_store(&host[t], meta[t]);
+  }
+  for (int i = t; i < copy_n; i += META_TPB) host_store(&copy_dst[i], copy_src[i]);
 }
 
 __global__ void k_table_caps(const int32_t* __restrict__ list, const int32_t* __restrict__ off,
@@ -1399,34 +1492,34 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
 }  // namespace
 
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
-               hipStream_t st, const uint8_t* skip, const int32_t* dcount) {
+               hipStream_t st, const uint8_t* skip, const int32_t* dcount,
+               const long long* copy_src, long long* copy_dst, int copy_n) {
   const int64_t nb = count > 0 ? ceil_div(count, BIN_TILE) : 1;
   const int64_t cap = count > 0 ? count : 1;
   s.lists.ensure(size_t(cap) * sizeof(int32_t));
   s.lists_rb.ensure(size_t(cap) * sizeof(int32_t));
   s.bcnt.ensure(size_t(NROWS * nb + 1) * sizeof(int32_t));
   s.boff.ensure(size_t(NROWS * nb + 1) * sizeof(int32_t));
-  // int32 slots: [0, NBINS) bin sizes, [NBINS, 2 NBINS) first-part sizes,
-  // [2 NBINS, 3 NBINS) bin starts, [3 NBINS] total, then the overflow count
-  // and the finished blocks; NROWS row volumes (int64) from slot 32 on
-  constexpr int M_START = 2 * NBINS, M_TOTAL = 3 * NBINS, M_OVF = 3 * NBINS + 1;
-  constexpr size_t META = 32 * sizeof(int32_t) + NROWS * sizeof(long long);
-  static_assert(M_OVF + 2 <= 32, "bin metadata slots overlap the volumes");
-  static_assert(META <= 256, "bin metadata must fit the pinned host buffer");
-  s.counts.ensure(META);
+  s.bvol.ensure(size_t(NROWS * nb) * sizeof(long long));
+  s.counts.ensure(META_WORDS * sizeof(int32_t));
   int32_t* counts = s.counts.as<int32_t>();
-  long long* vol = reinterpret_cast<long long*>(counts + 32);
   int32_t* bcnt = s.bcnt.as<int32_t>();
   int32_t* boff = s.boff.as<int32_t>();
-  DC_HIP(hipMemsetAsync(counts, 0, META, st));
+  long long* bvol = s.bvol.as<long long>();
+  if (!s.host_dev) DC_HIP(hipHostGetDevicePointer(&s.host_dev, s.host, 0));
+  // count, then the scan and the metadata in one block (the scan of many
+  // blocks' counts takes the two-launch scan first), then one wait
+  const int64_t M = count > 0 ? int64_t(NROWS) * nb : 0;
   if (count > 0) {
-    k_bin_count<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, bcnt, vol, nb);
-    DC_LAUNCH_CHECK();
-    scan_excl_i32(bcnt, boff, NROWS * nb, counts + M_TOTAL, st);
-    k_bin_starts<<<1, 64, 0, st>>>(boff, nb, counts + M_TOTAL, counts + M_START, counts);
+    k_bin_count<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, bcnt, bvol, nb);
     DC_LAUNCH_CHECK();
   }
-  DC_HIP(hipMemcpyAsync(s.host, counts, META, hipMemcpyDeviceToHost, st));
+  const bool one_block = M <= META_SCAN_MAX;
+  if (!one_block) scan_excl_i32(bcnt, boff, M, counts + M_TOTAL, st);
+  k_bin_meta<<<1, META_TPB, 0, st>>>(bcnt, boff, bvol, count > 0 ? nb : 0, one_block ? 1 : 0,
+                                      counts, static_cast<int32_t*>(s.host_dev), copy_src,
+                                      copy_dst, copy_src ? copy_n : 0);
+  DC_LAUNCH_CHECK();
   DC_HIP(hipStreamSynchronize(st));
   const int32_t* hc = static_cast<const int32_t*>(s.host);
   const long long* hv = reinterpret_cast<const long long*>(hc + 32);

@@ -77,36 +77,50 @@ __global__ void __launch_bounds__(TPB)
     }
     __syncthreads();  // wcount and btotal are rewritten by the next tile
   }
+  // every label left in the table gets one global update; the labels that
+  // this sweep touches first are appended to tlist with one counter update
+  // for the block
+  constexpr int FR = AGG_SLOTS / TPB;
+  __shared__ int fcount[FR][NW];
+  __shared__ long long fbase;
   __syncthreads();
-  for (int s = threadIdx.x; s < AGG_SLOTS; s += TPB) {
-    const int X = agg.keys[s];
-    if (X == EMPTY_KEY) continue;
-    const long long v = agg.vals[s];
-    if (v != 0) touch_label(X, v, dpack, tflag, tlist, stat);
-  }
-}
-
-__global__ void __launch_bounds__(TPB)
-    k_delta_intra(const int32_t* __restrict__ movers, const long long* stat,
-                  const int32_t* __restrict__ off, const int2* __restrict__ adj,
-                  const int32_t* __restrict__ C, const int32_t* __restrict__ Cn,
-                  long long* stat_w) {
-  const int64_t cnt = stat[ST_MOVES];
-  const int64_t nwaves = int64_t(gridDim.x) * NW;
-  const int lane = lane_id();
-  long long s = 0;
-  for (int64_t p = int64_t(blockIdx.x) * NW + threadIdx.x / WAVE; p < cnt; p += nwaves) {
-    int u = movers[p];
-    int cu = C[u], nu = Cn[u];
-    for (int32_t j = off[u] + lane; j < off[u + 1]; j += WAVE) {
-      int2 e = adj[j];
-      if (e.x == u) continue;
-      int cy = C[e.x], ny = Cn[e.x];
-      int d = int(nu == ny) - int(cu == cy);
-      if (d) s += (long long)e.y * d * (cy != ny ? 1 : 2);
+  int fx[FR];
+  uint64_t fm[FR];
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    const int X = agg.keys[r * TPB + threadIdx.x];
+    bool first = false;
+    if (X != EMPTY_KEY) {
+      const long long v = agg.vals[r * TPB + threadIdx.x];
+      if (v != 0) {
+        atomicAdd((unsigned long long*)&dpack[X], (unsigned long long)v);
+        first = atomicExch(&tflag[X], 1) == 0;
+      }
     }
+    fx[r] = first ? X : -1;
+    fm[r] = __ballot(first);
+    if (lane == 0) fcount[r][wid] = __popcll(fm[r]);
   }
-  block_add(s, &stat_w[ST_DI]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int r = 0; r < FR; ++r)
+      for (int w = 0; w < NW; ++w) tot += fcount[r][w];
+    fbase = tot ? (long long)atomicAdd((unsigned long long*)&stat[ST_TOUCHED],
+                                       (unsigned long long)tot)
+                : 0;
+  }
+  __syncthreads();
+  long long pos = fbase;
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    if (fx[r] >= 0) {
+      long long q = pos + __popcll(fm[r] & lt);
+      for (int w = 0; w < wid; ++w) q += fcount[r][w];
+      tlist[q] = fx[r];
+    }
+    for (int w = 0; w < NW; ++w) pos += fcount[r][w];
+  }
 }
 
 __device__ __forceinline__ int unpack_lo(long long d) { return int(uint32_t(uint64_t(d))); }
@@ -114,33 +128,60 @@ __device__ __forceinline__ int unpack_hi(long long d) {
   return int((d - (long long)unpack_lo(d)) >> 32);
 }
 
-__global__ void k_delta_squares(const int32_t* __restrict__ tlist,
-                                long long* stat, const long long* __restrict__ dpack,
-                                const int32_t* __restrict__ a) {
-  const int64_t cnt = stat[ST_TOUCHED];
+// The two terms of the exact Delta N in one launch: blocks [0, nb_intra)
+// sum the change of the intra-community weight over the movers' rows (one
+// wave per mover), the other blocks the change of sum a^2 over the touched
+// labels.
+__global__ void __launch_bounds__(TPB)
+    k_delta_terms(const int32_t* __restrict__ movers, const int32_t* __restrict__ tlist,
+                  const int32_t* __restrict__ off, const int2* __restrict__ adj,
+                  const int32_t* __restrict__ C, const int32_t* __restrict__ Cn,
+                  const long long* __restrict__ dpack, const int32_t* __restrict__ a,
+                  int nb_intra, long long* stat) {
   long long s = 0;
-  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < cnt;
-       p += int64_t(gridDim.x) * blockDim.x) {
-    int X = tlist[p];
-    long long ao = a[X];
-    long long an = ao + unpack_lo(dpack[X]);
-    s += an * an - ao * ao;
+  if (int(blockIdx.x) < nb_intra) {
+    const int64_t cnt = stat[ST_MOVES];
+    const int64_t nwaves = int64_t(nb_intra) * NW;
+    const int lane = lane_id();
+    for (int64_t p = int64_t(blockIdx.x) * NW + threadIdx.x / WAVE; p < cnt; p += nwaves) {
+      const int u = movers[p];
+      const int cu = C[u], nu = Cn[u];
+      for (int32_t j = off[u] + lane; j < off[u + 1]; j += WAVE) {
+        const int2 e = adj[j];
+        if (e.x == u) continue;
+        const int cy = C[e.x], ny = Cn[e.x];
+        const int d = int(nu == ny) - int(cu == cy);
+        if (d) s += (long long)e.y * d * (cy != ny ? 1 : 2);
+      }
+    }
+    block_add(s, &stat[ST_DI]);
+  } else {
+    const int64_t cnt = stat[ST_TOUCHED];
+    const int64_t nbs = int64_t(gridDim.x) - nb_intra;
+    for (int64_t p = (int64_t(blockIdx.x) - nb_intra) * TPB + threadIdx.x; p < cnt;
+         p += nbs * TPB) {
+      const int X = tlist[p];
+      const long long ao = a[X];
+      const long long an = ao + unpack_lo(dpack[X]);
+      s += an * an - ao * ao;
+    }
+    block_add(s, &stat[ST_DS]);
   }
-  block_add(s, &stat[ST_DS]);
 }
 
-__global__ void k_finalize(long long* stat, long long two_m) {
-  long long dN = two_m * stat[ST_DI] - stat[ST_DS];
-  stat[ST_DN] = dN;
-  stat[ST_KEEP] = (stat[ST_MOVES] > 0 && dN >= 0) ? 1 : 0;
-}
-
-__global__ void k_commit(const int32_t* __restrict__ movers,
-                         const int32_t* __restrict__ tlist, const long long* stat,
-                         int32_t* C, int32_t* Cn, long long* dpack, int32_t* tflag,
-                         int32_t* a, int32_t* sz) {
+// Keep (Delta N >= 0 and something moved) or revert the sweep: movers take
+// or drop their next labels, the touched labels' totals and sizes take
+// their changes, and the change buffers are cleared.  The last block to
+// finish writes the sweep's status block (Delta N and the decision
+// included) to host memory and clears the per-sweep counters, so the next
+// sweep needs no reset launch and the host no copy.
+__global__ void __launch_bounds__(TPB)
+    k_commit(const int32_t* __restrict__ movers, const int32_t* __restrict__ tlist,
+             long long* stat, long long two_m, int32_t* C, int32_t* Cn, long long* dpack,
+             int32_t* tflag, int32_t* a, int32_t* sz, unsigned* done, long long* host_stat) {
   const int64_t nm = stat[ST_MOVES], nt = stat[ST_TOUCHED];
-  const bool keep = stat[ST_KEEP] != 0;
+  const long long dN = two_m * stat[ST_DI] - stat[ST_DS];
+  const bool keep = nm > 0 && dN >= 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < nm; p += stride) {
     int u = movers[p];
@@ -158,6 +199,18 @@ __global__ void k_commit(const int32_t* __restrict__ movers,
     }
     dpack[X] = 0;
     tflag[X] = 0;
+  }
+  if (!last_block(done)) return;
+  for (int i = threadIdx.x; i < ST_COUNT; i += blockDim.x)
+    host_store(&host_stat[i], i == ST_DN ? dN : i == ST_KEEP ? (keep ? 1ll : 0ll) : stat[i]);
+  __syncthreads();  // every slot is read before the counters are cleared
+  if (threadIdx.x == 0) {
+    stat[ST_MOVES] = 0;
+    stat[ST_TOUCHED] = 0;
+    stat[ST_DI] = 0;
+    stat[ST_DS] = 0;
+    stat[ST_DN] = dN;
+    stat[ST_KEEP] = keep ? 1 : 0;
   }
 }
 
@@ -184,20 +237,17 @@ void sweep_reset(long long* stat, hipStream_t st) {
 void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, int32_t* C,
                  int32_t* Cn, int32_t* a, int32_t* sz, long long two_m, int32_t* movers,
                  long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
-                 hipStream_t st) {
+                 unsigned* done, long long* host_stat, hipStream_t st) {
   const int64_t cnt = n_active > 0 ? n_active : 1;
   k_apply_moves<<<grid_for(cnt, 512), TPB, 0, st>>>(active, n_active, C, Cn, g.k, dpack, tflag,
                                                      tlist, movers, stat);
   DC_LAUNCH_CHECK();
-  k_delta_intra<<<grid_for(cnt * WAVE, 4096), TPB, 0, st>>>(movers, stat, g.off, g.adj, C, Cn,
-                                                            stat);
+  const int nb_intra = grid_for(cnt * WAVE, 4096), nb_sq = grid_for(2 * cnt, 2048);
+  k_delta_terms<<<nb_intra + nb_sq, TPB, 0, st>>>(movers, tlist, g.off, g.adj, C, Cn, dpack, a,
+                                                  nb_intra, stat);
   DC_LAUNCH_CHECK();
-  k_delta_squares<<<grid_for(2 * cnt, 2048), TPB, 0, st>>>(tlist, stat, dpack, a);
-  DC_LAUNCH_CHECK();
-  k_finalize<<<1, 1, 0, st>>>(stat, two_m);
-  DC_LAUNCH_CHECK();
-  k_commit<<<grid_for(2 * cnt, 2048), TPB, 0, st>>>(movers, tlist, stat, C, Cn, dpack, tflag, a,
-                                                    sz);
+  k_commit<<<grid_for(2 * cnt, 2048), TPB, 0, st>>>(movers, tlist, stat, two_m, C, Cn, dpack,
+                                                    tflag, a, sz, done, host_stat);
   DC_LAUNCH_CHECK();
 }
 
