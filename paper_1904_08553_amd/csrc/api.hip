@@ -264,7 +264,8 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
     else
       coarsen(g, Cl, szl, al, cnt_in, minv_in, level == 0, c->n, c->map0.as<int32_t>(),
               c->cg[next], c->cnt[next].as<int32_t>(), c->minv[next].as<int32_t>(), c->cs, st);
-    if (level == 0) save_level1(c->cg[next], c->cs, c->minv[next].as<int32_t>(), c->inc, st);
+    if (level == 0 && !inc)
+      save_level1(c->cg[next], c->cs, c->minv[next].as<int32_t>(), c->inc, st);
     g = c->cg[next].view();
     start_level(Cl, Cn, al, szl, g.k, g.n, st);
     level++;
@@ -274,16 +275,16 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
   S.sweeps = int32_t(c->trace.size());
   const int32_t* cntL = c->cnt[(level - 1) % 2].as<int32_t>();
   const int32_t* minvL = c->minv[(level - 1) % 2].as<int32_t>();
+  // (the labels' first launch also clears the numerator's two counters)
+  long long* stat = c->stat.as<long long>();
+  static_assert(ST_S == ST_I + 1, "the numerator's counters are adjacent");
   finalize_labels(g.n, Cl, al, szl, cntL, minvL, c->n, c->map0.as<int32_t>(),
                   c->lab.as<int32_t>(), c->cntf.as<int32_t>(), c->C.as<int32_t>(),
-                  c->a0.as<int32_t>(), c->sz0.as<int32_t>(), st);
+                  c->a0.as<int32_t>(), c->sz0.as<int32_t>(), st, stat + ST_I);
   inc_finish(c->inc, c->C.as<int32_t>(), c->n, c->cs, st);  // H(G_t, C_t) for the next step
   c->inc_ready = false;
   // exact numerator on the final level (coarsening preserves N)
-  long long* stat = c->stat.as<long long>();
-  DC_HIP(hipMemsetAsync(stat + ST_I, 0, 16, st));
-  intra_weight(g.off, g.adj, Cl, g.n, stat + ST_I, st);
-  sum_squares(al, g.n, stat + ST_S, st);
+  modularity_terms(g.off, g.adj, Cl, al, g.n, stat + ST_I, stat + ST_S, st);
   read_stat(c);
   S.N = two_m * c->hstat[ST_I] - c->hstat[ST_S];
   S.two_m = two_m;
@@ -298,8 +299,8 @@ void finish_stats(dc_ctx* c, const LevelView& g) {
   S.sweeps = int32_t(c->trace.size());
   long long* stat = c->stat.as<long long>();
   DC_HIP(hipMemsetAsync(stat + ST_I, 0, 16, c->st));
-  intra_weight(g.off, g.adj, c->Cl.as<int32_t>(), g.n, stat + ST_I, c->st);
-  sum_squares(c->al.as<int32_t>(), g.n, stat + ST_S, c->st);
+  modularity_terms(g.off, g.adj, c->Cl.as<int32_t>(), c->al.as<int32_t>(), g.n, stat + ST_I,
+                   stat + ST_S, c->st);
   read_stat(c);
   S.N = c->two_m * c->hstat[ST_I] - c->hstat[ST_S];
   S.two_m = c->two_m;
@@ -664,15 +665,18 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
   const int nxt = c->cur ^ 1;
   c->off[nxt].ensure(size_t(n + 1) * 4);
   int32_t* off_new = c->off[nxt].as<int32_t>();
-  scan_excl_i32(c->new_deg.as<int32_t>(), off_new, n, off_new + n, st);
+  // (the scans write the new entry count and the insertion count to host
+  // memory as well: one wait, no copy)
+  int32_t* hb = static_cast<int32_t*>(c->hbuf);
+  scan_excl_i32(c->new_deg.as<int32_t>(), off_new, n, off_new + n, st, c->hbuf_dev);
   // insertion keys (sorted directed pairs) and their sources
   select_insertions(ch_op, nch, c->ins_flag.as<int32_t>(), st);
+  hb[1] = 0;
   scan_excl_i32(c->ins_flag.as<int32_t>(), c->ins_pos.as<int32_t>(), nch,
-                reinterpret_cast<int32_t*>(stat + ST_N2), st);
-  DC_HIP(hipMemcpyAsync(c->hbuf, off_new + n, 4, hipMemcpyDeviceToHost, st));
-  read_stat(c);
-  const int64_t nnz_new = *static_cast<int32_t*>(c->hbuf);
-  const int64_t n_ins = nch > 0 ? int32_t(hs[ST_N2]) : 0;
+                reinterpret_cast<int32_t*>(stat + ST_N2), st, c->hbuf_dev + 1);
+  DC_HIP(hipStreamSynchronize(st));
+  const int64_t nnz_new = hb[0];
+  const int64_t n_ins = nch > 0 ? hb[1] : 0;
   c->n_ins_last = n_ins;
   c->adj[nxt].ensure(size_t(nnz_new + 1) * 8);
   merge_rows(off_old, adj_old, c->nnz, off_new, c->adj[nxt].as<int2>(), n, cptr,
@@ -1038,7 +1042,7 @@ void for_each_buf(dc_ctx* c, F&& f) {
                   &c->cs.mstart, &c->cs.labof, &c->cs.mdeg, &c->cs.mvol, &c->cs.chead,
                   &c->cs.cpos, &c->cs.chunks, &c->cs.mcnt, &c->cs.pk0, &c->cs.pk1, &c->cs.pv0,
                   &c->cs.pv1, &c->cs.ph, &c->cs.pp, &c->cs.pS, &c->cs.pcnt, &c->cs.hidx,
-                  &c->cs.ukey, &c->cs.rc, &c->inc.hkey, &c->inc.hw, &c->inc.lkey, &c->inc.lw,
+                  &c->cs.ukey, &c->cs.rc, &c->inc.lkey, &c->inc.lw,
                   &c->inc.lminv, &c->inc.ek0, &c->inc.ek1, &c->inc.ev0, &c->inc.ev1,
                   &c->inc.heads, &c->inc.hpos, &c->inc.v64, &c->inc.S, &c->inc.starts,
                   &c->inc.nz, &c->inc.npos, &c->inc.mflag, &c->inc.mvol, &c->inc.tkey,
@@ -1226,6 +1230,7 @@ dc_status create_ctx(dc_ctx** out, int32_t n, const dc_options* opt, F&& build) 
     DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hstat), ST_COUNT * 8));
     DC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hstat_dev), c->hstat, 0));
     DC_HIP(hipHostMalloc(&c->hbuf, 64));
+    DC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hbuf_dev), c->hbuf, 0));
     DC_HIP(hipHostMalloc(&c->bins.host, 256));
     std::memset(c->bins.host, 0, 256);
     DC_HIP(hipHostMalloc(&c->cs.host, 64));

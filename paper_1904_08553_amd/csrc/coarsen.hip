@@ -257,10 +257,12 @@ __global__ void k_first_level_meta(const int32_t* __restrict__ labof,
                                    const int32_t* __restrict__ sz,
                                    const int32_t* __restrict__ mstart,
                                    const uint32_t* __restrict__ members, int32_t nc,
-                                   int32_t* cnt_out, int32_t* minv_out) {
+                                   int32_t* cnt_out, int32_t* minv_out, int32_t* minv_keep) {
   GRID_STRIDE(r, nc) {
     cnt_out[r] = sz[labof[r]];
-    minv_out[r] = int32_t(members[mstart[r]]);
+    const int32_t v = int32_t(members[mstart[r]]);
+    minv_out[r] = v;
+    if (minv_keep) minv_keep[r] = v;
   }
 }
 
@@ -420,21 +422,26 @@ __global__ void k_compact_runs(const uint64_t* __restrict__ keys, const int32_t*
 // Community-label entries to coarse ids; bad |= 1 for an entry that touches
 // an empty community or has a weight below 1 (cannot happen when H is the
 // graph of communities it claims to be).
+// The coarse CSR entries of the summed community pairs, and the level-1
+// graph kept for the next step (keys x*nc + y, weights).  An entry of an
+// empty community or of weight below 1 sets the flag in host memory.
 __global__ void k_inc_csr(const uint64_t* __restrict__ keys, const int32_t* __restrict__ w,
                           int64_t cnt, const int32_t* __restrict__ rank,
                           const int32_t* __restrict__ sz, int32_t n, int32_t nc, int2* adj,
-                          uint64_t* ukey, int32_t* bad) {
+                          uint64_t* ukey, int32_t* uw, int32_t* bad_host) {
   GRID_STRIDE(i, cnt) {
     const int32_t X = int32_t(keys[i] / uint64_t(n)), Y = int32_t(keys[i] % uint64_t(n));
     if (sz[X] <= 0 || sz[Y] <= 0 || w[i] < 1) {
-      *bad = 1;
+      host_store(bad_host, 1);
       adj[i] = make_int2(0, 0);
       ukey[i] = 0;
+      uw[i] = 0;
       continue;
     }
     const int32_t x = rank[X], y = rank[Y];
     adj[i] = make_int2(y, w[i]);
     ukey[i] = uint64_t(x) * uint64_t(nc) + uint64_t(y);
+    uw[i] = w[i];
   }
 }
 
@@ -444,14 +451,35 @@ __global__ void k_adj_weights(const int2* __restrict__ adj, int64_t m, int32_t* 
 
 // Level-1 entries relabelled by the final labels of their vertices (the
 // final label of a level-0 community is that of any of its members).
-__global__ void k_relabel(const uint64_t* __restrict__ lkey, int64_t m, int32_t nc,
-                          const int32_t* __restrict__ lminv, const int32_t* __restrict__ Ct,
-                          int32_t n, uint64_t* okey) {
+__global__ void k_relabel(const uint64_t* __restrict__ lkey, const int32_t* __restrict__ lw,
+                          int64_t m, int32_t nc, const int32_t* __restrict__ lminv,
+                          const int32_t* __restrict__ Ct, int32_t n, uint64_t* okey,
+                          uint32_t* ow) {
   GRID_STRIDE(i, m) {
     const uint64_t k = lkey[i];
     okey[i] = uint64_t(Ct[lminv[int32_t(k / uint64_t(nc))]]) * uint64_t(n) +
               uint64_t(Ct[lminv[int32_t(k % uint64_t(nc))]]);
+    ow[i] = uint32_t(lw[i]);
   }
+}
+
+// Starting values of finalize_labels: the smallest-member labels at +inf,
+// the member counts and the level-0 totals and sizes at zero, and the two
+// counters zero2 (may be null) at zero.
+__global__ void k_final_init(int32_t* lab, int32_t* cntf, int32_t nL, int32_t* a0, int32_t* sz0,
+                             int32_t n0, long long* zero2) {
+  const int64_t n = nL > n0 ? nL : n0;
+  GRID_STRIDE(i, n) {
+    if (i < nL) {
+      lab[i] = 0x7fffffff;
+      cntf[i] = 0;
+    }
+    if (i < n0) {
+      a0[i] = 0;
+      sz0[i] = 0;
+    }
+  }
+  if (zero2 && blockIdx.x == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -582,7 +610,7 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
   // level-0 vertex counts and smallest level-0 ids of the coarse vertices
   if (first_level) {
     k_first_level_meta<<<grid_for(nc), TPB, 0, st>>>(labof, sz, mstart, members, nc, cnt_out,
-                                                     minv_out);
+                                                     minv_out, nullptr);
     DC_LAUNCH_CHECK();
   } else {
     s.mcnt.ensure(size_t(nl + 1) * 4);
@@ -607,10 +635,25 @@ void swap_buf(DBuf& x, DBuf& y) {
   std::swap(x.bytes, y.bytes);
 }
 
+// ensure(bytes) that keeps the first `keep` bytes when the buffer grows
+void grow_keep(DBuf& b, size_t bytes, size_t keep, hipStream_t st) {
+  if (b.p && bytes <= b.bytes) return;
+  DBuf nb;
+  nb.ensure(bytes);
+  if (keep > 0 && b.p) DC_HIP(hipMemcpyAsync(nb.p, b.p, keep, hipMemcpyDeviceToDevice, st));
+  swap_buf(b, nb);  // the old buffer is freed (after the copy) with nb
+}
+
+int32_t* host_alias(CoarsenScratch& s) {
+  if (!s.host_dev) DC_HIP(hipHostGetDevicePointer(&s.host_dev, s.host, 0));
+  return static_cast<int32_t*>(s.host_dev);
+}
+
 // Sums runs of equal keys of a sorted list (values: int32 bit patterns) into
 // (okey, ow), dropping runs that sum to zero; returns the number kept.
 int64_t reduce_sorted(const uint64_t* keys, const uint32_t* vals, int64_t m, uint64_t* okey,
-                      int32_t* ow, IncCoarsen& H, int32_t* host, hipStream_t st) {
+                      int32_t* ow, IncCoarsen& H, int32_t* host, int32_t* host_dev,
+                      hipStream_t st) {
   if (m <= 0) return 0;
   const size_t mm = size_t(m) + 1;
   H.heads.ensure(mm * 4);
@@ -638,10 +681,9 @@ int64_t reduce_sorted(const uint64_t* keys, const uint32_t* vals, int64_t m, uin
                 reinterpret_cast<int64_t*>(S + m), st);
   k_run_sums<<<grid_for(m), TPB, 0, st>>>(heads, hpos, starts, S, m, nz, v64);
   DC_LAUNCH_CHECK();
-  scan_excl_i32(nz, npos, m, npos + m, st);
+  scan_excl_i32(nz, npos, m, npos + m, st, host_dev);
   k_compact_runs<<<grid_for(m), TPB, 0, st>>>(keys, nz, npos, v64, m, okey, ow);
   DC_LAUNCH_CHECK();
-  DC_HIP(hipMemcpyAsync(host, npos + m, 4, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
   return host[0];
 }
@@ -655,6 +697,7 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
                        hipStream_t st) {
   const int32_t nl = g.n;
   int32_t* host = static_cast<int32_t*>(s.host);
+  int32_t* hdev = host_alias(s);  // the kernels write the sizes the host reads here
   // ranks of the non-empty labels (as coarsen)
   s.flag.ensure(size_t(nl + 1) * 4);
   s.rank.ensure(size_t(nl + 1) * 4);
@@ -662,7 +705,7 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   int32_t* rank = s.rank.as<int32_t>();
   k_nonempty<<<grid_for(nl), TPB, 0, st>>>(sz, nl, flag);
   DC_LAUNCH_CHECK();
-  scan_excl_i32(flag, rank, nl, rank + nl, st);
+  scan_excl_i32(flag, rank, nl, rank + nl, st, hdev);
   // movers' row volumes
   H.mvol.ensure(size_t(nl + 1) * 4);
   H.mflag.ensure(size_t(nl + 1) * 4);
@@ -670,9 +713,7 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   int32_t* mpos = H.mflag.as<int32_t>();
   k_mover_vol<<<grid_for(nl), TPB, 0, st>>>(Cl, Cold, g.off, nl, mvol);
   DC_LAUNCH_CHECK();
-  scan_excl_i32(mvol, mpos, nl, mpos + nl, st);
-  DC_HIP(hipMemcpyAsync(host, rank + nl, 4, hipMemcpyDeviceToHost, st));
-  DC_HIP(hipMemcpyAsync(host + 1, mpos + nl, 4, hipMemcpyDeviceToHost, st));
+  scan_excl_i32(mvol, mpos, nl, mpos + nl, st, hdev + 1);
   DC_HIP(hipStreamSynchronize(st));
   const int32_t nc = host[0];
   const int64_t vol = host[1];
@@ -687,8 +728,13 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   s.rc.ensure(size_t(nl + 1) * 4);
   k_member_pairs<<<grid_for(nl), TPB, 0, st>>>(Cl, rank, nl, rkey, members, s.rc.as<int32_t>());
   DC_LAUNCH_CHECK();
-  radix_sort_pairs(rkey, members, s.keys1.as<uint64_t>(), s.vals1.as<uint32_t>(), nl,
-                   ilog2_ceil(uint64_t(nc)), st);
+  if (radix_sort_pairs_swap(rkey, members, s.keys1.as<uint64_t>(), s.vals1.as<uint32_t>(), nl,
+                            ilog2_ceil(uint64_t(nc)), st)) {
+    swap_buf(s.keys0, s.keys1);  // the sorted pairs are in the second buffers
+    swap_buf(s.vals0, s.vals1);
+    rkey = s.keys0.as<uint64_t>();
+    members = s.vals0.as<uint32_t>();
+  }
   s.cntr.ensure(size_t(nc + 1) * 4);
   s.mstart.ensure(size_t(nc + 1) * 4);
   s.labof.ensure(size_t(nc + 1) * 4);
@@ -699,18 +745,15 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   DC_LAUNCH_CHECK();
   scan_excl_i32(cntr, mstart, nc, mstart + nc, st);
 
-  // H(G_{t-1}, C_{t-1}) + the batch's changes + the movers' rows, one sort
+  // H(G_{t-1}, C_{t-1}) + the batch's changes + the movers' rows, one sort;
+  // H's h entries already lead the sort's input buffers (inc_finish)
   const int64_t h = H.h, m = h + nch + 4 * vol;
-  H.ek0.ensure(size_t(m + 1) * 8);
+  grow_keep(H.ek0, size_t(m + 1) * 8, size_t(h) * 8, st);
+  grow_keep(H.ev0, size_t(m + 1) * 4, size_t(h) * 4, st);
   H.ek1.ensure(size_t(m + 1) * 8);
-  H.ev0.ensure(size_t(m + 1) * 4);
   H.ev1.ensure(size_t(m + 1) * 4);
   uint64_t* ek = H.ek0.as<uint64_t>();
   uint32_t* ev = H.ev0.as<uint32_t>();
-  if (h > 0) {
-    DC_HIP(hipMemcpyAsync(ek, H.hkey.p, size_t(h) * 8, hipMemcpyDeviceToDevice, st));
-    DC_HIP(hipMemcpyAsync(ev, H.hw.p, size_t(h) * 4, hipMemcpyDeviceToDevice, st));
-  }
   if (nch > 0) {
     k_emit_changes<<<grid_for(nch), TPB, 0, st>>>(ch_key, ch_dk, nch, nl, Cold, ek + h, ev + h);
     DC_LAUNCH_CHECK();
@@ -725,35 +768,39 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   H.tkey.ensure(size_t(m + 1) * 8);
   H.tw.ensure(size_t(m + 1) * 4);
   const int64_t cnnz = reduce_sorted(ek, ev, m, H.tkey.as<uint64_t>(), H.tw.as<int32_t>(), H,
-                                     host, st);
+                                     host, hdev, st);
 
   // coarse CSR over coarse ids (rows come out sorted: ranks keep label order)
+  // its entries go to the coarse CSR and, as the level-1 graph kept for the
+  // next step, to H.lkey / H.lw
   out.off.ensure(size_t(nc + 1) * 4);
   out.adj.ensure(size_t(cnnz + 1) * 8);
   out.k.ensure(size_t(nc + 1) * 4);
-  s.ukey.ensure(size_t(cnnz + 1) * 8);
-  s.pcnt.ensure(8);
-  int32_t* bad = s.pcnt.as<int32_t>();
-  fill_i32(bad, 0, 1, st);
+  H.lkey.ensure(size_t(cnnz + 1) * 8);
+  H.lw.ensure(size_t(cnnz + 1) * 4);
+  H.lminv.ensure(size_t(nc + 1) * 4);
+  host[2] = 0;  // the self-check flag, set by the kernel in host memory
   if (cnnz > 0) {
     k_inc_csr<<<grid_for(cnnz), TPB, 0, st>>>(H.tkey.as<uint64_t>(), H.tw.as<int32_t>(), cnnz,
                                               rank, sz, nl, nc, out.adj.as<int2>(),
-                                              s.ukey.as<uint64_t>(), bad);
+                                              H.lkey.as<uint64_t>(), H.lw.as<int32_t>(),
+                                              hdev + 2);
     DC_LAUNCH_CHECK();
   }
-  DC_HIP(hipMemcpyAsync(host, bad, 4, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
-  if (host[0]) throw std::runtime_error("incremental coarsening: inconsistent community graph");
-  row_bounds(s.ukey.as<uint64_t>(), cnnz, nc, out.off.as<int32_t>(), st);
+  if (host[2]) throw std::runtime_error("incremental coarsening: inconsistent community graph");
+  row_bounds(H.lkey.as<uint64_t>(), cnnz, nc, out.off.as<int32_t>(), st);
   k_coarse_k<<<grid_for(nc), TPB, 0, st>>>(labof, a, nc, out.k.as<int32_t>());
   DC_LAUNCH_CHECK();
   out.n = nc;
   out.nnz = cnnz;
   k_first_level_meta<<<grid_for(nc), TPB, 0, st>>>(labof, sz, mstart, members, nc, cnt_out,
-                                                   minv_out);
+                                                   minv_out, H.lminv.as<int32_t>());
   DC_LAUNCH_CHECK();
   k_project<<<grid_for(nl), TPB, 0, st>>>(Cl, rank, nl, true, map0);
   DC_LAUNCH_CHECK();
+  H.lh = cnnz;
+  H.lnc = nc;
 }
 
 void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,
@@ -777,13 +824,14 @@ void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
                 hipStream_t st) {
   (void)s;
   const int64_t m = H.lh;
-  H.hkey.ensure(size_t(m + 1) * 8);
-  H.hw.ensure(size_t(m + 1) * 4);
+  // written where the next step's sort reads its input (coarsen_first_inc)
+  H.ek0.ensure(size_t(m + 1) * 8);
+  H.ev0.ensure(size_t(m + 1) * 4);
   if (m > 0) {
-    k_relabel<<<grid_for(m), TPB, 0, st>>>(H.lkey.as<uint64_t>(), m, H.lnc,
-                                           H.lminv.as<int32_t>(), Ct, n, H.hkey.as<uint64_t>());
+    k_relabel<<<grid_for(m), TPB, 0, st>>>(H.lkey.as<uint64_t>(), H.lw.as<int32_t>(), m, H.lnc,
+                                           H.lminv.as<int32_t>(), Ct, n, H.ek0.as<uint64_t>(),
+                                           H.ev0.as<uint32_t>());
     DC_LAUNCH_CHECK();
-    DC_HIP(hipMemcpyAsync(H.hw.p, H.lw.p, size_t(m) * 4, hipMemcpyDeviceToDevice, st));
   }
   H.h = m;
   H.valid = true;
@@ -792,13 +840,11 @@ void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
 void finalize_labels(int32_t nL, const int32_t* CL, const int32_t* aL, const int32_t* szL,
                      const int32_t* cntL, const int32_t* minvL, int32_t n0, const int32_t* map0,
                      int32_t* lab, int32_t* cntf, int32_t* C0, int32_t* a0, int32_t* sz0,
-                     hipStream_t st) {
-  fill_i32(lab, 0x7fffffff, nL, st);
-  fill_i32(cntf, 0, nL, st);
+                     hipStream_t st, long long* zero2) {
+  k_final_init<<<grid_for(nL > n0 ? nL : n0), TPB, 0, st>>>(lab, cntf, nL, a0, sz0, n0, zero2);
+  DC_LAUNCH_CHECK();
   k_final_min<<<grid_for(nL), TPB, 0, st>>>(CL, cntL, minvL, nL, lab, cntf);
   DC_LAUNCH_CHECK();
-  fill_i32(a0, 0, n0, st);
-  fill_i32(sz0, 0, n0, st);
   k_final_scatter<<<grid_for(nL), TPB, 0, st>>>(lab, cntf, aL, szL, nL, a0, sz0);
   DC_LAUNCH_CHECK();
   k_final_project<<<grid_for(n0), TPB, 0, st>>>(lab, CL, map0, n0, C0);

@@ -50,6 +50,7 @@ struct dc_ctx {
   long long* hstat_dev = nullptr;  // its address for the kernels that write it
   DBuf done;                   // finished-block counters (DONE_WORDS, zero between launches)
   void* hbuf = nullptr;        // pinned scratch for the kernels' host reads
+  int32_t* hbuf_dev = nullptr; // its address for the kernels that write it
   BinScratch bins;
   CoarsenScratch cs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -346,15 +346,22 @@ __device__ __forceinline__ int table_get(const int* keys, const int* vals,
 // primitives (prims.hip)
 
 // out[i] = sum_{j<i} in[j]; *total (device, may be null) = sum of all.
+// host_total (may be null): a device-visible address of pinned host memory
+// that the last kernel also writes the sum to, for the host to read after
+// its next wait on the stream (no copy).
 void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n,
-                   int32_t* total, hipStream_t st);
+                   int32_t* total, hipStream_t st, int32_t* host_total = nullptr);
 void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n,
-                   int64_t* total, hipStream_t st);
+                   int64_t* total, hipStream_t st, int64_t* host_total = nullptr);
 
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 // Sorted data ends in (k0, v0); (k1, v1) are scratch of the same size.
 void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                       int64_t n, int bits, hipStream_t st);
+// The same without the copy back: true when the sorted data ends in
+// (k1, v1) (an odd number of passes), false when in (k0, v0).
+bool radix_sort_pairs_swap(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                           int64_t n, int bits, hipStream_t st);
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);

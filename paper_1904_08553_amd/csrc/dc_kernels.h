@@ -146,5 +146,9 @@ void intra_weight(const int32_t* off, const int2* adj, const int32_t* C,
 void label_totals(const int32_t* k, const int32_t* C, int32_t n, int32_t* a,
                   hipStream_t st);
 void sum_squares(const int32_t* a, int32_t n, long long* S, hipStream_t st);
+// Both pieces in one launch over a partition whose label totals a are given:
+// *I += intra-community weight, *S += sum over labels of a^2.
+void modularity_terms(const int32_t* off, const int2* adj, const int32_t* C, const int32_t* a,
+                      int32_t n, long long* I, long long* S, hipStream_t st);
 
 }  // namespace dc

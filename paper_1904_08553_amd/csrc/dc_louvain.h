@@ -378,7 +378,8 @@ void nonempty_count(const int32_t* sz, int32_t n, long long* count, hipStream_t 
 struct CoarsenScratch {
   DBuf flag, rank, keys0, keys1, vals0, vals1, cntr, mstart, labof, mdeg, mvol, chead, cpos,
       chunks, mcnt, pk0, pk1, pv0, pv1, ph, pp, pS, pcnt, hidx, ukey, rc;
-  void* host = nullptr;  // pinned, 64 bytes
+  void* host = nullptr;      // pinned, 64 bytes
+  void* host_dev = nullptr;  // its address for the kernels that write it
 };
 
 struct CoarseGraph {
@@ -407,8 +408,7 @@ void coarsen(const LevelView& g, const int32_t* C, const int32_t* sz, const int3
 // smallest level-0 member of each of its vertices, from which the next H
 // is relabelled once the final labels are known.
 struct IncCoarsen {
-  DBuf hkey, hw;
-  int64_t h = 0;
+  int64_t h = 0;  // entries of H, at the front of ek0 / ev0
   bool valid = false;
   DBuf lkey, lw, lminv;
   int64_t lh = 0;
@@ -427,7 +427,8 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
                        const int32_t* ch_dk, int64_t nch, int32_t* map0, CoarseGraph& out,
                        int32_t* cnt_out, int32_t* minv_out, CoarsenScratch& s, IncCoarsen& H,
                        hipStream_t st);
-// Keeps the level-1 graph just built (and its vertices' smallest members).
+// Keeps the level-1 graph just built (and its vertices' smallest members);
+// coarsen_first_inc keeps its own as it builds it.
 void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,
                  IncCoarsen& H, hipStream_t st);
 // H(G_t, C_t) from the saved level-1 graph and the final labels C_t: its
@@ -438,10 +439,11 @@ void inc_finish(IncCoarsen& H, const int32_t* Ct, int32_t n, CoarsenScratch& s,
                 hipStream_t st);
 
 // Canonical labels of the final partition (smallest level-0 id per
-// community), the level-0 totals and sizes by label, and C_t.
+// community), the level-0 totals and sizes by label, and C_t.  zero2 (may
+// be null): two int64 counters cleared on the way (the caller's next sums).
 void finalize_labels(int32_t nL, const int32_t* CL, const int32_t* aL, const int32_t* szL,
                      const int32_t* cntL, const int32_t* minvL, int32_t n0, const int32_t* map0,
                      int32_t* lab, int32_t* cntf, int32_t* C0, int32_t* a0, int32_t* sz0,
-                     hipStream_t st);
+                     hipStream_t st, long long* zero2 = nullptr);
 
 }  // namespace dc

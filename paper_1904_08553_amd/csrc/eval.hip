@@ -1223,35 +1223,33 @@ __global__ void __launch_bounds__(META_TPB)
                int32_t* host, const long long* __restrict__ copy_src, long long* copy_dst,
                int copy_n) {
   __shared__ int wtot[META_TPB / WAVE];
-  __shared__ long long vrow[NROWS];
+  __shared__ long long vpart[META_TPB / WAVE][NROWS];
   __shared__ int meta[META_WORDS];
   const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
   const int64_t M = int64_t(NROWS) * nblocks;
-  if (t < NROWS) vrow[t] = 0;
   if (t < META_WORDS) meta[t] = 0;
   __syncthreads();
-  // row volumes: each thread sums its strided entries row by row
-  {
+  // row volumes: row by row, the threads stride over the blocks' partials
+  // (all loads independent), then one wave sum per row and wave
+#pragma unroll 1
+  for (int r = 0; r < NROWS; ++r) {
     long long acc = 0;
-    int row = -1;
-    for (int64_t k = t; k < M; k += META_TPB) {
-      const int r = int(k / nblocks);
-      if (r != row) {
-        if (row >= 0 && acc) atomicAdd((unsigned long long*)&vrow[row], (unsigned long long)acc);
-        row = r;
-        acc = 0;
-      }
-      acc += bvol[k];
-    }
-    if (row >= 0 && acc) atomicAdd((unsigned long long*)&vrow[row], (unsigned long long)acc);
+    for (int64_t b = t; b < nblocks; b += META_TPB) acc += bvol[int64_t(r) * nblocks + b];
+    acc = wave_sum(acc);
+    if (lane == 0) vpart[wid][r] = acc;
   }
   if (scan) {
-    // thread t scans the contiguous chunk [t * per, (t + 1) * per)
+    // thread t scans the contiguous chunk [t * per, (t + 1) * per), its
+    // counts held in registers (per <= META_PER)
     const int per = int(ceil_div(M, META_TPB));
     const int64_t b0 = int64_t(t) * per;
+    int v[META_PER];
     int sum = 0;
-    for (int i = 0; i < per; ++i)
-      if (b0 + i < M) sum += bcnt[b0 + i];
+#pragma unroll
+    for (int i = 0; i < META_PER; ++i) {
+      v[i] = (i < per && b0 + i < M) ? bcnt[b0 + i] : 0;
+      sum += v[i];
+    }
     const int incl = wave_incl_scan(sum);
     if (lane == WAVE - 1) wtot[wid] = incl;
     __syncthreads();
@@ -1266,11 +1264,11 @@ __global__ void __launch_bounds__(META_TPB)
     }
     __syncthreads();
     int run = wtot[wid] + incl - sum;
-    for (int i = 0; i < per; ++i)
-      if (b0 + i < M) {
-        boff[b0 + i] = run;
-        run += bcnt[b0 + i];
-      }
+#pragma unroll
+    for (int i = 0; i < META_PER; ++i) {
+      if (i < per && b0 + i < M) boff[b0 + i] = run;
+      run += v[i];
+    }
   } else if (t == 0) {
     meta[M_TOTAL] = counts[M_TOTAL];
   }
@@ -1286,7 +1284,8 @@ __global__ void __launch_bounds__(META_TPB)
     meta[NBINS + q] = s1 - s0;
   }
   if (t < NROWS) {
-    const long long v = vrow[t];
+    long long v = 0;
+    for (int w = 0; w < META_TPB / WAVE; ++w) v += vpart[w][t];
     meta[32 + 2 * t] = int(uint32_t(uint64_t(v)));
     meta[32 + 2 * t + 1] = int(uint32_t(uint64_t(v) >> 32));
   }

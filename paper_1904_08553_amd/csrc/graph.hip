@@ -516,7 +516,45 @@ __global__ void k_sum_squares(const int32_t* __restrict__ a, int32_t n,
   block_add(s, S);
 }
 
+// Blocks [0, nb_intra) add the intra-community weight (one wave per row),
+// the others the squares of the label totals.
+__global__ void __launch_bounds__(TPB)
+    k_modularity_terms(const int32_t* __restrict__ off, const int2* __restrict__ adj,
+                       const int32_t* __restrict__ C, const int32_t* __restrict__ a, int32_t n,
+                       int nb_intra, long long* I, long long* S) {
+  long long s = 0;
+  if (int(blockIdx.x) < nb_intra) {
+    const int64_t nwaves = int64_t(nb_intra) * (TPB / WAVE);
+    const int lane = lane_id();
+    for (int64_t row = int64_t(blockIdx.x) * (TPB / WAVE) + threadIdx.x / WAVE; row < n;
+         row += nwaves) {
+      const int32_t c = C[row];
+      for (int32_t j = off[row] + lane; j < off[row + 1]; j += WAVE) {
+        const int2 e = adj[j];
+        if (C[e.x] == c) s += e.y;
+      }
+    }
+    block_add(s, I);
+  } else {
+    const int64_t nbs = int64_t(gridDim.x) - nb_intra;
+    for (int64_t i = (int64_t(blockIdx.x) - nb_intra) * TPB + threadIdx.x; i < n; i += nbs * TPB) {
+      const long long x = a[i];
+      s += x * x;
+    }
+    block_add(s, S);
+  }
+}
+
 }  // namespace
+
+void modularity_terms(const int32_t* off, const int2* adj, const int32_t* C, const int32_t* a,
+                      int32_t n, long long* I, long long* S, hipStream_t st) {
+  if (n <= 0) return;
+  const int nb_intra = grid_for(int64_t(n) * WAVE, TPB, 4096);
+  const int nb_sq = grid_for(n, TPB, 2048);
+  k_modularity_terms<<<nb_intra + nb_sq, TPB, 0, st>>>(off, adj, C, a, n, nb_intra, I, S);
+  DC_LAUNCH_CHECK();
+}
 
 void validate_edges(const int32_t* u, const int32_t* v, const int32_t* w,
                     int64_t m, int32_t n, int32_t* flags, long long* wsum,
@@ -582,8 +620,9 @@ void resolve_changes(const uint64_t* keys, const uint32_t* vals, const int32_t* 
                      uint64_t* ch_key, int32_t* ch_op, int32_t* ch_w, int32_t* ch_dk,
                      int32_t* dnet, int32_t* flags, long long* wsum, hipStream_t st) {
   if (m <= 0) return;
-  fill_i32(run_w, 0, m, st);
-  fill_i32(run_ndel, 0, m, st);
+  void* zp[2] = {run_w, run_ndel};
+  const int64_t zb[2] = {4 * m, 4 * m};
+  zero_buffers(zp, zb, 2, st);
   k_run_accumulate<<<grid_for(m), TPB, 0, st>>>(keys, vals, pos, m, ins_w, run_key, run_w,
                                                 run_ndel);
   DC_LAUNCH_CHECK();

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(SCAN_THREADS)
 template <class T>
 __global__ void __launch_bounds__(SCAN_THREADS)
     k_tile_scan(const T* in, T* out, int64_t n, const T* __restrict__ part, int raw,
-                T* total, int64_t nblocks) {
+                T* total, int64_t nblocks, T* htotal) {
   __shared__ T lds[SCAN_THREADS / WAVE];
   T off = 0;
   if (part && raw) {
@@ -101,27 +101,31 @@ __global__ void __launch_bounds__(SCAN_THREADS)
     if (idx < n) out[idx] = run;
     run += v[i];
   }
-  if (total && blockIdx.x == nblocks - 1 && threadIdx.x == 0) *total = off + tot;
+  if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) {
+    if (total) *total = off + tot;
+    if (htotal) host_store(htotal, off + tot);
+  }
 }
 
 template <class T>
-__global__ void k_set_scalar(T* p, T v) {
-  *p = v;
+__global__ void k_set_scalar(T* p, T v, T* hp) {
+  if (p) *p = v;
+  if (hp) host_store(hp, v);
 }
 
 template <class T>
 void scan_excl_impl(const T* in, T* out, int64_t n, T* total, hipStream_t st,
-                    T* tmp, size_t tmp_elems) {
+                    T* tmp, size_t tmp_elems, T* htotal) {
   if (n <= 0) {
-    if (total) {
-      k_set_scalar<T><<<1, 1, 0, st>>>(total, T(0));
+    if (total || htotal) {
+      k_set_scalar<T><<<1, 1, 0, st>>>(total, T(0), htotal);
       DC_LAUNCH_CHECK();
     }
     return;
   }
   int64_t nb = ceil_div(n, SCAN_TILE);
   if (nb == 1) {
-    k_tile_scan<T><<<1, SCAN_THREADS, 0, st>>>(in, out, n, nullptr, 0, total, 1);
+    k_tile_scan<T><<<1, SCAN_THREADS, 0, st>>>(in, out, n, nullptr, 0, total, 1, htotal);
     DC_LAUNCH_CHECK();
     return;
   }
@@ -131,24 +135,24 @@ void scan_excl_impl(const T* in, T* out, int64_t n, T* total, hipStream_t st,
   DC_LAUNCH_CHECK();
   if (nb <= SCAN_RAW_MAX) {
     // each tile sums the totals before it (at most SCAN_RAW_MAX reads)
-    k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, 1, total, nb);
+    k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, 1, total, nb, htotal);
     DC_LAUNCH_CHECK();
     return;
   }
   // exclusive scan of the block partials in place (recursion on the tail)
-  scan_excl_impl<T>(part, part, nb, nullptr, st, tmp + nb, tmp_elems - size_t(nb));
-  k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, 0, total, nb);
+  scan_excl_impl<T>(part, part, nb, nullptr, st, tmp + nb, tmp_elems - size_t(nb), nullptr);
+  k_tile_scan<T><<<nb, SCAN_THREADS, 0, st>>>(in, out, n, part, 0, total, nb, htotal);
   DC_LAUNCH_CHECK();
 }
 
 template <class T>
-void scan_excl(const T* in, T* out, int64_t n, T* total, hipStream_t st) {
+void scan_excl(const T* in, T* out, int64_t n, T* total, hipStream_t st, T* htotal) {
   // partial sums need ~ n/2048 + n/2048^2 + ... elements
   size_t need = size_t(ceil_div(n, SCAN_TILE)) + 64;
   need += need / SCAN_TILE + 64;
   DBuf& b = prim_scratch().scan_tmp;
   b.ensure(need * sizeof(T));
-  scan_excl_impl<T>(in, out, n, total, st, b.as<T>(), b.bytes / sizeof(T));
+  scan_excl_impl<T>(in, out, n, total, st, b.as<T>(), b.bytes / sizeof(T), htotal);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,18 +367,26 @@ inline int grid_for(int64_t n, int threads = 256) {
 }  // namespace
 
 void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total,
-                   hipStream_t st) {
-  scan_excl<int32_t>(in, out, n, total, st);
+                   hipStream_t st, int32_t* host_total) {
+  scan_excl<int32_t>(in, out, n, total, st, host_total);
 }
 
 void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total,
-                   hipStream_t st) {
-  scan_excl<int64_t>(in, out, n, total, st);
+                   hipStream_t st, int64_t* host_total) {
+  scan_excl<int64_t>(in, out, n, total, st, host_total);
 }
 
 void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                       int64_t n, int bits, hipStream_t st) {
-  if (n <= 1 || bits <= 0) return;
+  if (radix_sort_pairs_swap(k0, v0, k1, v1, n, bits, st)) {
+    DC_HIP(hipMemcpyAsync(k0, k1, size_t(n) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    DC_HIP(hipMemcpyAsync(v0, v1, size_t(n) * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+}
+
+bool radix_sort_pairs_swap(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                           int64_t n, int bits, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return false;
   // fewest passes with digits of at most RS_MAX_DIGIT bits, equal widths
   const int passes = (bits + RS_MAX_DIGIT - 1) / RS_MAX_DIGIT;
   const int dbits = (bits + passes - 1) / passes;
@@ -397,10 +409,7 @@ void radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  if (ka != k0) {
-    DC_HIP(hipMemcpyAsync(k0, ka, size_t(n) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    DC_HIP(hipMemcpyAsync(v0, va, size_t(n) * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  }
+  return ka != k0;
 }
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
