@@ -718,11 +718,13 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     uint8_t* accflag = cascade ? c->accflag.as<uint8_t>() : nullptr;
     {
       // R, the community flags, the deletion-source flags, the accepted
-      // flags (cascade) and the union flags (fused) start at zero
-      void* zp[5] = {R, cflag, dflag, accflag, fused ? c->uflag.p : nullptr};
-      const int64_t zb[5] = {n, n, 4 * int64_t(n), cascade ? int64_t(n) : 0,
-                             fused ? int64_t(n) : 0};
-      zero_buffers(zp, zb, 5, st);
+      // flags (cascade), the union flags (fused) and the count of R_t's
+      // list start at zero
+      void* zp[6] = {R, cflag, dflag, accflag, fused ? c->uflag.p : nullptr,
+                     c->rpos2.as<int32_t>() + n};
+      const int64_t zb[6] = {n, n, 4 * int64_t(n), cascade ? int64_t(n) : 0,
+                             fused ? int64_t(n) : 0, 4};
+      zero_buffers(zp, zb, 6, st);
     }
     uint64_t* ins_keys = c->ins_keys.as<uint64_t>();
     gather_u64(ch_key, c->ins_flag.as<int32_t>(), c->ins_pos.as<int32_t>(), nch, ins_keys, st);
@@ -851,11 +853,8 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     }
     if (n_dsrc > 0 && !fused)
       mark_neighbourhoods(c->dlist.as<int32_t>(), n_dsrc, g0.off, g0.adj, R, st);
-    int32_t* rflag = c->rflag.as<int32_t>();
     int32_t* rpos2 = c->rpos2.as<int32_t>();
-    materialize_R(R, cflag, c->C.as<int32_t>(), n, rflag, st);
-    scan_excl_i32(rflag, rpos2, n, rpos2 + n, st);
-    compact_index(rflag, rpos2, n, c->Rlist.as<int32_t>(), st);
+    materialize_R(R, cflag, c->C.as<int32_t>(), n, c->Rlist.as<int32_t>(), rpos2 + n, st);
     S.ds_sources = n_src;
     S.del_sources = n_dsrc;
     S.vertex_evals += S.ds_sources + S.del_sources + S.cascade_candidates;
@@ -880,14 +879,13 @@ dc_status apply_front(dc_ctx* c, const dc_edges* add, const dc_edges* del, const
     if (score) {
       // R_t = touched vertices scoring at least theta
       uint8_t* R = c->R.as<uint8_t>();
-      int32_t* rflag = c->rflag.as<int32_t>();
       int32_t* rpos2 = c->rpos2.as<int32_t>();
-      fill_u8(R, 0, n, st);
+      void* zp[2] = {R, rpos2 + n};
+      const int64_t zb[2] = {n, 4};
+      zero_buffers(zp, zb, 2, st);
       select_by_score(c->Tlist.as<int32_t>(), c->T_count, c->logits.as<float>(), c->theta, R,
                       st);
-      merge_flags(R, nullptr, n, rflag, st);
-      scan_excl_i32(rflag, rpos2, n, rpos2 + n, st);
-      compact_index(rflag, rpos2, n, c->Rlist.as<int32_t>(), st);
+      materialize_R(R, nullptr, nullptr, n, c->Rlist.as<int32_t>(), rpos2 + n, st);
       // its length is read with the level-0 binning's wait (levels_begin)
       c->R_dcount = rpos2 + n;
       c->R_count = n;

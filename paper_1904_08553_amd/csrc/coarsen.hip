@@ -318,13 +318,7 @@ __global__ void k_final_project(const int32_t* __restrict__ lab,
   GRID_STRIDE(v, n0) { C0[v] = lab[CL[map0[v]]]; }
 }
 
-
 // ---- incremental first-level compaction ----------------------------------
-
-__global__ void k_mover_vol(const int32_t* __restrict__ Cl, const int32_t* __restrict__ Cold,
-                            const int32_t* __restrict__ off, int32_t n, int32_t* mvol) {
-  GRID_STRIDE(v, n) { mvol[v] = Cl[v] != Cold[v] ? off[v + 1] - off[v] : 0; }
-}
 
 // Entry q of mover u's row (u -> v, weight w) owns four slots from
 // 4 * (mpos[u] + q): w leaves (Cold u, Cold v) and joins (Cl u, Cl v); when v
@@ -416,6 +410,17 @@ __global__ void k_compact_runs(const uint64_t* __restrict__ keys, const int32_t*
       okey[npos[i]] = keys[i];
       ow[npos[i]] = int32_t(rsum[i]);
     }
+  }
+}
+
+// The two flag arrays of the incremental compaction: non-empty labels and
+// the row volumes of the level-0 movers.
+__global__ void k_inc_flags(const int32_t* __restrict__ sz, const int32_t* __restrict__ Cl,
+                            const int32_t* __restrict__ Cold, const int32_t* __restrict__ off,
+                            int32_t n, int32_t* flag, int32_t* mvol) {
+  GRID_STRIDE(v, n) {
+    flag[v] = sz[v] > 0 ? 1 : 0;
+    mvol[v] = Cl[v] != Cold[v] ? off[v + 1] - off[v] : 0;
   }
 }
 
@@ -703,16 +708,14 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   s.rank.ensure(size_t(nl + 1) * 4);
   int32_t* flag = s.flag.as<int32_t>();
   int32_t* rank = s.rank.as<int32_t>();
-  k_nonempty<<<grid_for(nl), TPB, 0, st>>>(sz, nl, flag);
-  DC_LAUNCH_CHECK();
-  scan_excl_i32(flag, rank, nl, rank + nl, st, hdev);
-  // movers' row volumes
+  // and the movers' row volumes
   H.mvol.ensure(size_t(nl + 1) * 4);
   H.mflag.ensure(size_t(nl + 1) * 4);
   int32_t* mvol = H.mvol.as<int32_t>();
   int32_t* mpos = H.mflag.as<int32_t>();
-  k_mover_vol<<<grid_for(nl), TPB, 0, st>>>(Cl, Cold, g.off, nl, mvol);
+  k_inc_flags<<<grid_for(nl), TPB, 0, st>>>(sz, Cl, Cold, g.off, nl, flag, mvol);
   DC_LAUNCH_CHECK();
+  scan_excl_i32(flag, rank, nl, rank + nl, st, hdev);
   scan_excl_i32(mvol, mpos, nl, mpos + nl, st, hdev + 1);
   DC_HIP(hipStreamSynchronize(st));
   const int32_t nc = host[0];

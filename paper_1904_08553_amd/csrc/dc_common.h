@@ -367,7 +367,7 @@ void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 // Sets count (<= 6) device buffers of bytes[j] bytes each to zero in one
-// launch; each buffer starts 16-byte aligned.
+// launch; a buffer of 16 bytes or more starts 16-byte aligned.
 void zero_buffers(void* const* p, const int64_t* bytes, int count, hipStream_t st);
 void iota_i32(int32_t* p, int64_t n, hipStream_t st);
 // dst[j][i] = src[j][i] for j < count (<= 4) in one launch.

@@ -350,9 +350,12 @@ void screen_union(const uint64_t* ch_key, const int32_t* ch_op, const int32_t* i
 // R[i] = 1 and R[Gamma(i)] = 1 for every listed vertex.
 void mark_neighbourhoods(const int32_t* list, int64_t cnt, const int32_t* off, const int2* adj,
                          uint8_t* R, hipStream_t st);
-// R[v] |= cflag[C[v]]; rflag[v] = R[v].
+// R[v] |= cflag[C[v]] (cflag null: R as it is), and the vertices with
+// R[v] != 0 appended to list
+// (*count, zero before the call, becomes their number; the order of the
+// list is not fixed).
 void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n,
-                   int32_t* rflag, hipStream_t st);
+                   int32_t* list, int32_t* count, hipStream_t st);
 // Cn[v] = pre[v] for every listed v with R[v] != 0: the first sweep's
 // decisions that the screening pass already took.
 void apply_pre(const int32_t* list, int64_t cnt, const uint8_t* R, const int32_t* pre,

@@ -148,13 +148,50 @@ __global__ void k_mark_neighbourhoods(const int32_t* __restrict__ list,
   }
 }
 
-__global__ void k_materialize_R(uint8_t* R, const uint8_t* __restrict__ cflag,
-                                const int32_t* __restrict__ C, int32_t n,
-                                int32_t* rflag) {
-  GRID_STRIDE(v, n) {
-    uint8_t r = R[v] | cflag[C[v]];
-    R[v] = r;
-    rflag[v] = r;
+// R[v] |= cflag[C[v]] (cflag may be null), and the vertices of R appended
+// to list: a block
+// takes RL_ROUNDS tiles of TPB vertices and reserves its places with one
+// atomic on *count (ascending within the block, blocks in any order).
+constexpr int RL_ROUNDS = 8;
+__global__ void __launch_bounds__(TPB)
+    k_materialize_R(uint8_t* R, const uint8_t* __restrict__ cflag,
+                    const int32_t* __restrict__ C, int32_t n, int32_t* list, int32_t* count) {
+  __shared__ int wc[RL_ROUNDS][TPB / WAVE];
+  __shared__ int base;
+  const int lane = lane_id(), wid = threadIdx.x / WAVE;
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  const int64_t v0 = int64_t(blockIdx.x) * (RL_ROUNDS * TPB) + threadIdx.x;
+  uint64_t fm[RL_ROUNDS];
+  bool f[RL_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RL_ROUNDS; ++r) {
+    const int64_t v = v0 + int64_t(r) * TPB;
+    f[r] = false;
+    if (v < n) {
+      const uint8_t x = cflag ? uint8_t(R[v] | cflag[C[v]]) : R[v];
+      if (cflag) R[v] = x;
+      f[r] = x != 0;
+    }
+    fm[r] = __ballot(f[r]);
+    if (lane == 0) wc[r][wid] = __popcll(fm[r]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int r = 0; r < RL_ROUNDS; ++r)
+      for (int w = 0; w < TPB / WAVE; ++w) tot += wc[r][w];
+    base = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  int pos = base;
+#pragma unroll
+  for (int r = 0; r < RL_ROUNDS; ++r) {
+    if (f[r]) {
+      int q = pos + __popcll(fm[r] & lt);
+      for (int w = 0; w < wid; ++w) q += wc[r][w];
+      list[q] = int32_t(v0 + int64_t(r) * TPB);
+    }
+    for (int w = 0; w < TPB / WAVE; ++w) pos += wc[r][w];
   }
 }
 
@@ -308,9 +345,10 @@ void mark_neighbourhoods(const int32_t* list, int64_t cnt, const int32_t* off, c
 }
 
 void materialize_R(uint8_t* R, const uint8_t* cflag, const int32_t* C, int32_t n,
-                   int32_t* rflag, hipStream_t st) {
+                   int32_t* list, int32_t* count, hipStream_t st) {
   if (n <= 0) return;
-  k_materialize_R<<<grid_for(n), TPB, 0, st>>>(R, cflag, C, n, rflag);
+  k_materialize_R<<<int(ceil_div(n, RL_ROUNDS * TPB)), TPB, 0, st>>>(R, cflag, C, n, list,
+                                                                      count);
   DC_LAUNCH_CHECK();
 }
 
