@@ -246,6 +246,7 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
     if (level > 0) {
       Bins bins;
       make_bins(nullptr, g.n, g.off, bins, c->bins, st);
+      inc_check(c->cs);
       level_gain = run_sweeps(c, g, nullptr, g.n, bins, level, T, true);
     }
     const bool stop = (level + 1 >= c->opt.max_levels) || (level >= 1 && level_gain <= T);
@@ -283,9 +284,17 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
                   c->a0.as<int32_t>(), c->sz0.as<int32_t>(), st, stat + ST_I);
   inc_finish(c->inc, c->C.as<int32_t>(), c->n, c->cs, st);  // H(G_t, C_t) for the next step
   c->inc_ready = false;
-  // exact numerator on the final level (coarsening preserves N)
+  // exact numerator on the final level (coarsening preserves N); C_t goes
+  // to the caller of dc_apply_batch before the same wait
   modularity_terms(g.off, g.adj, Cl, al, g.n, stat + ST_I, stat + ST_S, st);
+  if (c->out_C) {
+    DC_HIP(hipMemcpyAsync(c->out_C, c->C.p, size_t(c->n) * 4,
+                          c->out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          st));
+    c->out_C = nullptr;
+  }
   read_stat(c);
+  inc_check(c->cs);
   S.N = two_m * c->hstat[ST_I] - c->hstat[ST_S];
   S.two_m = two_m;
   S.q = two_m == 0 ? 0.0 : double(S.N) / (double(two_m) * double(two_m));
@@ -922,12 +931,21 @@ void screening_counts(dc_ctx* c) {
   S.accepted_volume = hs[ST_ACCVOL];
 }
 
-// Last part of a time step: C_t to the caller (device or host memory).
-void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device) {
-  if (!C_out) return;
-  DC_HIP(hipMemcpyAsync(C_out, c->C.p, size_t(c->n) * 4,
-                        out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+// Last part of a time step: C_t to the caller (device or host memory),
+// unless levels_finish has already copied it with its last wait.
+void apply_output(dc_ctx* c) {
+  if (!c->out_C) return;
+  DC_HIP(hipMemcpyAsync(c->out_C, c->C.p, size_t(c->n) * 4,
+                        c->out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        c->st));
   DC_HIP(hipStreamSynchronize(c->st));
+  c->out_C = nullptr;
+}
+
+void apply_output(dc_ctx* c, int32_t* C_out, int32_t out_on_device) {
+  c->out_C = C_out;
+  c->out_on_device = out_on_device;
+  apply_output(c);
 }
 
 // Device time and algorithmic bytes of a timed step's phases (the bytes of
@@ -962,8 +980,14 @@ dc_status do_apply(dc_ctx* c, const dc_edges* add, const dc_edges* del, int32_t*
     c->phase_timing = false;
     return s;
   }
+  c->out_C = C_out;
+  c->out_on_device = out_on_device;
+  struct ClearOut {  // no destination outlives the call (also on an error)
+    dc_ctx* c;
+    ~ClearOut() { c->out_C = nullptr; }
+  } clear_out{c};
   run_levels(c, act, nact);
-  apply_output(c, C_out, out_on_device);
+  apply_output(c);
   mark_phase(c, 4);
   if (c->phase_timing) phase_stats(c);
   c->phase_timing = false;

@@ -790,8 +790,7 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
                                               hdev + 2);
     DC_LAUNCH_CHECK();
   }
-  DC_HIP(hipStreamSynchronize(st));
-  if (host[2]) throw std::runtime_error("incremental coarsening: inconsistent community graph");
+  s.inc_check = true;  // read after the caller's next wait (inc_check)
   row_bounds(H.lkey.as<uint64_t>(), cnnz, nc, out.off.as<int32_t>(), st);
   k_coarse_k<<<grid_for(nc), TPB, 0, st>>>(labof, a, nc, out.k.as<int32_t>());
   DC_LAUNCH_CHECK();
@@ -804,6 +803,13 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
   DC_LAUNCH_CHECK();
   H.lh = cnnz;
   H.lnc = nc;
+}
+
+void inc_check(CoarsenScratch& s) {
+  if (!s.inc_check) return;
+  s.inc_check = false;
+  if (static_cast<const int32_t*>(s.host)[2])
+    throw std::runtime_error("incremental coarsening: inconsistent community graph");
 }
 
 void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,

@@ -58,6 +58,8 @@ struct dc_ctx {
   bool phase_timing = false;   // record them (dc_apply_batch with timing = 1)
   std::vector<dc_sweep_rec> trace;
   dc_step_stats stats{};
+  int32_t* out_C = nullptr;   // C_t's destination of the running dc_apply_batch (copied
+  int32_t out_on_device = 0;  // with the last wait of the step)
   int64_t R_count = 0;
   const int32_t* R_dcount = nullptr;  // |R_t| in device memory, not yet read back
   bool have_R_all = true;

@@ -383,6 +383,7 @@ struct CoarsenScratch {
       chunks, mcnt, pk0, pk1, pv0, pv1, ph, pp, pS, pcnt, hidx, ukey, rc;
   void* host = nullptr;      // pinned, 64 bytes
   void* host_dev = nullptr;  // its address for the kernels that write it
+  bool inc_check = false;    // coarsen_first_inc's self-check flag awaits a wait
 };
 
 struct CoarseGraph {
@@ -430,6 +431,10 @@ void coarsen_first_inc(const LevelView& g, const int32_t* Cl, const int32_t* Col
                        const int32_t* ch_dk, int64_t nch, int32_t* map0, CoarseGraph& out,
                        int32_t* cnt_out, int32_t* minv_out, CoarsenScratch& s, IncCoarsen& H,
                        hipStream_t st);
+// After the caller's next wait on the stream following coarsen_first_inc:
+// raises its self-check (an entry of an empty community or of weight below
+// 1 in the graph of communities), which the kernel reports in host memory.
+void inc_check(CoarsenScratch& s);
 // Keeps the level-1 graph just built (and its vertices' smallest members);
 // coarsen_first_inc keeps its own as it builds it.
 void save_level1(const CoarseGraph& out, const CoarsenScratch& s, const int32_t* minv,

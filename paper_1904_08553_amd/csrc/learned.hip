@@ -397,16 +397,18 @@ __global__ void k_flags(const uint8_t* __restrict__ a, const uint8_t* __restrict
     flag[v] = (a[v] | (b ? b[v] : 0)) ? 1 : 0;
 }
 
-// one wave per listed vertex
+// 16 lanes per listed vertex (four vertices per wave: the rows are short)
+constexpr int MT_GS = 16;
 __global__ void k_mark_touched(const int32_t* __restrict__ list, const int32_t* __restrict__ count,
                                const int32_t* __restrict__ off, const int2* __restrict__ adj,
                                uint8_t* out) {
   const int64_t cnt = *count;
-  const int64_t nwaves = int64_t(gridDim.x) * NW;
-  for (int64_t p = int64_t(blockIdx.x) * NW + threadIdx.x / WAVE; p < cnt; p += nwaves) {
+  const int gl = lane_id() % MT_GS;
+  const int64_t ngroups = int64_t(gridDim.x) * (TPB / MT_GS);
+  for (int64_t p = (int64_t(blockIdx.x) * TPB + threadIdx.x) / MT_GS; p < cnt; p += ngroups) {
     const int i = list[p];
-    if (lane_id() == 0) out[i] = 1;
-    for (int32_t j = off[i] + lane_id(); j < off[i + 1]; j += WAVE) out[adj[j].x] = 1;
+    if (gl == 0) out[i] = 1;
+    for (int32_t j = off[i] + gl; j < off[i + 1]; j += MT_GS) out[adj[j].x] = 1;
   }
 }
 
@@ -460,14 +462,16 @@ void merge_flags(const uint8_t* a, const uint8_t* b, int32_t n, int32_t* flag, h
 void mark_touched(const int32_t* list, const int32_t* count, int64_t max_count,
                   const int32_t* off, const int2* adj, uint8_t* out, hipStream_t st) {
   if (max_count <= 0) return;
-  k_mark_touched<<<grid_for(max_count * WAVE, 4096), TPB, 0, st>>>(list, count, off, adj, out);
+  k_mark_touched<<<grid_for(max_count * MT_GS, 4096), TPB, 0, st>>>(list, count, off, adj, out);
   DC_LAUNCH_CHECK();
 }
 
 void mlp_forward(const uint16_t* wq, const uint16_t* X, int64_t n, float* logits, hipStream_t st) {
   if (n <= 0) return;
+  // each wave loads the whole network into registers once, so the grid
+  // stays at a few blocks per CU and the waves loop over many tiles
   int64_t b = ceil_div(ceil_div(n, 16), NW);
-  if (b > 2048) b = 2048;
+  if (b > 1024) b = 1024;
   k_mlp_forward<<<int(b), TPB, 0, st>>>(wq, X, n, logits);
   DC_LAUNCH_CHECK();
 }
