@@ -30,52 +30,70 @@ __device__ __forceinline__ void touch_label(int X, long long v, long long* dpack
   }
 }
 
+// Block b takes AM_ROUNDS tiles of the active list; all its entries and
+// their labels are loaded first, the block reserves its movers' places in
+// the mover list with one atomic (a counter that every tile added to
+// serialised thousands of same-address atomics when the movers were few and
+// spread out), then lists them and applies their label changes.
+constexpr int AM_ROUNDS = 8;
 __global__ void __launch_bounds__(TPB)
     k_apply_moves(const int32_t* __restrict__ list, int64_t cnt,
                   const int32_t* __restrict__ C, const int32_t* __restrict__ Cn,
                   const int32_t* __restrict__ k, long long* dpack, int32_t* tflag,
                   int32_t* tlist, int32_t* movers, long long* stat) {
   __shared__ AggLds agg;
-  __shared__ int wcount[NW];
-  __shared__ int btotal;
+  __shared__ int wc[AM_ROUNDS][NW];
   __shared__ long long bbase;
+  __shared__ int btotal;
   const int wid = threadIdx.x / WAVE, lane = lane_id();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
-  const int64_t stride = int64_t(gridDim.x) * TPB;
-  // the block's label changes are summed in LDS over all its tiles, so a
-  // large community gets one update per block (see agg_try)
+  const int64_t v0 = int64_t(blockIdx.x) * (AM_ROUNDS * TPB) + threadIdx.x;
+  int u[AM_ROUNDS], from[AM_ROUNDS], to[AM_ROUNDS];
+  uint64_t fm[AM_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < AM_ROUNDS; ++r) {
+    const int64_t p = v0 + int64_t(r) * TPB;
+    u[r] = p < cnt ? (list ? list[p] : int(p)) : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < AM_ROUNDS; ++r) {
+    from[r] = u[r] >= 0 ? C[u[r]] : 0;
+    to[r] = u[r] >= 0 ? Cn[u[r]] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < AM_ROUNDS; ++r) {
+    fm[r] = __ballot(from[r] != to[r]);
+    if (lane == 0) wc[r][wid] = __popcll(fm[r]);
+  }
+  // the block's label changes are summed in LDS, so a large community gets
+  // one update per block (see agg_try)
   agg_init(agg);
-  for (int64_t base = int64_t(blockIdx.x) * TPB; base < cnt; base += stride) {
-    const int64_t p = base + threadIdx.x;
-    int u = 0;
-    bool mover = false;
-    if (p < cnt) {
-      u = list ? list[p] : int(p);
-      mover = Cn[u] != C[u];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int r = 0; r < AM_ROUNDS; ++r)
+      for (int w = 0; w < NW; ++w) tot += wc[r][w];
+    btotal = tot;
+    bbase = tot ? (long long)atomicAdd((unsigned long long*)&stat[ST_MOVES],
+                                       (unsigned long long)tot)
+                : 0;
+  }
+  __syncthreads();
+  if (btotal == 0) return;  // uniform: nothing moved in this block's tiles
+  long long run = bbase;
+#pragma unroll
+  for (int r = 0; r < AM_ROUNDS; ++r) {
+    if (from[r] != to[r]) {
+      long long pos = run + __popcll(fm[r] & lt);
+      for (int w = 0; w < wid; ++w) pos += wc[r][w];
+      movers[pos] = u[r];
+      const int ku = k[u[r]];
+      if (!agg_try(agg, from[r], pack2(-ku, -1)))
+        touch_label(from[r], pack2(-ku, -1), dpack, tflag, tlist, stat);
+      if (!agg_try(agg, to[r], pack2(ku, 1)))
+        touch_label(to[r], pack2(ku, 1), dpack, tflag, tlist, stat);
     }
-    const uint64_t m = __ballot(mover);
-    if (lane == 0) wcount[wid] = __popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int tot = 0;
-      for (int w = 0; w < NW; ++w) tot += wcount[w];
-      btotal = tot;
-      bbase = tot ? (long long)atomicAdd((unsigned long long*)&stat[ST_MOVES],
-                                         (unsigned long long)tot)
-                  : 0;
-    }
-    __syncthreads();
-    if (btotal == 0) continue;  // uniform: nothing moved in this tile
-    if (mover) {
-      long long pos = bbase + __popcll(m & lt);
-      for (int w = 0; w < wid; ++w) pos += wcount[w];
-      movers[pos] = u;
-      const int ku = k[u];
-      const int from = C[u], to = Cn[u];
-      if (!agg_try(agg, from, pack2(-ku, -1))) touch_label(from, pack2(-ku, -1), dpack, tflag, tlist, stat);
-      if (!agg_try(agg, to, pack2(ku, 1))) touch_label(to, pack2(ku, 1), dpack, tflag, tlist, stat);
-    }
-    __syncthreads();  // wcount and btotal are rewritten by the next tile
+    for (int w = 0; w < NW; ++w) run += wc[r][w];
   }
   // every label left in the table gets one global update; the labels that
   // this sweep touches first are appended to tlist with one counter update
@@ -85,7 +103,7 @@ __global__ void __launch_bounds__(TPB)
   __shared__ long long fbase;
   __syncthreads();
   int fx[FR];
-  uint64_t fm[FR];
+  uint64_t gm[FR];
 #pragma unroll
   for (int r = 0; r < FR; ++r) {
     const int X = agg.keys[r * TPB + threadIdx.x];
@@ -98,8 +116,8 @@ __global__ void __launch_bounds__(TPB)
       }
     }
     fx[r] = first ? X : -1;
-    fm[r] = __ballot(first);
-    if (lane == 0) fcount[r][wid] = __popcll(fm[r]);
+    gm[r] = __ballot(first);
+    if (lane == 0) fcount[r][wid] = __popcll(gm[r]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -115,7 +133,7 @@ __global__ void __launch_bounds__(TPB)
 #pragma unroll
   for (int r = 0; r < FR; ++r) {
     if (fx[r] >= 0) {
-      long long q = pos + __popcll(fm[r] & lt);
+      long long q = pos + __popcll(gm[r] & lt);
       for (int w = 0; w < wid; ++w) q += fcount[r][w];
       tlist[q] = fx[r];
     }
@@ -123,15 +141,17 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
+constexpr int DT_GS = 16;  // lanes per mover in k_delta_terms
+
 __device__ __forceinline__ int unpack_lo(long long d) { return int(uint32_t(uint64_t(d))); }
 __device__ __forceinline__ int unpack_hi(long long d) {
   return int((d - (long long)unpack_lo(d)) >> 32);
 }
 
 // The two terms of the exact Delta N in one launch: blocks [0, nb_intra)
-// sum the change of the intra-community weight over the movers' rows (one
-// wave per mover), the other blocks the change of sum a^2 over the touched
-// labels.
+// sum the change of the intra-community weight over the movers' rows (16
+// lanes per mover), the other blocks the change of sum a^2 over the
+// touched labels.
 __global__ void __launch_bounds__(TPB)
     k_delta_terms(const int32_t* __restrict__ movers, const int32_t* __restrict__ tlist,
                   const int32_t* __restrict__ off, const int2* __restrict__ adj,
@@ -141,17 +161,39 @@ __global__ void __launch_bounds__(TPB)
   long long s = 0;
   if (int(blockIdx.x) < nb_intra) {
     const int64_t cnt = stat[ST_MOVES];
+    const int lane = lane_id(), gl = lane % DT_GS;
     const int64_t nwaves = int64_t(nb_intra) * NW;
-    const int lane = lane_id();
-    for (int64_t p = int64_t(blockIdx.x) * NW + threadIdx.x / WAVE; p < cnt; p += nwaves) {
-      const int u = movers[p];
-      const int cu = C[u], nu = Cn[u];
-      for (int32_t j = off[u] + lane; j < off[u + 1]; j += WAVE) {
-        const int2 e = adj[j];
-        if (e.x == u) continue;
-        const int cy = C[e.x], ny = Cn[e.x];
-        const int d = int(nu == ny) - int(cu == cy);
-        if (d) s += (long long)e.y * d * (cy != ny ? 1 : 2);
+    // a wave takes WAVE / DT_GS movers per round; a row longer than a wave
+    // is left to the whole wave afterwards, so hubs keep wave speed
+    for (int64_t wb = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * (WAVE / DT_GS);
+         wb < cnt; wb += nwaves * (WAVE / DT_GS)) {
+      const int64_t p = wb + lane / DT_GS;
+      const bool have = p < cnt;
+      const int u = have ? movers[p] : 0;
+      const int32_t rb = have ? off[u] : 0, re = have ? off[u + 1] : 0;
+      const int cu = have ? C[u] : 0, nu = have ? Cn[u] : 0;
+      const bool wide = re - rb > WAVE;
+      if (!wide) {
+        for (int32_t j = rb + gl; j < re; j += DT_GS) {
+          const int2 e = adj[j];
+          if (e.x == u) continue;
+          const int cy = C[e.x], ny = Cn[e.x];
+          const int d = int(nu == ny) - int(cu == cy);
+          if (d) s += (long long)e.y * d * (cy != ny ? 1 : 2);
+        }
+      }
+      for (uint64_t wm = __ballot(wide && gl == 0); wm; wm &= wm - 1) {
+        const int l = __ffsll((unsigned long long)wm) - 1;
+        const int wu = __builtin_amdgcn_readlane(u, l);
+        const int wcu = __builtin_amdgcn_readlane(cu, l), wnu = __builtin_amdgcn_readlane(nu, l);
+        const int32_t wre = __builtin_amdgcn_readlane(re, l);
+        for (int32_t j = __builtin_amdgcn_readlane(rb, l) + lane; j < wre; j += WAVE) {
+          const int2 e = adj[j];
+          if (e.x == wu) continue;
+          const int cy = C[e.x], ny = Cn[e.x];
+          const int d = int(wnu == ny) - int(wcu == cy);
+          if (d) s += (long long)e.y * d * (cy != ny ? 1 : 2);
+        }
       }
     }
     block_add(s, &stat[ST_DI]);
@@ -239,15 +281,18 @@ void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, in
                  long long* dpack, int32_t* tflag, int32_t* tlist, long long* stat,
                  unsigned* done, long long* host_stat, hipStream_t st) {
   const int64_t cnt = n_active > 0 ? n_active : 1;
-  k_apply_moves<<<grid_for(cnt, 512), TPB, 0, st>>>(active, n_active, C, Cn, g.k, dpack, tflag,
-                                                     tlist, movers, stat);
+  k_apply_moves<<<int(ceil_div(cnt, AM_ROUNDS * TPB)), TPB, 0, st>>>(
+      active, n_active, C, Cn, g.k, dpack, tflag, tlist, movers, stat);
   DC_LAUNCH_CHECK();
-  const int nb_intra = grid_for(cnt * WAVE, 4096), nb_sq = grid_for(2 * cnt, 2048);
+  // grids sized for the active list (the movers are known on the device
+  // only); the loops stride, so most sweeps' few movers leave blocks idle
+  const int nb_intra = grid_for(ceil_div(cnt, WAVE / DT_GS) * WAVE, 4096);
+  const int nb_sq = grid_for(2 * cnt, 256);
   k_delta_terms<<<nb_intra + nb_sq, TPB, 0, st>>>(movers, tlist, g.off, g.adj, C, Cn, dpack, a,
                                                   nb_intra, stat);
   DC_LAUNCH_CHECK();
-  k_commit<<<grid_for(2 * cnt, 2048), TPB, 0, st>>>(movers, tlist, stat, two_m, C, Cn, dpack,
-                                                    tflag, a, sz, done, host_stat);
+  k_commit<<<grid_for(2 * cnt, 512), TPB, 0, st>>>(movers, tlist, stat, two_m, C, Cn, dpack,
+                                                   tflag, a, sz, done, host_stat);
   DC_LAUNCH_CHECK();
 }
 

@@ -198,8 +198,8 @@ def evaluate(seeds, w, theta, workers=8, modes=("all", "delta", "learned"), n=No
     """Each graph's four batches under full re-evaluation (ALL), plain
     Delta-screening, Delta-screening with the cascade extension (mode
     "cascade", threshold CASCADE) and LEARNED; per mode the batch times (each
-    call returns after C_t is written), changes, Q per batch, level-0
-    evaluations."""
+    call returns after C_t is written to a device buffer, inputs resident),
+    changes, Q per batch, level-0 evaluations."""
     import torch
     code = {"all": dc.MODE_ALL, "delta": dc.MODE_DELTA, "cascade": dc.MODE_DELTA,
             "learned": dc.MODE_LEARNED}
@@ -207,6 +207,7 @@ def evaluate(seeds, w, theta, workers=8, modes=("all", "delta", "learned"), n=No
     src = pregen if pregen is not None else graphs(seeds, workers, n)
     for s, nn, (u, v, w_), batches in src:
         dev = _dev_batches(batches)
+        out_C = torch.empty(nn, dtype=torch.int32, device="cuda")  # C_t stays in HBM
         for m in modes:
             extra = {"cascade": CASCADE} if m == "cascade" else {}
             g = dc.DynamicCommunities(nn, u, v, w_, mode=code[m], **extra)
@@ -215,7 +216,7 @@ def evaluate(seeds, w, theta, workers=8, modes=("all", "delta", "learned"), n=No
             torch.cuda.synchronize()
             for b, hb in zip(dev, batches):
                 t = time.perf_counter()
-                g.apply_batch(*b)
+                g.apply_batch(*b, out=out_C)
                 out[m]["ms"].append((time.perf_counter() - t) * 1e3)
                 st = g.stats
                 out[m]["changes"] += hb.size
