@@ -245,7 +245,8 @@ void levels_finish(dc_ctx* c, LevelRun& L, long long level0_gain) {
   while (true) {
     if (level > 0) {
       Bins bins;
-      make_bins(nullptr, g.n, g.off, bins, c->bins, st);
+      make_bins(nullptr, g.n, g.off, bins, c->bins, st, nullptr, nullptr, nullptr, nullptr, 0,
+                true);
       inc_check(c->cs);
       level_gain = run_sweeps(c, g, nullptr, g.n, bins, level, T, true);
     }
@@ -369,7 +370,8 @@ void run_levels_slm(dc_ctx* c, const int32_t* active, int64_t n_active) {
     start_level(Cl, Cn, al, szl, g.k, g.n, st);
     const LevelView gs{g.n, nnz_s, c->sub_off.as<int32_t>(), c->sub_adj.as<int2>(), g.k};
     Bins rb;
-    make_bins(nullptr, g.n, gs.off, rb, c->bins, st);
+    make_bins(nullptr, g.n, gs.off, rb, c->bins, st, nullptr, nullptr, nullptr, nullptr, 0,
+              level > 0);
     (void)run_sweeps(c, gs, nullptr, g.n, rb, level, T, true, false, 1);
     // 4. compaction by the refined communities
     const int next = level % 2;
@@ -393,7 +395,7 @@ void run_levels_slm(dc_ctx* c, const int32_t* active, int64_t n_active) {
     totals_sizes(g.k, Cl, g.n, al, szl, st);
     if (!reduced) break;
     Bins b;
-    make_bins(nullptr, g.n, g.off, b, c->bins, st);
+    make_bins(nullptr, g.n, g.off, b, c->bins, st, nullptr, nullptr, nullptr, nullptr, 0, true);
     (void)run_sweeps(c, g, nullptr, g.n, b, level, T, true);
   }
   const int32_t *cntL, *minvL;

@@ -163,10 +163,12 @@ struct BinScratch {
 // the caller needs no wait of its own to read it.  copy_src (may be null):
 // copy_n int64 slots copied to copy_dst (device-visible pinned host memory)
 // before the same wait, e.g. a status block the caller reads with the bins.
+// coarse: the graph of a level above 0, whose rows hold mostly distinct
+// labels (rows past half of WTAB_MAX go to the block-table bin).
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
                hipStream_t st, const uint8_t* skip = nullptr, const int32_t* dcount = nullptr,
                const long long* copy_src = nullptr, long long* copy_dst = nullptr,
-               int copy_n = 0);
+               int copy_n = 0, bool coarse = false);
 
 // Clears the per-sweep counters of the status block (before the first
 // sweep of a level; each sweep_apply clears them again for the next one).

@@ -1081,8 +1081,10 @@ __global__ void k_build_multi(const MultiSeg* __restrict__ segs, int nsegs, Mult
 constexpr int BIN_ITEMS = 4;
 constexpr int BIN_TILE = TPB * BIN_ITEMS;
 
-__device__ __forceinline__ int bin_of(int d) {
-  return d <= 16 ? 0 : d <= 32 ? 1 : d <= 64 ? 2 : d <= WTAB_MAX ? 3 : d <= BTAB_MAX ? 4 : 5;
+// wmax: the longest row of bin W (WTAB_MAX, or half of it on coarse levels,
+// whose rows hold mostly distinct labels and would overflow the wave table)
+__device__ __forceinline__ int bin_of(int d, int wmax) {
+  return d <= 16 ? 0 : d <= 32 ? 1 : d <= 64 ? 2 : d <= wmax ? 3 : d <= BTAB_MAX ? 4 : 5;
 }
 
 // Rows of the binning: bin q of a vertex v is split into row 2q (evaluated
@@ -1093,7 +1095,7 @@ constexpr int NROWS = 2 * NBINS;
 __global__ void __launch_bounds__(TPB)
     k_bin_count(const int32_t* __restrict__ list, int64_t cnt, const int32_t* __restrict__ dcnt,
                 const int32_t* __restrict__ off, const uint8_t* __restrict__ skip, int32_t* bcnt,
-                long long* bvol, int64_t nblocks) {
+                long long* bvol, int64_t nblocks, int wmax) {
   if (dcnt) cnt = *dcnt;  // the list's length on the device (cnt: its bound)
   __shared__ int c[NROWS];
   __shared__ long long v[NROWS];
@@ -1114,7 +1116,7 @@ __global__ void __launch_bounds__(TPB)
     if (p < cnt) {
       const int u = list ? list[p] : int(p);
       const int d = off[u + 1] - off[u];
-      const int row = 2 * bin_of(d) + (skip && skip[u] ? 1 : 0);
+      const int row = 2 * bin_of(d, wmax) + (skip && skip[u] ? 1 : 0);
 #pragma unroll
       for (int q = 0; q < NROWS; ++q) {
         if (row == q) {
@@ -1146,7 +1148,7 @@ __global__ void __launch_bounds__(TPB)
     k_bin_scatter(const int32_t* __restrict__ list, int64_t cnt,
                   const int32_t* __restrict__ dcnt, const int32_t* __restrict__ off,
                   const uint8_t* __restrict__ skip, const int32_t* __restrict__ boff,
-                  int64_t nblocks, int32_t* out, int32_t* out_rb) {
+                  int64_t nblocks, int32_t* out, int32_t* out_rb, int wmax) {
   if (dcnt) cnt = *dcnt;
   __shared__ int base[NROWS];
   __shared__ int wc[NW][NROWS];
@@ -1161,7 +1163,7 @@ __global__ void __launch_bounds__(TPB)
     if (valid) {
       u = list ? list[p] : int(p);
       rb = off[u];
-      row = 2 * bin_of(off[u + 1] - rb) + (skip && skip[u] ? 1 : 0);
+      row = 2 * bin_of(off[u + 1] - rb, wmax) + (skip && skip[u] ? 1 : 0);
     }
     int rank = 0;
 #pragma unroll
@@ -1492,7 +1494,8 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
 
 void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, BinScratch& s,
                hipStream_t st, const uint8_t* skip, const int32_t* dcount,
-               const long long* copy_src, long long* copy_dst, int copy_n) {
+               const long long* copy_src, long long* copy_dst, int copy_n, bool coarse) {
+  const int wmax = coarse ? WTAB_MAX / 2 : WTAB_MAX;
   const int64_t nb = count > 0 ? ceil_div(count, BIN_TILE) : 1;
   const int64_t cap = count > 0 ? count : 1;
   s.lists.ensure(size_t(cap) * sizeof(int32_t));
@@ -1510,7 +1513,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   // blocks' counts takes the two-launch scan first), then one wait
   const int64_t M = count > 0 ? int64_t(NROWS) * nb : 0;
   if (count > 0) {
-    k_bin_count<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, bcnt, bvol, nb);
+    k_bin_count<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, bcnt, bvol, nb, wmax);
     DC_LAUNCH_CHECK();
   }
   const bool one_block = M <= META_SCAN_MAX;
@@ -1551,7 +1554,7 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
   b.gslots = 0;
   if (count > 0) {
     k_bin_scatter<<<nb, TPB, 0, st>>>(list, count, dcount, off, skip, boff, nb, lists,
-                                      lists_rb);
+                                      lists_rb, wmax);
     DC_LAUNCH_CHECK();
   }
   constexpr int G = NBINS - 1;

@@ -141,7 +141,6 @@ __global__ void __launch_bounds__(TPB)
   }
 }
 
-constexpr int DT_GS = 16;  // lanes per mover in k_delta_terms
 
 __device__ __forceinline__ int unpack_lo(long long d) { return int(uint32_t(uint64_t(d))); }
 __device__ __forceinline__ int unpack_hi(long long d) {
@@ -149,9 +148,10 @@ __device__ __forceinline__ int unpack_hi(long long d) {
 }
 
 // The two terms of the exact Delta N in one launch: blocks [0, nb_intra)
-// sum the change of the intra-community weight over the movers' rows (16
-// lanes per mover), the other blocks the change of sum a^2 over the
-// touched labels.
+// sum the change of the intra-community weight over the movers' rows (GS
+// lanes per mover: 16 on graphs of short rows, a wave otherwise), the other
+// blocks the change of sum a^2 over the touched labels.
+template <int GS>
 __global__ void __launch_bounds__(TPB)
     k_delta_terms(const int32_t* __restrict__ movers, const int32_t* __restrict__ tlist,
                   const int32_t* __restrict__ off, const int2* __restrict__ adj,
@@ -161,20 +161,20 @@ __global__ void __launch_bounds__(TPB)
   long long s = 0;
   if (int(blockIdx.x) < nb_intra) {
     const int64_t cnt = stat[ST_MOVES];
-    const int lane = lane_id(), gl = lane % DT_GS;
+    const int lane = lane_id(), gl = lane % GS;
     const int64_t nwaves = int64_t(nb_intra) * NW;
-    // a wave takes WAVE / DT_GS movers per round; a row longer than a wave
-    // is left to the whole wave afterwards, so hubs keep wave speed
-    for (int64_t wb = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * (WAVE / DT_GS);
-         wb < cnt; wb += nwaves * (WAVE / DT_GS)) {
-      const int64_t p = wb + lane / DT_GS;
+    // a wave takes WAVE / GS movers per round; a row longer than a wave is
+    // left to the whole wave afterwards, so hubs keep wave speed
+    for (int64_t wb = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * (WAVE / GS);
+         wb < cnt; wb += nwaves * (WAVE / GS)) {
+      const int64_t p = wb + lane / GS;
       const bool have = p < cnt;
       const int u = have ? movers[p] : 0;
       const int32_t rb = have ? off[u] : 0, re = have ? off[u + 1] : 0;
       const int cu = have ? C[u] : 0, nu = have ? Cn[u] : 0;
-      const bool wide = re - rb > WAVE;
+      const bool wide = GS < WAVE && re - rb > WAVE;
       if (!wide) {
-        for (int32_t j = rb + gl; j < re; j += DT_GS) {
+        for (int32_t j = rb + gl; j < re; j += GS) {
           const int2 e = adj[j];
           if (e.x == u) continue;
           const int cy = C[e.x], ny = Cn[e.x];
@@ -286,10 +286,16 @@ void sweep_apply(const LevelView& g, const int32_t* active, int64_t n_active, in
   DC_LAUNCH_CHECK();
   // grids sized for the active list (the movers are known on the device
   // only); the loops stride, so most sweeps' few movers leave blocks idle
-  const int nb_intra = grid_for(ceil_div(cnt, WAVE / DT_GS) * WAVE, 4096);
   const int nb_sq = grid_for(2 * cnt, 256);
-  k_delta_terms<<<nb_intra + nb_sq, TPB, 0, st>>>(movers, tlist, g.off, g.adj, C, Cn, dpack, a,
-                                                  nb_intra, stat);
+  if (g.nnz <= 16 * int64_t(g.n)) {  // short rows: four movers per wave
+    const int nb_intra = grid_for(ceil_div(cnt, 4) * WAVE, 4096);
+    k_delta_terms<16><<<nb_intra + nb_sq, TPB, 0, st>>>(movers, tlist, g.off, g.adj, C, Cn,
+                                                        dpack, a, nb_intra, stat);
+  } else {
+    const int nb_intra = grid_for(cnt * WAVE, 4096);
+    k_delta_terms<WAVE><<<nb_intra + nb_sq, TPB, 0, st>>>(movers, tlist, g.off, g.adj, C, Cn,
+                                                          dpack, a, nb_intra, stat);
+  }
   DC_LAUNCH_CHECK();
   k_commit<<<grid_for(2 * cnt, 512), TPB, 0, st>>>(movers, tlist, stat, two_m, C, Cn, dpack,
                                                    tflag, a, sz, done, host_stat);
