@@ -27,7 +27,7 @@ constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;  // 2048
 constexpr int64_t SCAN_RAW_MAX = 1024;  // tiles whose offsets are summed in-kernel
 
-template <class T>
+template <class T, int NT = SCAN_THREADS>
 __device__ T block_excl_scan(T v, T* lds, T* total) {
   const int lane = lane_id(), wid = threadIdx.x / WAVE;
   T x = v;
@@ -40,7 +40,7 @@ __device__ T block_excl_scan(T v, T* lds, T* total) {
   __syncthreads();
   T pre = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < SCAN_THREADS / WAVE; ++w) {
+  for (int w = 0; w < NT / WAVE; ++w) {
     T t = lds[w];
     pre += (w < wid) ? t : T(0);
     tot += t;
@@ -158,8 +158,13 @@ void scan_excl(const T* in, T* out, int64_t n, T* total, hipStream_t st, T* htot
 // ---------------------------------------------------------------------------
 // radix sort
 
-constexpr int RS_THREADS = 256;
-constexpr int RS_ROUNDS = 8;
+// A tile of RS_TILE keys per block of the histogram and the scatter, 1024
+// threads each: a batch of a few hundred thousand keys makes fewer tiles
+// than the chip has CUs, so each block's chain of dependent steps is kept
+// short by giving it many waves (two keys per thread) instead of long
+// per-thread loops.
+constexpr int RS_THREADS = 1024;
+constexpr int RS_ROUNDS = 2;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 2048 keys per block
 constexpr int RS_MAX_DIGIT = 10;  // 40-bit keys in 4 passes
 constexpr int RS_BINS = 1 << RS_MAX_DIGIT;       // bins of the widest digit
@@ -195,7 +200,6 @@ __global__ void __launch_bounds__(RS_THREADS)
 // Column scan of the digit-major histogram, one block per digit: the
 // tiles' counts of digit d become their exclusive prefix in place, and the
 // digit's total goes to dtot[d] (the digit bases are summed by the scatter).
-static_assert(RS_THREADS == SCAN_THREADS, "the radix kernels use the scan's block scan");
 __global__ void __launch_bounds__(SCAN_THREADS)
     k_radix_colscan(int32_t* hist, int64_t nblocks, int32_t* dtot) {
   __shared__ int32_t lds[SCAN_THREADS / WAVE];
@@ -238,7 +242,7 @@ __global__ void __launch_bounds__(RS_THREADS)
                     const int32_t* __restrict__ colscan, const int32_t* __restrict__ dtot,
                     int64_t nblocks) {
   __shared__ int32_t base_d[RS_BINS];
-  __shared__ int32_t wcnt[RS_WAVES][RS_BINS];
+  __shared__ int32_t wcnt[RS_WAVES][RS_BINS];  // 64 KB
   __shared__ int32_t lds[RS_WAVES];
   const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
   const int bins = 1 << dbits;
@@ -255,7 +259,7 @@ __global__ void __launch_bounds__(RS_THREADS)
       s += dv[i];
     }
     int32_t tot;
-    int32_t run = block_excl_scan<int32_t>(s, lds, &tot);
+    int32_t run = block_excl_scan<int32_t, RS_THREADS>(s, lds, &tot);
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
       const int d = t * DPT + i;
