@@ -548,20 +548,19 @@ __device__ __forceinline__ long long screen_pair(const EvalArgs& A, int i0, bool
   return accepted;
 }
 
+// The items of one row-length bin of at most 64 entries, groups of GS
+// lanes, as block bid of nblocks (ls: the wave's zeroed LDS row).
 template <int MODE, int GS>
-__global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
+__device__ __forceinline__ void eval_group_body(const EvalArgs& A, int64_t bid, int64_t nblocks,
+                                                int* ls) {
   constexpr int GPW = WAVE / GS;  // groups per wave
   const int lane = lane_id();
   const int gl = lane & (GS - 1);
   const int gbase = lane - gl;
-  __shared__ int lsum_all[NW][WAVE];
-  int* ls = lsum_all[threadIdx.x / WAVE];
-  ls[lane] = 0;
-  wave_sync();
   const int64_t cnt = *A.count;
-  const int64_t ngroups = int64_t(gridDim.x) * NW * GPW;
+  const int64_t ngroups = nblocks * NW * GPW;
   long long accepted = 0;
-  const int64_t g0 = (int64_t(blockIdx.x) * NW + threadIdx.x / WAVE) * GPW + lane / GS;
+  const int64_t g0 = (bid * NW + threadIdx.x / WAVE) * GPW + lane / GS;
   // every group of a wave runs the same number of iterations (wave-uniform)
   const int64_t w0 = g0 - lane / GS;
   if constexpr (MODE == EV_SWEEP || MODE == EV_FEAT || MODE == EV_DSBOTH) {
@@ -592,6 +591,35 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
     accepted = group_sum_ll<WAVE>(accepted);
     if (lane == 0 && accepted) add_accepted(A.stat, accepted);
   }
+}
+
+template <int MODE, int GS>
+__global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
+  __shared__ int lsum_all[NW][WAVE];
+  int* ls = lsum_all[threadIdx.x / WAVE];
+  ls[lane_id()] = 0;
+  wave_sync();
+  eval_group_body<MODE, GS>(A, blockIdx.x, gridDim.x, ls);
+}
+
+// The three short-row bins in one launch, block ranges [0, nb16), [nb16,
+// nb16 + nb32) and the rest (the screening and feature passes: their lists
+// are subsets, too short for a launch each to fill the chip, so three
+// launches in a row each waited out the latency of one evaluation).
+template <int MODE>
+__global__ void __launch_bounds__(TPB)
+    k_eval_groups(EvalArgs A16, EvalArgs A32, EvalArgs A64, int nb16, int nb32) {
+  __shared__ int lsum_all[NW][WAVE];
+  int* ls = lsum_all[threadIdx.x / WAVE];
+  ls[lane_id()] = 0;
+  wave_sync();
+  const int b = int(blockIdx.x);
+  if (b < nb16)
+    eval_group_body<MODE, 16>(A16, b, nb16, ls);
+  else if (b < nb16 + nb32)
+    eval_group_body<MODE, 32>(A32, b - nb16, nb32, ls);
+  else
+    eval_group_body<MODE, 64>(A64, b - nb16 - nb32, int64_t(gridDim.x) - nb16 - nb32, ls);
 }
 
 // --------------------------------------------------------------------------
@@ -1426,12 +1454,30 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   // and the feature pass (their loads interleaved); a wave holds 64 / GS
   // groups
   constexpr int PAIR = (MODE == EV_SWEEP || MODE == EV_DSBOTH || MODE == EV_FEAT) ? 2 : 1;
-  if (bins.n[0] > 0) {
+  // the screening and feature passes take their three short-row bins in
+  // one launch (k_eval_groups); the sweeps keep a launch per bin
+  constexpr bool JOINT = MODE == EV_DSBOTH || MODE == EV_FEAT;
+  if constexpr (JOINT) {
+    if (bins.n[0] + bins.n[1] + bins.n[2] > 0) {
+      const int nb[3] = {bins.n[0] > 0 ? wave_grid(ceil_div(bins.n[0], 4 * PAIR)) : 0,
+                         bins.n[1] > 0 ? wave_grid(ceil_div(bins.n[1], 2 * PAIR)) : 0,
+                         bins.n[2] > 0 ? wave_grid(ceil_div(bins.n[2], PAIR)) : 0};
+      EvalArgs Aq[3];
+      for (int q = 0; q < 3; ++q) {
+        setbin(q);
+        Aq[q] = A;
+      }
+      k_eval_groups<MODE><<<nb[0] + nb[1] + nb[2], TPB, 0, st>>>(Aq[0], Aq[1], Aq[2], nb[0],
+                                                                  nb[1]);
+      DC_LAUNCH_CHECK();
+    }
+  }
+  if (!JOINT && bins.n[0] > 0) {
     setbin(0);
     k_eval_group<MODE, 16><<<wave_grid(ceil_div(bins.n[0], 4 * PAIR)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
   }
-  if (bins.n[1] > 0) {
+  if (!JOINT && bins.n[1] > 0) {
     setbin(1);
     if (ev0) DC_HIP(hipEventRecord(ev0, st));
     k_eval_group<MODE, 32><<<wave_grid(ceil_div(bins.n[1], 2 * PAIR)), TPB, 0, st>>>(A);
@@ -1457,7 +1503,7 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
     DC_LAUNCH_CHECK();
     DC_HIP(hipEventRecord(bins.join, bins.side));
   }
-  if (bins.n[2] > 0) {
+  if (!JOINT && bins.n[2] > 0) {
     setbin(2);
     k_eval_group<MODE, 64><<<wave_grid(ceil_div(bins.n[2], PAIR)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
