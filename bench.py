@@ -27,10 +27,10 @@ if ROOT not in sys.path:
 
 METRIC = "edge updates/sec at matched modularity (ΔS vs full); p50/p99 per-batch latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC = os.path.join(ROOT, "profiles", "k_eval_group32_dcsbm_1M_20M_traffic.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "k_eval_groups_dcsbm_1M_20M_traffic.json")
 
 
-ISSUE = os.path.join(ROOT, "profiles", "k_eval_group32_dcsbm_1M_20M_issue.json")
+ISSUE = os.path.join(ROOT, "profiles", "k_eval_groups_dcsbm_1M_20M_issue.json")
 
 
 def measured_issue():
@@ -561,8 +561,8 @@ def main():
     if d["k_launch"] > 0 and d["k_ms"] > 0:
         ach = d["k_bytes"] / (d["k_ms"] * 1e-3) / 1e9
         out["roofline"] = {
-            "kernel": "k_eval_group<0, 32> (level-0/1+ sweeps, rows of 17-32 entries, "
-                      "two vertices per wave)",
+            "kernel": "k_eval_groups<0> (level-0/1+ sweeps, rows of at most 64 entries: "
+                      "the bins of 16, 32 and 64 lanes per vertex in one launch)",
             "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "launches": d["k_launch"], "avg_launch_us": d["k_ms"] * 1e3 / d["k_launch"],

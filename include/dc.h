@@ -169,8 +169,8 @@ typedef struct dc_step_stats {
   int64_t two_m;          /* 2m of G_t                                      */
   double q;               /* N / (2m)^2                                     */
   double ms_total;        /* host wall time of the call                     */
-  double ms_sweep_kernel; /* device time of the sweep kernel for rows of 17
-                             to 32 entries (two vertices per wave), summed
+  double ms_sweep_kernel; /* device time of the sweep kernel for rows of at
+                             most 64 entries (one launch per sweep), summed
                              over its launches; timing = 1 only            */
   int64_t sweep_launches; /* launches of that kernel timed                  */
   int64_t sweep_bytes;    /* their algorithmic bytes: 12 per adjacency entry

@@ -140,7 +140,7 @@ bool sweep_account(dc_ctx* c, const LevelView& g, int level, int s, const Bins& 
       // algorithmic bytes of the timed launch: 12 B per adjacency entry
       // (8 B entry + 4 B neighbour label) and 32 B per evaluated vertex
       // (two offsets, label, degree, own total and size, best total, result)
-      S.sweep_bytes += 12 * bins.vol[TIMED_BIN] + 32 * bins.n[TIMED_BIN];
+      for (int q = 0; q < TIMED_BINS; ++q) S.sweep_bytes += 12 * bins.vol[q] + 32 * bins.n[q];
     }
     dc_sweep_rec r{};
     r.level = level;
@@ -180,7 +180,7 @@ long long run_sweeps(dc_ctx* c, const LevelView& g, const int32_t* act, int64_t 
   for (int s = 0; s < c->opt.max_sweeps; ++s) {
     if (s == 1) bins = all_bins;
     if (s == 0) sweep_reset(c->stat.as<long long>(), st);  // later: cleared by sweep_apply
-    const bool timed = record && c->opt.timing && bins.n[TIMED_BIN] > 0;
+    const bool timed = record && c->opt.timing && bins.n[0] + bins.n[1] + bins.n[2] > 0;
     sweep_eval(g, c->Cl.as<int32_t>(), c->Cn.as<int32_t>(), c->al.as<int32_t>(),
                c->szl.as<int32_t>(), c->two_m, c->opt.singleton_guard, bins,
                c->stat.as<long long>(), st, timed ? c->ev0 : nullptr,

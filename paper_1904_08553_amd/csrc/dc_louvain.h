@@ -58,7 +58,7 @@ constexpr int WTAB_SLOTS = 1024;  // (merged sweeps; single graphs use 512 slots
                                   // and a full-table retry on overflow)
 constexpr int BTAB_MAX = 4096;    // one block, block LDS table
 constexpr int BTAB_SLOTS = 8192;  // beyond: one block, global table
-constexpr int TIMED_BIN = 1;      // the bin whose launches the timing option brackets
+constexpr int TIMED_BINS = 3;     // the timing option brackets the launch of bins [0, 3)
 
 struct LevelView {
   int32_t n;
@@ -174,8 +174,8 @@ void make_bins(const int32_t* list, int64_t count, const int32_t* off, Bins& b, 
 // sweep of a level; each sweep_apply clears them again for the next one).
 void sweep_reset(long long* stat, hipStream_t st);
 // Writes the next label of every active vertex that moves.  ev0/ev1 (may be
-// null) bracket the launch of bin TIMED_BIN (rows of 17 to 32 entries, two
-// vertices per wave), the kernel that carries the most vertices.
+// null) bracket the one launch of bins [0, TIMED_BINS) (rows of at most 64
+// entries), the kernel that carries the most vertices.
 void sweep_eval(const LevelView& g, const int32_t* C, int32_t* Cn, const int32_t* a,
                 const int32_t* sz, long long two_m, int guard, const Bins& bins,
                 long long* stat, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);

@@ -603,9 +603,9 @@ __global__ void __launch_bounds__(TPB) k_eval_group(EvalArgs A) {
 }
 
 // The three short-row bins in one launch, block ranges [0, nb16), [nb16,
-// nb16 + nb32) and the rest (the screening and feature passes: their lists
-// are subsets, too short for a launch each to fill the chip, so three
-// launches in a row each waited out the latency of one evaluation).
+// nb16 + nb32) and the rest: three launches in a row each waited out the
+// latency of one evaluation, which a bin too short to fill the chip (the
+// screening set's, the sweeps' over part of the vertices) cannot hide.
 template <int MODE>
 __global__ void __launch_bounds__(TPB)
     k_eval_groups(EvalArgs A16, EvalArgs A32, EvalArgs A64, int nb16, int nb32) {
@@ -1454,9 +1454,9 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   // and the feature pass (their loads interleaved); a wave holds 64 / GS
   // groups
   constexpr int PAIR = (MODE == EV_SWEEP || MODE == EV_DSBOTH || MODE == EV_FEAT) ? 2 : 1;
-  // the screening and feature passes take their three short-row bins in
-  // one launch (k_eval_groups); the sweeps keep a launch per bin
-  constexpr bool JOINT = MODE == EV_DSBOTH || MODE == EV_FEAT;
+  // the sweeps and the screening and feature passes take their three
+  // short-row bins in one launch (k_eval_groups), which ev0 / ev1 bracket
+  constexpr bool JOINT = MODE == EV_SWEEP || MODE == EV_DSBOTH || MODE == EV_FEAT;
   if constexpr (JOINT) {
     if (bins.n[0] + bins.n[1] + bins.n[2] > 0) {
       const int nb[3] = {bins.n[0] > 0 ? wave_grid(ceil_div(bins.n[0], 4 * PAIR)) : 0,
@@ -1467,9 +1467,11 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
         setbin(q);
         Aq[q] = A;
       }
+      if (ev0) DC_HIP(hipEventRecord(ev0, st));
       k_eval_groups<MODE><<<nb[0] + nb[1] + nb[2], TPB, 0, st>>>(Aq[0], Aq[1], Aq[2], nb[0],
                                                                   nb[1]);
       DC_LAUNCH_CHECK();
+      if (ev1) DC_HIP(hipEventRecord(ev1, st));
     }
   }
   if (!JOINT && bins.n[0] > 0) {
@@ -1479,10 +1481,8 @@ void launch_eval(const EvalArgs& base, const Bins& bins, hipStream_t st, hipEven
   }
   if (!JOINT && bins.n[1] > 0) {
     setbin(1);
-    if (ev0) DC_HIP(hipEventRecord(ev0, st));
     k_eval_group<MODE, 32><<<wave_grid(ceil_div(bins.n[1], 2 * PAIR)), TPB, 0, st>>>(A);
     DC_LAUNCH_CHECK();
-    if (ev1) DC_HIP(hipEventRecord(ev1, st));
   }
   // hub rows: few long blocks, so they run on the second stream beside the
   // other bins (all read one snapshot and write disjoint labels; shared
