@@ -1101,6 +1101,7 @@ void ctx_evict(dc_ctx* c, SavedState& s) {
   DC_HIP(hipMemcpyAsync(s.sz.data(), c->sz0.p, n * 4, hipMemcpyDeviceToHost, st));
   DC_HIP(hipStreamSynchronize(st));
   for_each_buf(c, [](DBuf& b) { b.release(); });
+  pool_trim();  // the evicted bytes leave the GPU, not just the context
   c->inc.valid = false;  // the first step after restore compacts from all of G_t
   c->inc.h = 0;
 }

@@ -52,10 +52,24 @@ bool sync_check_enabled();
     if (::dc::sync_check_enabled()) DC_HIP(hipDeviceSynchronize());        \
   } while (0)
 
+// Device memory of the library's buffers (alloc.hip).  Blocks come in size
+// classes (four per doubling, so at most 25% over the request) and go back
+// to a process-wide cache when released; pool_alloc hands out a cached block
+// of the class before it calls hipMalloc, so a new context (a graph added
+// to a server, a restored one, one graph per test) does not pay a hipMalloc
+// per buffer in its first batch.  Released blocks become reusable after one
+// device-wide wait on each device that released one (taken by the next
+// pool_alloc), which is what hipFree costs anyway.  When hipMalloc runs out of memory, the cache
+// is freed and the allocation tried once more.  pool_trim frees the cache
+// (eviction to host memory calls it, so the evicted bytes leave the GPU).
+void* pool_alloc(size_t bytes, size_t* got);
+void pool_free(void* p, size_t bytes) noexcept;
+void pool_trim() noexcept;
+
 // Grow-only device buffer; contents are not preserved on growth.  Growth
 // takes 25% headroom so sizes that creep up step by step (the edge count of
-// a growing graph) do not pay a hipFree/hipMalloc pair (an implicit device
-// synchronisation) on every call.
+// a growing graph) do not pay a release and a new block (a device-wide wait)
+// on every call.
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -64,16 +78,15 @@ struct DBuf {
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, bytes);
     p = nullptr;
     bytes = 0;
   }
   void ensure(size_t b) {
     if (b <= bytes && p) return;
     release();
-    size_t want = b < 256 ? 256 : b + b / 4;
-    DC_HIP(hipMalloc(&p, want));
-    bytes = want;
+    const size_t want = b < 256 ? 256 : b + b / 4;
+    p = pool_alloc(want, &bytes);
   }
   template <class T>
   T* as() const {
