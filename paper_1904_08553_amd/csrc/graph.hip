@@ -325,12 +325,26 @@ __global__ void __launch_bounds__(RC_TPB)
 constexpr int MT_PER = MERGE_TILE / TPB;    // old entries per thread
 constexpr int MT_SEGS = MERGE_TILE / WAVE;  // wave-wide segments of a tile
 constexpr int MT_CH = 512;                  // changes of a tile staged in LDS
+constexpr int MT_ST = MT_CH / TPB + 1;      // staging loads per thread (covers MT_CH + 1)
+static_assert(MT_ST * TPB > MT_CH, "the staging loads cover the slice and its end");
 
 // first k in [a, b) with keys[k] >= key
 __device__ __forceinline__ int change_rank(const uint64_t* keys, int a, int b, uint64_t key) {
   while (a < b) {
     const int mid = (a + b) >> 1;
     if (keys[mid] < key)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  return a;
+}
+
+// first k in [a, b) with nbr[k] >= v (the changes of one row, by neighbour)
+__device__ __forceinline__ int nbr_rank(const int32_t* nbr, int a, int b, int32_t v) {
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (nbr[mid] < v)
       a = mid + 1;
     else
       b = mid;
@@ -352,9 +366,13 @@ __device__ __forceinline__ int change_rank(const uint64_t* keys, int a, int b, u
 // A tile block first puts, at each row's first entry inside the tile, that
 // row's id, offset shift and change range into LDS, together with the
 // tile's slice of the change list (the rows of a tile own one contiguous
-// slice).  An entry finds its row's slot by a ballot over the row-start
-// marks of its 64-entry segment (the nearest mark at or before the lane),
-// or from the slot recorded for the segment's first entry.
+// slice): per change its neighbour id, its weight, and its op packed with
+// cnet relative to the slice's start.  An entry finds its row's slot by a
+// ballot over the row-start marks of its 64-entry segment (the nearest mark
+// at or before the lane), or from the slot recorded for the segment's first
+// entry.  The global loads before the first barrier take clamped indexes
+// instead of per-lane bounds branches, so a wave issues them together
+// rather than one round trip after another.
 //
 // The first `nib` blocks instead place the insertions: NEW change q of row
 // r goes after the old entries of r with a smaller neighbour (binary search
@@ -372,8 +390,9 @@ __global__ void __launch_bounds__(TPB)
   __shared__ int32_t s_cb[MERGE_TILE];   // ... cptr[r]
   __shared__ int32_t s_ce[MERGE_TILE];   // ... cptr[r + 1]
   __shared__ int32_t s_seg[MT_SEGS];     // slot of the row holding entry q * WAVE
-  __shared__ uint64_t s_key[MT_CH];
-  __shared__ int32_t s_net[MT_CH + 1];
+  __shared__ int32_t s_nbr[MT_CH];       // neighbour id of change c0 + k
+  __shared__ int32_t s_w[MT_CH];         // its weight
+  __shared__ int32_t s_nop[MT_CH + 1];   // (cnet[c0 + k] - cnet[c0]) * 8 + its op
 
   if (int(blockIdx.x) < nib) {
     for (int64_t q = int64_t(blockIdx.x) * TPB + threadIdx.x; q < nch; q += int64_t(nib) * TPB) {
@@ -391,30 +410,54 @@ __global__ void __launch_bounds__(TPB)
   const int64_t tile = int64_t(blockIdx.x) - nib;
   const int64_t t0 = tile * MERGE_TILE;
   const int64_t t1 = t0 + MERGE_TILE < nnz_old ? t0 + MERGE_TILE : nnz_old;
-  const int len = int(t1 - t0);
+  const int len = int(t1 - t0);  // >= 1: the grid holds ceil(nnz_old / MERGE_TILE) tiles
   const int lane = lane_id();
   const int wbase = int(threadIdx.x / WAVE) * (WAVE * MT_PER);
   int2 e[MT_PER];
 #pragma unroll
   for (int q = 0; q < MT_PER; ++q) {
     const int i = wbase + q * WAVE + lane;
-    e[q] = i < len ? adj_old[t0 + i] : make_int2(0, 0);
+    e[q] = adj_old[t0 + (i < len ? i : len - 1)];  // lanes past the end store nothing
   }
-  for (int i = threadIdx.x; i < MERGE_TILE; i += TPB) s_row[i] = -1;
-  const int32_t r0 = tile_row[tile], r1 = tile_row[tile + 1];
-  // the bounds of this thread's first row are loaded before the barrier
+  const int32_t r0 = tile_row[tile], r1 = tile_row[tile + 1];  // rows, r1 <= n - 1
+  // the bounds of this thread's first row (clamped to r1 where the tile has
+  // fewer rows than threads; only rows <= r1 are put)
   const int32_t rf = r0 + int32_t(threadIdx.x);
   const bool hf = rf <= r1;
-  const int32_t fb = hf ? off_old[rf] : 0, fen = hf ? off_old[rf + 1] : 0;
-  const int32_t fnb = hf ? off_new[rf] : 0, fcb = hf ? cptr[rf] : 0, fce = hf ? cptr[rf + 1] : 0;
+  const int32_t rc = hf ? rf : r1;
+  const int32_t fb = off_old[rc], fen = off_old[rc + 1];
+  const int32_t fnb = off_new[rc], fcb = cptr[rc], fce = cptr[rc + 1];
   const int32_t c0 = cptr[r0], nloc = cptr[r1 + 1] - c0;
   const bool staged = nloc <= MT_CH;  // block-uniform
-  if (staged) {
-    for (int k = threadIdx.x; k <= nloc; k += TPB) {
-      if (k < nloc) s_key[k] = ch_key[c0 + k];
-      s_net[k] = cnet[c0 + k];
+  if (staged && nloc > 0) {           // block-uniform; then c0 + nloc - 1 < nch
+    int32_t sn[MT_ST];
+    uint64_t sk[MT_ST];
+    int32_t so[MT_ST], sw[MT_ST];
+#pragma unroll
+    for (int u = 0; u < MT_ST; ++u) {
+      const int k = u * TPB + int(threadIdx.x);
+      const int kn = k < nloc ? k : nloc;      // cnet has nch + 1 entries
+      const int kc = k < nloc ? k : nloc - 1;  // the change arrays nch
+      sn[u] = cnet[c0 + kn];
+      sk[u] = ch_key[c0 + kc];
+      so[u] = ch_op[c0 + kc];
+      sw[u] = ch_w[c0 + kc];
+    }
+    const int32_t base = cnet[c0];
+#pragma unroll
+    for (int u = 0; u < MT_ST; ++u) {
+      const int k = u * TPB + int(threadIdx.x);
+      if (k < nloc) {
+        const uint64_t row = sk[u] / uint64_t(n);
+        s_nbr[k] = int32_t(sk[u] - row * uint64_t(n));
+        s_w[k] = sw[u];
+        s_nop[k] = (sn[u] - base) * 8 + so[u];
+      } else if (k == nloc) {
+        s_nop[k] = (sn[u] - base) * 8;
+      }
     }
   }
+  for (int i = threadIdx.x; i < MERGE_TILE; i += TPB) s_row[i] = -1;
   __syncthreads();
   auto put = [&](int32_t r, int32_t b, int32_t en, int32_t sh, int32_t cb, int32_t ce) {
     const int64_t lo = b > t0 ? int64_t(b) : t0, hi = en < t1 ? int64_t(en) : t1;
@@ -444,25 +487,27 @@ __global__ void __launch_bounds__(TPB)
     int32_t shift = s_sh[p];
     int2 v = e[q];
     if (cb != ce) {
-      const uint64_t key = uint64_t(r) * uint64_t(n) + uint64_t(uint32_t(v.x));
-      int k;
-      bool eq;
+      int32_t op = 0, w = 0;
       if (staged) {
-        k = change_rank(s_key, cb - c0, ce - c0, key);
-        eq = k < ce - c0 && s_key[k] == key;
-        shift += s_net[k] - s_net[cb - c0];
-        k += c0;
+        const int k = nbr_rank(s_nbr, cb - c0, ce - c0, v.x);
+        const int32_t pk = s_nop[k];
+        shift += (pk >> 3) - (s_nop[cb - c0] >> 3);
+        if (k < ce - c0 && s_nbr[k] == v.x) {
+          op = pk & 7;
+          w = s_w[k];
+        }
       } else {
-        k = change_rank(ch_key, cb, ce, key);
-        eq = k < ce && ch_key[k] == key;
+        const uint64_t key = uint64_t(r) * uint64_t(n) + uint64_t(uint32_t(v.x));
+        const int k = change_rank(ch_key, cb, ce, key);
         shift += cnet[k] - cnet[cb];
+        if (k < ce && ch_key[k] == key) {
+          op = ch_op[k];
+          w = ch_w[k];
+        }
       }
-      if (eq) {
-        const int32_t op = ch_op[k];
-        if (op == OP_DELETE) continue;
-        if (op == OP_ADD) v.y += ch_w[k];
-        if (op == OP_REPLACE) v.y = ch_w[k];
-      }
+      if (op == OP_DELETE) continue;
+      if (op == OP_ADD) v.y += w;
+      if (op == OP_REPLACE) v.y = w;
     }
     adj_new[t0 + i + shift] = v;
   }
