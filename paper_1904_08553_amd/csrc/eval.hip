@@ -1139,17 +1139,34 @@ __global__ void __launch_bounds__(TPB)
     lc[q] = 0;
     lv[q] = 0;
   }
-  for (int r = 0; r < BIN_ITEMS; ++r) {
-    int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
-    if (p < cnt) {
-      const int u = list ? list[p] : int(p);
-      const int d = off[u + 1] - off[u];
-      const int row = 2 * bin_of(d, wmax) + (skip && skip[u] ? 1 : 0);
+  if (cnt > 0) {  // block-uniform
+    // the BIN_ITEMS vertices, then their bounds and flags: clamped indexes,
+    // so each round of loads is in flight together
+    int u[BIN_ITEMS], d[BIN_ITEMS], sk[BIN_ITEMS];
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) {
+      const int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
+      const int64_t pc = p < cnt ? p : cnt - 1;
+      u[r] = list ? list[pc] : int(pc);
+    }
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) d[r] = off[u[r] + 1] - off[u[r]];
+    if (skip) {
+#pragma unroll
+      for (int r = 0; r < BIN_ITEMS; ++r) sk[r] = skip[u[r]];
+    } else {
+#pragma unroll
+      for (int r = 0; r < BIN_ITEMS; ++r) sk[r] = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) {
+      const int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
+      const int row = p < cnt ? 2 * bin_of(d[r], wmax) + (sk[r] ? 1 : 0) : -1;
 #pragma unroll
       for (int q = 0; q < NROWS; ++q) {
         if (row == q) {
           lc[q]++;
-          lv[q] += d;
+          lv[q] += d[r];
         }
       }
     }
@@ -1184,15 +1201,46 @@ __global__ void __launch_bounds__(TPB)
   if (threadIdx.x < NROWS) base[threadIdx.x] = boff[int64_t(threadIdx.x) * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
-  for (int r = 0; r < BIN_ITEMS; ++r) {
-    int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
-    const bool valid = p < cnt;
-    int u = 0, row = -1, rb = 0;
-    if (valid) {
-      u = list ? list[p] : int(p);
-      rb = off[u];
-      row = 2 * bin_of(off[u + 1] - rb, wmax) + (skip && skip[u] ? 1 : 0);
+  // every item's vertex, row start and row first (clamped indexes: the
+  // loads of a round are in flight together), then the ranking rounds
+  int uu[BIN_ITEMS], rrow[BIN_ITEMS], rrb[BIN_ITEMS];
+  if (cnt > 0) {  // block-uniform
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) {
+      const int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
+      const int64_t pc = p < cnt ? p : cnt - 1;
+      uu[r] = list ? list[pc] : int(pc);
     }
+    int b1[BIN_ITEMS], sk[BIN_ITEMS];
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) {
+      rrb[r] = off[uu[r]];
+      b1[r] = off[uu[r] + 1];
+    }
+    if (skip) {
+#pragma unroll
+      for (int r = 0; r < BIN_ITEMS; ++r) sk[r] = skip[uu[r]];
+    } else {
+#pragma unroll
+      for (int r = 0; r < BIN_ITEMS; ++r) sk[r] = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) {
+      const int64_t p = int64_t(blockIdx.x) * BIN_TILE + int64_t(r) * TPB + threadIdx.x;
+      rrow[r] = p < cnt ? 2 * bin_of(b1[r] - rrb[r], wmax) + (sk[r] ? 1 : 0) : -1;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < BIN_ITEMS; ++r) {
+      uu[r] = 0;
+      rrb[r] = 0;
+      rrow[r] = -1;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < BIN_ITEMS; ++r) {
+    const bool valid = rrow[r] >= 0;
+    const int u = uu[r], row = rrow[r], rb = rrb[r];
     int rank = 0;
 #pragma unroll
     for (int q = 0; q < NROWS; ++q) {

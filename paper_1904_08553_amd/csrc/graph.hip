@@ -260,13 +260,16 @@ __global__ void __launch_bounds__(RC_TPB)
     int32_t b[RC_U], e[RC_U], ob[RC_U], oe[RC_U], cu[RC_U];
 #pragma unroll
     for (int r = 0; r < RC_U; ++r) {
+      // clamped index (n >= 1): unconditional loads, all in flight together
       const int64_t u = u0 + r * stride;
       const bool h = u < n;
-      b[r] = h ? cptr[u] : 0;
-      e[r] = h ? cptr[u + 1] : 0;
-      ob[r] = h ? off[u] : 0;
-      oe[r] = h ? off[u + 1] : 0;
-      cu[r] = h ? C[u] : 0;
+      const int64_t uc = h ? u : n - 1;
+      const int32_t x0 = cptr[uc], x1 = cptr[uc + 1], y0 = off[uc], y1 = off[uc + 1], c = C[uc];
+      b[r] = h ? x0 : 0;
+      e[r] = h ? x1 : 0;
+      ob[r] = h ? y0 : 0;
+      oe[r] = h ? y1 : 0;
+      cu[r] = h ? c : 0;
     }
 #pragma unroll
     for (int r = 0; r < RC_U; ++r) {

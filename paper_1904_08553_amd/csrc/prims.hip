@@ -58,8 +58,11 @@ __global__ void __launch_bounds__(SCAN_THREADS)
   T s = 0;
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) {
-    int64_t idx = base + int64_t(i) * SCAN_THREADS + threadIdx.x;
-    if (idx < n) s += in[idx];
+    // clamped (n >= 1 in a launched tile): one unconditional load per item,
+    // so the eight loads are in flight together
+    const int64_t idx = base + int64_t(i) * SCAN_THREADS + threadIdx.x;
+    const T x = in[idx < n ? idx : n - 1];
+    s += idx < n ? x : T(0);
   }
   T tot;
   (void)block_excl_scan<T>(s, lds, &tot);

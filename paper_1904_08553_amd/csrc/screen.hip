@@ -163,15 +163,34 @@ __global__ void __launch_bounds__(TPB)
   const int64_t v0 = int64_t(blockIdx.x) * (RL_ROUNDS * TPB) + threadIdx.x;
   uint64_t fm[RL_ROUNDS];
   bool f[RL_ROUNDS];
+  // the rounds' flags (and labels, then community flags) are loaded round
+  // after round at clamped indexes (n >= 1), so each kind is in flight
+  // together; lanes past n use none of it
+  uint8_t x[RL_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RL_ROUNDS; ++r) {
     const int64_t v = v0 + int64_t(r) * TPB;
-    f[r] = false;
-    if (v < n) {
-      const uint8_t x = cflag ? uint8_t(R[v] | cflag[C[v]]) : R[v];
-      if (cflag) R[v] = x;
-      f[r] = x != 0;
+    x[r] = R[v < n ? v : n - 1];
+  }
+  if (cflag) {
+    int32_t c[RL_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RL_ROUNDS; ++r) {
+      const int64_t v = v0 + int64_t(r) * TPB;
+      c[r] = C[v < n ? v : n - 1];
     }
+#pragma unroll
+    for (int r = 0; r < RL_ROUNDS; ++r) x[r] |= cflag[c[r]];
+#pragma unroll
+    for (int r = 0; r < RL_ROUNDS; ++r) {
+      const int64_t v = v0 + int64_t(r) * TPB;
+      if (v < n) R[v] = x[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RL_ROUNDS; ++r) {
+    const int64_t v = v0 + int64_t(r) * TPB;
+    f[r] = v < n && x[r] != 0;
     fm[r] = __ballot(f[r]);
     if (lane == 0) wc[r][wid] = __popcll(fm[r]);
   }
