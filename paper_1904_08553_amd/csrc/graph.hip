@@ -296,11 +296,22 @@ __global__ void __launch_bounds__(RC_TPB)
           dk = sk;
         }
       }
-      if (e[r] - b[r] <= RC_MANY) {
-        for (int32_t q = b[r]; q < e[r]; ++q) {
-          const int32_t op = ch_op[q];
-          dd += op == OP_NEW ? 1 : (op == OP_DELETE ? -1 : 0);
-          dk += ch_dk[q];
+      if (e[r] > b[r] && e[r] - b[r] <= RC_MANY) {
+        // all RC_MANY slots loaded at once (indexes clamped to the row's
+        // last change), then the ones inside the row summed
+        int32_t ops[RC_MANY], dks[RC_MANY];
+#pragma unroll
+        for (int j = 0; j < RC_MANY; ++j) {
+          const int32_t q = b[r] + j < e[r] ? b[r] + j : e[r] - 1;
+          ops[j] = ch_op[q];
+          dks[j] = ch_dk[q];
+        }
+#pragma unroll
+        for (int j = 0; j < RC_MANY; ++j) {
+          if (b[r] + j < e[r]) {
+            dd += ops[j] == OP_NEW ? 1 : (ops[j] == OP_DELETE ? -1 : 0);
+            dk += dks[j];
+          }
         }
       }
       if (u >= n) continue;
