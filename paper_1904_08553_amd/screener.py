@@ -203,7 +203,7 @@ def evaluate(seeds, w, theta, workers=8, modes=("all", "delta", "learned"), n=No
     import torch
     code = {"all": dc.MODE_ALL, "delta": dc.MODE_DELTA, "cascade": dc.MODE_DELTA,
             "learned": dc.MODE_LEARNED}
-    out = {m: dict(ms=[], changes=0, q=[], level0=0, R=0, touched=0) for m in modes}
+    out = {m: dict(ms=[], bi=[], changes=0, q=[], level0=0, R=0, touched=0) for m in modes}
     src = pregen if pregen is not None else graphs(seeds, workers, n)
     for s, nn, (u, v, w_), batches in src:
         dev = _dev_batches(batches)
@@ -214,10 +214,11 @@ def evaluate(seeds, w, theta, workers=8, modes=("all", "delta", "learned"), n=No
             if m == "learned":
                 g.set_screener(w, theta)
             torch.cuda.synchronize()
-            for b, hb in zip(dev, batches):
+            for i, (b, hb) in enumerate(zip(dev, batches)):
                 t = time.perf_counter()
                 g.apply_batch(*b, out=out_C)
                 out[m]["ms"].append((time.perf_counter() - t) * 1e3)
+                out[m]["bi"].append(i)
                 st = g.stats
                 out[m]["changes"] += hb.size
                 out[m]["q"].append(st.q)
@@ -234,7 +235,14 @@ def summarize(res):
     qa = np.asarray(res["all"]["q"]) if "all" in res else None
     for m, r in res.items():
         t = sum(r["ms"]) / 1e3
-        d = dict(edge_updates_per_s=r["changes"] / t, ms_per_batch=float(np.mean(r["ms"])),
+        ms = np.asarray(r["ms"])
+        later = ms[np.asarray(r["bi"]) > 0]
+        # each graph's first batch also sets up its new context (buffers
+        # taken from the allocator); the later batches and the median show
+        # the steady state without it or single slow batches
+        d = dict(edge_updates_per_s=r["changes"] / t, ms_per_batch=float(ms.mean()),
+                 ms_per_batch_median=float(np.median(ms)),
+                 ms_per_later_batch=float(later.mean()) if later.size else None,
                  level0_evals=r["level0"], R_total=r["R"])
         if qa is not None:
             rel = (np.asarray(r["q"]) - qa) / np.abs(qa)
@@ -244,6 +252,11 @@ def summarize(res):
     if "delta" in s and "learned" in s:
         s["learned_speedup_over_delta"] = (s["learned"]["edge_updates_per_s"]
                                            / s["delta"]["edge_updates_per_s"])
+        s["learned_speedup_over_delta_median"] = (s["delta"]["ms_per_batch_median"]
+                                                  / s["learned"]["ms_per_batch_median"])
+        if s["learned"]["ms_per_later_batch"]:
+            s["learned_speedup_over_delta_later"] = (s["delta"]["ms_per_later_batch"]
+                                                     / s["learned"]["ms_per_later_batch"])
     if "delta" in s and "cascade" in s:
         s["cascade_speedup_over_delta"] = (s["cascade"]["edge_updates_per_s"]
                                            / s["delta"]["edge_updates_per_s"])
