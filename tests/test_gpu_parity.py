@@ -101,6 +101,32 @@ def test_dcsbm_with_hubs(seed):
         compare(o, g, f"step {t}")
 
 
+def test_contexts_on_reused_device_memory():
+    """Device buffers of a destroyed context go back to the library's block
+    cache and the next context takes them with the old contents in place:
+    a graph run after another graph of the same size (and then after its own
+    earlier run) still equals the oracle, so no kernel relies on memory that
+    starts at zero unless it clears it."""
+    gen_a = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=7)
+    gen_b = W.DCSBM(n=20000, m=200000, blocks=40, dmax=20000, seed=8)
+    (ua, va, wa), it_a = gen_a.stream(2, frac=0.01)
+    (ub, vb, wb), it_b = gen_b.stream(2, frac=0.01)
+    batches_b = list(it_b)
+    _log("case: reused memory, graph A fills the cache")
+    ga = dc.DynamicCommunities(gen_a.n, ua, va, wa)
+    for b in it_a:
+        ga.apply_batch(b.add_u, b.add_v, b.add_w, b.del_u, b.del_v)
+    ga.close()
+    for rep in range(2):
+        _log(f"case: reused memory, graph B run {rep}")
+        o, g = make_pair(gen_b.n, ub, vb, wb)
+        compare(o, g, f"run {rep} init")
+        for t, b in enumerate(batches_b):
+            step_pair(o, g, b)
+            compare(o, g, f"run {rep} step {t}")
+        g.close()
+
+
 def test_batch_errors_leave_state_unchanged():
     from paper_1904_08553_amd.dc import DCError
     _log("case: batch errors")
