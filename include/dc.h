@@ -260,6 +260,16 @@ dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w);
 
 void dc_destroy(dc_ctx* ctx);
 
+/* Device memory of the library comes from a block cache: buffers released by
+ * dc_destroy (and by buffers that grow) stay cached and are handed to later
+ * contexts before hipMalloc is called.  This call frees every cached block
+ * (after one wait for each device that released a block); memory held by
+ * live contexts is untouched.  The cache is also freed when a served graph
+ * is evicted to host memory and when hipMalloc reports no memory (the
+ * allocation is then tried once more).  Call it from no thread that is
+ * stepping a context at the same time. */
+void dc_trim_device_cache(void);
+
 /* Checkpoint of a context: G_t as a CSR in host memory (as dc_export_csr,
  * sizes from dc_num_entries) and C_t[n]. */
 dc_status dc_export_state(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w,

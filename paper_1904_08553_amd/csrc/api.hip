@@ -1493,6 +1493,8 @@ dc_status dc_export_csr(dc_ctx* ctx, int64_t* off, int32_t* col, int32_t* w) {
 
 void dc_destroy(dc_ctx* ctx) { destroy_ctx(ctx); }
 
+void dc_trim_device_cache(void) { pool_trim(); }
+
 dc_status dc_screener_set(dc_ctx* ctx, const float* w, float theta) {
   return guarded(ctx, [&] {
     if (!w) {

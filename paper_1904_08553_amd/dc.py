@@ -79,7 +79,7 @@ class StepStats(ct.Structure):
 EXPORTS = [
     "dc_default_options", "dc_init", "dc_apply_batch", "dc_modularity", "dc_communities",
     "dc_last_R", "dc_last_trace", "dc_last_stats", "dc_num_entries", "dc_export_csr",
-    "dc_destroy", "dc_strerror", "dc_last_error", "dc_screener_set", "dc_last_samples",
+    "dc_destroy", "dc_trim_device_cache", "dc_strerror", "dc_last_error", "dc_screener_set", "dc_last_samples",
     "dc_mlp_create", "dc_mlp_set_weights", "dc_mlp_get_weights", "dc_mlp_forward", "dc_mlp_grad",
     "dc_mlp_grad_noalloc", "dc_mlp_train_step", "dc_mlp_destroy", "dc_export_state", "dc_init_from_state",
     "dc_server_create", "dc_server_add_graph", "dc_server_submit", "dc_server_poll",
@@ -137,6 +137,8 @@ def load(path: str = LIB_PATH):
     L.dc_export_csr.restype = i32
     L.dc_destroy.argtypes = [P]
     L.dc_destroy.restype = None
+    L.dc_trim_device_cache.argtypes = []
+    L.dc_trim_device_cache.restype = None
     L.dc_strerror.argtypes = [i32]
     L.dc_strerror.restype = ct.c_char_p
     L.dc_last_error.argtypes = []
@@ -424,6 +426,12 @@ CKPT_VERSION = 1
 
 class CheckpointError(RuntimeError):
     """A checkpoint file that is not a complete, intact checkpoint."""
+
+
+def trim_device_cache():
+    """Frees the device blocks that destroyed contexts left in the library's
+    block cache (dc_trim_device_cache); live contexts keep their memory."""
+    load().dc_trim_device_cache()
 
 
 def _ckpt_digest(n, off, col, w, C):
