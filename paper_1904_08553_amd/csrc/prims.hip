@@ -213,7 +213,9 @@ __global__ void __launch_bounds__(SCAN_THREADS)
     int32_t v[4], s = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      v[i] = base + i < nblocks ? col[base + i] : 0;
+      // clamped index (nblocks >= 1): the four loads in flight together
+      const int32_t x = col[base + i < nblocks ? base + i : nblocks - 1];
+      v[i] = base + i < nblocks ? x : 0;
       s += v[i];
     }
     int32_t tot;
@@ -249,24 +251,45 @@ __global__ void __launch_bounds__(RS_THREADS)
   __shared__ int32_t lds[RS_WAVES];
   const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
   const int bins = 1 << dbits;
+  const int64_t wbase = int64_t(blockIdx.x) * RS_TILE + int64_t(wid) * RS_WCHUNK;
+  // every global load of the block first, at clamped indexes (bins >= 2,
+  // n >= 2), so the digit totals, this tile's digit offsets and the wave's
+  // keys and values are in flight together: the wave's keys and values (all
+  // rounds, loaded before the first is ranked), then per digit its total
+  // and its count in the tiles before this one
+  uint64_t kr[RS_ROUNDS];
+  uint32_t vr[RS_ROUNDS];
+  int32_t rk[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t idx = wbase + int64_t(r) * WAVE + lane;
+    const int64_t ic = idx < n ? idx : n - 1;
+    kr[r] = kin[ic];
+    vr[r] = vin[ic];
+  }
+  constexpr int DPT = RS_BINS / RS_THREADS;
+  int32_t dv[DPT], cs[DPT];
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int d = t * DPT + i;
+    const int dc = d < bins ? d : bins - 1;
+    const int32_t x = dtot[dc], y = colscan[int64_t(dc) * nblocks + blockIdx.x];
+    dv[i] = d < bins ? x : 0;
+    cs[i] = y;
+  }
   // output base of each digit in this tile: the totals of the smaller
   // digits (a block scan, RS_BINS / RS_THREADS digits per thread) plus the
   // digit's count in the tiles before this one
   {
-    constexpr int DPT = RS_BINS / RS_THREADS;
-    int32_t dv[DPT], s = 0;
+    int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < DPT; ++i) {
-      const int d = t * DPT + i;
-      dv[i] = d < bins ? dtot[d] : 0;
-      s += dv[i];
-    }
+    for (int i = 0; i < DPT; ++i) s += dv[i];
     int32_t tot;
     int32_t run = block_excl_scan<int32_t, RS_THREADS>(s, lds, &tot);
 #pragma unroll
     for (int i = 0; i < DPT; ++i) {
       const int d = t * DPT + i;
-      if (d < bins) base_d[d] = run + colscan[int64_t(d) * nblocks + blockIdx.x];
+      if (d < bins) base_d[d] = run + cs[i];
       run += dv[i];
     }
   }
@@ -277,17 +300,6 @@ __global__ void __launch_bounds__(RS_THREADS)
   __syncthreads();
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   const uint64_t mask = uint64_t(bins - 1);
-  const int64_t wbase = int64_t(blockIdx.x) * RS_TILE + int64_t(wid) * RS_WCHUNK;
-  // the wave's keys and values, all rounds loaded before the first is ranked
-  uint64_t kr[RS_ROUNDS];
-  uint32_t vr[RS_ROUNDS];
-  int32_t rk[RS_ROUNDS];
-#pragma unroll
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t idx = wbase + int64_t(r) * WAVE + lane;
-    kr[r] = idx < n ? kin[idx] : 0;
-    vr[r] = idx < n ? vin[idx] : 0;
-  }
   int32_t* own = wcnt[wid];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
