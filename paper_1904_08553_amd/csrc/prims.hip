@@ -26,6 +26,7 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;  // 2048
 constexpr int64_t SCAN_RAW_MAX = 1024;  // tiles whose offsets are summed in-kernel
+static_assert(SCAN_RAW_MAX % SCAN_THREADS == 0, "raw partials per thread");
 
 template <class T, int NT = SCAN_THREADS>
 __device__ T block_excl_scan(T v, T* lds, T* total) {
@@ -78,23 +79,35 @@ __global__ void __launch_bounds__(SCAN_THREADS)
     k_tile_scan(const T* in, T* out, int64_t n, const T* __restrict__ part, int raw,
                 T* total, int64_t nblocks, T* htotal) {
   __shared__ T lds[SCAN_THREADS / WAVE];
+  // the tile's items and the partials before it are loaded first, at
+  // clamped indexes (n >= 1, nblocks >= 1), so they are in flight together
+  const int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
+  T v[SCAN_ITEMS];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    const int64_t idx = base + i;
+    const T x = in[idx < n ? idx : n - 1];
+    v[i] = idx < n ? x : T(0);
+  }
   T off = 0;
-  if (part && raw) {
+  if (part && raw) {  // nblocks <= SCAN_RAW_MAX
+    T pv[SCAN_RAW_MAX / SCAN_THREADS];
+#pragma unroll
+    for (int j = 0; j < SCAN_RAW_MAX / SCAN_THREADS; ++j) {
+      const int64_t b = int64_t(threadIdx.x) + int64_t(j) * SCAN_THREADS;
+      const T x = part[b < nblocks ? b : nblocks - 1];
+      pv[j] = b < int64_t(blockIdx.x) ? x : T(0);
+    }
     T acc = 0;
-    for (int64_t b = threadIdx.x; b < int64_t(blockIdx.x); b += SCAN_THREADS) acc += part[b];
+#pragma unroll
+    for (int j = 0; j < SCAN_RAW_MAX / SCAN_THREADS; ++j) acc += pv[j];
     (void)block_excl_scan<T>(acc, lds, &off);
   } else if (part) {
     off = part[blockIdx.x];
   }
-  int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
-  T v[SCAN_ITEMS];
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    int64_t idx = base + i;
-    v[i] = idx < n ? in[idx] : T(0);
-    s += v[i];
-  }
+  for (int i = 0; i < SCAN_ITEMS; ++i) s += v[i];
   T tot;
   T pre = block_excl_scan<T>(s, lds, &tot);
   T run = off + pre;
